@@ -1,0 +1,248 @@
+/*
+ * symten — block-sparse symmetric tensors and one CTM environment move on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * A tensor is a direct sum of dense blocks, one per tuple of charge labels
+ * that obeys the abelian addition rule (Sec. 2, Eq. tensor-blocks and the
+ * rank-2 example): sum over legs of dir * q == flux, dir = +1 for an
+ * incoming and -1 for an outgoing leg.  A contraction pairs the blocks whose
+ * labels agree on the contracted legs and multiplies their dense parts
+ * (Sec. 2, contraction rule r_k = m_t . m_s); results with equal open labels
+ * are summed in place (Sec. 2, grouping by output quantum numbers).
+ *
+ * Conventions shared by every entry point:
+ *  - U(1) charges are integers in units of 2*S^z.  Only U(1) is implemented;
+ *    SYMTEN_SU2 descriptors are rejected with SYMTEN_E_UNSUPPORTED.
+ *  - A leg's sectors are given as parallel arrays (label, reduced dim); the
+ *    library sorts them by label ascending, which fixes the state order.
+ *  - Canonical block order is lexicographic in the labels, leg 0 slowest.
+ *    symten_upload / symten_download exchange values in that order,
+ *    row-major inside each block.
+ *  - Device storage: one buffer per tensor owned by the library.  Blocks are
+ *    strided views into it (symten_block_info reports offset and strides in
+ *    elements); tensors made by symten_create are contiguous row-major.
+ *  - Every call that takes a `stream` enqueues its device work on that HIP
+ *    stream (NULL = the default stream) and returns without waiting, unless
+ *    documented otherwise.  Calls that overlap on one tensor race.
+ *  - Every function returns 0 (SYMTEN_OK) or a negative status; the message
+ *    of the last failure on the calling thread is symten_last_error().  No
+ *    C++ exception crosses this interface.
+ */
+#ifndef SYMTEN_H
+#define SYMTEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SYMTEN_OK              0
+#define SYMTEN_E_INVAL        -1  /* bad argument, null handle, bad shape */
+#define SYMTEN_E_LEGS         -2  /* contracted legs not dual (direction or sectors) */
+#define SYMTEN_E_SYM          -3  /* symmetry rule violated (e.g. SU(2) flux != 0) */
+#define SYMTEN_E_NOMEM        -4  /* device or host allocation failed */
+#define SYMTEN_E_HIP          -5  /* a HIP runtime call failed */
+#define SYMTEN_E_LINALG       -6  /* QR/SVD failed, NaN/Inf met, nothing kept */
+#define SYMTEN_E_CAPACITY     -7  /* a fixed-size limit was exceeded */
+#define SYMTEN_E_UNSUPPORTED  -8  /* valid request not implemented */
+#define SYMTEN_E_NODEVICE     -9  /* the call needs a GPU and none is usable */
+
+/* ---- enums ------------------------------------------------------------ */
+#define SYMTEN_U1   1
+#define SYMTEN_SU2  2
+
+#define SYMTEN_IN   1
+#define SYMTEN_OUT -1
+
+/* storage element type */
+#define SYMTEN_F64  0
+#define SYMTEN_F32  1
+
+/* arithmetic of the sector products:
+ * F64    - FP64 MFMA (storage F64)
+ * F32    - FP32 MFMA (storage F32)
+ * BF16   - operands rounded to bf16, FP32 accumulation (storage F32)
+ * BF16X3 - each FP32 operand split x = hi + lo (hi = bf16(x),
+ *          lo = bf16(x - hi)); product hi*hi + hi*lo + lo*hi on bf16 MFMA
+ *          with FP32 accumulation (storage F32)                           */
+#define SYMTEN_PREC_F64     0
+#define SYMTEN_PREC_F32     1
+#define SYMTEN_PREC_BF16    2
+#define SYMTEN_PREC_BF16X3  3
+
+#define SYMTEN_MAX_RANK 8
+
+typedef struct symten_tensor* symten_t;
+typedef struct ctm_env* ctm_env_t;
+
+/* Tensor description.  `labels` and `dims` are the concatenation over legs
+ * of each leg's sector list; leg l owns nsec[l] consecutive entries.
+ * Sectors of dim 0 are ignored; labels within a leg must be distinct.      */
+typedef struct {
+    int group;          /* SYMTEN_U1 (SYMTEN_SU2 rejected)                  */
+    int rank;           /* 1 .. SYMTEN_MAX_RANK                             */
+    const int* dirs;    /* [rank] SYMTEN_IN / SYMTEN_OUT                    */
+    const int* nsec;    /* [rank] number of sectors per leg                 */
+    const int* labels;  /* [sum nsec] U(1) charge (units of 2 S^z)          */
+    const int* dims;    /* [sum nsec] reduced sector dimension (>= 0)       */
+    int flux;           /* total charge: sum dir*q of every block           */
+    int dtype;          /* SYMTEN_F64 or SYMTEN_F32                         */
+} symten_desc;
+
+/* ---- tensors (Sec. 2, Eq. tensor-blocks) ------------------------------ */
+
+/* Enumerate the allowed blocks (canonical order) and allocate a zeroed
+ * device buffer holding them contiguously.  Needs a GPU.                   */
+int symten_create(symten_t* out, const symten_desc* d, void* stream);
+
+/* Same enumeration without any device memory: the handle answers the
+ * metadata queries below and can be used for planning (symten_plan_info),
+ * but every device operation on it fails with SYMTEN_E_INVAL.  Runs on a
+ * host without a GPU.                                                      */
+int symten_create_meta(symten_t* out, const symten_desc* d);
+
+void symten_destroy(symten_t t);
+
+int symten_rank(symten_t t, int* rank);
+int symten_flux(symten_t t, int* flux);
+int symten_dtype(symten_t t, int* dtype);
+/* sectors of one leg: labels/dims must hold at least *nsec entries; pass
+ * NULL to query the count only.                                             */
+int symten_leg_info(symten_t t, int leg, int* dir, int* nsec, int* labels, int* dims);
+int symten_num_blocks(symten_t t, int64_t* n);
+/* total number of stored block elements (sum of block sizes)              */
+int symten_nnz(symten_t t, int64_t* n);
+/* block i in canonical order: labels[rank], shape[rank], offset and
+ * strides[rank] in elements of the device buffer.                           */
+int symten_block_info(symten_t t, int64_t i, int* labels, int* shape,
+                      int64_t* offset, int64_t* strides);
+/* device buffer and its size in elements (>= nnz when blocks are strided). */
+int symten_device_ptr(symten_t t, void** ptr, int64_t* elems);
+
+/* Host FP64 values in canonical block order, row-major inside each block,
+ * `n` = nnz.  Values are rounded to the storage type (round to nearest).
+ * Synchronous with respect to the host buffer.                             */
+int symten_upload(symten_t t, const double* values, int64_t n, void* stream);
+int symten_download(symten_t t, double* values, int64_t n, void* stream);
+
+/* ---- block-sparse contraction (Sec. 2, contraction rule) -------------- */
+
+typedef struct {
+    int64_t pairs;        /* matched block pairs                             */
+    int64_t out_blocks;   /* output blocks reached by at least one pair      */
+    int64_t useful_flops; /* sum over pairs of 2*m*n*k                       */
+    int64_t groups;       /* dense charge-sector GEMMs the pairs fuse into   */
+    int64_t gemm_flops;   /* flops of those GEMMs incl. structural zeros     */
+    int64_t max_m, max_n, max_k;
+} symten_plan_stats;
+
+/* Contract legs legsA[i] of A with legsB[i] of B (i < ncon).  The output
+ * legs are A's open legs then B's open legs (each in their order), then
+ * permuted: output leg j is that list's entry out_perm[j] (NULL = identity).
+ * Contracted legs must have opposite directions and identical sector lists,
+ * else SYMTEN_E_LEGS.  Zero matched pairs is valid (a tensor without
+ * blocks).  `prec` must suit both storage types (F64 needs F64 storage,
+ * the others F32).  Output flux = flux(A) + flux(B).                       */
+int symten_contract(symten_t* out, symten_t A, symten_t B, int ncon,
+                    const int* legsA, const int* legsB, const int* out_perm,
+                    int prec, void* stream);
+
+/* Host-only planning of the same contraction: fills `info` and, if `out`
+ * is not NULL, a metadata-only output tensor.  No GPU needed.              */
+int symten_plan_info(symten_t A, symten_t B, int ncon, const int* legsA,
+                     const int* legsB, const int* out_perm,
+                     symten_plan_stats* info, symten_t* out);
+
+/* ---- double layer (Sec. 3.2: rank-4 double-layer tensor) -------------- */
+
+/* a[L,U,R,D] = sum_s A[s,l,u,r,d] A[s,l',u',r',d'] (A real) for a rank-5 A
+ * with legs (physical in, l in, u in, r out, d out); each (ket, bra) pair
+ * of virtual legs becomes one leg of charge q_ket - q_bra whose states are
+ * ordered by that charge, then q_ket, then (i_ket, i_bra) row-major.
+ * Output dtype = A's dtype, flux 0.                                         */
+int symten_double_layer(symten_t* a_out, symten_t A, void* stream);
+
+/* ---- enlarged corners -------------------------------------------------- */
+
+/* which = 1..4.  Inputs follow the clockwise environment convention:
+ * C[in, out]; T[chi_in, D2, chi_out] with D2 outgoing for T1, T4 and
+ * incoming for T2, T3; a[L in, U in, R out, D out].
+ *   1: ((C1 T1) T4) a -> [x1, x4, r, d]    Ta = T1, Tb = T4
+ *   2: ((C2 T1) T2) a -> [x1, x2, l, d]    Ta = T1, Tb = T2
+ *   3: ((C3 T3) T2) a -> [x3, x2, l, u]    Ta = T3, Tb = T2
+ *   4: ((C4 T3) T4) a -> [x3, x4, u, r]    Ta = T3, Tb = T4
+ * `info` (may be NULL) receives the summed plan statistics of the 3 steps. */
+int symten_enlarged_corner(symten_t* out, int which, symten_t C, symten_t Ta,
+                           symten_t Tb, symten_t a, int prec,
+                           symten_plan_stats* info, void* stream);
+
+/* Batched corners: n independent corner-1 contractions ((C T1) T4) a, each
+ * step of all n fused into one grouped-GEMM launch.  use_graph != 0 records
+ * the whole batch into a HIP graph on first use and replays it afterwards
+ * (inputs must keep their structures and buffers).  out[i] receive the
+ * corners; info (may be NULL) the summed statistics.                       */
+int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* C,
+                                    const symten_t* Ta, const symten_t* Tb,
+                                    const symten_t* a, int prec, int use_graph,
+                                    symten_plan_stats* info, void* stream);
+
+/* ---- CTM environment and one move ------------------------------------- */
+
+#define CTM_LEFT 0
+#define CTM_MAX_SECTORS 64
+
+typedef struct {
+    int nsec;                        /* sectors of the new chi leg         */
+    int charge[CTM_MAX_SECTORS];
+    int kept[CTM_MAX_SECTORS];
+    int n_sv_sectors;                /* sectors that had singular values   */
+    int sv_charge[CTM_MAX_SECTORS];
+    int sv_count[CTM_MAX_SECTORS];
+    double trunc_err;                /* sum discarded s^2 / sum s^2        */
+    double gap;                      /* (s_last_kept - s_first_dropped)/s_max */
+    double s_max;
+    int64_t flops_corners, flops_halves, flops_renorm; /* useful flops     */
+    int64_t flops_proj;              /* FP64 flops of M = R_u R_d^T        */
+    double ms_corners, ms_halves, ms_proj, ms_renorm, ms_total;
+} ctm_move_stats;
+
+/* The environment takes its own references to C1..C4, T1..T4 (it keeps the
+ * handles; do not destroy them while the environment lives).               */
+int ctm_env_create(ctm_env_t* env, const symten_t C[4], const symten_t T[4]);
+void ctm_env_destroy(ctm_env_t env);
+/* Current tensor k: 0..3 = C1..C4, 4..7 = T1..T4.  Returns a new handle
+ * (sharing the storage) that the caller releases with symten_destroy.      */
+int ctm_env_get(ctm_env_t env, int k, symten_t* t);
+
+/* One CTM move (only CTM_LEFT): four enlarged corners, halves
+ * H_u = C~1 C~2 and H_d = C~4 C~3, per fused charge FP64 QR of H_u^T, H_d^T,
+ * M = R_u R_d^T, SVD M = U S V^T, global top-chi truncation (ties: charge,
+ * then index ascending; s <= 1e-14 s_max dropped), projectors
+ * P = R_d^T V S^-1/2 and P~ = S^-1/2 U^T R_u (largest-magnitude entry of
+ * every P~ row made positive), then C1' = (C1 T1) P, T4' = P~ (T4 a) P,
+ * C4' = P~ (C4 T3), each scaled to unit Frobenius norm in FP64.  `chi`
+ * counts states.  Synchronises `stream` once (truncation needs the singular
+ * values on the host) and again at the end when `st` is not NULL.          */
+int ctm_move(ctm_env_t env, symten_t a, int dir, int chi, int prec,
+             ctm_move_stats* st, void* stream);
+
+/* Singular values of the last move, per sector in charge order, each
+ * sector descending.  cap = capacity of `s`; *n receives the count.        */
+int ctm_move_singular_values(ctm_env_t env, double* s, int64_t cap, int64_t* n);
+/* Projectors of the last move as tensors (new handles, FP64, released with
+ * symten_destroy): P[chi out, D2 in, k in] and P~[k out, chi in, D2 out].   */
+int ctm_move_projectors(ctm_env_t env, symten_t* P, symten_t* Pt);
+
+/* ---- misc --------------------------------------------------------------- */
+const char* symten_last_error(void);
+int symten_version(void);
+/* Wait for all work on `stream`.                                            */
+int symten_sync(void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYMTEN_H */

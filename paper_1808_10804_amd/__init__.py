@@ -1,0 +1,12 @@
+"""MI355X-native block-sparse symmetric CTM contractions (libsymten binding).
+
+The compute path lives in libsymten.so (HIP for gfx950, C ABI in
+include/symten.h); this package only loads it and marshals arguments.
+"""
+from . import _lib
+from .symten import (Tensor, CtmEnv, contract, plan_info, double_layer, enlarged_corner,
+                     enlarged_corners_batched, sync, IN, OUT)
+from ._lib import SymtenError
+
+__all__ = ["Tensor", "CtmEnv", "contract", "plan_info", "double_layer", "enlarged_corner",
+           "enlarged_corners_batched", "sync", "IN", "OUT", "SymtenError"]

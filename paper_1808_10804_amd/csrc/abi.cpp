@@ -1,0 +1,1033 @@
+// C ABI of libsymten and the CTM move (enlarged corners, halves, FP64
+// projectors through rocSOLVER/rocBLAS, renormalisation, normalisation).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <list>
+#include <mutex>
+#include <numeric>
+#include <unordered_map>
+
+#include "internal.hpp"
+
+struct symten_tensor {
+    symten::TensorPtr t;
+};
+
+namespace symten {
+
+void upload_sync(BufferPtr& buf, const void* host, size_t bytes);
+void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems);
+void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw);
+void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix);
+void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles);
+void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+                     void* const* d_ptrs, bool src_f64, bool dst_f64, hipStream_t s);
+void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, void* const* d_ptrs,
+                     Prec prec, int cfg, hipStream_t s);
+int choose_tile_cfg(const ContractPlan& p);
+void launch_extract_upper(const double* W, int ldw, int r, int n, double* R, int ldr, hipStream_t s);
+void launch_scale_cols(double* X, int ld, int rows, int cols, const double* s, hipStream_t st);
+void launch_scale_rows(double* X, int ld, int rows, int cols, const double* s, hipStream_t st);
+
+namespace {
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& m) {
+    g_err = m;
+    return code;
+}
+
+template <class F>
+int guard(F&& f) {
+    try {
+        f();
+        return SYMTEN_OK;
+    } catch (const Error& e) {
+        return set_err(e.code, e.what());
+    } catch (const std::bad_alloc&) {
+        return set_err(SYMTEN_E_NOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return set_err(SYMTEN_E_INVAL, e.what());
+    } catch (...) {
+        return set_err(SYMTEN_E_INVAL, "unknown error");
+    }
+}
+
+Tensor& T(symten_t h) {
+    if (!h || !h->t) fail(SYMTEN_E_INVAL, "null tensor handle");
+    return *h->t;
+}
+
+symten_t wrap(TensorPtr p) {
+    auto* h = new symten_tensor;
+    h->t = std::move(p);
+    return h;
+}
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// ---- plan cache ----------------------------------------------------------
+struct PlanCache {
+    std::mutex mu;
+    std::list<std::pair<std::string, std::shared_ptr<ContractPlan>>> lru;
+    std::unordered_map<std::string, decltype(lru)::iterator> map;
+    size_t cap = 512;
+};
+PlanCache& cache() {
+    static PlanCache* c = new PlanCache();
+    return *c;
+}
+
+std::shared_ptr<ContractPlan> get_plan(const Tensor& A, const Tensor& B, int ncon, const int* la, const int* lb,
+                                       const int* perm, int prec) {
+    std::string key = tensor_signature(A) + "#" + tensor_signature(B) + "#" + std::to_string(ncon) + ":";
+    for (int i = 0; i < ncon; ++i) key += std::to_string(la[i]) + "," + std::to_string(lb[i]) + ";";
+    const int ro = A.rank() + B.rank() - 2 * ncon;
+    key += "p";
+    if (perm) for (int j = 0; j < ro; ++j) key += std::to_string(perm[j]) + ",";
+    key += "#" + std::to_string(prec);
+    PlanCache& C = cache();
+    {
+        std::lock_guard<std::mutex> lk(C.mu);
+        auto it = C.map.find(key);
+        if (it != C.map.end()) {
+            C.lru.splice(C.lru.begin(), C.lru, it->second);
+            return it->second->second;
+        }
+    }
+    auto p = plan_contraction(A, B, ncon, la, lb, perm, prec);
+    std::lock_guard<std::mutex> lk(C.mu);
+    C.lru.emplace_front(key, p);
+    C.map[key] = C.lru.begin();
+    while (C.lru.size() > C.cap) {
+        C.map.erase(C.lru.back().first);
+        C.lru.pop_back();
+    }
+    return p;
+}
+
+struct Contracted {
+    TensorPtr t;
+    std::shared_ptr<ContractPlan> plan;
+};
+
+Contracted contract(const Tensor& A, const Tensor& B, std::initializer_list<int> la, std::initializer_list<int> lb,
+                    const std::vector<int>& perm, int prec, hipStream_t s) {
+    std::vector<int> a(la), b(lb);
+    auto p = get_plan(A, B, (int)a.size(), a.data(), b.data(), perm.empty() ? nullptr : perm.data(), prec);
+    return {run_contraction(*p, A, B, s), p};
+}
+
+void add_info(symten_plan_stats& acc, const symten_plan_stats& x) {
+    acc.pairs += x.pairs;
+    acc.out_blocks += x.out_blocks;
+    acc.useful_flops += x.useful_flops;
+    acc.groups += x.groups;
+    acc.gemm_flops += x.gemm_flops;
+    acc.max_m = std::max(acc.max_m, x.max_m);
+    acc.max_n = std::max(acc.max_n, x.max_n);
+    acc.max_k = std::max(acc.max_k, x.max_k);
+}
+
+// Legs of the three steps of corner `which` (see the header).
+struct CornerSpec {
+    std::vector<int> l1a, l1b, l2a, l2b, l3a, l3b;
+};
+CornerSpec corner_spec(int which) {
+    switch (which) {
+        case 1: return {{1}, {0}, {0}, {2}, {3, 0}, {0, 1}};
+        case 2: return {{0}, {2}, {0}, {0}, {1, 2}, {1, 2}};
+        case 3: return {{1}, {0}, {0}, {2}, {3, 0}, {2, 3}};
+        case 4: return {{0}, {2}, {0}, {0}, {2, 1}, {0, 3}};
+        default: fail(SYMTEN_E_INVAL, "enlarged corner: which must be 1..4");
+    }
+}
+
+struct CornerResult {
+    TensorPtr step1, step2, corner;
+    symten_plan_stats info{};
+};
+
+CornerResult corner(int which, const Tensor& C, const Tensor& Ta, const Tensor& Tb, const Tensor& a, int prec,
+                    hipStream_t s) {
+    CornerSpec sp = corner_spec(which);
+    CornerResult r;
+    auto run = [&](const Tensor& X, const Tensor& Y, const std::vector<int>& la, const std::vector<int>& lb) {
+        auto p = get_plan(X, Y, (int)la.size(), la.data(), lb.data(), nullptr, prec);
+        add_info(r.info, p->info);
+        return run_contraction(*p, X, Y, s);
+    };
+    r.step1 = run(C, Ta, sp.l1a, sp.l1b);
+    r.step2 = run(*r.step1, Tb, sp.l2a, sp.l2b);
+    r.corner = run(*r.step2, a, sp.l3a, sp.l3b);
+    return r;
+}
+
+// ---- rocBLAS/rocSOLVER status -------------------------------------------
+void rb_check(rocblas_status st, const char* what) {
+    if (st != rocblas_status_success)
+        fail(SYMTEN_E_LINALG, std::string(what) + " failed: " + rocblas_status_to_string(st));
+}
+
+struct Timer {
+    hipEvent_t e[8];
+    int n = 0;
+    bool on = false;
+    void init(bool enable) {
+        on = enable;
+        if (on) for (auto& x : e) HIPCHK(hipEventCreate(&x));
+    }
+    void mark(hipStream_t s) {
+        if (on && n < 8) HIPCHK(hipEventRecord(e[n++], s));
+    }
+    double ms(int a, int b) {
+        float t = 0.f;
+        if (!on || b >= n) return 0.0;
+        HIPCHK(hipEventElapsedTime(&t, e[a], e[b]));
+        return t;
+    }
+    ~Timer() {
+        if (on) for (auto& x : e) (void)hipEventDestroy(x);
+    }
+};
+}  // namespace
+
+}  // namespace symten
+
+using namespace symten;
+
+struct ctm_env {
+    TensorPtr C[4], T[4];
+    std::vector<double> svals;
+    symten_tensor P, Pt;
+    rocblas_handle rb = nullptr;
+    ~ctm_env() {
+        if (rb) rocblas_destroy_handle(rb);
+    }
+};
+
+// ============================================================ kernels used
+// by the projector stage (small, FP64)
+namespace symten {
+__global__ void extract_upper_kernel(const double* __restrict__ W, int ldw, int r, int n, double* __restrict__ R,
+                                     int ldr) {
+    const int64_t tot = (int64_t)r * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int row = (int)(i % r), col = (int)(i / r);
+        R[row + (int64_t)col * ldr] = row <= col ? W[row + (int64_t)col * ldw] : 0.0;
+    }
+}
+__global__ void scale_cols_kernel(double* __restrict__ X, int ld, int rows, int cols, const double* __restrict__ s) {
+    const int64_t tot = (int64_t)rows * cols;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int row = (int)(i % rows), col = (int)(i / rows);
+        X[row + (int64_t)col * ld] *= 1.0 / sqrt(s[col]);
+    }
+}
+__global__ void scale_rows_kernel(double* __restrict__ X, int ld, int rows, int cols, const double* __restrict__ s) {
+    const int64_t tot = (int64_t)rows * cols;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int row = (int)(i % rows), col = (int)(i / rows);
+        X[row + (int64_t)col * ld] *= 1.0 / sqrt(s[row]);
+    }
+}
+static int g1d(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+void launch_extract_upper(const double* W, int ldw, int r, int n, double* R, int ldr, hipStream_t s) {
+    if ((int64_t)r * n == 0) return;
+    hipLaunchKernelGGL(extract_upper_kernel, dim3(g1d((int64_t)r * n)), dim3(256), 0, s, W, ldw, r, n, R, ldr);
+    HIPCHK(hipGetLastError());
+}
+void launch_scale_cols(double* X, int ld, int rows, int cols, const double* sv, hipStream_t st) {
+    if ((int64_t)rows * cols == 0) return;
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(g1d((int64_t)rows * cols)), dim3(256), 0, st, X, ld, rows, cols, sv);
+    HIPCHK(hipGetLastError());
+}
+void launch_scale_rows(double* X, int ld, int rows, int cols, const double* sv, hipStream_t st) {
+    if ((int64_t)rows * cols == 0) return;
+    hipLaunchKernelGGL(scale_rows_kernel, dim3(g1d((int64_t)rows * cols)), dim3(256), 0, st, X, ld, rows, cols, sv);
+    HIPCHK(hipGetLastError());
+}
+}  // namespace symten
+
+namespace {
+
+TensorPtr make_desc_tensor(const symten_desc* d) {
+    if (!d) fail(SYMTEN_E_INVAL, "null descriptor");
+    if (d->group == SYMTEN_SU2) fail(SYMTEN_E_UNSUPPORTED, "SU(2) tensors are not implemented");
+    if (d->group != SYMTEN_U1) fail(SYMTEN_E_INVAL, "unknown symmetry group");
+    if (d->rank < 1 || d->rank > SYMTEN_MAX_RANK) fail(SYMTEN_E_INVAL, "rank must be 1..8");
+    if (!d->dirs || !d->nsec || !d->labels || !d->dims) fail(SYMTEN_E_INVAL, "null array in descriptor");
+    if (d->dtype != SYMTEN_F64 && d->dtype != SYMTEN_F32) fail(SYMTEN_E_INVAL, "dtype must be F64 or F32");
+    auto t = std::make_shared<Tensor>();
+    t->group = d->group;
+    t->flux = d->flux;
+    t->dtype = d->dtype;
+    int pos = 0;
+    for (int l = 0; l < d->rank; ++l) {
+        if (d->dirs[l] != 1 && d->dirs[l] != -1) fail(SYMTEN_E_INVAL, "leg direction must be +1 or -1");
+        if (d->nsec[l] < 0 || d->nsec[l] > 4096) fail(SYMTEN_E_INVAL, "bad sector count");
+        std::vector<std::pair<int, int>> secs;
+        for (int s = 0; s < d->nsec[l]; ++s, ++pos) {
+            if (d->dims[pos] < 0) fail(SYMTEN_E_INVAL, "negative sector dimension");
+            if (d->dims[pos] > 0) secs.push_back({d->labels[pos], d->dims[pos]});
+        }
+        std::sort(secs.begin(), secs.end());
+        for (size_t i = 1; i < secs.size(); ++i)
+            if (secs[i].first == secs[i - 1].first) fail(SYMTEN_E_INVAL, "duplicate sector label on a leg");
+        Leg L;
+        L.dir = d->dirs[l];
+        for (auto& s : secs) { L.q.push_back(s.first); L.d.push_back(s.second); }
+        t->legs.push_back(L);
+    }
+    t->elems = enumerate_blocks(*t);
+    return t;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* symten_last_error(void) { return g_err.c_str(); }
+int symten_version(void) { return 1; }
+
+int symten_sync(void* stream) {
+    return guard([&] { HIPCHK(hipStreamSynchronize(S(stream))); });
+}
+
+int symten_create_meta(symten_t* out, const symten_desc* d) {
+    return guard([&] {
+        if (!out) fail(SYMTEN_E_INVAL, "null output");
+        *out = wrap(make_desc_tensor(d));
+    });
+}
+
+int symten_create(symten_t* out, const symten_desc* d, void* stream) {
+    return guard([&] {
+        if (!out) fail(SYMTEN_E_INVAL, "null output");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+            (void)hipGetLastError();
+            fail(SYMTEN_E_NODEVICE, "no GPU available");
+        }
+        auto t = make_desc_tensor(d);
+        t->buf = device_alloc(std::max<int64_t>(t->elems, 1) * t->esize());
+        t->meta_only = false;
+        launch_fill_zero(t->buf->ptr, ((std::max<int64_t>(t->elems, 1) * t->esize() + 3) / 4) * 4, S(stream));
+        *out = wrap(t);
+    });
+}
+
+void symten_destroy(symten_t t) { delete t; }
+
+int symten_rank(symten_t t, int* r) {
+    return guard([&] { if (!r) fail(SYMTEN_E_INVAL, "null"); *r = T(t).rank(); });
+}
+int symten_flux(symten_t t, int* f) {
+    return guard([&] { if (!f) fail(SYMTEN_E_INVAL, "null"); *f = T(t).flux; });
+}
+int symten_dtype(symten_t t, int* d) {
+    return guard([&] { if (!d) fail(SYMTEN_E_INVAL, "null"); *d = T(t).dtype; });
+}
+int symten_leg_info(symten_t t, int leg, int* dir, int* nsec, int* labels, int* dims) {
+    return guard([&] {
+        Tensor& x = T(t);
+        if (leg < 0 || leg >= x.rank()) fail(SYMTEN_E_INVAL, "leg out of range");
+        const Leg& L = x.legs[leg];
+        if (dir) *dir = L.dir;
+        if (nsec) *nsec = (int)L.q.size();
+        for (size_t i = 0; i < L.q.size(); ++i) {
+            if (labels) labels[i] = L.q[i];
+            if (dims) dims[i] = L.d[i];
+        }
+    });
+}
+int symten_num_blocks(symten_t t, int64_t* n) {
+    return guard([&] { if (!n) fail(SYMTEN_E_INVAL, "null"); *n = (int64_t)T(t).blocks.size(); });
+}
+int symten_nnz(symten_t t, int64_t* n) {
+    return guard([&] { if (!n) fail(SYMTEN_E_INVAL, "null"); *n = T(t).nnz(); });
+}
+int symten_block_info(symten_t t, int64_t i, int* labels, int* shape, int64_t* offset, int64_t* strides) {
+    return guard([&] {
+        Tensor& x = T(t);
+        if (i < 0 || i >= (int64_t)x.blocks.size()) fail(SYMTEN_E_INVAL, "block index out of range");
+        const Block& b = x.blocks[i];
+        for (int l = 0; l < x.rank(); ++l) {
+            if (labels) labels[l] = b.q[l];
+            if (shape) shape[l] = b.shape[l];
+            if (strides) strides[l] = b.stride[l];
+        }
+        if (offset) *offset = b.offset;
+    });
+}
+int symten_device_ptr(symten_t t, void** ptr, int64_t* elems) {
+    return guard([&] {
+        Tensor& x = T(t);
+        if (ptr) *ptr = x.data();
+        if (elems) *elems = x.elems;
+    });
+}
+
+int symten_upload(symten_t t, const double* values, int64_t n, void* stream) {
+    return guard([&] {
+        Tensor& x = T(t);
+        check_device_tensor(x, "upload");
+        if (n != x.nnz()) fail(SYMTEN_E_INVAL, "upload: value count differs from nnz");
+        if (n > 0 && !values) fail(SYMTEN_E_INVAL, "upload: null values");
+        const size_t es = x.esize();
+        std::vector<char> host((size_t)std::max<int64_t>(x.elems, 1) * es, 0);
+        HIPCHK(hipStreamSynchronize(S(stream)));
+        HIPCHK(hipMemcpy(host.data(), x.data(), x.elems * es, hipMemcpyDeviceToHost));
+        int64_t pos = 0;
+        for (auto& b : x.blocks) {
+            const int R = x.rank();
+            std::vector<int> idx(R, 0);
+            for (int64_t e = 0; e < b.size; ++e) {
+                int64_t off = b.offset;
+                for (int l = 0; l < R; ++l) off += idx[l] * b.stride[l];
+                const double v = values[pos++];
+                if (x.dtype == SYMTEN_F64) ((double*)host.data())[off] = v;
+                else ((float*)host.data())[off] = (float)v;
+                for (int l = R - 1; l >= 0; --l) {
+                    if (++idx[l] < b.shape[l]) break;
+                    idx[l] = 0;
+                }
+            }
+        }
+        HIPCHK(hipMemcpy(x.data(), host.data(), x.elems * es, hipMemcpyHostToDevice));
+    });
+}
+
+int symten_download(symten_t t, double* values, int64_t n, void* stream) {
+    return guard([&] {
+        Tensor& x = T(t);
+        check_device_tensor(x, "download");
+        if (n != x.nnz()) fail(SYMTEN_E_INVAL, "download: value count differs from nnz");
+        if (n > 0 && !values) fail(SYMTEN_E_INVAL, "download: null values");
+        const size_t es = x.esize();
+        std::vector<char> host((size_t)std::max<int64_t>(x.elems, 1) * es, 0);
+        HIPCHK(hipStreamSynchronize(S(stream)));
+        HIPCHK(hipMemcpy(host.data(), x.data(), x.elems * es, hipMemcpyDeviceToHost));
+        int64_t pos = 0;
+        for (auto& b : x.blocks) {
+            const int R = x.rank();
+            std::vector<int> idx(R, 0);
+            for (int64_t e = 0; e < b.size; ++e) {
+                int64_t off = b.offset;
+                for (int l = 0; l < R; ++l) off += idx[l] * b.stride[l];
+                values[pos++] = x.dtype == SYMTEN_F64 ? ((double*)host.data())[off] : (double)((float*)host.data())[off];
+                for (int l = R - 1; l >= 0; --l) {
+                    if (++idx[l] < b.shape[l]) break;
+                    idx[l] = 0;
+                }
+            }
+        }
+    });
+}
+
+int symten_plan_info(symten_t A, symten_t B, int ncon, const int* legsA, const int* legsB, const int* out_perm,
+                     symten_plan_stats* info, symten_t* out) {
+    return guard([&] {
+        auto p = plan_contraction(T(A), T(B), ncon, legsA, legsB, out_perm, T(A).dtype == SYMTEN_F64 ? SYMTEN_PREC_F64 : SYMTEN_PREC_F32);
+        if (info) *info = p->info;
+        if (out) *out = wrap(std::make_shared<Tensor>(*p->out_meta));
+    });
+}
+
+int symten_contract(symten_t* out, symten_t A, symten_t B, int ncon, const int* legsA, const int* legsB,
+                    const int* out_perm, int prec, void* stream) {
+    return guard([&] {
+        if (!out) fail(SYMTEN_E_INVAL, "null output");
+        auto p = get_plan(T(A), T(B), ncon, legsA, legsB, out_perm, prec);
+        *out = wrap(run_contraction(*p, T(A), T(B), S(stream)));
+    });
+}
+
+int symten_double_layer(symten_t* a_out, symten_t A, void* stream) {
+    return guard([&] {
+        if (!a_out) fail(SYMTEN_E_INVAL, "null output");
+        *a_out = wrap(double_layer(T(A), S(stream)));
+    });
+}
+
+int symten_enlarged_corner(symten_t* out, int which, symten_t C, symten_t Ta, symten_t Tb, symten_t a, int prec,
+                           symten_plan_stats* info, void* stream) {
+    return guard([&] {
+        if (!out) fail(SYMTEN_E_INVAL, "null output");
+        CornerResult r = corner(which, T(C), T(Ta), T(Tb), T(a), prec, S(stream));
+        if (info) *info = r.info;
+        *out = wrap(r.corner);
+    });
+}
+
+}  // extern "C"
+
+// ---- batched corners ------------------------------------------------------
+namespace {
+struct BatchStep {
+    std::vector<std::shared_ptr<ContractPlan>> plans;
+    BufferPtr tasks, prefix, groups, tiles, ptrs, apanel, bpanel, out;
+    int ntasks = 0, ntiles = 0, cfg = 0;
+    int64_t nchunks = 0;
+    std::vector<int64_t> c_base;
+    std::vector<void*> table;     // host copy of the pointer table
+    bool src_f64 = false, panel_f64 = false;
+    Prec prec = Prec::F32;
+    symten_plan_stats info{};
+};
+struct BatchState {
+    int n = 0;
+    BatchStep step[3];
+    std::vector<TensorPtr> outs[3];
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void*> inputs;    // data pointers the tables were built for
+    ~BatchState() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+std::mutex g_batch_mu;
+std::map<std::string, std::shared_ptr<BatchState>> g_batch;
+
+// Concatenate the per-contraction plans of one step into one launch pair.
+void build_step(BatchStep& B, const std::vector<const Tensor*>& As, const std::vector<const Tensor*>& Bs, int n) {
+    std::vector<CopyTask> tasks;
+    std::vector<GemmGroup> groups;
+    std::vector<int64_t> a_base(n), b_base(n);
+    int64_t ap = 0, bp = 0, cp = 0;
+    B.c_base.assign(n, 0);
+    B.info = {};
+    for (int i = 0; i < n; ++i) {
+        const ContractPlan& p = *B.plans[i];
+        a_base[i] = ap;
+        b_base[i] = bp;
+        B.c_base[i] = cp;
+        ap += (p.a_panel_elems + 31) / 32 * 32;
+        bp += (p.b_panel_elems + 31) / 32 * 32;
+        cp += (p.out_elems + 31) / 32 * 32;
+        add_info(B.info, p.info);
+        for (CopyTask t : p.copies) {
+            if (t.src_buf == 0) t.src_buf = i;
+            else if (t.src_buf == 1) t.src_buf = n + i;
+            if (t.dst_buf == 2) { t.dst_buf = 2 * n; t.dst_off += a_base[i]; }
+            else { t.dst_buf = 2 * n + 1; t.dst_off += b_base[i]; }
+            tasks.push_back(t);
+        }
+        for (auto& g : p.groups) {
+            GemmGroup x{};
+            x.a_off = g.a_off + a_base[i];
+            x.b_off = g.b_off + b_base[i];
+            x.c_off = g.c_off + B.c_base[i];
+            x.M = g.M;
+            x.N = g.N;
+            x.K = g.K;
+            x.lda = x.ldb = g.lda;
+            x.ldc = g.N;
+            x.a_buf = 2 * n;
+            x.b_buf = 2 * n + 1;
+            x.c_buf = 2 * n + 2;
+            groups.push_back(x);
+        }
+    }
+    B.prec = B.plans[0]->prec;
+    B.panel_f64 = B.plans[0]->panel_f64;
+    B.src_f64 = As[0]->dtype == SYMTEN_F64;
+    for (int i = 0; i < n; ++i)
+        if (B.plans[i]->prec != B.prec || (As[i]->dtype == SYMTEN_F64) != B.src_f64)
+            fail(SYMTEN_E_INVAL, "batched corners: inputs differ in storage type");
+    {
+        std::vector<int64_t> sizes(2 * n + 3);
+        for (int i = 0; i < n; ++i) { sizes[i] = As[i]->elems; sizes[n + i] = Bs[i]->elems; }
+        sizes[2 * n] = ap;
+        sizes[2 * n + 1] = bp;
+        sizes[2 * n + 2] = cp;
+        validate_tasks(tasks, sizes);
+        validate_groups(groups, sizes, B.panel_f64 ? 2 : 4);
+    }
+    const size_t pe = B.panel_f64 ? 8 : 4;
+    const size_t oe = B.src_f64 ? 8 : 4;
+    B.apanel = device_alloc(std::max<int64_t>(ap, 1) * pe);
+    B.bpanel = device_alloc(std::max<int64_t>(bp, 1) * pe);
+    B.out = device_alloc(std::max<int64_t>(cp, 1) * oe);
+    std::vector<int64_t> prefix;
+    copy_prefix(tasks, prefix);
+    B.ntasks = (int)tasks.size();
+    B.nchunks = prefix.back();
+    upload_sync(B.tasks, tasks.data(), tasks.size() * sizeof(CopyTask));
+    upload_sync(B.prefix, prefix.data(), prefix.size() * sizeof(int64_t));
+    B.cfg = (B.info.max_m >= 128 && B.info.max_n >= 128) ? 1 : 0;
+    std::vector<TileWork> tiles;
+    build_tiles(groups, B.prec, B.cfg, tiles);
+    B.ntiles = (int)tiles.size();
+    upload_sync(B.groups, groups.data(), groups.size() * sizeof(GemmGroup));
+    upload_sync(B.tiles, tiles.data(), tiles.size() * sizeof(TileWork));
+    B.ptrs = device_alloc(sizeof(void*) * (2 * n + 3));
+}
+
+void set_table(BatchStep& B, const std::vector<void*>& a, const std::vector<void*>& b) {
+    const int n = (int)a.size();
+    std::vector<void*> t(2 * n + 3);
+    for (int i = 0; i < n; ++i) { t[i] = a[i]; t[n + i] = b[i]; }
+    t[2 * n] = B.apanel->ptr;
+    t[2 * n + 1] = B.bpanel->ptr;
+    t[2 * n + 2] = B.out->ptr;
+    if (t != B.table) {
+        HIPCHK(hipMemcpy(B.ptrs->ptr, t.data(), t.size() * sizeof(void*), hipMemcpyHostToDevice));
+        B.table = t;
+    }
+}
+
+void run_step(const BatchStep& B, hipStream_t s) {
+    copy_launch_dev((const CopyTask*)B.tasks->ptr, (const int64_t*)B.prefix->ptr, B.ntasks, B.nchunks,
+                    (void* const*)B.ptrs->ptr, B.src_f64, B.panel_f64, s);
+    gemm_launch_dev((const TileWork*)B.tiles->ptr, B.ntiles, (const GemmGroup*)B.groups->ptr,
+                    (void* const*)B.ptrs->ptr, B.prec, B.cfg, s);
+}
+
+std::vector<TensorPtr> step_outputs(const BatchStep& B, int n) {
+    std::vector<TensorPtr> outs(n);
+    const size_t es = B.src_f64 ? 8 : 4;
+    for (int i = 0; i < n; ++i) {
+        auto t = std::make_shared<Tensor>(*B.plans[i]->out_meta);
+        // a view into the step's shared output buffer
+        for (auto& b : t->blocks) b.offset += B.c_base[i];
+        t->elems = B.c_base[i] + B.plans[i]->out_elems;
+        t->buf = B.out;
+        t->meta_only = false;
+        outs[i] = t;
+        (void)es;
+    }
+    return outs;
+}
+}  // namespace
+
+extern "C" {
+
+int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, const symten_t* Tas,
+                                    const symten_t* Tbs, const symten_t* as, int prec, int use_graph,
+                                    symten_plan_stats* info, void* stream) {
+    return guard([&] {
+        if (n <= 0 || !out || !Cs || !Tas || !Tbs || !as) fail(SYMTEN_E_INVAL, "batched corners: bad arguments");
+        const hipStream_t s = S(stream);
+        std::string key = std::to_string(n) + "|" + std::to_string(prec) + "|";
+        std::vector<void*> inputs;
+        for (int i = 0; i < n; ++i) {
+            for (symten_t h : {Cs[i], Tas[i], Tbs[i], as[i]}) {
+                check_device_tensor(T(h), "batched corners");
+                key += tensor_signature(T(h)) + "&";
+                inputs.push_back(T(h).data());
+            }
+        }
+        std::shared_ptr<BatchState> st;
+        {
+            std::lock_guard<std::mutex> lk(g_batch_mu);
+            auto it = g_batch.find(key);
+            if (it != g_batch.end()) st = it->second;
+        }
+        const CornerSpec sp = corner_spec(1);
+        if (!st) {
+            st = std::make_shared<BatchState>();
+            st->n = n;
+            std::vector<const Tensor*> A1, B1, B2, B3;
+            for (int i = 0; i < n; ++i) {
+                A1.push_back(&T(Cs[i]));
+                B1.push_back(&T(Tas[i]));
+                B2.push_back(&T(Tbs[i]));
+                B3.push_back(&T(as[i]));
+            }
+            for (int i = 0; i < n; ++i)
+                st->step[0].plans.push_back(get_plan(*A1[i], *B1[i], 1, sp.l1a.data(), sp.l1b.data(), nullptr, prec));
+            build_step(st->step[0], A1, B1, n);
+            st->outs[0] = step_outputs(st->step[0], n);
+            std::vector<const Tensor*> A2;
+            for (int i = 0; i < n; ++i) {
+                A2.push_back(st->outs[0][i].get());
+                st->step[1].plans.push_back(get_plan(*A2[i], *B2[i], 1, sp.l2a.data(), sp.l2b.data(), nullptr, prec));
+            }
+            build_step(st->step[1], A2, B2, n);
+            st->outs[1] = step_outputs(st->step[1], n);
+            std::vector<const Tensor*> A3;
+            for (int i = 0; i < n; ++i) {
+                A3.push_back(st->outs[1][i].get());
+                st->step[2].plans.push_back(get_plan(*A3[i], *B3[i], 2, sp.l3a.data(), sp.l3b.data(), nullptr, prec));
+            }
+            build_step(st->step[2], A3, B3, n);
+            st->outs[2] = step_outputs(st->step[2], n);
+            std::lock_guard<std::mutex> lk(g_batch_mu);
+            if (g_batch.size() > 16) g_batch.clear();
+            g_batch[key] = st;
+        }
+        if (st->inputs != inputs) {
+            // (re)point the tables at the current input buffers
+            std::vector<void*> c(n), t1(n), t4(n), a(n), o1(n), o2(n);
+            const size_t es = st->step[0].src_f64 ? 8 : 4;
+            for (int i = 0; i < n; ++i) {
+                c[i] = inputs[4 * i];
+                t1[i] = inputs[4 * i + 1];
+                t4[i] = inputs[4 * i + 2];
+                a[i] = inputs[4 * i + 3];
+                o1[i] = (char*)st->step[0].out->ptr;
+                o2[i] = (char*)st->step[1].out->ptr;
+                (void)es;
+            }
+            set_table(st->step[0], c, t1);
+            set_table(st->step[1], o1, t4);
+            set_table(st->step[2], o2, a);
+            st->inputs = inputs;
+            if (st->exec) {
+                (void)hipGraphExecDestroy(st->exec);
+                (void)hipGraphDestroy(st->graph);
+                st->exec = nullptr;
+                st->graph = nullptr;
+            }
+        }
+        if (use_graph) {
+            if (!st->exec) {
+                HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                try {
+                    for (int k = 0; k < 3; ++k) run_step(st->step[k], s);
+                } catch (...) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(s, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                HIPCHK(hipStreamEndCapture(s, &st->graph));
+                HIPCHK(hipGraphInstantiate(&st->exec, st->graph, nullptr, nullptr, 0));
+            }
+            HIPCHK(hipGraphLaunch(st->exec, s));
+        } else {
+            for (int k = 0; k < 3; ++k) run_step(st->step[k], s);
+        }
+        if (info) {
+            *info = {};
+            for (int k = 0; k < 3; ++k) add_info(*info, st->step[k].info);
+        }
+        for (int i = 0; i < n; ++i) out[i] = wrap(st->outs[2][i]);
+    });
+}
+
+int ctm_env_create(ctm_env_t* env, const symten_t C[4], const symten_t Tt[4]) {
+    return guard([&] {
+        if (!env || !C || !Tt) fail(SYMTEN_E_INVAL, "null argument");
+        auto* e = new ctm_env();
+        try {
+            for (int i = 0; i < 4; ++i) {
+                e->C[i] = T(C[i]).buf ? C[i]->t : nullptr;
+                e->T[i] = T(Tt[i]).buf ? Tt[i]->t : nullptr;
+                if (!e->C[i] || !e->T[i]) fail(SYMTEN_E_INVAL, "environment tensors need device storage");
+                if (e->C[i]->rank() != 2 || e->T[i]->rank() != 3) fail(SYMTEN_E_INVAL, "C must be rank 2 and T rank 3");
+            }
+            rb_check(rocblas_create_handle(&e->rb), "rocblas_create_handle");
+        } catch (...) {
+            delete e;
+            throw;
+        }
+        *env = e;
+    });
+}
+
+void ctm_env_destroy(ctm_env_t env) { delete env; }
+
+int ctm_env_get(ctm_env_t env, int k, symten_t* t) {
+    return guard([&] {
+        if (!env || !t || k < 0 || k > 7) fail(SYMTEN_E_INVAL, "bad argument");
+        *t = wrap(k < 4 ? env->C[k] : env->T[k - 4]);
+    });
+}
+
+int ctm_move_singular_values(ctm_env_t env, double* s, int64_t cap, int64_t* n) {
+    return guard([&] {
+        if (!env || !n) fail(SYMTEN_E_INVAL, "bad argument");
+        *n = (int64_t)env->svals.size();
+        if (s) std::copy(env->svals.begin(), env->svals.begin() + std::min<int64_t>(cap, *n), s);
+    });
+}
+
+int ctm_move_projectors(ctm_env_t env, symten_t* P, symten_t* Pt) {
+    return guard([&] {
+        if (!env || !env->P.t) fail(SYMTEN_E_INVAL, "no move has run");
+        if (P) *P = wrap(env->P.t);
+        if (Pt) *Pt = wrap(env->Pt.t);
+    });
+}
+
+int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_stats* st, void* stream) {
+    return guard([&] {
+        if (!env) fail(SYMTEN_E_INVAL, "null environment");
+        if (dir != CTM_LEFT) fail(SYMTEN_E_UNSUPPORTED, "only the left move is implemented");
+        if (chi < 1) fail(SYMTEN_E_INVAL, "chi must be positive");
+        Tensor& a = T(a_h);
+        check_device_tensor(a, "ctm_move(a)");
+        if (a.rank() != 4) fail(SYMTEN_E_INVAL, "a must have rank 4");
+        const hipStream_t s = S(stream);
+        const bool f64 = prec == SYMTEN_PREC_F64;
+        for (int i = 0; i < 4; ++i)
+            if ((env->C[i]->dtype == SYMTEN_F64) != f64 || (env->T[i]->dtype == SYMTEN_F64) != f64 ||
+                (a.dtype == SYMTEN_F64) != f64)
+                fail(SYMTEN_E_INVAL, "ctm_move: storage types do not match the precision");
+        Timer tm;
+        tm.init(st != nullptr);
+        tm.mark(s);
+        Tensor &C1 = *env->C[0], &C2 = *env->C[1], &C3 = *env->C[2], &C4 = *env->C[3];
+        Tensor &T1 = *env->T[0], &T2 = *env->T[1], &T3 = *env->T[2], &T4 = *env->T[3];
+        CornerResult k1 = corner(1, C1, T1, T4, a, prec, s);
+        CornerResult k2 = corner(2, C2, T1, T2, a, prec, s);
+        CornerResult k3 = corner(3, C3, T3, T2, a, prec, s);
+        CornerResult k4 = corner(4, C4, T3, T4, a, prec, s);
+        tm.mark(s);
+        // halves: H_u = C~1 C~2 -> [x4, d, x2, d2]; H_d = C~4 C~3 -> [x4, u, x2, u3]
+        Contracted hu = contract(*k1.corner, *k2.corner, {0, 2}, {0, 2}, {}, prec, s);
+        Contracted hd = contract(*k4.corner, *k3.corner, {0, 3}, {0, 2}, {}, prec, s);
+        tm.mark(s);
+
+        // ---- projectors, per fused charge Q of the left cut (FP64) ----------
+        rb_check(rocblas_set_stream(env->rb, s), "rocblas_set_stream");
+        struct QB {
+            int Q = 0, n = 0, m = 0, ru = 0, rd = 0, mn = 0;
+            const GroupPlan* gu = nullptr;
+            const GroupPlan* gd = nullptr;
+            BufferPtr W, Ru, Rd, M, U, Vt, S, E, tau, info;
+            int k = 0;
+        };
+        std::map<int, QB> qb;
+        for (auto& g : hu.plan->groups) {
+            const int Q = g.rows[0][0] - g.rows[0][1];
+            qb[Q].gu = &g;
+        }
+        for (auto& g : hd.plan->groups) {
+            const int Q = g.rows[0][0] - g.rows[0][1];
+            qb[Q].gd = &g;
+        }
+        const size_t es = f64 ? 8 : 4;
+        std::vector<int> qs;
+        for (auto& kv : qb) {
+            QB& b = kv.second;
+            b.Q = kv.first;
+            if (!b.gu || !b.gd) continue;   // no weight on one side: nothing to keep
+            if (b.gu->rows != b.gd->rows || b.gu->cols != b.gd->cols || b.gu->M != b.gd->M || b.gu->N != b.gd->N)
+                fail(SYMTEN_E_SYM, "ctm_move: upper and lower halves disagree on a cut basis");
+            b.n = b.gu->M;
+            b.m = b.gu->N;
+            qs.push_back(b.Q);
+        }
+        if (qs.empty()) fail(SYMTEN_E_LINALG, "ctm_move: the halves have no common charge sector");
+        std::vector<double> sv_host;
+        std::vector<int> sv_off;
+        {
+            // workspace: QR of H^T (col-major m x n = row-major n x m block of H)
+            for (int Q : qs) {
+                QB& b = qb[Q];
+                const int n = b.n, m = b.m;
+                b.ru = std::min(m, n);
+                b.rd = std::min(m, n);
+                b.mn = std::min(b.ru, b.rd);
+                b.tau = device_alloc(8 * std::max(1, std::min(m, n)));
+                b.info = device_alloc(8);
+                b.Ru = device_alloc(8 * (size_t)b.ru * n);
+                b.Rd = device_alloc(8 * (size_t)b.rd * n);
+                b.W = device_alloc(8 * (size_t)m * n);
+                for (int side = 0; side < 2; ++side) {
+                    const Tensor& H = side == 0 ? *hu.t : *hd.t;
+                    const GroupPlan* g = side == 0 ? b.gu : b.gd;
+                    const char* src = (const char*)H.data() + g->c_off * es;
+                    launch_cast(src, f64, b.W->ptr, true, (int64_t)m * n, s);
+                    rb_check(rocsolver_dgeqrf(env->rb, m, n, (double*)b.W->ptr, m, (double*)b.tau->ptr),
+                             "rocsolver_dgeqrf");
+                    launch_extract_upper((const double*)b.W->ptr, m, side == 0 ? b.ru : b.rd, n,
+                                         (double*)(side == 0 ? b.Ru : b.Rd)->ptr, side == 0 ? b.ru : b.rd, s);
+                }
+                // M = R_u R_d^T  (ru x rd)
+                b.M = device_alloc(8 * (size_t)b.ru * b.rd);
+                const double one = 1.0, zero = 0.0;
+                rb_check(rocblas_dgemm(env->rb, rocblas_operation_none, rocblas_operation_transpose, b.ru, b.rd, n, &one,
+                                       (const double*)b.Ru->ptr, b.ru, (const double*)b.Rd->ptr, b.rd, &zero,
+                                       (double*)b.M->ptr, b.ru),
+                         "rocblas_dgemm(M)");
+                b.S = device_alloc(8 * std::max(1, b.mn));
+                b.U = device_alloc(8 * (size_t)b.ru * b.mn);
+                b.Vt = device_alloc(8 * (size_t)b.mn * b.rd);
+                b.E = device_alloc(8 * std::max(1, b.mn));
+                rb_check(rocsolver_dgesvd(env->rb, rocblas_svect_singular, rocblas_svect_singular, b.ru, b.rd,
+                                          (double*)b.M->ptr, b.ru, (double*)b.S->ptr, (double*)b.U->ptr, b.ru,
+                                          (double*)b.Vt->ptr, b.mn, (double*)b.E->ptr, rocblas_outofplace,
+                                          (rocblas_int*)b.info->ptr),
+                         "rocsolver_dgesvd");
+            }
+            // singular values and status to the host (the one synchronisation)
+            int tot = 0;
+            for (int Q : qs) { sv_off.push_back(tot); tot += qb[Q].mn; }
+            sv_host.resize(tot);
+            std::vector<int> infos(qs.size());
+            for (size_t i = 0; i < qs.size(); ++i) {
+                QB& b = qb[qs[i]];
+                if (b.mn) HIPCHK(hipMemcpyAsync(sv_host.data() + sv_off[i], b.S->ptr, 8 * b.mn, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(&infos[i], b.info->ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+            }
+            HIPCHK(hipStreamSynchronize(s));
+            for (size_t i = 0; i < qs.size(); ++i)
+                if (infos[i] != 0) fail(SYMTEN_E_LINALG, "rocsolver_dgesvd did not converge");
+            for (double v : sv_host)
+                if (!std::isfinite(v)) fail(SYMTEN_E_LINALG, "non-finite singular value");
+        }
+        // ---- truncation: global top-chi, ties by charge then index ----------
+        struct SV { double s; int Q, j; };
+        std::vector<SV> all;
+        for (size_t i = 0; i < qs.size(); ++i)
+            for (int j = 0; j < qb[qs[i]].mn; ++j) all.push_back({sv_host[sv_off[i] + j], qs[i], j});
+        std::sort(all.begin(), all.end(), [](const SV& x, const SV& y) {
+            if (x.s != y.s) return x.s > y.s;
+            if (x.Q != y.Q) return x.Q < y.Q;
+            return x.j < y.j;
+        });
+        const double smax = all.empty() ? 0.0 : all[0].s;
+        int nkeep = 0;
+        while (nkeep < (int)all.size() && nkeep < chi && all[nkeep].s > 1e-14 * smax) ++nkeep;
+        if (nkeep == 0) fail(SYMTEN_E_LINALG, "ctm_move: no singular value above the cutoff");
+        double tot2 = 0.0, disc2 = 0.0;
+        for (size_t i = 0; i < all.size(); ++i) {
+            tot2 += all[i].s * all[i].s;
+            if ((int)i >= nkeep) disc2 += all[i].s * all[i].s;
+        }
+        for (int i = 0; i < nkeep; ++i) qb[all[i].Q].k += 1;
+        // the kept set of a sector is a prefix of its descending list
+        // ---- projector tensors P[chi out, D in, k in], P~[k out, chi in, D out]
+        const Leg& chiL = T4.legs[0];
+        const Leg& dL = a.legs[3];
+        auto P = std::make_shared<Tensor>();
+        auto Pt = std::make_shared<Tensor>();
+        for (auto* X : {P.get(), Pt.get()}) {
+            X->group = SYMTEN_U1;
+            X->flux = 0;
+            X->dtype = SYMTEN_F64;
+        }
+        Leg kin, kout;
+        kin.dir = 1;
+        kout.dir = -1;
+        for (int Q : qs)
+            if (qb[Q].k > 0) { kin.q.push_back(Q); kin.d.push_back(qb[Q].k); }
+        kout.q = kin.q;
+        kout.d = kin.d;
+        Leg chi_out = chiL, chi_in = chiL, d_in = dL, d_out = dL;
+        chi_out.dir = -1;
+        chi_in.dir = 1;
+        d_in.dir = 1;
+        d_out.dir = -1;
+        P->legs = {chi_out, d_in, kin};
+        Pt->legs = {kout, chi_in, d_out};
+        int64_t ptot = 0;
+        std::map<int, int64_t> pbase;
+        for (int Q : kin.q) { pbase[Q] = ptot; ptot += (int64_t)qb[Q].n * qb[Q].k; }
+        P->buf = device_alloc(8 * std::max<int64_t>(ptot, 1));
+        Pt->buf = device_alloc(8 * std::max<int64_t>(ptot, 1));
+        P->elems = Pt->elems = ptot;
+        P->meta_only = Pt->meta_only = false;
+        for (int Q : kin.q) {
+            QB& b = qb[Q];
+            const int n = b.n, k = b.k;
+            double* Pq = (double*)P->buf->ptr + pbase[Q];
+            double* Ptq = (double*)Pt->buf->ptr + pbase[Q];
+            const double one = 1.0, zero = 0.0;
+            // P = R_d^T V_k S^-1/2  (n x k, ld n); V_k = first k rows of V^T, transposed
+            rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_transpose, n, k, b.rd, &one,
+                                   (const double*)b.Rd->ptr, b.rd, (const double*)b.Vt->ptr, b.mn, &zero, Pq, n),
+                     "rocblas_dgemm(P)");
+            launch_scale_cols(Pq, n, n, k, (const double*)b.S->ptr, s);
+            // P~ = S^-1/2 U_k^T R_u  (k x n, ld k)
+            rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, k, n, b.ru, &one,
+                                   (const double*)b.U->ptr, b.ru, (const double*)b.Ru->ptr, b.ru, &zero, Ptq, k),
+                     "rocblas_dgemm(Pt)");
+            launch_scale_rows(Ptq, k, k, n, (const double*)b.S->ptr, s);
+            launch_sign_fix_rows(Ptq, k, k, n, Pq, n, s);
+            // blocks: one per (q_chi, q_D) row sub-block of this sector
+            const GroupPlan* g = b.gu;
+            for (size_t r = 0; r < g->rows.size(); ++r) {
+                const int qx = g->rows[r][0], qd = g->rows[r][1];
+                const int dx = chiL.dim_of(qx), dd = dL.dim_of(qd);
+                Block pb;
+                pb.q = {qx, qd, Q};
+                pb.shape = {dx, dd, k};
+                pb.stride = {dd, 1, n};
+                pb.offset = pbase[Q] + g->row_off[r];
+                pb.size = (int64_t)dx * dd * k;
+                P->blocks.push_back(pb);
+                Block tb;
+                tb.q = {Q, qx, qd};
+                tb.shape = {k, dx, dd};
+                tb.stride = {1, (int64_t)dd * k, k};
+                tb.offset = pbase[Q] + (int64_t)g->row_off[r] * k;
+                tb.size = pb.size;
+                Pt->blocks.push_back(tb);
+            }
+        }
+        for (auto* X : {P.get(), Pt.get()}) {
+            std::sort(X->blocks.begin(), X->blocks.end(), [](const Block& x, const Block& y) { return x.q < y.q; });
+            X->rebuild_index();
+        }
+        TensorPtr Pc = P, Ptc = Pt;
+        if (!f64) {
+            Pc = std::make_shared<Tensor>(*P);
+            Ptc = std::make_shared<Tensor>(*Pt);
+            Pc->dtype = Ptc->dtype = SYMTEN_F32;
+            Pc->buf = device_alloc(4 * std::max<int64_t>(ptot, 1));
+            Ptc->buf = device_alloc(4 * std::max<int64_t>(ptot, 1));
+            launch_cast(P->buf->ptr, true, Pc->buf->ptr, false, ptot, s);
+            launch_cast(Pt->buf->ptr, true, Ptc->buf->ptr, false, ptot, s);
+        }
+        tm.mark(s);
+        // ---- renormalise -----------------------------------------------------
+        Contracted c1n = contract(*k1.step1, *Pc, {0, 1}, {0, 1}, {1, 0}, prec, s);       // [k, x1]
+        Contracted t4a = contract(T4, a, {1}, {0}, {}, prec, s);                          // [y, x, u, r, d]
+        Contracted xx = contract(*t4a.t, *Pc, {0, 4}, {0, 1}, {}, prec, s);              // [x, u, r, k_lo]
+        Contracted t4n = contract(*Ptc, *xx.t, {1, 2}, {0, 1}, {2, 1, 0}, prec, s);     // [k_lo, r, k_hi]
+        Contracted c4n = contract(*k4.step1, *Ptc, {0, 2}, {1, 2}, {}, prec, s);          // [x3, k]
+        // ---- normalise in FP64 ----------------------------------------------
+        BufferPtr red = device_alloc(8 * (1 + 512));
+        for (TensorPtr X : {c1n.t, t4n.t, c4n.t}) {
+            launch_sumsq(X->data(), f64, X->elems, (double*)red->ptr, s);
+            launch_scale_by_inv_sqrt(X->data(), f64, X->elems, (const double*)red->ptr, s);
+        }
+        tm.mark(s);
+        env->C[0] = c1n.t;
+        env->T[3] = t4n.t;
+        env->C[3] = c4n.t;
+        env->P.t = P;
+        env->Pt.t = Pt;
+        env->svals.clear();
+        for (size_t i = 0; i < qs.size(); ++i)
+            for (int j = 0; j < qb[qs[i]].mn; ++j) env->svals.push_back(sv_host[sv_off[i] + j]);
+        if (st) {
+            std::memset(st, 0, sizeof(*st));
+            HIPCHK(hipStreamSynchronize(s));
+            st->nsec = std::min<int>((int)kin.q.size(), CTM_MAX_SECTORS);
+            for (int i = 0; i < st->nsec; ++i) { st->charge[i] = kin.q[i]; st->kept[i] = kin.d[i]; }
+            st->n_sv_sectors = std::min<int>((int)qs.size(), CTM_MAX_SECTORS);
+            for (int i = 0; i < st->n_sv_sectors; ++i) { st->sv_charge[i] = qs[i]; st->sv_count[i] = qb[qs[i]].mn; }
+            st->trunc_err = tot2 > 0 ? disc2 / tot2 : 0.0;
+            st->s_max = smax;
+            st->gap = nkeep < (int)all.size() ? (all[nkeep - 1].s - all[nkeep].s) / smax : INFINITY;
+            st->flops_corners = k1.info.useful_flops + k2.info.useful_flops + k3.info.useful_flops + k4.info.useful_flops;
+            st->flops_halves = hu.plan->info.useful_flops + hd.plan->info.useful_flops;
+            st->flops_renorm = c1n.plan->info.useful_flops + t4a.plan->info.useful_flops + xx.plan->info.useful_flops +
+                               t4n.plan->info.useful_flops + c4n.plan->info.useful_flops;
+            int64_t fp = 0;
+            for (int Q : qs) fp += 2LL * qb[Q].ru * qb[Q].rd * qb[Q].n;
+            st->flops_proj = fp;
+            st->ms_corners = tm.ms(0, 1);
+            st->ms_halves = tm.ms(1, 2);
+            st->ms_proj = tm.ms(2, 3);
+            st->ms_renorm = tm.ms(3, 4);
+            st->ms_total = tm.ms(0, 4);
+        }
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+// Internal data structures of libsymten: tensor metadata, contraction plans,
+// device work descriptors and the kernel launch interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/symten.h"
+
+namespace symten {
+
+// ---------------------------------------------------------------- errors ---
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define HIPCHK(x) ::symten::hip_check((x), #x)
+
+// ------------------------------------------------------------------ legs ---
+struct Leg {
+    int dir = 1;                 // +1 in, -1 out
+    std::vector<int> q;          // charges, ascending
+    std::vector<int> d;          // dims (all > 0)
+    int size() const { int s = 0; for (int x : d) s += x; return s; }
+    int index_of(int charge) const {
+        for (size_t i = 0; i < q.size(); ++i) if (q[i] == charge) return (int)i;
+        return -1;
+    }
+    int dim_of(int charge) const { int i = index_of(charge); return i < 0 ? 0 : d[i]; }
+    bool same_sectors(const Leg& o) const { return q == o.q && d == o.d; }
+};
+
+// ----------------------------------------------------------------- blocks ---
+struct Block {
+    std::vector<int> q;          // charge per leg
+    std::vector<int> shape;      // dims per leg
+    std::vector<int64_t> stride; // element strides per leg
+    int64_t offset = 0;          // element offset into the tensor buffer
+    int64_t size = 0;
+};
+
+// Caching device allocator (size-bucketed free lists, stream-ordered reuse).
+struct DeviceBuffer;
+using BufferPtr = std::shared_ptr<DeviceBuffer>;
+BufferPtr device_alloc(size_t bytes);
+struct DeviceBuffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    size_t cap = 0;
+    ~DeviceBuffer();
+};
+
+struct Tensor {
+    int group = SYMTEN_U1;
+    int flux = 0;
+    int dtype = SYMTEN_F32;
+    std::vector<Leg> legs;
+    std::vector<Block> blocks;               // canonical (lexicographic) order
+    std::map<std::vector<int>, int> index;   // charges -> block index
+    BufferPtr buf;                           // null for metadata-only handles
+    int64_t elems = 0;                       // buffer size in elements
+    bool meta_only = true;
+
+    int rank() const { return (int)legs.size(); }
+    int64_t nnz() const { int64_t s = 0; for (auto& b : blocks) s += b.size; return s; }
+    size_t esize() const { return dtype == SYMTEN_F64 ? 8 : 4; }
+    void* data() const { return buf ? buf->ptr : nullptr; }
+    void rebuild_index();
+};
+using TensorPtr = std::shared_ptr<Tensor>;
+
+// Allowed blocks of the given legs and flux, canonical order, contiguous
+// row-major layout; returns total element count.
+int64_t enumerate_blocks(Tensor& t);
+
+// ------------------------------------------------------------- device ops ---
+// Strided copy task: iterate a multi-index over dims (last fastest);
+// dst[dst_off + sum i*dstride] = src[src_off + sum i*sstride] (or 0 when
+// src_buf < 0).  Buffers are named by index into a pointer table.
+constexpr int kMaxCopyRank = 8;
+struct CopyTask {
+    int64_t src_off, dst_off;
+    int64_t sstride[kMaxCopyRank];
+    int64_t dstride[kMaxCopyRank];
+    int dims[kMaxCopyRank];
+    int rank;
+    int src_buf, dst_buf;
+    int count;          // product of dims (< 2^31)
+    float scale;        // multiplies the copied value
+    int pad_;
+};
+
+struct GemmGroup {
+    int64_t a_off, b_off, c_off;   // element offsets into their buffers
+    int M, N, K;
+    int lda, ldb, ldc;             // A: [M][lda] (K contiguous); B: [N][ldb]; C: [M][ldc]
+    int a_buf, b_buf, c_buf;
+    int tiles_n;                   // tiles along N (for tile decoding)
+    int pad_;
+};
+
+struct TileWork {
+    int group, tm, tn, kz;
+};
+
+// Pointer table handed to the kernels (device addresses).
+constexpr int kMaxBufs = 512;
+
+// Element type of a panel / buffer in a GEMM launch.
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X3 = 3 };
+
+struct LaunchCtx;   // owns staging memory for descriptors
+
+// Launch the strided copies (all tasks) on `stream`.  `bufs` are device
+// pointers; elements are double when is_f64, else float.  Source and
+// destination may have different types (src_f64 / dst_f64).
+void launch_copies(const std::vector<CopyTask>& tasks, const std::vector<void*>& bufs,
+                   bool src_f64, bool dst_f64, hipStream_t stream);
+
+// Grouped GEMM C_g = A_g * B_g^T over all groups, one launch per tile shape.
+void launch_grouped_gemm(const std::vector<GemmGroup>& groups, const std::vector<void*>& bufs,
+                         Prec prec, hipStream_t stream);
+
+void launch_cast(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n, hipStream_t s);
+void launch_fill_zero(void* dst, int64_t bytes, hipStream_t s);
+// FP64 sum of squares of n elements into *out (device double), then scale.
+void launch_sumsq(const void* x, bool f64, int64_t n, double* out, hipStream_t s);
+void launch_scale_by_inv_sqrt(void* x, bool f64, int64_t n, const double* sumsq, hipStream_t s);
+
+// Double layer.  Fused-leg tables are device int arrays.
+struct DoubleLayerArgs {
+    const void* A_dense;   // [phys][D0][D1][D2][D3] dense copy of A (same dtype)
+    int nphys, Dv[4];
+    const int* ket_of[4];  // fused state -> ket state
+    const int* bra_of[4];
+    const int64_t* blk_off;   // per output block offset
+    const int* blk_start;     // per output block first fused state per leg [nb*4]
+    const int* blk_shape;     // [nb*4]
+    const int64_t* blk_elem_start; // prefix of block sizes [nb+1]
+    int nblocks;
+    int64_t total;
+    void* out;
+    bool f64;
+};
+void launch_double_layer(const DoubleLayerArgs& a, hipStream_t s);
+// scatter of a contiguous-block tensor into a dense array
+void launch_sign_fix_rows(double* Pt, int ldPt, int rows, int n, double* P, int ldP, hipStream_t s);
+
+// -------------------------------------------------------------- contraction --
+struct GroupPlan {
+    int key;                      // contracted charge as seen from A
+    int M, N, K, lda;
+    int64_t a_off, b_off, c_off;  // into A panel ws, B panel ws, output buffer
+    std::vector<std::vector<int>> rows;   // alpha tuples (charges), in order
+    std::vector<std::vector<int>> cols;   // beta tuples
+    std::vector<int> row_off, col_off;
+};
+
+struct ContractPlan {
+    TensorPtr out_meta;                   // metadata of the output (no buffer)
+    std::vector<GroupPlan> groups;
+    std::vector<CopyTask> copies;         // bufs: 0 = A data, 1 = B data, 2 = A panels, 3 = B panels
+    int64_t a_panel_elems = 0, b_panel_elems = 0, out_elems = 0;
+    symten_plan_stats info{};
+    Prec prec = Prec::F32;
+    bool panel_f64 = false;
+    mutable std::shared_ptr<void> dev;    // device copies of the descriptors
+};
+
+// Build the plan (host only).  Throws Error on invalid input.
+std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B, int ncon,
+                                               const int* legsA, const int* legsB,
+                                               const int* out_perm, int prec);
+
+// Execute a plan: allocates the output buffer, gathers panels, runs the GEMMs.
+TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& B,
+                          hipStream_t stream);
+
+// Execute many plans with one gather launch and one GEMM launch.
+std::vector<TensorPtr> run_contractions_batched(
+    const std::vector<const ContractPlan*>& plans, const std::vector<const Tensor*>& As,
+    const std::vector<const Tensor*>& Bs, hipStream_t stream);
+
+TensorPtr double_layer(const Tensor& A, hipStream_t stream);
+
+// helpers
+std::string tensor_signature(const Tensor& t);
+void check_device_tensor(const Tensor& t, const char* what);
+
+}  // namespace symten

@@ -1,0 +1,663 @@
+// Device kernels of libsymten for gfx950 (CDNA4, 64-wide wavefronts).
+//
+//  * copy_kernel      strided gather of tensor blocks into GEMM panels
+//                     (block -> [open, contracted] layout, K-concatenated per
+//                     charge sector), with type conversion and zero fill.
+//  * gemm_kernel      grouped GEMM C_g = A_g B_g^T over all charge sectors of
+//                     one or many contractions: LDS-staged tiles, MFMA
+//                     f64 16x16x4, f32 32x32x2, bf16 32x32x16 (plain and
+//                     three-product split precision), FP32/FP64 accumulation.
+//  * double_layer     a = sum_s A A* with fused (ket, bra) legs.
+//  * reductions       FP64 sum of squares (deterministic two-pass), scaling,
+//                     casts, sign gauge of projector rows.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace symten {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f16_t __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
+
+// Pointer table passed by value (single contraction) or by device pointer
+// (batched launches prepared ahead of time).
+struct ArgPtrs {
+    void* p[8];
+    __device__ __forceinline__ void* get(int i) const { return p[i]; }
+};
+struct DevPtrs {
+    void* const* p;
+    __device__ __forceinline__ void* get(int i) const { return p[i]; }
+};
+
+// ===================================================================== copy
+constexpr int kCopyChunk = 1024;
+constexpr int kCopyThreads = 256;
+
+template <class Ptrs, typename TS, typename TD>
+__global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __restrict__ tasks,
+                                                            const int64_t* __restrict__ chunk_prefix,
+                                                            int ntasks, Ptrs ptrs) {
+    const int64_t chunk = blockIdx.x;
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {                       // last task with prefix <= chunk
+        int mid = (lo + hi + 1) >> 1;
+        if (chunk_prefix[mid] <= chunk) lo = mid; else hi = mid - 1;
+    }
+    const CopyTask& T = tasks[lo];
+    const int64_t base = (chunk - chunk_prefix[lo]) * kCopyChunk;
+    const TS* __restrict__ src = T.src_buf >= 0 ? (const TS*)ptrs.get(T.src_buf) : nullptr;
+    TD* __restrict__ dst = (TD*)ptrs.get(T.dst_buf);
+    const int rank = T.rank;
+    const float scale = T.scale;
+    for (int e = threadIdx.x; e < kCopyChunk; e += kCopyThreads) {
+        const int64_t idx = base + e;
+        if (idx >= T.count) break;
+        uint32_t r = (uint32_t)idx;
+        int64_t so = T.src_off, dofs = T.dst_off;
+        for (int k = rank - 1; k >= 0; --k) {
+            const uint32_t dk = (uint32_t)T.dims[k];
+            const uint32_t q = r / dk;
+            const uint32_t ik = r - q * dk;
+            r = q;
+            so += (int64_t)ik * T.sstride[k];
+            dofs += (int64_t)ik * T.dstride[k];
+        }
+        TD v = (TD)0;
+        if (src) v = (TD)src[so] * (TD)scale;
+        dst[dofs] = v;
+    }
+}
+
+// ===================================================================== gemm
+// Tile configurations.  256 threads = 4 waves in a 2x2 grid; each wave
+// owns a (BM/2) x (BN/2) sub-tile made of MT x MT MFMA tiles.
+template <int BM_, int BN_, int BK_>
+struct TileShape {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_;
+};
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rn(float x) {
+    // round to nearest, ties to even, on the bit pattern (finite inputs;
+    // NaN keeps a quiet mantissa bit)
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// ---- FP64: v_mfma_f64_16x16x4f64 -----------------------------------------
+// lane l: A[row l%16][k l/16], B[col l%16][k l/16]; acc i: row 4*(l/16)+i, col l%16
+template <class Ptrs, class S>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restrict__ tiles,
+                                                       const GemmGroup* __restrict__ groups,
+                                                       Ptrs ptrs) {
+    constexpr int BM = S::BM, BN = S::BN, BK = S::BK;
+    constexpr int LDK = BK + 1;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int TI = WM / 16, TJ = WN / 16;
+    __shared__ double As[BM * LDK];
+    __shared__ double Bs[BN * LDK];
+
+    const TileWork tw = tiles[blockIdx.x];
+    const GemmGroup g = groups[tw.group];
+    const double* __restrict__ A = (const double*)ptrs.get(g.a_buf) + g.a_off;
+    const double* __restrict__ B = (const double*)ptrs.get(g.b_buf) + g.b_off;
+    double* __restrict__ C = (double*)ptrs.get(g.c_buf) + g.c_off;
+    const int m0 = tw.tm * BM, n0 = tw.tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+    constexpr int VA = BM * BK / 2 / 256;   // double2 per thread for A
+    constexpr int VB = BN * BK / 2 / 256;
+    static_assert(VA >= 1 && VB >= 1, "tile too small");
+    double2 ra[VA], rb[VB];
+
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < VA; ++v) {
+            const int idx = tid + v * 256;
+            const int r = idx / (BK / 2), kq = (idx % (BK / 2)) * 2;
+            const int gr = m0 + r, gk = k0 + kq;
+            ra[v] = (gr < g.M && gk < g.lda) ? *(const double2*)(A + (int64_t)gr * g.lda + gk)
+                                             : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int v = 0; v < VB; ++v) {
+            const int idx = tid + v * 256;
+            const int r = idx / (BK / 2), kq = (idx % (BK / 2)) * 2;
+            const int gr = n0 + r, gk = k0 + kq;
+            rb[v] = (gr < g.N && gk < g.ldb) ? *(const double2*)(B + (int64_t)gr * g.ldb + gk)
+                                             : make_double2(0.0, 0.0);
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int v = 0; v < VA; ++v) {
+            const int idx = tid + v * 256;
+            const int r = idx / (BK / 2), kq = (idx % (BK / 2)) * 2;
+            As[r * LDK + kq] = ra[v].x;
+            As[r * LDK + kq + 1] = ra[v].y;
+        }
+#pragma unroll
+        for (int v = 0; v < VB; ++v) {
+            const int idx = tid + v * 256;
+            const int r = idx / (BK / 2), kq = (idx % (BK / 2)) * 2;
+            Bs[r * LDK + kq] = rb[v].x;
+            Bs[r * LDK + kq + 1] = rb[v].y;
+        }
+    };
+
+    d4_t acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    const int K = g.K;
+    if (K > 0) gload(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        sstore();
+        __syncthreads();
+        if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double a[TI], b[TJ];
+#pragma unroll
+            for (int i = 0; i < TI; ++i) a[i] = As[(wm + i * 16 + (lane & 15)) * LDK + kk + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) b[j] = Bs[(wn + j * 16 + (lane & 15)) * LDK + kk + (lane >> 4)];
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int col = n0 + wn + j * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + e;
+                if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
+            }
+        }
+}
+
+// ---- FP32 and BF16 variants on 32x32 MFMA tiles ---------------------------
+// f32 32x32x2: lane l: A[row l%32][k l/32]; bf16 32x32x16: A[row l%32][k 8*(l/32)+0..7]
+// acc i (16 values): row 8*(i/4) + 4*(l/32) + i%4, col l%32
+template <class Ptrs, class S, int MODE>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restrict__ tiles,
+                                                       const GemmGroup* __restrict__ groups,
+                                                       Ptrs ptrs) {
+    constexpr int BM = S::BM, BN = S::BN, BK = S::BK;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int TI = WM / 32, TJ = WN / 32;
+    static_assert(TI >= 1 && TJ >= 1, "tile too small");
+    // f32 LDS: row stride BK+1 floats; bf16 LDS: row stride BK+8 halves
+    constexpr int LDF = BK + 1;
+    constexpr int LDH = BK + 8;
+    constexpr bool BF = (MODE != 1);
+    constexpr bool SPLIT = (MODE == 3);
+    constexpr int ASZ = BF ? 1 : BM * LDF;
+    constexpr int BSZ = BF ? 1 : BN * LDF;
+    constexpr int AHS = BF ? BM * LDH : 1;
+    constexpr int BHS = BF ? BN * LDH : 1;
+    constexpr int ALS = SPLIT ? BM * LDH : 1;
+    constexpr int BLS = SPLIT ? BN * LDH : 1;
+    __shared__ float Af[ASZ];
+    __shared__ float Bf[BSZ];
+    __shared__ __attribute__((aligned(16))) unsigned short Ah[AHS];
+    __shared__ __attribute__((aligned(16))) unsigned short Bh[BHS];
+    __shared__ __attribute__((aligned(16))) unsigned short Al[ALS];
+    __shared__ __attribute__((aligned(16))) unsigned short Bl[BLS];
+
+    const TileWork tw = tiles[blockIdx.x];
+    const GemmGroup g = groups[tw.group];
+    const float* __restrict__ A = (const float*)ptrs.get(g.a_buf) + g.a_off;
+    const float* __restrict__ B = (const float*)ptrs.get(g.b_buf) + g.b_off;
+    float* __restrict__ C = (float*)ptrs.get(g.c_buf) + g.c_off;
+    const int m0 = tw.tm * BM, n0 = tw.tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+    constexpr int VA = BM * BK / 4 / 256;   // float4 per thread
+    constexpr int VB = BN * BK / 4 / 256;
+    static_assert(VA >= 1 && VB >= 1, "tile too small");
+    float4 ra[VA], rb[VB];
+
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < VA; ++v) {
+            const int idx = tid + v * 256;
+            const int r = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
+            const int gr = m0 + r, gk = k0 + kq;
+            ra[v] = (gr < g.M && gk < g.lda) ? *(const float4*)(A + (int64_t)gr * g.lda + gk)
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int v = 0; v < VB; ++v) {
+            const int idx = tid + v * 256;
+            const int r = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
+            const int gr = n0 + r, gk = k0 + kq;
+            rb[v] = (gr < g.N && gk < g.ldb) ? *(const float4*)(B + (int64_t)gr * g.ldb + gk)
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto store_split = [&](unsigned short* hi, unsigned short* lo, int off, float x) {
+        const unsigned short h = f32_to_bf16_rn(x);
+        hi[off] = h;
+        if constexpr (SPLIT) lo[off] = f32_to_bf16_rn(x - bf16_to_f32(h));
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int v = 0; v < VA; ++v) {
+            const int idx = tid + v * 256;
+            const int r = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
+            if constexpr (!BF) {
+                Af[r * LDF + kq + 0] = ra[v].x;
+                Af[r * LDF + kq + 1] = ra[v].y;
+                Af[r * LDF + kq + 2] = ra[v].z;
+                Af[r * LDF + kq + 3] = ra[v].w;
+            } else {
+                const int o = r * LDH + kq;
+                store_split(Ah, Al, o + 0, ra[v].x);
+                store_split(Ah, Al, o + 1, ra[v].y);
+                store_split(Ah, Al, o + 2, ra[v].z);
+                store_split(Ah, Al, o + 3, ra[v].w);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VB; ++v) {
+            const int idx = tid + v * 256;
+            const int r = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
+            if constexpr (!BF) {
+                Bf[r * LDF + kq + 0] = rb[v].x;
+                Bf[r * LDF + kq + 1] = rb[v].y;
+                Bf[r * LDF + kq + 2] = rb[v].z;
+                Bf[r * LDF + kq + 3] = rb[v].w;
+            } else {
+                const int o = r * LDH + kq;
+                store_split(Bh, Bl, o + 0, rb[v].x);
+                store_split(Bh, Bl, o + 1, rb[v].y);
+                store_split(Bh, Bl, o + 2, rb[v].z);
+                store_split(Bh, Bl, o + 3, rb[v].w);
+            }
+        }
+    };
+
+    f16_t acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+    const int K = g.K;
+    if (K > 0) gload(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        sstore();
+        __syncthreads();
+        if (k0 + BK < K) gload(k0 + BK);
+        if constexpr (!BF) {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 2) {
+                float a[TI], b[TJ];
+#pragma unroll
+                for (int i = 0; i < TI; ++i) a[i] = Af[(wm + i * 32 + (lane & 31)) * LDF + kk + (lane >> 5)];
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) b[j] = Bf[(wn + j * 32 + (lane & 31)) * LDF + kk + (lane >> 5)];
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 16) {
+                bf8_t ah[TI], bh[TJ], al[TI], bl[TJ];
+#pragma unroll
+                for (int i = 0; i < TI; ++i) {
+                    const int o = (wm + i * 32 + (lane & 31)) * LDH + kk + 8 * (lane >> 5);
+                    ah[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(Ah + o));
+                    if constexpr (SPLIT) al[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(Al + o));
+                }
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) {
+                    const int o = (wn + j * 32 + (lane & 31)) * LDH + kk + 8 * (lane >> 5);
+                    bh[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(Bh + o));
+                    if constexpr (SPLIT) bl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(Bl + o));
+                }
+#pragma unroll
+                for (int i = 0; i < TI; ++i)
+#pragma unroll
+                    for (int j = 0; j < TJ; ++j) {
+                        if constexpr (SPLIT) {
+                            // small terms first, then the leading product
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                        }
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                    }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int col = n0 + wn + j * 32 + (lane & 31);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = m0 + wm + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
+            }
+        }
+}
+
+// ================================================================ utilities
+__global__ void cast_kernel_d2f(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (float)s[i];
+}
+__global__ void cast_kernel_f2d(const float* __restrict__ s, double* __restrict__ d, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (double)s[i];
+}
+__global__ void fill_zero_kernel(uint32_t* __restrict__ d, int64_t nwords) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = 0u;
+}
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void sumsq_partial_kernel(const T* __restrict__ x, int64_t n,
+                                                                    double* __restrict__ partial) {
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
+        const double v = (double)x[i];
+        s = fma(v, v, s);
+    }
+    // wavefront reduction (64 lanes) then across the 4 waves via LDS
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    __shared__ double ws[kRedThreads / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kRedThreads / 64; ++w) t += ws[w];
+        partial[blockIdx.x] = t;
+    }
+}
+__global__ __launch_bounds__(kRedThreads) void sum_final_kernel(const double* __restrict__ partial, int n,
+                                                                double* __restrict__ out) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kRedThreads) s += partial[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    __shared__ double ws[kRedThreads / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kRedThreads / 64; ++w) t += ws[w];
+        *out = t;
+    }
+}
+template <typename T>
+__global__ void scale_inv_sqrt_kernel(T* __restrict__ x, int64_t n, const double* __restrict__ sumsq) {
+    const double s = *sumsq;
+    const double f = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = (T)((double)x[i] * f);
+}
+
+// Projector sign gauge: for each row j of P~ (col-major, ld ldPt, n cols)
+// find the largest |entry| (lowest column on ties); if it is negative, flip
+// row j of P~ and column j of P (col-major, ld ldP).
+__global__ __launch_bounds__(256) void sign_fix_kernel(double* __restrict__ Pt, int ldPt, int n,
+                                                       double* __restrict__ P, int ldP) {
+    const int j = blockIdx.x;
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int f = threadIdx.x; f < n; f += 256) {
+        const double v = fabs(Pt[j + (int64_t)f * ldPt]);
+        if (v > best || (v == best && f < bi)) { best = v; bi = f; }
+    }
+    __shared__ double sb[256];
+    __shared__ int si[256];
+    sb[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double ob = sb[threadIdx.x + s];
+            const int oi = si[threadIdx.x + s];
+            if (ob > sb[threadIdx.x] || (ob == sb[threadIdx.x] && oi < si[threadIdx.x])) {
+                sb[threadIdx.x] = ob;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const int arg = si[0];
+    const bool flip = arg < n && Pt[j + (int64_t)arg * ldPt] < 0.0;
+    __syncthreads();
+    if (flip) {
+        for (int f = threadIdx.x; f < n; f += 256) {
+            Pt[j + (int64_t)f * ldPt] = -Pt[j + (int64_t)f * ldPt];
+            P[(int64_t)j * ldP + f] = -P[(int64_t)j * ldP + f];
+        }
+    }
+}
+
+// Double layer: thread per output element.  Output blocks are contiguous
+// row-major in canonical order; per leg a fused state maps to (ket, bra)
+// states of the virtual leg.
+template <typename T>
+__global__ __launch_bounds__(256) void double_layer_kernel(DoubleLayerArgs a) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.total) return;
+    int lo = 0, hi = a.nblocks - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a.blk_elem_start[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const int b = lo;
+    int64_t r = i - a.blk_elem_start[b];
+    int f[4];
+#pragma unroll
+    for (int l = 3; l >= 0; --l) {
+        const int d = a.blk_shape[b * 4 + l];
+        f[l] = a.blk_start[b * 4 + l] + (int)(r % d);
+        r /= d;
+    }
+    int k[4], br[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        k[l] = a.ket_of[l][f[l]];
+        br[l] = a.bra_of[l][f[l]];
+    }
+    const T* __restrict__ Ad = (const T*)a.A_dense;
+    const int64_t s1 = a.Dv[3], s2 = s1 * a.Dv[2], s3 = s2 * a.Dv[1], s4 = s3 * a.Dv[0];
+    const int64_t ok = k[0] * s3 + k[1] * s2 + k[2] * s1 + k[3];
+    const int64_t ob = br[0] * s3 + br[1] * s2 + br[2] * s1 + br[3];
+    double acc = 0.0;
+    for (int s = 0; s < a.nphys; ++s) acc = fma((double)Ad[s * s4 + ok], (double)Ad[s * s4 + ob], acc);
+    ((T*)a.out)[a.blk_off[b] + (i - a.blk_elem_start[b])] = (T)acc;
+}
+
+// ============================================================ host launchers
+namespace {
+inline int grid_for(int64_t n, int threads, int cap = 65535 * 4) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+}  // namespace
+
+void launch_cast(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const int g = grid_for(n, 256, 8192);
+    if (src_f64 && !dst_f64)
+        hipLaunchKernelGGL(cast_kernel_d2f, dim3(g), dim3(256), 0, s, (const double*)src, (float*)dst, n);
+    else if (!src_f64 && dst_f64)
+        hipLaunchKernelGGL(cast_kernel_f2d, dim3(g), dim3(256), 0, s, (const float*)src, (double*)dst, n);
+    else
+        HIPCHK(hipMemcpyAsync(dst, src, n * (src_f64 ? 8 : 4), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipGetLastError());
+}
+
+void launch_fill_zero(void* dst, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0) return;
+    if (bytes % 4) fail(SYMTEN_E_INVAL, "fill_zero: size not a multiple of 4 bytes");
+    const int64_t nw = bytes / 4;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s, (uint32_t*)dst, nw);
+    HIPCHK(hipGetLastError());
+}
+
+void launch_sumsq(const void* x, bool f64, int64_t n, double* out, hipStream_t s) {
+    // partial sums live right after *out (caller provides 1 + kRedBlocks doubles)
+    double* partial = out + 1;
+    const int nb = (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + kRedThreads - 1) / kRedThreads));
+    if (f64)
+        hipLaunchKernelGGL(sumsq_partial_kernel<double>, dim3(nb), dim3(kRedThreads), 0, s, (const double*)x, n, partial);
+    else
+        hipLaunchKernelGGL(sumsq_partial_kernel<float>, dim3(nb), dim3(kRedThreads), 0, s, (const float*)x, n, partial);
+    hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(kRedThreads), 0, s, (const double*)partial, nb, out);
+    HIPCHK(hipGetLastError());
+}
+
+void launch_scale_by_inv_sqrt(void* x, bool f64, int64_t n, const double* sumsq, hipStream_t s) {
+    if (n <= 0) return;
+    const int g = grid_for(n, 256, 8192);
+    if (f64)
+        hipLaunchKernelGGL(scale_inv_sqrt_kernel<double>, dim3(g), dim3(256), 0, s, (double*)x, n, sumsq);
+    else
+        hipLaunchKernelGGL(scale_inv_sqrt_kernel<float>, dim3(g), dim3(256), 0, s, (float*)x, n, sumsq);
+    HIPCHK(hipGetLastError());
+}
+
+void launch_sign_fix_rows(double* Pt, int ldPt, int rows, int n, double* P, int ldP, hipStream_t s) {
+    if (rows <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(sign_fix_kernel, dim3(rows), dim3(256), 0, s, Pt, ldPt, n, P, ldP);
+    HIPCHK(hipGetLastError());
+}
+
+void launch_double_layer(const DoubleLayerArgs& a, hipStream_t s) {
+    if (a.total <= 0) return;
+    const int64_t g = (a.total + 255) / 256;
+    if (a.f64)
+        hipLaunchKernelGGL(double_layer_kernel<double>, dim3((unsigned)g), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(double_layer_kernel<float>, dim3((unsigned)g), dim3(256), 0, s, a);
+    HIPCHK(hipGetLastError());
+}
+
+// ---- prepared launches: device descriptors owned by the caller ------------
+void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+                     void* const* d_ptrs, bool src_f64, bool dst_f64, hipStream_t s) {
+    if (ntasks <= 0 || nchunks <= 0) return;
+    DevPtrs P{d_ptrs};
+    dim3 grid((unsigned)nchunks), block(kCopyThreads);
+    if (src_f64 && dst_f64)
+        hipLaunchKernelGGL((copy_kernel<DevPtrs, double, double>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
+    else if (src_f64)
+        hipLaunchKernelGGL((copy_kernel<DevPtrs, double, float>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
+    else if (dst_f64)
+        hipLaunchKernelGGL((copy_kernel<DevPtrs, float, double>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
+    else
+        hipLaunchKernelGGL((copy_kernel<DevPtrs, float, float>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
+    HIPCHK(hipGetLastError());
+}
+
+void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+                     const std::vector<void*>& ptrs, bool src_f64, bool dst_f64, hipStream_t s) {
+    if (ntasks <= 0 || nchunks <= 0) return;
+    if (ptrs.size() > 8) fail(SYMTEN_E_CAPACITY, "copy_launch_arg: more than 8 buffers");
+    ArgPtrs P{};
+    for (size_t i = 0; i < ptrs.size(); ++i) P.p[i] = ptrs[i];
+    dim3 grid((unsigned)nchunks), block(kCopyThreads);
+    if (src_f64 && dst_f64)
+        hipLaunchKernelGGL((copy_kernel<ArgPtrs, double, double>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
+    else if (src_f64)
+        hipLaunchKernelGGL((copy_kernel<ArgPtrs, double, float>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
+    else if (dst_f64)
+        hipLaunchKernelGGL((copy_kernel<ArgPtrs, float, double>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
+    else
+        hipLaunchKernelGGL((copy_kernel<ArgPtrs, float, float>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
+    HIPCHK(hipGetLastError());
+}
+
+// tile config ids: 0 = 64x64, 1 = 128x128
+int gemm_tile_bm(Prec p, int cfg) { (void)p; return cfg == 0 ? 64 : 128; }
+int gemm_tile_bn(Prec p, int cfg) { (void)p; return cfg == 0 ? 64 : 128; }
+
+template <class Ptrs>
+static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, Ptrs P, Prec prec,
+                          int cfg, hipStream_t s) {
+    dim3 grid((unsigned)ntiles), block(256);
+    switch (prec) {
+        case Prec::F64:
+            if (cfg == 0)
+                hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 64, 16>>), grid, block, 0, s, d_tiles, d_groups, P);
+            else
+                hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P);
+            break;
+        case Prec::F32:
+            if (cfg == 0)
+                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, 1>), grid, block, 0, s, d_tiles, d_groups, P);
+            else
+                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, 1>), grid, block, 0, s, d_tiles, d_groups, P);
+            break;
+        case Prec::BF16:
+            if (cfg == 0)
+                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, 2>), grid, block, 0, s, d_tiles, d_groups, P);
+            else
+                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, 2>), grid, block, 0, s, d_tiles, d_groups, P);
+            break;
+        case Prec::BF16X3:
+            if (cfg == 0)
+                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, 3>), grid, block, 0, s, d_tiles, d_groups, P);
+            else
+                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, 3>), grid, block, 0, s, d_tiles, d_groups, P);
+            break;
+    }
+    HIPCHK(hipGetLastError());
+}
+
+void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
+                     const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s) {
+    if (ntiles <= 0) return;
+    if (ptrs.size() > 8) fail(SYMTEN_E_CAPACITY, "gemm_launch_arg: more than 8 buffers");
+    ArgPtrs P{};
+    for (size_t i = 0; i < ptrs.size(); ++i) P.p[i] = ptrs[i];
+    gemm_dispatch(d_tiles, ntiles, d_groups, P, prec, cfg, s);
+}
+
+void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, void* const* d_ptrs,
+                     Prec prec, int cfg, hipStream_t s) {
+    if (ntiles <= 0) return;
+    gemm_dispatch(d_tiles, ntiles, d_groups, DevPtrs{d_ptrs}, prec, cfg, s);
+}
+
+}  // namespace symten

@@ -1,0 +1,793 @@
+// Host bookkeeping of libsymten: allowed-block enumeration, contraction
+// planning (charge-sector grouping of matched block pairs), plan execution,
+// the double layer, and a caching device allocator.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <set>
+#include <sstream>
+
+#include "internal.hpp"
+
+namespace symten {
+
+// launchers defined in kernels.hip
+void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+                     const std::vector<void*>& ptrs, bool src_f64, bool dst_f64, hipStream_t s);
+void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
+                     const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s);
+int gemm_tile_bm(Prec p, int cfg);
+int gemm_tile_bn(Prec p, int cfg);
+
+// ------------------------------------------------------------------ errors
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        std::ostringstream os;
+        os << what << ": " << hipGetErrorString(e);
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) throw Error(SYMTEN_E_NOMEM, os.str());
+        throw Error(SYMTEN_E_HIP, os.str());
+    }
+}
+
+// ------------------------------------------------------------- device pool
+namespace {
+struct Pool {
+    std::mutex mu;
+    std::multimap<size_t, void*> free_;   // capacity -> ptr
+    size_t held = 0;
+};
+Pool& pool() {
+    static Pool* p = new Pool();   // leaked on purpose: buffers may outlive statics
+    return *p;
+}
+size_t round_cap(size_t b) {
+    if (b < 4096) return 4096;
+    // round up to a multiple of 1/8 of the next power of two
+    size_t p = 1;
+    while (p < b) p <<= 1;
+    size_t step = std::max<size_t>(p / 8, 4096);
+    return (b + step - 1) / step * step;
+}
+}  // namespace
+
+BufferPtr device_alloc(size_t bytes) {
+    auto b = std::make_shared<DeviceBuffer>();
+    b->bytes = bytes;
+    if (bytes == 0) return b;
+    const size_t cap = round_cap(bytes);
+    {
+        Pool& P = pool();
+        std::lock_guard<std::mutex> lk(P.mu);
+        auto it = P.free_.lower_bound(cap);
+        if (it != P.free_.end() && it->first <= cap * 2) {
+            b->ptr = it->second;
+            b->cap = it->first;
+            P.free_.erase(it);
+            P.held -= b->cap;
+            return b;
+        }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cap);
+    if (e != hipSuccess) {
+        // release cached blocks and retry once
+        (void)hipGetLastError();
+        Pool& P = pool();
+        {
+            std::lock_guard<std::mutex> lk(P.mu);
+            (void)hipDeviceSynchronize();
+            for (auto& kv : P.free_) (void)hipFree(kv.second);
+            P.free_.clear();
+            P.held = 0;
+        }
+        e = hipMalloc(&p, cap);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(SYMTEN_E_NOMEM, "device allocation of " + std::to_string(cap) + " bytes failed");
+        }
+    }
+    b->ptr = p;
+    b->cap = cap;
+    return b;
+}
+
+DeviceBuffer::~DeviceBuffer() {
+    if (!ptr) return;
+    Pool& P = pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.free_.emplace(cap, ptr);
+    P.held += cap;
+}
+
+// ------------------------------------------------------------------ tensors
+void Tensor::rebuild_index() {
+    index.clear();
+    for (size_t i = 0; i < blocks.size(); ++i) index[blocks[i].q] = (int)i;
+}
+
+int64_t enumerate_blocks(Tensor& t) {
+    const int R = t.rank();
+    t.blocks.clear();
+    std::vector<int> sidx(R, 0);
+    int64_t off = 0;
+    if (R == 0) return 0;
+    for (const auto& l : t.legs)
+        if (l.q.empty()) { t.rebuild_index(); return 0; }
+    while (true) {
+        long s = 0;
+        for (int l = 0; l < R; ++l) s += (long)t.legs[l].dir * t.legs[l].q[sidx[l]];
+        if (s == t.flux) {
+            Block b;
+            b.q.resize(R);
+            b.shape.resize(R);
+            b.stride.resize(R);
+            int64_t sz = 1;
+            for (int l = 0; l < R; ++l) {
+                b.q[l] = t.legs[l].q[sidx[l]];
+                b.shape[l] = t.legs[l].d[sidx[l]];
+                sz *= b.shape[l];
+            }
+            int64_t st = 1;
+            for (int l = R - 1; l >= 0; --l) { b.stride[l] = st; st *= b.shape[l]; }
+            b.offset = off;
+            b.size = sz;
+            off += sz;
+            t.blocks.push_back(std::move(b));
+        }
+        int l = R - 1;
+        while (l >= 0 && ++sidx[l] == (int)t.legs[l].q.size()) { sidx[l] = 0; --l; }
+        if (l < 0) break;
+    }
+    t.rebuild_index();
+    return off;
+}
+
+std::string tensor_signature(const Tensor& t) {
+    std::ostringstream os;
+    os << "g" << t.group << "f" << t.flux << "t" << t.dtype << "|";
+    for (auto& l : t.legs) {
+        os << l.dir << ":";
+        for (size_t i = 0; i < l.q.size(); ++i) os << l.q[i] << "x" << l.d[i] << ",";
+        os << ";";
+    }
+    os << "|";
+    for (auto& b : t.blocks) {
+        for (int x : b.q) os << x << ",";
+        os << "@" << b.offset << "/";
+        for (auto s : b.stride) os << s << ",";
+        os << ";";
+    }
+    return os.str();
+}
+
+void check_device_tensor(const Tensor& t, const char* what) {
+    if (t.meta_only) fail(SYMTEN_E_INVAL, std::string(what) + ": tensor has no device storage");
+}
+
+// ------------------------------------------------------------- copy tasks
+static void simplify_task(CopyTask& t) {
+    // drop unit dims, merge dims contiguous in both source and destination
+    int n = 0;
+    int dims[kMaxCopyRank];
+    int64_t ss[kMaxCopyRank], ds[kMaxCopyRank];
+    for (int k = 0; k < t.rank; ++k) {
+        if (t.dims[k] == 1) continue;
+        dims[n] = t.dims[k];
+        ss[n] = t.sstride[k];
+        ds[n] = t.dstride[k];
+        ++n;
+    }
+    int m = 0;
+    for (int k = 0; k < n; ++k) {
+        if (m > 0 && ss[m - 1] == ss[k] * dims[k] && ds[m - 1] == ds[k] * dims[k] &&
+            (int64_t)dims[m - 1] * dims[k] < (1LL << 30)) {
+            dims[m - 1] *= dims[k];
+            ss[m - 1] = ss[k];
+            ds[m - 1] = ds[k];
+        } else {
+            dims[m] = dims[k];
+            ss[m] = ss[k];
+            ds[m] = ds[k];
+            ++m;
+        }
+    }
+    if (m == 0) { m = 1; dims[0] = 1; ss[0] = 1; ds[0] = 1; }
+    t.rank = m;
+    for (int k = 0; k < kMaxCopyRank; ++k) {
+        t.dims[k] = k < m ? dims[k] : 1;
+        t.sstride[k] = k < m ? ss[k] : 0;
+        t.dstride[k] = k < m ? ds[k] : 0;
+    }
+}
+
+static CopyTask make_task(int src_buf, int64_t src_off, int dst_buf, int64_t dst_off, const std::vector<int>& dims,
+                          const std::vector<int64_t>& sstr, const std::vector<int64_t>& dstr, float scale = 1.f) {
+    CopyTask t{};
+    if ((int)dims.size() > kMaxCopyRank) fail(SYMTEN_E_CAPACITY, "copy task rank exceeds 8");
+    t.src_buf = src_buf;
+    t.dst_buf = dst_buf;
+    t.src_off = src_off;
+    t.dst_off = dst_off;
+    t.rank = (int)dims.size();
+    int64_t c = 1;
+    for (size_t k = 0; k < dims.size(); ++k) {
+        t.dims[k] = dims[k];
+        t.sstride[k] = src_buf >= 0 ? sstr[k] : 0;
+        t.dstride[k] = dstr[k];
+        c *= dims[k];
+    }
+    if (c >= (1LL << 31)) fail(SYMTEN_E_CAPACITY, "copy task too large");
+    t.count = (int)c;
+    t.scale = scale;
+    simplify_task(t);
+    return t;
+}
+
+static std::vector<int64_t> suffix(const std::vector<int>& d, int64_t mult) {
+    std::vector<int64_t> s(d.size());
+    int64_t st = mult;
+    for (int k = (int)d.size() - 1; k >= 0; --k) { s[k] = st; st *= d[k]; }
+    return s;
+}
+static int64_t prod(const std::vector<int>& d) {
+    int64_t p = 1;
+    for (int x : d) p *= x;
+    return p;
+}
+
+// -------------------------------------------------------------- planning
+namespace {
+struct GroupBuild {
+    std::map<std::vector<int>, std::vector<int>> alpha_blocks;   // alpha -> A block ids
+    std::map<std::vector<int>, std::vector<int>> beta_blocks;    // beta -> B block ids
+    std::set<std::vector<int>> kapA, kapB;
+};
+}  // namespace
+
+std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B, int ncon, const int* legsA,
+                                               const int* legsB, const int* out_perm, int prec) {
+    if (A.group != SYMTEN_U1 || B.group != SYMTEN_U1) fail(SYMTEN_E_UNSUPPORTED, "contract: only U(1) tensors");
+    const int RA = A.rank(), RB = B.rank();
+    if (ncon < 0 || ncon > RA || ncon > RB) fail(SYMTEN_E_INVAL, "contract: bad ncon");
+    if (ncon > 0 && (!legsA || !legsB)) fail(SYMTEN_E_INVAL, "contract: null leg list");
+    std::vector<int> conA(ncon), conB(ncon);
+    std::vector<char> usedA(RA, 0), usedB(RB, 0);
+    for (int i = 0; i < ncon; ++i) {
+        conA[i] = legsA[i];
+        conB[i] = legsB[i];
+        if (conA[i] < 0 || conA[i] >= RA || conB[i] < 0 || conB[i] >= RB)
+            fail(SYMTEN_E_INVAL, "contract: leg index out of range");
+        if (usedA[conA[i]]++ || usedB[conB[i]]++) fail(SYMTEN_E_INVAL, "contract: leg listed twice");
+        const Leg& la = A.legs[conA[i]];
+        const Leg& lb = B.legs[conB[i]];
+        if (la.dir != -lb.dir) fail(SYMTEN_E_LEGS, "contract: contracted legs must have opposite directions");
+        if (!la.same_sectors(lb)) fail(SYMTEN_E_LEGS, "contract: contracted legs have different sectors");
+    }
+    Prec p;
+    switch (prec) {
+        case SYMTEN_PREC_F64: p = Prec::F64; break;
+        case SYMTEN_PREC_F32: p = Prec::F32; break;
+        case SYMTEN_PREC_BF16: p = Prec::BF16; break;
+        case SYMTEN_PREC_BF16X3: p = Prec::BF16X3; break;
+        default: fail(SYMTEN_E_INVAL, "contract: unknown precision");
+    }
+    if (A.dtype != B.dtype) fail(SYMTEN_E_INVAL, "contract: operands have different storage types");
+    if ((p == Prec::F64) != (A.dtype == SYMTEN_F64))
+        fail(SYMTEN_E_INVAL, "contract: PREC_F64 needs F64 storage, the other precisions F32 storage");
+
+    std::vector<int> freeA, freeB;
+    for (int l = 0; l < RA; ++l) if (!usedA[l]) freeA.push_back(l);
+    for (int l = 0; l < RB; ++l) if (!usedB[l]) freeB.push_back(l);
+    const int RO = (int)(freeA.size() + freeB.size());
+    if (RO == 0) fail(SYMTEN_E_UNSUPPORTED, "contract: full contraction to a scalar");
+    if (RO > SYMTEN_MAX_RANK) fail(SYMTEN_E_CAPACITY, "contract: output rank exceeds 8");
+    std::vector<int> perm(RO);
+    std::iota(perm.begin(), perm.end(), 0);
+    if (out_perm) {
+        std::vector<char> seen(RO, 0);
+        for (int j = 0; j < RO; ++j) {
+            perm[j] = out_perm[j];
+            if (perm[j] < 0 || perm[j] >= RO || seen[perm[j]]++) fail(SYMTEN_E_INVAL, "contract: bad out_perm");
+        }
+    }
+
+    auto plan = std::make_shared<ContractPlan>();
+    plan->prec = p;
+    plan->panel_f64 = (p == Prec::F64);
+    const int VW = plan->panel_f64 ? 2 : 4;   // 16-byte vectors in the GEMM loads
+
+    // group blocks by the contracted charge seen from A
+    std::map<int, GroupBuild> gb;
+    for (size_t i = 0; i < A.blocks.size(); ++i) {
+        const Block& b = A.blocks[i];
+        std::vector<int> al, ka;
+        int key = 0;
+        for (int l : freeA) al.push_back(b.q[l]);
+        for (int l : conA) { ka.push_back(b.q[l]); key += A.legs[l].dir * b.q[l]; }
+        GroupBuild& G = gb[key];
+        G.alpha_blocks[al].push_back((int)i);
+        G.kapA.insert(ka);
+    }
+    for (size_t i = 0; i < B.blocks.size(); ++i) {
+        const Block& b = B.blocks[i];
+        std::vector<int> be, ka;
+        int key = 0;
+        for (int l : freeB) be.push_back(b.q[l]);
+        for (int l : conB) { ka.push_back(b.q[l]); key -= B.legs[l].dir * b.q[l]; }
+        auto it = gb.find(key);
+        if (it == gb.end()) continue;
+        it->second.beta_blocks[be].push_back((int)i);
+        it->second.kapB.insert(ka);
+    }
+
+    // output metadata
+    auto out = std::make_shared<Tensor>();
+    out->group = SYMTEN_U1;
+    out->flux = A.flux + B.flux;
+    out->dtype = A.dtype;
+    std::vector<Leg> olegs;
+    for (int l : freeA) olegs.push_back(A.legs[l]);
+    for (int l : freeB) olegs.push_back(B.legs[l]);
+    out->legs.resize(RO);
+    for (int j = 0; j < RO; ++j) out->legs[j] = olegs[perm[j]];
+
+    int64_t a_pos = 0, b_pos = 0, c_pos = 0;
+    symten_plan_stats info{};
+    auto align32 = [](int64_t x) { return (x + 31) / 32 * 32; };
+
+    auto key_of = [](const Tensor& T, const Block& b, const std::vector<int>& legs) {
+        std::vector<int> k;
+        for (int l : legs) k.push_back(b.q[l]);
+        return k;
+    };
+
+    for (auto& kv : gb) {
+        GroupBuild& G = kv.second;
+        std::vector<std::vector<int>> kap;
+        for (auto& k : G.kapA) if (G.kapB.count(k)) kap.push_back(k);
+        if (kap.empty()) continue;
+        std::map<std::vector<int>, int> kidx;
+        for (size_t i = 0; i < kap.size(); ++i) kidx[kap[i]] = (int)i;
+        // kappa dims and offsets
+        std::vector<int> koff(kap.size());
+        std::vector<int64_t> kdim(kap.size());
+        int64_t K = 0;
+        for (size_t i = 0; i < kap.size(); ++i) {
+            int64_t d = 1;
+            for (int c = 0; c < ncon; ++c) d *= A.legs[conA[c]].dim_of(kap[i][c]);
+            kdim[i] = d;
+            koff[i] = (int)K;
+            K += d;
+        }
+        // rows: alphas with at least one A block whose kappa is kept
+        GroupPlan gp;
+        gp.key = kv.first;
+        std::vector<std::vector<int>> rows_blocks, cols_blocks;
+        int64_t M = 0, N = 0;
+        for (auto& ab : G.alpha_blocks) {
+            std::vector<int> keep;
+            for (int bi : ab.second)
+                if (kidx.count(key_of(A, A.blocks[bi], conA))) keep.push_back(bi);
+            if (keep.empty()) continue;
+            gp.rows.push_back(ab.first);
+            gp.row_off.push_back((int)M);
+            int64_t d = 1;
+            for (size_t c = 0; c < freeA.size(); ++c) d *= A.legs[freeA[c]].dim_of(ab.first[c]);
+            M += d;
+            rows_blocks.push_back(keep);
+        }
+        for (auto& bb : G.beta_blocks) {
+            std::vector<int> keep;
+            for (int bi : bb.second)
+                if (kidx.count(key_of(B, B.blocks[bi], conB))) keep.push_back(bi);
+            if (keep.empty()) continue;
+            gp.cols.push_back(bb.first);
+            gp.col_off.push_back((int)N);
+            int64_t d = 1;
+            for (size_t c = 0; c < freeB.size(); ++c) d *= B.legs[freeB[c]].dim_of(bb.first[c]);
+            N += d;
+            cols_blocks.push_back(keep);
+        }
+        if (M == 0 || N == 0 || K == 0) continue;
+        if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 30)) fail(SYMTEN_E_CAPACITY, "contract: sector too large");
+        const int64_t lda = (K + VW - 1) / VW * VW;
+        gp.M = (int)M;
+        gp.N = (int)N;
+        gp.K = (int)K;
+        gp.lda = (int)lda;
+        gp.a_off = a_pos;
+        gp.b_off = b_pos;
+        gp.c_off = c_pos;
+        a_pos = align32(a_pos + M * lda);
+        b_pos = align32(b_pos + N * lda);
+        c_pos += M * N;
+        info.groups += 1;
+        info.gemm_flops += 2 * M * N * K;
+        info.max_m = std::max<int64_t>(info.max_m, M);
+        info.max_n = std::max<int64_t>(info.max_n, N);
+        info.max_k = std::max<int64_t>(info.max_k, K);
+
+        // A panel tasks
+        for (size_t r = 0; r < gp.rows.size(); ++r) {
+            std::vector<char> present(kap.size(), 0);
+            std::vector<int> adims;
+            for (size_t c = 0; c < freeA.size(); ++c) adims.push_back(A.legs[freeA[c]].dim_of(gp.rows[r][c]));
+            const int64_t ra = prod(adims);
+            for (int bi : rows_blocks[r]) {
+                const Block& b = A.blocks[bi];
+                const int ki = kidx[key_of(A, b, conA)];
+                present[ki] = 1;
+                std::vector<int> dims, kd;
+                std::vector<int64_t> ss;
+                for (int l : freeA) { dims.push_back(b.shape[l]); ss.push_back(b.stride[l]); }
+                for (int l : conA) { dims.push_back(b.shape[l]); ss.push_back(b.stride[l]); kd.push_back(b.shape[l]); }
+                std::vector<int64_t> ds = suffix(adims, lda);
+                std::vector<int64_t> dk = suffix(kd, 1);
+                ds.insert(ds.end(), dk.begin(), dk.end());
+                plan->copies.push_back(make_task(0, b.offset, 2, gp.a_off + gp.row_off[r] * lda + koff[ki], dims, ss, ds));
+            }
+            for (size_t ki = 0; ki < kap.size(); ++ki)
+                if (!present[ki])
+                    plan->copies.push_back(make_task(-1, 0, 2, gp.a_off + gp.row_off[r] * lda + koff[ki],
+                                                     {(int)ra, (int)kdim[ki]}, {0, 0}, {lda, 1}));
+        }
+        if (lda > K)
+            plan->copies.push_back(make_task(-1, 0, 2, gp.a_off + K, {(int)M, (int)(lda - K)}, {0, 0}, {lda, 1}));
+        // B panel tasks: B_g stored [N][lda] (K contiguous)
+        for (size_t c = 0; c < gp.cols.size(); ++c) {
+            std::vector<char> present(kap.size(), 0);
+            std::vector<int> bdims;
+            for (size_t x = 0; x < freeB.size(); ++x) bdims.push_back(B.legs[freeB[x]].dim_of(gp.cols[c][x]));
+            const int64_t nb = prod(bdims);
+            for (int bi : cols_blocks[c]) {
+                const Block& b = B.blocks[bi];
+                const int ki = kidx[key_of(B, b, conB)];
+                present[ki] = 1;
+                std::vector<int> dims, kd;
+                std::vector<int64_t> ss;
+                for (int l : freeB) { dims.push_back(b.shape[l]); ss.push_back(b.stride[l]); }
+                for (int l : conB) { dims.push_back(b.shape[l]); ss.push_back(b.stride[l]); kd.push_back(b.shape[l]); }
+                std::vector<int64_t> ds = suffix(bdims, lda);
+                std::vector<int64_t> dk = suffix(kd, 1);
+                ds.insert(ds.end(), dk.begin(), dk.end());
+                plan->copies.push_back(make_task(1, b.offset, 3, gp.b_off + gp.col_off[c] * lda + koff[ki], dims, ss, ds));
+            }
+            for (size_t ki = 0; ki < kap.size(); ++ki)
+                if (!present[ki])
+                    plan->copies.push_back(make_task(-1, 0, 3, gp.b_off + gp.col_off[c] * lda + koff[ki],
+                                                     {(int)nb, (int)kdim[ki]}, {0, 0}, {lda, 1}));
+        }
+        if (lda > K)
+            plan->copies.push_back(make_task(-1, 0, 3, gp.b_off + K, {(int)N, (int)(lda - K)}, {0, 0}, {lda, 1}));
+
+        // output blocks reached by at least one pair; pair statistics
+        std::vector<std::vector<char>> arow(gp.rows.size(), std::vector<char>(kap.size(), 0));
+        std::vector<std::vector<char>> bcol(gp.cols.size(), std::vector<char>(kap.size(), 0));
+        for (size_t r = 0; r < gp.rows.size(); ++r)
+            for (int bi : rows_blocks[r]) arow[r][kidx[key_of(A, A.blocks[bi], conA)]] = 1;
+        for (size_t c = 0; c < gp.cols.size(); ++c)
+            for (int bi : cols_blocks[c]) bcol[c][kidx[key_of(B, B.blocks[bi], conB)]] = 1;
+        for (size_t r = 0; r < gp.rows.size(); ++r) {
+            std::vector<int> adims;
+            for (size_t c = 0; c < freeA.size(); ++c) adims.push_back(A.legs[freeA[c]].dim_of(gp.rows[r][c]));
+            const int64_t ma = prod(adims);
+            for (size_t c = 0; c < gp.cols.size(); ++c) {
+                int64_t npairs = 0, fl = 0;
+                std::vector<int> bdims;
+                for (size_t x = 0; x < freeB.size(); ++x) bdims.push_back(B.legs[freeB[x]].dim_of(gp.cols[c][x]));
+                const int64_t nbd = prod(bdims);
+                for (size_t ki = 0; ki < kap.size(); ++ki)
+                    if (arow[r][ki] && bcol[c][ki]) { ++npairs; fl += 2 * ma * nbd * kdim[ki]; }
+                if (!npairs) continue;
+                info.pairs += npairs;
+                info.useful_flops += fl;
+                info.out_blocks += 1;
+                Block ob;
+                std::vector<int> q = gp.rows[r];
+                q.insert(q.end(), gp.cols[c].begin(), gp.cols[c].end());
+                std::vector<int> shp = adims;
+                shp.insert(shp.end(), bdims.begin(), bdims.end());
+                std::vector<int64_t> st = suffix(adims, N);
+                std::vector<int64_t> sb = suffix(bdims, 1);
+                st.insert(st.end(), sb.begin(), sb.end());
+                ob.q.resize(RO);
+                ob.shape.resize(RO);
+                ob.stride.resize(RO);
+                for (int j = 0; j < RO; ++j) {
+                    ob.q[j] = q[perm[j]];
+                    ob.shape[j] = shp[perm[j]];
+                    ob.stride[j] = st[perm[j]];
+                }
+                ob.offset = gp.c_off + gp.row_off[r] * N + gp.col_off[c];
+                ob.size = ma * nbd;
+                out->blocks.push_back(std::move(ob));
+            }
+        }
+        plan->groups.push_back(std::move(gp));
+    }
+    std::sort(out->blocks.begin(), out->blocks.end(), [](const Block& x, const Block& y) { return x.q < y.q; });
+    out->rebuild_index();
+    out->elems = c_pos;
+    out->meta_only = true;
+    plan->out_meta = out;
+    plan->a_panel_elems = a_pos;
+    plan->b_panel_elems = b_pos;
+    plan->out_elems = c_pos;
+    plan->info = info;
+    return plan;
+}
+
+// -------------------------------------------------------------- execution
+namespace {
+// Device copies of a plan's descriptors, uploaded once per plan.
+struct DevPlan {
+    BufferPtr tasks, prefix, groups, tiles;
+    int ntasks = 0, ntiles = 0, cfg = 0;
+    int64_t nchunks = 0;
+    std::vector<GemmGroup> host_groups;
+    int64_t checked_a = -1, checked_b = -1;   // input sizes already validated
+};
+std::mutex g_devplan_mu;
+}  // namespace
+
+void upload_sync(BufferPtr& buf, const void* host, size_t bytes) {
+    buf = device_alloc(bytes);
+    if (bytes) HIPCHK(hipMemcpy(buf->ptr, host, bytes, hipMemcpyHostToDevice));
+}
+
+int choose_tile_cfg(const ContractPlan& p) {
+    // large tiles once the biggest sector fills them
+    return (p.info.max_m >= 128 && p.info.max_n >= 128) ? 1 : 0;
+}
+
+void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles) {
+    const int BM = gemm_tile_bm(prec, cfg), BN = gemm_tile_bn(prec, cfg);
+    std::vector<int> order(groups.size());
+    std::iota(order.begin(), order.end(), 0);
+    // longest K first so that the heaviest tiles start early
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return groups[a].K > groups[b].K; });
+    for (int gi : order) {
+        const GemmGroup& g = groups[gi];
+        const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+        for (int i = 0; i < tm; ++i)
+            for (int j = 0; j < tn; ++j) tiles.push_back(TileWork{gi, i, j, 0});
+    }
+}
+
+void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix) {
+    prefix.resize(tasks.size() + 1);
+    prefix[0] = 0;
+    for (size_t i = 0; i < tasks.size(); ++i) prefix[i + 1] = prefix[i] + (tasks[i].count + 1023) / 1024;
+}
+
+// Every element a task or a GEMM group touches must lie inside its buffer;
+// checked on the host before any descriptor reaches the device.
+void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems) {
+    for (const CopyTask& t : tasks) {
+        int64_t smax = t.src_off, dmax = t.dst_off, smin = t.src_off, dmin = t.dst_off;
+        for (int k = 0; k < t.rank; ++k) {
+            if (t.dims[k] < 1) fail(SYMTEN_E_INVAL, "internal: copy task with empty dim");
+            const int64_t ds = (int64_t)(t.dims[k] - 1) * t.dstride[k];
+            const int64_t ss = (int64_t)(t.dims[k] - 1) * t.sstride[k];
+            (ds >= 0 ? dmax : dmin) += ds;
+            (ss >= 0 ? smax : smin) += ss;
+        }
+        if (t.dst_buf < 0 || t.dst_buf >= (int)buf_elems.size() || dmin < 0 || dmax >= buf_elems[t.dst_buf])
+            fail(SYMTEN_E_INVAL, "internal: copy destination out of bounds");
+        if (t.src_buf >= 0 && (t.src_buf >= (int)buf_elems.size() || smin < 0 || smax >= buf_elems[t.src_buf]))
+            fail(SYMTEN_E_INVAL, "internal: copy source out of bounds");
+    }
+}
+
+void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw) {
+    for (const GemmGroup& g : groups) {
+        auto in = [&](int b, int64_t off, int64_t n) {
+            return b >= 0 && b < (int)buf_elems.size() && off >= 0 && off + n <= buf_elems[b];
+        };
+        if (g.M < 1 || g.N < 1 || g.K < 1 || g.lda < g.K || g.ldb < g.K || g.ldc < g.N || g.lda % vw ||
+            g.ldb % vw || g.a_off % vw || g.b_off % vw)
+            fail(SYMTEN_E_INVAL, "internal: GEMM group shape or alignment");
+        if (!in(g.a_buf, g.a_off, (int64_t)g.M * g.lda) || !in(g.b_buf, g.b_off, (int64_t)g.N * g.ldb) ||
+            !in(g.c_buf, g.c_off, (int64_t)(g.M - 1) * g.ldc + g.N))
+            fail(SYMTEN_E_INVAL, "internal: GEMM operand out of bounds");
+    }
+}
+
+static std::shared_ptr<DevPlan> dev_plan(const ContractPlan& p) {
+    std::lock_guard<std::mutex> lk(g_devplan_mu);
+    if (p.dev) return std::static_pointer_cast<DevPlan>(p.dev);
+    auto d = std::make_shared<DevPlan>();
+    std::vector<int64_t> prefix;
+    copy_prefix(p.copies, prefix);
+    d->ntasks = (int)p.copies.size();
+    d->nchunks = prefix.back();
+    upload_sync(d->tasks, p.copies.data(), p.copies.size() * sizeof(CopyTask));
+    upload_sync(d->prefix, prefix.data(), prefix.size() * sizeof(int64_t));
+    std::vector<GemmGroup> gg;
+    for (auto& g : p.groups) {
+        GemmGroup x{};
+        x.a_off = g.a_off;
+        x.b_off = g.b_off;
+        x.c_off = g.c_off;
+        x.M = g.M;
+        x.N = g.N;
+        x.K = g.K;
+        x.lda = g.lda;
+        x.ldb = g.lda;
+        x.ldc = g.N;
+        x.a_buf = 0;
+        x.b_buf = 1;
+        x.c_buf = 2;
+        gg.push_back(x);
+    }
+    d->cfg = choose_tile_cfg(p);
+    std::vector<TileWork> tiles;
+    build_tiles(gg, p.prec, d->cfg, tiles);
+    d->ntiles = (int)tiles.size();
+    validate_groups(gg, {p.a_panel_elems, p.b_panel_elems, p.out_elems}, p.panel_f64 ? 2 : 4);
+    d->host_groups = gg;
+    upload_sync(d->groups, gg.data(), gg.size() * sizeof(GemmGroup));
+    upload_sync(d->tiles, tiles.data(), tiles.size() * sizeof(TileWork));
+    p.dev = d;
+    return d;
+}
+
+TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& B, hipStream_t stream) {
+    check_device_tensor(A, "contract(A)");
+    check_device_tensor(B, "contract(B)");
+    auto out = std::make_shared<Tensor>(*p.out_meta);
+    out->meta_only = false;
+    out->buf = device_alloc(std::max<int64_t>(p.out_elems, 1) * out->esize());
+    if (p.groups.empty()) return out;
+    auto d = dev_plan(p);
+    if (d->checked_a != A.elems || d->checked_b != B.elems) {
+        validate_tasks(p.copies, {A.elems, B.elems, p.a_panel_elems, p.b_panel_elems});
+        d->checked_a = A.elems;
+        d->checked_b = B.elems;
+    }
+    const size_t pe = p.panel_f64 ? 8 : 4;
+    BufferPtr pa = device_alloc(std::max<int64_t>(p.a_panel_elems, 1) * pe);
+    BufferPtr pb = device_alloc(std::max<int64_t>(p.b_panel_elems, 1) * pe);
+    const bool src64 = A.dtype == SYMTEN_F64;
+    copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->nchunks,
+                    {A.data(), B.data(), pa->ptr, pb->ptr}, src64, p.panel_f64, stream);
+    gemm_launch_arg((const TileWork*)d->tiles->ptr, d->ntiles, (const GemmGroup*)d->groups->ptr,
+                    {pa->ptr, pb->ptr, out->data()}, p.prec, d->cfg, stream);
+    // pa/pb return to the pool here; later users are ordered on the same stream
+    return out;
+}
+
+// ------------------------------------------------------------ double layer
+TensorPtr double_layer(const Tensor& A, hipStream_t stream) {
+    check_device_tensor(A, "double_layer");
+    if (A.group != SYMTEN_U1) fail(SYMTEN_E_UNSUPPORTED, "double_layer: only U(1)");
+    if (A.rank() != 5) fail(SYMTEN_E_INVAL, "double_layer: A must have rank 5 (phys, l, u, r, d)");
+    const bool f64 = A.dtype == SYMTEN_F64;
+    // fused legs: Q = q_ket - q_bra, states ordered by Q, q_ket, (i_ket, i_bra)
+    auto out = std::make_shared<Tensor>();
+    out->group = SYMTEN_U1;
+    out->flux = 0;
+    out->dtype = A.dtype;
+    std::vector<std::vector<int>> ket_of(4), bra_of(4);
+    for (int l = 0; l < 4; ++l) {
+        const Leg& v = A.legs[l + 1];
+        std::vector<int> qs(v.size()), off(v.q.size());
+        int o = 0;
+        for (size_t s = 0; s < v.q.size(); ++s) {
+            off[s] = o;
+            for (int i = 0; i < v.d[s]; ++i) qs[o + i] = v.q[s];
+            o += v.d[s];
+        }
+        struct E { int Q, qk, ik, ib; };
+        std::vector<E> es;
+        for (int ik = 0; ik < v.size(); ++ik)
+            for (int ib = 0; ib < v.size(); ++ib) es.push_back({qs[ik] - qs[ib], qs[ik], ik, ib});
+        std::sort(es.begin(), es.end(), [](const E& x, const E& y) {
+            if (x.Q != y.Q) return x.Q < y.Q;
+            if (x.qk != y.qk) return x.qk < y.qk;
+            if (x.ik != y.ik) return x.ik < y.ik;
+            return x.ib < y.ib;
+        });
+        Leg F;
+        F.dir = v.dir;
+        for (auto& e : es) {
+            ket_of[l].push_back(e.ik);
+            bra_of[l].push_back(e.ib);
+            if (F.q.empty() || F.q.back() != e.Q) { F.q.push_back(e.Q); F.d.push_back(0); }
+            F.d.back() += 1;
+        }
+        out->legs.push_back(F);
+    }
+    const int64_t total = enumerate_blocks(*out);
+    out->elems = total;
+    out->meta_only = false;
+    out->buf = device_alloc(std::max<int64_t>(total, 1) * out->esize());
+    if (total == 0) return out;
+
+    // dense copy of A: [phys][v0][v1][v2][v3]
+    std::vector<int> Dv(5);
+    for (int l = 0; l < 5; ++l) Dv[l] = A.legs[l].size();
+    int64_t dense_n = 1;
+    for (int x : Dv) dense_n *= x;
+    std::vector<int64_t> dstr = suffix(Dv, 1);
+    std::vector<CopyTask> tasks;
+    std::vector<std::vector<int>> soff(5);
+    for (int l = 0; l < 5; ++l) {
+        int o = 0;
+        for (int d : A.legs[l].d) { soff[l].push_back(o); o += d; }
+    }
+    for (auto& b : A.blocks) {
+        int64_t doff = 0;
+        for (int l = 0; l < 5; ++l) doff += soff[l][A.legs[l].index_of(b.q[l])] * dstr[l];
+        std::vector<int64_t> ss(b.stride.begin(), b.stride.end());
+        tasks.push_back(make_task(0, b.offset, 1, doff, b.shape, ss, dstr));
+    }
+    BufferPtr dense = device_alloc(dense_n * out->esize());
+    launch_fill_zero(dense->ptr, dense_n * out->esize(), stream);
+    std::vector<int64_t> prefix;
+    copy_prefix(tasks, prefix);
+    BufferPtr dt, dp;
+    upload_sync(dt, tasks.data(), tasks.size() * sizeof(CopyTask));
+    upload_sync(dp, prefix.data(), prefix.size() * sizeof(int64_t));
+    copy_launch_arg((const CopyTask*)dt->ptr, (const int64_t*)dp->ptr, (int)tasks.size(), prefix.back(),
+                    {A.data(), dense->ptr}, f64, f64, stream);
+
+    // block tables
+    const int nb = (int)out->blocks.size();
+    std::vector<int64_t> boff(nb), bstart(nb + 1);
+    std::vector<int> bfirst(nb * 4), bshape(nb * 4);
+    std::vector<std::vector<int>> foff(4);
+    for (int l = 0; l < 4; ++l) {
+        int o = 0;
+        for (int d : out->legs[l].d) { foff[l].push_back(o); o += d; }
+    }
+    int64_t acc = 0;
+    for (int b = 0; b < nb; ++b) {
+        const Block& bl = out->blocks[b];
+        boff[b] = bl.offset;
+        bstart[b] = acc;
+        acc += bl.size;
+        for (int l = 0; l < 4; ++l) {
+            bfirst[b * 4 + l] = foff[l][out->legs[l].index_of(bl.q[l])];
+            bshape[b * 4 + l] = bl.shape[l];
+        }
+    }
+    bstart[nb] = acc;
+    std::vector<int> kb;   // ket tables then bra tables, concatenated
+    std::vector<int> kb_off(8);
+    for (int l = 0; l < 4; ++l) { kb_off[l] = (int)kb.size(); kb.insert(kb.end(), ket_of[l].begin(), ket_of[l].end()); }
+    for (int l = 0; l < 4; ++l) { kb_off[4 + l] = (int)kb.size(); kb.insert(kb.end(), bra_of[l].begin(), bra_of[l].end()); }
+    BufferPtr d_boff, d_bstart, d_bfirst, d_bshape, d_kb;
+    upload_sync(d_boff, boff.data(), boff.size() * 8);
+    upload_sync(d_bstart, bstart.data(), bstart.size() * 8);
+    upload_sync(d_bfirst, bfirst.data(), bfirst.size() * 4);
+    upload_sync(d_bshape, bshape.data(), bshape.size() * 4);
+    upload_sync(d_kb, kb.data(), kb.size() * 4);
+    DoubleLayerArgs a{};
+    a.A_dense = dense->ptr;
+    a.nphys = Dv[0];
+    for (int l = 0; l < 4; ++l) {
+        a.Dv[l] = Dv[l + 1];
+        a.ket_of[l] = (const int*)d_kb->ptr + kb_off[l];
+        a.bra_of[l] = (const int*)d_kb->ptr + kb_off[4 + l];
+    }
+    a.blk_off = (const int64_t*)d_boff->ptr;
+    a.blk_start = (const int*)d_bfirst->ptr;
+    a.blk_shape = (const int*)d_bshape->ptr;
+    a.blk_elem_start = (const int64_t*)d_bstart->ptr;
+    a.nblocks = nb;
+    a.total = total;
+    a.out = out->data();
+    a.f64 = f64;
+    launch_double_layer(a, stream);
+    // the temporaries go back to the pool; keep ordering by syncing (small)
+    HIPCHK(hipStreamSynchronize(stream));
+    return out;
+}
+
+}  // namespace symten

@@ -1,0 +1,250 @@
+"""Thin Python binding over libsymten's C ABI: argument marshalling only.
+
+Every step of the hot path (block enumeration, planning, gathers, sector
+GEMMs, projectors, normalisation) runs inside libsymten; this module only
+converts Python lists and numpy arrays to the C types of include/symten.h.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib, SymtenError, PREC
+
+IN, OUT = 1, -1
+
+
+def _stream(stream):
+    """A HIP stream handle: the caller's, else torch's current stream when a
+    GPU is visible, else the default stream."""
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return C.c_void_p(0)
+
+
+def _ints(xs):
+    xs = [int(x) for x in xs]
+    return (C.c_int * max(1, len(xs)))(*xs)
+
+
+def _prec(p):
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+class Tensor:
+    """Handle to a libsymten tensor (owns the handle, shares the storage)."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle) if not isinstance(handle, C.c_void_p) else handle
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().symten_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @staticmethod
+    def _desc(legs, flux, dtype):
+        """legs: list of (sectors dict {label: dim}, direction)."""
+        dirs = [int(d) for _, d in legs]
+        nsec = [len(s) for s, _ in legs]
+        labels = [int(q) for s, _ in legs for q in s]
+        dims = [int(s[q]) for s, _ in legs for q in s]
+        keep = (_ints(dirs), _ints(nsec), _ints(labels), _ints(dims))
+        dt = _lib.F64 if dtype in ("f64", _lib.F64) else _lib.F32
+        d = _lib.Desc(_lib.U1, len(legs), keep[0], keep[1], keep[2], keep[3], int(flux), dt)
+        return d, keep
+
+    @classmethod
+    def create(cls, legs, flux=0, dtype="f32", stream=None):
+        d, keep = cls._desc(legs, flux, dtype)
+        h = C.c_void_p()
+        check(lib().symten_create(C.byref(h), C.byref(d), _stream(stream)))
+        return cls(h)
+
+    @classmethod
+    def meta(cls, legs, flux=0, dtype="f32"):
+        d, keep = cls._desc(legs, flux, dtype)
+        h = C.c_void_p()
+        check(lib().symten_create_meta(C.byref(h), C.byref(d)))
+        return cls(h)
+
+    # ---- metadata -------------------------------------------------------
+    @property
+    def rank(self):
+        r = C.c_int()
+        check(lib().symten_rank(self._h, C.byref(r)))
+        return r.value
+
+    @property
+    def flux(self):
+        r = C.c_int()
+        check(lib().symten_flux(self._h, C.byref(r)))
+        return r.value
+
+    @property
+    def dtype(self):
+        r = C.c_int()
+        check(lib().symten_dtype(self._h, C.byref(r)))
+        return "f64" if r.value == _lib.F64 else "f32"
+
+    def legs(self):
+        out = []
+        for l in range(self.rank):
+            d, n = C.c_int(), C.c_int()
+            check(lib().symten_leg_info(self._h, l, C.byref(d), C.byref(n), None, None))
+            lab = (C.c_int * max(1, n.value))()
+            dim = (C.c_int * max(1, n.value))()
+            check(lib().symten_leg_info(self._h, l, None, None, lab, dim))
+            out.append(({int(lab[i]): int(dim[i]) for i in range(n.value)}, d.value))
+        return out
+
+    @property
+    def num_blocks(self):
+        n = C.c_int64()
+        check(lib().symten_num_blocks(self._h, C.byref(n)))
+        return n.value
+
+    @property
+    def nnz(self):
+        n = C.c_int64()
+        check(lib().symten_nnz(self._h, C.byref(n)))
+        return n.value
+
+    def blocks(self):
+        """[(labels tuple, shape tuple, offset, strides tuple)] in canonical order."""
+        R = self.rank
+        out = []
+        lab = (C.c_int * R)()
+        shp = (C.c_int * R)()
+        st = (C.c_int64 * R)()
+        off = C.c_int64()
+        for i in range(self.num_blocks):
+            check(lib().symten_block_info(self._h, i, lab, shp, C.byref(off), st))
+            out.append((tuple(lab), tuple(shp), off.value, tuple(st)))
+        return out
+
+    def device_ptr(self):
+        p, n = C.c_void_p(), C.c_int64()
+        check(lib().symten_device_ptr(self._h, C.byref(p), C.byref(n)))
+        return p.value, n.value
+
+    # ---- data -------------------------------------------------------------
+    def upload(self, values, stream=None):
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        check(lib().symten_upload(self._h, v.ctypes.data_as(C.POINTER(C.c_double)), v.size, _stream(stream)))
+        return self
+
+    def download(self, stream=None):
+        v = np.empty(self.nnz, dtype=np.float64)
+        check(lib().symten_download(self._h, v.ctypes.data_as(C.POINTER(C.c_double)), v.size, _stream(stream)))
+        return v
+
+    def block_dict(self, stream=None):
+        """{labels: ndarray} of the blocks, downloaded."""
+        vals = self.download(stream)
+        out, pos = {}, 0
+        for lab, shp, _, _ in self.blocks():
+            n = int(np.prod(shp))
+            out[lab] = vals[pos:pos + n].reshape(shp)
+            pos += n
+        return out
+
+
+def contract(A, B, legsA, legsB, out_perm=None, prec="f32", stream=None):
+    h = C.c_void_p()
+    perm = _ints(out_perm) if out_perm is not None else None
+    check(lib().symten_contract(C.byref(h), A._h, B._h, len(legsA), _ints(legsA), _ints(legsB), perm,
+                                _prec(prec), _stream(stream)))
+    return Tensor(h)
+
+
+def plan_info(A, B, legsA, legsB, out_perm=None):
+    """Host-only planning; returns (stats dict, metadata-only output Tensor)."""
+    st = _lib.PlanStats()
+    h = C.c_void_p()
+    perm = _ints(out_perm) if out_perm is not None else None
+    check(lib().symten_plan_info(A._h, B._h, len(legsA), _ints(legsA), _ints(legsB), perm, C.byref(st),
+                                 C.byref(h)))
+    return st.to_dict(), Tensor(h)
+
+
+def double_layer(A, stream=None):
+    h = C.c_void_p()
+    check(lib().symten_double_layer(C.byref(h), A._h, _stream(stream)))
+    return Tensor(h)
+
+
+def enlarged_corner(which, Cc, Ta, Tb, a, prec="f32", stream=None):
+    h = C.c_void_p()
+    st = _lib.PlanStats()
+    check(lib().symten_enlarged_corner(C.byref(h), int(which), Cc._h, Ta._h, Tb._h, a._h, _prec(prec),
+                                       C.byref(st), _stream(stream)))
+    return Tensor(h), st.to_dict()
+
+
+def enlarged_corners_batched(Cs, Tas, Tbs, As, prec="bf16x3", use_graph=False, stream=None):
+    n = len(Cs)
+    arr = lambda xs: (C.c_void_p * n)(*[x._h for x in xs])
+    outs = (C.c_void_p * n)()
+    st = _lib.PlanStats()
+    check(lib().symten_enlarged_corners_batched(n, outs, arr(Cs), arr(Tas), arr(Tbs), arr(As), _prec(prec),
+                                                int(bool(use_graph)), C.byref(st), _stream(stream)))
+    return [Tensor(C.c_void_p(outs[i])) for i in range(n)], st.to_dict()
+
+
+def sync(stream=None):
+    check(lib().symten_sync(_stream(stream)))
+
+
+class CtmEnv:
+    """CTM environment C1..C4, T1..T4 (clockwise bonds) with one-move updates."""
+
+    def __init__(self, Cs, Ts):
+        self._keep = list(Cs) + list(Ts)
+        h = C.c_void_p()
+        check(lib().ctm_env_create(C.byref(h), (C.c_void_p * 4)(*[c._h for c in Cs]),
+                                   (C.c_void_p * 4)(*[t._h for t in Ts])))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().ctm_env_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def get(self, k):
+        """k = 0..3: C1..C4, 4..7: T1..T4."""
+        h = C.c_void_p()
+        check(lib().ctm_env_get(self._h, int(k), C.byref(h)))
+        return Tensor(h)
+
+    def move(self, a, chi, prec="f32", direction=0, stats=True, stream=None):
+        st = _lib.MoveStats() if stats else None
+        check(lib().ctm_move(self._h, a._h, int(direction), int(chi), _prec(prec),
+                             C.byref(st) if stats else None, _stream(stream)))
+        return st.to_dict() if stats else None
+
+    def singular_values(self):
+        n = C.c_int64()
+        check(lib().ctm_move_singular_values(self._h, None, 0, C.byref(n)))
+        buf = (C.c_double * max(1, n.value))()
+        check(lib().ctm_move_singular_values(self._h, buf, n.value, C.byref(n)))
+        return np.array(buf[:n.value])
+
+    def projectors(self):
+        p, pt = C.c_void_p(), C.c_void_p()
+        check(lib().ctm_move_projectors(self._h, C.byref(p), C.byref(pt)))
+        return Tensor(p), Tensor(pt)

@@ -1,0 +1,190 @@
+"""GPU parity of the libsymten hot path against the FP64 oracle.
+
+Tolerances are relative Frobenius errors: 1e-12 for FP64 sector products,
+1e-5 for FP32 and for the bf16x3 split products; plain BF16 is checked only
+against a loose bound derived from its 8-bit significand.
+"""
+import numpy as np
+import pytest
+
+import paper_1808_10804_amd as st
+from oracle import u1
+from synth import config, batched_draws
+from workload import oracle_side, device_side, to_dense, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16x3": 1e-5, "bf16": 2e-2}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("mnk", [(1, 1, 1), (5, 7, 3), (64, 64, 64), (65, 130, 33), (200, 129, 257),
+                                 (300, 40, 1000), (17, 300, 5)])
+def test_single_sector_gemm(prec, mnk):
+    """One charge sector per leg: the contraction is a plain matrix product,
+    compared with numpy in FP64 (tiles, ragged M/N/K tails)."""
+    M, N, K = mnk
+    dt = "f64" if prec == "f64" else "f32"
+    rng = np.random.default_rng(M * 1000003 + N * 1009 + K)
+    a = rng.standard_normal((M, K))
+    b = rng.standard_normal((K, N))
+    A = st.Tensor.create([({0: M}, 1), ({0: K}, -1)], 0, dt).upload(a.ravel())
+    B = st.Tensor.create([({0: K}, 1), ({0: N}, -1)], 0, dt).upload(b.ravel())
+    Cc = st.contract(A, B, [1], [0], prec=prec)
+    got = Cc.download().reshape(M, N)
+    if dt == "f32":
+        a, b = a.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)
+    ref = a @ b
+    assert rel(got, ref) <= TOL[prec], rel(got, ref)
+
+
+def test_zero_pair_contraction_on_device():
+    A = st.Tensor.create([({0: 2}, 1), ({2: 3}, -1)], -2, "f32")
+    B = st.Tensor.create([({2: 3}, 1), ({4: 1}, -1)], 0, "f32")
+    out = st.contract(A, B, [1], [0])
+    assert out.num_blocks == 0 and out.nnz == 0
+    assert out.download().size == 0
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    c = config(1)
+    return c, oracle_side(c, c["seed"]), device_side(c, c["seed"], "f64")
+
+
+def test_double_layer_cfg1(cfg1):
+    c, (w, T, a, _), dev = cfg1
+    assert [l for l in dev["a"].legs()] == [(l.sectors(), l.dir) for l in w.a_legs]
+    got = to_dense(dev["a"])
+    assert rel(got, a) <= 1e-13
+    assert [b[0] for b in dev["a"].blocks()] == u1.allowed_blocks(w.a_legs, 0)
+
+
+def test_block_sparse_steps_cfg1(cfg1):
+    """Each step of corner 1 equals the dense contraction of the embedded
+    tensors, and the output blocks are the oracle's brute-force list."""
+    c, (w, T, a, _), dev = cfg1
+    CT = st.contract(dev["C1"], dev["T1"], [1], [0], prec="f64")
+    CTT = st.contract(CT, dev["T4"], [0], [2], prec="f64")
+    Cn = st.contract(CTT, dev["a"], [3, 0], [0, 1], prec="f64")
+    tabs = u1.corner_tables(w, 1)
+    d_ct = np.einsum("ab,bux->aux", T["C1"], T["T1"])
+    d_ctt = np.einsum("aux,yla->uxyl", d_ct, T["T4"])
+    d_c = np.einsum("uxyl,lurd->xyrd", d_ctt, a)
+    for dev_t, ref, tab in [(CT, d_ct, tabs[0]), (CTT, d_ctt, tabs[1]), (Cn, d_c, tabs[2])]:
+        assert [b[0] for b in dev_t.blocks()] == tab["out"].blocks
+        assert rel(to_dense(dev_t, tab["out"].legs), ref) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("which", [1, 2, 3, 4])
+def test_enlarged_corners_cfg1_f64(cfg1, which):
+    c, (w, T, a, _), dev = cfg1
+    names = {1: ("C1", "T1", "T4"), 2: ("C2", "T1", "T2"), 3: ("C3", "T3", "T2"), 4: ("C4", "T3", "T4")}[which]
+    Cn, info = st.enlarged_corner(which, dev[names[0]], dev[names[1]], dev[names[2]], dev["a"], prec="f64")
+    ref = u1.enlarged_corners(w, T, a)[which - 1]
+    # oracle leg orders -> library leg orders
+    perm = {1: (2, 0, 3, 1), 2: (0, 2, 1, 3), 3: (2, 0, 3, 1), 4: (2, 0, 1, 3)}[which]
+    ref = ref.transpose(perm)
+    tab = u1.corner_tables(w, which)
+    assert info["useful_flops"] == sum(s["flops"] for s in tab)
+    assert rel(to_dense(Cn, tab[2]["out"].legs), ref) <= TOL["f64"]
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    c = config(2)
+    return c, oracle_side(c, c["seed"])
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16"])
+def test_enlarged_corner_cfg2(cfg2, prec):
+    c, (w, T, a, _) = cfg2
+    dev = device_side(c, c["seed"], "f32")
+    Cn, info = st.enlarged_corner(1, dev["C1"], dev["T1"], dev["T4"], dev["a"], prec=prec)
+    ref = u1.enlarged_corners(w, T, a)[0].transpose(2, 0, 3, 1)
+    err = rel(to_dense(Cn, u1.corner_tables(w, 1)[2]["out"].legs), ref)
+    print(f"cfg2 corner1 {prec}: rel err {err:.3e}")
+    assert err <= TOL[prec]
+
+
+def _move_compare(w, T, a, chi, dev, prec):
+    env = st.CtmEnv([dev[k] for k in ("C1", "C2", "C3", "C4")], [dev[k] for k in ("T1", "T2", "T3", "T4")])
+    stats = env.move(dev["a"], chi, prec=prec)
+    mv = u1.ctm_left_move(w, T, a, chi)
+    pr = mv["proj"]
+    return env, stats, mv, pr
+
+
+def test_ctm_move_cfg1_f64(cfg1):
+    c, (w, T, a, _), dev = cfg1
+    chi = c["chi_target"]
+    env, stats, mv, pr = _move_compare(w, T, a, chi, dev, "f64")
+    # kept table and spectrum
+    assert stats["kept"] == pr["kept"]
+    sv_o = np.concatenate([pr["svals"][Q] for Q in sorted(pr["svals"])])
+    sv_g = env.singular_values()
+    assert rel(sv_g, sv_o) <= 1e-12
+    assert abs(stats["trunc_err"] - pr["trunc_err"]) <= 1e-12
+    # projectors (sign gauge fixed on both sides) and gauge-invariant objects
+    P, Pt = env.projectors()
+    kleg = pr["new_leg"]
+    Pd = to_dense(P, [u1.Leg(w.chi, -1), u1.Leg(w.dd, 1), kleg])
+    Ptd = to_dense(Pt, [kleg.flipped(), u1.Leg(w.chi, 1), u1.Leg(w.dd, -1)])
+    Fd, perm = u1.fuse(u1.Leg(w.chi, 1), u1.Leg(w.dd, 1), +1, -1, 1)
+    n = Fd.size
+    P_o = np.zeros((Pd.shape[0] * Pd.shape[1], Pd.shape[2]))
+    P_o[perm] = pr["P"]
+    Pt_o = np.zeros((Ptd.shape[0], Ptd.shape[1] * Ptd.shape[2]))
+    Pt_o[:, perm] = pr["Pt"]
+    assert rel(Pd.reshape(-1, Pd.shape[2]), P_o) <= 1e-11
+    assert rel(Ptd.reshape(Ptd.shape[0], -1), Pt_o) <= 1e-11
+    C1n = to_dense(env.get(0), [kleg, u1.Leg(w.chi, -1)])
+    T4n = to_dense(env.get(7), [kleg, u1.Leg(w.dd, -1), kleg.flipped()])
+    C4n = to_dense(env.get(3), [u1.Leg(w.chi, 1), kleg.flipped()])
+    assert rel(C1n, mv["C1"]) <= 1e-11
+    assert rel(T4n, mv["T4"]) <= 1e-11
+    assert rel(C4n, mv["C4"]) <= 1e-11
+    assert rel(u1.left_column(C1n, T4n, C4n), mv["L"]) <= 1e-11
+    # useful flops: corners and halves bit-exact against the brute force
+    fl = u1.move_gemm_flops(w, pr["kept"])
+    assert stats["flops_corners"] == fl["corners"]
+    assert stats["flops_halves"] == fl["halves"]
+    assert stats["flops_renorm"] == fl["renorm"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_ctm_move_cfg2(cfg2, prec):
+    c, (w, T, a, _) = cfg2
+    chi = c["chi_target"]
+    dev = device_side(c, c["seed"], "f32")
+    env, stats, mv, pr = _move_compare(w, T, a, chi, dev, prec)
+    gap = pr["gap"]
+    assert gap > 100 * TOL[prec]            # unambiguous cut for this tolerance
+    assert stats["kept"] == pr["kept"]
+    sv_o = np.concatenate([pr["svals"][Q] for Q in sorted(pr["svals"])])
+    e_sv = rel(env.singular_values(), sv_o)
+    kleg = pr["new_leg"]
+    C1n = to_dense(env.get(0), [kleg, u1.Leg(w.chi, -1)])
+    T4n = to_dense(env.get(7), [kleg, u1.Leg(w.dd, -1), kleg.flipped()])
+    C4n = to_dense(env.get(3), [u1.Leg(w.chi, 1), kleg.flipped()])
+    e_L = rel(u1.left_column(C1n, T4n, C4n), mv["L"])
+    print(f"cfg2 move {prec}: sv {e_sv:.3e} L {e_L:.3e} stats {stats['ms_total']:.3f} ms")
+    assert e_sv <= TOL[prec]
+    assert e_L <= TOL[prec] if prec == "f32" else e_L <= 5 * TOL[prec]
+
+
+def test_batched_corners_match_single_and_oracle():
+    draws = batched_draws(batch=6, chi_range=(32, 48))
+    cfgs = [dict(phys={-1: 1, 1: 1}, virt=d["virt"], chi=d["chi"], flux=1) for d in draws]
+    devs = [device_side(cf, 1813, "f32", batch=b) for b, cf in enumerate(cfgs)]
+    args = [[d["C1"] for d in devs], [d["T1"] for d in devs], [d["T4"] for d in devs], [d["a"] for d in devs]]
+    for use_graph in (False, True):
+        for rep in range(3):
+            outs, info = st.enlarged_corners_batched(*args, prec="bf16x3", use_graph=use_graph)
+            for b, (cf, dv, o) in enumerate(zip(cfgs, devs, outs)):
+                single, _ = st.enlarged_corner(1, dv["C1"], dv["T1"], dv["T4"], dv["a"], prec="bf16x3")
+                assert np.array_equal(o.download(), single.download())
+                if rep == 0 and not use_graph:
+                    w, T, a, _ = oracle_side(cf, 1813, batch=b)
+                    ref = u1.enlarged_corners(w, T, a)[0].transpose(2, 0, 3, 1)
+                    assert rel(to_dense(o, u1.corner_tables(w, 1)[2]["out"].legs), ref) <= TOL["bf16x3"]
