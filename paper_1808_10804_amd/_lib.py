@@ -97,6 +97,13 @@ def lib():
     """Load libsymten.so; raises if it was not built (no fallback)."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: when torch is present it has already
+        # loaded libamdhip64/rocBLAS/rocSOLVER (same sonames), and libsymten
+        # must bind to those so that torch's streams and memory are valid in it.
+        try:
+            import torch  # noqa: F401
+        except Exception:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "or python paper_1808_10804_amd/build.py")

@@ -691,16 +691,20 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, co
         }
         if (use_graph) {
             if (!st->exec) {
-                HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                // Capture on a library stream (the caller's may be the null
+                // stream, which cannot capture); nothing runs during capture.
+                static hipStream_t cap = nullptr;
+                if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+                HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
                 try {
-                    for (int k = 0; k < 3; ++k) run_step(st->step[k], s);
+                    for (int k = 0; k < 3; ++k) run_step(st->step[k], cap);
                 } catch (...) {
                     hipGraph_t g = nullptr;
-                    (void)hipStreamEndCapture(s, &g);
+                    (void)hipStreamEndCapture(cap, &g);
                     if (g) (void)hipGraphDestroy(g);
                     throw;
                 }
-                HIPCHK(hipStreamEndCapture(s, &st->graph));
+                HIPCHK(hipStreamEndCapture(cap, &st->graph));
                 HIPCHK(hipGraphInstantiate(&st->exec, st->graph, nullptr, nullptr, 0));
             }
             HIPCHK(hipGraphLaunch(st->exec, s));

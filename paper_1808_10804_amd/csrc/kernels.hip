@@ -96,7 +96,7 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
 }
 
 // ---- FP64: v_mfma_f64_16x16x4f64 -----------------------------------------
-// lane l: A[row l%16][k l/16], B[col l%16][k l/16]; acc i: row 4*(l/16)+i, col l%16
+// lane l: A[row l%16][k l/16], B[col l%16][k l/16]; acc e: row l/16 + 4*e, col l%16 (checked on gfx950)
 template <class Ptrs, class S>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restrict__ tiles,
                                                        const GemmGroup* __restrict__ groups,
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restric
             const int col = n0 + wn + j * 16 + (lane & 15);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + e;
+                const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * e;
                 if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
             }
         }
