@@ -236,6 +236,28 @@ int ctm_move_singular_values(ctm_env_t env, double* s, int64_t cap, int64_t* n);
  * symten_destroy): P[chi out, D2 in, k in] and P~[k out, chi in, D2 out].   */
 int ctm_move_projectors(ctm_env_t env, symten_t* P, symten_t* Pt);
 
+/* Replace tensor k (0..3 = C1..C4, 4..7 = T1..T4) of the environment; the
+ * environment keeps its own reference to t's storage.                      */
+int ctm_env_set(ctm_env_t env, int k, symten_t t);
+
+/* ---- kernel timing ------------------------------------------------------ */
+
+/* While enabled, every gather and grouped-GEMM launch is bracketed by HIP
+ * events on its stream.  symten_profile_end waits for those events and
+ * returns one entry per kernel (name = kernel symbol and tile shape).       */
+typedef struct {
+    char name[64];
+    int64_t launches;
+    double ms;               /* summed event time of the launches           */
+    int64_t useful_flops;    /* summed block-pair flops (GEMM kernels)      */
+    int64_t gemm_flops;      /* summed flops issued incl. structural zeros   */
+    int64_t bytes;           /* summed algorithmic bytes: operands read once
+                                and results written once                    */
+} symten_kernel_stat;
+
+int symten_profile_begin(void);
+int symten_profile_end(symten_kernel_stat* out, int cap, int* n);
+
 /* ---- misc --------------------------------------------------------------- */
 const char* symten_last_error(void);
 int symten_version(void);

@@ -4,7 +4,7 @@ The compute path lives in libsymten.so (HIP for gfx950, C ABI in
 include/symten.h); this package only loads it and marshals arguments.
 """
 from . import _lib
-from .symten import (Tensor, CtmEnv, contract, plan_info, double_layer, enlarged_corner,
+from .symten import (Tensor, CtmEnv, contract, plan_info, double_layer, enlarged_corner, profile_begin, profile_end,
                      enlarged_corners_batched, sync, IN, OUT)
 from ._lib import SymtenError
 

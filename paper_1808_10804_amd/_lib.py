@@ -53,6 +53,16 @@ class MoveStats(C.Structure):
         return d
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 64), ("launches", C.c_int64), ("ms", C.c_double),
+                ("useful_flops", C.c_int64), ("gemm_flops", C.c_int64), ("bytes", C.c_int64)]
+
+    def to_dict(self):
+        return {"name": self.name.decode(), "launches": int(self.launches), "ms": float(self.ms),
+                "useful_flops": int(self.useful_flops), "gemm_flops": int(self.gemm_flops),
+                "bytes": int(self.bytes)}
+
+
 _lib = None
 P = C.c_void_p
 H = C.c_void_p
@@ -87,6 +97,9 @@ SIGNATURES = {
     "ctm_move": (C.c_int, [H, H, C.c_int, C.c_int, C.c_int, C.POINTER(MoveStats), P]),
     "ctm_move_singular_values": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64, I64P]),
     "ctm_move_projectors": (C.c_int, [H, C.POINTER(H), C.POINTER(H)]),
+    "ctm_env_set": (C.c_int, [H, C.c_int, H]),
+    "symten_profile_begin": (C.c_int, []),
+    "symten_profile_end": (C.c_int, [C.POINTER(KernelStat), C.c_int, IP]),
     "symten_last_error": (C.c_char_p, []),
     "symten_version": (C.c_int, []),
     "symten_sync": (C.c_int, [P]),

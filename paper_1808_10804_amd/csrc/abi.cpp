@@ -32,8 +32,11 @@ void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_gro
                      Prec prec, int cfg, hipStream_t s);
 int choose_tile_cfg(const ContractPlan& p);
 void launch_extract_upper(const double* W, int ldw, int r, int n, double* R, int ldr, hipStream_t s);
-void launch_scale_cols(double* X, int ld, int rows, int cols, const double* s, hipStream_t st);
-void launch_scale_rows(double* X, int ld, int rows, int cols, const double* s, hipStream_t st);
+void launch_scale_cols(double* X, int ld, int rows, int cols, const double* s, double e, hipStream_t st);
+void launch_scale_rows(double* X, int ld, int rows, int cols, const double* s, double e, hipStream_t st);
+void launch_jw_build(const double* M, int ru, int rd, double* J, hipStream_t st);
+void launch_eig_to_svd(const double* Z, int N, const double* w, int mn, int ru, int rd, bool jw, double* S,
+                       double* U, double* V, hipStream_t st);
 
 namespace {
 thread_local std::string g_err;
@@ -223,19 +226,51 @@ __global__ void extract_upper_kernel(const double* __restrict__ W, int ldw, int 
         R[row + (int64_t)col * ldr] = row <= col ? W[row + (int64_t)col * ldw] : 0.0;
     }
 }
-__global__ void scale_cols_kernel(double* __restrict__ X, int ld, int rows, int cols, const double* __restrict__ s) {
+// X[:, j] *= s[j]^e  (col-major, ld)
+__global__ void scale_cols_kernel(double* __restrict__ X, int ld, int rows, int cols, const double* __restrict__ s,
+                                  double e) {
     const int64_t tot = (int64_t)rows * cols;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
         const int row = (int)(i % rows), col = (int)(i / rows);
-        X[row + (int64_t)col * ld] *= 1.0 / sqrt(s[col]);
+        X[row + (int64_t)col * ld] *= pow(s[col], e);
     }
 }
-__global__ void scale_rows_kernel(double* __restrict__ X, int ld, int rows, int cols, const double* __restrict__ s) {
+// X[i, :] *= s[i]^e
+__global__ void scale_rows_kernel(double* __restrict__ X, int ld, int rows, int cols, const double* __restrict__ s,
+                                  double e) {
     const int64_t tot = (int64_t)rows * cols;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
         const int row = (int)(i % rows), col = (int)(i / rows);
-        X[row + (int64_t)col * ld] *= 1.0 / sqrt(s[row]);
+        X[row + (int64_t)col * ld] *= pow(s[row], e);
     }
+}
+// J = [[0, M], [M^T, 0]]  (N = ru + rd, col-major), M col-major ru x rd
+__global__ void jw_build_kernel(const double* __restrict__ M, int ru, int rd, double* __restrict__ J) {
+    const int N = ru + rd;
+    const int64_t tot = (int64_t)N * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i % N), c = (int)(i / N);
+        double v = 0.0;
+        if (r < ru && c >= ru) v = M[r + (int64_t)(c - ru) * ru];
+        else if (r >= ru && c < ru) v = M[c + (int64_t)(r - ru) * ru];
+        J[i] = v;
+    }
+}
+// Largest mn eigenpairs (syevd returns ascending order) as singular triplets
+// in descending order.  Jordan-Wielandt: s = lambda, u = sqrt2 z[0:ru],
+// v = sqrt2 z[ru:]; Gram: s = sqrt(lambda), u = z.
+__global__ void eig_to_svd_kernel(const double* __restrict__ Z, int N, const double* __restrict__ w, int mn, int ru,
+                                  int rd, int jw, double* __restrict__ S, double* __restrict__ U,
+                                  double* __restrict__ V) {
+    const int j = blockIdx.x;
+    if (j >= mn) return;
+    const int idx = N - 1 - j;
+    const double lam = fmax(w[idx], 0.0);
+    if (threadIdx.x == 0) S[j] = jw ? lam : sqrt(lam);
+    const double f = jw ? sqrt(2.0) : 1.0;
+    for (int r = threadIdx.x; r < ru; r += blockDim.x) U[r + (int64_t)j * ru] = f * Z[r + (int64_t)idx * N];
+    if (jw)
+        for (int r = threadIdx.x; r < rd; r += blockDim.x) V[r + (int64_t)j * rd] = f * Z[ru + r + (int64_t)idx * N];
 }
 static int g1d(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
 void launch_extract_upper(const double* W, int ldw, int r, int n, double* R, int ldr, hipStream_t s) {
@@ -243,14 +278,26 @@ void launch_extract_upper(const double* W, int ldw, int r, int n, double* R, int
     hipLaunchKernelGGL(extract_upper_kernel, dim3(g1d((int64_t)r * n)), dim3(256), 0, s, W, ldw, r, n, R, ldr);
     HIPCHK(hipGetLastError());
 }
-void launch_scale_cols(double* X, int ld, int rows, int cols, const double* sv, hipStream_t st) {
+void launch_scale_cols(double* X, int ld, int rows, int cols, const double* sv, double e, hipStream_t st) {
     if ((int64_t)rows * cols == 0) return;
-    hipLaunchKernelGGL(scale_cols_kernel, dim3(g1d((int64_t)rows * cols)), dim3(256), 0, st, X, ld, rows, cols, sv);
+    hipLaunchKernelGGL(scale_cols_kernel, dim3(g1d((int64_t)rows * cols)), dim3(256), 0, st, X, ld, rows, cols, sv, e);
     HIPCHK(hipGetLastError());
 }
-void launch_scale_rows(double* X, int ld, int rows, int cols, const double* sv, hipStream_t st) {
+void launch_scale_rows(double* X, int ld, int rows, int cols, const double* sv, double e, hipStream_t st) {
     if ((int64_t)rows * cols == 0) return;
-    hipLaunchKernelGGL(scale_rows_kernel, dim3(g1d((int64_t)rows * cols)), dim3(256), 0, st, X, ld, rows, cols, sv);
+    hipLaunchKernelGGL(scale_rows_kernel, dim3(g1d((int64_t)rows * cols)), dim3(256), 0, st, X, ld, rows, cols, sv, e);
+    HIPCHK(hipGetLastError());
+}
+void launch_jw_build(const double* M, int ru, int rd, double* J, hipStream_t st) {
+    const int64_t N = ru + rd;
+    if (N == 0) return;
+    hipLaunchKernelGGL(jw_build_kernel, dim3(g1d(N * N)), dim3(256), 0, st, M, ru, rd, J);
+    HIPCHK(hipGetLastError());
+}
+void launch_eig_to_svd(const double* Z, int N, const double* w, int mn, int ru, int rd, bool jw, double* S,
+                       double* U, double* V, hipStream_t st) {
+    if (mn <= 0) return;
+    hipLaunchKernelGGL(eig_to_svd_kernel, dim3(mn), dim3(256), 0, st, Z, N, w, mn, ru, rd, jw ? 1 : 0, S, U, V);
     HIPCHK(hipGetLastError());
 }
 }  // namespace symten
@@ -481,6 +528,7 @@ struct BatchStep {
     bool src_f64 = false, panel_f64 = false;
     Prec prec = Prec::F32;
     symten_plan_stats info{};
+    int64_t copy_bytes = 0, gemm_bytes = 0;   // algorithmic bytes per launch
 };
 struct BatchState {
     int n = 0;
@@ -570,6 +618,8 @@ void build_step(BatchStep& B, const std::vector<const Tensor*>& As, const std::v
     upload_sync(B.groups, groups.data(), groups.size() * sizeof(GemmGroup));
     upload_sync(B.tiles, tiles.data(), tiles.size() * sizeof(TileWork));
     B.ptrs = device_alloc(sizeof(void*) * (2 * n + 3));
+    B.copy_bytes = symten::copy_bytes(tasks, oe, pe);
+    B.gemm_bytes = symten::gemm_bytes(groups, pe, oe);
 }
 
 void set_table(BatchStep& B, const std::vector<void*>& a, const std::vector<void*>& b) {
@@ -586,10 +636,17 @@ void set_table(BatchStep& B, const std::vector<void*>& a, const std::vector<void
 }
 
 void run_step(const BatchStep& B, hipStream_t s) {
-    copy_launch_dev((const CopyTask*)B.tasks->ptr, (const int64_t*)B.prefix->ptr, B.ntasks, B.nchunks,
-                    (void* const*)B.ptrs->ptr, B.src_f64, B.panel_f64, s);
-    gemm_launch_dev((const TileWork*)B.tiles->ptr, B.ntiles, (const GemmGroup*)B.groups->ptr,
-                    (void* const*)B.ptrs->ptr, B.prec, B.cfg, s);
+    profile_launch(std::string("copy_kernel<") + (B.src_f64 ? "f64" : "f32") + "," + (B.panel_f64 ? "f64" : "f32") +
+                       ",batched>",
+                   0, 0, B.copy_bytes, s, [&] {
+                       copy_launch_dev((const CopyTask*)B.tasks->ptr, (const int64_t*)B.prefix->ptr, B.ntasks,
+                                       B.nchunks, (void* const*)B.ptrs->ptr, B.src_f64, B.panel_f64, s);
+                   });
+    profile_launch(gemm_kernel_name(B.prec, B.cfg) + ",batched", B.info.useful_flops, B.info.gemm_flops,
+                   B.gemm_bytes, s, [&] {
+                       gemm_launch_dev((const TileWork*)B.tiles->ptr, B.ntiles, (const GemmGroup*)B.groups->ptr,
+                                       (void* const*)B.ptrs->ptr, B.prec, B.cfg, s);
+                   });
 }
 
 std::vector<TensorPtr> step_outputs(const BatchStep& B, int n) {
@@ -741,6 +798,30 @@ int ctm_env_create(ctm_env_t* env, const symten_t C[4], const symten_t Tt[4]) {
 
 void ctm_env_destroy(ctm_env_t env) { delete env; }
 
+int ctm_env_set(ctm_env_t env, int k, symten_t t) {
+    return guard([&] {
+        if (!env || k < 0 || k > 7) fail(SYMTEN_E_INVAL, "bad argument");
+        Tensor& x = T(t);
+        check_device_tensor(x, "ctm_env_set");
+        if (x.rank() != (k < 4 ? 2 : 3)) fail(SYMTEN_E_INVAL, "C must be rank 2 and T rank 3");
+        (k < 4 ? env->C[k] : env->T[k - 4]) = t->t;
+    });
+}
+
+int symten_profile_begin(void) {
+    return guard([&] { profile_begin(); });
+}
+
+int symten_profile_end(symten_kernel_stat* out, int cap, int* n) {
+    return guard([&] {
+        if (!n) fail(SYMTEN_E_INVAL, "null count");
+        std::vector<symten_kernel_stat> v = profile_end();
+        *n = (int)v.size();
+        if (out)
+            for (int i = 0; i < std::min(cap, *n); ++i) out[i] = v[i];
+    });
+}
+
 int ctm_env_get(ctm_env_t env, int k, symten_t* t) {
     return guard([&] {
         if (!env || !t || k < 0 || k > 7) fail(SYMTEN_E_INVAL, "bad argument");
@@ -799,7 +880,7 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
             int Q = 0, n = 0, m = 0, ru = 0, rd = 0, mn = 0;
             const GroupPlan* gu = nullptr;
             const GroupPlan* gd = nullptr;
-            BufferPtr W, Ru, Rd, M, U, Vt, S, E, tau, info;
+            BufferPtr W, Ru, Rd, M, U, V, S, E, Z, w, tau, info;
             int k = 0;
         };
         std::map<int, QB> qb;
@@ -856,15 +937,34 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
                                        (const double*)b.Ru->ptr, b.ru, (const double*)b.Rd->ptr, b.rd, &zero,
                                        (double*)b.M->ptr, b.ru),
                          "rocblas_dgemm(M)");
+                // SVD of M from a symmetric eigensolve (rocSOLVER's syevd is far
+                // faster than its gesvd at these sizes).  FP64 moves use the
+                // Jordan-Wielandt matrix [[0, M], [M^T, 0]] (eigenpairs +-s,
+                // [u; +-v]/sqrt2: no squaring of the condition number); the other
+                // precisions use the Gram matrix M M^T (eigenvalues s^2), whose
+                // extra rounding stays far below their own error budget.
                 b.S = device_alloc(8 * std::max(1, b.mn));
-                b.U = device_alloc(8 * (size_t)b.ru * b.mn);
-                b.Vt = device_alloc(8 * (size_t)b.mn * b.rd);
-                b.E = device_alloc(8 * std::max(1, b.mn));
-                rb_check(rocsolver_dgesvd(env->rb, rocblas_svect_singular, rocblas_svect_singular, b.ru, b.rd,
-                                          (double*)b.M->ptr, b.ru, (double*)b.S->ptr, (double*)b.U->ptr, b.ru,
-                                          (double*)b.Vt->ptr, b.mn, (double*)b.E->ptr, rocblas_outofplace,
-                                          (rocblas_int*)b.info->ptr),
-                         "rocsolver_dgesvd");
+                b.U = device_alloc(8 * std::max<size_t>(1, (size_t)b.ru * b.mn));
+                b.V = device_alloc(8 * std::max<size_t>(1, (size_t)b.rd * b.mn));
+                const int N = f64 ? b.ru + b.rd : b.ru;
+                b.Z = device_alloc(8 * std::max<size_t>(1, (size_t)N * N));
+                b.w = device_alloc(8 * std::max(1, N));
+                b.E = device_alloc(8 * std::max(1, N));
+                if (f64) {
+                    launch_jw_build((const double*)b.M->ptr, b.ru, b.rd, (double*)b.Z->ptr, s);
+                } else {
+                    rb_check(rocblas_dgemm(env->rb, rocblas_operation_none, rocblas_operation_transpose, b.ru, b.ru,
+                                           b.rd, &one, (const double*)b.M->ptr, b.ru, (const double*)b.M->ptr, b.ru,
+                                           &zero, (double*)b.Z->ptr, b.ru),
+                             "rocblas_dgemm(MM^T)");
+                }
+                if (N > 0)
+                    rb_check(rocsolver_dsyevd(env->rb, rocblas_evect_original, rocblas_fill_upper, N,
+                                              (double*)b.Z->ptr, N, (double*)b.w->ptr, (double*)b.E->ptr,
+                                              (rocblas_int*)b.info->ptr),
+                             "rocsolver_dsyevd");
+                launch_eig_to_svd((const double*)b.Z->ptr, N, (const double*)b.w->ptr, b.mn, b.ru, b.rd, f64,
+                                  (double*)b.S->ptr, (double*)b.U->ptr, (double*)b.V->ptr, s);
             }
             // singular values and status to the host (the one synchronisation)
             int tot = 0;
@@ -878,7 +978,7 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
             }
             HIPCHK(hipStreamSynchronize(s));
             for (size_t i = 0; i < qs.size(); ++i)
-                if (infos[i] != 0) fail(SYMTEN_E_LINALG, "rocsolver_dgesvd did not converge");
+                if (infos[i] != 0) fail(SYMTEN_E_LINALG, "rocsolver_dsyevd did not converge");
             for (double v : sv_host)
                 if (!std::isfinite(v)) fail(SYMTEN_E_LINALG, "non-finite singular value");
         }
@@ -940,16 +1040,24 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
             double* Pq = (double*)P->buf->ptr + pbase[Q];
             double* Ptq = (double*)Pt->buf->ptr + pbase[Q];
             const double one = 1.0, zero = 0.0;
-            // P = R_d^T V_k S^-1/2  (n x k, ld n); V_k = first k rows of V^T, transposed
-            rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_transpose, n, k, b.rd, &one,
-                                   (const double*)b.Rd->ptr, b.rd, (const double*)b.Vt->ptr, b.mn, &zero, Pq, n),
+            if (!f64) {
+                // Gram path: V_k = M^T U_k S_k^-1  (rd x k, ld rd)
+                rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, b.rd, k, b.ru,
+                                       &one, (const double*)b.M->ptr, b.ru, (const double*)b.U->ptr, b.ru, &zero,
+                                       (double*)b.V->ptr, b.rd),
+                         "rocblas_dgemm(V)");
+                launch_scale_cols((double*)b.V->ptr, b.rd, b.rd, k, (const double*)b.S->ptr, -1.0, s);
+            }
+            // P = R_d^T V_k S^-1/2  (n x k, ld n)
+            rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, n, k, b.rd, &one,
+                                   (const double*)b.Rd->ptr, b.rd, (const double*)b.V->ptr, b.rd, &zero, Pq, n),
                      "rocblas_dgemm(P)");
-            launch_scale_cols(Pq, n, n, k, (const double*)b.S->ptr, s);
+            launch_scale_cols(Pq, n, n, k, (const double*)b.S->ptr, -0.5, s);
             // P~ = S^-1/2 U_k^T R_u  (k x n, ld k)
             rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, k, n, b.ru, &one,
                                    (const double*)b.U->ptr, b.ru, (const double*)b.Ru->ptr, b.ru, &zero, Ptq, k),
                      "rocblas_dgemm(Pt)");
-            launch_scale_rows(Ptq, k, k, n, (const double*)b.S->ptr, s);
+            launch_scale_rows(Ptq, k, k, n, (const double*)b.S->ptr, -0.5, s);
             launch_sign_fix_rows(Ptq, k, k, n, Pq, n, s);
             // blocks: one per (q_chi, q_D) row sub-block of this sector
             const GroupPlan* g = b.gu;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -191,6 +192,16 @@ std::vector<TensorPtr> run_contractions_batched(
     const std::vector<const Tensor*>& Bs, hipStream_t stream);
 
 TensorPtr double_layer(const Tensor& A, hipStream_t stream);
+
+// kernel timing (events around launches while enabled)
+bool profiling();
+void profile_launch(const std::string& name, int64_t uf, int64_t gf, int64_t bytes, hipStream_t s,
+                    const std::function<void()>& launch);
+void profile_begin();
+std::vector<symten_kernel_stat> profile_end();
+std::string gemm_kernel_name(Prec p, int cfg);
+int64_t copy_bytes(const std::vector<CopyTask>& tasks, size_t se, size_t de);
+int64_t gemm_bytes(const std::vector<GemmGroup>& gs, size_t pe, size_t oe);
 
 // helpers
 std::string tensor_signature(const Tensor& t);

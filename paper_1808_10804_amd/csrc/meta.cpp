@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <numeric>
 #include <set>
@@ -523,6 +525,94 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
 }
 
 // -------------------------------------------------------------- execution
+// -------------------------------------------------------------- profiling
+namespace {
+struct ProfRec {
+    std::string name;
+    int64_t uf, gf, bytes;
+    hipEvent_t a, b;
+};
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRec> recs;
+};
+}  // namespace
+Profiler& profiler() {
+    static Profiler* p = new Profiler();
+    return *p;
+}
+bool profiling() { return profiler().on; }
+
+void profile_launch(const std::string& name, int64_t uf, int64_t gf, int64_t bytes, hipStream_t s,
+                    const std::function<void()>& launch) {
+    Profiler& P = profiler();
+    if (!P.on) { launch(); return; }
+    ProfRec r{name, uf, gf, bytes, nullptr, nullptr};
+    HIPCHK(hipEventCreate(&r.a));
+    HIPCHK(hipEventCreate(&r.b));
+    HIPCHK(hipEventRecord(r.a, s));
+    launch();
+    HIPCHK(hipEventRecord(r.b, s));
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.recs.push_back(r);
+}
+
+void profile_begin() {
+    Profiler& P = profiler();
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (auto& r : P.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    P.recs.clear();
+    P.on = true;
+}
+
+std::vector<symten_kernel_stat> profile_end() {
+    Profiler& P = profiler();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.on = false;
+    std::map<std::string, symten_kernel_stat> agg;
+    for (auto& r : P.recs) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        symten_kernel_stat& k = agg[r.name];
+        std::snprintf(k.name, sizeof(k.name), "%s", r.name.c_str());
+        k.launches += 1;
+        k.ms += ms;
+        k.useful_flops += r.uf;
+        k.gemm_flops += r.gf;
+        k.bytes += r.bytes;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    P.recs.clear();
+    std::vector<symten_kernel_stat> out;
+    for (auto& kv : agg) out.push_back(kv.second);
+    return out;
+}
+
+std::string gemm_kernel_name(Prec p, int cfg) {
+    const char* t = cfg == 0 ? "64x64" : "128x128";
+    switch (p) {
+        case Prec::F64: return std::string("gemm_f64_kernel<") + t + "x16>";
+        case Prec::F32: return std::string("gemm_f32_kernel<") + t + "x32,f32>";
+        case Prec::BF16: return std::string("gemm_f32_kernel<") + t + "x32,bf16>";
+        default: return std::string("gemm_f32_kernel<") + t + "x32,bf16x3>";
+    }
+}
+
+int64_t copy_bytes(const std::vector<CopyTask>& tasks, size_t se, size_t de) {
+    int64_t b = 0;
+    for (auto& t : tasks) b += (int64_t)t.count * ((t.src_buf >= 0 ? se : 0) + de);
+    return b;
+}
+
+int64_t gemm_bytes(const std::vector<GemmGroup>& gs, size_t pe, size_t oe) {
+    int64_t b = 0;
+    for (auto& g : gs) b += (int64_t)pe * ((int64_t)g.M * g.K + (int64_t)g.N * g.K) + (int64_t)oe * g.M * g.N;
+    return b;
+}
+
 namespace {
 // Device copies of a plan's descriptors, uploaded once per plan.
 struct DevPlan {
@@ -654,10 +744,18 @@ TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& 
     BufferPtr pa = device_alloc(std::max<int64_t>(p.a_panel_elems, 1) * pe);
     BufferPtr pb = device_alloc(std::max<int64_t>(p.b_panel_elems, 1) * pe);
     const bool src64 = A.dtype == SYMTEN_F64;
-    copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->nchunks,
-                    {A.data(), B.data(), pa->ptr, pb->ptr}, src64, p.panel_f64, stream);
-    gemm_launch_arg((const TileWork*)d->tiles->ptr, d->ntiles, (const GemmGroup*)d->groups->ptr,
-                    {pa->ptr, pb->ptr, out->data()}, p.prec, d->cfg, stream);
+    const size_t se = src64 ? 8 : 4;
+    const bool prof = profiling();
+    profile_launch(std::string("copy_kernel<") + (src64 ? "f64" : "f32") + "," + (p.panel_f64 ? "f64" : "f32") + ">",
+                   0, 0, prof ? copy_bytes(p.copies, se, pe) : 0, stream, [&] {
+                       copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks,
+                                       d->nchunks, {A.data(), B.data(), pa->ptr, pb->ptr}, src64, p.panel_f64, stream);
+                   });
+    profile_launch(gemm_kernel_name(p.prec, d->cfg), p.info.useful_flops, p.info.gemm_flops,
+                   prof ? gemm_bytes(d->host_groups, pe, out->esize()) : 0, stream, [&] {
+                       gemm_launch_arg((const TileWork*)d->tiles->ptr, d->ntiles, (const GemmGroup*)d->groups->ptr,
+                                       {pa->ptr, pb->ptr, out->data()}, p.prec, d->cfg, stream);
+                   });
     // pa/pb return to the pool here; later users are ordered on the same stream
     return out;
 }

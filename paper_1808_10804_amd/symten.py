@@ -206,6 +206,20 @@ def sync(stream=None):
     check(lib().symten_sync(_stream(stream)))
 
 
+def profile_begin():
+    """Bracket every gather / grouped-GEMM launch with HIP events from now on."""
+    check(lib().symten_profile_begin())
+
+
+def profile_end():
+    """Stop timing; returns one dict per kernel (launches, ms, flops, bytes)."""
+    cap = 256
+    buf = (_lib.KernelStat * cap)()
+    n = C.c_int()
+    check(lib().symten_profile_end(buf, cap, C.byref(n)))
+    return [buf[i].to_dict() for i in range(min(cap, n.value))]
+
+
 class CtmEnv:
     """CTM environment C1..C4, T1..T4 (clockwise bonds) with one-move updates."""
 
@@ -230,6 +244,11 @@ class CtmEnv:
         h = C.c_void_p()
         check(lib().ctm_env_get(self._h, int(k), C.byref(h)))
         return Tensor(h)
+
+    def set(self, k, t):
+        """Replace tensor k (0..3: C1..C4, 4..7: T1..T4)."""
+        check(lib().ctm_env_set(self._h, int(k), t._h))
+        self._keep.append(t)
 
     def move(self, a, chi, prec="f32", direction=0, stats=True, stream=None):
         st = _lib.MoveStats() if stats else None
