@@ -35,8 +35,20 @@ void launch_extract_upper(const double* W, int ldw, int r, int n, double* R, int
 void launch_scale_cols(double* X, int ld, int rows, int cols, const double* s, double e, hipStream_t st);
 void launch_scale_rows(double* X, int ld, int rows, int cols, const double* s, double e, hipStream_t st);
 void launch_jw_build(const double* M, int ru, int rd, double* J, hipStream_t st);
-void launch_eig_to_svd(const double* Z, int N, const double* w, int mn, int ru, int rd, bool jw, double* S,
-                       double* U, double* V, hipStream_t st);
+void launch_eig_to_svd(const double* Z, int NE, const double* w, int voff, int mn, int ru, int rd, bool jw,
+                       double* S, double* U, double* V, hipStream_t st);
+// zero-padded batches of col-major blocks for the projector factorizations
+constexpr int kMaxPadBatch = 32;
+struct PadArgs {
+    const void* src[kMaxPadBatch];
+    int rows[kMaxPadBatch];
+    int cols[kMaxPadBatch];
+    int count, N;
+    bool src_f64;
+};
+void launch_pad_blocks(const PadArgs& a, double* dst, hipStream_t st);
+void launch_extract_upper_batched(const double* H, int N, int count, double* R, hipStream_t st);
+void launch_jw_build_batched(const double* M, int N, int count, double* J, hipStream_t st);
 
 namespace {
 thread_local std::string g_err;
@@ -256,21 +268,58 @@ __global__ void jw_build_kernel(const double* __restrict__ M, int ru, int rd, do
         J[i] = v;
     }
 }
-// Largest mn eigenpairs (syevd returns ascending order) as singular triplets
-// in descending order.  Jordan-Wielandt: s = lambda, u = sqrt2 z[0:ru],
-// v = sqrt2 z[ru:]; Gram: s = sqrt(lambda), u = z.
-__global__ void eig_to_svd_kernel(const double* __restrict__ Z, int N, const double* __restrict__ w, int mn, int ru,
-                                  int rd, int jw, double* __restrict__ S, double* __restrict__ U,
+// Largest mn eigenpairs (syevd returns ascending order, NE of them) as
+// singular triplets in descending order.  Jordan-Wielandt: s = lambda,
+// u = sqrt2 z[0:ru], v = sqrt2 z[voff:voff+rd]; Gram: s = sqrt(lambda), u = z.
+__global__ void eig_to_svd_kernel(const double* __restrict__ Z, int NE, const double* __restrict__ w, int voff,
+                                  int mn, int ru, int rd, int jw, double* __restrict__ S, double* __restrict__ U,
                                   double* __restrict__ V) {
     const int j = blockIdx.x;
     if (j >= mn) return;
-    const int idx = N - 1 - j;
+    const int idx = NE - 1 - j;
     const double lam = fmax(w[idx], 0.0);
     if (threadIdx.x == 0) S[j] = jw ? lam : sqrt(lam);
     const double f = jw ? sqrt(2.0) : 1.0;
-    for (int r = threadIdx.x; r < ru; r += blockDim.x) U[r + (int64_t)j * ru] = f * Z[r + (int64_t)idx * N];
+    for (int r = threadIdx.x; r < ru; r += blockDim.x) U[r + (int64_t)j * ru] = f * Z[r + (int64_t)idx * NE];
     if (jw)
-        for (int r = threadIdx.x; r < rd; r += blockDim.x) V[r + (int64_t)j * rd] = f * Z[ru + r + (int64_t)idx * N];
+        for (int r = threadIdx.x; r < rd; r += blockDim.x)
+            V[r + (int64_t)j * rd] = f * Z[voff + r + (int64_t)idx * NE];
+}
+// Zero-padded FP64 copies of col-major blocks: dst[j] is N x N.
+__global__ void pad_blocks_kernel(PadArgs a, double* __restrict__ dst) {
+    const int j = blockIdx.y;
+    const int64_t N2 = (int64_t)a.N * a.N;
+    const int rows = a.rows[j], cols = a.cols[j];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N2; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i % a.N), c = (int)(i / a.N);
+        double v = 0.0;
+        if (r < rows && c < cols)
+            v = a.src_f64 ? ((const double*)a.src[j])[r + (int64_t)c * rows]
+                          : (double)((const float*)a.src[j])[r + (int64_t)c * rows];
+        dst[j * N2 + i] = v;
+    }
+}
+__global__ void extract_upper_batched_kernel(const double* __restrict__ H, int N, double* __restrict__ R) {
+    const int j = blockIdx.y;
+    const int64_t N2 = (int64_t)N * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N2; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i % N), c = (int)(i / N);
+        R[j * N2 + i] = r <= c ? H[j * N2 + i] : 0.0;
+    }
+}
+__global__ void jw_build_batched_kernel(const double* __restrict__ M, int N, double* __restrict__ J) {
+    const int j = blockIdx.y;
+    const int N2x = 2 * N;
+    const int64_t tot = (int64_t)N2x * N2x;
+    const double* Mj = M + (int64_t)j * N * N;
+    double* Jj = J + (int64_t)j * tot;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i % N2x), c = (int)(i / N2x);
+        double v = 0.0;
+        if (r < N && c >= N) v = Mj[r + (int64_t)(c - N) * N];
+        else if (r >= N && c < N) v = Mj[c + (int64_t)(r - N) * N];
+        Jj[i] = v;
+    }
 }
 static int g1d(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
 void launch_extract_upper(const double* W, int ldw, int r, int n, double* R, int ldr, hipStream_t s) {
@@ -294,10 +343,29 @@ void launch_jw_build(const double* M, int ru, int rd, double* J, hipStream_t st)
     hipLaunchKernelGGL(jw_build_kernel, dim3(g1d(N * N)), dim3(256), 0, st, M, ru, rd, J);
     HIPCHK(hipGetLastError());
 }
-void launch_eig_to_svd(const double* Z, int N, const double* w, int mn, int ru, int rd, bool jw, double* S,
-                       double* U, double* V, hipStream_t st) {
+void launch_eig_to_svd(const double* Z, int NE, const double* w, int voff, int mn, int ru, int rd, bool jw,
+                       double* S, double* U, double* V, hipStream_t st) {
     if (mn <= 0) return;
-    hipLaunchKernelGGL(eig_to_svd_kernel, dim3(mn), dim3(256), 0, st, Z, N, w, mn, ru, rd, jw ? 1 : 0, S, U, V);
+    hipLaunchKernelGGL(eig_to_svd_kernel, dim3(mn), dim3(256), 0, st, Z, NE, w, voff, mn, ru, rd, jw ? 1 : 0, S, U,
+                       V);
+    HIPCHK(hipGetLastError());
+}
+void launch_pad_blocks(const PadArgs& a, double* dst, hipStream_t st) {
+    if (a.count <= 0 || a.N <= 0) return;
+    dim3 grid((unsigned)g1d((int64_t)a.N * a.N), (unsigned)a.count);
+    hipLaunchKernelGGL(pad_blocks_kernel, grid, dim3(256), 0, st, a, dst);
+    HIPCHK(hipGetLastError());
+}
+void launch_extract_upper_batched(const double* H, int N, int count, double* R, hipStream_t st) {
+    if (count <= 0 || N <= 0) return;
+    dim3 grid((unsigned)g1d((int64_t)N * N), (unsigned)count);
+    hipLaunchKernelGGL(extract_upper_batched_kernel, grid, dim3(256), 0, st, H, N, R);
+    HIPCHK(hipGetLastError());
+}
+void launch_jw_build_batched(const double* M, int N, int count, double* J, hipStream_t st) {
+    if (count <= 0 || N <= 0) return;
+    dim3 grid((unsigned)g1d(4 * (int64_t)N * N), (unsigned)count);
+    hipLaunchKernelGGL(jw_build_batched_kernel, grid, dim3(256), 0, st, M, N, J);
     HIPCHK(hipGetLastError());
 }
 }  // namespace symten
@@ -880,7 +948,10 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
             int Q = 0, n = 0, m = 0, ru = 0, rd = 0, mn = 0;
             const GroupPlan* gu = nullptr;
             const GroupPlan* gd = nullptr;
-            BufferPtr W, Ru, Rd, M, U, V, S, E, Z, w, tau, info;
+            double *Ru_p = nullptr, *Rd_p = nullptr, *M_p = nullptr;   // padded, ld
+            int ld = 0;
+            int* info_p = nullptr;
+            BufferPtr U, V, S;
             int k = 0;
         };
         std::map<int, QB> qb;
@@ -907,64 +978,101 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         if (qs.empty()) fail(SYMTEN_E_LINALG, "ctm_move: the halves have no common charge sector");
         std::vector<double> sv_host;
         std::vector<int> sv_off;
+        std::vector<BufferPtr> keep_alive;
         {
-            // workspace: QR of H^T (col-major m x n = row-major n x m block of H)
+            // R factors of H_u^T = Q_u R_u and H_d^T = Q_d R_d, M = R_u R_d^T and
+            // its singular triplets, per fused charge.  rocSOLVER's factorizations
+            // are latency-bound (one launch sequence per column), so the blocks
+            // are grouped into size classes and each class is factorized in one
+            // strided-batched call: a block (col-major m x n = H^T) is zero-padded
+            // to the class size N, which leaves R = diag(R_A, 0) and
+            // M = diag(M_A, 0) exact; the padding adds only zero singular values.
+            // The SVD of M comes from a symmetric eigensolve (syevd is far faster
+            // than gesvd here): FP64 moves use the Jordan-Wielandt matrix
+            // [[0, M], [M^T, 0]] (eigenpairs +-s, [u; +-v]/sqrt2, no squaring of
+            // the condition number); the other precisions use M M^T (eigenvalues
+            // s^2), whose extra rounding is far below their own error budget.
+            std::vector<int> order = qs;
             for (int Q : qs) {
                 QB& b = qb[Q];
-                const int n = b.n, m = b.m;
-                b.ru = std::min(m, n);
-                b.rd = std::min(m, n);
-                b.mn = std::min(b.ru, b.rd);
-                b.tau = device_alloc(8 * std::max(1, std::min(m, n)));
-                b.info = device_alloc(8);
-                b.Ru = device_alloc(8 * (size_t)b.ru * n);
-                b.Rd = device_alloc(8 * (size_t)b.rd * n);
-                b.W = device_alloc(8 * (size_t)m * n);
-                for (int side = 0; side < 2; ++side) {
-                    const Tensor& H = side == 0 ? *hu.t : *hd.t;
-                    const GroupPlan* g = side == 0 ? b.gu : b.gd;
-                    const char* src = (const char*)H.data() + g->c_off * es;
-                    launch_cast(src, f64, b.W->ptr, true, (int64_t)m * n, s);
-                    rb_check(rocsolver_dgeqrf(env->rb, m, n, (double*)b.W->ptr, m, (double*)b.tau->ptr),
-                             "rocsolver_dgeqrf");
-                    launch_extract_upper((const double*)b.W->ptr, m, side == 0 ? b.ru : b.rd, n,
-                                         (double*)(side == 0 ? b.Ru : b.Rd)->ptr, side == 0 ? b.ru : b.rd, s);
+                b.ru = b.rd = b.mn = std::min(b.m, b.n);
+            }
+            std::sort(order.begin(), order.end(), [&](int x, int y) {
+                return std::max(qb[x].m, qb[x].n) > std::max(qb[y].m, qb[y].n);
+            });
+            const double one = 1.0, zero = 0.0;
+            size_t pos = 0;
+            while (pos < order.size()) {
+                const int N = std::max(qb[order[pos]].m, qb[order[pos]].n);
+                std::vector<int> cls;
+                while (pos < order.size() && (int)cls.size() < kMaxPadBatch / 2 &&
+                       2 * std::max(qb[order[pos]].m, qb[order[pos]].n) >= N)
+                    cls.push_back(order[pos++]);
+                const int B = (int)cls.size();
+                const size_t N2 = (size_t)N * N;
+                // H^T blocks (u, d interleaved) -> padded FP64 matrices
+                BufferPtr Hb = device_alloc(8 * N2 * 2 * B);
+                BufferPtr tau = device_alloc(8 * (size_t)N * 2 * B);
+                PadArgs pa{};
+                pa.count = 2 * B;
+                pa.N = N;
+                pa.src_f64 = f64;
+                for (int i = 0; i < B; ++i) {
+                    QB& b = qb[cls[i]];
+                    for (int side = 0; side < 2; ++side) {
+                        const Tensor& H = side == 0 ? *hu.t : *hd.t;
+                        const GroupPlan* g = side == 0 ? b.gu : b.gd;
+                        pa.src[2 * i + side] = (const char*)H.data() + g->c_off * es;
+                        pa.rows[2 * i + side] = b.m;   // col-major m x n (ld m)
+                        pa.cols[2 * i + side] = b.n;
+                    }
                 }
-                // M = R_u R_d^T  (ru x rd)
-                b.M = device_alloc(8 * (size_t)b.ru * b.rd);
-                const double one = 1.0, zero = 0.0;
-                rb_check(rocblas_dgemm(env->rb, rocblas_operation_none, rocblas_operation_transpose, b.ru, b.rd, n, &one,
-                                       (const double*)b.Ru->ptr, b.ru, (const double*)b.Rd->ptr, b.rd, &zero,
-                                       (double*)b.M->ptr, b.ru),
-                         "rocblas_dgemm(M)");
-                // SVD of M from a symmetric eigensolve (rocSOLVER's syevd is far
-                // faster than its gesvd at these sizes).  FP64 moves use the
-                // Jordan-Wielandt matrix [[0, M], [M^T, 0]] (eigenpairs +-s,
-                // [u; +-v]/sqrt2: no squaring of the condition number); the other
-                // precisions use the Gram matrix M M^T (eigenvalues s^2), whose
-                // extra rounding stays far below their own error budget.
-                b.S = device_alloc(8 * std::max(1, b.mn));
-                b.U = device_alloc(8 * std::max<size_t>(1, (size_t)b.ru * b.mn));
-                b.V = device_alloc(8 * std::max<size_t>(1, (size_t)b.rd * b.mn));
-                const int N = f64 ? b.ru + b.rd : b.ru;
-                b.Z = device_alloc(8 * std::max<size_t>(1, (size_t)N * N));
-                b.w = device_alloc(8 * std::max(1, N));
-                b.E = device_alloc(8 * std::max(1, N));
-                if (f64) {
-                    launch_jw_build((const double*)b.M->ptr, b.ru, b.rd, (double*)b.Z->ptr, s);
-                } else {
-                    rb_check(rocblas_dgemm(env->rb, rocblas_operation_none, rocblas_operation_transpose, b.ru, b.ru,
-                                           b.rd, &one, (const double*)b.M->ptr, b.ru, (const double*)b.M->ptr, b.ru,
-                                           &zero, (double*)b.Z->ptr, b.ru),
-                             "rocblas_dgemm(MM^T)");
+                launch_pad_blocks(pa, (double*)Hb->ptr, s);
+                rb_check(rocsolver_dgeqrf_strided_batched(env->rb, N, N, (double*)Hb->ptr, N, N2, (double*)tau->ptr,
+                                                          N, 2 * B),
+                         "rocsolver_dgeqrf_strided_batched");
+                BufferPtr Rb = device_alloc(8 * N2 * 2 * B);
+                launch_extract_upper_batched((const double*)Hb->ptr, N, 2 * B, (double*)Rb->ptr, s);
+                // M = R_u R_d^T for every block of the class
+                BufferPtr Mb = device_alloc(8 * N2 * B);
+                rb_check(rocblas_dgemm_strided_batched(env->rb, rocblas_operation_none, rocblas_operation_transpose, N, N,
+                                                       N, &one, (const double*)Rb->ptr, N, 2 * N2,
+                                                       (const double*)Rb->ptr + N2, N, 2 * N2, &zero,
+                                                       (double*)Mb->ptr, N, N2, B),
+                         "rocblas_dgemm_strided_batched(M)");
+                const int NE = f64 ? 2 * N : N;
+                const size_t NE2 = (size_t)NE * NE;
+                BufferPtr Zb = device_alloc(8 * NE2 * B);
+                BufferPtr wb = device_alloc(8 * (size_t)NE * B);
+                BufferPtr Eb = device_alloc(8 * (size_t)NE * B);
+                BufferPtr ib = device_alloc(8 * (size_t)B);
+                if (f64)
+                    launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, s);
+                else
+                    rb_check(rocblas_dgemm_strided_batched(env->rb, rocblas_operation_none, rocblas_operation_transpose,
+                                                           N, N, N, &one, (const double*)Mb->ptr, N, N2,
+                                                           (const double*)Mb->ptr, N, N2, &zero, (double*)Zb->ptr, N,
+                                                           N2, B),
+                             "rocblas_dgemm_strided_batched(MM^T)");
+                rb_check(rocsolver_dsyevd_strided_batched(env->rb, rocblas_evect_original, rocblas_fill_upper, NE,
+                                                          (double*)Zb->ptr, NE, NE2, (double*)wb->ptr, NE,
+                                                          (double*)Eb->ptr, NE, (rocblas_int*)ib->ptr, B),
+                         "rocsolver_dsyevd_strided_batched");
+                for (int i = 0; i < B; ++i) {
+                    QB& b = qb[cls[i]];
+                    b.Ru_p = (double*)Rb->ptr + 2 * i * N2;
+                    b.Rd_p = (double*)Rb->ptr + (2 * i + 1) * N2;
+                    b.M_p = (double*)Mb->ptr + i * N2;
+                    b.ld = N;
+                    b.info_p = (int*)ib->ptr + i;
+                    b.S = device_alloc(8 * std::max(1, b.mn));
+                    b.U = device_alloc(8 * std::max<size_t>(1, (size_t)b.ru * b.mn));
+                    b.V = device_alloc(8 * std::max<size_t>(1, (size_t)b.rd * b.mn));
+                    launch_eig_to_svd((const double*)Zb->ptr + i * NE2, NE, (const double*)wb->ptr + (size_t)i * NE,
+                                      N, b.mn, b.ru, b.rd, f64, (double*)b.S->ptr, (double*)b.U->ptr,
+                                      (double*)b.V->ptr, s);
                 }
-                if (N > 0)
-                    rb_check(rocsolver_dsyevd(env->rb, rocblas_evect_original, rocblas_fill_upper, N,
-                                              (double*)b.Z->ptr, N, (double*)b.w->ptr, (double*)b.E->ptr,
-                                              (rocblas_int*)b.info->ptr),
-                             "rocsolver_dsyevd");
-                launch_eig_to_svd((const double*)b.Z->ptr, N, (const double*)b.w->ptr, b.mn, b.ru, b.rd, f64,
-                                  (double*)b.S->ptr, (double*)b.U->ptr, (double*)b.V->ptr, s);
+                for (auto& x : {Hb, tau, Rb, Mb, Zb, wb, Eb, ib}) keep_alive.push_back(x);
             }
             // singular values and status to the host (the one synchronisation)
             int tot = 0;
@@ -974,7 +1082,7 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
             for (size_t i = 0; i < qs.size(); ++i) {
                 QB& b = qb[qs[i]];
                 if (b.mn) HIPCHK(hipMemcpyAsync(sv_host.data() + sv_off[i], b.S->ptr, 8 * b.mn, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipMemcpyAsync(&infos[i], b.info->ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(&infos[i], b.info_p, sizeof(int), hipMemcpyDeviceToHost, s));
             }
             HIPCHK(hipStreamSynchronize(s));
             for (size_t i = 0; i < qs.size(); ++i)
@@ -1043,19 +1151,19 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
             if (!f64) {
                 // Gram path: V_k = M^T U_k S_k^-1  (rd x k, ld rd)
                 rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, b.rd, k, b.ru,
-                                       &one, (const double*)b.M->ptr, b.ru, (const double*)b.U->ptr, b.ru, &zero,
+                                       &one, (const double*)b.M_p, b.ld, (const double*)b.U->ptr, b.ru, &zero,
                                        (double*)b.V->ptr, b.rd),
                          "rocblas_dgemm(V)");
                 launch_scale_cols((double*)b.V->ptr, b.rd, b.rd, k, (const double*)b.S->ptr, -1.0, s);
             }
             // P = R_d^T V_k S^-1/2  (n x k, ld n)
             rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, n, k, b.rd, &one,
-                                   (const double*)b.Rd->ptr, b.rd, (const double*)b.V->ptr, b.rd, &zero, Pq, n),
+                                   (const double*)b.Rd_p, b.ld, (const double*)b.V->ptr, b.rd, &zero, Pq, n),
                      "rocblas_dgemm(P)");
             launch_scale_cols(Pq, n, n, k, (const double*)b.S->ptr, -0.5, s);
             // P~ = S^-1/2 U_k^T R_u  (k x n, ld k)
             rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, k, n, b.ru, &one,
-                                   (const double*)b.U->ptr, b.ru, (const double*)b.Ru->ptr, b.ru, &zero, Ptq, k),
+                                   (const double*)b.U->ptr, b.ru, (const double*)b.Ru_p, b.ld, &zero, Ptq, k),
                      "rocblas_dgemm(Pt)");
             launch_scale_rows(Ptq, k, k, n, (const double*)b.S->ptr, -0.5, s);
             launch_sign_fix_rows(Ptq, k, k, n, Pq, n, s);
