@@ -475,9 +475,11 @@ def move_tables(w, kept):
     corners: three steps each for C~1..C~4;
     halves:  H_u = C~1 . C~2 over the top bond, H_d = C~4 . C~3 over the
              bottom bond;
-    renorm:  C1' = (C1 T1) . P ;  T4a = T4 . a ;  X = T4a . P ;
-             T4' = P~ . X ;  C4' = (C4 T3) . P~ ,
-             with C1 T1 and C4 T3 reused from the first corner steps.
+    renorm:  C1' = (C1 T1) . P ;  X1 = P~ . T4 ;  X2 = X1 . a ;
+             T4' = X2 . P ;  C4' = (C4 T3) . P~ ,
+             with C1 T1 and C4 T3 reused from the first corner steps (the
+             order fixes which block pairs exist, hence the flop count; the
+             dense result of renormalise() does not depend on it).
     """
     corners = {c: corner_tables(w, c) for c in (1, 2, 3, 4)}
     c1 = corners[1][2]["out"]   # [x1, x4, r, d]
@@ -492,12 +494,12 @@ def move_tables(w, kept):
     r_c1 = pair_table(CT, P, [0, 1], [0, 1])  # -> [x1, k]
     T4s = Struct.allowed(w.T_legs["T4"], 0)   # [y, l, x]
     a = Struct.allowed(w.a_legs, 0)
-    r_t4a = pair_table(T4s, a, [1], [0])      # -> [y, x, u, r, d]
-    r_x = pair_table(r_t4a["out"], P, [0, 4], [0, 1])   # -> [x, u, r, k_lo]
-    r_t4 = pair_table(Pt, r_x["out"], [1, 2], [0, 1])   # -> [k_hi, r, k_lo]
+    r_x1 = pair_table(Pt, T4s, [1], [2])                # -> [k_hi, u, y, l]
+    r_x2 = pair_table(r_x1["out"], a, [1, 3], [1, 0])   # -> [k_hi, y, r, d]
+    r_t4 = pair_table(r_x2["out"], P, [1, 3], [0, 1])   # -> [k_hi, r, k_lo]
     r_c4 = pair_table(C4T3, Pt, [0, 2], [1, 2])         # -> [x3, k]
     return dict(corners=corners, hu=hu, hd=hd,
-                renorm=dict(C1=r_c1, T4a=r_t4a, X=r_x, T4=r_t4, C4=r_c4))
+                renorm=dict(C1=r_c1, X1=r_x1, X2=r_x2, T4=r_t4, C4=r_c4))
 
 
 def move_gemm_flops(w, kept):

@@ -5,6 +5,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -182,6 +183,51 @@ CornerResult corner(int which, const Tensor& C, const Tensor& Ta, const Tensor& 
     r.step2 = run(*r.step1, Tb, sp.l2a, sp.l2b);
     r.corner = run(*r.step2, a, sp.l3a, sp.l3b);
     return r;
+}
+
+// Several independent contractions in one gather + one grouped-GEMM launch.
+struct ContractSpec {
+    const Tensor* A;
+    const Tensor* B;
+    std::vector<int> la, lb, perm;
+};
+std::vector<Contracted> contract_batched(const std::vector<ContractSpec>& specs, int prec, hipStream_t s) {
+    std::vector<std::shared_ptr<ContractPlan>> plans;
+    std::vector<const Tensor*> As, Bs;
+    for (auto& c : specs) {
+        plans.push_back(get_plan(*c.A, *c.B, (int)c.la.size(), c.la.data(), c.lb.data(),
+                                 c.perm.empty() ? nullptr : c.perm.data(), prec));
+        As.push_back(c.A);
+        Bs.push_back(c.B);
+    }
+    std::vector<TensorPtr> outs = run_contractions_batched(plans, As, Bs, s);
+    std::vector<Contracted> r;
+    for (size_t i = 0; i < specs.size(); ++i) r.push_back({outs[i], plans[i]});
+    return r;
+}
+
+// Corners `which` (inputs C, Ta, Tb each), step by step across all of them.
+std::vector<CornerResult> corners_batched(const std::vector<int>& which,
+                                          const std::vector<std::array<const Tensor*, 3>>& in, const Tensor& a,
+                                          int prec, hipStream_t s) {
+    const size_t n = which.size();
+    std::vector<CornerResult> res(n);
+    std::vector<CornerSpec> sp;
+    for (int w : which) sp.push_back(corner_spec(w));
+    for (int step = 0; step < 3; ++step) {
+        std::vector<ContractSpec> cs;
+        for (size_t i = 0; i < n; ++i) {
+            if (step == 0) cs.push_back({in[i][0], in[i][1], sp[i].l1a, sp[i].l1b, {}});
+            else if (step == 1) cs.push_back({res[i].step1.get(), in[i][2], sp[i].l2a, sp[i].l2b, {}});
+            else cs.push_back({res[i].step2.get(), &a, sp[i].l3a, sp[i].l3b, {}});
+        }
+        std::vector<Contracted> r = contract_batched(cs, prec, s);
+        for (size_t i = 0; i < n; ++i) {
+            add_info(res[i].info, r[i].plan->info);
+            (step == 0 ? res[i].step1 : step == 1 ? res[i].step2 : res[i].corner) = r[i].t;
+        }
+    }
+    return res;
 }
 
 // ---- rocBLAS/rocSOLVER status -------------------------------------------
@@ -588,9 +634,11 @@ int symten_enlarged_corner(symten_t* out, int which, symten_t C, symten_t Ta, sy
 namespace {
 struct BatchStep {
     std::vector<std::shared_ptr<ContractPlan>> plans;
-    BufferPtr tasks, prefix, groups, tiles, ptrs, apanel, bpanel, out;
-    int ntasks = 0, ntiles = 0, cfg = 0;
+    BufferPtr tasks, prefix, groups, ptrs, apanel, bpanel, out;
+    int ntasks = 0;
     int64_t nchunks = 0;
+    TileChoice tc;
+    std::vector<GemmGroup> host_groups;
     std::vector<int64_t> c_base;
     std::vector<void*> table;     // host copy of the pointer table
     bool src_f64 = false, panel_f64 = false;
@@ -679,12 +727,8 @@ void build_step(BatchStep& B, const std::vector<const Tensor*>& As, const std::v
     B.nchunks = prefix.back();
     upload_sync(B.tasks, tasks.data(), tasks.size() * sizeof(CopyTask));
     upload_sync(B.prefix, prefix.data(), prefix.size() * sizeof(int64_t));
-    B.cfg = (B.info.max_m >= 128 && B.info.max_n >= 128) ? 1 : 0;
-    std::vector<TileWork> tiles;
-    build_tiles(groups, B.prec, B.cfg, tiles);
-    B.ntiles = (int)tiles.size();
+    B.host_groups = groups;
     upload_sync(B.groups, groups.data(), groups.size() * sizeof(GemmGroup));
-    upload_sync(B.tiles, tiles.data(), tiles.size() * sizeof(TileWork));
     B.ptrs = device_alloc(sizeof(void*) * (2 * n + 3));
     B.copy_bytes = symten::copy_bytes(tasks, oe, pe);
     B.gemm_bytes = symten::gemm_bytes(groups, pe, oe);
@@ -703,18 +747,23 @@ void set_table(BatchStep& B, const std::vector<void*>& a, const std::vector<void
     }
 }
 
-void run_step(const BatchStep& B, hipStream_t s) {
+// One step of a batch: gather launch, then grouped GEMM.  With tune = true
+// (never under graph capture) the tile configuration is chosen first.
+void run_step(BatchStep& B, hipStream_t s, bool tune = false) {
     profile_launch(std::string("copy_kernel<") + (B.src_f64 ? "f64" : "f32") + "," + (B.panel_f64 ? "f64" : "f32") +
                        ",batched>",
                    0, 0, B.copy_bytes, s, [&] {
                        copy_launch_dev((const CopyTask*)B.tasks->ptr, (const int64_t*)B.prefix->ptr, B.ntasks,
                                        B.nchunks, (void* const*)B.ptrs->ptr, B.src_f64, B.panel_f64, s);
                    });
-    profile_launch(gemm_kernel_name(B.prec, B.cfg) + ",batched", B.info.useful_flops, B.info.gemm_flops,
-                   B.gemm_bytes, s, [&] {
-                       gemm_launch_dev((const TileWork*)B.tiles->ptr, B.ntiles, (const GemmGroup*)B.groups->ptr,
-                                       (void* const*)B.ptrs->ptr, B.prec, B.cfg, s);
-                   });
+    auto launch = [&](int cfg, const TileWork* t, int nt) {
+        gemm_launch_dev(t, nt, (const GemmGroup*)B.groups->ptr, (void* const*)B.ptrs->ptr, B.prec, cfg, s);
+    };
+    if (tune) autotune_gemm(B.tc, B.host_groups, B.prec, launch, s);
+    if (B.tc.cfg < 0) fail(SYMTEN_E_INVAL, "internal: batched GEMM launched before tuning");
+    const int cfg = B.tc.cfg;
+    profile_launch(gemm_kernel_name(B.prec, cfg) + ",batched", B.info.useful_flops, B.info.gemm_flops, B.gemm_bytes,
+                   s, [&] { launch(cfg, (const TileWork*)B.tc.tiles[cfg]->ptr, B.tc.ntiles[cfg]); });
 }
 
 std::vector<TensorPtr> step_outputs(const BatchStep& B, int n) {
@@ -813,6 +862,12 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, co
                 st->exec = nullptr;
                 st->graph = nullptr;
             }
+        }
+        bool tuned = true;
+        for (int k = 0; k < 3; ++k) tuned = tuned && st->step[k].tc.cfg >= 0;
+        if (!tuned) {
+            // first use: an eager pass that also picks every step's tile shape
+            for (int k = 0; k < 3; ++k) run_step(st->step[k], s, true);
         }
         if (use_graph) {
             if (!st->exec) {
@@ -932,14 +987,18 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         tm.mark(s);
         Tensor &C1 = *env->C[0], &C2 = *env->C[1], &C3 = *env->C[2], &C4 = *env->C[3];
         Tensor &T1 = *env->T[0], &T2 = *env->T[1], &T3 = *env->T[2], &T4 = *env->T[3];
-        CornerResult k1 = corner(1, C1, T1, T4, a, prec, s);
-        CornerResult k2 = corner(2, C2, T1, T2, a, prec, s);
-        CornerResult k3 = corner(3, C3, T3, T2, a, prec, s);
-        CornerResult k4 = corner(4, C4, T3, T4, a, prec, s);
+        // the four corners are independent: each of their three steps is one
+        // gather launch and one grouped-GEMM launch for all four
+        std::vector<CornerResult> ks =
+            corners_batched({1, 2, 3, 4}, {{&C1, &T1, &T4}, {&C2, &T1, &T2}, {&C3, &T3, &T2}, {&C4, &T3, &T4}}, a,
+                            prec, s);
+        CornerResult &k1 = ks[0], &k2 = ks[1], &k3 = ks[2], &k4 = ks[3];
         tm.mark(s);
         // halves: H_u = C~1 C~2 -> [x4, d, x2, d2]; H_d = C~4 C~3 -> [x4, u, x2, u3]
-        Contracted hu = contract(*k1.corner, *k2.corner, {0, 2}, {0, 2}, {}, prec, s);
-        Contracted hd = contract(*k4.corner, *k3.corner, {0, 3}, {0, 2}, {}, prec, s);
+        std::vector<Contracted> hh = contract_batched({{k1.corner.get(), k2.corner.get(), {0, 2}, {0, 2}, {}},
+                                                       {k4.corner.get(), k3.corner.get(), {0, 3}, {0, 2}, {}}},
+                                                      prec, s);
+        Contracted &hu = hh[0], &hd = hh[1];
         tm.mark(s);
 
         // ---- projectors, per fused charge Q of the left cut (FP64) ----------
@@ -1204,11 +1263,16 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         }
         tm.mark(s);
         // ---- renormalise -----------------------------------------------------
-        Contracted c1n = contract(*k1.step1, *Pc, {0, 1}, {0, 1}, {1, 0}, prec, s);       // [k, x1]
-        Contracted t4a = contract(T4, a, {1}, {0}, {}, prec, s);                          // [y, x, u, r, d]
-        Contracted xx = contract(*t4a.t, *Pc, {0, 4}, {0, 1}, {}, prec, s);              // [x, u, r, k_lo]
-        Contracted t4n = contract(*Ptc, *xx.t, {1, 2}, {0, 1}, {2, 1, 0}, prec, s);     // [k_lo, r, k_hi]
-        Contracted c4n = contract(*k4.step1, *Ptc, {0, 2}, {1, 2}, {}, prec, s);          // [x3, k]
+        // T4' = ((P~ T4) a) P: absorbing P~ first keeps the intermediates at
+        // chi' chi D^4 instead of the chi^2 D^6 of T4 a.
+        std::vector<Contracted> r3 =
+            contract_batched({{k1.step1.get(), Pc.get(), {0, 1}, {0, 1}, {1, 0}},      // C1' = [k, x1]
+                              {k4.step1.get(), Ptc.get(), {0, 2}, {1, 2}, {}},         // C4' = [x3, k]
+                              {Ptc.get(), &T4, {1}, {2}, {}}},                         // P~ T4 = [k_hi, u, y, l]
+                             prec, s);
+        Contracted &c1n = r3[0], &c4n = r3[1], &t4a = r3[2];
+        Contracted xx = contract(*t4a.t, a, {1, 3}, {1, 0}, {}, prec, s);               // [k_hi, y, r, d]
+        Contracted t4n = contract(*xx.t, *Pc, {1, 3}, {0, 1}, {2, 1, 0}, prec, s);      // [k_lo, r, k_hi]
         // ---- normalise in FP64 ----------------------------------------------
         BufferPtr red = device_alloc(8 * (1 + 512));
         for (TensorPtr X : {c1n.t, t4n.t, c4n.t}) {

@@ -188,10 +188,37 @@ TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& 
 
 // Execute many plans with one gather launch and one GEMM launch.
 std::vector<TensorPtr> run_contractions_batched(
-    const std::vector<const ContractPlan*>& plans, const std::vector<const Tensor*>& As,
+    const std::vector<std::shared_ptr<ContractPlan>>& plans, const std::vector<const Tensor*>& As,
     const std::vector<const Tensor*>& Bs, hipStream_t stream);
 
+// plan / descriptor helpers shared by the launch paths
+void upload_sync(BufferPtr& buf, const void* host, size_t bytes);
+void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles);
+void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix);
+void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems);
+void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw);
+
 TensorPtr double_layer(const Tensor& A, hipStream_t stream);
+
+// GEMM tile shapes and the autotuner that picks one per launch
+constexpr int kNumTileCfg = 5;
+int gemm_tile_bm(Prec p, int cfg);
+int gemm_tile_bn(Prec p, int cfg);
+bool gemm_tile_ok(Prec p, int cfg);
+struct TileChoice {
+    int cfg = -1;                          // chosen configuration (-1: not tuned)
+    BufferPtr tiles[kNumTileCfg];          // device tile lists per configuration
+    int ntiles[kNumTileCfg] = {0, 0, 0, 0, 0};
+    float ms[kNumTileCfg] = {0, 0, 0, 0, 0};
+};
+// Picks the tile configuration for this set of GEMM groups: a cached
+// decision for the same shapes, else each available configuration is timed
+// once with HIP events through `launch` (idempotent: C = A B is rewritten).
+// Must not be called while the stream is being captured.
+void autotune_gemm(TileChoice& tc, const std::vector<GemmGroup>& groups, Prec prec,
+                   const std::function<void(int cfg, const TileWork* tiles, int ntiles)>& launch,
+                   hipStream_t s);
+void ensure_tiles(TileChoice& tc, const std::vector<GemmGroup>& groups, Prec prec, int cfg);
 
 // kernel timing (events around launches while enabled)
 bool profiling();

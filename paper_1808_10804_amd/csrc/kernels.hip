@@ -28,7 +28,7 @@ typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
 // Pointer table passed by value (single contraction) or by device pointer
 // (batched launches prepared ahead of time).
 struct ArgPtrs {
-    void* p[8];
+    void* p[16];
     __device__ __forceinline__ void* get(int i) const { return p[i]; }
 };
 struct DevPtrs {
@@ -593,7 +593,7 @@ void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntask
 void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
                      const std::vector<void*>& ptrs, bool src_f64, bool dst_f64, hipStream_t s) {
     if (ntasks <= 0 || nchunks <= 0) return;
-    if (ptrs.size() > 8) fail(SYMTEN_E_CAPACITY, "copy_launch_arg: more than 8 buffers");
+    if (ptrs.size() > 16) fail(SYMTEN_E_CAPACITY, "copy_launch_arg: more than 16 buffers");
     ArgPtrs P{};
     for (size_t i = 0; i < ptrs.size(); ++i) P.p[i] = ptrs[i];
     dim3 grid((unsigned)nchunks), block(kCopyThreads);
@@ -609,38 +609,43 @@ void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntask
 }
 
 // tile config ids: 0 = 64x64, 1 = 128x128
-int gemm_tile_bm(Prec p, int cfg) { (void)p; return cfg == 0 ? 64 : 128; }
-int gemm_tile_bn(Prec p, int cfg) { (void)p; return cfg == 0 ? 64 : 128; }
+// Tile shapes (BM x BN): 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128,
+// 4 = 256x128 (FP32/BF16 kernels only).
+static const int kTileBM[kNumTileCfg] = {64, 128, 128, 64, 256};
+static const int kTileBN[kNumTileCfg] = {64, 128, 64, 128, 128};
+int gemm_tile_bm(Prec p, int cfg) { (void)p; return kTileBM[cfg]; }
+int gemm_tile_bn(Prec p, int cfg) { (void)p; return kTileBN[cfg]; }
+bool gemm_tile_ok(Prec p, int cfg) { return cfg >= 0 && cfg < kNumTileCfg && !(p == Prec::F64 && cfg == 4); }
+
+template <class Ptrs, int MODE>
+static void launch_f32_family(int cfg, dim3 grid, hipStream_t s, const TileWork* t, const GemmGroup* g, Ptrs P) {
+    dim3 block(256);
+    switch (cfg) {
+        case 0: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, MODE>), grid, block, 0, s, t, g, P); break;
+        case 1: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, MODE>), grid, block, 0, s, t, g, P); break;
+        case 2: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 32>, MODE>), grid, block, 0, s, t, g, P); break;
+        case 3: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 32>, MODE>), grid, block, 0, s, t, g, P); break;
+        default: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<256, 128, 32>, MODE>), grid, block, 0, s, t, g, P); break;
+    }
+}
 
 template <class Ptrs>
 static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, Ptrs P, Prec prec,
                           int cfg, hipStream_t s) {
+    if (!gemm_tile_ok(prec, cfg)) fail(SYMTEN_E_INVAL, "gemm: tile configuration not available");
     dim3 grid((unsigned)ntiles), block(256);
     switch (prec) {
         case Prec::F64:
-            if (cfg == 0)
-                hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 64, 16>>), grid, block, 0, s, d_tiles, d_groups, P);
-            else
-                hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P);
+            switch (cfg) {
+                case 0: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 64, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
+                case 1: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
+                case 2: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 64, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
+                default: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
+            }
             break;
-        case Prec::F32:
-            if (cfg == 0)
-                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, 1>), grid, block, 0, s, d_tiles, d_groups, P);
-            else
-                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, 1>), grid, block, 0, s, d_tiles, d_groups, P);
-            break;
-        case Prec::BF16:
-            if (cfg == 0)
-                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, 2>), grid, block, 0, s, d_tiles, d_groups, P);
-            else
-                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, 2>), grid, block, 0, s, d_tiles, d_groups, P);
-            break;
-        case Prec::BF16X3:
-            if (cfg == 0)
-                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, 3>), grid, block, 0, s, d_tiles, d_groups, P);
-            else
-                hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, 3>), grid, block, 0, s, d_tiles, d_groups, P);
-            break;
+        case Prec::F32: launch_f32_family<Ptrs, 1>(cfg, grid, s, d_tiles, d_groups, P); break;
+        case Prec::BF16: launch_f32_family<Ptrs, 2>(cfg, grid, s, d_tiles, d_groups, P); break;
+        case Prec::BF16X3: launch_f32_family<Ptrs, 3>(cfg, grid, s, d_tiles, d_groups, P); break;
     }
     HIPCHK(hipGetLastError());
 }
@@ -648,7 +653,7 @@ static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* 
 void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
                      const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s) {
     if (ntiles <= 0) return;
-    if (ptrs.size() > 8) fail(SYMTEN_E_CAPACITY, "gemm_launch_arg: more than 8 buffers");
+    if (ptrs.size() > 16) fail(SYMTEN_E_CAPACITY, "gemm_launch_arg: more than 16 buffers");
     ArgPtrs P{};
     for (size_t i = 0; i < ptrs.size(); ++i) P.p[i] = ptrs[i];
     gemm_dispatch(d_tiles, ntiles, d_groups, P, prec, cfg, s);

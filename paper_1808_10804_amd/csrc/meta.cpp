@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <mutex>
@@ -592,12 +593,12 @@ std::vector<symten_kernel_stat> profile_end() {
 }
 
 std::string gemm_kernel_name(Prec p, int cfg) {
-    const char* t = cfg == 0 ? "64x64" : "128x128";
+    const std::string t = std::to_string(gemm_tile_bm(p, cfg)) + "x" + std::to_string(gemm_tile_bn(p, cfg));
     switch (p) {
-        case Prec::F64: return std::string("gemm_f64_kernel<") + t + "x16>";
-        case Prec::F32: return std::string("gemm_f32_kernel<") + t + "x32,f32>";
-        case Prec::BF16: return std::string("gemm_f32_kernel<") + t + "x32,bf16>";
-        default: return std::string("gemm_f32_kernel<") + t + "x32,bf16x3>";
+        case Prec::F64: return "gemm_f64_kernel<" + t + "x16>";
+        case Prec::F32: return "gemm_f32_kernel<" + t + "x32,f32>";
+        case Prec::BF16: return "gemm_f32_kernel<" + t + "x32,bf16>";
+        default: return "gemm_f32_kernel<" + t + "x32,bf16x3>";
     }
 }
 
@@ -616,9 +617,10 @@ int64_t gemm_bytes(const std::vector<GemmGroup>& gs, size_t pe, size_t oe) {
 namespace {
 // Device copies of a plan's descriptors, uploaded once per plan.
 struct DevPlan {
-    BufferPtr tasks, prefix, groups, tiles;
-    int ntasks = 0, ntiles = 0, cfg = 0;
+    BufferPtr tasks, prefix, groups;
+    int ntasks = 0;
     int64_t nchunks = 0;
+    TileChoice tc;
     std::vector<GemmGroup> host_groups;
     int64_t checked_a = -1, checked_b = -1;   // input sizes already validated
 };
@@ -628,6 +630,107 @@ std::mutex g_devplan_mu;
 void upload_sync(BufferPtr& buf, const void* host, size_t bytes) {
     buf = device_alloc(bytes);
     if (bytes) HIPCHK(hipMemcpy(buf->ptr, host, bytes, hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;   // shape signature -> tile configuration
+bool g_tune_loaded = false;
+
+std::string shape_key(const std::vector<GemmGroup>& groups, Prec prec) {
+    std::string k = "p" + std::to_string((int)prec) + ":";
+    for (auto& g : groups) k += std::to_string(g.M) + "x" + std::to_string(g.N) + "x" + std::to_string(g.K) + ",";
+    char h[32];
+    std::snprintf(h, sizeof(h), "%016zx", std::hash<std::string>{}(k));
+    return std::string(h) + "/" + std::to_string(groups.size());
+}
+
+// Decisions persist across processes when SYMTEN_TUNE_CACHE names a file.
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("SYMTEN_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[128];
+    int cfg;
+    while (std::fscanf(f, "%127s %d", key, &cfg) == 2) g_tune[key] = cfg;
+    std::fclose(f);
+}
+void tune_store_locked(const std::string& key, int cfg) {
+    g_tune[key] = cfg;
+    const char* path = std::getenv("SYMTEN_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", key.c_str(), cfg);
+    std::fclose(f);
+}
+}  // namespace
+
+void ensure_tiles(TileChoice& tc, const std::vector<GemmGroup>& groups, Prec prec, int cfg) {
+    if (tc.tiles[cfg]) return;
+    std::vector<TileWork> tiles;
+    build_tiles(groups, prec, cfg, tiles);
+    tc.ntiles[cfg] = (int)tiles.size();
+    upload_sync(tc.tiles[cfg], tiles.data(), tiles.size() * sizeof(TileWork));
+}
+
+void autotune_gemm(TileChoice& tc, const std::vector<GemmGroup>& groups, Prec prec,
+                   const std::function<void(int, const TileWork*, int)>& launch, hipStream_t s) {
+    if (tc.cfg >= 0) return;
+    int maxm = 0, maxn = 0;
+    for (auto& g : groups) { maxm = std::max(maxm, g.M); maxn = std::max(maxn, g.N); }
+    const int heuristic = (maxm >= 128 && maxn >= 128) ? 1 : 0;
+    const char* forced = std::getenv("SYMTEN_TILE_CFG");
+    if (forced && *forced) {
+        const int c = std::atoi(forced);
+        tc.cfg = gemm_tile_ok(prec, c) ? c : heuristic;
+        ensure_tiles(tc, groups, prec, tc.cfg);
+        return;
+    }
+    const std::string key = shape_key(groups, prec);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end() && gemm_tile_ok(prec, it->second)) {
+            tc.cfg = it->second;
+            ensure_tiles(tc, groups, prec, tc.cfg);
+            return;
+        }
+    }
+    const char* off = std::getenv("SYMTEN_AUTOTUNE");
+    if (off && std::string(off) == "0") {
+        tc.cfg = heuristic;
+        ensure_tiles(tc, groups, prec, tc.cfg);
+        return;
+    }
+    hipEvent_t e[3];
+    for (auto& x : e) HIPCHK(hipEventCreate(&x));
+    int best = -1;
+    float best_ms = 0.f;
+    for (int c = 0; c < kNumTileCfg; ++c) {
+        if (!gemm_tile_ok(prec, c)) continue;
+        ensure_tiles(tc, groups, prec, c);
+        const TileWork* t = (const TileWork*)tc.tiles[c]->ptr;
+        HIPCHK(hipEventRecord(e[0], s));
+        launch(c, t, tc.ntiles[c]);   // first run: code-object load, caches
+        HIPCHK(hipEventRecord(e[1], s));
+        launch(c, t, tc.ntiles[c]);
+        HIPCHK(hipEventRecord(e[2], s));
+        HIPCHK(hipEventSynchronize(e[2]));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e[1], e[2]));
+        tc.ms[c] = ms;
+        if (best < 0 || ms < best_ms) { best = c; best_ms = ms; }
+    }
+    for (auto& x : e) (void)hipEventDestroy(x);
+    tc.cfg = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_store_locked(key, best);
 }
 
 int choose_tile_cfg(const ContractPlan& p) {
@@ -715,14 +818,9 @@ static std::shared_ptr<DevPlan> dev_plan(const ContractPlan& p) {
         x.c_buf = 2;
         gg.push_back(x);
     }
-    d->cfg = choose_tile_cfg(p);
-    std::vector<TileWork> tiles;
-    build_tiles(gg, p.prec, d->cfg, tiles);
-    d->ntiles = (int)tiles.size();
     validate_groups(gg, {p.a_panel_elems, p.b_panel_elems, p.out_elems}, p.panel_f64 ? 2 : 4);
     d->host_groups = gg;
     upload_sync(d->groups, gg.data(), gg.size() * sizeof(GemmGroup));
-    upload_sync(d->tiles, tiles.data(), tiles.size() * sizeof(TileWork));
     p.dev = d;
     return d;
 }
@@ -751,13 +849,163 @@ TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& 
                        copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks,
                                        d->nchunks, {A.data(), B.data(), pa->ptr, pb->ptr}, src64, p.panel_f64, stream);
                    });
-    profile_launch(gemm_kernel_name(p.prec, d->cfg), p.info.useful_flops, p.info.gemm_flops,
-                   prof ? gemm_bytes(d->host_groups, pe, out->esize()) : 0, stream, [&] {
-                       gemm_launch_arg((const TileWork*)d->tiles->ptr, d->ntiles, (const GemmGroup*)d->groups->ptr,
-                                       {pa->ptr, pb->ptr, out->data()}, p.prec, d->cfg, stream);
-                   });
+    auto launch = [&](int cfg, const TileWork* t, int nt) {
+        gemm_launch_arg(t, nt, (const GemmGroup*)d->groups->ptr, {pa->ptr, pb->ptr, out->data()}, p.prec, cfg, stream);
+    };
+    autotune_gemm(d->tc, d->host_groups, p.prec, launch, stream);
+    const int cfg = d->tc.cfg;
+    profile_launch(gemm_kernel_name(p.prec, cfg), p.info.useful_flops, p.info.gemm_flops,
+                   prof ? gemm_bytes(d->host_groups, pe, out->esize()) : 0, stream,
+                   [&] { launch(cfg, (const TileWork*)d->tc.tiles[cfg]->ptr, d->tc.ntiles[cfg]); });
     // pa/pb return to the pool here; later users are ordered on the same stream
     return out;
+}
+
+// ---------------------------------------------- several contractions at once
+// Independent contractions share one gather launch and one grouped-GEMM
+// launch: their copy tasks and GEMM groups are concatenated once per plan
+// combination, with buffer indices [A_0..A_n-1, B_0..B_n-1, A panels,
+// B panels, C_0..C_n-1] passed by value to the kernels.
+namespace {
+struct MultiDesc {
+    std::vector<std::shared_ptr<ContractPlan>> plans;   // keeps the plans alive
+    BufferPtr tasks, prefix, groups;
+    int ntasks = 0;
+    int64_t nchunks = 0, ap = 0, bp = 0;
+    TileChoice tc;
+    std::vector<CopyTask> host_tasks;
+    std::vector<GemmGroup> host_groups;
+    symten_plan_stats info{};
+    std::vector<int64_t> checked;   // buffer sizes already validated
+};
+std::mutex g_multi_mu;
+std::map<std::vector<const ContractPlan*>, std::shared_ptr<MultiDesc>> g_multi;
+
+std::shared_ptr<MultiDesc> multi_desc(const std::vector<std::shared_ptr<ContractPlan>>& plans) {
+    std::vector<const ContractPlan*> key;
+    for (auto& p : plans) key.push_back(p.get());
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    auto it = g_multi.find(key);
+    if (it != g_multi.end()) return it->second;
+    const int n = (int)plans.size();
+    auto d = std::make_shared<MultiDesc>();
+    d->plans = plans;
+    for (int i = 0; i < n; ++i) {
+        const ContractPlan& p = *plans[i];
+        const int64_t a0 = d->ap, b0 = d->bp;
+        d->ap += (p.a_panel_elems + 31) / 32 * 32;
+        d->bp += (p.b_panel_elems + 31) / 32 * 32;
+        for (CopyTask t : p.copies) {
+            if (t.src_buf == 0) t.src_buf = i;
+            else if (t.src_buf == 1) t.src_buf = n + i;
+            if (t.dst_buf == 2) { t.dst_buf = 2 * n; t.dst_off += a0; }
+            else { t.dst_buf = 2 * n + 1; t.dst_off += b0; }
+            d->host_tasks.push_back(t);
+        }
+        for (auto& g : p.groups) {
+            GemmGroup x{};
+            x.a_off = g.a_off + a0;
+            x.b_off = g.b_off + b0;
+            x.c_off = g.c_off;
+            x.M = g.M;
+            x.N = g.N;
+            x.K = g.K;
+            x.lda = x.ldb = g.lda;
+            x.ldc = g.N;
+            x.a_buf = 2 * n;
+            x.b_buf = 2 * n + 1;
+            x.c_buf = 2 * n + 2 + i;
+            d->host_groups.push_back(x);
+        }
+        d->info.pairs += p.info.pairs;
+        d->info.useful_flops += p.info.useful_flops;
+        d->info.gemm_flops += p.info.gemm_flops;
+        d->info.max_m = std::max(d->info.max_m, p.info.max_m);
+        d->info.max_n = std::max(d->info.max_n, p.info.max_n);
+    }
+    std::vector<int64_t> prefix;
+    copy_prefix(d->host_tasks, prefix);
+    d->ntasks = (int)d->host_tasks.size();
+    d->nchunks = prefix.back();
+    upload_sync(d->tasks, d->host_tasks.data(), d->host_tasks.size() * sizeof(CopyTask));
+    upload_sync(d->prefix, prefix.data(), prefix.size() * sizeof(int64_t));
+    upload_sync(d->groups, d->host_groups.data(), d->host_groups.size() * sizeof(GemmGroup));
+    if (g_multi.size() > 256) g_multi.clear();
+    g_multi[key] = d;
+    return d;
+}
+}  // namespace
+
+std::vector<TensorPtr> run_contractions_batched(const std::vector<std::shared_ptr<ContractPlan>>& plans,
+                                                const std::vector<const Tensor*>& As,
+                                                const std::vector<const Tensor*>& Bs, hipStream_t stream) {
+    const int n = (int)plans.size();
+    if (n == 0) return {};
+    if (n == 1) return {run_contraction(*plans[0], *As[0], *Bs[0], stream)};
+    if (n > 4) {   // 3n + 2 buffers must fit the 16-entry pointer table
+        std::vector<TensorPtr> out;
+        for (int i = 0; i < n; i += 4) {
+            const int e = std::min(n, i + 4);
+            auto part = run_contractions_batched({plans.begin() + i, plans.begin() + e}, {As.begin() + i, As.begin() + e},
+                                                 {Bs.begin() + i, Bs.begin() + e}, stream);
+            out.insert(out.end(), part.begin(), part.end());
+        }
+        return out;
+    }
+    const Prec prec = plans[0]->prec;
+    const bool src64 = As[0]->dtype == SYMTEN_F64;
+    for (int i = 0; i < n; ++i) {
+        check_device_tensor(*As[i], "contract(A)");
+        check_device_tensor(*Bs[i], "contract(B)");
+        if (plans[i]->prec != prec || (As[i]->dtype == SYMTEN_F64) != src64)
+            fail(SYMTEN_E_INVAL, "batched contractions must share precision and storage type");
+    }
+    auto d = multi_desc(plans);
+    std::vector<TensorPtr> outs(n);
+    std::vector<int64_t> sizes(3 * n + 2);
+    for (int i = 0; i < n; ++i) {
+        outs[i] = std::make_shared<Tensor>(*plans[i]->out_meta);
+        outs[i]->meta_only = false;
+        outs[i]->buf = device_alloc(std::max<int64_t>(plans[i]->out_elems, 1) * outs[i]->esize());
+        sizes[i] = As[i]->elems;
+        sizes[n + i] = Bs[i]->elems;
+        sizes[2 * n + 2 + i] = plans[i]->out_elems;
+    }
+    sizes[2 * n] = d->ap;
+    sizes[2 * n + 1] = d->bp;
+    if (d->host_groups.empty()) return outs;
+    if (d->checked != sizes) {
+        validate_tasks(d->host_tasks, sizes);
+        validate_groups(d->host_groups, sizes, plans[0]->panel_f64 ? 2 : 4);
+        d->checked = sizes;
+    }
+    const size_t pe = plans[0]->panel_f64 ? 8 : 4;
+    BufferPtr pa = device_alloc(std::max<int64_t>(d->ap, 1) * pe);
+    BufferPtr pb = device_alloc(std::max<int64_t>(d->bp, 1) * pe);
+    std::vector<void*> ptrs(3 * n + 2);
+    for (int i = 0; i < n; ++i) {
+        ptrs[i] = As[i]->data();
+        ptrs[n + i] = Bs[i]->data();
+        ptrs[2 * n + 2 + i] = outs[i]->data();
+    }
+    ptrs[2 * n] = pa->ptr;
+    ptrs[2 * n + 1] = pb->ptr;
+    const bool prof = profiling();
+    const size_t se = src64 ? 8 : 4;
+    profile_launch(std::string("copy_kernel<") + (src64 ? "f64" : "f32") + "," + (pe == 8 ? "f64" : "f32") + ">", 0, 0,
+                   prof ? copy_bytes(d->host_tasks, se, pe) : 0, stream, [&] {
+                       copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks,
+                                       d->nchunks, ptrs, src64, pe == 8, stream);
+                   });
+    auto launch = [&](int cfg, const TileWork* t, int nt) {
+        gemm_launch_arg(t, nt, (const GemmGroup*)d->groups->ptr, ptrs, prec, cfg, stream);
+    };
+    autotune_gemm(d->tc, d->host_groups, prec, launch, stream);
+    const int cfg = d->tc.cfg;
+    profile_launch(gemm_kernel_name(prec, cfg), d->info.useful_flops, d->info.gemm_flops,
+                   prof ? gemm_bytes(d->host_groups, pe, se) : 0, stream,
+                   [&] { launch(cfg, (const TileWork*)d->tc.tiles[cfg]->ptr, d->tc.ntiles[cfg]); });
+    return outs;
 }
 
 // ------------------------------------------------------------ double layer
