@@ -28,7 +28,7 @@ void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix);
 void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles);
 void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
-                     void* const* d_ptrs, bool src_f64, bool dst_f64, hipStream_t s);
+                     void* const* d_ptrs, bool src_f64, int dst_kind, hipStream_t s);
 void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, void* const* d_ptrs,
                      Prec prec, int cfg, hipStream_t s);
 int choose_tile_cfg(const ContractPlan& p);
@@ -707,16 +707,24 @@ void build_step(BatchStep& B, const std::vector<const Tensor*>& As, const std::v
     for (int i = 0; i < n; ++i)
         if (B.plans[i]->prec != B.prec || (As[i]->dtype == SYMTEN_F64) != B.src_f64)
             fail(SYMTEN_E_INVAL, "batched corners: inputs differ in storage type");
+    const int pl = panel_planes(B.prec);
+    if (B.prec == Prec::BF16X3) {   // lo planes follow the concatenated hi planes
+        for (auto& t : tasks) t.lo_off = t.dst_buf == 2 * n ? ap : bp;
+        for (auto& g : groups) {
+            g.a_lo = ap;
+            g.b_lo = bp;
+        }
+    }
     {
         std::vector<int64_t> sizes(2 * n + 3);
         for (int i = 0; i < n; ++i) { sizes[i] = As[i]->elems; sizes[n + i] = Bs[i]->elems; }
-        sizes[2 * n] = ap;
-        sizes[2 * n + 1] = bp;
+        sizes[2 * n] = pl * ap;
+        sizes[2 * n + 1] = pl * bp;
         sizes[2 * n + 2] = cp;
         validate_tasks(tasks, sizes);
-        validate_groups(groups, sizes, B.panel_f64 ? 2 : 4);
+        validate_groups(groups, sizes, panel_vw(B.prec));
     }
-    const size_t pe = B.panel_f64 ? 8 : 4;
+    const size_t pe = panel_esize(B.prec) * pl;
     const size_t oe = B.src_f64 ? 8 : 4;
     B.apanel = device_alloc(std::max<int64_t>(ap, 1) * pe);
     B.bpanel = device_alloc(std::max<int64_t>(bp, 1) * pe);
@@ -750,12 +758,10 @@ void set_table(BatchStep& B, const std::vector<void*>& a, const std::vector<void
 // One step of a batch: gather launch, then grouped GEMM.  With tune = true
 // (never under graph capture) the tile configuration is chosen first.
 void run_step(BatchStep& B, hipStream_t s, bool tune = false) {
-    profile_launch(std::string("copy_kernel<") + (B.src_f64 ? "f64" : "f32") + "," + (B.panel_f64 ? "f64" : "f32") +
-                       ",batched>",
-                   0, 0, B.copy_bytes, s, [&] {
-                       copy_launch_dev((const CopyTask*)B.tasks->ptr, (const int64_t*)B.prefix->ptr, B.ntasks,
-                                       B.nchunks, (void* const*)B.ptrs->ptr, B.src_f64, B.panel_f64, s);
-                   });
+    profile_launch(copy_kernel_name(B.src_f64, B.prec) + ",batched", 0, 0, B.copy_bytes, s, [&] {
+        copy_launch_dev((const CopyTask*)B.tasks->ptr, (const int64_t*)B.prefix->ptr, B.ntasks, B.nchunks,
+                        (void* const*)B.ptrs->ptr, B.src_f64, panel_dst_kind(B.prec), s);
+    });
     auto launch = [&](int cfg, const TileWork* t, int nt) {
         gemm_launch_dev(t, nt, (const GemmGroup*)B.groups->ptr, (void* const*)B.ptrs->ptr, B.prec, cfg, s);
     };

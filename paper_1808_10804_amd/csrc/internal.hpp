@@ -98,6 +98,7 @@ struct CopyTask {
     int count;          // product of dims (< 2^31)
     float scale;        // multiplies the copied value
     int pad_;
+    int64_t lo_off;     // split panels: the lo plane starts lo_off elements after the hi plane
 };
 
 struct GemmGroup {
@@ -107,7 +108,9 @@ struct GemmGroup {
     int a_buf, b_buf, c_buf;
     int tiles_n;                   // tiles along N (for tile decoding)
     int pad_;
+    int64_t a_lo, b_lo;            // split panels: offset of the lo plane from the hi plane
 };
+
 
 struct TileWork {
     int group, tm, tn, kz;
@@ -118,6 +121,12 @@ constexpr int kMaxBufs = 512;
 
 // Element type of a panel / buffer in a GEMM launch.
 enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X3 = 3 };
+
+// Panel element type per precision: FP64 -> double, FP32 -> float,
+// BF16 -> one bf16 plane, BF16X3 -> bf16 hi and lo planes.
+inline size_t panel_esize(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
+inline int panel_planes(Prec p) { return p == Prec::BF16X3 ? 2 : 1; }
+inline int panel_vw(Prec p) { return p == Prec::F64 ? 2 : (p == Prec::F32 ? 4 : 8); }   // 16-byte vectors
 
 struct LaunchCtx;   // owns staging memory for descriptors
 
@@ -227,6 +236,8 @@ void profile_launch(const std::string& name, int64_t uf, int64_t gf, int64_t byt
 void profile_begin();
 std::vector<symten_kernel_stat> profile_end();
 std::string gemm_kernel_name(Prec p, int cfg);
+std::string copy_kernel_name(bool src64, Prec p);
+int panel_dst_kind(Prec p);
 int64_t copy_bytes(const std::vector<CopyTask>& tasks, size_t se, size_t de);
 int64_t gemm_bytes(const std::vector<GemmGroup>& gs, size_t pe, size_t oe);
 

@@ -40,7 +40,23 @@ struct DevPtrs {
 constexpr int kCopyChunk = 1024;
 constexpr int kCopyThreads = 256;
 
-template <class Ptrs, typename TS, typename TD>
+__device__ __forceinline__ unsigned short f32_to_bf16_rn(float x) {
+    // round to nearest, ties to even, on the bit pattern (finite inputs;
+    // NaN keeps a quiet mantissa bit)
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// Destination kinds of the gather: float, double, one bf16 plane, or the
+// split x = hi + lo with hi = bf16(x), lo = bf16(x - hi) in two planes.
+enum : int { kDstF32 = 0, kDstF64 = 1, kDstBF16 = 2, kDstSplit = 3 };
+
+template <class Ptrs, typename TS, int DK>
 __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __restrict__ tasks,
                                                             const int64_t* __restrict__ chunk_prefix,
                                                             int ntasks, Ptrs ptrs) {
@@ -53,7 +69,7 @@ __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __re
     const CopyTask& T = tasks[lo];
     const int64_t base = (chunk - chunk_prefix[lo]) * kCopyChunk;
     const TS* __restrict__ src = T.src_buf >= 0 ? (const TS*)ptrs.get(T.src_buf) : nullptr;
-    TD* __restrict__ dst = (TD*)ptrs.get(T.dst_buf);
+    void* dstv = ptrs.get(T.dst_buf);
     const int rank = T.rank;
     const float scale = T.scale;
     for (int e = threadIdx.x; e < kCopyChunk; e += kCopyThreads) {
@@ -69,9 +85,16 @@ __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __re
             so += (int64_t)ik * T.sstride[k];
             dofs += (int64_t)ik * T.dstride[k];
         }
-        TD v = (TD)0;
-        if (src) v = (TD)src[so] * (TD)scale;
-        dst[dofs] = v;
+        if constexpr (DK == kDstF64) {
+            ((double*)dstv)[dofs] = src ? (double)src[so] * (double)scale : 0.0;
+        } else if constexpr (DK == kDstF32) {
+            ((float*)dstv)[dofs] = src ? (float)src[so] * scale : 0.f;
+        } else {
+            const float v = src ? (float)src[so] * scale : 0.f;
+            const unsigned short h = f32_to_bf16_rn(v);
+            ((unsigned short*)dstv)[dofs] = h;
+            if constexpr (DK == kDstSplit) ((unsigned short*)dstv)[dofs + T.lo_off] = f32_to_bf16_rn(v - bf16_to_f32(h));
+        }
     }
 }
 
@@ -82,18 +105,6 @@ template <int BM_, int BN_, int BK_>
 struct TileShape {
     static constexpr int BM = BM_, BN = BN_, BK = BK_;
 };
-
-__device__ __forceinline__ unsigned short f32_to_bf16_rn(float x) {
-    // round to nearest, ties to even, on the bit pattern (finite inputs;
-    // NaN keeps a quiet mantissa bit)
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
-    return __uint_as_float(((uint32_t)h) << 16);
-}
 
 // ---- FP64: v_mfma_f64_16x16x4f64 -----------------------------------------
 // lane l: A[row l%16][k l/16], B[col l%16][k l/16]; acc e: row l/16 + 4*e, col l%16 (checked on gfx950)
@@ -372,6 +383,134 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
         }
 }
 
+// ---- BF16 panels: v_mfma_f32_32x32x16_bf16 ---------------------------------
+// The gather has already rounded (BF16) or split (BF16X3: hi plane, lo plane
+// a_lo / b_lo elements later) the operands, so tiles go global -> LDS as
+// 16-byte vectors with no conversion.  bf16x3 accumulates lo*hi and hi*lo
+// before hi*hi, all in FP32.
+template <class Ptrs, class S, bool SPLIT>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restrict__ tiles,
+                                                        const GemmGroup* __restrict__ groups, Ptrs ptrs) {
+    constexpr int BM = S::BM, BN = S::BN, BK = S::BK;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int TI = WM / 32, TJ = WN / 32;
+    constexpr int LDH = BK + 8;
+    constexpr int PL = SPLIT ? 2 : 1;
+    static_assert(TI >= 1 && TJ >= 1 && BK % 16 == 0, "tile shape");
+    __shared__ __attribute__((aligned(16))) unsigned short As[PL][BM * LDH];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[PL][BN * LDH];
+
+    const TileWork tw = tiles[blockIdx.x];
+    const GemmGroup g = groups[tw.group];
+    const unsigned short* __restrict__ A = (const unsigned short*)ptrs.get(g.a_buf) + g.a_off;
+    const unsigned short* __restrict__ B = (const unsigned short*)ptrs.get(g.b_buf) + g.b_off;
+    float* __restrict__ C = (float*)ptrs.get(g.c_buf) + g.c_off;
+    const int m0 = tw.tm * BM, n0 = tw.tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+
+    constexpr int VA = BM * BK / 8 / 256;   // 16-byte vectors per thread and plane
+    constexpr int VB = BN * BK / 8 / 256;
+    static_assert(VA >= 1 && VB >= 1, "tile too small");
+    us8_t ra[PL][VA], rb[PL][VB];
+    const us8_t zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < PL; ++p) {
+#pragma unroll
+            for (int v = 0; v < VA; ++v) {
+                const int idx = tid + v * 256;
+                const int r = idx / (BK / 8), kq = (idx % (BK / 8)) * 8;
+                const int gr = m0 + r, gk = k0 + kq;
+                ra[p][v] = (gr < g.M && gk < g.lda)
+                               ? *(const us8_t*)(A + (p ? g.a_lo : 0) + (int64_t)gr * g.lda + gk)
+                               : zero8;
+            }
+#pragma unroll
+            for (int v = 0; v < VB; ++v) {
+                const int idx = tid + v * 256;
+                const int r = idx / (BK / 8), kq = (idx % (BK / 8)) * 8;
+                const int gr = n0 + r, gk = k0 + kq;
+                rb[p][v] = (gr < g.N && gk < g.ldb)
+                               ? *(const us8_t*)(B + (p ? g.b_lo : 0) + (int64_t)gr * g.ldb + gk)
+                               : zero8;
+            }
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int p = 0; p < PL; ++p) {
+#pragma unroll
+            for (int v = 0; v < VA; ++v) {
+                const int idx = tid + v * 256;
+                const int r = idx / (BK / 8), kq = (idx % (BK / 8)) * 8;
+                *(us8_t*)(&As[p][r * LDH + kq]) = ra[p][v];
+            }
+#pragma unroll
+            for (int v = 0; v < VB; ++v) {
+                const int idx = tid + v * 256;
+                const int r = idx / (BK / 8), kq = (idx % (BK / 8)) * 8;
+                *(us8_t*)(&Bs[p][r * LDH + kq]) = rb[p][v];
+            }
+        }
+    };
+
+    f16_t acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+    const int K = g.K;
+    if (K > 0) gload(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        sstore();
+        __syncthreads();
+        if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            bf8_t ah[TI], bh[TJ], al[TI], bl[TJ];
+#pragma unroll
+            for (int i = 0; i < TI; ++i) {
+                const int o = (wm + i * 32 + (lane & 31)) * LDH + kk + 8 * (lane >> 5);
+                ah[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&As[0][o]));
+                if constexpr (SPLIT) al[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&As[PL - 1][o]));
+            }
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) {
+                const int o = (wn + j * 32 + (lane & 31)) * LDH + kk + 8 * (lane >> 5);
+                bh[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&Bs[0][o]));
+                if constexpr (SPLIT) bl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&Bs[PL - 1][o]));
+            }
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j) {
+                    if constexpr (SPLIT) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    }
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int col = n0 + wn + j * 32 + (lane & 31);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = m0 + wm + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+                if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
+            }
+        }
+}
+
 // ================================================================ utilities
 __global__ void cast_kernel_d2f(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -574,41 +713,45 @@ void launch_double_layer(const DoubleLayerArgs& a, hipStream_t s) {
 }
 
 // ---- prepared launches: device descriptors owned by the caller ------------
-void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
-                     void* const* d_ptrs, bool src_f64, bool dst_f64, hipStream_t s) {
-    if (ntasks <= 0 || nchunks <= 0) return;
-    DevPtrs P{d_ptrs};
+template <class Ptrs>
+static void copy_dispatch(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks, Ptrs P,
+                          bool src_f64, int dst_kind, hipStream_t s) {
     dim3 grid((unsigned)nchunks), block(kCopyThreads);
-    if (src_f64 && dst_f64)
-        hipLaunchKernelGGL((copy_kernel<DevPtrs, double, double>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
-    else if (src_f64)
-        hipLaunchKernelGGL((copy_kernel<DevPtrs, double, float>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
-    else if (dst_f64)
-        hipLaunchKernelGGL((copy_kernel<DevPtrs, float, double>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
-    else
-        hipLaunchKernelGGL((copy_kernel<DevPtrs, float, float>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
+#define SYMTEN_COPY(TS, DK) \
+    hipLaunchKernelGGL((copy_kernel<Ptrs, TS, DK>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P)
+    if (src_f64) {
+        switch (dst_kind) {
+            case kDstF64: SYMTEN_COPY(double, kDstF64); break;
+            case kDstF32: SYMTEN_COPY(double, kDstF32); break;
+            default: fail(SYMTEN_E_INVAL, "copy: bf16 panels need FP32 sources");
+        }
+    } else {
+        switch (dst_kind) {
+            case kDstF64: SYMTEN_COPY(float, kDstF64); break;
+            case kDstF32: SYMTEN_COPY(float, kDstF32); break;
+            case kDstBF16: SYMTEN_COPY(float, kDstBF16); break;
+            default: SYMTEN_COPY(float, kDstSplit); break;
+        }
+    }
+#undef SYMTEN_COPY
     HIPCHK(hipGetLastError());
 }
 
+void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+                     void* const* d_ptrs, bool src_f64, int dst_kind, hipStream_t s) {
+    if (ntasks <= 0 || nchunks <= 0) return;
+    copy_dispatch(d_tasks, d_prefix, ntasks, nchunks, DevPtrs{d_ptrs}, src_f64, dst_kind, s);
+}
+
 void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
-                     const std::vector<void*>& ptrs, bool src_f64, bool dst_f64, hipStream_t s) {
+                     const std::vector<void*>& ptrs, bool src_f64, int dst_kind, hipStream_t s) {
     if (ntasks <= 0 || nchunks <= 0) return;
     if (ptrs.size() > 16) fail(SYMTEN_E_CAPACITY, "copy_launch_arg: more than 16 buffers");
     ArgPtrs P{};
     for (size_t i = 0; i < ptrs.size(); ++i) P.p[i] = ptrs[i];
-    dim3 grid((unsigned)nchunks), block(kCopyThreads);
-    if (src_f64 && dst_f64)
-        hipLaunchKernelGGL((copy_kernel<ArgPtrs, double, double>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
-    else if (src_f64)
-        hipLaunchKernelGGL((copy_kernel<ArgPtrs, double, float>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
-    else if (dst_f64)
-        hipLaunchKernelGGL((copy_kernel<ArgPtrs, float, double>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
-    else
-        hipLaunchKernelGGL((copy_kernel<ArgPtrs, float, float>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P);
-    HIPCHK(hipGetLastError());
+    copy_dispatch(d_tasks, d_prefix, ntasks, nchunks, P, src_f64, dst_kind, s);
 }
 
-// tile config ids: 0 = 64x64, 1 = 128x128
 // Tile shapes (BM x BN): 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128,
 // 4 = 256x128 (FP32/BF16 kernels only).
 static const int kTileBM[kNumTileCfg] = {64, 128, 128, 64, 256};
@@ -617,15 +760,27 @@ int gemm_tile_bm(Prec p, int cfg) { (void)p; return kTileBM[cfg]; }
 int gemm_tile_bn(Prec p, int cfg) { (void)p; return kTileBN[cfg]; }
 bool gemm_tile_ok(Prec p, int cfg) { return cfg >= 0 && cfg < kNumTileCfg && !(p == Prec::F64 && cfg == 4); }
 
-template <class Ptrs, int MODE>
+template <class Ptrs>
 static void launch_f32_family(int cfg, dim3 grid, hipStream_t s, const TileWork* t, const GemmGroup* g, Ptrs P) {
     dim3 block(256);
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, MODE>), grid, block, 0, s, t, g, P); break;
-        case 1: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, MODE>), grid, block, 0, s, t, g, P); break;
-        case 2: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 32>, MODE>), grid, block, 0, s, t, g, P); break;
-        case 3: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 32>, MODE>), grid, block, 0, s, t, g, P); break;
-        default: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<256, 128, 32>, MODE>), grid, block, 0, s, t, g, P); break;
+        case 0: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, 1>), grid, block, 0, s, t, g, P); break;
+        case 1: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
+        case 2: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 32>, 1>), grid, block, 0, s, t, g, P); break;
+        case 3: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
+        default: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<256, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
+    }
+}
+
+template <class Ptrs, bool SPLIT>
+static void launch_bf16_family(int cfg, dim3 grid, hipStream_t s, const TileWork* t, const GemmGroup* g, Ptrs P) {
+    dim3 block(256);
+    switch (cfg) {
+        case 0: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 64, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
+        case 1: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
+        case 2: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 64, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
+        case 3: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
+        default: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<256, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
     }
 }
 
@@ -643,9 +798,9 @@ static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* 
                 default: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
             }
             break;
-        case Prec::F32: launch_f32_family<Ptrs, 1>(cfg, grid, s, d_tiles, d_groups, P); break;
-        case Prec::BF16: launch_f32_family<Ptrs, 2>(cfg, grid, s, d_tiles, d_groups, P); break;
-        case Prec::BF16X3: launch_f32_family<Ptrs, 3>(cfg, grid, s, d_tiles, d_groups, P); break;
+        case Prec::F32: launch_f32_family<Ptrs>(cfg, grid, s, d_tiles, d_groups, P); break;
+        case Prec::BF16: launch_bf16_family<Ptrs, false>(cfg, grid, s, d_tiles, d_groups, P); break;
+        case Prec::BF16X3: launch_bf16_family<Ptrs, true>(cfg, grid, s, d_tiles, d_groups, P); break;
     }
     HIPCHK(hipGetLastError());
 }

@@ -19,7 +19,22 @@ namespace symten {
 
 // launchers defined in kernels.hip
 void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
-                     const std::vector<void*>& ptrs, bool src_f64, bool dst_f64, hipStream_t s);
+                     const std::vector<void*>& ptrs, bool src_f64, int dst_kind, hipStream_t s);
+
+// gather destination kind for the panels of a precision (see copy_kernel)
+int panel_dst_kind(Prec p) {
+    switch (p) {
+        case Prec::F64: return 1;
+        case Prec::F32: return 0;
+        case Prec::BF16: return 2;
+        default: return 3;
+    }
+}
+
+std::string copy_kernel_name(bool src64, Prec p) {
+    static const char* dst[] = {"f64", "f32", "bf16", "bf16x2"};
+    return std::string("copy_kernel<") + (src64 ? "f64" : "f32") + "," + dst[(int)p] + ">";
+}
 void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
                      const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s);
 int gemm_tile_bm(Prec p, int cfg);
@@ -302,7 +317,7 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
     auto plan = std::make_shared<ContractPlan>();
     plan->prec = p;
     plan->panel_f64 = (p == Prec::F64);
-    const int VW = plan->panel_f64 ? 2 : 4;   // 16-byte vectors in the GEMM loads
+    const int VW = panel_vw(p);   // 16-byte vectors in the GEMM loads
 
     // group blocks by the contracted charge seen from A
     std::map<int, GroupBuild> gb;
@@ -522,6 +537,8 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
     plan->b_panel_elems = b_pos;
     plan->out_elems = c_pos;
     plan->info = info;
+    if (p == Prec::BF16X3)   // lo plane follows the whole hi plane of its panel buffer
+        for (auto& t : plan->copies) t.lo_off = t.dst_buf == 2 ? a_pos : b_pos;
     return plan;
 }
 
@@ -770,7 +787,9 @@ void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_
             (ds >= 0 ? dmax : dmin) += ds;
             (ss >= 0 ? smax : smin) += ss;
         }
-        if (t.dst_buf < 0 || t.dst_buf >= (int)buf_elems.size() || dmin < 0 || dmax >= buf_elems[t.dst_buf])
+        // split panels also write lo_off elements further (the lo plane)
+        if (t.dst_buf < 0 || t.dst_buf >= (int)buf_elems.size() || dmin < 0 || t.lo_off < 0 ||
+            dmax + t.lo_off >= buf_elems[t.dst_buf])
             fail(SYMTEN_E_INVAL, "internal: copy destination out of bounds");
         if (t.src_buf >= 0 && (t.src_buf >= (int)buf_elems.size() || smin < 0 || smax >= buf_elems[t.src_buf]))
             fail(SYMTEN_E_INVAL, "internal: copy source out of bounds");
@@ -788,6 +807,9 @@ void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int
         if (!in(g.a_buf, g.a_off, (int64_t)g.M * g.lda) || !in(g.b_buf, g.b_off, (int64_t)g.N * g.ldb) ||
             !in(g.c_buf, g.c_off, (int64_t)(g.M - 1) * g.ldc + g.N))
             fail(SYMTEN_E_INVAL, "internal: GEMM operand out of bounds");
+        if (g.a_lo % vw || g.b_lo % vw || !in(g.a_buf, g.a_off + g.a_lo, (int64_t)g.M * g.lda) ||
+            !in(g.b_buf, g.b_off + g.b_lo, (int64_t)g.N * g.ldb))
+            fail(SYMTEN_E_INVAL, "internal: GEMM lo plane out of bounds");
     }
 }
 
@@ -816,9 +838,14 @@ static std::shared_ptr<DevPlan> dev_plan(const ContractPlan& p) {
         x.a_buf = 0;
         x.b_buf = 1;
         x.c_buf = 2;
+        if (p.prec == Prec::BF16X3) {
+            x.a_lo = p.a_panel_elems;
+            x.b_lo = p.b_panel_elems;
+        }
         gg.push_back(x);
     }
-    validate_groups(gg, {p.a_panel_elems, p.b_panel_elems, p.out_elems}, p.panel_f64 ? 2 : 4);
+    const int pl = panel_planes(p.prec);
+    validate_groups(gg, {pl * p.a_panel_elems, pl * p.b_panel_elems, p.out_elems}, panel_vw(p.prec));
     d->host_groups = gg;
     upload_sync(d->groups, gg.data(), gg.size() * sizeof(GemmGroup));
     p.dev = d;
@@ -833,22 +860,22 @@ TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& 
     out->buf = device_alloc(std::max<int64_t>(p.out_elems, 1) * out->esize());
     if (p.groups.empty()) return out;
     auto d = dev_plan(p);
+    const int pl = panel_planes(p.prec);
     if (d->checked_a != A.elems || d->checked_b != B.elems) {
-        validate_tasks(p.copies, {A.elems, B.elems, p.a_panel_elems, p.b_panel_elems});
+        validate_tasks(p.copies, {A.elems, B.elems, pl * p.a_panel_elems, pl * p.b_panel_elems});
         d->checked_a = A.elems;
         d->checked_b = B.elems;
     }
-    const size_t pe = p.panel_f64 ? 8 : 4;
+    const size_t pe = panel_esize(p.prec) * pl;   // bytes per panel element, all planes
     BufferPtr pa = device_alloc(std::max<int64_t>(p.a_panel_elems, 1) * pe);
     BufferPtr pb = device_alloc(std::max<int64_t>(p.b_panel_elems, 1) * pe);
     const bool src64 = A.dtype == SYMTEN_F64;
     const size_t se = src64 ? 8 : 4;
     const bool prof = profiling();
-    profile_launch(std::string("copy_kernel<") + (src64 ? "f64" : "f32") + "," + (p.panel_f64 ? "f64" : "f32") + ">",
-                   0, 0, prof ? copy_bytes(p.copies, se, pe) : 0, stream, [&] {
-                       copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks,
-                                       d->nchunks, {A.data(), B.data(), pa->ptr, pb->ptr}, src64, p.panel_f64, stream);
-                   });
+    profile_launch(copy_kernel_name(src64, p.prec), 0, 0, prof ? copy_bytes(p.copies, se, pe) : 0, stream, [&] {
+        copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->nchunks,
+                        {A.data(), B.data(), pa->ptr, pb->ptr}, src64, panel_dst_kind(p.prec), stream);
+    });
     auto launch = [&](int cfg, const TileWork* t, int nt) {
         gemm_launch_arg(t, nt, (const GemmGroup*)d->groups->ptr, {pa->ptr, pb->ptr, out->data()}, p.prec, cfg, stream);
     };
@@ -923,6 +950,13 @@ std::shared_ptr<MultiDesc> multi_desc(const std::vector<std::shared_ptr<Contract
         d->info.max_m = std::max(d->info.max_m, p.info.max_m);
         d->info.max_n = std::max(d->info.max_n, p.info.max_n);
     }
+    if (plans[0]->prec == Prec::BF16X3) {   // lo planes follow the concatenated hi planes
+        for (auto& t : d->host_tasks) t.lo_off = t.dst_buf == 2 * n ? d->ap : d->bp;
+        for (auto& g : d->host_groups) {
+            g.a_lo = d->ap;
+            g.b_lo = d->bp;
+        }
+    }
     std::vector<int64_t> prefix;
     copy_prefix(d->host_tasks, prefix);
     d->ntasks = (int)d->host_tasks.size();
@@ -971,15 +1005,16 @@ std::vector<TensorPtr> run_contractions_batched(const std::vector<std::shared_pt
         sizes[n + i] = Bs[i]->elems;
         sizes[2 * n + 2 + i] = plans[i]->out_elems;
     }
-    sizes[2 * n] = d->ap;
-    sizes[2 * n + 1] = d->bp;
+    const int pl = panel_planes(prec);
+    sizes[2 * n] = pl * d->ap;
+    sizes[2 * n + 1] = pl * d->bp;
     if (d->host_groups.empty()) return outs;
     if (d->checked != sizes) {
         validate_tasks(d->host_tasks, sizes);
-        validate_groups(d->host_groups, sizes, plans[0]->panel_f64 ? 2 : 4);
+        validate_groups(d->host_groups, sizes, panel_vw(prec));
         d->checked = sizes;
     }
-    const size_t pe = plans[0]->panel_f64 ? 8 : 4;
+    const size_t pe = panel_esize(prec) * pl;
     BufferPtr pa = device_alloc(std::max<int64_t>(d->ap, 1) * pe);
     BufferPtr pb = device_alloc(std::max<int64_t>(d->bp, 1) * pe);
     std::vector<void*> ptrs(3 * n + 2);
@@ -992,11 +1027,10 @@ std::vector<TensorPtr> run_contractions_batched(const std::vector<std::shared_pt
     ptrs[2 * n + 1] = pb->ptr;
     const bool prof = profiling();
     const size_t se = src64 ? 8 : 4;
-    profile_launch(std::string("copy_kernel<") + (src64 ? "f64" : "f32") + "," + (pe == 8 ? "f64" : "f32") + ">", 0, 0,
-                   prof ? copy_bytes(d->host_tasks, se, pe) : 0, stream, [&] {
-                       copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks,
-                                       d->nchunks, ptrs, src64, pe == 8, stream);
-                   });
+    profile_launch(copy_kernel_name(src64, prec), 0, 0, prof ? copy_bytes(d->host_tasks, se, pe) : 0, stream, [&] {
+        copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->nchunks, ptrs,
+                        src64, panel_dst_kind(prec), stream);
+    });
     auto launch = [&](int cfg, const TileWork* t, int nt) {
         gemm_launch_arg(t, nt, (const GemmGroup*)d->groups->ptr, ptrs, prec, cfg, stream);
     };
