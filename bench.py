@@ -80,12 +80,85 @@ def cpu_baseline(cfgd):
             "seconds": dt}
 
 
+def build_corner_inputs(cfgd, key, dtype, st, draw, TENSOR_INDEX):
+    """C1, T1, T4, a of one corner-1 contraction with seeded draws."""
+    phys, virt, chi, flux = cfgd["phys"], cfgd["virt"], cfgd["chi"], cfgd["flux"]
+    A = st.Tensor.create([(phys, 1), (virt, 1), (virt, 1), (virt, -1), (virt, -1)], flux, dtype)
+    A.upload(draw(key + (TENSOR_INDEX["A"],), A.nnz))
+    a = st.double_layer(A)
+    dd = a.legs()[0][0]
+    T = {"a": a}
+    legs = {"C1": [(chi, 1), (chi, -1)], "T1": [(chi, 1), (dd, -1), (chi, -1)], "T4": [(chi, 1), (dd, -1), (chi, -1)]}
+    for n, l in legs.items():
+        T[n] = st.Tensor.create(l, 0, dtype)
+        T[n].upload(draw(key + (TENSOR_INDEX[n],), T[n].nnz))
+    return T
+
+
+def bench_batched(args):
+    """64 independent corner contractions: one grouped launch per step in
+    bf16x3 (HIP graph) against per-contraction FP32 launches."""
+    import torch
+    import paper_1808_10804_amd as st
+    from synth import config, draw, batched_draws, TENSOR_INDEX
+
+    c5 = config(5)
+    draws = batched_draws(c5["seed"], c5["batch"], c5["D_choices"], c5["chi_range"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    ins = [build_corner_inputs(dict(phys=c5["phys"], flux=c5["flux"], virt=d["virt"], chi=d["chi"]),
+                               (c5["seed"], b), "f32", st, draw, TENSOR_INDEX) for b, d in enumerate(draws)]
+    Cs, T1s, T4s, As = ([x[k] for x in ins] for k in ("C1", "T1", "T4", "a"))
+
+    def run_batched():
+        return st.enlarged_corners_batched(Cs, T1s, T4s, As, prec=args.prec or "bf16x3", use_graph=True,
+                                           stream=stream)
+
+    def run_single():
+        fl = 0
+        for x in ins:
+            _, info = st.enlarged_corner(1, x["C1"], x["T1"], x["T4"], x["a"], prec="f32", stream=stream)
+            fl += info["useful_flops"]
+        return fl
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, r
+
+    ms_b, (outs, info) = timed(run_batched, args.steps)
+    ms_s, fl_s = timed(run_single, max(1, args.steps // 2))
+    flops = info["useful_flops"]
+    st.profile_begin()
+    for _ in range(args.steps):
+        run_batched()
+    torch.cuda.synchronize()
+    kst = st.profile_end()
+    out = {
+        "metric": "useful GFLOP/s of 64 batched enlarged corners (bf16x3, one grouped launch per step, HIP graph)",
+        "value": flops / (ms_b * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.prec or "bf16x3", "data": "synthetic (seeded Gaussian blocks)",
+        "config": {"workload": c5["name"], "batch": c5["batch"], "D": [d["D"] for d in draws],
+                   "chi": [d["chi_total"] for d in draws]},
+        "useful_flops": flops, "per_contraction_f32": {"ms": ms_s, "gflops": fl_s / (ms_s * 1e-3) / 1e9},
+        "speedup_vs_per_contraction_f32": ms_s / ms_b,
+        "kernels": sorted(kst, key=lambda k: -k["ms"])[:6],
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 4])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 4, 5])
     ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -93,6 +166,9 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "the move's multi-GPU sharding is described, not implemented.", file=sys.stderr)
         sys.exit(2)
+    if args.config == 5:
+        bench_batched(args)
+        return
 
     import torch
     import paper_1808_10804_amd as st
