@@ -10,9 +10,28 @@
  * (Sec. 2, contraction rule r_k = m_t . m_s); results with equal open labels
  * are summed in place (Sec. 2, grouping by output quantum numbers).
  *
+ * SU(2) tensors (Sec. 2, Eq. tensor-cgc: each block is a reduced tensor
+ * times a generalised Clebsch-Gordan tensor) carry one doubled spin 2j per
+ * leg and one coupling tree per block: the incoming legs, in leg order, are
+ * coupled left to right by Clebsch-Gordan coefficients (Condon-Shortley
+ * phase) to a total spin K, the outgoing legs likewise to the same K, and
+ * the block's basis tensor is c[m..] = sum_M C_in(m_in; K M) C_out(m_out; K M).
+ * The tree labels are (in-chain intermediate spins, out-chain intermediate
+ * spins, K), all doubled.  Contracting two such tensors multiplies the
+ * reduced blocks and expands each product of basis tensors in the output's
+ * basis; the expansion coefficients (recoupling scalars) are computed on the
+ * host in FP64 when the contraction is planned and scale the gathered A
+ * operands (Sec. 2, reduction of blocks with parallel CGCs).
+ *
  * Conventions shared by every entry point:
- *  - U(1) charges are integers in units of 2*S^z.  Only U(1) is implemented;
- *    SYMTEN_SU2 descriptors are rejected with SYMTEN_E_UNSUPPORTED.
+ *  - U(1) charges are integers in units of 2*S^z; SU(2) labels are doubled
+ *    spins 2j (0..64) and an SU(2) tensor's flux must be 0 (Sec. 2: no
+ *    quantum-number shift inside a tensor), else SYMTEN_E_SYM.
+ *  - SU(2) sector dims are multiplet counts (reduced dims); a multiplet of
+ *    spin j holds 2j+1 states.  The SU(2) path covers tensors and
+ *    contractions (symten_contract, symten_plan_info, symten_enlarged_corner);
+ *    the double layer, the batched corners and ctm_move take U(1) only
+ *    (SYMTEN_E_UNSUPPORTED otherwise).
  *  - A leg's sectors are given as parallel arrays (label, reduced dim); the
  *    library sorts them by label ascending, which fixes the state order.
  *  - Canonical block order is lexicographic in the labels, leg 0 slowest.
@@ -82,13 +101,14 @@ typedef struct ctm_env* ctm_env_t;
  * of each leg's sector list; leg l owns nsec[l] consecutive entries.
  * Sectors of dim 0 are ignored; labels within a leg must be distinct.      */
 typedef struct {
-    int group;          /* SYMTEN_U1 (SYMTEN_SU2 rejected)                  */
+    int group;          /* SYMTEN_U1 or SYMTEN_SU2                          */
     int rank;           /* 1 .. SYMTEN_MAX_RANK                             */
     const int* dirs;    /* [rank] SYMTEN_IN / SYMTEN_OUT                    */
     const int* nsec;    /* [rank] number of sectors per leg                 */
-    const int* labels;  /* [sum nsec] U(1) charge (units of 2 S^z)          */
+    const int* labels;  /* [sum nsec] U(1) charge (units of 2 S^z);
+                           SU(2) doubled spin 2j                            */
     const int* dims;    /* [sum nsec] reduced sector dimension (>= 0)       */
-    int flux;           /* total charge: sum dir*q of every block           */
+    int flux;           /* U(1): sum dir*q of every block; SU(2): 0         */
     int dtype;          /* SYMTEN_F64 or SYMTEN_F32                         */
 } symten_desc;
 
@@ -119,6 +139,22 @@ int symten_nnz(symten_t t, int64_t* n);
  * strides[rank] in elements of the device buffer.                           */
 int symten_block_info(symten_t t, int64_t i, int* labels, int* shape,
                       int64_t* offset, int64_t* strides);
+/* SU(2) coupling-tree labels of block i (in-chain intermediates, out-chain
+ * intermediates, total spin K; doubled).  `tree` must hold rank entries;
+ * *ntree = 0 for U(1) tensors.  Either pointer may be NULL.                */
+int symten_block_tree(symten_t t, int64_t i, int* ntree, int* tree);
+/* Clebsch-Gordan coefficient <j1 m1; j2 m2 | J M> (Condon-Shortley phase),
+ * every argument doubled, as used by the SU(2) planner (Racah's sum in
+ * extended precision).  Spins 0..64 (J 0..128); 0 outside the selection
+ * rules.                                                                   */
+int symten_su2_cg(int tj1, int tm1, int tj2, int tm2, int tJ, int tM, double* value);
+/* Expand an SU(2) tensor into the U(1) tensor of its S^z components: leg
+ * charges 2m, flux 0; inside a charge sector the states are ordered by spin
+ * ascending, then multiplet index; each element is the sum over the block's
+ * coupling trees of reduced value times basis-tensor entry (Sec. 2, Eq.
+ * tensor-cgc).  The new handle owns a new buffer of the input's dtype.
+ * Waits for `stream` before returning.                                      */
+int symten_su2_to_u1(symten_t* out, symten_t in, void* stream);
 /* device buffer and its size in elements (>= nnz when blocks are strided). */
 int symten_device_ptr(symten_t t, void** ptr, int64_t* elems);
 

@@ -5,8 +5,9 @@ include/symten.h); this package only loads it and marshals arguments.
 """
 from . import _lib
 from .symten import (Tensor, CtmEnv, contract, plan_info, double_layer, enlarged_corner, profile_begin, profile_end,
-                     enlarged_corners_batched, sync, IN, OUT)
+                     enlarged_corners_batched, sync, su2_cg, IN, OUT)
 from ._lib import SymtenError
 
 __all__ = ["Tensor", "CtmEnv", "contract", "plan_info", "double_layer", "enlarged_corner",
-           "enlarged_corners_batched", "sync", "IN", "OUT", "SymtenError"]
+           "enlarged_corners_batched", "sync", "su2_cg", "profile_begin", "profile_end", "IN", "OUT",
+           "SymtenError"]

@@ -80,6 +80,9 @@ SIGNATURES = {
     "symten_num_blocks": (C.c_int, [H, I64P]),
     "symten_nnz": (C.c_int, [H, I64P]),
     "symten_block_info": (C.c_int, [H, C.c_int64, IP, IP, I64P, I64P]),
+    "symten_block_tree": (C.c_int, [H, C.c_int64, IP, IP]),
+    "symten_su2_to_u1": (C.c_int, [C.POINTER(H), H, P]),
+    "symten_su2_cg": (C.c_int, [C.c_int] * 6 + [C.POINTER(C.c_double)]),
     "symten_device_ptr": (C.c_int, [H, C.POINTER(P), I64P]),
     "symten_upload": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64, P]),
     "symten_download": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64, P]),

@@ -420,8 +420,8 @@ namespace {
 
 TensorPtr make_desc_tensor(const symten_desc* d) {
     if (!d) fail(SYMTEN_E_INVAL, "null descriptor");
-    if (d->group == SYMTEN_SU2) fail(SYMTEN_E_UNSUPPORTED, "SU(2) tensors are not implemented");
-    if (d->group != SYMTEN_U1) fail(SYMTEN_E_INVAL, "unknown symmetry group");
+    if (d->group != SYMTEN_U1 && d->group != SYMTEN_SU2) fail(SYMTEN_E_INVAL, "unknown symmetry group");
+    if (d->group == SYMTEN_SU2 && d->flux != 0) fail(SYMTEN_E_SYM, "SU(2) tensors are invariant: flux must be 0");
     if (d->rank < 1 || d->rank > SYMTEN_MAX_RANK) fail(SYMTEN_E_INVAL, "rank must be 1..8");
     if (!d->dirs || !d->nsec || !d->labels || !d->dims) fail(SYMTEN_E_INVAL, "null array in descriptor");
     if (d->dtype != SYMTEN_F64 && d->dtype != SYMTEN_F32) fail(SYMTEN_E_INVAL, "dtype must be F64 or F32");
@@ -436,6 +436,8 @@ TensorPtr make_desc_tensor(const symten_desc* d) {
         std::vector<std::pair<int, int>> secs;
         for (int s = 0; s < d->nsec[l]; ++s, ++pos) {
             if (d->dims[pos] < 0) fail(SYMTEN_E_INVAL, "negative sector dimension");
+            if (d->group == SYMTEN_SU2 && (d->labels[pos] < 0 || d->labels[pos] > 64))
+                fail(SYMTEN_E_INVAL, "SU(2) labels are doubled spins 0..64");
             if (d->dims[pos] > 0) secs.push_back({d->labels[pos], d->dims[pos]});
         }
         std::sort(secs.begin(), secs.end());
@@ -446,7 +448,7 @@ TensorPtr make_desc_tensor(const symten_desc* d) {
         for (auto& s : secs) { L.q.push_back(s.first); L.d.push_back(s.second); }
         t->legs.push_back(L);
     }
-    t->elems = enumerate_blocks(*t);
+    t->elems = t->group == SYMTEN_SU2 ? enumerate_blocks_su2(*t) : enumerate_blocks(*t);
     return t;
 }
 
@@ -526,6 +528,30 @@ int symten_block_info(symten_t t, int64_t i, int* labels, int* shape, int64_t* o
             if (strides) strides[l] = b.stride[l];
         }
         if (offset) *offset = b.offset;
+    });
+}
+int symten_block_tree(symten_t t, int64_t i, int* ntree, int* tree) {
+    return guard([&] {
+        Tensor& x = T(t);
+        if (i < 0 || i >= (int64_t)x.blocks.size()) fail(SYMTEN_E_INVAL, "block index out of range");
+        const Block& b = x.blocks[i];
+        if (ntree) *ntree = (int)b.tree.size();
+        if (tree)
+            for (size_t k = 0; k < b.tree.size(); ++k) tree[k] = b.tree[k];
+    });
+}
+int symten_su2_to_u1(symten_t* out, symten_t in, void* stream) {
+    return guard([&] {
+        if (!out) fail(SYMTEN_E_INVAL, "null output");
+        *out = wrap(su2_to_u1(T(in), S(stream)));
+    });
+}
+int symten_su2_cg(int tj1, int tm1, int tj2, int tm2, int tJ, int tM, double* value) {
+    return guard([&] {
+        if (!value) fail(SYMTEN_E_INVAL, "null output");
+        if (tj1 < 0 || tj2 < 0 || tJ < 0 || tj1 > 64 || tj2 > 64 || tJ > 128)
+            fail(SYMTEN_E_INVAL, "doubled spins must be 0..64 (J: 0..128)");
+        *value = cg_coeff(tj1, tm1, tj2, tm2, tJ, tM);
     });
 }
 int symten_device_ptr(symten_t t, void** ptr, int64_t* elems) {
@@ -802,6 +828,7 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, co
         for (int i = 0; i < n; ++i) {
             for (symten_t h : {Cs[i], Tas[i], Tbs[i], as[i]}) {
                 check_device_tensor(T(h), "batched corners");
+                if (T(h).group != SYMTEN_U1) fail(SYMTEN_E_UNSUPPORTED, "batched corners: U(1) tensors only");
                 key += tensor_signature(T(h)) + "&";
                 inputs.push_back(T(h).data());
             }
@@ -915,6 +942,8 @@ int ctm_env_create(ctm_env_t* env, const symten_t C[4], const symten_t Tt[4]) {
                 e->T[i] = T(Tt[i]).buf ? Tt[i]->t : nullptr;
                 if (!e->C[i] || !e->T[i]) fail(SYMTEN_E_INVAL, "environment tensors need device storage");
                 if (e->C[i]->rank() != 2 || e->T[i]->rank() != 3) fail(SYMTEN_E_INVAL, "C must be rank 2 and T rank 3");
+                if (e->C[i]->group != SYMTEN_U1 || e->T[i]->group != SYMTEN_U1)
+                    fail(SYMTEN_E_UNSUPPORTED, "environment: U(1) tensors only");
             }
             rb_check(rocblas_create_handle(&e->rb), "rocblas_create_handle");
         } catch (...) {
@@ -982,6 +1011,7 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         Tensor& a = T(a_h);
         check_device_tensor(a, "ctm_move(a)");
         if (a.rank() != 4) fail(SYMTEN_E_INVAL, "a must have rank 4");
+        if (a.group != SYMTEN_U1) fail(SYMTEN_E_UNSUPPORTED, "ctm_move: U(1) tensors only");
         const hipStream_t s = S(stream);
         const bool f64 = prec == SYMTEN_PREC_F64;
         for (int i = 0; i < 4; ++i)

@@ -42,7 +42,8 @@ struct Leg {
 
 // ----------------------------------------------------------------- blocks ---
 struct Block {
-    std::vector<int> q;          // charge per leg
+    std::vector<int> q;          // charge per leg (SU(2): doubled spin 2j)
+    std::vector<int> tree;       // SU(2) coupling-tree labels (empty for U(1))
     std::vector<int> shape;      // dims per leg
     std::vector<int64_t> stride; // element strides per leg
     int64_t offset = 0;          // element offset into the tensor buffer
@@ -66,7 +67,7 @@ struct Tensor {
     int dtype = SYMTEN_F32;
     std::vector<Leg> legs;
     std::vector<Block> blocks;               // canonical (lexicographic) order
-    std::map<std::vector<int>, int> index;   // charges -> block index
+    std::map<std::vector<int>, int> index;   // labels (charges, then tree) -> block index
     BufferPtr buf;                           // null for metadata-only handles
     int64_t elems = 0;                       // buffer size in elements
     bool meta_only = true;
@@ -82,6 +83,10 @@ using TensorPtr = std::shared_ptr<Tensor>;
 // Allowed blocks of the given legs and flux, canonical order, contiguous
 // row-major layout; returns total element count.
 int64_t enumerate_blocks(Tensor& t);
+// SU(2): one block per (spin per leg, coupling tree), lexicographic.
+int64_t enumerate_blocks_su2(Tensor& t);
+// Clebsch-Gordan coefficient <j1 m1; j2 m2 | J M>, all arguments doubled.
+double cg_coeff(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
 
 // ------------------------------------------------------------- device ops ---
 // Strided copy task: iterate a multi-index over dims (last fastest);
@@ -96,8 +101,7 @@ struct CopyTask {
     int rank;
     int src_buf, dst_buf;
     int count;          // product of dims (< 2^31)
-    float scale;        // multiplies the copied value
-    int pad_;
+    double scale;       // multiplies the copied value (SU(2) recoupling scalar)
     int64_t lo_off;     // split panels: the lo plane starts lo_off elements after the hi plane
 };
 
@@ -128,17 +132,11 @@ inline size_t panel_esize(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 
 inline int panel_planes(Prec p) { return p == Prec::BF16X3 ? 2 : 1; }
 inline int panel_vw(Prec p) { return p == Prec::F64 ? 2 : (p == Prec::F32 ? 4 : 8); }   // 16-byte vectors
 
-struct LaunchCtx;   // owns staging memory for descriptors
-
-// Launch the strided copies (all tasks) on `stream`.  `bufs` are device
-// pointers; elements are double when is_f64, else float.  Source and
-// destination may have different types (src_f64 / dst_f64).
-void launch_copies(const std::vector<CopyTask>& tasks, const std::vector<void*>& bufs,
-                   bool src_f64, bool dst_f64, hipStream_t stream);
-
-// Grouped GEMM C_g = A_g * B_g^T over all groups, one launch per tile shape.
-void launch_grouped_gemm(const std::vector<GemmGroup>& groups, const std::vector<void*>& bufs,
-                         Prec prec, hipStream_t stream);
+// Gather launch over a task list already on the device (at most 16 buffers).
+// dst_kind: 0 float, 1 double, 2 bf16, 3 bf16 hi/lo split, 4 accumulate
+// (dst += scale * src, source type).
+void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+                     const std::vector<void*>& ptrs, bool src_f64, int dst_kind, hipStream_t s);
 
 void launch_cast(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n, hipStream_t s);
 void launch_fill_zero(void* dst, int64_t bytes, hipStream_t s);
@@ -185,6 +183,21 @@ struct ContractPlan {
     bool panel_f64 = false;
     mutable std::shared_ptr<void> dev;    // device copies of the descriptors
 };
+
+// Strided copy task over dims (last fastest); simplified (unit dims dropped,
+// contiguous dims merged).  src_buf < 0 writes zeros.
+CopyTask make_copy_task(int src_buf, int64_t src_off, int dst_buf, int64_t dst_off, const std::vector<int>& dims,
+                        const std::vector<int64_t>& sstr, const std::vector<int64_t>& dstr, double scale = 1.0);
+
+// Expansion of an SU(2) tensor into the U(1) tensor of its S^z components
+// (charges 2m; within a charge, states by spin then multiplet index).
+TensorPtr su2_to_u1(const Tensor& in, hipStream_t stream);
+
+// SU(2) part of plan_contraction, called after the leg checks.
+std::shared_ptr<ContractPlan> plan_contraction_su2(const Tensor& A, const Tensor& B, const std::vector<int>& conA,
+                                                   const std::vector<int>& conB, const std::vector<int>& freeA,
+                                                   const std::vector<int>& freeB, const std::vector<int>& perm,
+                                                   Prec p);
 
 // Build the plan (host only).  Throws Error on invalid input.
 std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B, int ncon,

@@ -52,9 +52,10 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
     return __uint_as_float(((uint32_t)h) << 16);
 }
 
-// Destination kinds of the gather: float, double, one bf16 plane, or the
-// split x = hi + lo with hi = bf16(x), lo = bf16(x - hi) in two planes.
-enum : int { kDstF32 = 0, kDstF64 = 1, kDstBF16 = 2, kDstSplit = 3 };
+// Destination kinds of the gather: float, double, one bf16 plane, the
+// split x = hi + lo with hi = bf16(x), lo = bf16(x - hi) in two planes, or
+// accumulation (dst += scale * src) in the source type.
+enum : int { kDstF32 = 0, kDstF64 = 1, kDstBF16 = 2, kDstSplit = 3, kDstAcc = 4 };
 
 template <class Ptrs, typename TS, int DK>
 __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __restrict__ tasks,
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __re
     const TS* __restrict__ src = T.src_buf >= 0 ? (const TS*)ptrs.get(T.src_buf) : nullptr;
     void* dstv = ptrs.get(T.dst_buf);
     const int rank = T.rank;
-    const float scale = T.scale;
+    const double scale = T.scale;
     for (int e = threadIdx.x; e < kCopyChunk; e += kCopyThreads) {
         const int64_t idx = base + e;
         if (idx >= T.count) break;
@@ -85,12 +86,14 @@ __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __re
             so += (int64_t)ik * T.sstride[k];
             dofs += (int64_t)ik * T.dstride[k];
         }
-        if constexpr (DK == kDstF64) {
-            ((double*)dstv)[dofs] = src ? (double)src[so] * (double)scale : 0.0;
+        if constexpr (DK == kDstAcc) {
+            if (src) ((TS*)dstv)[dofs] += src[so] * (TS)scale;
+        } else if constexpr (DK == kDstF64) {
+            ((double*)dstv)[dofs] = src ? (double)src[so] * scale : 0.0;
         } else if constexpr (DK == kDstF32) {
-            ((float*)dstv)[dofs] = src ? (float)src[so] * scale : 0.f;
+            ((float*)dstv)[dofs] = src ? (float)src[so] * (float)scale : 0.f;
         } else {
-            const float v = src ? (float)src[so] * scale : 0.f;
+            const float v = src ? (float)src[so] * (float)scale : 0.f;
             const unsigned short h = f32_to_bf16_rn(v);
             ((unsigned short*)dstv)[dofs] = h;
             if constexpr (DK == kDstSplit) ((unsigned short*)dstv)[dofs + T.lo_off] = f32_to_bf16_rn(v - bf16_to_f32(h));
@@ -723,6 +726,7 @@ static void copy_dispatch(const CopyTask* d_tasks, const int64_t* d_prefix, int 
         switch (dst_kind) {
             case kDstF64: SYMTEN_COPY(double, kDstF64); break;
             case kDstF32: SYMTEN_COPY(double, kDstF32); break;
+            case kDstAcc: SYMTEN_COPY(double, kDstAcc); break;
             default: fail(SYMTEN_E_INVAL, "copy: bf16 panels need FP32 sources");
         }
     } else {
@@ -730,6 +734,7 @@ static void copy_dispatch(const CopyTask* d_tasks, const int64_t* d_prefix, int 
             case kDstF64: SYMTEN_COPY(float, kDstF64); break;
             case kDstF32: SYMTEN_COPY(float, kDstF32); break;
             case kDstBF16: SYMTEN_COPY(float, kDstBF16); break;
+            case kDstAcc: SYMTEN_COPY(float, kDstAcc); break;
             default: SYMTEN_COPY(float, kDstSplit); break;
         }
     }

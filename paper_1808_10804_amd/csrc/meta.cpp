@@ -17,9 +17,6 @@
 
 namespace symten {
 
-// launchers defined in kernels.hip
-void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
-                     const std::vector<void*>& ptrs, bool src_f64, int dst_kind, hipStream_t s);
 
 // gather destination kind for the panels of a precision (see copy_kernel)
 int panel_dst_kind(Prec p) {
@@ -125,7 +122,14 @@ DeviceBuffer::~DeviceBuffer() {
 // ------------------------------------------------------------------ tensors
 void Tensor::rebuild_index() {
     index.clear();
-    for (size_t i = 0; i < blocks.size(); ++i) index[blocks[i].q] = (int)i;
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        std::vector<int> key = blocks[i].q;
+        if (!blocks[i].tree.empty()) {
+            key.push_back(-1);   // spins are >= 0: the marker cannot collide
+            key.insert(key.end(), blocks[i].tree.begin(), blocks[i].tree.end());
+        }
+        index[key] = (int)i;
+    }
 }
 
 int64_t enumerate_blocks(Tensor& t) {
@@ -176,6 +180,7 @@ std::string tensor_signature(const Tensor& t) {
     os << "|";
     for (auto& b : t.blocks) {
         for (int x : b.q) os << x << ",";
+        for (int x : b.tree) os << "t" << x;
         os << "@" << b.offset << "/";
         for (auto s : b.stride) os << s << ",";
         os << ";";
@@ -223,8 +228,8 @@ static void simplify_task(CopyTask& t) {
     }
 }
 
-static CopyTask make_task(int src_buf, int64_t src_off, int dst_buf, int64_t dst_off, const std::vector<int>& dims,
-                          const std::vector<int64_t>& sstr, const std::vector<int64_t>& dstr, float scale = 1.f) {
+CopyTask make_copy_task(int src_buf, int64_t src_off, int dst_buf, int64_t dst_off, const std::vector<int>& dims,
+                        const std::vector<int64_t>& sstr, const std::vector<int64_t>& dstr, double scale) {
     CopyTask t{};
     if ((int)dims.size() > kMaxCopyRank) fail(SYMTEN_E_CAPACITY, "copy task rank exceeds 8");
     t.src_buf = src_buf;
@@ -269,7 +274,7 @@ struct GroupBuild {
 
 std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B, int ncon, const int* legsA,
                                                const int* legsB, const int* out_perm, int prec) {
-    if (A.group != SYMTEN_U1 || B.group != SYMTEN_U1) fail(SYMTEN_E_UNSUPPORTED, "contract: only U(1) tensors");
+    if (A.group != B.group) fail(SYMTEN_E_SYM, "contract: operands have different symmetry groups");
     const int RA = A.rank(), RB = B.rank();
     if (ncon < 0 || ncon > RA || ncon > RB) fail(SYMTEN_E_INVAL, "contract: bad ncon");
     if (ncon > 0 && (!legsA || !legsB)) fail(SYMTEN_E_INVAL, "contract: null leg list");
@@ -313,6 +318,8 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
             if (perm[j] < 0 || perm[j] >= RO || seen[perm[j]]++) fail(SYMTEN_E_INVAL, "contract: bad out_perm");
         }
     }
+
+    if (A.group == SYMTEN_SU2) return plan_contraction_su2(A, B, conA, conB, freeA, freeB, perm, p);
 
     auto plan = std::make_shared<ContractPlan>();
     plan->prec = p;
@@ -447,15 +454,15 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
                 std::vector<int64_t> ds = suffix(adims, lda);
                 std::vector<int64_t> dk = suffix(kd, 1);
                 ds.insert(ds.end(), dk.begin(), dk.end());
-                plan->copies.push_back(make_task(0, b.offset, 2, gp.a_off + gp.row_off[r] * lda + koff[ki], dims, ss, ds));
+                plan->copies.push_back(make_copy_task(0, b.offset, 2, gp.a_off + gp.row_off[r] * lda + koff[ki], dims, ss, ds));
             }
             for (size_t ki = 0; ki < kap.size(); ++ki)
                 if (!present[ki])
-                    plan->copies.push_back(make_task(-1, 0, 2, gp.a_off + gp.row_off[r] * lda + koff[ki],
+                    plan->copies.push_back(make_copy_task(-1, 0, 2, gp.a_off + gp.row_off[r] * lda + koff[ki],
                                                      {(int)ra, (int)kdim[ki]}, {0, 0}, {lda, 1}));
         }
         if (lda > K)
-            plan->copies.push_back(make_task(-1, 0, 2, gp.a_off + K, {(int)M, (int)(lda - K)}, {0, 0}, {lda, 1}));
+            plan->copies.push_back(make_copy_task(-1, 0, 2, gp.a_off + K, {(int)M, (int)(lda - K)}, {0, 0}, {lda, 1}));
         // B panel tasks: B_g stored [N][lda] (K contiguous)
         for (size_t c = 0; c < gp.cols.size(); ++c) {
             std::vector<char> present(kap.size(), 0);
@@ -473,15 +480,15 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
                 std::vector<int64_t> ds = suffix(bdims, lda);
                 std::vector<int64_t> dk = suffix(kd, 1);
                 ds.insert(ds.end(), dk.begin(), dk.end());
-                plan->copies.push_back(make_task(1, b.offset, 3, gp.b_off + gp.col_off[c] * lda + koff[ki], dims, ss, ds));
+                plan->copies.push_back(make_copy_task(1, b.offset, 3, gp.b_off + gp.col_off[c] * lda + koff[ki], dims, ss, ds));
             }
             for (size_t ki = 0; ki < kap.size(); ++ki)
                 if (!present[ki])
-                    plan->copies.push_back(make_task(-1, 0, 3, gp.b_off + gp.col_off[c] * lda + koff[ki],
+                    plan->copies.push_back(make_copy_task(-1, 0, 3, gp.b_off + gp.col_off[c] * lda + koff[ki],
                                                      {(int)nb, (int)kdim[ki]}, {0, 0}, {lda, 1}));
         }
         if (lda > K)
-            plan->copies.push_back(make_task(-1, 0, 3, gp.b_off + K, {(int)N, (int)(lda - K)}, {0, 0}, {lda, 1}));
+            plan->copies.push_back(make_copy_task(-1, 0, 3, gp.b_off + K, {(int)N, (int)(lda - K)}, {0, 0}, {lda, 1}));
 
         // output blocks reached by at least one pair; pair statistics
         std::vector<std::vector<char>> arow(gp.rows.size(), std::vector<char>(kap.size(), 0));
@@ -1105,7 +1112,7 @@ TensorPtr double_layer(const Tensor& A, hipStream_t stream) {
         int64_t doff = 0;
         for (int l = 0; l < 5; ++l) doff += soff[l][A.legs[l].index_of(b.q[l])] * dstr[l];
         std::vector<int64_t> ss(b.stride.begin(), b.stride.end());
-        tasks.push_back(make_task(0, b.offset, 1, doff, b.shape, ss, dstr));
+        tasks.push_back(make_copy_task(0, b.offset, 1, doff, b.shape, ss, dstr));
     }
     BufferPtr dense = device_alloc(dense_n * out->esize());
     launch_fill_zero(dense->ptr, dense_n * out->esize(), stream);

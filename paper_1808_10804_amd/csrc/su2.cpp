@@ -1,0 +1,571 @@
+// SU(2) reduced tensors: canonical coupling-tree blocks and the contraction
+// plan with recoupling scalars.
+//
+// A block carries one spin per leg and one coupling tree (Sec. 2, Eq.
+// tensor-cgc: t_i = m_i (x) c_i).  Incoming legs are coupled left to right
+// by Clebsch-Gordan coefficients to a total spin K, outgoing legs likewise
+// to the same K; the tree labels are (in-chain intermediates, out-chain
+// intermediates, K) and the block's generalised CGC tensor is
+// c[m_1..m_R] = sum_M C_in(m_in; K M) C_out(m_out; K M).
+//
+// A contraction multiplies reduced blocks and CGC tensors separately (Sec. 2,
+// contraction rule r_k = (m_t . m_s) (x) (c_t . c_s)); the product c_t . c_s
+// is expanded in the canonical basis of the output legs, and every non-zero
+// coefficient X becomes one scaled term of the output block's sector GEMM.
+// The scalars are computed once per plan on the host in FP64.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace symten {
+
+// ------------------------------------------------------ Clebsch-Gordan
+// <j1 m1; j2 m2 | J M>, arguments doubled, Condon-Shortley phase, from
+// Racah's closed form (sum over k), in long double.
+static long double lfact(int n) {
+    static std::vector<long double> f = [] {
+        std::vector<long double> v(200, 1.0L);
+        for (int i = 1; i < 200; ++i) v[i] = v[i - 1] * i;
+        return v;
+    }();
+    return f[n];
+}
+
+double cg_coeff(int tj1, int tm1, int tj2, int tm2, int tJ, int tM) {
+    if (tm1 + tm2 != tM) return 0.0;
+    if (tJ < std::abs(tj1 - tj2) || tJ > tj1 + tj2 || (tj1 + tj2 + tJ) % 2) return 0.0;
+    if (std::abs(tm1) > tj1 || std::abs(tm2) > tj2 || std::abs(tM) > tJ) return 0.0;
+    if ((tj1 + tm1) % 2 || (tj2 + tm2) % 2 || (tJ + tM) % 2) return 0.0;
+    const int a = (tj1 + tj2 - tJ) / 2, b = (tj1 - tj2 + tJ) / 2, c = (-tj1 + tj2 + tJ) / 2;
+    const int d = (tj1 + tj2 + tJ) / 2 + 1;
+    const long double pre = std::sqrt((tJ + 1) * lfact(a) * lfact(b) * lfact(c) / lfact(d)) *
+                            std::sqrt(lfact((tj1 + tm1) / 2) * lfact((tj1 - tm1) / 2) * lfact((tj2 + tm2) / 2) *
+                                      lfact((tj2 - tm2) / 2) * lfact((tJ + tM) / 2) * lfact((tJ - tM) / 2));
+    long double s = 0.0L;
+    for (int k = 0; k <= d; ++k) {
+        const int e1 = a - k, e2 = (tj1 - tm1) / 2 - k, e3 = (tj2 + tm2) / 2 - k;
+        const int e4 = (tJ - tj2 + tm1) / 2 + k, e5 = (tJ - tj1 - tm2) / 2 + k;
+        if (e1 < 0 || e2 < 0 || e3 < 0 || e4 < 0 || e5 < 0) continue;
+        const long double den = lfact(k) * lfact(e1) * lfact(e2) * lfact(e3) * lfact(e4) * lfact(e5);
+        s += ((k % 2) ? -1.0L : 1.0L) / den;
+    }
+    return (double)(pre * s);
+}
+
+// ------------------------------------------------------------ trees
+static std::vector<std::vector<int>> chains(const std::vector<int>& tjs) {
+    if (tjs.empty()) return {{0}};
+    std::vector<std::vector<int>> out{{tjs[0]}};
+    for (size_t i = 1; i < tjs.size(); ++i) {
+        std::vector<std::vector<int>> nxt;
+        for (auto& c : out) {
+            const int k = c.back();
+            for (int K = std::abs(k - tjs[i]); K <= k + tjs[i]; K += 2) {
+                auto d = c;
+                d.push_back(K);
+                nxt.push_back(d);
+            }
+        }
+        out.swap(nxt);
+    }
+    return out;
+}
+
+static void split_dirs(const std::vector<Leg>& legs, std::vector<int>& ins, std::vector<int>& outs) {
+    ins.clear();
+    outs.clear();
+    for (size_t i = 0; i < legs.size(); ++i) (legs[i].dir > 0 ? ins : outs).push_back((int)i);
+}
+
+// all (tj tuple, tree) of the legs, canonical (lexicographic) order
+static std::vector<std::pair<std::vector<int>, std::vector<int>>> su2_labels(const std::vector<Leg>& legs) {
+    std::vector<int> ins, outs;
+    split_dirs(legs, ins, outs);
+    std::vector<std::pair<std::vector<int>, std::vector<int>>> res;
+    const int R = (int)legs.size();
+    std::vector<int> idx(R, 0);
+    for (auto& l : legs)
+        if (l.q.empty()) return res;
+    while (true) {
+        std::vector<int> tj(R);
+        for (int l = 0; l < R; ++l) tj[l] = legs[l].q[idx[l]];
+        std::vector<int> ti, to;
+        for (int i : ins) ti.push_back(tj[i]);
+        for (int o : outs) to.push_back(tj[o]);
+        for (auto& a : chains(ti))
+            for (auto& b : chains(to)) {
+                if (a.back() != b.back()) continue;
+                std::vector<int> tree;
+                for (size_t k = 1; k + 1 < a.size(); ++k) tree.push_back(a[k]);
+                for (size_t k = 1; k + 1 < b.size(); ++k) tree.push_back(b[k]);
+                tree.push_back(a.back());
+                res.push_back({tj, tree});
+            }
+        int l = R - 1;
+        while (l >= 0 && ++idx[l] == (int)legs[l].q.size()) { idx[l] = 0; --l; }
+        if (l < 0) break;
+    }
+    std::sort(res.begin(), res.end());
+    return res;
+}
+
+int64_t enumerate_blocks_su2(Tensor& t) {
+    t.blocks.clear();
+    int64_t off = 0;
+    for (auto& lt : su2_labels(t.legs)) {
+        Block b;
+        b.q = lt.first;
+        b.tree = lt.second;
+        const int R = t.rank();
+        b.shape.resize(R);
+        b.stride.resize(R);
+        int64_t sz = 1;
+        for (int l = 0; l < R; ++l) {
+            b.shape[l] = t.legs[l].dim_of(b.q[l]);
+            sz *= b.shape[l];
+        }
+        int64_t st = 1;
+        for (int l = R - 1; l >= 0; --l) { b.stride[l] = st; st *= b.shape[l]; }
+        b.offset = off;
+        b.size = sz;
+        off += sz;
+        t.blocks.push_back(std::move(b));
+    }
+    t.rebuild_index();
+    return off;
+}
+
+// ------------------------------------------------------- CGC tensors
+namespace {
+struct DenseT {
+    std::vector<int> shape;   // (tj + 1) per leg
+    std::vector<double> v;    // row-major
+};
+
+// C(m_1..m_r; K M) of one chain as [m_1..m_r][M]
+std::vector<double> chain_tensor(const std::vector<int>& tjs, const std::vector<int>& chain, int K) {
+    if (tjs.empty()) return {1.0};
+    int64_t n = 1;
+    for (int t : tjs) n *= t + 1;
+    std::vector<double> C(n * (K + 1), 0.0);
+    std::vector<int> mm(tjs.size());
+    for (int64_t lin = 0; lin < n; ++lin) {
+        int64_t r = lin;
+        for (int i = (int)tjs.size() - 1; i >= 0; --i) {
+            mm[i] = -tjs[i] + 2 * (int)(r % (tjs[i] + 1));
+            r /= tjs[i] + 1;
+        }
+        double val = 1.0;
+        int mu = mm[0];
+        for (size_t s = 1; s < tjs.size() && val != 0.0; ++s) {
+            const int nmu = mu + mm[s];
+            val *= cg_coeff(chain[s - 1], mu, tjs[s], mm[s], chain[s], nmu);
+            mu = nmu;
+        }
+        if (val != 0.0 && std::abs(mu) <= K) C[lin * (K + 1) + (mu + K) / 2] = val;
+    }
+    return C;
+}
+
+DenseT cgc_tensor(const std::vector<Leg>& legs, const std::vector<int>& tj, const std::vector<int>& tree) {
+    std::vector<int> ins, outs;
+    split_dirs(legs, ins, outs);
+    const int K = tree.back();
+    const size_t nim = ins.size() >= 2 ? ins.size() - 2 : 0;
+    const size_t nom = outs.size() >= 2 ? outs.size() - 2 : 0;
+    auto make_chain = [&](const std::vector<int>& tjs, size_t from, size_t cnt) {
+        if (tjs.empty()) return std::vector<int>{0};
+        if (tjs.size() == 1) return std::vector<int>{tjs[0]};
+        std::vector<int> c{tjs[0]};
+        for (size_t k = 0; k < cnt; ++k) c.push_back(tree[from + k]);
+        c.push_back(K);
+        return c;
+    };
+    std::vector<int> ti, to;
+    for (int i : ins) ti.push_back(tj[i]);
+    for (int o : outs) to.push_back(tj[o]);
+    const std::vector<double> Ci = chain_tensor(ti, make_chain(ti, 0, nim), K);
+    const std::vector<double> Co = chain_tensor(to, make_chain(to, nim, nom), K);
+    const int64_t ni = (int64_t)Ci.size() / (K + 1), no = (int64_t)Co.size() / (K + 1);
+    DenseT c;
+    const int R = (int)legs.size();
+    c.shape.resize(R);
+    for (int l = 0; l < R; ++l) c.shape[l] = tj[l] + 1;
+    c.v.assign(ni * no, 0.0);
+    // strides of the (ins..., outs...) order inside the leg-order tensor
+    std::vector<int64_t> st(R);
+    int64_t s = 1;
+    for (int l = R - 1; l >= 0; --l) { st[l] = s; s *= c.shape[l]; }
+    std::vector<int> order = ins;
+    order.insert(order.end(), outs.begin(), outs.end());
+    for (int64_t a = 0; a < ni; ++a)
+        for (int64_t b = 0; b < no; ++b) {
+            double v = 0.0;
+            for (int M = 0; M <= K; ++M) v += Ci[a * (K + 1) + M] * Co[b * (K + 1) + M];
+            if (v == 0.0) continue;
+            // decode (a over ins, b over outs) into the leg-order index
+            int64_t lin = 0, ra = a, rb = b;
+            for (int k = (int)ins.size() - 1; k >= 0; --k) {
+                lin += (ra % c.shape[ins[k]]) * st[ins[k]];
+                ra /= c.shape[ins[k]];
+            }
+            for (int k = (int)outs.size() - 1; k >= 0; --k) {
+                lin += (rb % c.shape[outs[k]]) * st[outs[k]];
+                rb /= c.shape[outs[k]];
+            }
+            c.v[lin] = v;
+        }
+    return c;
+}
+
+std::mutex g_cgc_mu;
+std::map<std::vector<int>, DenseT> g_cgc;   // key: dirs, tj, tree
+
+const DenseT& cgc_cached(const std::vector<Leg>& legs, const std::vector<int>& tj, const std::vector<int>& tree) {
+    std::vector<int> key;
+    for (auto& l : legs) key.push_back(l.dir);
+    key.push_back(1000);
+    key.insert(key.end(), tj.begin(), tj.end());
+    key.push_back(1000);
+    key.insert(key.end(), tree.begin(), tree.end());
+    std::lock_guard<std::mutex> lk(g_cgc_mu);
+    auto it = g_cgc.find(key);
+    if (it != g_cgc.end()) return it->second;
+    return g_cgc.emplace(key, cgc_tensor(legs, tj, tree)).first->second;
+}
+
+// P[free_a..., free_b...] = sum over contracted m of cA * cB
+DenseT contract_cgc(const DenseT& ca, const DenseT& cb, const std::vector<int>& conA, const std::vector<int>& conB,
+                    const std::vector<int>& freeA, const std::vector<int>& freeB) {
+    DenseT p;
+    for (int l : freeA) p.shape.push_back(ca.shape[l]);
+    for (int l : freeB) p.shape.push_back(cb.shape[l]);
+    int64_t nfa = 1, nfb = 1, nk = 1;
+    for (int l : freeA) nfa *= ca.shape[l];
+    for (int l : freeB) nfb *= cb.shape[l];
+    for (int l : conA) nk *= ca.shape[l];
+    auto strides = [](const std::vector<int>& shape) {
+        std::vector<int64_t> st(shape.size());
+        int64_t s = 1;
+        for (int l = (int)shape.size() - 1; l >= 0; --l) { st[l] = s; s *= shape[l]; }
+        return st;
+    };
+    const std::vector<int64_t> sa = strides(ca.shape), sb = strides(cb.shape);
+    auto offsets = [](const std::vector<int>& legs, const std::vector<int>& shape, const std::vector<int64_t>& st) {
+        int64_t n = 1;
+        for (int l : legs) n *= shape[l];
+        std::vector<int64_t> off(n, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t r = i, o = 0;
+            for (int k = (int)legs.size() - 1; k >= 0; --k) {
+                o += (r % shape[legs[k]]) * st[legs[k]];
+                r /= shape[legs[k]];
+            }
+            off[i] = o;
+        }
+        return off;
+    };
+    const auto ofa = offsets(freeA, ca.shape, sa), oka = offsets(conA, ca.shape, sa);
+    const auto ofb = offsets(freeB, cb.shape, sb), okb = offsets(conB, cb.shape, sb);
+    p.v.assign(nfa * nfb, 0.0);
+    for (int64_t i = 0; i < nfa; ++i)
+        for (int64_t k = 0; k < nk; ++k) {
+            const double x = ca.v[ofa[i] + oka[k]];
+            if (x == 0.0) continue;
+            for (int64_t j = 0; j < nfb; ++j) p.v[i * nfb + j] += x * cb.v[ofb[j] + okb[k]];
+        }
+    return p;
+}
+}  // namespace
+
+// -------------------------------------------------------------- planning
+namespace {
+std::vector<int64_t> suffix_strides(const std::vector<int>& d, int64_t mult) {
+    std::vector<int64_t> s(d.size());
+    int64_t st = mult;
+    for (int k = (int)d.size() - 1; k >= 0; --k) { s[k] = st; st *= d[k]; }
+    return s;
+}
+
+// <c_o, P> / <c_o, c_o> where P is laid out in the unpermuted output order
+// and c_o in the permuted one (out leg j is unpermuted leg perm[j]).
+double project(const DenseT& co, const DenseT& pr, const std::vector<int>& perm) {
+    const int RO = (int)perm.size();
+    std::vector<int64_t> st_un(RO);
+    int64_t s = 1;
+    for (int l = RO - 1; l >= 0; --l) { st_un[l] = s; s *= pr.shape[l]; }
+    double num = 0.0, den = 0.0;
+    std::vector<int> idx(RO, 0);
+    const int64_t n = (int64_t)co.v.size();
+    for (int64_t lin = 0; lin < n; ++lin) {
+        const double cv = co.v[lin];
+        if (cv != 0.0) {
+            int64_t o = 0;
+            for (int j = 0; j < RO; ++j) o += idx[j] * st_un[perm[j]];
+            num += cv * pr.v[o];
+            den += cv * cv;
+        }
+        for (int j = RO - 1; j >= 0; --j) {
+            if (++idx[j] < co.shape[j]) break;
+            idx[j] = 0;
+        }
+    }
+    return den > 0.0 ? num / den : 0.0;
+}
+}  // namespace
+
+// Reduced contraction (Sec. 2, Eq. contraction rule with CGCs): every matched
+// pair (A block, B block) contributes (m_A . m_B) x (c_A . c_B); the CGC
+// product is expanded in the canonical basis of the output legs,
+// c_A . c_B = sum_b X_b c_b, and each X_b != 0 adds X_b m_A . m_B to output
+// block b.  All terms of one output block form one GEMM: the K ranges of the
+// terms are concatenated, the A panel of a term carries X_b.  Scalars whose
+// magnitude is below 1e-13 are structural zeros and are dropped.
+std::shared_ptr<ContractPlan> plan_contraction_su2(const Tensor& A, const Tensor& B, const std::vector<int>& conA,
+                                                   const std::vector<int>& conB, const std::vector<int>& freeA,
+                                                   const std::vector<int>& freeB, const std::vector<int>& perm,
+                                                   Prec p) {
+    const int RO = (int)perm.size();
+    auto plan = std::make_shared<ContractPlan>();
+    plan->prec = p;
+    plan->panel_f64 = p == Prec::F64;
+    const int VW = panel_vw(p);
+
+    auto out = std::make_shared<Tensor>();
+    out->group = SYMTEN_SU2;
+    out->flux = 0;
+    out->dtype = A.dtype;
+    std::vector<Leg> olegs;   // unpermuted order: A free legs, then B free legs
+    for (int l : freeA) olegs.push_back(A.legs[l]);
+    for (int l : freeB) olegs.push_back(B.legs[l]);
+    out->legs.resize(RO);
+    for (int j = 0; j < RO; ++j) out->legs[j] = olegs[perm[j]];
+    const auto olabels = su2_labels(out->legs);
+    std::map<std::vector<int>, std::vector<int>> trees_of;   // output spins -> canonical block ids
+    for (size_t i = 0; i < olabels.size(); ++i) trees_of[olabels[i].first].push_back((int)i);
+
+    // B blocks by contracted spins
+    std::map<std::vector<int>, std::vector<int>> b_by_con;
+    for (size_t ib = 0; ib < B.blocks.size(); ++ib) {
+        std::vector<int> k;
+        for (int c : conB) k.push_back(B.blocks[ib].q[c]);
+        b_by_con[k].push_back((int)ib);
+    }
+
+    struct Term { int a, b; double x; };
+    std::map<int, std::vector<Term>> terms;   // canonical output block -> terms
+    for (size_t ia = 0; ia < A.blocks.size(); ++ia) {
+        const Block& ba = A.blocks[ia];
+        std::vector<int> k;
+        for (int c : conA) k.push_back(ba.q[c]);
+        auto hit = b_by_con.find(k);
+        if (hit == b_by_con.end()) continue;
+        const DenseT& ca = cgc_cached(A.legs, ba.q, ba.tree);
+        for (int ib : hit->second) {
+            const Block& bb = B.blocks[ib];
+            std::vector<int> tj_un;
+            for (int l : freeA) tj_un.push_back(ba.q[l]);
+            for (int l : freeB) tj_un.push_back(bb.q[l]);
+            std::vector<int> tj(RO);
+            for (int j = 0; j < RO; ++j) tj[j] = tj_un[perm[j]];
+            auto ot = trees_of.find(tj);
+            if (ot == trees_of.end()) continue;
+            const DenseT& cb = cgc_cached(B.legs, bb.q, bb.tree);
+            const DenseT pr = contract_cgc(ca, cb, conA, conB, freeA, freeB);
+            for (int ob : ot->second) {
+                const double x = project(cgc_cached(out->legs, tj, olabels[ob].second), pr, perm);
+                if (std::fabs(x) > 1e-13) terms[ob].push_back({(int)ia, ib, x});
+            }
+        }
+    }
+
+    symten_plan_stats info{};
+    int64_t a_pos = 0, b_pos = 0, c_pos = 0;
+    auto align32 = [](int64_t x) { return (x + 31) / 32 * 32; };
+    for (auto& kv : terms) {
+        const auto& lab = olabels[kv.first];
+        const std::vector<Term>& tl = kv.second;
+        const Block& ba0 = A.blocks[tl[0].a];
+        const Block& bb0 = B.blocks[tl[0].b];
+        std::vector<int> adims, bdims;
+        for (int l : freeA) adims.push_back(ba0.shape[l]);
+        for (int l : freeB) bdims.push_back(bb0.shape[l]);
+        int64_t M = 1, N = 1, K = 0;
+        for (int d : adims) M *= d;
+        for (int d : bdims) N *= d;
+        std::vector<int64_t> koff, kdim;
+        for (auto& t : tl) {
+            int64_t k = 1;
+            for (int c : conA) k *= A.blocks[t.a].shape[c];
+            koff.push_back(K);
+            kdim.push_back(k);
+            K += k;
+        }
+        if (M == 0 || N == 0 || K == 0) continue;
+        if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 30)) fail(SYMTEN_E_CAPACITY, "contract: sector too large");
+        const int64_t lda = (K + VW - 1) / VW * VW;
+        GroupPlan gp;
+        gp.key = kv.first;
+        gp.M = (int)M;
+        gp.N = (int)N;
+        gp.K = (int)K;
+        gp.lda = (int)lda;
+        gp.a_off = a_pos;
+        gp.b_off = b_pos;
+        gp.c_off = c_pos;
+        a_pos = align32(a_pos + M * lda);
+        b_pos = align32(b_pos + N * lda);
+        c_pos += M * N;
+        info.groups += 1;
+        info.gemm_flops += 2 * M * N * K;
+        info.max_m = std::max<int64_t>(info.max_m, M);
+        info.max_n = std::max<int64_t>(info.max_n, N);
+        info.max_k = std::max<int64_t>(info.max_k, K);
+        for (size_t ti = 0; ti < tl.size(); ++ti) {
+            const Block& ba = A.blocks[tl[ti].a];
+            const Block& bb = B.blocks[tl[ti].b];
+            std::vector<int> dims, kd;
+            std::vector<int64_t> ss;
+            for (int l : freeA) { dims.push_back(ba.shape[l]); ss.push_back(ba.stride[l]); }
+            for (int l : conA) { dims.push_back(ba.shape[l]); ss.push_back(ba.stride[l]); kd.push_back(ba.shape[l]); }
+            std::vector<int64_t> ds = suffix_strides(adims, lda), dk = suffix_strides(kd, 1);
+            ds.insert(ds.end(), dk.begin(), dk.end());
+            plan->copies.push_back(make_copy_task(0, ba.offset, 2, gp.a_off + koff[ti], dims, ss, ds, tl[ti].x));
+            dims.clear();
+            ss.clear();
+            for (int l : freeB) { dims.push_back(bb.shape[l]); ss.push_back(bb.stride[l]); }
+            for (int l : conB) { dims.push_back(bb.shape[l]); ss.push_back(bb.stride[l]); }
+            ds = suffix_strides(bdims, lda);
+            ds.insert(ds.end(), dk.begin(), dk.end());
+            plan->copies.push_back(make_copy_task(1, bb.offset, 3, gp.b_off + koff[ti], dims, ss, ds, 1.0));
+            info.pairs += 1;
+            info.useful_flops += 2 * M * N * kdim[ti];
+        }
+        if (lda > K) {
+            plan->copies.push_back(make_copy_task(-1, 0, 2, gp.a_off + K, {(int)M, (int)(lda - K)}, {0, 0}, {lda, 1}));
+            plan->copies.push_back(make_copy_task(-1, 0, 3, gp.b_off + K, {(int)N, (int)(lda - K)}, {0, 0}, {lda, 1}));
+        }
+        // output block: row-major [A free..., B free...] = M x N, seen through the permutation
+        Block ob;
+        ob.q = lab.first;
+        ob.tree = lab.second;
+        std::vector<int> shp = adims;
+        shp.insert(shp.end(), bdims.begin(), bdims.end());
+        std::vector<int64_t> st = suffix_strides(adims, N), sb = suffix_strides(bdims, 1);
+        st.insert(st.end(), sb.begin(), sb.end());
+        ob.shape.resize(RO);
+        ob.stride.resize(RO);
+        for (int j = 0; j < RO; ++j) {
+            ob.shape[j] = shp[perm[j]];
+            ob.stride[j] = st[perm[j]];
+        }
+        ob.offset = gp.c_off;
+        ob.size = M * N;
+        out->blocks.push_back(std::move(ob));
+        info.out_blocks += 1;
+        plan->groups.push_back(std::move(gp));
+    }
+    // canonical order (terms is keyed by the canonical index, so already sorted)
+    out->rebuild_index();
+    out->elems = c_pos;
+    out->meta_only = true;
+    plan->out_meta = out;
+    plan->a_panel_elems = a_pos;
+    plan->b_panel_elems = b_pos;
+    plan->out_elems = c_pos;
+    plan->info = info;
+    if (p == Prec::BF16X3)
+        for (auto& t : plan->copies) t.lo_off = t.dst_buf == 2 ? a_pos : b_pos;
+    return plan;
+}
+
+// ------------------------------------------------------- S^z expansion
+// t[(a_1, m_1), ..] = sum over the trees of the spin tuple of
+// m_tree[a_1, ..] c_tree[m_1, ..] (Sec. 2, Eq. tensor-cgc), written into the
+// U(1) blocks of charges (m_1, ..).  The trees of one spin tuple touch the same
+// elements, so the gathers run in layers (layer t = t-th tree of every spin
+// tuple), each accumulating onto the zeroed output.
+TensorPtr su2_to_u1(const Tensor& in, hipStream_t stream) {
+    if (in.group != SYMTEN_SU2) fail(SYMTEN_E_INVAL, "su2_to_u1: tensor is not SU(2)");
+    check_device_tensor(in, "su2_to_u1");
+    const int R = in.rank();
+    auto out = std::make_shared<Tensor>();
+    out->group = SYMTEN_U1;
+    out->flux = 0;
+    out->dtype = in.dtype;
+    // per leg: (tj, m) -> position of multiplet 0 of spin tj inside charge m
+    std::vector<std::map<std::pair<int, int>, int>> pos(R);
+    for (int l = 0; l < R; ++l) {
+        const Leg& L = in.legs[l];
+        int tmax = 0;
+        for (int t : L.q) tmax = std::max(tmax, t);
+        Leg U;
+        U.dir = L.dir;
+        for (int m = -tmax; m <= tmax; ++m) {
+            int d = 0;
+            for (size_t i = 0; i < L.q.size(); ++i) {
+                const int t = L.q[i];
+                if (t >= std::abs(m) && (t - m) % 2 == 0) {
+                    pos[l][{t, m}] = d;
+                    d += L.d[i];
+                }
+            }
+            if (d > 0) { U.q.push_back(m); U.d.push_back(d); }
+        }
+        out->legs.push_back(U);
+    }
+    out->elems = enumerate_blocks(*out);
+    out->buf = device_alloc(std::max<int64_t>(out->elems, 1) * out->esize());
+    out->meta_only = false;
+    launch_fill_zero(out->buf->ptr, ((std::max<int64_t>(out->elems, 1) * out->esize() + 3) / 4) * 4, stream);
+
+    std::vector<std::vector<CopyTask>> layers;
+    std::map<std::vector<int>, int> layer_of;   // spins -> trees seen so far
+    for (const Block& b : in.blocks) {
+        if (b.size == 0) continue;
+        const int layer = layer_of[b.q]++;
+        if ((int)layers.size() <= layer) layers.resize(layer + 1);
+        const DenseT& c = cgc_cached(in.legs, b.q, b.tree);
+        std::vector<int> idx(R, 0);
+        for (size_t lin = 0; lin < c.v.size(); ++lin) {
+            if (c.v[lin] != 0.0) {
+                std::vector<int> qs(R);
+                for (int l = 0; l < R; ++l) qs[l] = -b.q[l] + 2 * idx[l];
+                auto it = out->index.find(qs);
+                if (it == out->index.end()) fail(SYMTEN_E_SYM, "su2_to_u1: CGC entry outside the U(1) blocks");
+                const Block& ub = out->blocks[it->second];
+                int64_t doff = ub.offset;
+                for (int l = 0; l < R; ++l) doff += (int64_t)pos[l].at({b.q[l], qs[l]}) * ub.stride[l];
+                layers[layer].push_back(make_copy_task(0, b.offset, 1, doff, b.shape, b.stride, ub.stride, c.v[lin]));
+            }
+            for (int l = R - 1; l >= 0; --l) {
+                if (++idx[l] < c.shape[l]) break;
+                idx[l] = 0;
+            }
+        }
+    }
+    const bool f64 = in.dtype == SYMTEN_F64;
+    std::vector<BufferPtr> keep;
+    for (auto& tasks : layers) {
+        if (tasks.empty()) continue;
+        validate_tasks(tasks, {in.elems, out->elems});
+        std::vector<int64_t> prefix;
+        copy_prefix(tasks, prefix);
+        BufferPtr dt, dp;
+        upload_sync(dt, tasks.data(), tasks.size() * sizeof(CopyTask));
+        upload_sync(dp, prefix.data(), prefix.size() * sizeof(int64_t));
+        copy_launch_arg((const CopyTask*)dt->ptr, (const int64_t*)dp->ptr, (int)tasks.size(), prefix.back(),
+                        {in.data(), out->data()}, f64, /*accumulate*/ 4, stream);
+        keep.push_back(dt);
+        keep.push_back(dp);
+    }
+    // the descriptor buffers return to the pool when `keep` goes: wait first
+    HIPCHK(hipStreamSynchronize(stream));
+    return out;
+}
+
+}  // namespace symten

@@ -53,27 +53,29 @@ class Tensor:
             self._h = None
 
     @staticmethod
-    def _desc(legs, flux, dtype):
-        """legs: list of (sectors dict {label: dim}, direction)."""
+    def _desc(legs, flux, dtype, group="u1"):
+        """legs: list of (sectors dict {label: dim}, direction); labels are
+        U(1) charges or, for group "su2", doubled spins."""
         dirs = [int(d) for _, d in legs]
         nsec = [len(s) for s, _ in legs]
         labels = [int(q) for s, _ in legs for q in s]
         dims = [int(s[q]) for s, _ in legs for q in s]
         keep = (_ints(dirs), _ints(nsec), _ints(labels), _ints(dims))
         dt = _lib.F64 if dtype in ("f64", _lib.F64) else _lib.F32
-        d = _lib.Desc(_lib.U1, len(legs), keep[0], keep[1], keep[2], keep[3], int(flux), dt)
+        g = _lib.SU2 if group in ("su2", _lib.SU2) else _lib.U1
+        d = _lib.Desc(g, len(legs), keep[0], keep[1], keep[2], keep[3], int(flux), dt)
         return d, keep
 
     @classmethod
-    def create(cls, legs, flux=0, dtype="f32", stream=None):
-        d, keep = cls._desc(legs, flux, dtype)
+    def create(cls, legs, flux=0, dtype="f32", stream=None, group="u1"):
+        d, keep = cls._desc(legs, flux, dtype, group)
         h = C.c_void_p()
         check(lib().symten_create(C.byref(h), C.byref(d), _stream(stream)))
         return cls(h)
 
     @classmethod
-    def meta(cls, legs, flux=0, dtype="f32"):
-        d, keep = cls._desc(legs, flux, dtype)
+    def meta(cls, legs, flux=0, dtype="f32", group="u1"):
+        d, keep = cls._desc(legs, flux, dtype, group)
         h = C.c_void_p()
         check(lib().symten_create_meta(C.byref(h), C.byref(d)))
         return cls(h)
@@ -133,6 +135,23 @@ class Tensor:
             out.append((tuple(lab), tuple(shp), off.value, tuple(st)))
         return out
 
+    def trees(self):
+        """SU(2) coupling-tree labels of every block (empty tuples for U(1))."""
+        R = self.rank
+        buf = (C.c_int * R)()
+        n = C.c_int()
+        out = []
+        for i in range(self.num_blocks):
+            check(lib().symten_block_tree(self._h, i, C.byref(n), buf))
+            out.append(tuple(buf[k] for k in range(n.value)))
+        return out
+
+    def to_u1(self, stream=None):
+        """SU(2) tensor -> U(1) tensor of its S^z components (library expansion)."""
+        h = C.c_void_p()
+        check(lib().symten_su2_to_u1(C.byref(h), self._h, _stream(stream)))
+        return Tensor(h)
+
     def device_ptr(self):
         p, n = C.c_void_p(), C.c_int64()
         check(lib().symten_device_ptr(self._h, C.byref(p), C.byref(n)))
@@ -158,6 +177,13 @@ class Tensor:
             out[lab] = vals[pos:pos + n].reshape(shp)
             pos += n
         return out
+
+
+def su2_cg(tj1, tm1, tj2, tm2, tJ, tM):
+    """The library's Clebsch-Gordan coefficient, arguments doubled."""
+    v = C.c_double()
+    check(lib().symten_su2_cg(tj1, tm1, tj2, tm2, tJ, tM, C.byref(v)))
+    return v.value
 
 
 def contract(A, B, legsA, legsB, out_perm=None, prec="f32", stream=None):

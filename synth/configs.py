@@ -52,6 +52,8 @@ CONFIGS = {
             what="full CTM left move"),
     3: dict(name="su2_move_D10_chi100_f32", group="SU2", phys={1: 1}, flux=0,
             virt={0: 1, 1: 3, 2: 1}, chi={0: 11, 1: 13, 2: 13, 3: 6}, chi_target=100,
+            # multiplets of the fused (ket, bra) leg of the double layer
+            dd={0: 11, 1: 12, 2: 12, 3: 6, 4: 1},
             prec="f32", seed=1811,
             what="SU(2) reduced CTM move"),
     4: dict(name="u1_move_D8_chi200_sweep", group="U1", phys=PHYS_U1, flux=1,

@@ -7,8 +7,9 @@ tensor's values knowing only how many it needs.
 import numpy as np
 
 # Fixed tensor order of a workload: site tensor, four corners, four edges.
+# "a" is drawn directly only where a workload takes a random double-layer tensor.
 TENSOR_INDEX = {"A": 0, "C1": 1, "C2": 2, "C3": 3, "C4": 4,
-                "T1": 5, "T2": 6, "T3": 7, "T4": 8}
+                "T1": 5, "T2": 6, "T3": 7, "T4": 8, "a": 9}
 
 
 def draw(key, n):

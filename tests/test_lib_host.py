@@ -153,11 +153,18 @@ def test_error_codes():
     with pytest.raises(st.SymtenError) as e:
         st.plan_info(A, B, [5], [0])
     assert e.value.code == -1
-    # SU(2) descriptors are rejected, not mis-handled
-    d, keep = st.Tensor._desc([({0: 1}, 1), ({0: 1}, -1)], 0, "f32")
-    d.group = _lib.SU2
-    h = C.c_void_p()
-    assert _lib.lib().symten_create_meta(C.byref(h), C.byref(d)) == -8
+    # SU(2): flux must be 0 (no quantum-number shift), spins are >= 0
+    with pytest.raises(st.SymtenError) as e:
+        st.Tensor.meta([({0: 1}, 1), ({0: 1}, -1)], flux=2, group="su2")
+    assert e.value.code == -3
+    with pytest.raises(st.SymtenError) as e:
+        st.Tensor.meta([({-1: 1}, 1), ({1: 1}, -1)], flux=0, group="su2")
+    assert e.value.code == -1
+    # mixing groups in one contraction
+    S = st.Tensor.meta([({1: 3}, 1), ({0: 2}, -1)], flux=0, group="su2")
+    with pytest.raises(st.SymtenError) as e:
+        st.plan_info(A, S, [1], [0])
+    assert e.value.code == -3
     # device operations on metadata-only tensors fail cleanly
     with pytest.raises(st.SymtenError) as e:
         A.upload([0.0] * A.nnz)
