@@ -43,32 +43,91 @@ def build_workload(cfgd, seed, dtype, st, draw, TENSOR_INDEX):
     return T
 
 
-def traffic_for(kernel_name):
-    """HBM bytes per launch of `kernel_name` from the committed counter
-    summary, if it was taken on the current kernel sources; else None."""
+def sources_sha256():
+    """Hash of the library sources (kernels, planner, ABI)."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1808_10804_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".cpp", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_for(kernel_name, workload):
+    """HBM bytes per launch of `kernel_name` on `workload` from the committed
+    counter summary, if it was taken on the current library sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1808_10804_amd", "csrc", "kernels.hip"), "rb").read()
-    if rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("sources_sha256") != sources_sha256() or rec.get("workload") != workload:
         return None
     k = rec.get("kernels", {}).get(kernel_name)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def profile_name(rocprof_name):
+    """libsymten's profile name of a kernel from its demangled name."""
+    import re
+    m = re.search(r"symten::(gemm_f32_kernel|gemm_f64_kernel|gemm_bf16_kernel|copy_kernel)<([^()]*)>\(", rocprof_name)
+    if not m:
+        return None
+    fam, args = m.group(1), m.group(2)
+    t = re.search(r"TileShape<(\d+), (\d+), (\d+)>", args)
+    last = args.rsplit(",", 1)[-1].strip()
+    if fam == "gemm_f64_kernel":
+        return "gemm_f64_kernel<%sx%sx%s>" % t.groups()
+    if fam == "gemm_f32_kernel":
+        return "gemm_f32_kernel<%sx%sx%s,f32>" % t.groups()
+    if fam == "gemm_bf16_kernel":
+        return "gemm_bf16_kernel<%sx%sx%s,%s>" % (t.groups() + ("bf16x3" if last == "1" else "bf16",))
+    src = "f64" if "double" in args else "f32"
+    dst = {"0": "f32", "1": "f64", "2": "bf16", "3": "bf16x2", "4": "acc"}.get(last, last)
+    return "copy_kernel<%s,%s>" % (src, dst)
+
+
+def write_traffic(base, workload, command):
+    """profiles/traffic.json from the FETCH_SIZE / WRITE_SIZE summaries under
+    `base` (bench and calibration copy), scaled by the calibration copy."""
+    load = lambda n: json.load(open(os.path.join(base, n + ".summary.json")))
+    cal = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        rows = [r for r in load("pmc_copy_" + c) if "copyBuffer" in r["kernel"] and r["counter"] == c]
+        cal[c] = rows[0]["avg_per_dispatch"] * 1024.0 / (256 << 20)
+    kern = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        for r in load("pmc_" + c):
+            name = profile_name(r["kernel"])
+            if name is None or r["counter"] != c:
+                continue
+            k = kern.setdefault(name, {})
+            k[c.lower() + "_kib_per_dispatch"] = r["avg_per_dispatch"]
+            k[c.lower() + "_dispatches"] = r["dispatches"]
+            k[("fetch" if c == "FETCH_SIZE" else "write") + "_bytes_per_launch"] = r["avg_per_dispatch"] * 1024.0 / cal[c]
+    for k in kern.values():
+        if "fetch_bytes_per_launch" in k and "write_bytes_per_launch" in k:
+            k["bytes_per_launch"] = k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+    rec = {"sources_sha256": sources_sha256(), "workload": workload, "command": command,
+           "calibration": {"copy_bytes_each_way": 256 << 20, "fetch_counter_per_byte": cal["FETCH_SIZE"],
+                           "write_counter_per_byte": cal["WRITE_SIZE"]},
+           "kernels": kern}
+    json.dump(rec, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_baseline(cfgd):
     """The FP64 dense oracle timed on the host on one full move of the same
     workload (the oracle as it stands, BLAS threads = host cores)."""
     from oracle import u1
-    from synth import draw, TENSOR_INDEX
+    from synth import draw, TENSOR_INDEX, SITE_AND_ENV
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         threads = len(os.sched_getaffinity(0))
     w = u1.Workload(cfgd["phys"], cfgd["virt"], cfgd["chi"], cfgd["flux"])
-    vals = {n: draw((cfgd["seed"], TENSOR_INDEX[n]), w.nnz_of(n)) for n in TENSOR_INDEX}
+    vals = {n: draw((cfgd["seed"], TENSOR_INDEX[n]), w.nnz_of(n)) for n in SITE_AND_ENV}
     t0 = time.perf_counter()
     T = w.dense_tensors(vals)
     a, _ = u1.double_layer(T["A"], w.A_legs)
@@ -153,12 +212,134 @@ def bench_batched(args):
     print(json.dumps(out))
 
 
+def bench_su2(args):
+    """SU(2) workload: the four enlarged corners and the two halves of a left
+    move on reduced tensors (recoupling scalars in the gather), against the
+    same contractions on the U(1)-expanded (S^z) tensors through the same
+    kernels.  a is a random invariant tensor with the double layer's legs."""
+    import torch
+    import paper_1808_10804_amd as st
+    from synth import config, draw, TENSOR_INDEX
+
+    c = config(3)
+    chi, dd = c["chi"], c["dd"]
+    prec = args.prec or "f32"
+    dtype = "f64" if prec == "f64" else "f32"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    legs = {"T1": [(chi, 1), (dd, -1), (chi, -1)], "T2": [(chi, 1), (dd, 1), (chi, -1)],
+            "T3": [(chi, 1), (dd, 1), (chi, -1)], "T4": [(chi, 1), (dd, -1), (chi, -1)],
+            "a": [(dd, 1), (dd, 1), (dd, -1), (dd, -1)]}
+    for n in ("C1", "C2", "C3", "C4"):
+        legs[n] = [(chi, 1), (chi, -1)]
+    R = {}
+    for n, l in legs.items():
+        R[n] = st.Tensor.create(l, dtype=dtype, group="su2", stream=stream)
+        R[n].upload(draw((c["seed"], TENSOR_INDEX[n]), R[n].nnz), stream=stream)
+    U = {n: t.to_u1(stream=stream) for n, t in R.items()}
+
+    def step(T):
+        k = [st.enlarged_corner(w, T["C%d" % w], T[ta], T[tb], T["a"], prec=prec, stream=stream)
+             for w, ta, tb in ((1, "T1", "T4"), (2, "T1", "T2"), (3, "T3", "T2"), (4, "T3", "T4"))]
+        hu = st.contract(k[0][0], k[1][0], [0, 2], [0, 2], prec=prec, stream=stream)
+        hd = st.contract(k[3][0], k[2][0], [0, 3], [0, 2], prec=prec, stream=stream)
+        return k, hu, hd
+
+    def flops(T):
+        k, hu, hd = step(T)
+        fl = sum(x[1]["useful_flops"] for x in k)
+        for A, B, la, lb in ((k[0][0], k[1][0], [0, 2], [0, 2]), (k[3][0], k[2][0], [0, 3], [0, 2])):
+            fl += st.plan_info(A, B, la, lb)[0]["useful_flops"]
+        return fl
+
+    def timed(T):
+        for _ in range(args.warmup):
+            step(T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(T)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    ms_r, ms_u = timed(R), timed(U)
+    fl_r, fl_u = flops(R), flops(U)
+    st.profile_begin()
+    for _ in range(args.steps):
+        step(R)
+    torch.cuda.synchronize()
+    kst = st.profile_end()
+    dom = max(kst, key=lambda k: k["ms"])
+    avg = dom["ms"] / dom["launches"]
+    roof = None
+    if dom["name"].startswith("gemm"):
+        ach = dom["useful_flops"] / dom["launches"] / (avg * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                "frac": ach / PEAK_TFLOPS[prec], "traffic": None, "kernel": dom["name"], "avg_launch_ms": avg}
+    out = {
+        "metric": "useful GFLOP/s of the SU(2) reduced corners and halves of one left move",
+        "value": fl_r / (ms_r * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_r, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": prec, "data": "synthetic (seeded Gaussian reduced blocks)",
+        "config": {"workload": c["name"], "virtual": c["virt"], "chi_multiplets": chi, "dd_multiplets": dd,
+                   "chi_total": 100, "steps_timed": "4 enlarged corners + 2 halves"},
+        "roofline": roof,
+        "reduced": {"ms": ms_r, "useful_flops": fl_r},
+        "u1_expanded": {"ms": ms_u, "useful_flops": fl_u, "gflops": fl_u / (ms_u * 1e-3) / 1e9},
+        "speedup_vs_u1_expanded": ms_u / ms_r, "flop_ratio_expanded_over_reduced": fl_u / fl_r,
+        "kernels": sorted(kst, key=lambda k: -k["ms"])[:6],
+    }
+    print(json.dumps(out))
+
+
+def calibrate_copy():
+    """A plain device copy of known size, for scaling the HBM traffic
+    counters (FETCH_SIZE / WRITE_SIZE) of the profiled kernels."""
+    import torch
+    n = 64 << 20                                   # 64 Mi float32 = 256 MiB each way
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes_read": 4 * n, "calibration_copy_bytes_written": 4 * n,
+                      "dispatches": 5}))
+
+
+def pmc_summary(path):
+    """Average per dispatch of every counter in the rocprofv3 counter CSVs
+    under `path`, per kernel name (KiB for FETCH_SIZE / WRITE_SIZE)."""
+    import csv
+    import glob
+    acc = {}
+    for f in glob.glob(os.path.join(path, "**", "*counter_collection*.csv"), recursive=True):
+        for row in csv.DictReader(open(f)):
+            key = (row.get("Kernel_Name", "?"), row.get("Counter_Name", "?"))
+            disp = row.get("Dispatch_Id", row.get("Correlation_Id", "?"))
+            d = acc.setdefault(key, {})
+            d[disp] = d.get(disp, 0.0) + float(row.get("Counter_Value", 0.0))
+    out = []
+    for (kern, ctr), d in sorted(acc.items()):
+        out.append({"kernel": kern, "counter": ctr, "dispatches": len(d), "avg_per_dispatch": sum(d.values()) / len(d)})
+    print(json.dumps(out, indent=1))
+
+
 def main():
+    if "--calibrate-copy" in sys.argv:
+        calibrate_copy()
+        return
+    if "--pmc-summary" in sys.argv:
+        pmc_summary(sys.argv[sys.argv.index("--pmc-summary") + 1])
+        return
+    if "--write-traffic" in sys.argv:
+        i = sys.argv.index("--write-traffic")
+        write_traffic(sys.argv[i + 1], sys.argv[i + 2], " ".join(sys.argv[i + 3:]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 4, 5])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -168,6 +349,9 @@ def main():
         sys.exit(2)
     if args.config == 5:
         bench_batched(args)
+        return
+    if args.config == 3:
+        bench_su2(args)
         return
 
     import torch
@@ -229,7 +413,7 @@ def main():
             achieved = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS}
-        tb = traffic_for(dom["name"])
+        tb = traffic_for(dom["name"], cfgd["name"])
         roof["traffic"] = tb
         roof["kernel"] = dom["name"]
         roof["launches_per_step"] = dom["launches"] / args.steps

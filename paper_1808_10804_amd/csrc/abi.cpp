@@ -32,10 +32,8 @@ void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntask
 void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, void* const* d_ptrs,
                      Prec prec, int cfg, hipStream_t s);
 int choose_tile_cfg(const ContractPlan& p);
-void launch_extract_upper(const double* W, int ldw, int r, int n, double* R, int ldr, hipStream_t s);
 void launch_scale_cols(double* X, int ld, int rows, int cols, const double* s, double e, hipStream_t st);
 void launch_scale_rows(double* X, int ld, int rows, int cols, const double* s, double e, hipStream_t st);
-void launch_jw_build(const double* M, int ru, int rd, double* J, hipStream_t st);
 void launch_eig_to_svd(const double* Z, int NE, const double* w, int voff, int mn, int ru, int rd, bool jw,
                        double* S, double* U, double* V, hipStream_t st);
 // zero-padded batches of col-major blocks for the projector factorizations
@@ -48,7 +46,6 @@ struct PadArgs {
     bool src_f64;
 };
 void launch_pad_blocks(const PadArgs& a, double* dst, hipStream_t st);
-void launch_extract_upper_batched(const double* H, int N, int count, double* R, hipStream_t st);
 void launch_jw_build_batched(const double* M, int N, int count, double* J, hipStream_t st);
 
 namespace {
@@ -268,22 +265,26 @@ struct ctm_env {
     std::vector<double> svals;
     symten_tensor P, Pt;
     rocblas_handle rb = nullptr;
+    // side streams for the size classes of the projector eigensolves, which
+    // are latency-bound and overlap well (default priority, non-blocking)
+    static constexpr int kAux = 3;
+    hipStream_t aux[kAux] = {};
+    rocblas_handle rb_aux[kAux] = {};
+    hipEvent_t ev_start = nullptr, ev_done[kAux] = {};
     ~ctm_env() {
         if (rb) rocblas_destroy_handle(rb);
+        for (int i = 0; i < kAux; ++i) {
+            if (rb_aux[i]) rocblas_destroy_handle(rb_aux[i]);
+            if (ev_done[i]) (void)hipEventDestroy(ev_done[i]);
+            if (aux[i]) (void)hipStreamDestroy(aux[i]);
+        }
+        if (ev_start) (void)hipEventDestroy(ev_start);
     }
 };
 
 // ============================================================ kernels used
 // by the projector stage (small, FP64)
 namespace symten {
-__global__ void extract_upper_kernel(const double* __restrict__ W, int ldw, int r, int n, double* __restrict__ R,
-                                     int ldr) {
-    const int64_t tot = (int64_t)r * n;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-        const int row = (int)(i % r), col = (int)(i / r);
-        R[row + (int64_t)col * ldr] = row <= col ? W[row + (int64_t)col * ldw] : 0.0;
-    }
-}
 // X[:, j] *= s[j]^e  (col-major, ld)
 __global__ void scale_cols_kernel(double* __restrict__ X, int ld, int rows, int cols, const double* __restrict__ s,
                                   double e) {
@@ -300,18 +301,6 @@ __global__ void scale_rows_kernel(double* __restrict__ X, int ld, int rows, int 
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
         const int row = (int)(i % rows), col = (int)(i / rows);
         X[row + (int64_t)col * ld] *= pow(s[row], e);
-    }
-}
-// J = [[0, M], [M^T, 0]]  (N = ru + rd, col-major), M col-major ru x rd
-__global__ void jw_build_kernel(const double* __restrict__ M, int ru, int rd, double* __restrict__ J) {
-    const int N = ru + rd;
-    const int64_t tot = (int64_t)N * N;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
-        const int r = (int)(i % N), c = (int)(i / N);
-        double v = 0.0;
-        if (r < ru && c >= ru) v = M[r + (int64_t)(c - ru) * ru];
-        else if (r >= ru && c < ru) v = M[c + (int64_t)(r - ru) * ru];
-        J[i] = v;
     }
 }
 // Largest mn eigenpairs (syevd returns ascending order, NE of them) as
@@ -345,14 +334,6 @@ __global__ void pad_blocks_kernel(PadArgs a, double* __restrict__ dst) {
         dst[j * N2 + i] = v;
     }
 }
-__global__ void extract_upper_batched_kernel(const double* __restrict__ H, int N, double* __restrict__ R) {
-    const int j = blockIdx.y;
-    const int64_t N2 = (int64_t)N * N;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N2; i += (int64_t)gridDim.x * blockDim.x) {
-        const int r = (int)(i % N), c = (int)(i / N);
-        R[j * N2 + i] = r <= c ? H[j * N2 + i] : 0.0;
-    }
-}
 __global__ void jw_build_batched_kernel(const double* __restrict__ M, int N, double* __restrict__ J) {
     const int j = blockIdx.y;
     const int N2x = 2 * N;
@@ -368,11 +349,6 @@ __global__ void jw_build_batched_kernel(const double* __restrict__ M, int N, dou
     }
 }
 static int g1d(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
-void launch_extract_upper(const double* W, int ldw, int r, int n, double* R, int ldr, hipStream_t s) {
-    if ((int64_t)r * n == 0) return;
-    hipLaunchKernelGGL(extract_upper_kernel, dim3(g1d((int64_t)r * n)), dim3(256), 0, s, W, ldw, r, n, R, ldr);
-    HIPCHK(hipGetLastError());
-}
 void launch_scale_cols(double* X, int ld, int rows, int cols, const double* sv, double e, hipStream_t st) {
     if ((int64_t)rows * cols == 0) return;
     hipLaunchKernelGGL(scale_cols_kernel, dim3(g1d((int64_t)rows * cols)), dim3(256), 0, st, X, ld, rows, cols, sv, e);
@@ -381,12 +357,6 @@ void launch_scale_cols(double* X, int ld, int rows, int cols, const double* sv, 
 void launch_scale_rows(double* X, int ld, int rows, int cols, const double* sv, double e, hipStream_t st) {
     if ((int64_t)rows * cols == 0) return;
     hipLaunchKernelGGL(scale_rows_kernel, dim3(g1d((int64_t)rows * cols)), dim3(256), 0, st, X, ld, rows, cols, sv, e);
-    HIPCHK(hipGetLastError());
-}
-void launch_jw_build(const double* M, int ru, int rd, double* J, hipStream_t st) {
-    const int64_t N = ru + rd;
-    if (N == 0) return;
-    hipLaunchKernelGGL(jw_build_kernel, dim3(g1d(N * N)), dim3(256), 0, st, M, ru, rd, J);
     HIPCHK(hipGetLastError());
 }
 void launch_eig_to_svd(const double* Z, int NE, const double* w, int voff, int mn, int ru, int rd, bool jw,
@@ -400,12 +370,6 @@ void launch_pad_blocks(const PadArgs& a, double* dst, hipStream_t st) {
     if (a.count <= 0 || a.N <= 0) return;
     dim3 grid((unsigned)g1d((int64_t)a.N * a.N), (unsigned)a.count);
     hipLaunchKernelGGL(pad_blocks_kernel, grid, dim3(256), 0, st, a, dst);
-    HIPCHK(hipGetLastError());
-}
-void launch_extract_upper_batched(const double* H, int N, int count, double* R, hipStream_t st) {
-    if (count <= 0 || N <= 0) return;
-    dim3 grid((unsigned)g1d((int64_t)N * N), (unsigned)count);
-    hipLaunchKernelGGL(extract_upper_batched_kernel, grid, dim3(256), 0, st, H, N, R);
     HIPCHK(hipGetLastError());
 }
 void launch_jw_build_batched(const double* M, int N, int count, double* J, hipStream_t st) {
@@ -946,6 +910,13 @@ int ctm_env_create(ctm_env_t* env, const symten_t C[4], const symten_t Tt[4]) {
                     fail(SYMTEN_E_UNSUPPORTED, "environment: U(1) tensors only");
             }
             rb_check(rocblas_create_handle(&e->rb), "rocblas_create_handle");
+            HIPCHK(hipEventCreateWithFlags(&e->ev_start, hipEventDisableTiming));
+            for (int i = 0; i < ctm_env::kAux; ++i) {
+                HIPCHK(hipStreamCreateWithFlags(&e->aux[i], hipStreamNonBlocking));
+                HIPCHK(hipEventCreateWithFlags(&e->ev_done[i], hipEventDisableTiming));
+                rb_check(rocblas_create_handle(&e->rb_aux[i]), "rocblas_create_handle");
+                rb_check(rocblas_set_stream(e->rb_aux[i], e->aux[i]), "rocblas_set_stream");
+            }
         } catch (...) {
             delete e;
             throw;
@@ -1043,7 +1014,7 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
             int Q = 0, n = 0, m = 0, ru = 0, rd = 0, mn = 0;
             const GroupPlan* gu = nullptr;
             const GroupPlan* gd = nullptr;
-            double *Ru_p = nullptr, *Rd_p = nullptr, *M_p = nullptr;   // padded, ld
+            double *HuT_p = nullptr, *HdT_p = nullptr, *Y_p = nullptr;   // padded, ld
             int ld = 0;
             int* info_p = nullptr;
             BufferPtr U, V, S;
@@ -1075,28 +1046,36 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         std::vector<int> sv_off;
         std::vector<BufferPtr> keep_alive;
         {
-            // R factors of H_u^T = Q_u R_u and H_d^T = Q_d R_d, M = R_u R_d^T and
-            // its singular triplets, per fused charge.  rocSOLVER's factorizations
-            // are latency-bound (one launch sequence per column), so the blocks
-            // are grouped into size classes and each class is factorized in one
-            // strided-batched call: a block (col-major m x n = H^T) is zero-padded
-            // to the class size N, which leaves R = diag(R_A, 0) and
-            // M = diag(M_A, 0) exact; the padding adds only zero singular values.
-            // The SVD of M comes from a symmetric eigensolve (syevd is far faster
-            // than gesvd here): FP64 moves use the Jordan-Wielandt matrix
-            // [[0, M], [M^T, 0]] (eigenpairs +-s, [u; +-v]/sqrt2, no squaring of
-            // the condition number); the other precisions use M M^T (eigenvalues
-            // s^2), whose extra rounding is far below their own error budget.
+            // The scheme factorizes H_u^T = Q_u R_u and H_d^T = Q_d R_d and takes the
+            // SVD of M = R_u R_d^T.  Since Y = H_u^T H_d = Q_u M Q_d^T, Y has the
+            // same non-zero singular values, with U_Y = Q_u U and V_Y = Q_d V, so
+            //   P  = R_d^T V S^-1/2 = H_d V_Y S^-1/2,
+            //   P~ = S^-1/2 U^T R_u = S^-1/2 U_Y^T H_u^T,
+            // and no QR factorization is needed: per fused charge one FP64 GEMM
+            // forms Y and one symmetric eigensolve gives its singular triplets.
+            // rocSOLVER's eigensolver is latency-bound (one launch sequence per
+            // column), so the blocks are grouped into size classes and each class
+            // is solved in one strided-batched call: a block (col-major m x n =
+            // H^T) is zero-padded to the class size N, which leaves
+            // Y = diag(Y_A, 0) exact; the padding adds only zero singular values.
+            // FP64 moves use the Jordan-Wielandt matrix [[0, Y], [Y^T, 0]]
+            // (eigenpairs +-s, [u; +-v]/sqrt2, no squaring of the condition
+            // number); the other precisions use Y Y^T (eigenvalues s^2), whose
+            // extra rounding is far below their own error budget.
             std::vector<int> order = qs;
             for (int Q : qs) {
                 QB& b = qb[Q];
-                b.ru = b.rd = b.mn = std::min(b.m, b.n);
+                b.ru = b.rd = b.m;              // rows of U_Y and V_Y
+                b.mn = std::min(b.m, b.n);      // rank bound: singular values reported
             }
             std::sort(order.begin(), order.end(), [&](int x, int y) {
                 return std::max(qb[x].m, qb[x].n) > std::max(qb[y].m, qb[y].n);
             });
             const double one = 1.0, zero = 0.0;
             size_t pos = 0;
+            int ncls = 0;
+            bool aux_used[ctm_env::kAux] = {};
+            HIPCHK(hipEventRecord(env->ev_start, s));
             while (pos < order.size()) {
                 const int N = std::max(qb[order[pos]].m, qb[order[pos]].n);
                 std::vector<int> cls;
@@ -1104,10 +1083,21 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
                        2 * std::max(qb[order[pos]].m, qb[order[pos]].n) >= N)
                     cls.push_back(order[pos++]);
                 const int B = (int)cls.size();
+                // the largest class runs on the caller's stream, the others on
+                // the side streams (round robin), all after the halves
+                const int c = ncls++;
+                hipStream_t cs = s;
+                rocblas_handle rh = env->rb;
+                if (c > 0) {
+                    const int a = (c - 1) % ctm_env::kAux;
+                    cs = env->aux[a];
+                    rh = env->rb_aux[a];
+                    if (!aux_used[a]) HIPCHK(hipStreamWaitEvent(cs, env->ev_start, 0));
+                    aux_used[a] = true;
+                }
                 const size_t N2 = (size_t)N * N;
                 // H^T blocks (u, d interleaved) -> padded FP64 matrices
                 BufferPtr Hb = device_alloc(8 * N2 * 2 * B);
-                BufferPtr tau = device_alloc(8 * (size_t)N * 2 * B);
                 PadArgs pa{};
                 pa.count = 2 * B;
                 pa.N = N;
@@ -1122,19 +1112,14 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
                         pa.cols[2 * i + side] = b.n;
                     }
                 }
-                launch_pad_blocks(pa, (double*)Hb->ptr, s);
-                rb_check(rocsolver_dgeqrf_strided_batched(env->rb, N, N, (double*)Hb->ptr, N, N2, (double*)tau->ptr,
-                                                          N, 2 * B),
-                         "rocsolver_dgeqrf_strided_batched");
-                BufferPtr Rb = device_alloc(8 * N2 * 2 * B);
-                launch_extract_upper_batched((const double*)Hb->ptr, N, 2 * B, (double*)Rb->ptr, s);
-                // M = R_u R_d^T for every block of the class
+                launch_pad_blocks(pa, (double*)Hb->ptr, cs);
+                // Y = H_u^T H_d for every block of the class
                 BufferPtr Mb = device_alloc(8 * N2 * B);
-                rb_check(rocblas_dgemm_strided_batched(env->rb, rocblas_operation_none, rocblas_operation_transpose, N, N,
-                                                       N, &one, (const double*)Rb->ptr, N, 2 * N2,
-                                                       (const double*)Rb->ptr + N2, N, 2 * N2, &zero,
+                rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N,
+                                                       N, &one, (const double*)Hb->ptr, N, 2 * N2,
+                                                       (const double*)Hb->ptr + N2, N, 2 * N2, &zero,
                                                        (double*)Mb->ptr, N, N2, B),
-                         "rocblas_dgemm_strided_batched(M)");
+                         "rocblas_dgemm_strided_batched(Y)");
                 const int NE = f64 ? 2 * N : N;
                 const size_t NE2 = (size_t)NE * NE;
                 BufferPtr Zb = device_alloc(8 * NE2 * B);
@@ -1142,22 +1127,22 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
                 BufferPtr Eb = device_alloc(8 * (size_t)NE * B);
                 BufferPtr ib = device_alloc(8 * (size_t)B);
                 if (f64)
-                    launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, s);
+                    launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, cs);
                 else
-                    rb_check(rocblas_dgemm_strided_batched(env->rb, rocblas_operation_none, rocblas_operation_transpose,
+                    rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose,
                                                            N, N, N, &one, (const double*)Mb->ptr, N, N2,
                                                            (const double*)Mb->ptr, N, N2, &zero, (double*)Zb->ptr, N,
                                                            N2, B),
                              "rocblas_dgemm_strided_batched(MM^T)");
-                rb_check(rocsolver_dsyevd_strided_batched(env->rb, rocblas_evect_original, rocblas_fill_upper, NE,
+                rb_check(rocsolver_dsyevd_strided_batched(rh, rocblas_evect_original, rocblas_fill_upper, NE,
                                                           (double*)Zb->ptr, NE, NE2, (double*)wb->ptr, NE,
                                                           (double*)Eb->ptr, NE, (rocblas_int*)ib->ptr, B),
                          "rocsolver_dsyevd_strided_batched");
                 for (int i = 0; i < B; ++i) {
                     QB& b = qb[cls[i]];
-                    b.Ru_p = (double*)Rb->ptr + 2 * i * N2;
-                    b.Rd_p = (double*)Rb->ptr + (2 * i + 1) * N2;
-                    b.M_p = (double*)Mb->ptr + i * N2;
+                    b.HuT_p = (double*)Hb->ptr + 2 * i * N2;          // H_u^T, col-major m x n
+                    b.HdT_p = (double*)Hb->ptr + (2 * i + 1) * N2;    // H_d^T
+                    b.Y_p = (double*)Mb->ptr + i * N2;
                     b.ld = N;
                     b.info_p = (int*)ib->ptr + i;
                     b.S = device_alloc(8 * std::max(1, b.mn));
@@ -1165,10 +1150,15 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
                     b.V = device_alloc(8 * std::max<size_t>(1, (size_t)b.rd * b.mn));
                     launch_eig_to_svd((const double*)Zb->ptr + i * NE2, NE, (const double*)wb->ptr + (size_t)i * NE,
                                       N, b.mn, b.ru, b.rd, f64, (double*)b.S->ptr, (double*)b.U->ptr,
-                                      (double*)b.V->ptr, s);
+                                      (double*)b.V->ptr, cs);
                 }
-                for (auto& x : {Hb, tau, Rb, Mb, Zb, wb, Eb, ib}) keep_alive.push_back(x);
+                for (auto& x : {Hb, Mb, Zb, wb, Eb, ib}) keep_alive.push_back(x);
             }
+            for (int a = 0; a < ctm_env::kAux; ++a)
+                if (aux_used[a]) {
+                    HIPCHK(hipEventRecord(env->ev_done[a], env->aux[a]));
+                    HIPCHK(hipStreamWaitEvent(s, env->ev_done[a], 0));
+                }
             // singular values and status to the host (the one synchronisation)
             int tot = 0;
             for (int Q : qs) { sv_off.push_back(tot); tot += qb[Q].mn; }
@@ -1244,21 +1234,21 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
             double* Ptq = (double*)Pt->buf->ptr + pbase[Q];
             const double one = 1.0, zero = 0.0;
             if (!f64) {
-                // Gram path: V_k = M^T U_k S_k^-1  (rd x k, ld rd)
+                // Gram path: V_k = Y^T U_k S_k^-1  (rd x k, ld rd)
                 rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, b.rd, k, b.ru,
-                                       &one, (const double*)b.M_p, b.ld, (const double*)b.U->ptr, b.ru, &zero,
+                                       &one, (const double*)b.Y_p, b.ld, (const double*)b.U->ptr, b.ru, &zero,
                                        (double*)b.V->ptr, b.rd),
                          "rocblas_dgemm(V)");
                 launch_scale_cols((double*)b.V->ptr, b.rd, b.rd, k, (const double*)b.S->ptr, -1.0, s);
             }
-            // P = R_d^T V_k S^-1/2  (n x k, ld n)
+            // P = H_d V_k S^-1/2  (n x k, ld n; H_d = (H_d^T)^T)
             rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, n, k, b.rd, &one,
-                                   (const double*)b.Rd_p, b.ld, (const double*)b.V->ptr, b.rd, &zero, Pq, n),
+                                   (const double*)b.HdT_p, b.ld, (const double*)b.V->ptr, b.rd, &zero, Pq, n),
                      "rocblas_dgemm(P)");
             launch_scale_cols(Pq, n, n, k, (const double*)b.S->ptr, -0.5, s);
-            // P~ = S^-1/2 U_k^T R_u  (k x n, ld k)
+            // P~ = S^-1/2 U_k^T H_u^T  (k x n, ld k)
             rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, k, n, b.ru, &one,
-                                   (const double*)b.U->ptr, b.ru, (const double*)b.Ru_p, b.ld, &zero, Ptq, k),
+                                   (const double*)b.U->ptr, b.ru, (const double*)b.HuT_p, b.ld, &zero, Ptq, k),
                      "rocblas_dgemm(Pt)");
             launch_scale_rows(Ptq, k, k, n, (const double*)b.S->ptr, -0.5, s);
             launch_sign_fix_rows(Ptq, k, k, n, Pq, n, s);

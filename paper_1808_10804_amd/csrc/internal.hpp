@@ -92,7 +92,12 @@ double cg_coeff(int tj1, int tm1, int tj2, int tm2, int tJ, int tM);
 // Strided copy task: iterate a multi-index over dims (last fastest);
 // dst[dst_off + sum i*dstride] = src[src_off + sum i*sstride] (or 0 when
 // src_buf < 0).  Buffers are named by index into a pointer table.
+// A task may also sum several equally strided sources of the same buffer:
+// dst = scale * src[src_off + i] + sum_t xscale[t] * src[xsrc_off[t] + i]
+// (SU(2) operands: blocks that differ only in their coupling tree are
+// combined with their recoupling scalars before the product).
 constexpr int kMaxCopyRank = 8;
+constexpr int kMaxExtraSrc = 7;
 struct CopyTask {
     int64_t src_off, dst_off;
     int64_t sstride[kMaxCopyRank];
@@ -103,6 +108,10 @@ struct CopyTask {
     int count;          // product of dims (< 2^31)
     double scale;       // multiplies the copied value (SU(2) recoupling scalar)
     int64_t lo_off;     // split panels: the lo plane starts lo_off elements after the hi plane
+    int nextra;         // number of extra sources (0 .. kMaxExtraSrc)
+    int pad_;
+    int64_t xsrc_off[kMaxExtraSrc];
+    double xscale[kMaxExtraSrc];
 };
 
 struct GemmGroup {

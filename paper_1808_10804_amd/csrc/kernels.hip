@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <cstdio>
 #include <vector>
 
@@ -86,14 +87,22 @@ __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __re
             so += (int64_t)ik * T.sstride[k];
             dofs += (int64_t)ik * T.dstride[k];
         }
+        // weighted sum of the sources (one source unless SU(2) trees are combined)
+        using AT = std::conditional_t<DK == kDstF64, double, TS>;   // arithmetic type
+        AT sv = 0;
+        if (src) {
+            sv = (AT)src[so] * (AT)scale;
+            const int64_t rel = so - T.src_off;
+            for (int t = 0; t < T.nextra; ++t) sv += (AT)src[T.xsrc_off[t] + rel] * (AT)T.xscale[t];
+        }
         if constexpr (DK == kDstAcc) {
-            if (src) ((TS*)dstv)[dofs] += src[so] * (TS)scale;
+            if (src) ((TS*)dstv)[dofs] += sv;
         } else if constexpr (DK == kDstF64) {
-            ((double*)dstv)[dofs] = src ? (double)src[so] * scale : 0.0;
+            ((double*)dstv)[dofs] = (double)sv;
         } else if constexpr (DK == kDstF32) {
-            ((float*)dstv)[dofs] = src ? (float)src[so] * (float)scale : 0.f;
+            ((float*)dstv)[dofs] = (float)sv;
         } else {
-            const float v = src ? (float)src[so] * (float)scale : 0.f;
+            const float v = (float)sv;
             const unsigned short h = f32_to_bf16_rn(v);
             ((unsigned short*)dstv)[dofs] = h;
             if constexpr (DK == kDstSplit) ((unsigned short*)dstv)[dofs + T.lo_off] = f32_to_bf16_rn(v - bf16_to_f32(h));

@@ -621,8 +621,8 @@ std::string gemm_kernel_name(Prec p, int cfg) {
     switch (p) {
         case Prec::F64: return "gemm_f64_kernel<" + t + "x16>";
         case Prec::F32: return "gemm_f32_kernel<" + t + "x32,f32>";
-        case Prec::BF16: return "gemm_f32_kernel<" + t + "x32,bf16>";
-        default: return "gemm_f32_kernel<" + t + "x32,bf16x3>";
+        case Prec::BF16: return "gemm_bf16_kernel<" + t + "x32,bf16>";
+        default: return "gemm_bf16_kernel<" + t + "x32,bf16x3>";
     }
 }
 
@@ -800,6 +800,12 @@ void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_
             fail(SYMTEN_E_INVAL, "internal: copy destination out of bounds");
         if (t.src_buf >= 0 && (t.src_buf >= (int)buf_elems.size() || smin < 0 || smax >= buf_elems[t.src_buf]))
             fail(SYMTEN_E_INVAL, "internal: copy source out of bounds");
+        if (t.nextra < 0 || t.nextra > kMaxExtraSrc || (t.nextra > 0 && t.src_buf < 0))
+            fail(SYMTEN_E_INVAL, "internal: bad extra source count");
+        for (int x = 0; x < t.nextra; ++x) {
+            const int64_t lo = smin - t.src_off + t.xsrc_off[x], hi = smax - t.src_off + t.xsrc_off[x];
+            if (lo < 0 || hi >= buf_elems[t.src_buf]) fail(SYMTEN_E_INVAL, "internal: extra copy source out of bounds");
+        }
     }
 }
 

@@ -394,17 +394,51 @@ std::shared_ptr<ContractPlan> plan_contraction_su2(const Tensor& A, const Tensor
         std::vector<int> adims, bdims;
         for (int l : freeA) adims.push_back(ba0.shape[l]);
         for (int l : freeB) bdims.push_back(bb0.shape[l]);
-        int64_t M = 1, N = 1, K = 0;
+        int64_t M = 1, N = 1;
         for (int d : adims) M *= d;
         for (int d : bdims) N *= d;
-        std::vector<int64_t> koff, kdim;
-        for (auto& t : tl) {
-            int64_t k = 1;
-            for (int c : conA) k *= A.blocks[t.a].shape[c];
-            koff.push_back(K);
-            kdim.push_back(k);
-            K += k;
-        }
+        // K segments.  A-major: one segment per distinct A block, whose B
+        // panel is the sum over that block's terms of x * B block (blocks that
+        // differ in their tree only, same shape); B-major: the mirror image.
+        // The layout with the smaller K is taken.  Sources of one segment
+        // must share strides and number at most 1 + kMaxExtraSrc.
+        struct Seg {
+            int major;                                  // block of the major side
+            std::vector<std::pair<int, double>> minor;  // (block, scalar) summed on the other side
+            int64_t k;
+        };
+        auto segments = [&](bool a_major) {
+            const Tensor& Mj = a_major ? A : B;
+            const Tensor& Mn = a_major ? B : A;
+            const std::vector<int>& conM = a_major ? conA : conB;
+            std::map<int, std::vector<std::pair<int, double>>> by;
+            for (auto& t : tl) (a_major ? by[t.a] : by[t.b]).push_back({a_major ? t.b : t.a, t.x});
+            std::vector<Seg> out;
+            for (auto& e : by) {
+                int64_t k = 1;
+                for (int c : conM) k *= Mj.blocks[e.first].shape[c];
+                Seg cur{e.first, {}, k};
+                for (auto& m : e.second) {
+                    const bool fits = cur.minor.empty() ||
+                                      ((int)cur.minor.size() <= kMaxExtraSrc &&
+                                       Mn.blocks[m.first].stride == Mn.blocks[cur.minor[0].first].stride);
+                    if (!fits) {
+                        out.push_back(cur);
+                        cur.minor.clear();
+                    }
+                    cur.minor.push_back(m);
+                }
+                out.push_back(cur);
+            }
+            return out;
+        };
+        const std::vector<Seg> seg_a = segments(true), seg_b = segments(false);
+        int64_t ka = 0, kb = 0;
+        for (auto& g : seg_a) ka += g.k;
+        for (auto& g : seg_b) kb += g.k;
+        const bool a_major = ka <= kb;
+        const std::vector<Seg>& segs = a_major ? seg_a : seg_b;
+        const int64_t K = a_major ? ka : kb;
         if (M == 0 || N == 0 || K == 0) continue;
         if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 30)) fail(SYMTEN_E_CAPACITY, "contract: sector too large");
         const int64_t lda = (K + VW - 1) / VW * VW;
@@ -422,28 +456,37 @@ std::shared_ptr<ContractPlan> plan_contraction_su2(const Tensor& A, const Tensor
         c_pos += M * N;
         info.groups += 1;
         info.gemm_flops += 2 * M * N * K;
+        info.useful_flops += 2 * M * N * K;
+        info.pairs += (int64_t)tl.size();
         info.max_m = std::max<int64_t>(info.max_m, M);
         info.max_n = std::max<int64_t>(info.max_n, N);
         info.max_k = std::max<int64_t>(info.max_k, K);
-        for (size_t ti = 0; ti < tl.size(); ++ti) {
-            const Block& ba = A.blocks[tl[ti].a];
-            const Block& bb = B.blocks[tl[ti].b];
+        // panel task of one side: [free..., contracted...] of the listed blocks,
+        // summed with their scalars, into columns koff.. of the panel rows
+        auto panel_task = [&](const Tensor& X, const std::vector<int>& fr, const std::vector<int>& co,
+                              const std::vector<int>& fdims, int src, int dst, int64_t doff,
+                              const std::vector<std::pair<int, double>>& srcs) {
+            const Block& b0 = X.blocks[srcs[0].first];
             std::vector<int> dims, kd;
             std::vector<int64_t> ss;
-            for (int l : freeA) { dims.push_back(ba.shape[l]); ss.push_back(ba.stride[l]); }
-            for (int l : conA) { dims.push_back(ba.shape[l]); ss.push_back(ba.stride[l]); kd.push_back(ba.shape[l]); }
-            std::vector<int64_t> ds = suffix_strides(adims, lda), dk = suffix_strides(kd, 1);
+            for (int l : fr) { dims.push_back(b0.shape[l]); ss.push_back(b0.stride[l]); }
+            for (int l : co) { dims.push_back(b0.shape[l]); ss.push_back(b0.stride[l]); kd.push_back(b0.shape[l]); }
+            std::vector<int64_t> ds = suffix_strides(fdims, lda), dk = suffix_strides(kd, 1);
             ds.insert(ds.end(), dk.begin(), dk.end());
-            plan->copies.push_back(make_copy_task(0, ba.offset, 2, gp.a_off + koff[ti], dims, ss, ds, tl[ti].x));
-            dims.clear();
-            ss.clear();
-            for (int l : freeB) { dims.push_back(bb.shape[l]); ss.push_back(bb.stride[l]); }
-            for (int l : conB) { dims.push_back(bb.shape[l]); ss.push_back(bb.stride[l]); }
-            ds = suffix_strides(bdims, lda);
-            ds.insert(ds.end(), dk.begin(), dk.end());
-            plan->copies.push_back(make_copy_task(1, bb.offset, 3, gp.b_off + koff[ti], dims, ss, ds, 1.0));
-            info.pairs += 1;
-            info.useful_flops += 2 * M * N * kdim[ti];
+            CopyTask t = make_copy_task(src, b0.offset, dst, doff, dims, ss, ds, srcs[0].second);
+            t.nextra = (int)srcs.size() - 1;
+            for (int x = 1; x < (int)srcs.size(); ++x) {
+                t.xsrc_off[x - 1] = X.blocks[srcs[x].first].offset;
+                t.xscale[x - 1] = srcs[x].second;
+            }
+            plan->copies.push_back(t);
+        };
+        int64_t koff = 0;
+        for (const Seg& g : segs) {
+            const std::vector<std::pair<int, double>> major{{g.major, 1.0}};
+            panel_task(A, freeA, conA, adims, 0, 2, gp.a_off + koff, a_major ? major : g.minor);
+            panel_task(B, freeB, conB, bdims, 1, 3, gp.b_off + koff, a_major ? g.minor : major);
+            koff += g.k;
         }
         if (lda > K) {
             plan->copies.push_back(make_copy_task(-1, 0, 2, gp.a_off + K, {(int)M, (int)(lda - K)}, {0, 0}, {lda, 1}));

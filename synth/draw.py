@@ -10,6 +10,8 @@ import numpy as np
 # "a" is drawn directly only where a workload takes a random double-layer tensor.
 TENSOR_INDEX = {"A": 0, "C1": 1, "C2": 2, "C3": 3, "C4": 4,
                 "T1": 5, "T2": 6, "T3": 7, "T4": 8, "a": 9}
+# the tensors of a U(1) workload, which builds a from A
+SITE_AND_ENV = ("A", "C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4")
 
 
 def draw(key, n):

@@ -122,13 +122,19 @@ def test_plan_terms_match_recoupling_scalars(case):
     got = [(lab, tr) for (lab, _, _, _), tr in zip(O.blocks(), O.trees())]
     assert got == [out_blocks[ob] for ob in reached]
     assert info["pairs"] == len(terms)
+    # one GEMM per output block; its K runs over the distinct A blocks of its
+    # terms (B blocks summed with their scalars) or over the distinct B
+    # blocks, whichever is shorter
     ba, bb = su2.blocks(LA), su2.blocks(LB)
     fl = 0
-    for (ia, ib, ob) in terms:
-        m = np.prod([LA[l].n(ba[ia][0][l]) for l in fA])
-        n = np.prod([LB[l].n(bb[ib][0][l]) for l in fB])
-        k = np.prod([LA[l].n(ba[ia][0][l]) for l in conA])
-        fl += 2 * m * n * k
+    for ob in reached:
+        tj = out_blocks[ob][0]
+        mn = np.prod([Lo[j].n(tj[j]) for j in range(len(Lo))])
+        ia_set = {ia for (ia, ib, o) in terms if o == ob}
+        ib_set = {ib for (ia, ib, o) in terms if o == ob}
+        ka = sum(np.prod([LA[l].n(ba[ia][0][l]) for l in conA]) for ia in ia_set)
+        kb = sum(np.prod([LB[l].n(bb[ib][0][l]) for l in conB]) for ib in ib_set)
+        fl += 2 * mn * min(ka, kb)
     assert info["useful_flops"] == fl
     # output legs are the free legs in the requested order
     assert [({t: n for t, n in zip(l.tjs, l.mult)}, l.dir) for l in Lo] == O.legs()

@@ -12,14 +12,14 @@ import pytest
 
 from oracle import u1
 from oracle.u1 import IN, OUT, Leg, Workload
-from synth import config, draw, TENSOR_INDEX
+from synth import config, draw, TENSOR_INDEX, SITE_AND_ENV
 
 TINY = dict(phys={-1: 1, 1: 1}, virt={0: 1, 2: 1}, chi={-2: 1, 0: 2, 2: 1}, flux=1)
 
 
 def make(cfgd, seed):
     w = Workload(cfgd["phys"], cfgd["virt"], cfgd["chi"], cfgd["flux"])
-    vals = {n: draw((seed, TENSOR_INDEX[n]), w.nnz_of(n)) for n in TENSOR_INDEX}
+    vals = {n: draw((seed, TENSOR_INDEX[n]), w.nnz_of(n)) for n in SITE_AND_ENV}
     T = w.dense_tensors(vals)
     a, a_legs = u1.double_layer(T["A"], w.A_legs)
     return w, T, a, a_legs
