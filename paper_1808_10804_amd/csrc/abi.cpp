@@ -10,6 +10,8 @@
 #include <cstring>
 #include <functional>
 #include <list>
+#include <map>
+#include <sstream>
 #include <mutex>
 #include <numeric>
 #include <unordered_map>
@@ -417,6 +419,538 @@ TensorPtr make_desc_tensor(const symten_desc* d) {
 }
 
 }  // namespace
+
+namespace symten {
+namespace {
+// One diagonal block of the fused left cut: a U(1) charge or an SU(2) spin.
+struct CutSector {
+    int key = 0;                 // fused charge Q, or doubled spin 2J
+    int weight = 1;              // states per kept value: 1 (U(1)) or 2J+1 (SU(2))
+    int n = 0, m = 0;            // rows (left cut) x columns (right cut)
+    const void* hu = nullptr;    // row-major n x m blocks of the two halves
+    const void* hd = nullptr;    // (storage type of the move)
+    // filled by cut_projectors
+    int mn = 0;                  // singular values reported (min(n, m))
+    int k = 0;                   // kept
+    int64_t pbase = 0;           // offset of P[key] (n x k) and P~[key] (k x n)
+};
+struct ProjOut {
+    std::vector<double> sv;      // reduced singular values, sector by sector, descending
+    BufferPtr P, Pt;             // FP64, column-major per sector at CutSector::pbase
+    int64_t ptot = 0;
+    double tot2 = 0, disc2 = 0, smax = 0, gap = 0;
+    int64_t flops = 0;
+};
+
+// Projectors of the left cut from the blocks of the two halves (FP64).
+//
+// The scheme factorizes H_u^T = Q_u R_u and H_d^T = Q_d R_d and takes the
+// SVD of M = R_u R_d^T.  Since Y = H_u^T H_d = Q_u M Q_d^T, Y has the same
+// non-zero singular values, with U_Y = Q_u U and V_Y = Q_d V, so
+//   P  = R_d^T V S^-1/2 = H_d V_Y S^-1/2,
+//   P~ = S^-1/2 U^T R_u = S^-1/2 U_Y^T H_u^T,
+// and no QR factorization is needed: per sector one FP64 GEMM forms Y and
+// one symmetric eigensolve gives its singular triplets.  rocSOLVER's
+// eigensolver is latency-bound (one launch sequence per column), so the
+// sectors are grouped into size classes and each class is solved in one
+// strided-batched call: a block (col-major m x n = H^T) is zero-padded to the
+// class size N, which leaves Y = diag(Y_A, 0) exact; the padding adds only
+// zero singular values.  The largest class runs on the caller's stream, the
+// others on the side streams.  FP64 moves use the Jordan-Wielandt matrix
+// [[0, Y], [Y^T, 0]] (eigenpairs +-s, [u; +-v]/sqrt2, no squaring of the
+// condition number); the other precisions use Y Y^T (eigenvalues s^2), whose
+// extra rounding is far below their own error budget.
+//
+// Truncation (global over sectors): values in descending order (ties: key
+// ascending, then index), each kept while the kept states, counted with the
+// sector's weight, stay within chi, stopping at the first that does not fit
+// (a multiplet is never split) and at values <= 1e-14 s_max.  P~ rows get
+// the sign gauge (largest-magnitude entry positive).  One host
+// synchronisation (the singular values).
+ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool f64, hipStream_t s) {
+    if (secs.empty()) fail(SYMTEN_E_LINALG, "ctm_move: the halves have no common sector");
+    rb_check(rocblas_set_stream(env->rb, s), "rocblas_set_stream");
+    struct Work {
+        int ru = 0, rd = 0, ld = 0;
+        double *HuT = nullptr, *HdT = nullptr, *Y = nullptr;
+        int* info = nullptr;
+        BufferPtr U, V, S;
+    };
+    std::vector<Work> w(secs.size());
+    ProjOut out;
+    std::vector<int> sv_off;
+    std::vector<BufferPtr> keep_alive;
+    {
+        std::vector<int> order(secs.size());
+        std::iota(order.begin(), order.end(), 0);
+        for (size_t i = 0; i < secs.size(); ++i) {
+            w[i].ru = w[i].rd = secs[i].m;                       // rows of U_Y and V_Y
+            secs[i].mn = std::min(secs[i].m, secs[i].n);          // rank bound: values reported
+        }
+        auto dim = [&](int i) { return std::max(secs[i].m, secs[i].n); };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return dim(x) > dim(y); });
+        const double one = 1.0, zero = 0.0;
+        size_t pos = 0;
+        int ncls = 0;
+        bool aux_used[ctm_env::kAux] = {};
+        HIPCHK(hipEventRecord(env->ev_start, s));
+        while (pos < order.size()) {
+            const int N = dim(order[pos]);
+            std::vector<int> cls;
+            while (pos < order.size() && (int)cls.size() < kMaxPadBatch / 2 && 2 * dim(order[pos]) >= N)
+                cls.push_back(order[pos++]);
+            const int B = (int)cls.size();
+            // the largest class runs on the caller's stream, the others on the
+            // side streams (round robin), all after the halves
+            const int c = ncls++;
+            hipStream_t cs = s;
+            rocblas_handle rh = env->rb;
+            if (c > 0) {
+                const int a = (c - 1) % ctm_env::kAux;
+                cs = env->aux[a];
+                rh = env->rb_aux[a];
+                if (!aux_used[a]) HIPCHK(hipStreamWaitEvent(cs, env->ev_start, 0));
+                aux_used[a] = true;
+            }
+            const size_t N2 = (size_t)N * N;
+            // H^T blocks (u, d interleaved) -> padded FP64 matrices
+            BufferPtr Hb = device_alloc(8 * N2 * 2 * B);
+            PadArgs pa{};
+            pa.count = 2 * B;
+            pa.N = N;
+            pa.src_f64 = f64;
+            for (int i = 0; i < B; ++i) {
+                const CutSector& b = secs[cls[i]];
+                for (int side = 0; side < 2; ++side) {
+                    pa.src[2 * i + side] = side == 0 ? b.hu : b.hd;
+                    pa.rows[2 * i + side] = b.m;   // col-major m x n (ld m)
+                    pa.cols[2 * i + side] = b.n;
+                }
+            }
+            launch_pad_blocks(pa, (double*)Hb->ptr, cs);
+            // Y = H_u^T H_d for every block of the class
+            BufferPtr Mb = device_alloc(8 * N2 * B);
+            rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N, N,
+                                                   &one, (const double*)Hb->ptr, N, 2 * N2,
+                                                   (const double*)Hb->ptr + N2, N, 2 * N2, &zero, (double*)Mb->ptr, N,
+                                                   N2, B),
+                     "rocblas_dgemm_strided_batched(Y)");
+            const int NE = f64 ? 2 * N : N;
+            const size_t NE2 = (size_t)NE * NE;
+            BufferPtr Zb = device_alloc(8 * NE2 * B);
+            BufferPtr wb = device_alloc(8 * (size_t)NE * B);
+            BufferPtr Eb = device_alloc(8 * (size_t)NE * B);
+            BufferPtr ib = device_alloc(8 * (size_t)B);
+            if (f64)
+                launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, cs);
+            else
+                rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N,
+                                                       N, &one, (const double*)Mb->ptr, N, N2,
+                                                       (const double*)Mb->ptr, N, N2, &zero, (double*)Zb->ptr, N, N2,
+                                                       B),
+                         "rocblas_dgemm_strided_batched(YY^T)");
+            rb_check(rocsolver_dsyevd_strided_batched(rh, rocblas_evect_original, rocblas_fill_upper, NE,
+                                                      (double*)Zb->ptr, NE, NE2, (double*)wb->ptr, NE,
+                                                      (double*)Eb->ptr, NE, (rocblas_int*)ib->ptr, B),
+                     "rocsolver_dsyevd_strided_batched");
+            for (int i = 0; i < B; ++i) {
+                const CutSector& b = secs[cls[i]];
+                Work& x = w[cls[i]];
+                x.HuT = (double*)Hb->ptr + 2 * i * N2;          // H_u^T, col-major m x n
+                x.HdT = (double*)Hb->ptr + (2 * i + 1) * N2;    // H_d^T
+                x.Y = (double*)Mb->ptr + i * N2;
+                x.ld = N;
+                x.info = (int*)ib->ptr + i;
+                x.S = device_alloc(8 * std::max(1, b.mn));
+                x.U = device_alloc(8 * std::max<size_t>(1, (size_t)x.ru * b.mn));
+                x.V = device_alloc(8 * std::max<size_t>(1, (size_t)x.rd * b.mn));
+                launch_eig_to_svd((const double*)Zb->ptr + i * NE2, NE, (const double*)wb->ptr + (size_t)i * NE, N,
+                                  b.mn, x.ru, x.rd, f64, (double*)x.S->ptr, (double*)x.U->ptr, (double*)x.V->ptr, cs);
+            }
+            for (auto& x : {Hb, Mb, Zb, wb, Eb, ib}) keep_alive.push_back(x);
+        }
+        for (int a = 0; a < ctm_env::kAux; ++a)
+            if (aux_used[a]) {
+                HIPCHK(hipEventRecord(env->ev_done[a], env->aux[a]));
+                HIPCHK(hipStreamWaitEvent(s, env->ev_done[a], 0));
+            }
+        // singular values and status to the host (the one synchronisation)
+        int tot = 0;
+        for (auto& c : secs) { sv_off.push_back(tot); tot += c.mn; }
+        out.sv.resize(tot);
+        std::vector<int> infos(secs.size());
+        for (size_t i = 0; i < secs.size(); ++i) {
+            if (secs[i].mn)
+                HIPCHK(hipMemcpyAsync(out.sv.data() + sv_off[i], w[i].S->ptr, 8 * secs[i].mn, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&infos[i], w[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t i = 0; i < secs.size(); ++i)
+            if (infos[i] != 0) fail(SYMTEN_E_LINALG, "rocsolver_dsyevd did not converge");
+        for (double v : out.sv)
+            if (!std::isfinite(v)) fail(SYMTEN_E_LINALG, "non-finite singular value");
+    }
+    // ---- truncation ------------------------------------------------------
+    struct SV { double s; int key, sec, j; };
+    std::vector<SV> all;
+    for (size_t i = 0; i < secs.size(); ++i)
+        for (int j = 0; j < secs[i].mn; ++j) all.push_back({out.sv[sv_off[i] + j], secs[i].key, (int)i, j});
+    std::sort(all.begin(), all.end(), [](const SV& x, const SV& y) {
+        if (x.s != y.s) return x.s > y.s;
+        if (x.key != y.key) return x.key < y.key;
+        return x.j < y.j;
+    });
+    out.smax = all.empty() ? 0.0 : all[0].s;
+    int nkeep = 0, states = 0;
+    while (nkeep < (int)all.size() && all[nkeep].s > 1e-14 * out.smax &&
+           states + secs[all[nkeep].sec].weight <= chi) {
+        states += secs[all[nkeep].sec].weight;
+        ++nkeep;
+    }
+    if (nkeep == 0) fail(SYMTEN_E_LINALG, "ctm_move: no singular value above the cutoff");
+    for (size_t i = 0; i < all.size(); ++i) {
+        const double v = secs[all[i].sec].weight * all[i].s * all[i].s;
+        out.tot2 += v;
+        if ((int)i >= nkeep) out.disc2 += v;
+    }
+    out.gap = nkeep < (int)all.size() ? (all[nkeep - 1].s - all[nkeep].s) / out.smax : INFINITY;
+    for (int i = 0; i < nkeep; ++i) secs[all[i].sec].k += 1;
+    // the kept set of a sector is a prefix of its descending list
+    // ---- P = H_d V_k S^-1/2 (n x k), P~ = S^-1/2 U_k^T H_u^T (k x n) -------
+    for (auto& c : secs) {
+        c.pbase = out.ptot;
+        out.ptot += (int64_t)c.n * c.k;
+    }
+    out.P = device_alloc(8 * std::max<int64_t>(out.ptot, 1));
+    out.Pt = device_alloc(8 * std::max<int64_t>(out.ptot, 1));
+    const double one = 1.0, zero = 0.0;
+    for (size_t i = 0; i < secs.size(); ++i) {
+        const CutSector& c = secs[i];
+        Work& x = w[i];
+        out.flops += 2LL * x.ru * x.rd * c.n;
+        if (c.k == 0) continue;
+        const int n = c.n, k = c.k;
+        double* Pq = (double*)out.P->ptr + c.pbase;
+        double* Ptq = (double*)out.Pt->ptr + c.pbase;
+        if (!f64) {
+            // Gram path: V_k = Y^T U_k S_k^-1  (rd x k, ld rd)
+            rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, x.rd, k, x.ru, &one,
+                                   (const double*)x.Y, x.ld, (const double*)x.U->ptr, x.ru, &zero, (double*)x.V->ptr,
+                                   x.rd),
+                     "rocblas_dgemm(V)");
+            launch_scale_cols((double*)x.V->ptr, x.rd, x.rd, k, (const double*)x.S->ptr, -1.0, s);
+        }
+        // P = H_d V_k S^-1/2  (n x k, ld n; H_d = (H_d^T)^T)
+        rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, n, k, x.rd, &one,
+                               (const double*)x.HdT, x.ld, (const double*)x.V->ptr, x.rd, &zero, Pq, n),
+                 "rocblas_dgemm(P)");
+        launch_scale_cols(Pq, n, n, k, (const double*)x.S->ptr, -0.5, s);
+        // P~ = S^-1/2 U_k^T H_u^T  (k x n, ld k)
+        rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, k, n, x.ru, &one,
+                               (const double*)x.U->ptr, x.ru, (const double*)x.HuT, x.ld, &zero, Ptq, k),
+                 "rocblas_dgemm(Pt)");
+        launch_scale_rows(Ptq, k, k, n, (const double*)x.S->ptr, -0.5, s);
+        launch_sign_fix_rows(Ptq, k, k, n, Pq, n, s);
+    }
+    // the work buffers go back to the pool here; later launches that reuse
+    // them are ordered after these on the same stream
+    return out;
+}
+
+void fill_cut_stats(ctm_move_stats* st, const std::vector<CutSector>& secs, const ProjOut& po) {
+    int nk = 0;
+    for (auto& c : secs)
+        if (c.k > 0 && nk < CTM_MAX_SECTORS) { st->charge[nk] = c.key; st->kept[nk] = c.k; ++nk; }
+    st->nsec = nk;
+    st->n_sv_sectors = std::min<int>((int)secs.size(), CTM_MAX_SECTORS);
+    for (int i = 0; i < st->n_sv_sectors; ++i) { st->sv_charge[i] = secs[i].key; st->sv_count[i] = secs[i].mn; }
+    st->trunc_err = po.tot2 > 0 ? po.disc2 / po.tot2 : 0.0;
+    st->s_max = po.smax;
+    st->gap = po.gap;
+    st->flops_proj = po.flops;
+}
+}  // namespace
+}  // namespace symten
+
+namespace symten {
+namespace {
+// ---------------------------------------------------------------- SU(2) move
+Leg dual_leg(const Leg& l) {
+    Leg d = l;
+    d.dir = -l.dir;
+    return d;
+}
+
+// Fusion isometry F[a, b, f] (SU(2)): f's multiplets of spin J are the pairs
+// (multiplet of a with spin ja, multiplet of b with spin jb) with J in ja x jb,
+// ordered by (ja, jb) then row-major (i_a, i_b).  Reduced block (ja, jb, J) is
+// w * delta(f, pair index) with w = sqrt((2J+1)/(2K+1)) for the block's tree
+// root K, which makes the dense F unitary (its basis tensors restricted to a
+// fixed f state have squared norm (2K+1)/(2J+1) by Schur's lemma).  Cached
+// per leg structure.
+TensorPtr fusion_isometry(const Leg& la, const Leg& lb, int fdir, int dtype, hipStream_t s) {
+    static std::mutex mu;
+    static std::map<std::string, TensorPtr> cache;
+    std::ostringstream key;
+    for (const Leg* l : {&la, &lb}) {
+        key << l->dir << ":";
+        for (size_t i = 0; i < l->q.size(); ++i) key << l->q[i] << "x" << l->d[i] << ",";
+        key << ";";
+    }
+    key << fdir << "/" << dtype;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key.str());
+    if (it != cache.end()) return it->second;
+    // fused multiplets and the position of each (ja, jb) pair inside J
+    std::map<int, int> nJ;
+    std::map<std::array<int, 3>, int> base;
+    for (size_t ia = 0; ia < la.q.size(); ++ia)
+        for (size_t ib = 0; ib < lb.q.size(); ++ib)
+            for (int J = std::abs(la.q[ia] - lb.q[ib]); J <= la.q[ia] + lb.q[ib]; J += 2) {
+                base[{la.q[ia], lb.q[ib], J}] = nJ[J];
+                nJ[J] += la.d[ia] * lb.d[ib];
+            }
+    Leg f;
+    f.dir = fdir;
+    for (auto& kv : nJ) { f.q.push_back(kv.first); f.d.push_back(kv.second); }
+    auto F = std::make_shared<Tensor>();
+    F->group = SYMTEN_SU2;
+    F->flux = 0;
+    F->dtype = dtype;
+    F->legs = {la, lb, f};
+    F->elems = enumerate_blocks_su2(*F);
+    std::vector<double> host((size_t)std::max<int64_t>(F->elems, 1), 0.0);
+    for (const Block& b : F->blocks) {
+        const int ja = b.q[0], jb = b.q[1], J = b.q[2], K = b.tree.back();
+        const double w = std::sqrt((J + 1.0) / (K + 1.0));
+        const int na = b.shape[0], nb = b.shape[1];
+        const int b0 = base.at({ja, jb, J});
+        for (int x = 0; x < na; ++x)
+            for (int y = 0; y < nb; ++y)
+                host[b.offset + x * b.stride[0] + y * b.stride[1] + (int64_t)(b0 + x * nb + y) * b.stride[2]] = w;
+    }
+    const size_t es = F->esize();
+    F->buf = device_alloc(std::max<int64_t>(F->elems, 1) * es);
+    F->meta_only = false;
+    if (dtype == SYMTEN_F64) {
+        HIPCHK(hipMemcpy(F->buf->ptr, host.data(), F->elems * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> h32(host.begin(), host.end());
+        HIPCHK(hipMemcpy(F->buf->ptr, h32.data(), F->elems * 4, hipMemcpyHostToDevice));
+    }
+    (void)s;
+    cache[key.str()] = F;
+    return F;
+}
+
+// The same tensor with every leg reversed.  A real invariant tensor stays
+// invariant under the conjugate transformation law, and its basis tensor
+// sum_M C_in C_out is symmetric in the two chains, so only the tree labels
+// change: (in intermediates, out intermediates, K) -> (out, in, K).  Shares
+// the buffer.
+TensorPtr flip_all(const TensorPtr& t) {
+    auto r = std::make_shared<Tensor>(*t);
+    int nin = 0, nout = 0;
+    for (auto& l : r->legs) {
+        (l.dir > 0 ? nin : nout) += 1;
+        l.dir = -l.dir;
+    }
+    const int mi = std::max(0, nin - 2), mo = std::max(0, nout - 2);
+    for (auto& b : r->blocks) {
+        std::vector<int> tr(b.tree.begin() + mi, b.tree.begin() + mi + mo);
+        tr.insert(tr.end(), b.tree.begin(), b.tree.begin() + mi);
+        tr.push_back(b.tree.back());
+        b.tree = tr;
+    }
+    std::sort(r->blocks.begin(), r->blocks.end(),
+              [](const Block& x, const Block& y) { return std::tie(x.q, x.tree) < std::tie(y.q, y.tree); });
+    r->rebuild_index();
+    return r;
+}
+
+// X <- X / |X|_F for an SU(2) tensor: the dense norm is
+// sum over blocks of (2K+1) |m_b|^2 (basis tensors of different trees are
+// orthogonal, |c|^2 = 2K+1).  FP64 two-pass reduction over a weighted copy.
+void normalise_su2(Tensor& X, bool f64, hipStream_t s) {
+    std::vector<CopyTask> tasks;
+    int64_t pos = 0;
+    for (const Block& b : X.blocks) {
+        if (b.size == 0) continue;
+        std::vector<int64_t> ds(b.shape.size());
+        int64_t st = 1;
+        for (int l = (int)b.shape.size() - 1; l >= 0; --l) { ds[l] = st; st *= b.shape[l]; }
+        tasks.push_back(make_copy_task(0, b.offset, 1, pos, b.shape, b.stride, ds, std::sqrt(b.tree.back() + 1.0)));
+        pos += b.size;
+    }
+    if (tasks.empty()) return;
+    BufferPtr tmp = device_alloc(pos * X.esize());
+    validate_tasks(tasks, {X.elems, pos});
+    std::vector<int64_t> prefix;
+    copy_prefix(tasks, prefix);
+    BufferPtr dt, dp;
+    upload_sync(dt, tasks.data(), tasks.size() * sizeof(CopyTask));
+    upload_sync(dp, prefix.data(), prefix.size() * sizeof(int64_t));
+    copy_launch_arg((const CopyTask*)dt->ptr, (const int64_t*)dp->ptr, (int)tasks.size(), prefix.back(),
+                    {X.data(), tmp->ptr}, f64, f64 ? 1 : 0, s);
+    BufferPtr red = device_alloc(8 * (1 + 512));
+    launch_sumsq(tmp->ptr, f64, pos, (double*)red->ptr, s);
+    launch_scale_by_inv_sqrt(X.data(), f64, X.elems, (const double*)red->ptr, s);
+    HIPCHK(hipStreamSynchronize(s));   // descriptor and scratch buffers go back to the pool
+}
+
+// One left move on SU(2) reduced tensors.  Corners, halves and the
+// renormalisation are the U(1) move's contractions (recoupling scalars in
+// the gathers).  For the projectors the two legs of each cut are fused by a
+// unitary isometry into one multiplet leg, which turns each half into an
+// (in, out) rank-2 tensor: block diagonal in the total spin J of the cut, one
+// reduced matrix per J whose dense form is that matrix times the identity on
+// 2J+1 states (the rank-2 example of Sec. 2).  The projector stage then runs
+// per J exactly as per charge, keeps whole multiplets (2J+1 states each)
+// within chi, and the projectors are mapped back through the isometry.
+void move_su2(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st, hipStream_t s) {
+    const bool f64 = prec == SYMTEN_PREC_F64;
+    const int dtype = f64 ? SYMTEN_F64 : SYMTEN_F32;
+    Timer tm;
+    tm.init(st != nullptr);
+    tm.mark(s);
+    Tensor &C1 = *env->C[0], &C2 = *env->C[1], &C3 = *env->C[2], &C4 = *env->C[3];
+    Tensor &T1 = *env->T[0], &T2 = *env->T[1], &T3 = *env->T[2], &T4 = *env->T[3];
+    std::vector<CornerResult> ks =
+        corners_batched({1, 2, 3, 4}, {{&C1, &T1, &T4}, {&C2, &T1, &T2}, {&C3, &T3, &T2}, {&C4, &T3, &T4}}, a, prec, s);
+    CornerResult &k1 = ks[0], &k2 = ks[1], &k3 = ks[2], &k4 = ks[3];
+    tm.mark(s);
+    std::vector<Contracted> hh = contract_batched({{k1.corner.get(), k2.corner.get(), {0, 2}, {0, 2}, {}},
+                                                   {k4.corner.get(), k3.corner.get(), {0, 3}, {0, 2}, {}}},
+                                                  prec, s);
+    const Tensor& Hu = *hh[0].t;   // [x4, d, x2, d2]
+    const Tensor& Hd = *hh[1].t;   // [x4, u, x2, u3]
+    // the rows of the two halves are the two sides of the cut bond: dual legs
+    for (int l = 0; l < 2; ++l)
+        if (Hu.legs[l].dir != -Hd.legs[l].dir || !Hu.legs[l].same_sectors(Hd.legs[l]))
+            fail(SYMTEN_E_SYM, "ctm_move: upper and lower halves disagree on a cut basis");
+    // one dense isometry fuses the rows of both halves (F_L for H_u's leg
+    // directions, its reversal for H_d's), so that Y = H_u^T H_d is block
+    // diagonal in the fused spin; the columns get isometries of their own
+    TensorPtr FL = fusion_isometry(dual_leg(Hu.legs[0]), dual_leg(Hu.legs[1]), 1, dtype, s);
+    TensorPtr FLbar = flip_all(FL);
+    TensorPtr FRu = fusion_isometry(dual_leg(Hu.legs[2]), dual_leg(Hu.legs[3]), -1, dtype, s);
+    TensorPtr FRd = fusion_isometry(dual_leg(Hd.legs[2]), dual_leg(Hd.legs[3]), 1, dtype, s);
+    std::vector<Contracted> f1 = contract_batched({{&Hu, FL.get(), {0, 1}, {0, 1}, {}},
+                                                   {&Hd, FLbar.get(), {0, 1}, {0, 1}, {}}}, prec, s);   // [x2, d2, L]
+    std::vector<Contracted> f2 = contract_batched({{f1[0].t.get(), FRu.get(), {0, 1}, {0, 1}, {}},
+                                                   {f1[1].t.get(), FRd.get(), {0, 1}, {0, 1}, {}}}, prec, s);   // [L, R]
+    const Tensor& Gu = *f2[0].t;
+    const Tensor& Gd = *f2[1].t;
+    tm.mark(s);
+    // ---- projectors per total spin J of the cut --------------------------
+    const size_t es = f64 ? 8 : 4;
+    std::vector<CutSector> secs;
+    for (const Block& bu : Gu.blocks) {
+        const Block* bd = nullptr;
+        for (const Block& x : Gd.blocks)
+            if (x.q == bu.q && x.tree == bu.tree) bd = &x;
+        if (!bd) continue;
+        if (bd->shape != bu.shape) fail(SYMTEN_E_SYM, "ctm_move: fused halves disagree on a cut basis");
+        for (const Block* x : {&bu, bd})
+            if (x->stride[0] != x->shape[1] || x->stride[1] != 1)
+                fail(SYMTEN_E_INVAL, "internal: fused half block is not row-major");
+        CutSector c;
+        c.key = bu.q[0];
+        c.weight = bu.q[0] + 1;
+        c.n = bu.shape[0];
+        c.m = bu.shape[1];
+        c.hu = (const char*)Gu.data() + bu.offset * es;
+        c.hd = (const char*)Gd.data() + bd->offset * es;
+        secs.push_back(c);
+    }
+    ProjOut po = cut_projectors(env, secs, chi, f64, s);
+    // P''[L out, k in] (n x k col-major per J), P~''[k out, L in] (k x n)
+    auto P2 = std::make_shared<Tensor>();
+    auto Pt2 = std::make_shared<Tensor>();
+    Leg kin, kout, Lout = dual_leg(FL->legs[2]), Lin = FL->legs[2];
+    kin.dir = 1;
+    kout.dir = -1;
+    for (auto& c : secs)
+        if (c.k > 0) { kin.q.push_back(c.key); kin.d.push_back(c.k); }
+    kout.q = kin.q;
+    kout.d = kin.d;
+    P2->legs = {Lout, kin};
+    Pt2->legs = {kout, Lin};
+    for (auto* X : {P2.get(), Pt2.get()}) {
+        X->group = SYMTEN_SU2;
+        X->flux = 0;
+        X->dtype = SYMTEN_F64;
+        X->elems = po.ptot;
+        X->meta_only = false;
+    }
+    P2->buf = po.P;
+    Pt2->buf = po.Pt;
+    for (auto& c : secs) {
+        if (c.k == 0) continue;
+        Block pb;
+        pb.q = {c.key, c.key};
+        pb.tree = {c.key};
+        pb.shape = {c.n, c.k};
+        pb.stride = {1, c.n};
+        pb.offset = c.pbase;
+        pb.size = (int64_t)c.n * c.k;
+        P2->blocks.push_back(pb);
+        Block tb = pb;
+        tb.shape = {c.k, c.n};
+        tb.stride = {1, c.k};
+        Pt2->blocks.push_back(tb);
+    }
+    P2->rebuild_index();
+    Pt2->rebuild_index();
+    TensorPtr P2c = P2, Pt2c = Pt2;
+    if (!f64) {
+        P2c = std::make_shared<Tensor>(*P2);
+        Pt2c = std::make_shared<Tensor>(*Pt2);
+        P2c->dtype = Pt2c->dtype = SYMTEN_F32;
+        P2c->buf = device_alloc(4 * std::max<int64_t>(po.ptot, 1));
+        Pt2c->buf = device_alloc(4 * std::max<int64_t>(po.ptot, 1));
+        launch_cast(P2->buf->ptr, true, P2c->buf->ptr, false, po.ptot, s);
+        launch_cast(Pt2->buf->ptr, true, Pt2c->buf->ptr, false, po.ptot, s);
+    }
+    std::vector<Contracted> pp = contract_batched({{FL.get(), P2c.get(), {2}, {0}, {}},          // P  = [x4, d, k]
+                                                   {Pt2c.get(), FLbar.get(), {1}, {2}, {}}},   // P~ = [k, x4, d]
+                                                  prec, s);
+    TensorPtr Pc = pp[0].t, Ptc = pp[1].t;
+    tm.mark(s);
+    // ---- renormalise, as in the U(1) move ---------------------------------
+    std::vector<Contracted> r3 =
+        contract_batched({{k1.step1.get(), Pc.get(), {0, 1}, {0, 1}, {1, 0}},      // C1' = [k, x1]
+                          {k4.step1.get(), Ptc.get(), {0, 2}, {1, 2}, {}},         // C4' = [x3, k]
+                          {Ptc.get(), &T4, {1}, {2}, {}}},                         // P~ T4 = [k_hi, u, y, l]
+                         prec, s);
+    Contracted &c1n = r3[0], &c4n = r3[1], &t4a = r3[2];
+    Contracted xx = contract(*t4a.t, a, {1, 3}, {1, 0}, {}, prec, s);              // [k_hi, y, r, d]
+    Contracted t4n = contract(*xx.t, *Pc, {1, 3}, {0, 1}, {2, 1, 0}, prec, s);     // [k_lo, r, k_hi]
+    for (TensorPtr X : {c1n.t, t4n.t, c4n.t}) normalise_su2(*X, f64, s);
+    tm.mark(s);
+    env->C[0] = c1n.t;
+    env->T[3] = t4n.t;
+    env->C[3] = c4n.t;
+    env->P.t = Pc;
+    env->Pt.t = Ptc;
+    env->svals = po.sv;
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        HIPCHK(hipStreamSynchronize(s));
+        fill_cut_stats(st, secs, po);
+        st->flops_corners = k1.info.useful_flops + k2.info.useful_flops + k3.info.useful_flops + k4.info.useful_flops;
+        st->flops_halves = hh[0].plan->info.useful_flops + hh[1].plan->info.useful_flops;
+        st->flops_renorm = c1n.plan->info.useful_flops + t4a.plan->info.useful_flops + xx.plan->info.useful_flops +
+                           t4n.plan->info.useful_flops + c4n.plan->info.useful_flops;
+        st->ms_corners = tm.ms(0, 1);
+        st->ms_halves = tm.ms(1, 2);
+        st->ms_proj = tm.ms(2, 3);
+        st->ms_renorm = tm.ms(3, 4);
+        st->ms_total = tm.ms(0, 4);
+    }
+}
+}  // namespace
+}  // namespace symten
 
 // =================================================================== C ABI
 extern "C" {
@@ -906,8 +1440,8 @@ int ctm_env_create(ctm_env_t* env, const symten_t C[4], const symten_t Tt[4]) {
                 e->T[i] = T(Tt[i]).buf ? Tt[i]->t : nullptr;
                 if (!e->C[i] || !e->T[i]) fail(SYMTEN_E_INVAL, "environment tensors need device storage");
                 if (e->C[i]->rank() != 2 || e->T[i]->rank() != 3) fail(SYMTEN_E_INVAL, "C must be rank 2 and T rank 3");
-                if (e->C[i]->group != SYMTEN_U1 || e->T[i]->group != SYMTEN_U1)
-                    fail(SYMTEN_E_UNSUPPORTED, "environment: U(1) tensors only");
+                if (e->C[i]->group != e->C[0]->group || e->T[i]->group != e->C[0]->group)
+                    fail(SYMTEN_E_SYM, "environment: tensors of different symmetry groups");
             }
             rb_check(rocblas_create_handle(&e->rb), "rocblas_create_handle");
             HIPCHK(hipEventCreateWithFlags(&e->ev_start, hipEventDisableTiming));
@@ -982,13 +1516,19 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         Tensor& a = T(a_h);
         check_device_tensor(a, "ctm_move(a)");
         if (a.rank() != 4) fail(SYMTEN_E_INVAL, "a must have rank 4");
-        if (a.group != SYMTEN_U1) fail(SYMTEN_E_UNSUPPORTED, "ctm_move: U(1) tensors only");
         const hipStream_t s = S(stream);
         const bool f64 = prec == SYMTEN_PREC_F64;
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) {
             if ((env->C[i]->dtype == SYMTEN_F64) != f64 || (env->T[i]->dtype == SYMTEN_F64) != f64 ||
                 (a.dtype == SYMTEN_F64) != f64)
                 fail(SYMTEN_E_INVAL, "ctm_move: storage types do not match the precision");
+            if (env->C[i]->group != a.group || env->T[i]->group != a.group)
+                fail(SYMTEN_E_SYM, "ctm_move: environment and site tensor have different symmetry groups");
+        }
+        if (a.group == SYMTEN_SU2) {
+            move_su2(env, a, chi, prec, st, s);
+            return;
+        }
         Timer tm;
         tm.init(st != nullptr);
         tm.mark(s);
@@ -1009,193 +1549,28 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         tm.mark(s);
 
         // ---- projectors, per fused charge Q of the left cut (FP64) ----------
-        rb_check(rocblas_set_stream(env->rb, s), "rocblas_set_stream");
-        struct QB {
-            int Q = 0, n = 0, m = 0, ru = 0, rd = 0, mn = 0;
-            const GroupPlan* gu = nullptr;
-            const GroupPlan* gd = nullptr;
-            double *HuT_p = nullptr, *HdT_p = nullptr, *Y_p = nullptr;   // padded, ld
-            int ld = 0;
-            int* info_p = nullptr;
-            BufferPtr U, V, S;
-            int k = 0;
-        };
-        std::map<int, QB> qb;
-        for (auto& g : hu.plan->groups) {
-            const int Q = g.rows[0][0] - g.rows[0][1];
-            qb[Q].gu = &g;
-        }
-        for (auto& g : hd.plan->groups) {
-            const int Q = g.rows[0][0] - g.rows[0][1];
-            qb[Q].gd = &g;
-        }
+        std::map<int, const GroupPlan*> gu_of, gd_of;
+        for (auto& g : hu.plan->groups) gu_of[g.rows[0][0] - g.rows[0][1]] = &g;
+        for (auto& g : hd.plan->groups) gd_of[g.rows[0][0] - g.rows[0][1]] = &g;
         const size_t es = f64 ? 8 : 4;
-        std::vector<int> qs;
-        for (auto& kv : qb) {
-            QB& b = kv.second;
-            b.Q = kv.first;
-            if (!b.gu || !b.gd) continue;   // no weight on one side: nothing to keep
-            if (b.gu->rows != b.gd->rows || b.gu->cols != b.gd->cols || b.gu->M != b.gd->M || b.gu->N != b.gd->N)
+        std::vector<CutSector> secs;
+        for (auto& kv : gu_of) {
+            auto it = gd_of.find(kv.first);
+            if (it == gd_of.end()) continue;   // no weight on one side: nothing to keep
+            const GroupPlan* gu = kv.second;
+            const GroupPlan* gd = it->second;
+            if (gu->rows != gd->rows || gu->cols != gd->cols || gu->M != gd->M || gu->N != gd->N)
                 fail(SYMTEN_E_SYM, "ctm_move: upper and lower halves disagree on a cut basis");
-            b.n = b.gu->M;
-            b.m = b.gu->N;
-            qs.push_back(b.Q);
+            CutSector c;
+            c.key = kv.first;
+            c.weight = 1;
+            c.n = gu->M;
+            c.m = gu->N;
+            c.hu = (const char*)hu.t->data() + gu->c_off * es;
+            c.hd = (const char*)hd.t->data() + gd->c_off * es;
+            secs.push_back(c);
         }
-        if (qs.empty()) fail(SYMTEN_E_LINALG, "ctm_move: the halves have no common charge sector");
-        std::vector<double> sv_host;
-        std::vector<int> sv_off;
-        std::vector<BufferPtr> keep_alive;
-        {
-            // The scheme factorizes H_u^T = Q_u R_u and H_d^T = Q_d R_d and takes the
-            // SVD of M = R_u R_d^T.  Since Y = H_u^T H_d = Q_u M Q_d^T, Y has the
-            // same non-zero singular values, with U_Y = Q_u U and V_Y = Q_d V, so
-            //   P  = R_d^T V S^-1/2 = H_d V_Y S^-1/2,
-            //   P~ = S^-1/2 U^T R_u = S^-1/2 U_Y^T H_u^T,
-            // and no QR factorization is needed: per fused charge one FP64 GEMM
-            // forms Y and one symmetric eigensolve gives its singular triplets.
-            // rocSOLVER's eigensolver is latency-bound (one launch sequence per
-            // column), so the blocks are grouped into size classes and each class
-            // is solved in one strided-batched call: a block (col-major m x n =
-            // H^T) is zero-padded to the class size N, which leaves
-            // Y = diag(Y_A, 0) exact; the padding adds only zero singular values.
-            // FP64 moves use the Jordan-Wielandt matrix [[0, Y], [Y^T, 0]]
-            // (eigenpairs +-s, [u; +-v]/sqrt2, no squaring of the condition
-            // number); the other precisions use Y Y^T (eigenvalues s^2), whose
-            // extra rounding is far below their own error budget.
-            std::vector<int> order = qs;
-            for (int Q : qs) {
-                QB& b = qb[Q];
-                b.ru = b.rd = b.m;              // rows of U_Y and V_Y
-                b.mn = std::min(b.m, b.n);      // rank bound: singular values reported
-            }
-            std::sort(order.begin(), order.end(), [&](int x, int y) {
-                return std::max(qb[x].m, qb[x].n) > std::max(qb[y].m, qb[y].n);
-            });
-            const double one = 1.0, zero = 0.0;
-            size_t pos = 0;
-            int ncls = 0;
-            bool aux_used[ctm_env::kAux] = {};
-            HIPCHK(hipEventRecord(env->ev_start, s));
-            while (pos < order.size()) {
-                const int N = std::max(qb[order[pos]].m, qb[order[pos]].n);
-                std::vector<int> cls;
-                while (pos < order.size() && (int)cls.size() < kMaxPadBatch / 2 &&
-                       2 * std::max(qb[order[pos]].m, qb[order[pos]].n) >= N)
-                    cls.push_back(order[pos++]);
-                const int B = (int)cls.size();
-                // the largest class runs on the caller's stream, the others on
-                // the side streams (round robin), all after the halves
-                const int c = ncls++;
-                hipStream_t cs = s;
-                rocblas_handle rh = env->rb;
-                if (c > 0) {
-                    const int a = (c - 1) % ctm_env::kAux;
-                    cs = env->aux[a];
-                    rh = env->rb_aux[a];
-                    if (!aux_used[a]) HIPCHK(hipStreamWaitEvent(cs, env->ev_start, 0));
-                    aux_used[a] = true;
-                }
-                const size_t N2 = (size_t)N * N;
-                // H^T blocks (u, d interleaved) -> padded FP64 matrices
-                BufferPtr Hb = device_alloc(8 * N2 * 2 * B);
-                PadArgs pa{};
-                pa.count = 2 * B;
-                pa.N = N;
-                pa.src_f64 = f64;
-                for (int i = 0; i < B; ++i) {
-                    QB& b = qb[cls[i]];
-                    for (int side = 0; side < 2; ++side) {
-                        const Tensor& H = side == 0 ? *hu.t : *hd.t;
-                        const GroupPlan* g = side == 0 ? b.gu : b.gd;
-                        pa.src[2 * i + side] = (const char*)H.data() + g->c_off * es;
-                        pa.rows[2 * i + side] = b.m;   // col-major m x n (ld m)
-                        pa.cols[2 * i + side] = b.n;
-                    }
-                }
-                launch_pad_blocks(pa, (double*)Hb->ptr, cs);
-                // Y = H_u^T H_d for every block of the class
-                BufferPtr Mb = device_alloc(8 * N2 * B);
-                rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N,
-                                                       N, &one, (const double*)Hb->ptr, N, 2 * N2,
-                                                       (const double*)Hb->ptr + N2, N, 2 * N2, &zero,
-                                                       (double*)Mb->ptr, N, N2, B),
-                         "rocblas_dgemm_strided_batched(Y)");
-                const int NE = f64 ? 2 * N : N;
-                const size_t NE2 = (size_t)NE * NE;
-                BufferPtr Zb = device_alloc(8 * NE2 * B);
-                BufferPtr wb = device_alloc(8 * (size_t)NE * B);
-                BufferPtr Eb = device_alloc(8 * (size_t)NE * B);
-                BufferPtr ib = device_alloc(8 * (size_t)B);
-                if (f64)
-                    launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, cs);
-                else
-                    rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose,
-                                                           N, N, N, &one, (const double*)Mb->ptr, N, N2,
-                                                           (const double*)Mb->ptr, N, N2, &zero, (double*)Zb->ptr, N,
-                                                           N2, B),
-                             "rocblas_dgemm_strided_batched(MM^T)");
-                rb_check(rocsolver_dsyevd_strided_batched(rh, rocblas_evect_original, rocblas_fill_upper, NE,
-                                                          (double*)Zb->ptr, NE, NE2, (double*)wb->ptr, NE,
-                                                          (double*)Eb->ptr, NE, (rocblas_int*)ib->ptr, B),
-                         "rocsolver_dsyevd_strided_batched");
-                for (int i = 0; i < B; ++i) {
-                    QB& b = qb[cls[i]];
-                    b.HuT_p = (double*)Hb->ptr + 2 * i * N2;          // H_u^T, col-major m x n
-                    b.HdT_p = (double*)Hb->ptr + (2 * i + 1) * N2;    // H_d^T
-                    b.Y_p = (double*)Mb->ptr + i * N2;
-                    b.ld = N;
-                    b.info_p = (int*)ib->ptr + i;
-                    b.S = device_alloc(8 * std::max(1, b.mn));
-                    b.U = device_alloc(8 * std::max<size_t>(1, (size_t)b.ru * b.mn));
-                    b.V = device_alloc(8 * std::max<size_t>(1, (size_t)b.rd * b.mn));
-                    launch_eig_to_svd((const double*)Zb->ptr + i * NE2, NE, (const double*)wb->ptr + (size_t)i * NE,
-                                      N, b.mn, b.ru, b.rd, f64, (double*)b.S->ptr, (double*)b.U->ptr,
-                                      (double*)b.V->ptr, cs);
-                }
-                for (auto& x : {Hb, Mb, Zb, wb, Eb, ib}) keep_alive.push_back(x);
-            }
-            for (int a = 0; a < ctm_env::kAux; ++a)
-                if (aux_used[a]) {
-                    HIPCHK(hipEventRecord(env->ev_done[a], env->aux[a]));
-                    HIPCHK(hipStreamWaitEvent(s, env->ev_done[a], 0));
-                }
-            // singular values and status to the host (the one synchronisation)
-            int tot = 0;
-            for (int Q : qs) { sv_off.push_back(tot); tot += qb[Q].mn; }
-            sv_host.resize(tot);
-            std::vector<int> infos(qs.size());
-            for (size_t i = 0; i < qs.size(); ++i) {
-                QB& b = qb[qs[i]];
-                if (b.mn) HIPCHK(hipMemcpyAsync(sv_host.data() + sv_off[i], b.S->ptr, 8 * b.mn, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipMemcpyAsync(&infos[i], b.info_p, sizeof(int), hipMemcpyDeviceToHost, s));
-            }
-            HIPCHK(hipStreamSynchronize(s));
-            for (size_t i = 0; i < qs.size(); ++i)
-                if (infos[i] != 0) fail(SYMTEN_E_LINALG, "rocsolver_dsyevd did not converge");
-            for (double v : sv_host)
-                if (!std::isfinite(v)) fail(SYMTEN_E_LINALG, "non-finite singular value");
-        }
-        // ---- truncation: global top-chi, ties by charge then index ----------
-        struct SV { double s; int Q, j; };
-        std::vector<SV> all;
-        for (size_t i = 0; i < qs.size(); ++i)
-            for (int j = 0; j < qb[qs[i]].mn; ++j) all.push_back({sv_host[sv_off[i] + j], qs[i], j});
-        std::sort(all.begin(), all.end(), [](const SV& x, const SV& y) {
-            if (x.s != y.s) return x.s > y.s;
-            if (x.Q != y.Q) return x.Q < y.Q;
-            return x.j < y.j;
-        });
-        const double smax = all.empty() ? 0.0 : all[0].s;
-        int nkeep = 0;
-        while (nkeep < (int)all.size() && nkeep < chi && all[nkeep].s > 1e-14 * smax) ++nkeep;
-        if (nkeep == 0) fail(SYMTEN_E_LINALG, "ctm_move: no singular value above the cutoff");
-        double tot2 = 0.0, disc2 = 0.0;
-        for (size_t i = 0; i < all.size(); ++i) {
-            tot2 += all[i].s * all[i].s;
-            if ((int)i >= nkeep) disc2 += all[i].s * all[i].s;
-        }
-        for (int i = 0; i < nkeep; ++i) qb[all[i].Q].k += 1;
-        // the kept set of a sector is a prefix of its descending list
+        ProjOut po = cut_projectors(env, secs, chi, f64, s);
         // ---- projector tensors P[chi out, D in, k in], P~[k out, chi in, D out]
         const Leg& chiL = T4.legs[0];
         const Leg& dL = a.legs[3];
@@ -1209,8 +1584,8 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         Leg kin, kout;
         kin.dir = 1;
         kout.dir = -1;
-        for (int Q : qs)
-            if (qb[Q].k > 0) { kin.q.push_back(Q); kin.d.push_back(qb[Q].k); }
+        for (auto& c : secs)
+            if (c.k > 0) { kin.q.push_back(c.key); kin.d.push_back(c.k); }
         kout.q = kin.q;
         kout.d = kin.d;
         Leg chi_out = chiL, chi_in = chiL, d_in = dL, d_out = dL;
@@ -1220,40 +1595,16 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         d_out.dir = -1;
         P->legs = {chi_out, d_in, kin};
         Pt->legs = {kout, chi_in, d_out};
-        int64_t ptot = 0;
-        std::map<int, int64_t> pbase;
-        for (int Q : kin.q) { pbase[Q] = ptot; ptot += (int64_t)qb[Q].n * qb[Q].k; }
-        P->buf = device_alloc(8 * std::max<int64_t>(ptot, 1));
-        Pt->buf = device_alloc(8 * std::max<int64_t>(ptot, 1));
+        const int64_t ptot = po.ptot;
+        P->buf = po.P;
+        Pt->buf = po.Pt;
         P->elems = Pt->elems = ptot;
         P->meta_only = Pt->meta_only = false;
-        for (int Q : kin.q) {
-            QB& b = qb[Q];
-            const int n = b.n, k = b.k;
-            double* Pq = (double*)P->buf->ptr + pbase[Q];
-            double* Ptq = (double*)Pt->buf->ptr + pbase[Q];
-            const double one = 1.0, zero = 0.0;
-            if (!f64) {
-                // Gram path: V_k = Y^T U_k S_k^-1  (rd x k, ld rd)
-                rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, b.rd, k, b.ru,
-                                       &one, (const double*)b.Y_p, b.ld, (const double*)b.U->ptr, b.ru, &zero,
-                                       (double*)b.V->ptr, b.rd),
-                         "rocblas_dgemm(V)");
-                launch_scale_cols((double*)b.V->ptr, b.rd, b.rd, k, (const double*)b.S->ptr, -1.0, s);
-            }
-            // P = H_d V_k S^-1/2  (n x k, ld n; H_d = (H_d^T)^T)
-            rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, n, k, b.rd, &one,
-                                   (const double*)b.HdT_p, b.ld, (const double*)b.V->ptr, b.rd, &zero, Pq, n),
-                     "rocblas_dgemm(P)");
-            launch_scale_cols(Pq, n, n, k, (const double*)b.S->ptr, -0.5, s);
-            // P~ = S^-1/2 U_k^T H_u^T  (k x n, ld k)
-            rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, k, n, b.ru, &one,
-                                   (const double*)b.U->ptr, b.ru, (const double*)b.HuT_p, b.ld, &zero, Ptq, k),
-                     "rocblas_dgemm(Pt)");
-            launch_scale_rows(Ptq, k, k, n, (const double*)b.S->ptr, -0.5, s);
-            launch_sign_fix_rows(Ptq, k, k, n, Pq, n, s);
+        for (auto& c : secs) {
+            if (c.k == 0) continue;
+            const int Q = c.key, n = c.n, k = c.k;
             // blocks: one per (q_chi, q_D) row sub-block of this sector
-            const GroupPlan* g = b.gu;
+            const GroupPlan* g = gu_of[Q];
             for (size_t r = 0; r < g->rows.size(); ++r) {
                 const int qx = g->rows[r][0], qd = g->rows[r][1];
                 const int dx = chiL.dim_of(qx), dd = dL.dim_of(qd);
@@ -1261,14 +1612,14 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
                 pb.q = {qx, qd, Q};
                 pb.shape = {dx, dd, k};
                 pb.stride = {dd, 1, n};
-                pb.offset = pbase[Q] + g->row_off[r];
+                pb.offset = c.pbase + g->row_off[r];
                 pb.size = (int64_t)dx * dd * k;
                 P->blocks.push_back(pb);
                 Block tb;
                 tb.q = {Q, qx, qd};
                 tb.shape = {k, dx, dd};
                 tb.stride = {1, (int64_t)dd * k, k};
-                tb.offset = pbase[Q] + (int64_t)g->row_off[r] * k;
+                tb.offset = c.pbase + (int64_t)g->row_off[r] * k;
                 tb.size = pb.size;
                 Pt->blocks.push_back(tb);
             }
@@ -1311,26 +1662,16 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         env->C[3] = c4n.t;
         env->P.t = P;
         env->Pt.t = Pt;
-        env->svals.clear();
-        for (size_t i = 0; i < qs.size(); ++i)
-            for (int j = 0; j < qb[qs[i]].mn; ++j) env->svals.push_back(sv_host[sv_off[i] + j]);
+        env->svals = po.sv;
         if (st) {
             std::memset(st, 0, sizeof(*st));
             HIPCHK(hipStreamSynchronize(s));
-            st->nsec = std::min<int>((int)kin.q.size(), CTM_MAX_SECTORS);
-            for (int i = 0; i < st->nsec; ++i) { st->charge[i] = kin.q[i]; st->kept[i] = kin.d[i]; }
-            st->n_sv_sectors = std::min<int>((int)qs.size(), CTM_MAX_SECTORS);
-            for (int i = 0; i < st->n_sv_sectors; ++i) { st->sv_charge[i] = qs[i]; st->sv_count[i] = qb[qs[i]].mn; }
-            st->trunc_err = tot2 > 0 ? disc2 / tot2 : 0.0;
-            st->s_max = smax;
-            st->gap = nkeep < (int)all.size() ? (all[nkeep - 1].s - all[nkeep].s) / smax : INFINITY;
+            fill_cut_stats(st, secs, po);
             st->flops_corners = k1.info.useful_flops + k2.info.useful_flops + k3.info.useful_flops + k4.info.useful_flops;
             st->flops_halves = hu.plan->info.useful_flops + hd.plan->info.useful_flops;
             st->flops_renorm = c1n.plan->info.useful_flops + t4a.plan->info.useful_flops + xx.plan->info.useful_flops +
                                t4n.plan->info.useful_flops + c4n.plan->info.useful_flops;
-            int64_t fp = 0;
-            for (int Q : qs) fp += 2LL * qb[Q].ru * qb[Q].rd * qb[Q].n;
-            st->flops_proj = fp;
+
             st->ms_corners = tm.ms(0, 1);
             st->ms_halves = tm.ms(1, 2);
             st->ms_proj = tm.ms(2, 3);

@@ -137,3 +137,121 @@ def test_cfg3_expansion_of_inputs_vs_oracle():
         L = [su2.Leg(s, d) for s, d in legs[n]]
         ref, ulegs = su2.to_u1(su2.expand(L, vals[n]), L)
         assert rel(to_dense(dev[n].to_u1(), ulegs), ref) <= 1e-15
+
+
+# ---------------------------------------------------------------- SU(2) move
+def _env_legs(chi, dd):
+    L = corner_legs(chi, dd)
+    for n in ("C2", "C3", "C4"):
+        L[n] = [(chi, IN), (chi, OUT)]
+    L["T2"] = [(chi, IN), (dd, IN), (chi, OUT)]
+    L["T3"] = [(chi, IN), (dd, IN), (chi, OUT)]
+    return L
+
+
+def _su2_env(legs, vals, dt):
+    dev = device(legs, vals, dt)
+    env = st.CtmEnv([dev[k] for k in ("C1", "C2", "C3", "C4")], [dev[k] for k in ("T1", "T2", "T3", "T4")])
+    return env, dev
+
+
+def _expanded_u1(legs, vals):
+    """Dense S^z-ordered arrays of the SU(2) tensors and the U(1) sector lists
+    of their chi and D^2 legs (oracle expansion)."""
+    out = {}
+    for n, spec in legs.items():
+        L = [su2.Leg(s, d) for s, d in spec]
+        out[n], _ = su2.to_u1(su2.expand(L, vals[n]), L)
+    chi_u1 = su2.Leg(legs["C1"][0][0], IN).u1_leg().sectors()
+    dd_u1 = su2.Leg(legs["a"][0][0], IN).u1_leg().sectors()
+    return out, chi_u1, dd_u1
+
+
+def _dense_u1(t):
+    """Device SU(2) tensor -> dense array in the S^z state order (oracle expansion)."""
+    v, L = reduced_full(t)
+    d, _ = su2.to_u1(su2.expand(L, v), L)
+    return d
+
+
+def _spectrum_states(sv, stats):
+    """Reduced singular values repeated 2J+1 times, descending."""
+    out, pos = [], 0
+    for tj, n in sorted(stats["sv_sectors"].items()):
+        out += list(np.repeat(sv[pos:pos + n], tj + 1))
+        pos += n
+    return np.sort(np.array(out))[::-1]
+
+
+SMALL_MOVE = dict(chi={0: 2, 1: 2, 2: 1}, dd={0: 2, 1: 2, 2: 1}, chi_target=7)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_su2_move_small_vs_oracle(prec):
+    """SU(2) left move against the oracle's U(1) move on the CG-expanded
+    tensors, truncated to the same number of states: spectrum (each reduced
+    value 2J+1 times), the projector P P~ on the cut, and the gauge-invariant
+    left column."""
+    from types import SimpleNamespace
+    from oracle import u1
+    legs = _env_legs(SMALL_MOVE["chi"], SMALL_MOVE["dd"])
+    vals = su2_values(legs, 1811)
+    dt = "f64" if prec == "f64" else "f32"
+    env, dev = _su2_env(legs, vals, dt)
+    print(f"su2 small move {prec}", flush=True)
+    stats = env.move(dev["a"], SMALL_MOVE["chi_target"], prec=prec)
+    kept_states = sum((tj + 1) * k for tj, k in stats["kept"].items())
+    assert 0 < kept_states <= SMALL_MOVE["chi_target"]
+    D, chi_u1, dd_u1 = _expanded_u1(legs, vals)
+    w = SimpleNamespace(chi=chi_u1, dd=dd_u1)
+    mv = u1.ctm_left_move(w, D, D["a"], kept_states)
+    assert sum(mv["proj"]["kept"].values()) == kept_states
+    tol = 1e-11 if prec == "f64" else 5e-5
+    # spectrum
+    ref = np.sort(np.concatenate([s for _, s in sorted(mv["proj"]["svals"].items())]))[::-1]
+    got = _spectrum_states(env.singular_values(), stats)
+    n = min(len(got), len(ref))
+    assert np.max(np.abs(got[:n] - ref[:n])) <= tol * ref[0]
+    # projector on the cut, in the oracle's fused (chi, D^2) order
+    P, Pt = env.projectors()
+    Pd, Ptd = _dense_u1(P), _dense_u1(Pt)
+    nX, nD = Pd.shape[0], Pd.shape[1]
+    Pi = np.einsum("xdk,kye->xdye", Pd, Ptd).reshape(nX * nD, nX * nD)
+    _, perm = u1._fat(w, "diff")
+    err_pi = rel(Pi[np.ix_(perm, perm)], mv["Pi"])
+    # left column
+    Lg = u1.left_column(_dense_u1(env.get(0)), _dense_u1(env.get(7)), _dense_u1(env.get(3)))
+    err_l = rel(Lg, mv["L"])
+    print(f"  kept states {kept_states}, Pi rel err {err_pi:.3e}, left column rel err {err_l:.3e}")
+    assert err_pi <= tol and err_l <= tol
+
+
+def test_cfg3_move_reduced_vs_u1_expanded():
+    """Full SU(2) workload (FP32): the reduced move against the U(1) move on the
+    library's S^z expansion of the same tensors, truncated to the same number
+    of states: spectra and the gauge-invariant left column."""
+    from oracle import u1
+    c = config(3)
+    legs = _env_legs(c["chi"], c["dd"])
+    vals = su2_values(legs, c["seed"])
+    env, dev = _su2_env(legs, vals, "f32")
+    print("cfg3 su2 move", flush=True)
+    stats = env.move(dev["a"], c["chi_target"], prec="f32")
+    kept_states = sum((tj + 1) * k for tj, k in stats["kept"].items())
+    assert 0 < kept_states <= c["chi_target"]
+    U = {n: t.to_u1() for n, t in dev.items()}
+    envu = st.CtmEnv([U[k] for k in ("C1", "C2", "C3", "C4")], [U[k] for k in ("T1", "T2", "T3", "T4")])
+    print("cfg3 u1-expanded move", flush=True)
+    stu = envu.move(U["a"], kept_states, prec="f32")
+    assert sum(stu["kept"].values()) == kept_states
+    got = _spectrum_states(env.singular_values(), stats)
+    ref = np.sort(envu.singular_values())[::-1]
+    n = min(len(got), len(ref))
+    err_s = np.max(np.abs(got[:n] - ref[:n])) / ref[0]
+    Lg = u1.left_column(_dense_u1(env.get(0)), _dense_u1(env.get(7)), _dense_u1(env.get(3)))
+    Lu = u1.left_column(to_dense(envu.get(0)), to_dense(envu.get(7)), to_dense(envu.get(3)))
+    err_l = rel(Lg, Lu)
+    print(f"cfg3 move: kept states {kept_states}, spectrum err {err_s:.3e}, left column rel diff {err_l:.3e}; "
+          f"reduced flops {stats['flops_corners'] + stats['flops_halves'] + stats['flops_renorm']:.3e}, "
+          f"expanded {stu['flops_corners'] + stu['flops_halves'] + stu['flops_renorm']:.3e}")
+    assert err_s <= 1e-5 and err_l <= 5e-5
