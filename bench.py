@@ -213,10 +213,11 @@ def bench_batched(args):
 
 
 def bench_su2(args):
-    """SU(2) workload: the four enlarged corners and the two halves of a left
-    move on reduced tensors (recoupling scalars in the gather), against the
-    same contractions on the U(1)-expanded (S^z) tensors through the same
-    kernels.  a is a random invariant tensor with the double layer's legs."""
+    """SU(2) workload: one full left move on reduced tensors (recoupling
+    scalars in the gathers, projectors per total spin), against the same move
+    on the U(1)-expanded (S^z) tensors through the same kernels, truncated to
+    the same number of states.  a = A A* is the double layer of a seeded
+    SU(2) site tensor (physical spin 1/2)."""
     import torch
     import paper_1808_10804_amd as st
     from synth import config, draw, TENSOR_INDEX
@@ -228,65 +229,77 @@ def bench_su2(args):
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
     legs = {"T1": [(chi, 1), (dd, -1), (chi, -1)], "T2": [(chi, 1), (dd, 1), (chi, -1)],
-            "T3": [(chi, 1), (dd, 1), (chi, -1)], "T4": [(chi, 1), (dd, -1), (chi, -1)],
-            "a": [(dd, 1), (dd, 1), (dd, -1), (dd, -1)]}
+            "T3": [(chi, 1), (dd, 1), (chi, -1)], "T4": [(chi, 1), (dd, -1), (chi, -1)]}
     for n in ("C1", "C2", "C3", "C4"):
         legs[n] = [(chi, 1), (chi, -1)]
     R = {}
     for n, l in legs.items():
         R[n] = st.Tensor.create(l, dtype=dtype, group="su2", stream=stream)
         R[n].upload(draw((c["seed"], TENSOR_INDEX[n]), R[n].nnz), stream=stream)
+    v = c["virt"]
+    A = st.Tensor.create([(c["phys"], 1), (v, 1), (v, 1), (v, -1), (v, -1)], dtype=dtype, group="su2", stream=stream)
+    A.upload(draw((c["seed"], TENSOR_INDEX["A"]), A.nnz), stream=stream)
+    R["a"] = st.double_layer(A, stream=stream)
     U = {n: t.to_u1(stream=stream) for n, t in R.items()}
 
-    def step(T):
-        k = [st.enlarged_corner(w, T["C%d" % w], T[ta], T[tb], T["a"], prec=prec, stream=stream)
-             for w, ta, tb in ((1, "T1", "T4"), (2, "T1", "T2"), (3, "T3", "T2"), (4, "T3", "T4"))]
-        hu = st.contract(k[0][0], k[1][0], [0, 2], [0, 2], prec=prec, stream=stream)
-        hd = st.contract(k[3][0], k[2][0], [0, 3], [0, 2], prec=prec, stream=stream)
-        return k, hu, hd
+    def runner(T, chi_states):
+        env = st.CtmEnv([T[k] for k in ("C1", "C2", "C3", "C4")], [T[k] for k in ("T1", "T2", "T3", "T4")])
 
-    def flops(T):
-        k, hu, hd = step(T)
-        fl = sum(x[1]["useful_flops"] for x in k)
-        for A, B, la, lb in ((k[0][0], k[1][0], [0, 2], [0, 2]), (k[3][0], k[2][0], [0, 3], [0, 2])):
-            fl += st.plan_info(A, B, la, lb)[0]["useful_flops"]
-        return fl
+        def step(stats=False):
+            env.set(0, T["C1"])
+            env.set(3, T["C4"])
+            env.set(7, T["T4"])
+            return env.move(T["a"], chi_states, prec=prec, stats=stats, stream=stream)
+        return step
 
-    def timed(T):
+    def timed(step):
         for _ in range(args.warmup):
-            step(T)
+            step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(T)
+            step()
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / args.steps
 
-    ms_r, ms_u = timed(R), timed(U)
-    fl_r, fl_u = flops(R), flops(U)
+    step_r = runner(R, c["chi_target"])
+    ms_r = timed(step_r)
+    sr = step_r(stats=True)
+    kept_states = sum((tj + 1) * k for tj, k in sr["kept"].items())
+    step_u = runner(U, kept_states)
+    ms_u = timed(step_u)
+    su = step_u(stats=True)
+    fl = lambda x: x["flops_corners"] + x["flops_halves"] + x["flops_renorm"]
     st.profile_begin()
     for _ in range(args.steps):
-        step(R)
+        step_r()
     torch.cuda.synchronize()
     kst = st.profile_end()
     dom = max(kst, key=lambda k: k["ms"])
     avg = dom["ms"] / dom["launches"]
-    roof = None
     if dom["name"].startswith("gemm"):
         ach = dom["useful_flops"] / dom["launches"] / (avg * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                "frac": ach / PEAK_TFLOPS[prec], "traffic": None, "kernel": dom["name"], "avg_launch_ms": avg}
+                "frac": ach / PEAK_TFLOPS[prec]}
+    else:
+        ach = dom["bytes"] / dom["launches"] / (avg * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+    roof.update({"traffic": traffic_for(dom["name"], c["name"]), "kernel": dom["name"], "avg_launch_ms": avg,
+                 "launches_per_step": dom["launches"] / args.steps})
+    phases = ("ms_corners", "ms_halves", "ms_proj", "ms_renorm", "ms_total")
     out = {
-        "metric": "useful GFLOP/s of the SU(2) reduced corners and halves of one left move",
-        "value": fl_r / (ms_r * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "metric": "useful GFLOP/s per CTM move (SU(2) reduced left move, sector GEMMs on MFMA)",
+        "value": fl(sr) / (ms_r * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_r, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": prec, "data": "synthetic (seeded Gaussian reduced blocks)",
         "config": {"workload": c["name"], "virtual": c["virt"], "chi_multiplets": chi, "dd_multiplets": dd,
-                   "chi_total": 100, "steps_timed": "4 enlarged corners + 2 halves"},
+                   "chi_states": c["chi_target"], "parallelism": "single GPU"},
         "roofline": roof,
-        "reduced": {"ms": ms_r, "useful_flops": fl_r},
-        "u1_expanded": {"ms": ms_u, "useful_flops": fl_u, "gflops": fl_u / (ms_u * 1e-3) / 1e9},
-        "speedup_vs_u1_expanded": ms_u / ms_r, "flop_ratio_expanded_over_reduced": fl_u / fl_r,
+        "reduced": {"ms": ms_r, "useful_flops": fl(sr), "phase_ms": {k: sr[k] for k in phases},
+                    "kept_multiplets": sr["kept"], "kept_states": kept_states},
+        "u1_expanded": {"ms": ms_u, "useful_flops": fl(su), "gflops": fl(su) / (ms_u * 1e-3) / 1e9,
+                        "phase_ms": {k: su[k] for k in phases}},
+        "speedup_vs_u1_expanded": ms_u / ms_r, "flop_ratio_expanded_over_reduced": fl(su) / fl(sr),
         "kernels": sorted(kst, key=lambda k: -k["ms"])[:6],
     }
     print(json.dumps(out))

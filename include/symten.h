@@ -28,10 +28,9 @@
  *    spins 2j (0..64) and an SU(2) tensor's flux must be 0 (Sec. 2: no
  *    quantum-number shift inside a tensor), else SYMTEN_E_SYM.
  *  - SU(2) sector dims are multiplet counts (reduced dims); a multiplet of
- *    spin j holds 2j+1 states.  The SU(2) path covers tensors and
- *    contractions (symten_contract, symten_plan_info, symten_enlarged_corner);
- *    the double layer, the batched corners and ctm_move take U(1) only
- *    (SYMTEN_E_UNSUPPORTED otherwise).
+ *    spin j holds 2j+1 states.  Every entry point takes both groups except
+ *    the batched corners (U(1) only, SYMTEN_E_UNSUPPORTED otherwise); all
+ *    operands of one call must share the group (SYMTEN_E_SYM otherwise).
  *  - A leg's sectors are given as parallel arrays (label, reduced dim); the
  *    library sorts them by label ascending, which fixes the state order.
  *  - Canonical block order is lexicographic in the labels, leg 0 slowest.
@@ -195,9 +194,16 @@ int symten_plan_info(symten_t A, symten_t B, int ncon, const int* legsA,
 /* ---- double layer (Sec. 3.2: rank-4 double-layer tensor) -------------- */
 
 /* a[L,U,R,D] = sum_s A[s,l,u,r,d] A[s,l',u',r',d'] (A real) for a rank-5 A
- * with legs (physical in, l in, u in, r out, d out); each (ket, bra) pair
- * of virtual legs becomes one leg of charge q_ket - q_bra whose states are
- * ordered by that charge, then q_ket, then (i_ket, i_bra) row-major.
+ * with legs (physical in, l in, u in, r out, d out).
+ * U(1): each (ket, bra) pair of virtual legs becomes one leg of charge
+ * q_ket - q_bra whose states are ordered by that charge, then q_ket, then
+ * (i_ket, i_bra) row-major.
+ * SU(2): each (ket, bra) pair becomes one multiplet leg: for every spin pair
+ * (j_ket, j_bra) in lexicographic order and every J in j_ket x j_bra,
+ * n_ket * n_bra multiplets of spin J, row-major in (ket, bra) multiplet; the
+ * fusion map is the unitary whose blocks are sqrt((2J+1)/(2j_ket+1)) times
+ * the Clebsch-Gordan basis tensor of the legs (ket dual, bra dual, fused),
+ * the bra legs running opposite to the ket legs.  Synchronises `stream`.
  * Output dtype = A's dtype, flux 0.                                         */
 int symten_double_layer(symten_t* a_out, symten_t A, void* stream);
 
@@ -232,16 +238,17 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* C,
 
 typedef struct {
     int nsec;                        /* sectors of the new chi leg         */
-    int charge[CTM_MAX_SECTORS];
-    int kept[CTM_MAX_SECTORS];
+    int charge[CTM_MAX_SECTORS];     /* U(1) charge, or SU(2) spin 2J      */
+    int kept[CTM_MAX_SECTORS];       /* kept values (SU(2): multiplets)    */
     int n_sv_sectors;                /* sectors that had singular values   */
     int sv_charge[CTM_MAX_SECTORS];
     int sv_count[CTM_MAX_SECTORS];
-    double trunc_err;                /* sum discarded s^2 / sum s^2        */
+    double trunc_err;                /* sum discarded s^2 / sum s^2, each
+                                        SU(2) value counted 2J+1 times     */
     double gap;                      /* (s_last_kept - s_first_dropped)/s_max */
     double s_max;
     int64_t flops_corners, flops_halves, flops_renorm; /* useful flops     */
-    int64_t flops_proj;              /* FP64 flops of M = R_u R_d^T        */
+    int64_t flops_proj;              /* FP64 flops of Y = H_u^T H_d        */
     double ms_corners, ms_halves, ms_proj, ms_renorm, ms_total;
 } ctm_move_stats;
 
@@ -253,23 +260,32 @@ void ctm_env_destroy(ctm_env_t env);
  * (sharing the storage) that the caller releases with symten_destroy.      */
 int ctm_env_get(ctm_env_t env, int k, symten_t* t);
 
-/* One CTM move (only CTM_LEFT): four enlarged corners, halves
- * H_u = C~1 C~2 and H_d = C~4 C~3, per fused charge FP64 QR of H_u^T, H_d^T,
- * M = R_u R_d^T, SVD M = U S V^T, global top-chi truncation (ties: charge,
- * then index ascending; s <= 1e-14 s_max dropped), projectors
- * P = R_d^T V S^-1/2 and P~ = S^-1/2 U^T R_u (largest-magnitude entry of
- * every P~ row made positive), then C1' = (C1 T1) P, T4' = P~ (T4 a) P,
+/* One CTM move (only CTM_LEFT; Sec. 3, the projector scheme it cites):
+ * four enlarged corners, halves H_u = C~1 C~2 and H_d = C~4 C~3, per fused
+ * sector of the left cut the singular triplets of M = R_u R_d^T (QR
+ * H_u^T = Q_u R_u, H_d^T = Q_d R_d; taken from Y = H_u^T H_d, which has the
+ * same singular values, with V_Y = Q_d V and U_Y = Q_u U), global truncation
+ * to chi states (ties: sector, then index ascending; s <= 1e-14 s_max
+ * dropped), projectors P = R_d^T V S^-1/2 = H_d V_Y S^-1/2 and
+ * P~ = S^-1/2 U^T R_u = S^-1/2 U_Y^T H_u^T (largest-magnitude entry of every
+ * P~ row made positive), then C1' = (C1 T1) P, T4' = P~ (T4 a) P,
  * C4' = P~ (C4 T3), each scaled to unit Frobenius norm in FP64.  `chi`
- * counts states.  Synchronises `stream` once (truncation needs the singular
- * values on the host) and again at the end when `st` is not NULL.          */
+ * counts states.  U(1): sectors are fused charges.  SU(2): the two legs of
+ * each side of the cut are fused by a unitary isometry into one multiplet
+ * leg, sectors are its total spins J, each kept value is a multiplet of
+ * 2J+1 states and multiplets are kept whole (descending, stopping at the
+ * first that does not fit).  Synchronises `stream` once (truncation needs
+ * the singular values on the host) and again at the end when `st` is not
+ * NULL.                                                                     */
 int ctm_move(ctm_env_t env, symten_t a, int dir, int chi, int prec,
              ctm_move_stats* st, void* stream);
 
 /* Singular values of the last move, per sector in charge order, each
  * sector descending.  cap = capacity of `s`; *n receives the count.        */
 int ctm_move_singular_values(ctm_env_t env, double* s, int64_t cap, int64_t* n);
-/* Projectors of the last move as tensors (new handles, FP64, released with
- * symten_destroy): P[chi out, D2 in, k in] and P~[k out, chi in, D2 out].   */
+/* Projectors of the last move as tensors (new handles, released with
+ * symten_destroy): P[chi out, D2 in, k in] and P~[k out, chi in, D2 out];
+ * FP64 for U(1), the move's storage type for SU(2).                         */
 int ctm_move_projectors(ctm_env_t env, symten_t* P, symten_t* Pt);
 
 /* Replace tensor k (0..3 = C1..C4, 4..7 = T1..T4) of the environment; the

@@ -293,3 +293,47 @@ def fuse(la, lb, direction):
             for J in range(abs(ta - tb), ta + tb + 1, 2):
                 sec[J] = sec.get(J, 0) + na * nb
     return Leg(sec, direction)
+
+
+def fusion_isometry(la, lb, fdir):
+    """Unitary F[a, b, f] fusing legs la, lb into one multiplet leg f (dir
+    fdir): f's spin-J multiplets are the pairs (multiplet of la with spin ja,
+    multiplet of lb with spin jb) with J in ja x jb, ordered by (ja, jb), then
+    row-major (i_a, i_b).  Its reduced block (ja, jb, J) is
+    sqrt((2J+1)/(2K+1)) times the placement of those pairs, K the root of the
+    block's tree.  Returns (legs, reduced values)."""
+    nJ, base = {}, {}
+    for ja in la.tjs:
+        for jb in lb.tjs:
+            for J in range(abs(ja - jb), ja + jb + 1, 2):
+                base[(ja, jb, J)] = nJ.get(J, 0)
+                nJ[J] = nJ.get(J, 0) + la.n(ja) * lb.n(jb)
+    lf = Leg(nJ, fdir)
+    legs = [la, lb, lf]
+    vals = []
+    for (ja, jb, J), tree in blocks(legs):
+        m = np.zeros((la.n(ja), lb.n(jb), lf.n(J)))
+        w = np.sqrt((J + 1) / (tree[-1] + 1))
+        for x in range(la.n(ja)):
+            for y in range(lb.n(jb)):
+                m[x, y, base[(ja, jb, J)] + x * lb.n(jb) + y] = w
+        vals.append(m.ravel())
+    return legs, np.concatenate(vals)
+
+
+def double_layer(A_legs, A_values):
+    """a[L, U, R, D] = sum_s A[s, l, u, r, d] A*[s, l', u', r', d'] with each
+    (ket, bra) pair fused into one multiplet leg (Sec. 3.2's rank-4 double
+    layer).  A* is A (real) with every leg reversed, so the bra leg of a bond
+    runs opposite to its ket leg; the fusion tensor of a bond with ket leg v
+    has legs (v reversed, v, fused with v's direction).  Returns (a legs,
+    reduced values, dense a in SU(2) state order)."""
+    A = expand(A_legs, A_values)
+    a8 = np.einsum("sabcd,sefgh->aebfcgdh", A, A)      # [l, l', u, u', r, r', d, d']
+    out, a_legs = a8, []
+    for v in A_legs[1:]:
+        Fl, Fv = fusion_isometry(Leg(v.sectors(), -v.dir), Leg(v.sectors(), v.dir), v.dir)
+        F = expand(Fl, Fv)                             # [ket, bra, fused]
+        out = np.tensordot(out, F, axes=([0, 1], [0, 1]))   # consumes the leading pair, appends fused
+        a_legs.append(Fl[2])
+    return a_legs, reduce(a_legs, out), out

@@ -230,6 +230,17 @@ void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_
 void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw);
 
 TensorPtr double_layer(const Tensor& A, hipStream_t stream);
+// SU(2) double layer (S^z components, U(1) double layer, per-leg change to
+// the fused multiplet basis, reduction).
+TensorPtr double_layer_su2(const Tensor& A, hipStream_t stream);
+// Fused (ket, bra) states of a U(1) double-layer leg: charge q_ket - q_bra,
+// ordered by that charge, then q_ket, then (i_ket, i_bra); ket/bra are state
+// indices of the leg (charge-major order).
+void double_layer_states(const Leg& v, std::vector<int>& ket, std::vector<int>& bra, Leg& fused);
+// SU(2) tensor with legs `legs` from the U(1) tensor of its S^z components
+// (the inverse of su2_to_u1 on invariant tensors): projection of every block
+// onto its basis tensor.
+TensorPtr u1_to_su2(const Tensor& U, const std::vector<Leg>& legs, hipStream_t stream);
 
 // GEMM tile shapes and the autotuner that picks one per launch
 constexpr int kNumTileCfg = 5;

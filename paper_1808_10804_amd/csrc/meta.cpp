@@ -1056,9 +1056,38 @@ std::vector<TensorPtr> run_contractions_batched(const std::vector<std::shared_pt
 }
 
 // ------------------------------------------------------------ double layer
+void double_layer_states(const Leg& v, std::vector<int>& ket, std::vector<int>& bra, Leg& fused) {
+    std::vector<int> qs(v.size());
+    int o = 0;
+    for (size_t s = 0; s < v.q.size(); ++s) {
+        for (int i = 0; i < v.d[s]; ++i) qs[o + i] = v.q[s];
+        o += v.d[s];
+    }
+    struct E { int Q, qk, ik, ib; };
+    std::vector<E> es;
+    for (int ik = 0; ik < v.size(); ++ik)
+        for (int ib = 0; ib < v.size(); ++ib) es.push_back({qs[ik] - qs[ib], qs[ik], ik, ib});
+    std::sort(es.begin(), es.end(), [](const E& x, const E& y) {
+        if (x.Q != y.Q) return x.Q < y.Q;
+        if (x.qk != y.qk) return x.qk < y.qk;
+        if (x.ik != y.ik) return x.ik < y.ik;
+        return x.ib < y.ib;
+    });
+    ket.clear();
+    bra.clear();
+    fused = Leg();
+    fused.dir = v.dir;
+    for (auto& e : es) {
+        ket.push_back(e.ik);
+        bra.push_back(e.ib);
+        if (fused.q.empty() || fused.q.back() != e.Q) { fused.q.push_back(e.Q); fused.d.push_back(0); }
+        fused.d.back() += 1;
+    }
+}
+
 TensorPtr double_layer(const Tensor& A, hipStream_t stream) {
+    if (A.group == SYMTEN_SU2) return double_layer_su2(A, stream);
     check_device_tensor(A, "double_layer");
-    if (A.group != SYMTEN_U1) fail(SYMTEN_E_UNSUPPORTED, "double_layer: only U(1)");
     if (A.rank() != 5) fail(SYMTEN_E_INVAL, "double_layer: A must have rank 5 (phys, l, u, r, d)");
     const bool f64 = A.dtype == SYMTEN_F64;
     // fused legs: Q = q_ket - q_bra, states ordered by Q, q_ket, (i_ket, i_bra)
@@ -1068,32 +1097,8 @@ TensorPtr double_layer(const Tensor& A, hipStream_t stream) {
     out->dtype = A.dtype;
     std::vector<std::vector<int>> ket_of(4), bra_of(4);
     for (int l = 0; l < 4; ++l) {
-        const Leg& v = A.legs[l + 1];
-        std::vector<int> qs(v.size()), off(v.q.size());
-        int o = 0;
-        for (size_t s = 0; s < v.q.size(); ++s) {
-            off[s] = o;
-            for (int i = 0; i < v.d[s]; ++i) qs[o + i] = v.q[s];
-            o += v.d[s];
-        }
-        struct E { int Q, qk, ik, ib; };
-        std::vector<E> es;
-        for (int ik = 0; ik < v.size(); ++ik)
-            for (int ib = 0; ib < v.size(); ++ib) es.push_back({qs[ik] - qs[ib], qs[ik], ik, ib});
-        std::sort(es.begin(), es.end(), [](const E& x, const E& y) {
-            if (x.Q != y.Q) return x.Q < y.Q;
-            if (x.qk != y.qk) return x.qk < y.qk;
-            if (x.ik != y.ik) return x.ik < y.ik;
-            return x.ib < y.ib;
-        });
         Leg F;
-        F.dir = v.dir;
-        for (auto& e : es) {
-            ket_of[l].push_back(e.ik);
-            bra_of[l].push_back(e.ib);
-            if (F.q.empty() || F.q.back() != e.Q) { F.q.push_back(e.Q); F.d.push_back(0); }
-            F.d.back() += 1;
-        }
+        double_layer_states(A.legs[l + 1], ket_of[l], bra_of[l], F);
         out->legs.push_back(F);
     }
     const int64_t total = enumerate_blocks(*out);

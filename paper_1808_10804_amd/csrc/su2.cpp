@@ -611,4 +611,215 @@ TensorPtr su2_to_u1(const Tensor& in, hipStream_t stream) {
     return out;
 }
 
+// ------------------------------------------------- S^z basis helpers
+namespace {
+// S^z (U(1)) leg of an SU(2) leg: charges 2m; inside a charge the states run
+// over spins ascending, then multiplets.  pos[(tj, m)] = first state of spin
+// tj inside charge m; state_of[i] = (tj, multiplet, m) of U(1) state i.
+struct SzLeg {
+    Leg u1;
+    std::map<std::pair<int, int>, int> pos;
+    std::vector<std::array<int, 3>> state_of;
+};
+SzLeg sz_leg(const Leg& L) {
+    SzLeg r;
+    int tmax = 0;
+    for (int t : L.q) tmax = std::max(tmax, t);
+    r.u1.dir = L.dir;
+    for (int m = -tmax; m <= tmax; ++m) {
+        int d = 0;
+        for (size_t i = 0; i < L.q.size(); ++i) {
+            const int t = L.q[i];
+            if (t >= std::abs(m) && (t - m) % 2 == 0) {
+                r.pos[{t, m}] = d;
+                for (int a = 0; a < L.d[i]; ++a) r.state_of.push_back({t, a, m});
+                d += L.d[i];
+            }
+        }
+        if (d > 0) { r.u1.q.push_back(m); r.u1.d.push_back(d); }
+    }
+    return r;
+}
+}  // namespace
+
+TensorPtr u1_to_su2(const Tensor& U, const std::vector<Leg>& legs, hipStream_t stream) {
+    if (U.group != SYMTEN_U1) fail(SYMTEN_E_INVAL, "u1_to_su2: tensor is not U(1)");
+    check_device_tensor(U, "u1_to_su2");
+    const int R = (int)legs.size();
+    if (U.rank() != R) fail(SYMTEN_E_INVAL, "u1_to_su2: rank mismatch");
+    std::vector<SzLeg> sz;
+    for (int l = 0; l < R; ++l) {
+        sz.push_back(sz_leg(legs[l]));
+        if (sz[l].u1.dir != U.legs[l].dir || !sz[l].u1.same_sectors(U.legs[l]))
+            fail(SYMTEN_E_LEGS, "u1_to_su2: U(1) legs are not the S^z legs of the SU(2) legs");
+    }
+    auto out = std::make_shared<Tensor>();
+    out->group = SYMTEN_SU2;
+    out->flux = 0;
+    out->dtype = U.dtype;
+    out->legs = legs;
+    out->elems = enumerate_blocks_su2(*out);
+    out->buf = device_alloc(std::max<int64_t>(out->elems, 1) * out->esize());
+    out->meta_only = false;
+    launch_fill_zero(out->buf->ptr, ((std::max<int64_t>(out->elems, 1) * out->esize() + 3) / 4) * 4, stream);
+    // m[a..] = sum_m c[m] t[(a, m)..] / <c, c>: one accumulating gather per
+    // non-zero basis-tensor entry; layer t holds the t-th entry of every block
+    std::vector<std::vector<CopyTask>> layers;
+    for (const Block& b : out->blocks) {
+        if (b.size == 0) continue;
+        const DenseT& c = cgc_cached(out->legs, b.q, b.tree);
+        double nrm = 0.0;
+        for (double v : c.v) nrm += v * v;
+        std::vector<int> idx(R, 0);
+        int layer = 0;
+        for (size_t lin = 0; lin < c.v.size(); ++lin) {
+            if (c.v[lin] != 0.0) {
+                std::vector<int> qs(R);
+                for (int l = 0; l < R; ++l) qs[l] = -b.q[l] + 2 * idx[l];
+                auto it = U.index.find(qs);
+                if (it != U.index.end()) {
+                    const Block& ub = U.blocks[it->second];
+                    int64_t soff = ub.offset;
+                    for (int l = 0; l < R; ++l) soff += (int64_t)sz[l].pos.at({b.q[l], qs[l]}) * ub.stride[l];
+                    if ((int)layers.size() <= layer) layers.resize(layer + 1);
+                    layers[layer++].push_back(
+                        make_copy_task(0, soff, 1, b.offset, b.shape, ub.stride, b.stride, c.v[lin] / nrm));
+                }
+            }
+            for (int l = R - 1; l >= 0; --l) {
+                if (++idx[l] < c.shape[l]) break;
+                idx[l] = 0;
+            }
+        }
+    }
+    const bool f64 = U.dtype == SYMTEN_F64;
+    std::vector<BufferPtr> keep;
+    for (auto& tasks : layers) {
+        if (tasks.empty()) continue;
+        validate_tasks(tasks, {U.elems, out->elems});
+        std::vector<int64_t> prefix;
+        copy_prefix(tasks, prefix);
+        BufferPtr dt, dp;
+        upload_sync(dt, tasks.data(), tasks.size() * sizeof(CopyTask));
+        upload_sync(dp, prefix.data(), prefix.size() * sizeof(int64_t));
+        copy_launch_arg((const CopyTask*)dt->ptr, (const int64_t*)dp->ptr, (int)tasks.size(), prefix.back(),
+                        {U.data(), out->data()}, f64, /*accumulate*/ 4, stream);
+        keep.push_back(dt);
+        keep.push_back(dp);
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    return out;
+}
+
+// ------------------------------------------------------------ double layer
+// a = sum_sigma A A* with the (ket, bra) legs of every bond fused into one
+// multiplet leg (Sec. 3.2: rank-4 double-layer tensors).  The fused leg of a
+// bond with multiplets {j: n} holds, for every pair (j_ket, j_bra) in
+// lexicographic order and every J in j_ket x j_bra, n_ket * n_bra multiplets
+// of spin J, row-major in (ket multiplet, bra multiplet).  The fusion map is
+// the unitary F[ket, bra, fused] whose blocks are w * c_F with the
+// Clebsch-Gordan basis tensor c_F of legs (ket dual, bra dual, fused) and
+// w = sqrt((2J+1)/(2j_ket+1)); the bra legs belong to A* and run opposite to
+// the ket legs, which is where the conjugate representation enters.
+//
+// Computed in the S^z basis: the U(1) double layer of A's S^z components, a
+// change of basis on each fused leg (a U(1) contraction with F written as a
+// charge-diagonal matrix), then the projection onto a's multiplet blocks.
+// This runs once per site tensor, not per move.
+TensorPtr double_layer_su2(const Tensor& A, hipStream_t s) {
+    check_device_tensor(A, "double_layer");
+    if (A.rank() != 5) fail(SYMTEN_E_INVAL, "double_layer: A must have rank 5 (phys, l, u, r, d)");
+    const bool f64 = A.dtype == SYMTEN_F64;
+    const int prec = f64 ? SYMTEN_PREC_F64 : SYMTEN_PREC_F32;
+    TensorPtr Au = su2_to_u1(A, s);
+    TensorPtr au = double_layer(*Au, s);
+    std::vector<Leg> fused(4);
+    std::vector<TensorPtr> W(4);
+    for (int x = 0; x < 4; ++x) {
+        const Leg& v = A.legs[x + 1];
+        // multiplets of the fused leg and the first multiplet of each (j_ket, j_bra) pair
+        std::map<int, int> nJ;
+        std::map<std::array<int, 3>, int> base;
+        for (size_t k = 0; k < v.q.size(); ++k)
+            for (size_t b = 0; b < v.q.size(); ++b)
+                for (int J = std::abs(v.q[k] - v.q[b]); J <= v.q[k] + v.q[b]; J += 2) {
+                    base[{v.q[k], v.q[b], J}] = nJ[J];
+                    nJ[J] += v.d[k] * v.d[b];
+                }
+        Leg F;
+        F.dir = v.dir;
+        for (auto& kv : nJ) { F.q.push_back(kv.first); F.d.push_back(kv.second); }
+        fused[x] = F;
+        const SzLeg vs = sz_leg(v), fs = sz_leg(F);
+        std::vector<int> ket, bra;
+        Leg dl;
+        double_layer_states(vs.u1, ket, bra, dl);
+        if (dl.q != au->legs[x].q || dl.d != au->legs[x].d) fail(SYMTEN_E_INVAL, "internal: double-layer leg");
+        // W[fused U(1) state, S^z state of F] (U(1) tensor, charge diagonal)
+        auto w = std::make_shared<Tensor>();
+        w->group = SYMTEN_U1;
+        w->flux = 0;
+        w->dtype = A.dtype;
+        Leg rows = dl;
+        rows.dir = -v.dir;
+        w->legs = {rows, fs.u1};
+        w->elems = enumerate_blocks(*w);
+        std::vector<double> host((size_t)std::max<int64_t>(w->elems, 1), 0.0);
+        std::vector<Leg> flegs(3);
+        flegs[0].dir = -v.dir;   // ket dual
+        flegs[1].dir = v.dir;    // bra dual (the bra leg of A* runs opposite)
+        flegs[2].dir = v.dir;    // fused
+        std::vector<int> row_in_sector(ket.size());
+        {
+            std::map<int, int> cnt;
+            int o = 0;
+            for (size_t r = 0; r < ket.size(); ++r) {
+                const int Q = vs.state_of[ket[r]][2] - vs.state_of[bra[r]][2];
+                row_in_sector[r] = cnt[Q]++;
+                (void)o;
+            }
+        }
+        for (size_t r = 0; r < ket.size(); ++r) {
+            const auto& K = vs.state_of[ket[r]];
+            const auto& B = vs.state_of[bra[r]];
+            const int Q = K[2] - B[2];
+            const int jk = K[0], jb = B[0];
+            for (int J = std::abs(jk - jb); J <= jk + jb; J += 2) {
+                if (std::abs(Q) > J) continue;
+                const DenseT& c = cgc_cached(flegs, {jk, jb, J}, {jk});
+                const double val = std::sqrt((J + 1.0) / (jk + 1.0)) *
+                                   c.v[((int64_t)((K[2] + jk) / 2) * (jb + 1) + (B[2] + jb) / 2) * (J + 1) + (Q + J) / 2];
+                if (val == 0.0) continue;
+                const int f = base.at({jk, jb, J}) + K[1] * v.dim_of(jb) + B[1];
+                auto it = w->index.find(std::vector<int>{Q, Q});
+                if (it == w->index.end()) fail(SYMTEN_E_INVAL, "internal: fusion block");
+                const Block& wb = w->blocks[it->second];
+                const int col = fs.pos.at({J, Q}) + f;
+                host[wb.offset + (int64_t)row_in_sector[r] * wb.stride[0] + (int64_t)col * wb.stride[1]] = val;
+            }
+        }
+        w->buf = device_alloc(std::max<int64_t>(w->elems, 1) * w->esize());
+        w->meta_only = false;
+        if (f64) {
+            HIPCHK(hipMemcpy(w->buf->ptr, host.data(), w->elems * 8, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> h32(host.begin(), host.end());
+            HIPCHK(hipMemcpy(w->buf->ptr, h32.data(), w->elems * 4, hipMemcpyHostToDevice));
+        }
+        W[x] = w;
+    }
+    // change of basis on the four legs (each contraction rotates the leg order)
+    TensorPtr cur = au;
+    std::vector<std::shared_ptr<ContractPlan>> keep;
+    for (int x = 0; x < 4; ++x) {
+        const int la = 0, lb = 0;
+        auto p = plan_contraction(*cur, *W[x], 1, &la, &lb, nullptr, prec);
+        keep.push_back(p);
+        cur = run_contraction(*p, *cur, *W[x], s);
+    }
+    TensorPtr a = u1_to_su2(*cur, fused, s);
+    HIPCHK(hipStreamSynchronize(s));
+    return a;
+}
+
 }  // namespace symten

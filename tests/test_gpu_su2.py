@@ -255,3 +255,46 @@ def test_cfg3_move_reduced_vs_u1_expanded():
           f"reduced flops {stats['flops_corners'] + stats['flops_halves'] + stats['flops_renorm']:.3e}, "
           f"expanded {stu['flops_corners'] + stu['flops_halves'] + stu['flops_renorm']:.3e}")
     assert err_s <= 1e-5 and err_l <= 5e-5
+
+
+# ------------------------------------------------------- SU(2) double layer
+def _site_legs(virt):
+    return [({1: 1}, IN), (virt, IN), (virt, IN), (virt, OUT), (virt, OUT)]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_su2_double_layer_vs_oracle(dt):
+    spec = _site_legs({0: 1, 1: 2, 2: 1})
+    L = [su2.Leg(s, d) for s, d in spec]
+    vals = draw((1811, 0), su2.nnz(L))
+    A = st.Tensor.create(spec, dtype=dt, group="su2").upload(vals)
+    print(f"su2 double layer {dt}", flush=True)
+    a = st.double_layer(A)
+    got, La = reduced_full(a)
+    a_legs, ref, _ = su2.double_layer(L, vals)
+    assert [(l.sectors(), l.dir) for l in La] == [(l.sectors(), l.dir) for l in a_legs]
+    err = rel(got, ref)
+    print(f"  rel err {err:.3e}")
+    assert err <= (1e-13 if dt == "f64" else 1e-6)
+
+
+def test_cfg3_double_layer_legs_and_norm():
+    """Full-size SU(2) site tensor: the fused legs are the workload's D^2 leg
+    and the dense norm of a (sum over blocks of (2K+1) |m|^2) equals
+    |sum_s A_s (x) A_s|, computed from the physical Gram matrix of A."""
+    c = config(3)
+    spec = [(c["phys"], IN), (c["virt"], IN), (c["virt"], IN), (c["virt"], OUT), (c["virt"], OUT)]
+    L = [su2.Leg(s, d) for s, d in spec]
+    vals = draw((c["seed"], 0), su2.nnz(L))
+    A = st.Tensor.create(spec, dtype="f64", group="su2").upload(vals)
+    a = st.double_layer(A)
+    assert [(s, d) for s, d in a.legs()] == [(c["dd"], IN), (c["dd"], IN), (c["dd"], OUT), (c["dd"], OUT)]
+    v = a.download()
+    pos, n2 = 0, 0.0
+    for (lab, shp, _, _), tr in zip(a.blocks(), a.trees()):
+        k = int(np.prod(shp))
+        n2 += (tr[-1] + 1) * float(np.sum(v[pos:pos + k] ** 2))
+        pos += k
+    Ad = su2.expand(L, vals).reshape(L[0].size, -1)
+    G = Ad @ Ad.T
+    assert np.isclose(n2, np.sum(G * G), rtol=1e-12)

@@ -157,3 +157,41 @@ def test_fused_double_layer_leg():
     vu = v.u1_leg()
     fu, _ = u1.fuse(vu, vu, +1, +1, IN)
     assert F.u1_leg().sectors() == fu.sectors()
+
+
+@pytest.mark.parametrize("dirs", [(IN, IN, OUT), (OUT, IN, IN), (IN, OUT, OUT), (OUT, OUT, IN), (OUT, IN, OUT)])
+def test_fusion_isometry_is_unitary(dirs):
+    la, lb = su2.Leg({0: 1, 1: 2, 2: 1}, dirs[0]), su2.Leg({1: 1, 2: 2}, dirs[1])
+    legs, v = su2.fusion_isometry(la, lb, dirs[2])
+    F = su2.expand(legs, v).reshape(la.size * lb.size, -1)
+    assert F.shape[0] == F.shape[1]
+    assert np.allclose(F.T @ F, np.eye(F.shape[1]), atol=1e-14)
+    assert np.allclose(F @ F.T, np.eye(F.shape[0]), atol=1e-14)
+
+
+def test_double_layer_su2_pins():
+    """The fused double layer is an invariant tensor (reduce + expand gives it
+    back; a bra leg run in the ket's direction breaks this), the fusion keeps
+    the Frobenius norm, and unfusing gives a PSD (ket) x (bra) matrix with
+    trace |A|^2."""
+    v = {0: 1, 1: 2, 2: 1}
+    A_legs = [su2.Leg({1: 1}, IN), su2.Leg(v, IN), su2.Leg(v, IN), su2.Leg(v, OUT), su2.Leg(v, OUT)]
+    vals = _rand(A_legs, 7)
+    a_legs, ared, ad = su2.double_layer(A_legs, vals)
+    assert [l.dir for l in a_legs] == [IN, IN, OUT, OUT]
+    assert a_legs[0].sectors() == su2.fuse(A_legs[1], A_legs[1], IN).sectors()
+    assert np.allclose(su2.expand(a_legs, ared), ad, atol=1e-13)
+    A = su2.expand(A_legs, vals)
+    a8 = np.einsum("sabcd,sefgh->aebfcgdh", A, A)
+    assert np.isclose(np.linalg.norm(ad), np.linalg.norm(a8))
+    # unfuse with the transposed isometries
+    u = ad
+    for x, vl in enumerate(A_legs[1:]):
+        Fl, Fv = su2.fusion_isometry(su2.Leg(vl.sectors(), -vl.dir), su2.Leg(vl.sectors(), vl.dir), vl.dir)
+        F = su2.expand(Fl, Fv)
+        u = np.tensordot(u, F, axes=([0], [2]))          # fused leg -> (ket, bra), appended
+    n = A_legs[1].size
+    M = u.reshape([n, n] * 4).transpose(0, 2, 4, 6, 1, 3, 5, 7).reshape(n ** 4, n ** 4)
+    assert np.allclose(M, M.T, atol=1e-12)
+    assert np.min(np.linalg.eigvalsh(M)) > -1e-10 * np.max(np.abs(M))
+    assert np.isclose(np.trace(M), np.sum(A * A))
