@@ -112,7 +112,13 @@ struct CopyTask {
     int pad_;
     int64_t xsrc_off[kMaxExtraSrc];
     double xscale[kMaxExtraSrc];
+    // transposing copy (the destination's unit-stride dim is not the
+    // source's): tiles of (1 << lg_out) x (1024 >> lg_out) elements staged
+    // through LDS, read along dim tr_in, written along dim tr_out; -1: direct
+    int tr_in, tr_out, lg_out, pad2_;
 };
+// chunks (workgroups) of a copy task: 1024 elements, or one LDS tile
+int64_t copy_task_chunks(const CopyTask& t);
 
 struct GemmGroup {
     int64_t a_off, b_off, c_off;   // element offsets into their buffers

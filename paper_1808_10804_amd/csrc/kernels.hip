@@ -58,10 +58,34 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
 // accumulation (dst += scale * src) in the source type.
 enum : int { kDstF32 = 0, kDstF64 = 1, kDstBF16 = 2, kDstSplit = 3, kDstAcc = 4 };
 
+// One destination element of the gather: conversion to the destination kind.
+template <typename TS, int DK, typename AT>
+__device__ __forceinline__ void copy_store(void* dstv, int64_t dofs, int64_t lo_off, AT sv, bool have_src) {
+    if constexpr (DK == kDstAcc) {
+        if (have_src) ((TS*)dstv)[dofs] += (TS)sv;
+    } else if constexpr (DK == kDstF64) {
+        ((double*)dstv)[dofs] = (double)sv;
+    } else if constexpr (DK == kDstF32) {
+        ((float*)dstv)[dofs] = (float)sv;
+    } else {
+        const float v = (float)sv;
+        const unsigned short h = f32_to_bf16_rn(v);
+        ((unsigned short*)dstv)[dofs] = h;
+        if constexpr (DK == kDstSplit) ((unsigned short*)dstv)[dofs + lo_off] = f32_to_bf16_rn(v - bf16_to_f32(h));
+    }
+}
+
+// Strided gather over a task list.  Each workgroup takes one chunk of one
+// task: 1024 consecutive elements (direct copies), or one tile of a
+// transposing copy, read along the source's unit-stride dim into LDS and
+// written along the destination's unit-stride dim.  A task may sum several
+// equally strided sources with their scalars (SU(2) tree-sibling blocks).
 template <class Ptrs, typename TS, int DK>
 __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __restrict__ tasks,
                                                             const int64_t* __restrict__ chunk_prefix,
                                                             int ntasks, Ptrs ptrs) {
+    using AT = std::conditional_t<DK == kDstF64, double, TS>;   // arithmetic type
+    __shared__ AT tile[kCopyChunk + 128];
     const int64_t chunk = blockIdx.x;
     int lo = 0, hi = ntasks - 1;
     while (lo < hi) {                       // last task with prefix <= chunk
@@ -69,11 +93,55 @@ __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __re
         if (chunk_prefix[mid] <= chunk) lo = mid; else hi = mid - 1;
     }
     const CopyTask& T = tasks[lo];
-    const int64_t base = (chunk - chunk_prefix[lo]) * kCopyChunk;
+    const int64_t local = chunk - chunk_prefix[lo];
     const TS* __restrict__ src = T.src_buf >= 0 ? (const TS*)ptrs.get(T.src_buf) : nullptr;
     void* dstv = ptrs.get(T.dst_buf);
     const int rank = T.rank;
     const double scale = T.scale;
+    auto gather = [&](int64_t so) -> AT {
+        AT sv = (AT)src[so] * (AT)scale;
+        const int64_t rel = so - T.src_off;
+        for (int t = 0; t < T.nextra; ++t) sv += (AT)src[T.xsrc_off[t] + rel] * (AT)T.xscale[t];
+        return sv;
+    };
+    if (T.tr_in >= 0) {
+        // ---- transposing tile: TO destination-contiguous x TI source-contiguous
+        const int din = T.tr_in, dout = T.tr_out;
+        const int lgo = T.lg_out, lgi = 10 - T.lg_out;
+        const int TO = 1 << lgo, TI = 1 << lgi;
+        const int Din = T.dims[din], Dout = T.dims[dout];
+        const int nto = (Dout + TO - 1) >> lgo, nti = (Din + TI - 1) >> lgi;
+        int64_t r = local;
+        const int to = (int)(r % nto);
+        r /= nto;
+        const int ti = (int)(r % nti);
+        r /= nti;
+        int64_t so = T.src_off, dofs = T.dst_off;
+        for (int k = rank - 1; k >= 0; --k) {
+            if (k == din || k == dout) continue;
+            const int ik = (int)(r % T.dims[k]);
+            r /= T.dims[k];
+            so += (int64_t)ik * T.sstride[k];
+            dofs += (int64_t)ik * T.dstride[k];
+        }
+        const int i0 = ti << lgi, o0 = to << lgo;
+        const int64_t ssi = T.sstride[din], sso = T.sstride[dout];
+        const int64_t dsi = T.dstride[din], dso = T.dstride[dout];
+        for (int e = threadIdx.x; e < kCopyChunk; e += kCopyThreads) {
+            const int ii = e & (TI - 1), oo = e >> lgi;
+            const int gi = i0 + ii, go = o0 + oo;
+            if (gi < Din && go < Dout) tile[oo * (TI + 1) + ii] = gather(so + gi * ssi + go * sso);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kCopyChunk; e += kCopyThreads) {
+            const int oo = e & (TO - 1), ii = e >> lgo;
+            const int gi = i0 + ii, go = o0 + oo;
+            if (gi < Din && go < Dout)
+                copy_store<TS, DK>(dstv, dofs + gi * dsi + go * dso, T.lo_off, tile[oo * (TI + 1) + ii], true);
+        }
+        return;
+    }
+    const int64_t base = local * kCopyChunk;
     for (int e = threadIdx.x; e < kCopyChunk; e += kCopyThreads) {
         const int64_t idx = base + e;
         if (idx >= T.count) break;
@@ -87,26 +155,7 @@ __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __re
             so += (int64_t)ik * T.sstride[k];
             dofs += (int64_t)ik * T.dstride[k];
         }
-        // weighted sum of the sources (one source unless SU(2) trees are combined)
-        using AT = std::conditional_t<DK == kDstF64, double, TS>;   // arithmetic type
-        AT sv = 0;
-        if (src) {
-            sv = (AT)src[so] * (AT)scale;
-            const int64_t rel = so - T.src_off;
-            for (int t = 0; t < T.nextra; ++t) sv += (AT)src[T.xsrc_off[t] + rel] * (AT)T.xscale[t];
-        }
-        if constexpr (DK == kDstAcc) {
-            if (src) ((TS*)dstv)[dofs] += sv;
-        } else if constexpr (DK == kDstF64) {
-            ((double*)dstv)[dofs] = (double)sv;
-        } else if constexpr (DK == kDstF32) {
-            ((float*)dstv)[dofs] = (float)sv;
-        } else {
-            const float v = (float)sv;
-            const unsigned short h = f32_to_bf16_rn(v);
-            ((unsigned short*)dstv)[dofs] = h;
-            if constexpr (DK == kDstSplit) ((unsigned short*)dstv)[dofs + T.lo_off] = f32_to_bf16_rn(v - bf16_to_f32(h));
-        }
+        copy_store<TS, DK>(dstv, dofs, T.lo_off, src ? gather(so) : (AT)0, src != nullptr);
     }
 }
 

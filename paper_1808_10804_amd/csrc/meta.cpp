@@ -226,6 +226,34 @@ static void simplify_task(CopyTask& t) {
         t.sstride[k] = k < m ? ss[k] : 0;
         t.dstride[k] = k < m ? ds[k] : 0;
     }
+    // a copy whose unit-stride destination dim reads with a large source
+    // stride while another dim is unit-stride in the source is transposed
+    // through LDS so that both sides stay coalesced
+    t.tr_in = t.tr_out = -1;
+    t.lg_out = 0;
+    if (t.src_buf >= 0) {
+        int din = -1, dout = -1;
+        for (int k = 0; k < m; ++k) {
+            if (t.sstride[k] == 1) din = k;
+            if (t.dstride[k] == 1) dout = k;
+        }
+        // only when both dims fill a 32 x 32 tile: for smaller dims the idle
+        // part of the tile costs more than the uncoalesced reads save
+        if (din >= 0 && dout >= 0 && din != dout && t.dims[din] >= 32 && t.dims[dout] >= 32) {
+            t.tr_in = din;
+            t.tr_out = dout;
+            t.lg_out = 5;
+        }
+    }
+}
+
+int64_t copy_task_chunks(const CopyTask& t) {
+    if (t.tr_in < 0) return (t.count + 1023) / 1024;
+    const int64_t to = 1 << t.lg_out, ti = 1024 >> t.lg_out;
+    int64_t n = ((t.dims[t.tr_out] + to - 1) / to) * ((t.dims[t.tr_in] + ti - 1) / ti);
+    for (int k = 0; k < t.rank; ++k)
+        if (k != t.tr_in && k != t.tr_out) n *= t.dims[k];
+    return n;
 }
 
 CopyTask make_copy_task(int src_buf, int64_t src_off, int dst_buf, int64_t dst_off, const std::vector<int>& dims,
@@ -779,7 +807,7 @@ void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix) {
     prefix.resize(tasks.size() + 1);
     prefix[0] = 0;
-    for (size_t i = 0; i < tasks.size(); ++i) prefix[i + 1] = prefix[i] + (tasks[i].count + 1023) / 1024;
+    for (size_t i = 0; i < tasks.size(); ++i) prefix[i + 1] = prefix[i] + copy_task_chunks(tasks[i]);
 }
 
 // Every element a task or a GEMM group touches must lie inside its buffer;
