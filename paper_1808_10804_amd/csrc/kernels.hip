@@ -181,6 +181,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restric
     __shared__ double Bs[BN * LDK];
 
     const TileWork tw = tiles[blockIdx.x];
+    if (tw.group < 0) return;   // padding of the per-XCD tile lists
     const GemmGroup g = groups[tw.group];
     const double* __restrict__ A = (const double*)ptrs.get(g.a_buf) + g.a_off;
     const double* __restrict__ B = (const double*)ptrs.get(g.b_buf) + g.b_off;
@@ -299,6 +300,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
     __shared__ __attribute__((aligned(16))) unsigned short Bl[BLS];
 
     const TileWork tw = tiles[blockIdx.x];
+    if (tw.group < 0) return;   // padding of the per-XCD tile lists
     const GemmGroup g = groups[tw.group];
     const float* __restrict__ A = (const float*)ptrs.get(g.a_buf) + g.a_off;
     const float* __restrict__ B = (const float*)ptrs.get(g.b_buf) + g.b_off;
@@ -462,6 +464,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
     __shared__ __attribute__((aligned(16))) unsigned short Bs[PL][BN * LDH];
 
     const TileWork tw = tiles[blockIdx.x];
+    if (tw.group < 0) return;   // padding of the per-XCD tile lists
     const GemmGroup g = groups[tw.group];
     const unsigned short* __restrict__ A = (const unsigned short*)ptrs.get(g.a_buf) + g.a_off;
     const unsigned short* __restrict__ B = (const unsigned short*)ptrs.get(g.b_buf) + g.b_off;

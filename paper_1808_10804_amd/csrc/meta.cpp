@@ -790,18 +790,61 @@ int choose_tile_cfg(const ContractPlan& p) {
     return (p.info.max_m >= 128 && p.info.max_n >= 128) ? 1 : 0;
 }
 
+// Tile list of one grouped-GEMM launch, laid out for the 8 XCDs of the chip.
+// Workgroups are dispatched to the XCDs round robin (workgroup p runs on XCD
+// p mod 8), and each XCD has its own L2, so the tiles that share operand
+// panels are kept on one XCD: every group (or, for a group heavier than an
+// eighth of the launch, a contiguous range of its tile rows) goes to one XCD,
+// the XCDs are balanced by greedy longest-first assignment of the work
+// (tiles x K), each XCD's list runs longest K first, and the lists are
+// interleaved with no-op entries (group -1) padding the shorter ones.
 void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles) {
+    constexpr int kXcd = 8;
     const int BM = gemm_tile_bm(prec, cfg), BN = gemm_tile_bn(prec, cfg);
-    std::vector<int> order(groups.size());
-    std::iota(order.begin(), order.end(), 0);
-    // longest K first so that the heaviest tiles start early
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return groups[a].K > groups[b].K; });
-    for (int gi : order) {
+    struct Item { int group, r0, r1; double work; };
+    double total = 0.0;
+    for (auto& g : groups) {
+        const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+        total += (double)tm * tn * g.K;
+    }
+    const double target = total / kXcd;
+    std::vector<Item> items;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
         const GemmGroup& g = groups[gi];
         const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
-        for (int i = 0; i < tm; ++i)
-            for (int j = 0; j < tn; ++j) tiles.push_back(TileWork{gi, i, j, 0});
+        const double row_work = (double)tn * g.K;
+        const double w = row_work * tm;
+        const int parts = target > 0 ? std::max(1, std::min(tm, (int)std::ceil(w / target))) : 1;
+        for (int p = 0; p < parts; ++p) {
+            const int r0 = (int)((int64_t)tm * p / parts), r1 = (int)((int64_t)tm * (p + 1) / parts);
+            if (r1 > r0) items.push_back({(int)gi, r0, r1, row_work * (r1 - r0)});
+        }
     }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.work > b.work; });
+    std::vector<std::vector<Item>> bin(kXcd);
+    std::vector<double> load(kXcd, 0.0);
+    for (auto& it : items) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bin[x].push_back(it);
+        load[x] += it.work;
+    }
+    std::vector<std::vector<TileWork>> lists(kXcd);
+    size_t longest = 0;
+    for (int x = 0; x < kXcd; ++x) {
+        // longest K first inside the XCD so that the heaviest tiles start early
+        std::stable_sort(bin[x].begin(), bin[x].end(),
+                         [&](const Item& a, const Item& b) { return groups[a.group].K > groups[b.group].K; });
+        for (auto& it : bin[x]) {
+            const int tn = (groups[it.group].N + BN - 1) / BN;
+            for (int i = it.r0; i < it.r1; ++i)
+                for (int j = 0; j < tn; ++j) lists[x].push_back(TileWork{it.group, i, j, 0});
+        }
+        longest = std::max(longest, lists[x].size());
+    }
+    tiles.reserve(tiles.size() + longest * kXcd);
+    for (size_t i = 0; i < longest; ++i)
+        for (int x = 0; x < kXcd; ++x)
+            tiles.push_back(i < lists[x].size() ? lists[x][i] : TileWork{-1, 0, 0, 0});
 }
 
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix) {
