@@ -193,11 +193,28 @@ def bench_batched(args):
     ms_b, (outs, info) = timed(run_batched, args.steps)
     ms_s, fl_s = timed(run_single, max(1, args.steps // 2))
     flops = info["useful_flops"]
+    # per-kernel durations: the same batched launches run eagerly (a graph
+    # replay carries no per-launch events)
     st.profile_begin()
     for _ in range(args.steps):
-        run_batched()
+        st.enlarged_corners_batched(Cs, T1s, T4s, As, prec=args.prec or "bf16x3", use_graph=False, stream=stream)
     torch.cuda.synchronize()
     kst = st.profile_end()
+    prec = args.prec or "bf16x3"
+    dom = max(kst, key=lambda k: k["ms"]) if kst else None
+    roof = None
+    if dom is not None:
+        avg = dom["ms"] / dom["launches"]
+        if dom["name"].startswith("gemm"):
+            ach = dom["useful_flops"] / dom["launches"] / (avg * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                    "frac": ach / PEAK_TFLOPS[prec]}
+        else:
+            ach = dom["bytes"] / dom["launches"] / (avg * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS}
+        roof.update({"traffic": traffic_for(dom["name"], c5["name"]), "kernel": dom["name"], "avg_launch_ms": avg,
+                     "launches_per_step": dom["launches"] / args.steps})
     out = {
         "metric": "useful GFLOP/s of 64 batched enlarged corners (bf16x3, one grouped launch per step, HIP graph)",
         "value": flops / (ms_b * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -205,6 +222,7 @@ def bench_batched(args):
         "vs_baseline": None, "dtype": args.prec or "bf16x3", "data": "synthetic (seeded Gaussian blocks)",
         "config": {"workload": c5["name"], "batch": c5["batch"], "D": [d["D"] for d in draws],
                    "chi": [d["chi_total"] for d in draws]},
+        "roofline": roof,
         "useful_flops": flops, "per_contraction_f32": {"ms": ms_s, "gflops": fl_s / (ms_s * 1e-3) / 1e9},
         "speedup_vs_per_contraction_f32": ms_s / ms_b,
         "kernels": sorted(kst, key=lambda k: -k["ms"])[:6],
@@ -305,6 +323,22 @@ def bench_su2(args):
     print(json.dumps(out))
 
 
+def use_recorded_tiles(workload):
+    """GEMM tile choices recorded with the committed counter runs: when
+    profiles/tune_<workload>.txt exists (and SYMTEN_TUNE_CACHE is not set),
+    the autotuner starts from a private copy of it, so that the launches are
+    the ones whose HBM traffic was counted."""
+    import shutil
+    import tempfile
+    path = os.path.join(ROOT, "profiles", "tune_%s.txt" % workload)
+    if os.environ.get("SYMTEN_TUNE_CACHE") or not os.path.exists(path):
+        return
+    fd, tmp = tempfile.mkstemp(prefix="symten_tune_", suffix=".txt")
+    os.close(fd)
+    shutil.copy(path, tmp)
+    os.environ["SYMTEN_TUNE_CACHE"] = tmp
+
+
 def calibrate_copy():
     """A plain device copy of known size, for scaling the HBM traffic
     counters (FETCH_SIZE / WRITE_SIZE) of the profiled kernels."""
@@ -373,6 +407,7 @@ def main():
 
     cfgd = config(args.config)
     prec = args.prec or {"sweep": "f32"}.get(cfgd["prec"], cfgd["prec"])
+    use_recorded_tiles(cfgd["name"])
     dtype = "f64" if prec == "f64" else "f32"
     chi = cfgd["chi_target"]
     torch.cuda.set_device(0)
