@@ -25,6 +25,7 @@ import numpy as np
 
 IN, OUT = +1, -1
 TRUNC_REL_CUTOFF = 1e-14   # singular values <= cutoff * s_max are dropped
+DEGENERATE_REL = 1e-8   # relative spread of a degenerate set of singular values
 
 
 class Leg:
@@ -285,6 +286,12 @@ def projectors(Hu, Hd, F_left, F_right, chi, cutoff=TRUNC_REL_CUTOFF):
     allsv = sorted(((-s, Q, j) for Q, d in per_Q.items() for j, s in enumerate(d["s"])))
     s_max = -allsv[0][0] if allsv else 0.0
     kept = [(Q, j) for (ms, Q, j) in allsv[:chi] if -ms > cutoff * s_max]
+    # a set of (near-)degenerate values is never split at the cut: values
+    # within DEGENERATE_REL of the last kept one are dropped with it
+    n = len(kept)
+    while 1 < n < len(allsv) and -allsv[n][0] >= (1.0 - DEGENERATE_REL) * (-allsv[n - 1][0]):
+        n -= 1
+    kept = kept[:n]
     kept_set = set(kept)
     discarded = [-ms for (ms, Q, j) in allsv if (Q, j) not in kept_set]
     tot = sum(ms * ms for (ms, _, _) in allsv)

@@ -1,0 +1,158 @@
+"""Pins of the whole-environment oracle: the dense move equals the pinned
+U(1) oracle's move; the partition function per site is invariant under a
+quarter turn of the network, exact on a product network, and (on a 2 x 2
+patch) exact on a two-copy environment whose 1 x 1 estimate is provably
+biased; the closed networks agree with independently written contractions;
+the iteration with the error estimate of Sec. 3 follows its rules; and the
+CTM reproduces the square-ice entropy (Lieb: W = (4/3)^(3/2) states per site;
+a textbook result, not from the paper)."""
+import numpy as np
+import pytest
+
+from oracle import ctm, u1
+from synth import config
+from workload import oracle_side
+
+W_ICE = (4.0 / 3.0) ** 1.5
+
+
+def test_dense_left_move_matches_u1_oracle():
+    c = config(1)
+    w, T, a, _ = oracle_side(c, c["seed"])
+    mv = u1.ctm_left_move(w, T, a, c["chi_target"])
+    C = [T["C1"], T["C2"], T["C3"], T["C4"]]
+    Tt = [T["T1"], T["T2"], T["T3"], T["T4"]]
+    C1n, T4n, C4n, s = ctm.left_move(C, Tt, a, c["chi_target"])
+    L1 = u1.left_column(mv["C1"], mv["T4"], mv["C4"])
+    L2 = u1.left_column(C1n, T4n, C4n)
+    assert np.linalg.norm(L1 - L2) <= 1e-12 * np.linalg.norm(L1)
+    ref = np.sort(np.concatenate(list(mv["proj"]["svals"].values())))[::-1]
+    assert np.allclose(s, ref[:len(s)], rtol=0, atol=1e-13 * ref[0])
+
+
+def test_site_partition_quarter_turn_and_product_network():
+    rng = np.random.default_rng(0)
+    C = [rng.standard_normal((3, 3)) for _ in range(4)]
+    T = [rng.standard_normal((3, 2, 3)) for _ in range(4)]
+    a = rng.standard_normal((2, 2, 2, 2))
+    k0, z0 = ctm.site_partition(C, T, a)
+    k1, z1 = ctm.site_partition(*ctm.rotate(C, T, a))
+    assert np.isclose(k0, k1, rtol=1e-13)
+    assert np.isclose(z0[0], z1[0]) and np.isclose(z0[3], z1[3])
+    assert np.isclose(z0[1], z1[2]) and np.isclose(z0[2], z1[1])     # a row turns into a column
+    # one-dimensional bonds: every Z is a product and kappa is the site weight
+    c, t, al = 0.7, 1.9, 2.3
+    k, _ = ctm.site_partition([np.full((1, 1), c)] * 4, [np.full((1, 1, 1), t)] * 4, np.full((1, 1, 1, 1), al))
+    assert np.isclose(k, al, rtol=1e-14)
+
+
+def _random_env(seed, chi=3, D=2):
+    rng = np.random.default_rng(seed)
+    C = [rng.standard_normal((chi, chi)) for _ in range(4)]
+    T = [rng.standard_normal((chi, D, chi)) for _ in range(4)]
+    return C, T, rng.standard_normal((D, D, D, D))
+
+
+def test_closed_networks_match_hand_written_contractions():
+    """z_block (the generated network contracted in list order) against the pairwise
+    contractions of site_partition for n, m <= 1 and against explicitly
+    spelled 2 x 1 and 2 x 2 networks."""
+    C, T, a = _random_env(1)
+    _, z = ctm.site_partition(C, T, a)
+    for (n, m), ref in zip(((0, 0), (1, 0), (0, 1), (1, 1)), z):
+        assert np.isclose(ctm.z_block(C, T, a, n, m), ref, rtol=1e-12)
+    C1, C2, C3, C4 = C
+    T1, T2, T3, T4 = T
+    # top: C1 T1 T1 C2; right: T2 T2; C3; bottom: T3 T3 (right to left); C4; left: T4 T4 (bottom to top)
+    z22 = np.einsum("ab,buc,cwd,de,erf,fsg,gh,hti,iyj,jk,kLm,mla,lupv,pwrq,Lvxy,xqst->",
+                    C1, T1, T1, C2, T2, T2, C3, T3, T3, C4, T4, T4, a, a, a, a, optimize="greedy")
+    z21 = np.einsum("ab,buc,cwd,de,erf,fg,gqi,ivj,jk,kla,lupv,pwrq->",
+                    C1, T1, T1, C2, T2, C3, T3, T3, C4, T4, a, a, optimize="greedy")
+    assert np.isclose(ctm.z_block(C, T, a, 2, 2), z22, rtol=1e-12)
+    assert np.isclose(ctm.z_block(C, T, a, 2, 1), z21, rtol=1e-12)
+
+
+def test_closed_networks_quarter_turn():
+    """Turning the network a quarter turn exchanges columns and rows."""
+    C, T, a = _random_env(2)
+    Cr, Tr, ar = ctm.rotate(C, T, a)
+    for n in range(3):
+        for m in range(3):
+            assert np.isclose(ctm.z_block(Cr, Tr, ar, n, m), ctm.z_block(C, T, a, m, n), rtol=1e-12)
+
+
+def test_block_estimator_product_network():
+    c, t, al = 0.7, 1.9, 2.3
+    Cs, Ts, a = [np.full((1, 1), c)] * 4, [np.full((1, 1, 1), t)] * 4, np.full((1, 1, 1, 1), al)
+    for b in (1, 2):
+        k, z = ctm.site_partition_block(Cs, Ts, a, b)
+        assert np.isclose(k, al, rtol=1e-14)
+        assert np.isclose(z[3], c ** 4 * t ** (4 * b) * al ** (b * b), rtol=1e-14)
+
+
+def test_block_estimator_two_parity_copies():
+    """A bond of two states (charge parities 0, 1), corners diagonal with
+    unequal weights c_i = (1, r_i), every edge tensor moving parity p to 1 - p
+    with weight t, one-state site tensor alpha.  Then
+    Z_nm = t^(2n+2m) alpha^(nm) sum_p c1_p c2_(p+n) c3_(p+n+m) c4_(p+m): the
+    1 x 1 ratio is alpha times a corner factor that is not 1, the 2 x 2 ratio
+    is exactly alpha^4."""
+    r = [1.0, 1.7, 0.6, 2.2, 0.9]
+    c = [None] + [np.array([1.0, r[i]]) for i in range(1, 5)]
+    t, al = 1.3, 1.45
+    Cs = [np.diag(c[i]) for i in range(1, 5)]
+    Te = np.zeros((2, 1, 2))
+    Te[0, 0, 1] = Te[1, 0, 0] = t
+    a = np.full((1, 1, 1, 1), al)
+    Ts = [Te] * 4
+
+    def zf(n, m):
+        return t ** (2 * n + 2 * m) * al ** (n * m) * sum(
+            c[1][p] * c[2][(p + n) % 2] * c[3][(p + n + m) % 2] * c[4][(p + m) % 2] for p in (0, 1))
+    for n in range(3):
+        for m in range(3):
+            assert np.isclose(ctm.z_block(Cs, Ts, a, n, m), zf(n, m), rtol=1e-13)
+    k1, _ = ctm.site_partition_block(Cs, Ts, a, 1)
+    bias = zf(1, 1) * zf(0, 0) / (zf(1, 0) * zf(0, 1)) / al
+    assert abs(bias - 1.0) > 0.05
+    assert np.isclose(k1, al * bias, rtol=1e-13)
+    k2, _ = ctm.site_partition_block(Cs, Ts, a, 2)
+    assert np.isclose(k2, al, rtol=1e-13)
+
+
+def test_run_follows_the_error_rules():
+    """On a product network every step leaves kappa unchanged, so each chi
+    stops after one step, the second chi agrees with the first and the run
+    ends there; with max_steps = 2 and tol = 0 on a random network, two steps
+    at each of the chis 4, 8 (chi_max 15 stops the doubling) and the errors
+    are the changes between the recorded values."""
+    c, t, al = 0.7, 1.9, 2.3
+    Cs, Ts, a = [np.full((1, 1), c)] * 4, [np.full((1, 1, 1), t)] * 4, np.full((1, 1, 1, 1), al)
+    _, _, r = ctm.run(Cs, Ts, a, 2, chi_max=128, block=2, max_steps=15, tol=1e-8)
+    assert (r["steps"], r["levels"], r["total_steps"], r["chi"]) == (1, 2, 2, 4)
+    assert np.isclose(r["kappa"], al) and r["error"] < 1e-12
+    C, T, ad = _random_env(3, chi=4)
+    vals = []
+    Ck, Tk = C, T
+    for chi in (4, 8):
+        vals.append([ctm.site_partition_block(Ck, Tk, ad, 1)[0]])
+        for _ in range(2):
+            for d in range(4):
+                Ck, Tk, _ = ctm.move(Ck, Tk, ad, chi, d)
+            vals[-1].append(ctm.site_partition_block(Ck, Tk, ad, 1)[0])
+    _, _, r = ctm.run(C, T, ad, 4, chi_max=15, block=1, max_steps=2, tol=0.0)
+    assert (r["steps"], r["levels"], r["total_steps"], r["chi"]) == (2, 2, 4, 8)
+    h = vals[1]
+    assert r["kappa"] == h[-1]
+    assert r["err_steps"] == max(abs(h[1] - h[0]), abs(h[2] - h[1]))
+    assert r["err_chi"] == abs(vals[1][-1] - vals[0][-1])
+    assert r["error"] == max(r["err_steps"], r["err_chi"])
+
+
+@pytest.mark.parametrize("block", [1, 2])
+def test_square_ice_entropy(block):
+    a = ctm.vertex_tensor(ctm.ice_weights())
+    assert np.count_nonzero(a) == 6
+    C, T = ctm.initial_environment()
+    _, _, r = ctm.run(C, T, a, 8, block=block, max_steps=300, tol=1e-9)
+    assert abs(r["kappa"] - W_ICE) <= 1e-3 * W_ICE

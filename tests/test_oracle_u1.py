@@ -325,3 +325,18 @@ def test_new_leg_charges(move1):
     assert np.all(mv["C1"][~u1.conserving_mask([k, X.flipped()], 0)] == 0.0)
     assert np.all(mv["T4"][~u1.conserving_mask([k, D.flipped(), k.flipped()], 0)] == 0.0)
     assert np.all(mv["C4"][~u1.conserving_mask([X, k.flipped()], 0)] == 0.0)
+
+
+def test_truncation_never_splits_a_degenerate_set():
+    """Singular values 3, 2 (charge 0) and 2 (charge 1): chi = 2 would keep
+    one of the equal pair, so only the 3 is kept; chi = 3 keeps all three; a
+    pair split by 1e-6 (beyond the 1e-8 spread of a degenerate set) is cut
+    as usual."""
+    F = u1.Leg({0: 2, 1: 1}, u1.IN)
+
+    def kept(s1, chi):
+        return u1.projectors(np.eye(3), np.diag([3.0, 2.0, s1]), F, F, chi)["kept"]
+    assert kept(2.0, 2) == {0: 1}
+    assert kept(2.0, 3) == {0: 2, 1: 1}
+    assert kept(2.0 * (1 - 1e-6), 2) == {0: 2}
+    assert kept(2.0 * (1 - 1e-6), 1) == {0: 1}
