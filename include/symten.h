@@ -207,6 +207,16 @@ int symten_plan_info(symten_t A, symten_t B, int ncon, const int* legsA,
  * Output dtype = A's dtype, flux 0.                                         */
 int symten_double_layer(symten_t* a_out, symten_t A, void* stream);
 
+/* Double layer with a one-site operator between the layers (Sec. 3's
+ * expectation values): b = sum over (s_bra, s_ket) of op[s_bra * d + s_ket]
+ * A[s_ket, ...] (ket) A[s_bra, ...] (bra), the legs fused as in
+ * symten_double_layer; for real A, Z(b) / Z(a) = <psi|O|psi> / <psi|psi>.
+ * op is host memory, d x d row-major, d = the physical dimension of A
+ * (at most 8), over A's physical states in charge order.  Every non-zero
+ * entry must move the charge by one amount f = q(s_bra) - q(s_ket)
+ * (SYMTEN_E_SYM otherwise); b's flux is dir(phys) * f.  U(1) only.        */
+int symten_double_layer_op(symten_t* b_out, symten_t A, const double* op, void* stream);
+
 /* ---- enlarged corners -------------------------------------------------- */
 
 /* which = 1..4.  Inputs follow the clockwise environment convention:
@@ -233,7 +243,10 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* C,
 
 /* ---- CTM environment and one move ------------------------------------- */
 
-#define CTM_LEFT 0
+#define CTM_LEFT   0
+#define CTM_TOP    1
+#define CTM_RIGHT  2
+#define CTM_BOTTOM 3
 #define CTM_MAX_SECTORS 64
 
 typedef struct {
@@ -260,7 +273,14 @@ void ctm_env_destroy(ctm_env_t env);
  * (sharing the storage) that the caller releases with symten_destroy.      */
 int ctm_env_get(ctm_env_t env, int k, symten_t* t);
 
-/* One CTM move (only CTM_LEFT; Sec. 3, the projector scheme it cites):
+/* One CTM move (Sec. 3, the projector scheme it cites) toward direction
+ * `dir`: CTM_LEFT absorbs a column into C1, T4, C4; CTM_TOP, CTM_RIGHT and
+ * CTM_BOTTOM are the left move of the network turned 1, 2 or 3 quarter turns
+ * counterclockwise (C1' = C2, ..., T4' = T1, a'[l,u,r,d] = a[u,r,d,l], the
+ * legs that land against the (in, in, out, out) convention reversed: a U(1)
+ * relabelling, no data moves) and update C1, T1, C2 / C2, T2, C3 / C3, T3, C4.
+ * SU(2) environments take CTM_LEFT only (SYMTEN_E_UNSUPPORTED otherwise).
+ * The left move:
  * four enlarged corners, halves H_u = C~1 C~2 and H_d = C~4 C~3, per fused
  * sector of the left cut the singular triplets of M = R_u R_d^T (QR
  * H_u^T = Q_u R_u, H_d^T = Q_d R_d; taken from Y = H_u^T H_d, which has the
@@ -279,6 +299,66 @@ int ctm_env_get(ctm_env_t env, int k, symten_t* t);
  * NULL.                                                                     */
 int ctm_move(ctm_env_t env, symten_t a, int dir, int chi, int prec,
              ctm_move_stats* st, void* stream);
+
+/* Partition function per site of a classical model (U(1)), FP64, from
+ * the environment of a 1x1 cell, on a block x block patch (block 1 or 2):
+ * kappa^(block^2) = Z_bb Z_00 / (Z_b0 Z_0b), Z_nm the closed network of the
+ * four corners with n columns and m rows of edge tensors and the n x m site
+ * tensors a between them (Z_00 = Tr C1 C2 C3 C4); the boundary factors cancel
+ * in the ratio.  block = 2 also cancels the corner weights when the
+ * environment bonds alternate between two charge parities from site to site
+ * (every D charge odd, e.g. arrow models), which bias block = 1; it needs a
+ * positive ratio (SYMTEN_E_LINALG otherwise).  z (may be NULL) receives
+ * Z_00, Z_b0, Z_0b, Z_bb.  Synchronous.                                      */
+int ctm_site_partition(ctm_env_t env, symten_t a, int block, double* kappa, double* z, void* stream);
+
+/* Expectation value on an n x m patch (n columns, m rows; 1 <= n, m <= 2)
+ * of the 1x1-cell environment, FP64: value = Z_nm(sites) / Z_nm(a), where
+ * Z_nm(sites) is the closed network of ctm_site_partition with the site
+ * tensors replaced by sites[n*m] (row-major: row 0 on top, column 0 on the
+ * left; each a rank-4 U(1) tensor with a's legs, any flux; a patch whose
+ * fluxes do not add up to 0 gives 0).  For a PEPS, sites are double layers
+ * with one-site operators between the layers (symten_double_layer_op) and
+ * the value is <O_1 O_2 ...> of Sec. 3's energy evaluation; for a classical
+ * model they are impurity weights.  Synchronous.                            */
+int ctm_expectation(ctm_env_t env, symten_t a, int n, int m, const symten_t* sites, double* value,
+                    void* stream);
+
+/* Nearest-neighbour Heisenberg energy per bond, S_i . S_j = Sz Sz +
+ * (S+ S- + S- S+)/2 (J = 1), FP64, of the state A[phys, l, u, r, d]
+ * (U(1); physical charges 2m for m = -S..S, one state each, S <= 7/2) in
+ * the current environment, which must be the environment of A's double
+ * layer: *e_h on a horizontal bond (2 x 1 patch), *e_v on a vertical one.
+ * The double layers with Sz, S+, S- between the layers are built on the
+ * device (symten_double_layer_op).  Synchronous.                           */
+int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e_v, void* stream);
+
+/* CTM iteration with the error estimate of Sec. 3 (U(1)).  A step is one
+ * move toward each of the four sides (left, top, right, bottom).  At fixed
+ * chi, steps run until kappa changes by less than tol from one step to the
+ * next, or max_steps steps (the value before the first step is measured
+ * too); err_steps is the larger of the last two changes.  Then chi doubles,
+ * continuing from the current environment, while 2 chi <= chi_max, until the
+ * values at the last two chis differ by less than tol; err_chi is that
+ * difference (0 with one chi).  error = max(err_steps, err_chi); kappa is the
+ * value at the last chi.  The paper's settings: tol = 1e-8, max_steps = 15,
+ * chi_max = 128.                                                            */
+typedef struct {
+    int chi;          /* first environment dimension (states) */
+    int chi_max;      /* doubling stops before chi would exceed it */
+    int prec;         /* SYMTEN_PREC_* of the moves */
+    int block;        /* kappa estimator patch, 1 or 2 (ctm_site_partition) */
+    int max_steps;    /* steps per chi */
+    double tol;       /* absolute change of kappa */
+} ctm_run_opts;
+typedef struct {
+    double kappa, err_steps, err_chi, error;
+    int steps;        /* steps at the last chi */
+    int total_steps;  /* steps over all chis */
+    int chi;          /* last chi */
+    int levels;       /* number of chis */
+} ctm_run_result;
+int ctm_run(ctm_env_t env, symten_t a, const ctm_run_opts* opts, ctm_run_result* result, void* stream);
 
 /* Singular values of the last move, per sector in charge order, each
  * sector descending.  cap = capacity of `s`; *n receives the count.        */

@@ -14,6 +14,8 @@ row-major and the truncation is the global top-chi of one dense SVD.
 """
 import numpy as np
 
+from . import u1
+
 CUTOFF = 1e-14
 DEGENERATE_REL = 1e-8
 
@@ -98,7 +100,7 @@ def site_partition(C, T, a):
     return z11 * z00 / (z10 * z01), (z00, z10, z01, z11)
 
 
-def network(C, T, a, n, m):
+def network(C, T, a, n, m, sites=None):
     """The closed network Z_nm as (tensor, bond labels) pairs: the corners,
     n edge tensors on the top and bottom sides, m on the left and right, and
     the n x m site tensors.  Bond names: h (top chi bonds, left to right),
@@ -107,7 +109,8 @@ def network(C, T, a, n, m):
     the top edge), ("H", i, j) the D bond right of column j in row i (column
     0 = the left edge).  Listed top row first, then row by row (right edge,
     sites right to left, left edge), then the bottom row, so that every
-    tensor shares a bond with those before it."""
+    tensor shares a bond with those before it.  sites (optional): n*m site
+    tensors replacing a, row-major (row 0 on top, column 0 on the left)."""
     C1, C2, C3, C4 = C
     T1, T2, T3, T4 = T
     net = [(C1, [("w", m), ("h", 0)])]
@@ -115,7 +118,8 @@ def network(C, T, a, n, m):
     net.append((C2, [("h", n), ("v", 0)]))
     for i in range(1, m + 1):
         net.append((T2, [("v", i - 1), ("H", i, n), ("v", i)]))
-        net += [(a, [("H", i, j - 1), ("V", i - 1, j), ("H", i, j), ("V", i, j)]) for j in range(n, 0, -1)]
+        net += [(a if sites is None else sites[(i - 1) * n + (j - 1)],
+                 [("H", i, j - 1), ("V", i - 1, j), ("H", i, j), ("V", i, j)]) for j in range(n, 0, -1)]
         net.append((T4, [("w", m - i), ("H", i, 0), ("w", m - i + 1)]))
     net.append((C3, [("v", m), ("g", 0)]))
     net += [(T3, [("g", n - j), ("V", m, j), ("g", n - j + 1)]) for j in range(n, 0, -1)]
@@ -123,10 +127,10 @@ def network(C, T, a, n, m):
     return net
 
 
-def z_block(C, T, a, n, m):
+def z_block(C, T, a, n, m, sites=None):
     """Z_nm: the tensors of `network` contracted one after another, each over
     every bond it shares with the part already contracted."""
-    net = network(C, T, a, n, m)
+    net = network(C, T, a, n, m, sites)
     X, xl = net[0]
     for t, tl in net[1:]:
         shared = [b for b in xl if b in tl]
@@ -143,6 +147,26 @@ def site_partition_block(C, T, a, b):
     z = tuple(z_block(C, T, a, n, m) for n, m in ((0, 0), (b, 0), (0, b), (b, b)))
     r = z[3] * z[0] / (z[1] * z[2])
     return (r if b == 1 else r ** (1.0 / (b * b))), z
+
+
+def expectation(C, T, a, sites, n, m):
+    """Z_nm(sites) / Z_nm(a)."""
+    return z_block(C, T, a, n, m, sites) / z_block(C, T, a, n, m)
+
+
+def heisenberg_bond_energy(C, T, A, A_legs):
+    """<S_i . S_j> = <Sz Sz> + (<S+ S-> + <S- S+>)/2 on a horizontal (2 x 1
+    patch) and a vertical (1 x 2) bond, from dense double layers with the
+    spin operators between the layers."""
+    from oracle import u1
+    sz, sp, sm = u1.spin_operators(A_legs[0])
+    a = u1.double_layer(A, A_legs)[0]
+    bz, bp, bm = (u1.double_layer_op(A, A_legs, o) for o in (sz, sp, sm))
+
+    def bond(n, m):
+        return (expectation(C, T, a, [bz, bz], n, m)
+                + 0.5 * (expectation(C, T, a, [bp, bm], n, m) + expectation(C, T, a, [bm, bp], n, m)))
+    return bond(2, 1), bond(1, 2)
 
 
 def run(C, T, a, chi, chi_max=None, block=1, max_steps=15, tol=1e-8):

@@ -200,6 +200,32 @@ def double_layer(A, A_legs):
     return a4[np.ix_(*perms)], legs
 
 
+def double_layer_op(A, A_legs, op):
+    """The double layer with a one-site operator between the layers:
+    b = sum over (s_bra, s_ket) of op[s_bra, s_ket] A[s_ket, ...] (ket)
+    A[s_bra, ...] (bra), legs fused as in double_layer; for real A the
+    network with b in place of a gives <psi|O|psi> (Sec. 3's expectation
+    values)."""
+    b8 = np.einsum("tk,kabcd,tefgh->aebfcgdh", op, A, A)
+    perms = [fuse(leg, leg, +1, -1, leg.dir)[1] for leg in A_legs[1:]]
+    n = [leg.size for leg in A_legs[1:]]
+    b4 = b8.reshape(n[0] * n[0], n[1] * n[1], n[2] * n[2], n[3] * n[3])
+    return b4[np.ix_(*perms)]
+
+
+def spin_operators(phys_leg):
+    """Sz, S+, S- on a physical leg with charges 2m, m = -S..S (one state
+    each, charge order), as matrices [bra, ket]."""
+    ms = [q / 2.0 for q in phys_leg.charges]
+    assert phys_leg.dims == [1] * len(ms) and all(b - a == 1.0 for a, b in zip(ms, ms[1:]))
+    S = ms[-1]
+    n = len(ms)
+    sz, sp = np.diag(ms), np.zeros((n, n))
+    for k in range(n - 1):
+        sp[k + 1, k] = np.sqrt(S * (S + 1) - ms[k] * (ms[k] + 1))
+    return sz, sp, sp.T.copy()
+
+
 # --------------------------------------------------------------------------
 # Enlarged corners, halves, projectors, renormalisation
 # --------------------------------------------------------------------------

@@ -53,6 +53,20 @@ class MoveStats(C.Structure):
         return d
 
 
+class RunOpts(C.Structure):
+    _fields_ = [("chi", C.c_int), ("chi_max", C.c_int), ("prec", C.c_int), ("block", C.c_int),
+                ("max_steps", C.c_int), ("tol", C.c_double)]
+
+
+class RunResult(C.Structure):
+    _fields_ = [("kappa", C.c_double), ("err_steps", C.c_double), ("err_chi", C.c_double),
+                ("error", C.c_double), ("steps", C.c_int), ("total_steps", C.c_int), ("chi", C.c_int),
+                ("levels", C.c_int)]
+
+    def to_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 64), ("launches", C.c_int64), ("ms", C.c_double),
                 ("useful_flops", C.c_int64), ("gemm_flops", C.c_int64), ("bytes", C.c_int64)]
@@ -98,6 +112,11 @@ SIGNATURES = {
     "ctm_env_destroy": (None, [H]),
     "ctm_env_get": (C.c_int, [H, C.c_int, C.POINTER(H)]),
     "ctm_move": (C.c_int, [H, H, C.c_int, C.c_int, C.c_int, C.POINTER(MoveStats), P]),
+    "ctm_site_partition": (C.c_int, [H, H, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double), P]),
+    "ctm_run": (C.c_int, [H, H, C.POINTER(RunOpts), C.POINTER(RunResult), P]),
+    "ctm_expectation": (C.c_int, [H, H, C.c_int, C.c_int, C.POINTER(H), C.POINTER(C.c_double), P]),
+    "ctm_heisenberg_bond_energy": (C.c_int, [H, H, C.POINTER(C.c_double), C.POINTER(C.c_double), P]),
+    "symten_double_layer_op": (C.c_int, [C.POINTER(H), H, C.POINTER(C.c_double), P]),
     "ctm_move_singular_values": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64, I64P]),
     "ctm_move_projectors": (C.c_int, [H, C.POINTER(H), C.POINTER(H)]),
     "ctm_env_set": (C.c_int, [H, C.c_int, H]),

@@ -426,8 +426,8 @@ namespace {
 struct CutSector {
     int key = 0;                 // fused charge Q, or doubled spin 2J
     int weight = 1;              // states per kept value: 1 (U(1)) or 2J+1 (SU(2))
-    int n = 0, m = 0;            // rows (left cut) x columns (right cut)
-    const void* hu = nullptr;    // row-major n x m blocks of the two halves
+    int n = 0, mu = 0, md = 0;   // rows (left cut) x columns (right cut) of H_u, H_d
+    const void* hu = nullptr;    // row-major n x mu and n x md blocks of the halves
     const void* hd = nullptr;    // (storage type of the move)
     // filled by cut_projectors
     int mn = 0;                  // singular values reported (min(n, m))
@@ -484,10 +484,11 @@ ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool
         std::vector<int> order(secs.size());
         std::iota(order.begin(), order.end(), 0);
         for (size_t i = 0; i < secs.size(); ++i) {
-            w[i].ru = w[i].rd = secs[i].m;                       // rows of U_Y and V_Y
-            secs[i].mn = std::min(secs[i].m, secs[i].n);          // rank bound: values reported
+            w[i].ru = secs[i].mu;                                // rows of U_Y
+            w[i].rd = secs[i].md;                                // rows of V_Y
+            secs[i].mn = std::min(secs[i].n, std::min(secs[i].mu, secs[i].md));   // rank bound
         }
-        auto dim = [&](int i) { return std::max(secs[i].m, secs[i].n); };
+        auto dim = [&](int i) { return std::max(secs[i].n, std::max(secs[i].mu, secs[i].md)); };
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return dim(x) > dim(y); });
         const double one = 1.0, zero = 0.0;
         size_t pos = 0;
@@ -523,7 +524,7 @@ ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool
                 const CutSector& b = secs[cls[i]];
                 for (int side = 0; side < 2; ++side) {
                     pa.src[2 * i + side] = side == 0 ? b.hu : b.hd;
-                    pa.rows[2 * i + side] = b.m;   // col-major m x n (ld m)
+                    pa.rows[2 * i + side] = side == 0 ? b.mu : b.md;   // col-major m x n (ld m)
                     pa.cols[2 * i + side] = b.n;
                 }
             }
@@ -606,6 +607,12 @@ ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool
            states + secs[all[nkeep].sec].weight <= chi) {
         states += secs[all[nkeep].sec].weight;
         ++nkeep;
+    }
+    // a set of (near-)degenerate values is never split at the cut: values
+    // within 1e-8 (relative) of the last kept one are dropped with it
+    while (nkeep > 1 && nkeep < (int)all.size() && all[nkeep].s >= (1.0 - 1e-8) * all[nkeep - 1].s) {
+        states -= secs[all[nkeep - 1].sec].weight;
+        --nkeep;
     }
     if (nkeep == 0) fail(SYMTEN_E_LINALG, "ctm_move: no singular value above the cutoff");
     for (size_t i = 0; i < all.size(); ++i) {
@@ -858,7 +865,7 @@ void move_su2(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st, hi
         c.key = bu.q[0];
         c.weight = bu.q[0] + 1;
         c.n = bu.shape[0];
-        c.m = bu.shape[1];
+        c.mu = c.md = bu.shape[1];
         c.hu = (const char*)Gu.data() + bu.offset * es;
         c.hd = (const char*)Gd.data() + bd->offset * es;
         secs.push_back(c);
@@ -942,6 +949,417 @@ void move_su2(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st, hi
         st->flops_halves = hh[0].plan->info.useful_flops + hh[1].plan->info.useful_flops;
         st->flops_renorm = c1n.plan->info.useful_flops + t4a.plan->info.useful_flops + xx.plan->info.useful_flops +
                            t4n.plan->info.useful_flops + c4n.plan->info.useful_flops;
+        st->ms_corners = tm.ms(0, 1);
+        st->ms_halves = tm.ms(1, 2);
+        st->ms_proj = tm.ms(2, 3);
+        st->ms_renorm = tm.ms(3, 4);
+        st->ms_total = tm.ms(0, 4);
+    }
+}
+}  // namespace
+}  // namespace symten
+
+namespace symten {
+namespace {
+// ------------------------------------------------ network turned a quarter
+// U(1) leg reversal: direction and charges negated, block data unchanged
+// (the addition rule keeps holding; the sectors of the leg reverse order).
+TensorPtr flip_legs_u1(const TensorPtr& t, std::initializer_list<int> legs) {
+    auto r = std::make_shared<Tensor>(*t);
+    for (int l : legs) {
+        Leg& L = r->legs[l];
+        L.dir = -L.dir;
+        std::vector<int> q(L.q.rbegin(), L.q.rend()), d(L.d.rbegin(), L.d.rend());
+        for (auto& x : q) x = -x;
+        L.q = q;
+        L.d = d;
+        for (auto& b : r->blocks) b.q[l] = -b.q[l];
+    }
+    std::sort(r->blocks.begin(), r->blocks.end(), [](const Block& x, const Block& y) { return x.q < y.q; });
+    r->rebuild_index();
+    return r;
+}
+
+// Leg permutation (new leg j = old leg perm[j]); shares the buffer.
+TensorPtr permute_legs(const TensorPtr& t, const std::vector<int>& perm) {
+    auto r = std::make_shared<Tensor>(*t);
+    const int R = t->rank();
+    for (int j = 0; j < R; ++j) r->legs[j] = t->legs[perm[j]];
+    for (size_t i = 0; i < t->blocks.size(); ++i) {
+        const Block& b = t->blocks[i];
+        Block& nb = r->blocks[i];
+        for (int j = 0; j < R; ++j) {
+            nb.q[j] = b.q[perm[j]];
+            nb.shape[j] = b.shape[perm[j]];
+            nb.stride[j] = b.stride[perm[j]];
+        }
+    }
+    std::sort(r->blocks.begin(), r->blocks.end(), [](const Block& x, const Block& y) { return x.q < y.q; });
+    r->rebuild_index();
+    return r;
+}
+
+// The network turned a quarter counterclockwise, in the conventions of the
+// left move: C1' = C2, C2' = C3, C3' = C4, C4' = C1 and T1' = T2, T2' = T3,
+// T3' = T4, T4' = T1 keep the clockwise chi bonds; a'[l,u,r,d] = a[u,r,d,l].
+// The legs that land on the wrong side of the (in, in, out, out) convention
+// of a, and the D^2 legs of T1' and T3', are reversed (both ends of each such
+// bond).  Four turns give back the original tensors.
+void rotate_ccw(std::array<TensorPtr, 4>& C, std::array<TensorPtr, 4>& T, TensorPtr& a) {
+    const std::array<TensorPtr, 4> Cn{C[1], C[2], C[3], C[0]};
+    const std::array<TensorPtr, 4> Tn{flip_legs_u1(T[1], {1}), T[2], flip_legs_u1(T[3], {1}), T[0]};
+    a = flip_legs_u1(permute_legs(a, {1, 2, 3, 0}), {1, 3});
+    C = Cn;
+    T = Tn;
+}
+
+// Full trace of a rank-2 U(1) tensor whose two legs are the two ends of one
+// bond (FP64 on the host).
+double trace_u1(const Tensor& X) {
+    if (X.rank() != 2) fail(SYMTEN_E_INVAL, "internal: trace of a non-matrix");
+    std::vector<char> host((size_t)std::max<int64_t>(X.elems, 1) * X.esize());
+    HIPCHK(hipMemcpy(host.data(), X.data(), X.elems * X.esize(), hipMemcpyDeviceToHost));
+    double t = 0.0;
+    for (const Block& b : X.blocks) {
+        if (b.q[0] != b.q[1] || b.shape[0] != b.shape[1]) continue;
+        for (int i = 0; i < b.shape[0]; ++i) {
+            const int64_t o = b.offset + i * (b.stride[0] + b.stride[1]);
+            t += X.dtype == SYMTEN_F64 ? ((const double*)host.data())[o] : (double)((const float*)host.data())[o];
+        }
+    }
+    return t;
+}
+
+// FP64 copy of a tensor (same blocks and strides).
+TensorPtr as_f64(const TensorPtr& t, hipStream_t s) {
+    if (t->dtype == SYMTEN_F64) return t;
+    auto r = std::make_shared<Tensor>(*t);
+    r->dtype = SYMTEN_F64;
+    r->buf = device_alloc(8 * std::max<int64_t>(t->elems, 1));
+    launch_cast(t->data(), false, r->buf->ptr, true, t->elems, s);
+    return r;
+}
+
+// A tensor of a closed network with one bond label per leg.
+struct Labelled {
+    TensorPtr t;
+    std::vector<int> lab;
+};
+
+// X contracted with Y over every bond label they share except `keep` (the
+// bond left open for the closing trace), in FP64; the result's legs are X's
+// open legs in order, then Y's.
+Labelled join(const Labelled& X, const Labelled& Y, int keep, hipStream_t s) {
+    std::vector<int> la, lb;
+    for (size_t i = 0; i < X.lab.size(); ++i)
+        for (size_t j = 0; j < Y.lab.size(); ++j)
+            if (X.lab[i] == Y.lab[j] && X.lab[i] != keep) {
+                la.push_back((int)i);
+                lb.push_back((int)j);
+            }
+    if (la.empty()) fail(SYMTEN_E_INVAL, "internal: network step without a shared bond");
+    auto p = get_plan(*X.t, *Y.t, (int)la.size(), la.data(), lb.data(), nullptr, SYMTEN_PREC_F64);
+    Labelled r{run_contraction(*p, *X.t, *Y.t, s), {}};
+    for (size_t i = 0; i < X.lab.size(); ++i)
+        if (std::find(la.begin(), la.end(), (int)i) == la.end()) r.lab.push_back(X.lab[i]);
+    for (size_t j = 0; j < Y.lab.size(); ++j)
+        if (std::find(lb.begin(), lb.end(), (int)j) == lb.end()) r.lab.push_back(Y.lab[j]);
+    return r;
+}
+
+// Z_nm: the four corners with n columns and m rows of edge tensors between
+// them and the n x m site tensors a inside (n, m <= 2), contracted in FP64.
+// Bonds: the chi bonds run C1 -h-> T1 .. T1 -> C2 -v-> T2 .. T2 -> C3 -g->
+// T3 (right to left) -> C4 -w-> T4 (bottom to top) -> C1; the D bonds are
+// vert(i, j) below row i of column j (row 0 = the T1 row) and hor(i, j) right
+// of column j in row i (column 0 = the T4 column).  C1's incoming bond stays
+// open until the end and closes as a trace.
+// sites (optional): n*m tensors replacing a, row i (top to bottom) major,
+// column j (left to right) minor.
+double zblock(const std::array<TensorPtr, 4>& C, const std::array<TensorPtr, 4>& T, const TensorPtr& a, int n,
+              int m, hipStream_t s, const TensorPtr* sites = nullptr) {
+    auto h = [](int j) { return 1000 + j; };
+    auto v = [](int i) { return 2000 + i; };
+    auto g = [](int j) { return 3000 + j; };
+    auto w = [](int i) { return 4000 + i; };
+    auto vert = [](int i, int j) { return 5000 + 100 * i + j; };
+    auto hor = [](int i, int j) { return 6000 + 100 * i + j; };
+    const int keep = w(m);
+    Labelled X{C[0], {w(m), h(0)}};
+    for (int j = 1; j <= n; ++j) X = join(X, {T[0], {h(j - 1), vert(0, j), h(j)}}, keep, s);
+    X = join(X, {C[1], {h(n), v(0)}}, keep, s);
+    for (int i = 1; i <= m; ++i) {
+        X = join(X, {T[1], {v(i - 1), hor(i, n), v(i)}}, keep, s);
+        for (int j = n; j >= 1; --j) {
+            const TensorPtr& site = sites ? sites[(i - 1) * n + (j - 1)] : a;
+            X = join(X, {site, {hor(i, j - 1), vert(i - 1, j), hor(i, j), vert(i, j)}}, keep, s);
+        }
+        X = join(X, {T[3], {w(m - i), hor(i, 0), w(m - i + 1)}}, keep, s);
+    }
+    X = join(X, {C[2], {v(m), g(0)}}, keep, s);
+    for (int j = n; j >= 1; --j) X = join(X, {T[2], {g(n - j), vert(m, j), g(n - j + 1)}}, keep, s);
+    X = join(X, {C[3], {g(n), w(0)}}, keep, s);
+    if (X.t->rank() != 2 || X.lab[0] != keep || X.lab[1] != keep) fail(SYMTEN_E_INVAL, "internal: network not closed");
+    return trace_u1(*X.t);
+}
+
+// Partition function per site of a classical model from the environment of a
+// 1x1 cell, estimated on a b x b block: kappa^(b^2) = Z_bb Z_00 / (Z_b0 Z_0b),
+// the boundary factors cancelling in the ratio.  b = 2 also cancels the
+// corner weights when the environment bonds alternate between two charge
+// parities from one site to the next (every D charge odd): with one column or
+// row the corners of the two parity copies pair up unequally.  z receives
+// Z_00, Z_b0, Z_0b, Z_bb.
+double site_partition(ctm_env* env, const TensorPtr& a_in, int b, double z[4], hipStream_t s) {
+    std::array<TensorPtr, 4> C, T;
+    for (int i = 0; i < 4; ++i) {
+        C[i] = as_f64(env->C[i], s);
+        T[i] = as_f64(env->T[i], s);
+    }
+    TensorPtr a = as_f64(a_in, s);
+    z[0] = zblock(C, T, a, 0, 0, s);
+    z[1] = zblock(C, T, a, b, 0, s);
+    z[2] = zblock(C, T, a, 0, b, s);
+    z[3] = zblock(C, T, a, b, b, s);
+    const double den = z[1] * z[2];
+    if (den == 0.0 || !std::isfinite(den)) fail(SYMTEN_E_LINALG, "site partition: vanishing normalisation");
+    const double r = z[3] * z[0] / den;
+    if (b == 1) return r;
+    if (!(r > 0.0)) fail(SYMTEN_E_LINALG, "site partition: non-positive block ratio");
+    return std::pow(r, 1.0 / (b * b));
+}
+
+std::array<TensorPtr, 4> env_f64(const TensorPtr* X, hipStream_t s) {
+    std::array<TensorPtr, 4> r;
+    for (int i = 0; i < 4; ++i) r[i] = as_f64(X[i], s);
+    return r;
+}
+
+// <O> = Z_nm(sites) / Z_nm(a): the n x m patch with its site tensors replaced
+// (row-major), in FP64.
+double expectation(ctm_env* env, const TensorPtr& a, int n, int m, const std::vector<TensorPtr>& sites,
+                   hipStream_t s) {
+    std::array<TensorPtr, 4> C = env_f64(env->C, s), T = env_f64(env->T, s);
+    TensorPtr a64 = as_f64(a, s);
+    std::vector<TensorPtr> b;
+    for (const auto& x : sites) b.push_back(as_f64(x, s));
+    const double z = zblock(C, T, a64, n, m, s);
+    if (z == 0.0 || !std::isfinite(z)) fail(SYMTEN_E_LINALG, "expectation: vanishing normalisation");
+    return zblock(C, T, a64, n, m, s, b.data()) / z;
+}
+}  // namespace
+}  // namespace symten
+
+namespace symten {
+namespace {
+// One U(1) left move on the environment's current tensors (see ctm_move).
+void move_u1_left(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st, hipStream_t s) {
+    const bool f64 = prec == SYMTEN_PREC_F64;
+    Timer tm;
+    tm.init(st != nullptr);
+    tm.mark(s);
+    Tensor &C1 = *env->C[0], &C2 = *env->C[1], &C3 = *env->C[2], &C4 = *env->C[3];
+    Tensor &T1 = *env->T[0], &T2 = *env->T[1], &T3 = *env->T[2], &T4 = *env->T[3];
+    // the four corners are independent: each of their three steps is one
+    // gather launch and one grouped-GEMM launch for all four
+    std::vector<CornerResult> ks =
+        corners_batched({1, 2, 3, 4}, {{&C1, &T1, &T4}, {&C2, &T1, &T2}, {&C3, &T3, &T2}, {&C4, &T3, &T4}}, a,
+                        prec, s);
+    CornerResult &k1 = ks[0], &k2 = ks[1], &k3 = ks[2], &k4 = ks[3];
+    tm.mark(s);
+    // halves: H_u = C~1 C~2 -> [x4, d, x2, d2]; H_d = C~4 C~3 -> [x4, u, x2, u3]
+    std::vector<Contracted> hh = contract_batched({{k1.corner.get(), k2.corner.get(), {0, 2}, {0, 2}, {}},
+                                                   {k4.corner.get(), k3.corner.get(), {0, 3}, {0, 2}, {}}},
+                                                  prec, s);
+    Contracted &hu = hh[0], &hd = hh[1];
+    tm.mark(s);
+
+    // ---- projectors, per fused charge Q of the left cut (FP64) ----------
+    std::map<int, const GroupPlan*> gu_of, gd_of;
+    for (auto& g : hu.plan->groups) gu_of[g.rows[0][0] - g.rows[0][1]] = &g;
+    for (auto& g : hd.plan->groups) gd_of[g.rows[0][0] - g.rows[0][1]] = &g;
+    const size_t es = f64 ? 8 : 4;
+    const Leg& chiL = T4.legs[0];
+    const Leg& dL = a.legs[3];
+    // The rows of both halves are the (q_chi, q_D) blocks of the cut reached
+    // by their contractions; where the two sets differ, both halves are laid
+    // out over the union (rows missing on one side are zero).
+    std::vector<CutSector> secs;
+    std::map<int, std::vector<std::vector<int>>> rows_of;   // Q -> union rows
+    std::map<int, std::map<std::vector<int>, int>> row_off_of;
+    std::vector<BufferPtr> row_bufs;
+    std::vector<CopyTask> row_tasks[2];
+    int64_t row_elems[2] = {0, 0};
+    struct Pending { size_t sec; int side; int64_t off; };
+    std::vector<Pending> pending;
+    for (auto& kv : gu_of) {
+        auto it = gd_of.find(kv.first);
+        if (it == gd_of.end()) continue;   // no weight on one side: nothing to keep
+        const GroupPlan* gs[2] = {kv.second, it->second};
+        std::vector<std::vector<int>> rows = gs[0]->rows;
+        rows.insert(rows.end(), gs[1]->rows.begin(), gs[1]->rows.end());
+        std::sort(rows.begin(), rows.end());
+        rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+        std::map<std::vector<int>, int> roff;
+        int n = 0;
+        for (auto& r : rows) {
+            roff[r] = n;
+            n += chiL.dim_of(r[0]) * dL.dim_of(r[1]);
+        }
+        CutSector c;
+        c.key = kv.first;
+        c.weight = 1;
+        c.n = n;
+        c.mu = gs[0]->N;
+        c.md = gs[1]->N;
+        for (int side = 0; side < 2; ++side) {
+            const GroupPlan* g = gs[side];
+            const Tensor& H = side == 0 ? *hu.t : *hd.t;
+            const void* base = (const char*)H.data() + g->c_off * es;
+            if (g->rows == rows) {
+                (side == 0 ? c.hu : c.hd) = base;
+                continue;
+            }
+            // copy the present row blocks into a zeroed union-row matrix
+            const int m = g->N;
+            for (size_t r = 0; r < g->rows.size(); ++r) {
+                const int rd = chiL.dim_of(g->rows[r][0]) * dL.dim_of(g->rows[r][1]);
+                row_tasks[side].push_back(make_copy_task(0, g->c_off + (int64_t)g->row_off[r] * m, 1,
+                                                         row_elems[side] + (int64_t)roff[g->rows[r]] * m,
+                                                         {rd, m}, {m, 1}, {m, 1}));
+                row_tasks[side].back().src_buf = side;   // 0: H_u, 1: H_d
+                row_tasks[side].back().dst_buf = 2 + side;
+            }
+            pending.push_back({secs.size(), side, row_elems[side]});
+            row_elems[side] += (int64_t)n * m;
+        }
+        rows_of[c.key] = rows;
+        row_off_of[c.key] = roff;
+        secs.push_back(c);
+    }
+    if (!pending.empty()) {
+        BufferPtr ub[2];
+        for (int side = 0; side < 2; ++side) {
+            ub[side] = device_alloc(std::max<int64_t>(row_elems[side], 1) * es);
+            launch_fill_zero(ub[side]->ptr, ((std::max<int64_t>(row_elems[side], 1) * es + 3) / 4) * 4, s);
+            row_bufs.push_back(ub[side]);
+        }
+        std::vector<CopyTask> tasks = row_tasks[0];
+        tasks.insert(tasks.end(), row_tasks[1].begin(), row_tasks[1].end());
+        validate_tasks(tasks, {hu.t->elems, hd.t->elems, std::max<int64_t>(row_elems[0], 1),
+                               std::max<int64_t>(row_elems[1], 1)});
+        std::vector<int64_t> prefix;
+        copy_prefix(tasks, prefix);
+        BufferPtr dt, dp;
+        upload_sync(dt, tasks.data(), tasks.size() * sizeof(CopyTask));
+        upload_sync(dp, prefix.data(), prefix.size() * sizeof(int64_t));
+        copy_launch_arg((const CopyTask*)dt->ptr, (const int64_t*)dp->ptr, (int)tasks.size(), prefix.back(),
+                        {hu.t->data(), hd.t->data(), ub[0]->ptr, ub[1]->ptr}, f64, f64 ? 1 : 0, s);
+        row_bufs.push_back(dt);
+        row_bufs.push_back(dp);
+        for (auto& pd : pending)
+            (pd.side == 0 ? secs[pd.sec].hu : secs[pd.sec].hd) = (const char*)ub[pd.side]->ptr + pd.off * es;
+    }
+    ProjOut po = cut_projectors(env, secs, chi, f64, s);
+    // ---- projector tensors P[chi out, D in, k in], P~[k out, chi in, D out]
+    auto P = std::make_shared<Tensor>();
+    auto Pt = std::make_shared<Tensor>();
+    for (auto* X : {P.get(), Pt.get()}) {
+        X->group = SYMTEN_U1;
+        X->flux = 0;
+        X->dtype = SYMTEN_F64;
+    }
+    Leg kin, kout;
+    kin.dir = 1;
+    kout.dir = -1;
+    for (auto& c : secs)
+        if (c.k > 0) { kin.q.push_back(c.key); kin.d.push_back(c.k); }
+    kout.q = kin.q;
+    kout.d = kin.d;
+    Leg chi_out = chiL, chi_in = chiL, d_in = dL, d_out = dL;
+    chi_out.dir = -1;
+    chi_in.dir = 1;
+    d_in.dir = 1;
+    d_out.dir = -1;
+    P->legs = {chi_out, d_in, kin};
+    Pt->legs = {kout, chi_in, d_out};
+    const int64_t ptot = po.ptot;
+    P->buf = po.P;
+    Pt->buf = po.Pt;
+    P->elems = Pt->elems = ptot;
+    P->meta_only = Pt->meta_only = false;
+    for (auto& c : secs) {
+        if (c.k == 0) continue;
+        const int Q = c.key, n = c.n, k = c.k;
+        // blocks: one per (q_chi, q_D) row sub-block of this sector
+        for (const auto& row : rows_of[Q]) {
+            const int qx = row[0], qd = row[1];
+            const int dx = chiL.dim_of(qx), dd = dL.dim_of(qd);
+            const int64_t ro = row_off_of[Q][row];
+            Block pb;
+            pb.q = {qx, qd, Q};
+            pb.shape = {dx, dd, k};
+            pb.stride = {dd, 1, n};
+            pb.offset = c.pbase + ro;
+            pb.size = (int64_t)dx * dd * k;
+            P->blocks.push_back(pb);
+            Block tb;
+            tb.q = {Q, qx, qd};
+            tb.shape = {k, dx, dd};
+            tb.stride = {1, (int64_t)dd * k, k};
+            tb.offset = c.pbase + ro * k;
+            tb.size = pb.size;
+            Pt->blocks.push_back(tb);
+        }
+    }
+    for (auto* X : {P.get(), Pt.get()}) {
+        std::sort(X->blocks.begin(), X->blocks.end(), [](const Block& x, const Block& y) { return x.q < y.q; });
+        X->rebuild_index();
+    }
+    TensorPtr Pc = P, Ptc = Pt;
+    if (!f64) {
+        Pc = std::make_shared<Tensor>(*P);
+        Ptc = std::make_shared<Tensor>(*Pt);
+        Pc->dtype = Ptc->dtype = SYMTEN_F32;
+        Pc->buf = device_alloc(4 * std::max<int64_t>(ptot, 1));
+        Ptc->buf = device_alloc(4 * std::max<int64_t>(ptot, 1));
+        launch_cast(P->buf->ptr, true, Pc->buf->ptr, false, ptot, s);
+        launch_cast(Pt->buf->ptr, true, Ptc->buf->ptr, false, ptot, s);
+    }
+    tm.mark(s);
+    // ---- renormalise -----------------------------------------------------
+    // T4' = ((P~ T4) a) P: absorbing P~ first keeps the intermediates at
+    // chi' chi D^4 instead of the chi^2 D^6 of T4 a.
+    std::vector<Contracted> r3 =
+        contract_batched({{k1.step1.get(), Pc.get(), {0, 1}, {0, 1}, {1, 0}},      // C1' = [k, x1]
+                          {k4.step1.get(), Ptc.get(), {0, 2}, {1, 2}, {}},         // C4' = [x3, k]
+                          {Ptc.get(), &T4, {1}, {2}, {}}},                         // P~ T4 = [k_hi, u, y, l]
+                         prec, s);
+    Contracted &c1n = r3[0], &c4n = r3[1], &t4a = r3[2];
+    Contracted xx = contract(*t4a.t, a, {1, 3}, {1, 0}, {}, prec, s);               // [k_hi, y, r, d]
+    Contracted t4n = contract(*xx.t, *Pc, {1, 3}, {0, 1}, {2, 1, 0}, prec, s);      // [k_lo, r, k_hi]
+    // ---- normalise in FP64 ----------------------------------------------
+    BufferPtr red = device_alloc(8 * (1 + 512));
+    for (TensorPtr X : {c1n.t, t4n.t, c4n.t}) {
+        launch_sumsq(X->data(), f64, X->elems, (double*)red->ptr, s);
+        launch_scale_by_inv_sqrt(X->data(), f64, X->elems, (const double*)red->ptr, s);
+    }
+    tm.mark(s);
+    env->C[0] = c1n.t;
+    env->T[3] = t4n.t;
+    env->C[3] = c4n.t;
+    env->P.t = P;
+    env->Pt.t = Pt;
+    env->svals = po.sv;
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        HIPCHK(hipStreamSynchronize(s));
+        fill_cut_stats(st, secs, po);
+        st->flops_corners = k1.info.useful_flops + k2.info.useful_flops + k3.info.useful_flops + k4.info.useful_flops;
+        st->flops_halves = hu.plan->info.useful_flops + hd.plan->info.useful_flops;
+        st->flops_renorm = c1n.plan->info.useful_flops + t4a.plan->info.useful_flops + xx.plan->info.useful_flops +
+                           t4n.plan->info.useful_flops + c4n.plan->info.useful_flops;
+
         st->ms_corners = tm.ms(0, 1);
         st->ms_halves = tm.ms(1, 2);
         st->ms_proj = tm.ms(2, 3);
@@ -1511,7 +1929,7 @@ int ctm_move_projectors(ctm_env_t env, symten_t* P, symten_t* Pt) {
 int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_stats* st, void* stream) {
     return guard([&] {
         if (!env) fail(SYMTEN_E_INVAL, "null environment");
-        if (dir != CTM_LEFT) fail(SYMTEN_E_UNSUPPORTED, "only the left move is implemented");
+        if (dir < CTM_LEFT || dir > CTM_BOTTOM) fail(SYMTEN_E_INVAL, "ctm_move: direction must be 0..3");
         if (chi < 1) fail(SYMTEN_E_INVAL, "chi must be positive");
         Tensor& a = T(a_h);
         check_device_tensor(a, "ctm_move(a)");
@@ -1526,158 +1944,157 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
                 fail(SYMTEN_E_SYM, "ctm_move: environment and site tensor have different symmetry groups");
         }
         if (a.group == SYMTEN_SU2) {
+            if (dir != CTM_LEFT) fail(SYMTEN_E_UNSUPPORTED, "ctm_move: SU(2) moves are left moves only");
             move_su2(env, a, chi, prec, st, s);
             return;
         }
-        Timer tm;
-        tm.init(st != nullptr);
-        tm.mark(s);
-        Tensor &C1 = *env->C[0], &C2 = *env->C[1], &C3 = *env->C[2], &C4 = *env->C[3];
-        Tensor &T1 = *env->T[0], &T2 = *env->T[1], &T3 = *env->T[2], &T4 = *env->T[3];
-        // the four corners are independent: each of their three steps is one
-        // gather launch and one grouped-GEMM launch for all four
-        std::vector<CornerResult> ks =
-            corners_batched({1, 2, 3, 4}, {{&C1, &T1, &T4}, {&C2, &T1, &T2}, {&C3, &T3, &T2}, {&C4, &T3, &T4}}, a,
-                            prec, s);
-        CornerResult &k1 = ks[0], &k2 = ks[1], &k3 = ks[2], &k4 = ks[3];
-        tm.mark(s);
-        // halves: H_u = C~1 C~2 -> [x4, d, x2, d2]; H_d = C~4 C~3 -> [x4, u, x2, u3]
-        std::vector<Contracted> hh = contract_batched({{k1.corner.get(), k2.corner.get(), {0, 2}, {0, 2}, {}},
-                                                       {k4.corner.get(), k3.corner.get(), {0, 3}, {0, 2}, {}}},
-                                                      prec, s);
-        Contracted &hu = hh[0], &hd = hh[1];
-        tm.mark(s);
+        if (dir == CTM_LEFT) {
+            move_u1_left(env, a, chi, prec, st, s);
+            return;
+        }
+        // the other directions: the left move of the network turned by `dir`
+        // quarter turns counterclockwise, then turned back
+        std::array<TensorPtr, 4> C{env->C[0], env->C[1], env->C[2], env->C[3]};
+        std::array<TensorPtr, 4> Tt{env->T[0], env->T[1], env->T[2], env->T[3]};
+        TensorPtr ar = a_h->t;
+        for (int r = 0; r < dir; ++r) rotate_ccw(C, Tt, ar);
+        for (int i = 0; i < 4; ++i) { env->C[i] = C[i]; env->T[i] = Tt[i]; }
+        try {
+            move_u1_left(env, *ar, chi, prec, st, s);
+        } catch (...) {
+            for (int r = dir; r < 4; ++r) rotate_ccw(C, Tt, ar);
+            for (int i = 0; i < 4; ++i) { env->C[i] = C[i]; env->T[i] = Tt[i]; }
+            throw;
+        }
+        for (int i = 0; i < 4; ++i) { C[i] = env->C[i]; Tt[i] = env->T[i]; }
+        for (int r = dir; r < 4; ++r) rotate_ccw(C, Tt, ar);
+        for (int i = 0; i < 4; ++i) { env->C[i] = C[i]; env->T[i] = Tt[i]; }
+    });
+}
 
-        // ---- projectors, per fused charge Q of the left cut (FP64) ----------
-        std::map<int, const GroupPlan*> gu_of, gd_of;
-        for (auto& g : hu.plan->groups) gu_of[g.rows[0][0] - g.rows[0][1]] = &g;
-        for (auto& g : hd.plan->groups) gd_of[g.rows[0][0] - g.rows[0][1]] = &g;
-        const size_t es = f64 ? 8 : 4;
-        std::vector<CutSector> secs;
-        for (auto& kv : gu_of) {
-            auto it = gd_of.find(kv.first);
-            if (it == gd_of.end()) continue;   // no weight on one side: nothing to keep
-            const GroupPlan* gu = kv.second;
-            const GroupPlan* gd = it->second;
-            if (gu->rows != gd->rows || gu->cols != gd->cols || gu->M != gd->M || gu->N != gd->N)
-                fail(SYMTEN_E_SYM, "ctm_move: upper and lower halves disagree on a cut basis");
-            CutSector c;
-            c.key = kv.first;
-            c.weight = 1;
-            c.n = gu->M;
-            c.m = gu->N;
-            c.hu = (const char*)hu.t->data() + gu->c_off * es;
-            c.hd = (const char*)hd.t->data() + gd->c_off * es;
-            secs.push_back(c);
+int ctm_site_partition(ctm_env_t env, symten_t a, int block, double* kappa, double* z, void* stream) {
+    return guard([&] {
+        if (!env || !kappa) fail(SYMTEN_E_INVAL, "null argument");
+        if (block != 1 && block != 2) fail(SYMTEN_E_INVAL, "block must be 1 or 2");
+        Tensor& at = T(a);
+        check_device_tensor(at, "ctm_site_partition(a)");
+        if (at.group != SYMTEN_U1 || env->C[0]->group != SYMTEN_U1)
+            fail(SYMTEN_E_UNSUPPORTED, "ctm_site_partition: U(1) tensors only");
+        if (at.rank() != 4) fail(SYMTEN_E_INVAL, "a must have rank 4");
+        double zz[4];
+        *kappa = site_partition(env, a->t, block, zz, S(stream));
+        if (z) std::copy(zz, zz + 4, z);
+    });
+}
+
+int ctm_expectation(ctm_env_t env, symten_t a, int n, int m, const symten_t* sites, double* value, void* stream) {
+    return guard([&] {
+        if (!env || !sites || !value) fail(SYMTEN_E_INVAL, "null argument");
+        if (n < 1 || m < 1 || n > 2 || m > 2) fail(SYMTEN_E_INVAL, "ctm_expectation: patch of 1 or 2 columns and rows");
+        Tensor& at = T(a);
+        check_device_tensor(at, "ctm_expectation(a)");
+        if (at.group != SYMTEN_U1 || env->C[0]->group != SYMTEN_U1)
+            fail(SYMTEN_E_UNSUPPORTED, "ctm_expectation: U(1) tensors only");
+        std::vector<TensorPtr> b;
+        for (int k = 0; k < n * m; ++k) {
+            Tensor& bt = T(sites[k]);
+            check_device_tensor(bt, "ctm_expectation(site)");
+            if (bt.group != SYMTEN_U1 || bt.rank() != 4) fail(SYMTEN_E_INVAL, "ctm_expectation: sites are rank-4 U(1) tensors");
+            for (int l = 0; l < 4; ++l)
+                if (bt.legs[l].dir != at.legs[l].dir || bt.legs[l].q != at.legs[l].q || bt.legs[l].d != at.legs[l].d)
+                    fail(SYMTEN_E_LEGS, "ctm_expectation: a site's legs differ from a's");
+            b.push_back(sites[k]->t);
         }
-        ProjOut po = cut_projectors(env, secs, chi, f64, s);
-        // ---- projector tensors P[chi out, D in, k in], P~[k out, chi in, D out]
-        const Leg& chiL = T4.legs[0];
-        const Leg& dL = a.legs[3];
-        auto P = std::make_shared<Tensor>();
-        auto Pt = std::make_shared<Tensor>();
-        for (auto* X : {P.get(), Pt.get()}) {
-            X->group = SYMTEN_U1;
-            X->flux = 0;
-            X->dtype = SYMTEN_F64;
-        }
-        Leg kin, kout;
-        kin.dir = 1;
-        kout.dir = -1;
-        for (auto& c : secs)
-            if (c.k > 0) { kin.q.push_back(c.key); kin.d.push_back(c.k); }
-        kout.q = kin.q;
-        kout.d = kin.d;
-        Leg chi_out = chiL, chi_in = chiL, d_in = dL, d_out = dL;
-        chi_out.dir = -1;
-        chi_in.dir = 1;
-        d_in.dir = 1;
-        d_out.dir = -1;
-        P->legs = {chi_out, d_in, kin};
-        Pt->legs = {kout, chi_in, d_out};
-        const int64_t ptot = po.ptot;
-        P->buf = po.P;
-        Pt->buf = po.Pt;
-        P->elems = Pt->elems = ptot;
-        P->meta_only = Pt->meta_only = false;
-        for (auto& c : secs) {
-            if (c.k == 0) continue;
-            const int Q = c.key, n = c.n, k = c.k;
-            // blocks: one per (q_chi, q_D) row sub-block of this sector
-            const GroupPlan* g = gu_of[Q];
-            for (size_t r = 0; r < g->rows.size(); ++r) {
-                const int qx = g->rows[r][0], qd = g->rows[r][1];
-                const int dx = chiL.dim_of(qx), dd = dL.dim_of(qd);
-                Block pb;
-                pb.q = {qx, qd, Q};
-                pb.shape = {dx, dd, k};
-                pb.stride = {dd, 1, n};
-                pb.offset = c.pbase + g->row_off[r];
-                pb.size = (int64_t)dx * dd * k;
-                P->blocks.push_back(pb);
-                Block tb;
-                tb.q = {Q, qx, qd};
-                tb.shape = {k, dx, dd};
-                tb.stride = {1, (int64_t)dd * k, k};
-                tb.offset = c.pbase + (int64_t)g->row_off[r] * k;
-                tb.size = pb.size;
-                Pt->blocks.push_back(tb);
+        *value = expectation(env, a->t, n, m, b, S(stream));
+    });
+}
+
+int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e_v, void* stream) {
+    return guard([&] {
+        if (!env || !e_h || !e_v) fail(SYMTEN_E_INVAL, "null argument");
+        Tensor& At = T(A);
+        check_device_tensor(At, "ctm_heisenberg_bond_energy(A)");
+        if (At.group != SYMTEN_U1 || At.rank() != 5)
+            fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: A is a rank-5 U(1) tensor");
+        // physical states: charges 2m = -2S, -2S+2, ..., 2S, one state each
+        const Leg& ph = At.legs[0];
+        const int np = ph.size();
+        if (np < 2 || np > kMaxOpStates) fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: spin 1/2 .. 7/2");
+        for (int k = 0; k < np; ++k)
+            if ((int)ph.q.size() != np || ph.d[k] != 1 || ph.q[k] != -(np - 1) + 2 * k)
+                fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: physical charges must be 2m, m = -S..S");
+        const double S2 = 0.5 * (np - 1);
+        std::vector<double> sz(np * np, 0.0), sp(np * np, 0.0), sm(np * np, 0.0);
+        for (int k = 0; k < np; ++k) {
+            const double mz = -S2 + k;
+            sz[k * np + k] = mz;
+            if (k + 1 < np) {
+                const double c = std::sqrt(S2 * (S2 + 1.0) - mz * (mz + 1.0));
+                sp[(k + 1) * np + k] = c;       // <m+1| S+ |m>
+                sm[k * np + (k + 1)] = c;       // <m| S- |m+1>
             }
         }
-        for (auto* X : {P.get(), Pt.get()}) {
-            std::sort(X->blocks.begin(), X->blocks.end(), [](const Block& x, const Block& y) { return x.q < y.q; });
-            X->rebuild_index();
-        }
-        TensorPtr Pc = P, Ptc = Pt;
-        if (!f64) {
-            Pc = std::make_shared<Tensor>(*P);
-            Ptc = std::make_shared<Tensor>(*Pt);
-            Pc->dtype = Ptc->dtype = SYMTEN_F32;
-            Pc->buf = device_alloc(4 * std::max<int64_t>(ptot, 1));
-            Ptc->buf = device_alloc(4 * std::max<int64_t>(ptot, 1));
-            launch_cast(P->buf->ptr, true, Pc->buf->ptr, false, ptot, s);
-            launch_cast(Pt->buf->ptr, true, Ptc->buf->ptr, false, ptot, s);
-        }
-        tm.mark(s);
-        // ---- renormalise -----------------------------------------------------
-        // T4' = ((P~ T4) a) P: absorbing P~ first keeps the intermediates at
-        // chi' chi D^4 instead of the chi^2 D^6 of T4 a.
-        std::vector<Contracted> r3 =
-            contract_batched({{k1.step1.get(), Pc.get(), {0, 1}, {0, 1}, {1, 0}},      // C1' = [k, x1]
-                              {k4.step1.get(), Ptc.get(), {0, 2}, {1, 2}, {}},         // C4' = [x3, k]
-                              {Ptc.get(), &T4, {1}, {2}, {}}},                         // P~ T4 = [k_hi, u, y, l]
-                             prec, s);
-        Contracted &c1n = r3[0], &c4n = r3[1], &t4a = r3[2];
-        Contracted xx = contract(*t4a.t, a, {1, 3}, {1, 0}, {}, prec, s);               // [k_hi, y, r, d]
-        Contracted t4n = contract(*xx.t, *Pc, {1, 3}, {0, 1}, {2, 1, 0}, prec, s);      // [k_lo, r, k_hi]
-        // ---- normalise in FP64 ----------------------------------------------
-        BufferPtr red = device_alloc(8 * (1 + 512));
-        for (TensorPtr X : {c1n.t, t4n.t, c4n.t}) {
-            launch_sumsq(X->data(), f64, X->elems, (double*)red->ptr, s);
-            launch_scale_by_inv_sqrt(X->data(), f64, X->elems, (const double*)red->ptr, s);
-        }
-        tm.mark(s);
-        env->C[0] = c1n.t;
-        env->T[3] = t4n.t;
-        env->C[3] = c4n.t;
-        env->P.t = P;
-        env->Pt.t = Pt;
-        env->svals = po.sv;
-        if (st) {
-            std::memset(st, 0, sizeof(*st));
-            HIPCHK(hipStreamSynchronize(s));
-            fill_cut_stats(st, secs, po);
-            st->flops_corners = k1.info.useful_flops + k2.info.useful_flops + k3.info.useful_flops + k4.info.useful_flops;
-            st->flops_halves = hu.plan->info.useful_flops + hd.plan->info.useful_flops;
-            st->flops_renorm = c1n.plan->info.useful_flops + t4a.plan->info.useful_flops + xx.plan->info.useful_flops +
-                               t4n.plan->info.useful_flops + c4n.plan->info.useful_flops;
+        hipStream_t s = S(stream);
+        TensorPtr a = double_layer(At, s);
+        TensorPtr bz = double_layer(At, s, sz.data()), bp = double_layer(At, s, sp.data()),
+                  bm = double_layer(At, s, sm.data());
+        // S_i . S_j = Sz Sz + (S+ S- + S- S+) / 2 on the pair (left, right) or (top, bottom)
+        auto bond = [&](int n, int m) {
+            return expectation(env, a, n, m, {bz, bz}, s) +
+                   0.5 * (expectation(env, a, n, m, {bp, bm}, s) + expectation(env, a, n, m, {bm, bp}, s));
+        };
+        *e_h = bond(2, 1);
+        *e_v = bond(1, 2);
+    });
+}
 
-            st->ms_corners = tm.ms(0, 1);
-            st->ms_halves = tm.ms(1, 2);
-            st->ms_proj = tm.ms(2, 3);
-            st->ms_renorm = tm.ms(3, 4);
-            st->ms_total = tm.ms(0, 4);
+int symten_double_layer_op(symten_t* b_out, symten_t A, const double* op, void* stream) {
+    return guard([&] {
+        if (!b_out || !op) fail(SYMTEN_E_INVAL, "null argument");
+        *b_out = wrap(double_layer(T(A), S(stream), op));
+    });
+}
+
+int ctm_run(ctm_env_t env, symten_t a, const ctm_run_opts* o, ctm_run_result* r, void* stream) {
+    return guard([&] {
+        if (!env || !o || !r) fail(SYMTEN_E_INVAL, "null argument");
+        if (o->chi < 1 || o->max_steps < 1 || (o->block != 1 && o->block != 2) || !(o->tol >= 0.0))
+            fail(SYMTEN_E_INVAL, "ctm_run: bad options");
+        Tensor& at = T(a);
+        check_device_tensor(at, "ctm_run(a)");
+        if (at.group != SYMTEN_U1 || env->C[0]->group != SYMTEN_U1)
+            fail(SYMTEN_E_UNSUPPORTED, "ctm_run: U(1) tensors only");
+        ctm_run_result res{};
+        double z[4], prev_level = 0.0;
+        for (int chi = o->chi;; chi *= 2) {
+            // steps at fixed chi until the value moves by less than tol, or max_steps
+            double v = site_partition(env, a->t, o->block, z, S(stream));
+            double d1 = 0.0, d2 = 0.0;          // the last two changes
+            int st = 0;
+            while (st < o->max_steps) {
+                for (int dir = CTM_LEFT; dir <= CTM_BOTTOM; ++dir) {
+                    const int rc = ctm_move(env, a, dir, chi, o->prec, nullptr, stream);
+                    if (rc != SYMTEN_OK) fail(rc, g_err);
+                }
+                ++st;
+                const double nv = site_partition(env, a->t, o->block, z, S(stream));
+                d2 = d1;
+                d1 = std::fabs(nv - v);
+                v = nv;
+                if (d1 < o->tol) break;
+            }
+            res.err_steps = std::max(d1, d2);
+            res.steps = st;
+            res.total_steps += st;
+            res.err_chi = res.levels > 0 ? std::fabs(v - prev_level) : 0.0;
+            res.kappa = v;
+            res.chi = chi;
+            ++res.levels;
+            if ((res.levels > 1 && res.err_chi < o->tol) || 2 * (int64_t)chi > o->chi_max) break;
+            prev_level = v;
         }
+        res.error = std::max(res.err_steps, res.err_chi);
+        *r = res;
     });
 }
 

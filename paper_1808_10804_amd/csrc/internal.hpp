@@ -160,6 +160,7 @@ void launch_sumsq(const void* x, bool f64, int64_t n, double* out, hipStream_t s
 void launch_scale_by_inv_sqrt(void* x, bool f64, int64_t n, const double* sumsq, hipStream_t s);
 
 // Double layer.  Fused-leg tables are device int arrays.
+constexpr int kMaxOpStates = 8;   // physical states of a one-site operator
 struct DoubleLayerArgs {
     const void* A_dense;   // [phys][D0][D1][D2][D3] dense copy of A (same dtype)
     int nphys, Dv[4];
@@ -173,6 +174,10 @@ struct DoubleLayerArgs {
     int64_t total;
     void* out;
     bool f64;
+    // optional one-site operator between the layers: out = sum over
+    // (s_bra, s_ket) of op[s_bra * nphys + s_ket] A[s_ket] (ket) A[s_bra] (bra)
+    bool has_op;
+    double op[kMaxOpStates * kMaxOpStates];
 };
 void launch_double_layer(const DoubleLayerArgs& a, hipStream_t s);
 // scatter of a contiguous-block tensor into a dense array
@@ -235,7 +240,10 @@ void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefi
 void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems);
 void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw);
 
-TensorPtr double_layer(const Tensor& A, hipStream_t stream);
+// op (may be null): nphys x nphys row-major over A's physical states,
+// op[s_bra][s_ket]; every non-zero entry must move the charge by the same
+// amount (the result's flux follows from it).
+TensorPtr double_layer(const Tensor& A, hipStream_t stream, const double* op = nullptr);
 // SU(2) double layer (S^z components, U(1) double layer, per-leg change to
 // the fused multiplet basis, reduction).
 TensorPtr double_layer_su2(const Tensor& A, hipStream_t stream);

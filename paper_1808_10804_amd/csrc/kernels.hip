@@ -704,7 +704,15 @@ __global__ __launch_bounds__(256) void double_layer_kernel(DoubleLayerArgs a) {
     const int64_t ok = k[0] * s3 + k[1] * s2 + k[2] * s1 + k[3];
     const int64_t ob = br[0] * s3 + br[1] * s2 + br[2] * s1 + br[3];
     double acc = 0.0;
-    for (int s = 0; s < a.nphys; ++s) acc = fma((double)Ad[s * s4 + ok], (double)Ad[s * s4 + ob], acc);
+    if (!a.has_op) {
+        for (int s = 0; s < a.nphys; ++s) acc = fma((double)Ad[s * s4 + ok], (double)Ad[s * s4 + ob], acc);
+    } else {
+        for (int sb = 0; sb < a.nphys; ++sb) {
+            double row = 0.0;
+            for (int sk = 0; sk < a.nphys; ++sk) row = fma(a.op[sb * a.nphys + sk], (double)Ad[sk * s4 + ok], row);
+            acc = fma(row, (double)Ad[sb * s4 + ob], acc);
+        }
+    }
     ((T*)a.out)[a.blk_off[b] + (i - a.blk_elem_start[b])] = (T)acc;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1156,15 +1157,39 @@ void double_layer_states(const Leg& v, std::vector<int>& ket, std::vector<int>& 
     }
 }
 
-TensorPtr double_layer(const Tensor& A, hipStream_t stream) {
-    if (A.group == SYMTEN_SU2) return double_layer_su2(A, stream);
+TensorPtr double_layer(const Tensor& A, hipStream_t stream, const double* op) {
+    if (A.group == SYMTEN_SU2) {
+        if (op) fail(SYMTEN_E_UNSUPPORTED, "double_layer: operators take U(1) tensors");
+        return double_layer_su2(A, stream);
+    }
     check_device_tensor(A, "double_layer");
     if (A.rank() != 5) fail(SYMTEN_E_INVAL, "double_layer: A must have rank 5 (phys, l, u, r, d)");
     const bool f64 = A.dtype == SYMTEN_F64;
+    const int np = A.legs[0].size();
+    // flux: sum_l dir_l (q_ket - q_bra) = dir_phys (q_s_bra - q_s_ket) for
+    // every non-zero op[s_bra][s_ket]
+    int flux = 0;
+    if (op) {
+        if (np > kMaxOpStates) fail(SYMTEN_E_INVAL, "double_layer: operator on more than 8 physical states");
+        std::vector<int> qs;
+        for (size_t k = 0; k < A.legs[0].q.size(); ++k)
+            for (int i = 0; i < A.legs[0].d[k]; ++i) qs.push_back(A.legs[0].q[k]);
+        bool any = false;
+        for (int sb = 0; sb < np; ++sb)
+            for (int sk = 0; sk < np; ++sk) {
+                const double v = op[sb * np + sk];
+                if (!std::isfinite(v)) fail(SYMTEN_E_INVAL, "double_layer: operator entry not finite");
+                if (v == 0.0) continue;
+                const int f = A.legs[0].dir * (qs[sb] - qs[sk]);
+                if (any && f != flux) fail(SYMTEN_E_SYM, "double_layer: operator does not move the charge by one amount");
+                flux = f;
+                any = true;
+            }
+    }
     // fused legs: Q = q_ket - q_bra, states ordered by Q, q_ket, (i_ket, i_bra)
     auto out = std::make_shared<Tensor>();
     out->group = SYMTEN_U1;
-    out->flux = 0;
+    out->flux = flux;
     out->dtype = A.dtype;
     std::vector<std::vector<int>> ket_of(4), bra_of(4);
     for (int l = 0; l < 4; ++l) {
@@ -1253,6 +1278,8 @@ TensorPtr double_layer(const Tensor& A, hipStream_t stream) {
     a.total = total;
     a.out = out->data();
     a.f64 = f64;
+    a.has_op = op != nullptr;
+    if (op) std::copy(op, op + np * np, a.op);
     launch_double_layer(a, stream);
     // the temporaries go back to the pool; keep ordering by syncing (small)
     HIPCHK(hipStreamSynchronize(stream));

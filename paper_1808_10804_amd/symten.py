@@ -210,6 +210,15 @@ def double_layer(A, stream=None):
     return Tensor(h)
 
 
+def double_layer_op(A, op, stream=None):
+    """Double layer with the one-site operator op[s_bra, s_ket] between the
+    layers (a d x d array over A's physical states in charge order)."""
+    o = np.ascontiguousarray(np.asarray(op, dtype=np.float64))
+    h = C.c_void_p()
+    check(lib().symten_double_layer_op(C.byref(h), A._h, o.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+    return Tensor(h)
+
+
 def enlarged_corner(which, Cc, Ta, Tb, a, prec="f32", stream=None):
     h = C.c_void_p()
     st = _lib.PlanStats()
@@ -281,6 +290,38 @@ class CtmEnv:
         check(lib().ctm_move(self._h, a._h, int(direction), int(chi), _prec(prec),
                              C.byref(st) if stats else None, _stream(stream)))
         return st.to_dict() if stats else None
+
+    def site_partition(self, a, block=1, stream=None):
+        """(kappa, [Z_00, Z_b0, Z_0b, Z_bb]) of a classical model on a
+        block x block patch (block 1 or 2), FP64."""
+        k = C.c_double()
+        z = (C.c_double * 4)()
+        check(lib().ctm_site_partition(self._h, a._h, int(block), C.byref(k), z, _stream(stream)))
+        return k.value, list(z)
+
+    def expectation(self, a, sites, n, m, stream=None):
+        """Z_nm(sites) / Z_nm(a) with the n x m patch's site tensors replaced
+        (row-major list), FP64."""
+        hs = (C.c_void_p * (n * m))(*[t._h for t in sites])
+        v = C.c_double()
+        check(lib().ctm_expectation(self._h, a._h, int(n), int(m), hs, C.byref(v), _stream(stream)))
+        return v.value
+
+    def heisenberg_bond_energy(self, A, stream=None):
+        """(e_h, e_v): <S_i . S_j> on a horizontal and a vertical bond, FP64."""
+        eh, ev = C.c_double(), C.c_double()
+        check(lib().ctm_heisenberg_bond_energy(self._h, A._h, C.byref(eh), C.byref(ev), _stream(stream)))
+        return eh.value, ev.value
+
+    def run(self, a, chi, chi_max=None, prec="f64", block=1, max_steps=15, tol=1e-8, stream=None):
+        """CTM steps with the error estimate of Sec. 3: returns a dict with
+        kappa, err_steps, err_chi, error, steps, total_steps, chi, levels.
+        chi_max None: chi stays fixed."""
+        o = _lib.RunOpts(int(chi), int(chi if chi_max is None else chi_max), _prec(prec), int(block),
+                         int(max_steps), float(tol))
+        r = _lib.RunResult()
+        check(lib().ctm_run(self._h, a._h, C.byref(o), C.byref(r), _stream(stream)))
+        return r.to_dict()
 
     def singular_values(self):
         n = C.c_int64()

@@ -177,3 +177,16 @@ def test_error_codes():
         st.Tensor.meta([({0: 1}, 2)], flux=0)
     with pytest.raises(st.SymtenError):
         st.Tensor.meta([({0: -1}, 1)], flux=0)
+
+
+def test_ctm_entry_points_reject_bad_arguments():
+    """Argument checks of the CTM driver entry points run before any device
+    work: null environments, a bad patch size and bad run options."""
+    import ctypes as C
+    from paper_1808_10804_amd import _lib
+    L = _lib.lib()
+    k = C.c_double()
+    assert L.ctm_site_partition(None, None, 1, C.byref(k), None, None) == -1
+    assert L.ctm_run(None, None, None, None, None) == -1
+    o, r = _lib.RunOpts(8, 8, 0, 3, 15, 1e-8), _lib.RunResult()
+    assert L.ctm_run(None, None, C.byref(o), C.byref(r), None) == -1

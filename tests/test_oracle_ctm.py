@@ -156,3 +156,102 @@ def test_square_ice_entropy(block):
     C, T = ctm.initial_environment()
     _, _, r = ctm.run(C, T, a, 8, block=block, max_steps=300, tol=1e-9)
     assert abs(r["kappa"] - W_ICE) <= 1e-3 * W_ICE
+
+
+# ------------------------------------------------ expectation values (Sec. 3)
+def _u1_state(seed, virt={-1: 1, 0: 1, 1: 1}):
+    """A random U(1) site tensor A[phys, l, u, r, d] with spin-1/2 physical
+    states, dense embedding (flux +1)."""
+    legs = [u1.Leg({-1: 1, 1: 1}, u1.IN)] + [u1.Leg(virt, d) for d in (u1.IN, u1.IN, u1.OUT, u1.OUT)]
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal([l.size for l in legs]) * u1.conserving_mask(legs, 1)
+    return A, legs
+
+
+def test_operator_double_layer_pins():
+    """Identity between the layers gives the double layer; the trace over
+    every (ket, bra) pair is sum op[t, k] <A_k, A_t> (the Gram matrix of the
+    physical slices); an operator that raises the charge by 2 gives a tensor
+    whose non-zero entries all carry fused flux +2."""
+    A, legs = _u1_state(5)
+    a, a_legs = u1.double_layer(A, legs)
+    sz, sp, sm = u1.spin_operators(legs[0])
+    assert np.allclose(sz, np.diag([-0.5, 0.5])) and np.allclose(sp, [[0, 0], [1, 0]]) and np.allclose(sm, sp.T)
+    assert np.allclose(u1.double_layer_op(A, legs, np.eye(2)), a, rtol=0, atol=1e-14)
+    G = np.einsum("kabcd,tabcd->kt", A, A)
+    rng = np.random.default_rng(6)
+    op = rng.standard_normal((2, 2))
+    b = u1.double_layer_op(A, legs, op)
+    n = [l.size for l in legs[1:]]
+    perms = [u1.fuse(l, l, +1, -1, l.dir)[1] for l in legs[1:]]
+    b8 = np.zeros([x * x for x in n])
+    b8[np.ix_(*perms)] = b
+    b8 = b8.reshape(n[0], n[0], n[1], n[1], n[2], n[2], n[3], n[3])
+    assert np.isclose(np.einsum("aabbccdd->", b8), np.sum(op * G.T), rtol=1e-13)
+    bp = u1.double_layer_op(A, legs, sp)
+    assert np.count_nonzero(bp) > 0
+    assert np.all(bp[~u1.conserving_mask(a_legs, 2)] == 0)
+
+
+def test_heisenberg_ferromagnet_product_state():
+    """D = 1 with every spin up (or down): the product state is exact with the
+    trivial environment and <S_i . S_j> = 1/4 on both bonds."""
+    for q in (1, -1):
+        legs = [u1.Leg({-1: 1, 1: 1}, u1.IN)] + [u1.Leg({0: 1}, d) for d in (u1.IN, u1.IN, u1.OUT, u1.OUT)]
+        A = np.zeros((2, 1, 1, 1, 1))
+        A[(q + 1) // 2] = 1.7
+        C, T = [np.ones((1, 1))] * 4, [np.ones((1, 1, 1))] * 4
+        eh, ev = ctm.heisenberg_bond_energy(C, T, A, legs)
+        assert np.isclose(eh, 0.25, rtol=1e-14) and np.isclose(ev, 0.25, rtol=1e-14)
+
+
+def test_heisenberg_su2_invariant_state():
+    """An SU(2)-invariant site tensor (from the SU(2) oracle, expanded to
+    S^z states) in the traced open boundary: the two-site reduced state is a
+    singlet-triplet mixture, so <S+ S-> + <S- S+> = 4 <Sz Sz> on each bond,
+    <Sz> = 0 on a site, and the bond energy is 3 <Sz Sz>."""
+    from oracle import su2
+    v = {0: 1, 1: 1}
+    sl = [su2.Leg({1: 1}, su2.IN)] + [su2.Leg(v, d) for d in (su2.IN, su2.IN, su2.OUT, su2.OUT)]
+    vals = np.random.default_rng(7).standard_normal(su2.nnz(sl))
+    A, legs = su2.to_u1(su2.expand(sl, vals), sl)
+    a, a_legs = u1.double_layer(A, legs)
+    C, T = _identity_env_from(legs)
+    sz, sp, sm = u1.spin_operators(legs[0])
+    bz, bp, bm = (u1.double_layer_op(A, legs, o) for o in (sz, sp, sm))
+    assert abs(ctm.expectation(C, T, a, [bz], 1, 1)) < 1e-13
+    for n, m in ((2, 1), (1, 2)):
+        zz = ctm.expectation(C, T, a, [bz, bz], n, m)
+        pm = ctm.expectation(C, T, a, [bp, bm], n, m) + ctm.expectation(C, T, a, [bm, bp], n, m)
+        assert abs(zz) > 1e-3
+        assert np.isclose(pm, 4 * zz, rtol=1e-11)
+    eh, ev = ctm.heisenberg_bond_energy(C, T, A, legs)
+    assert np.isclose(eh, 3 * ctm.expectation(C, T, a, [bz, bz], 2, 1), rtol=1e-11)
+    assert np.isclose(ev, 3 * ctm.expectation(C, T, a, [bz, bz], 1, 2), rtol=1e-11)
+
+
+def _identity_env_from(A_legs):
+    """chi = 1 environment pairing ket and bra states on every D^2 leg (the
+    traced open boundary), in the fused order of the double layer."""
+    Ts = []
+    # T1 meets a's up leg, T2 the right, T3 the down, T4 the left leg
+    for l in (A_legs[2], A_legs[3], A_legs[4], A_legs[1]):
+        F, perm = u1.fuse(l, l, +1, -1, l.dir)
+        n = l.size
+        t = np.zeros((1, F.size, 1))
+        t[0, [f for f, p in enumerate(perm) if p // n == p % n], 0] = 1.0
+        Ts.append(t)
+    return [np.ones((1, 1))] * 4, Ts
+
+
+def test_expectation_sums_over_a_decomposition():
+    """a = sum of the six square-ice vertices: the one-site expectations of
+    the single vertices add up to 1 in a converged environment, and the
+    two-site ones over all 36 pairs too."""
+    w = ctm.ice_weights()
+    a = ctm.vertex_tensor(w)
+    C, T = ctm.initial_environment()
+    C, T, _ = ctm.run(C, T, a, 8, block=2, max_steps=40, tol=1e-9)
+    parts = [ctm.vertex_tensor({k: 1.0}) for k in w]
+    assert np.isclose(sum(ctm.expectation(C, T, a, [p], 1, 1) for p in parts), 1.0, rtol=1e-12)
+    assert np.isclose(sum(ctm.expectation(C, T, a, [p, q], 2, 1) for p in parts for q in parts), 1.0, rtol=1e-12)
