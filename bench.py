@@ -28,7 +28,8 @@ HBM_PEAK_GBS = 8000.0
 def build_workload(cfgd, seed, dtype, st, draw, TENSOR_INDEX):
     """Device tensors of the workload filled with the seeded draws."""
     phys, virt, chi, flux = cfgd["phys"], cfgd["virt"], cfgd["chi"], cfgd["flux"]
-    T = {"A": st.Tensor.create([(phys, 1), (virt, 1), (virt, 1), (virt, -1), (virt, -1)], flux, dtype)}
+    g = cfgd["group"].lower()
+    T = {"A": st.Tensor.create([(phys, 1), (virt, 1), (virt, 1), (virt, -1), (virt, -1)], flux, dtype, group=g)}
     T["A"].upload(draw((seed, TENSOR_INDEX["A"]), T["A"].nnz))
     T["a"] = st.double_layer(T["A"])
     dd = T["a"].legs()[0][0]
@@ -38,7 +39,7 @@ def build_workload(cfgd, seed, dtype, st, draw, TENSOR_INDEX):
     for c in ("C2", "C3", "C4"):
         legs[c] = legs["C1"]
     for n, l in legs.items():
-        T[n] = st.Tensor.create(l, 0, dtype)
+        T[n] = st.Tensor.create(l, 0, dtype, group=g)
         T[n].upload(draw((seed, TENSOR_INDEX[n]), T[n].nnz))
     return T
 
@@ -116,7 +117,7 @@ def write_traffic(base, workload, command):
     print(json.dumps(rec, indent=1))
 
 
-def cpu_baseline(cfgd):
+def cpu_baseline(cfgd, gpu_flops=None):
     """The FP64 dense oracle timed on the host on one full move of the same
     workload (the oracle as it stands, BLAS threads = host cores)."""
     from oracle import u1
@@ -126,6 +127,8 @@ def cpu_baseline(cfgd):
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         threads = len(os.sched_getaffinity(0))
+    if cfgd["group"] == "Z2":
+        return cpu_baseline_z2(cfgd, threads, gpu_flops)
     w = u1.Workload(cfgd["phys"], cfgd["virt"], cfgd["chi"], cfgd["flux"])
     vals = {n: draw((cfgd["seed"], TENSOR_INDEX[n]), w.nnz_of(n)) for n in SITE_AND_ENV}
     t0 = time.perf_counter()
@@ -137,6 +140,33 @@ def cpu_baseline(cfgd):
     return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"one full left move of the same workload (dense FP64, {dt:.1f} s)",
             "seconds": dt}
+
+
+def cpu_baseline_z2(cfgd, threads, gpu_flops=None):
+    """The whole-environment dense FP64 oracle timed on one left move of the
+    Z2 workload (inputs embedded on the host from the same seeded draws)."""
+    from oracle import u1, ctm
+    from synth import draw, TENSOR_INDEX
+    L = lambda s, d: u1.Leg(s, d)
+    phys, virt, chi = cfgd["phys"], cfgd["virt"], cfgd["chi"]
+    A_legs = [L(phys, 1), L(virt, 1), L(virt, 1), L(virt, -1), L(virt, -1)]
+    t0 = time.perf_counter()
+    A = u1.embed(A_legs, cfgd["flux"], draw((cfgd["seed"], TENSOR_INDEX["A"]), u1.nnz(A_legs, cfgd["flux"], 2)), 2)
+    a, a_legs = u1.double_layer(A, A_legs, modulus=2)
+    dd = a_legs[0].sectors()
+    legs = {"C1": [L(chi, 1), L(chi, -1)], "T1": [L(chi, 1), L(dd, -1), L(chi, -1)],
+            "T2": [L(chi, 1), L(dd, 1), L(chi, -1)], "T3": [L(chi, 1), L(dd, 1), L(chi, -1)],
+            "T4": [L(chi, 1), L(dd, -1), L(chi, -1)]}
+    for c in ("C2", "C3", "C4"):
+        legs[c] = legs["C1"]
+    D = {n: u1.embed(l, 0, draw((cfgd["seed"], TENSOR_INDEX[n]), u1.nnz(l, 0, 2)), 2) for n, l in legs.items()}
+    ctm.left_move([D["C1"], D["C2"], D["C3"], D["C4"]], [D["T1"], D["T2"], D["T3"], D["T4"]], a,
+                  cfgd["chi_target"])
+    dt = time.perf_counter() - t0
+    return {"value": None if gpu_flops is None else gpu_flops / dt / 1e9, "unit": "GFLOP/s",
+            "cores": int(threads), "kind": "oracle", "seconds": dt,
+            "sample": f"one full left move of the same workload (dense FP64 whole-environment oracle, {dt:.1f} s); "
+                      "useful flops counted as on the GPU side"}
 
 
 def build_corner_inputs(cfgd, key, dtype, st, draw, TENSOR_INDEX):
@@ -386,7 +416,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -470,7 +500,7 @@ def main():
         roof["useful_flops_per_launch"] = dom["useful_flops"] / dom["launches"]
 
     out = {
-        "metric": "useful GFLOP/s per CTM move (U(1) left move, sector GEMMs on MFMA)",
+        "metric": f"useful GFLOP/s per CTM move ({cfgd['group'].replace('U1', 'U(1)')} left move, sector GEMMs on MFMA)",
         "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": prec, "data": "synthetic (seeded Gaussian blocks)",
@@ -484,7 +514,7 @@ def main():
         "kernels": sorted(kstats, key=lambda k: -k["ms"])[:6],
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfgd)
+        out["cpu_baseline"] = cpu_baseline(cfgd, flops)
     print(json.dumps(out))
 
 

@@ -71,6 +71,7 @@ extern "C" {
 /* ---- enums ------------------------------------------------------------ */
 #define SYMTEN_U1   1
 #define SYMTEN_SU2  2
+#define SYMTEN_Z2   3
 
 #define SYMTEN_IN   1
 #define SYMTEN_OUT -1
@@ -100,7 +101,7 @@ typedef struct ctm_env* ctm_env_t;
  * of each leg's sector list; leg l owns nsec[l] consecutive entries.
  * Sectors of dim 0 are ignored; labels within a leg must be distinct.      */
 typedef struct {
-    int group;          /* SYMTEN_U1 or SYMTEN_SU2                          */
+    int group;          /* SYMTEN_U1, SYMTEN_SU2 or SYMTEN_Z2               */
     int rank;           /* 1 .. SYMTEN_MAX_RANK                             */
     const int* dirs;    /* [rank] SYMTEN_IN / SYMTEN_OUT                    */
     const int* nsec;    /* [rank] number of sectors per leg                 */

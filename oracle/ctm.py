@@ -247,3 +247,41 @@ def initial_environment():
                 if qi + qd - qo == 0:
                     Tin[i, j, o] = 1.0
     return [C, C, C, C], [Tout, Tin, Tin, Tout]
+
+
+# --------------------------------------------------------------------------
+# The classical Ising model with Z2-symmetric tensors
+# --------------------------------------------------------------------------
+def ising_tensor(beta):
+    """Site tensor of the square-lattice Ising model (J = 1) in the parity
+    basis of the bonds: exp(beta s s') = cosh(beta) + s s' sinh(beta) =
+    sum_p c_p s^p s'^p with c_0 = cosh, c_1 = sinh; each bond weight is split
+    as sqrt(c_p) to its two sites, and the sum over the site spin leaves
+    a[p_l, p_u, p_r, p_d] = 2 prod_i sqrt(c_(p_i)) when the parities add up to
+    0 mod 2, else 0 (Z2 conservation)."""
+    c = np.array([np.cosh(beta), np.sinh(beta)])
+    a = np.zeros((2, 2, 2, 2))
+    for p in np.ndindex(2, 2, 2, 2):
+        if sum(p) % 2 == 0:
+            a[p] = 2.0 * np.prod(np.sqrt(c[list(p)]))
+    return a
+
+
+def onsager_log_z(beta, n=512):
+    """ln Z per site of the square-lattice Ising model (Onsager):
+    ln 2 + (1 / 8 pi^2) int int ln[cosh(2b)^2 - sinh(2b)(cos t1 + cos t2)]
+    over [0, 2 pi]^2, by the trapezoid rule on an n x n grid (exponentially
+    accurate for a smooth periodic integrand, i.e. away from the critical
+    point)."""
+    t = 2.0 * np.pi * np.arange(n) / n
+    c1, c2 = np.meshgrid(np.cos(t), np.cos(t), indexing="ij")
+    f = np.log(np.cosh(2 * beta) ** 2 - np.sinh(2 * beta) * (c1 + c2))
+    return np.log(2.0) + 0.5 * f.mean()
+
+
+def ising_initial_environment():
+    """chi = 1 environment of charge-0 bonds: C = 1, T[0, p, 0] = 1 for the
+    even bond parity p = 0 (the only block the rule allows)."""
+    t = np.zeros((1, 2, 1))
+    t[0, 0, 0] = 1.0
+    return [np.ones((1, 1))] * 4, [t] * 4

@@ -64,11 +64,13 @@ class Leg:
 # Blocks and dense embedding (Sec. 2, Eq. tensor-blocks and the rank-2 example)
 # --------------------------------------------------------------------------
 
-def allowed_blocks(legs, flux):
-    """Charge tuples of all blocks obeying sum dir*q == flux, canonical order."""
+def allowed_blocks(legs, flux, modulus=0):
+    """Charge tuples of all blocks obeying sum dir*q == flux (modulo
+    `modulus` for Z_n charges), canonical order."""
     out = []
     for qs in itertools.product(*[leg.charges for leg in legs]):
-        if sum(leg.dir * q for leg, q in zip(legs, qs)) == flux:
+        s = sum(leg.dir * q for leg, q in zip(legs, qs)) - flux
+        if (s % modulus == 0) if modulus else s == 0:
             out.append(tuple(qs))
     return out
 
@@ -81,17 +83,17 @@ def block_slices(legs, qs):
     return tuple(slice(leg.offsets()[q], leg.offsets()[q] + leg.dim(q)) for leg, q in zip(legs, qs))
 
 
-def nnz(legs, flux):
-    return int(sum(np.prod(block_shape(legs, b)) for b in allowed_blocks(legs, flux)))
+def nnz(legs, flux, modulus=0):
+    return int(sum(np.prod(block_shape(legs, b)) for b in allowed_blocks(legs, flux, modulus)))
 
 
-def embed(legs, flux, values):
+def embed(legs, flux, values, modulus=0):
     """Dense FP64 array whose allowed blocks hold ``values`` in canonical
     block order, row-major inside each block; zero elsewhere."""
     values = np.asarray(values, dtype=np.float64)
     dense = np.zeros([leg.size for leg in legs])
     pos = 0
-    for b in allowed_blocks(legs, flux):
+    for b in allowed_blocks(legs, flux, modulus):
         shp = block_shape(legs, b)
         n = int(np.prod(shp))
         dense[block_slices(legs, b)] = values[pos:pos + n].reshape(shp)
@@ -101,14 +103,15 @@ def embed(legs, flux, values):
     return dense
 
 
-def conserving_mask(legs, flux):
-    """Boolean array, True where the state charges obey the addition rule."""
+def conserving_mask(legs, flux, modulus=0):
+    """Boolean array, True where the state charges obey the addition rule
+    (modulo `modulus` for Z_n charges, e.g. 2 for parities)."""
     tot = np.zeros([leg.size for leg in legs], dtype=np.int64)
     for ax, leg in enumerate(legs):
         shape = [1] * len(legs)
         shape[ax] = leg.size
         tot = tot + leg.dir * leg.state_charges().reshape(shape)
-    return tot == flux
+    return (tot - flux) % modulus == 0 if modulus else tot == flux
 
 
 def extract_block(dense, legs, qs):
@@ -119,8 +122,9 @@ def extract_block(dense, legs, qs):
 # Leg fusion
 # --------------------------------------------------------------------------
 
-def fuse(leg_a, leg_b, sa, sb, direction):
-    """Fuse two legs into one leg with charge Q = sa*q_a + sb*q_b.
+def fuse(leg_a, leg_b, sa, sb, direction, modulus=0):
+    """Fuse two legs into one leg with charge Q = sa*q_a + sb*q_b (taken
+    modulo `modulus` for Z_n charges).
 
     Fused states are ordered by Q ascending, then q_a ascending, then
     (i_a, i_b) row-major.  Returns (fused leg, perm) where perm[f] is the
@@ -130,7 +134,8 @@ def fuse(leg_a, leg_b, sa, sb, direction):
     entries = []
     for ia in range(leg_a.size):
         for ib in range(leg_b.size):
-            entries.append((sa * qa[ia] + sb * qb[ib], qa[ia], ia, ib))
+            Q = sa * qa[ia] + sb * qb[ib]
+            entries.append((int(Q % modulus) if modulus else int(Q), qa[ia], ia, ib))
     entries.sort()
     perm = np.array([ia * leg_b.size + ib for _, _, ia, ib in entries], dtype=np.int64)
     sectors = {}
@@ -185,14 +190,14 @@ class Workload:
         return out
 
 
-def double_layer(A, A_legs):
+def double_layer(A, A_legs, modulus=0):
     """a = sum_sigma A[sigma,...] A*[sigma,...] with every (ket, bra) pair of
     virtual legs fused into one leg of charge q_ket - q_bra (Sec. 3.2: the
     rank-4 double-layer tensor).  A is real, so A* = A."""
     a8 = np.einsum("sabcd,sefgh->aebfcgdh", A, A)
     perms, legs = [], []
     for leg in A_legs[1:]:
-        F, p = fuse(leg, leg, +1, -1, leg.dir)
+        F, p = fuse(leg, leg, +1, -1, leg.dir, modulus)
         perms.append(p)
         legs.append(F)
     n = [leg.size for leg in A_legs[1:]]
@@ -200,14 +205,14 @@ def double_layer(A, A_legs):
     return a4[np.ix_(*perms)], legs
 
 
-def double_layer_op(A, A_legs, op):
+def double_layer_op(A, A_legs, op, modulus=0):
     """The double layer with a one-site operator between the layers:
     b = sum over (s_bra, s_ket) of op[s_bra, s_ket] A[s_ket, ...] (ket)
     A[s_bra, ...] (bra), legs fused as in double_layer; for real A the
     network with b in place of a gives <psi|O|psi> (Sec. 3's expectation
     values)."""
     b8 = np.einsum("tk,kabcd,tefgh->aebfcgdh", op, A, A)
-    perms = [fuse(leg, leg, +1, -1, leg.dir)[1] for leg in A_legs[1:]]
+    perms = [fuse(leg, leg, +1, -1, leg.dir, modulus)[1] for leg in A_legs[1:]]
     n = [leg.size for leg in A_legs[1:]]
     b4 = b8.reshape(n[0] * n[0], n[1] * n[1], n[2] * n[2], n[3] * n[3])
     return b4[np.ix_(*perms)]

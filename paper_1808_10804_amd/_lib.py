@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "libsymten.so")
 OK = 0
 ERRORS = {-1: "E_INVAL", -2: "E_LEGS", -3: "E_SYM", -4: "E_NOMEM", -5: "E_HIP",
           -6: "E_LINALG", -7: "E_CAPACITY", -8: "E_UNSUPPORTED", -9: "E_NODEVICE"}
-U1, SU2 = 1, 2
+U1, SU2, Z2 = 1, 2, 3
 F64, F32 = 0, 1
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 MAX_SECTORS = 64

@@ -386,7 +386,9 @@ namespace {
 
 TensorPtr make_desc_tensor(const symten_desc* d) {
     if (!d) fail(SYMTEN_E_INVAL, "null descriptor");
-    if (d->group != SYMTEN_U1 && d->group != SYMTEN_SU2) fail(SYMTEN_E_INVAL, "unknown symmetry group");
+    if (d->group != SYMTEN_U1 && d->group != SYMTEN_SU2 && d->group != SYMTEN_Z2)
+        fail(SYMTEN_E_INVAL, "unknown symmetry group");
+    if (d->group == SYMTEN_Z2 && d->flux != 0 && d->flux != 1) fail(SYMTEN_E_SYM, "Z2 flux is a parity, 0 or 1");
     if (d->group == SYMTEN_SU2 && d->flux != 0) fail(SYMTEN_E_SYM, "SU(2) tensors are invariant: flux must be 0");
     if (d->rank < 1 || d->rank > SYMTEN_MAX_RANK) fail(SYMTEN_E_INVAL, "rank must be 1..8");
     if (!d->dirs || !d->nsec || !d->labels || !d->dims) fail(SYMTEN_E_INVAL, "null array in descriptor");
@@ -404,6 +406,8 @@ TensorPtr make_desc_tensor(const symten_desc* d) {
             if (d->dims[pos] < 0) fail(SYMTEN_E_INVAL, "negative sector dimension");
             if (d->group == SYMTEN_SU2 && (d->labels[pos] < 0 || d->labels[pos] > 64))
                 fail(SYMTEN_E_INVAL, "SU(2) labels are doubled spins 0..64");
+            if (d->group == SYMTEN_Z2 && d->labels[pos] != 0 && d->labels[pos] != 1)
+                fail(SYMTEN_E_INVAL, "Z2 labels are parities 0, 1");
             if (d->dims[pos] > 0) secs.push_back({d->labels[pos], d->dims[pos]});
         }
         std::sort(secs.begin(), secs.end());
@@ -966,14 +970,17 @@ namespace {
 // (the addition rule keeps holding; the sectors of the leg reverse order).
 TensorPtr flip_legs_u1(const TensorPtr& t, std::initializer_list<int> legs) {
     auto r = std::make_shared<Tensor>(*t);
+    const int cm = charge_mod(t->group);
     for (int l : legs) {
         Leg& L = r->legs[l];
         L.dir = -L.dir;
-        std::vector<int> q(L.q.rbegin(), L.q.rend()), d(L.d.rbegin(), L.d.rend());
-        for (auto& x : q) x = -x;
-        L.q = q;
-        L.d = d;
-        for (auto& b : r->blocks) b.q[l] = -b.q[l];
+        std::vector<std::pair<int, int>> secs;
+        for (size_t k = 0; k < L.q.size(); ++k) secs.push_back({cnorm(-L.q[k], cm), L.d[k]});
+        std::sort(secs.begin(), secs.end());
+        L.q.clear();
+        L.d.clear();
+        for (auto& sd : secs) { L.q.push_back(sd.first); L.d.push_back(sd.second); }
+        for (auto& b : r->blocks) b.q[l] = cnorm(-b.q[l], cm);
     }
     std::sort(r->blocks.begin(), r->blocks.end(), [](const Block& x, const Block& y) { return x.q < y.q; });
     r->rebuild_index();
@@ -1176,8 +1183,9 @@ void move_u1_left(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st
 
     // ---- projectors, per fused charge Q of the left cut (FP64) ----------
     std::map<int, const GroupPlan*> gu_of, gd_of;
-    for (auto& g : hu.plan->groups) gu_of[g.rows[0][0] - g.rows[0][1]] = &g;
-    for (auto& g : hd.plan->groups) gd_of[g.rows[0][0] - g.rows[0][1]] = &g;
+    const int cm = charge_mod(a.group);
+    for (auto& g : hu.plan->groups) gu_of[cnorm(g.rows[0][0] - g.rows[0][1], cm)] = &g;
+    for (auto& g : hd.plan->groups) gd_of[cnorm(g.rows[0][0] - g.rows[0][1], cm)] = &g;
     const size_t es = f64 ? 8 : 4;
     const Leg& chiL = T4.legs[0];
     const Leg& dL = a.legs[3];
@@ -1265,7 +1273,7 @@ void move_u1_left(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st
     auto P = std::make_shared<Tensor>();
     auto Pt = std::make_shared<Tensor>();
     for (auto* X : {P.get(), Pt.get()}) {
-        X->group = SYMTEN_U1;
+        X->group = a.group;
         X->flux = 0;
         X->dtype = SYMTEN_F64;
     }
@@ -1744,7 +1752,7 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, co
         for (int i = 0; i < n; ++i) {
             for (symten_t h : {Cs[i], Tas[i], Tbs[i], as[i]}) {
                 check_device_tensor(T(h), "batched corners");
-                if (T(h).group != SYMTEN_U1) fail(SYMTEN_E_UNSUPPORTED, "batched corners: U(1) tensors only");
+                if (!abelian(T(h).group)) fail(SYMTEN_E_UNSUPPORTED, "batched corners: U(1) or Z2 tensors only");
                 key += tensor_signature(T(h)) + "&";
                 inputs.push_back(T(h).data());
             }
@@ -1978,8 +1986,8 @@ int ctm_site_partition(ctm_env_t env, symten_t a, int block, double* kappa, doub
         if (block != 1 && block != 2) fail(SYMTEN_E_INVAL, "block must be 1 or 2");
         Tensor& at = T(a);
         check_device_tensor(at, "ctm_site_partition(a)");
-        if (at.group != SYMTEN_U1 || env->C[0]->group != SYMTEN_U1)
-            fail(SYMTEN_E_UNSUPPORTED, "ctm_site_partition: U(1) tensors only");
+        if (!abelian(at.group) || env->C[0]->group != at.group)
+            fail(SYMTEN_E_UNSUPPORTED, "ctm_site_partition: U(1) or Z2 tensors only");
         if (at.rank() != 4) fail(SYMTEN_E_INVAL, "a must have rank 4");
         double zz[4];
         *kappa = site_partition(env, a->t, block, zz, S(stream));
@@ -1993,13 +2001,13 @@ int ctm_expectation(ctm_env_t env, symten_t a, int n, int m, const symten_t* sit
         if (n < 1 || m < 1 || n > 2 || m > 2) fail(SYMTEN_E_INVAL, "ctm_expectation: patch of 1 or 2 columns and rows");
         Tensor& at = T(a);
         check_device_tensor(at, "ctm_expectation(a)");
-        if (at.group != SYMTEN_U1 || env->C[0]->group != SYMTEN_U1)
-            fail(SYMTEN_E_UNSUPPORTED, "ctm_expectation: U(1) tensors only");
+        if (!abelian(at.group) || env->C[0]->group != at.group)
+            fail(SYMTEN_E_UNSUPPORTED, "ctm_expectation: U(1) or Z2 tensors only");
         std::vector<TensorPtr> b;
         for (int k = 0; k < n * m; ++k) {
             Tensor& bt = T(sites[k]);
             check_device_tensor(bt, "ctm_expectation(site)");
-            if (bt.group != SYMTEN_U1 || bt.rank() != 4) fail(SYMTEN_E_INVAL, "ctm_expectation: sites are rank-4 U(1) tensors");
+            if (bt.group != at.group || bt.rank() != 4) fail(SYMTEN_E_INVAL, "ctm_expectation: sites are rank-4 tensors of a's group");
             for (int l = 0; l < 4; ++l)
                 if (bt.legs[l].dir != at.legs[l].dir || bt.legs[l].q != at.legs[l].q || bt.legs[l].d != at.legs[l].d)
                     fail(SYMTEN_E_LEGS, "ctm_expectation: a site's legs differ from a's");
@@ -2062,8 +2070,8 @@ int ctm_run(ctm_env_t env, symten_t a, const ctm_run_opts* o, ctm_run_result* r,
             fail(SYMTEN_E_INVAL, "ctm_run: bad options");
         Tensor& at = T(a);
         check_device_tensor(at, "ctm_run(a)");
-        if (at.group != SYMTEN_U1 || env->C[0]->group != SYMTEN_U1)
-            fail(SYMTEN_E_UNSUPPORTED, "ctm_run: U(1) tensors only");
+        if (!abelian(at.group) || env->C[0]->group != at.group)
+            fail(SYMTEN_E_UNSUPPORTED, "ctm_run: U(1) or Z2 tensors only");
         ctm_run_result res{};
         double z[4], prev_level = 0.0;
         for (int chi = o->chi;; chi *= 2) {

@@ -80,6 +80,13 @@ struct Tensor {
 };
 using TensorPtr = std::shared_ptr<Tensor>;
 
+// Abelian groups: U(1) charges are integers, Z2 charges parities 0, 1 with
+// every sum taken mod 2.  charge_mod is 0 for U(1), 2 for Z2; cnorm brings a
+// sum of charges back to its label.
+inline int charge_mod(int group) { return group == SYMTEN_Z2 ? 2 : 0; }
+inline int cnorm(long q, int m) { return m ? (int)(((q % m) + m) % m) : (int)q; }
+inline bool abelian(int group) { return group == SYMTEN_U1 || group == SYMTEN_Z2; }
+
 // Allowed blocks of the given legs and flux, canonical order, contiguous
 // row-major layout; returns total element count.
 int64_t enumerate_blocks(Tensor& t);
@@ -250,7 +257,7 @@ TensorPtr double_layer_su2(const Tensor& A, hipStream_t stream);
 // Fused (ket, bra) states of a U(1) double-layer leg: charge q_ket - q_bra,
 // ordered by that charge, then q_ket, then (i_ket, i_bra); ket/bra are state
 // indices of the leg (charge-major order).
-void double_layer_states(const Leg& v, std::vector<int>& ket, std::vector<int>& bra, Leg& fused);
+void double_layer_states(const Leg& v, std::vector<int>& ket, std::vector<int>& bra, Leg& fused, int cm = 0);
 // SU(2) tensor with legs `legs` from the U(1) tensor of its S^z components
 // (the inverse of su2_to_u1 on invariant tensors): projection of every block
 // onto its basis tensor.

@@ -144,7 +144,7 @@ int64_t enumerate_blocks(Tensor& t) {
     while (true) {
         long s = 0;
         for (int l = 0; l < R; ++l) s += (long)t.legs[l].dir * t.legs[l].q[sidx[l]];
-        if (s == t.flux) {
+        if (cnorm(s - t.flux, charge_mod(t.group)) == 0) {
             Block b;
             b.q.resize(R);
             b.shape.resize(R);
@@ -356,6 +356,7 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
     const int VW = panel_vw(p);   // 16-byte vectors in the GEMM loads
 
     // group blocks by the contracted charge seen from A
+    const int cm = charge_mod(A.group);
     std::map<int, GroupBuild> gb;
     for (size_t i = 0; i < A.blocks.size(); ++i) {
         const Block& b = A.blocks[i];
@@ -363,6 +364,7 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
         int key = 0;
         for (int l : freeA) al.push_back(b.q[l]);
         for (int l : conA) { ka.push_back(b.q[l]); key += A.legs[l].dir * b.q[l]; }
+        key = cnorm(key, cm);
         GroupBuild& G = gb[key];
         G.alpha_blocks[al].push_back((int)i);
         G.kapA.insert(ka);
@@ -373,6 +375,7 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
         int key = 0;
         for (int l : freeB) be.push_back(b.q[l]);
         for (int l : conB) { ka.push_back(b.q[l]); key -= B.legs[l].dir * b.q[l]; }
+        key = cnorm(key, cm);
         auto it = gb.find(key);
         if (it == gb.end()) continue;
         it->second.beta_blocks[be].push_back((int)i);
@@ -381,8 +384,8 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
 
     // output metadata
     auto out = std::make_shared<Tensor>();
-    out->group = SYMTEN_U1;
-    out->flux = A.flux + B.flux;
+    out->group = A.group;
+    out->flux = cnorm(A.flux + B.flux, cm);
     out->dtype = A.dtype;
     std::vector<Leg> olegs;
     for (int l : freeA) olegs.push_back(A.legs[l]);
@@ -1128,7 +1131,7 @@ std::vector<TensorPtr> run_contractions_batched(const std::vector<std::shared_pt
 }
 
 // ------------------------------------------------------------ double layer
-void double_layer_states(const Leg& v, std::vector<int>& ket, std::vector<int>& bra, Leg& fused) {
+void double_layer_states(const Leg& v, std::vector<int>& ket, std::vector<int>& bra, Leg& fused, int cm) {
     std::vector<int> qs(v.size());
     int o = 0;
     for (size_t s = 0; s < v.q.size(); ++s) {
@@ -1138,7 +1141,7 @@ void double_layer_states(const Leg& v, std::vector<int>& ket, std::vector<int>& 
     struct E { int Q, qk, ik, ib; };
     std::vector<E> es;
     for (int ik = 0; ik < v.size(); ++ik)
-        for (int ib = 0; ib < v.size(); ++ib) es.push_back({qs[ik] - qs[ib], qs[ik], ik, ib});
+        for (int ib = 0; ib < v.size(); ++ib) es.push_back({cnorm(qs[ik] - qs[ib], cm), qs[ik], ik, ib});
     std::sort(es.begin(), es.end(), [](const E& x, const E& y) {
         if (x.Q != y.Q) return x.Q < y.Q;
         if (x.qk != y.qk) return x.qk < y.qk;
@@ -1180,7 +1183,7 @@ TensorPtr double_layer(const Tensor& A, hipStream_t stream, const double* op) {
                 const double v = op[sb * np + sk];
                 if (!std::isfinite(v)) fail(SYMTEN_E_INVAL, "double_layer: operator entry not finite");
                 if (v == 0.0) continue;
-                const int f = A.legs[0].dir * (qs[sb] - qs[sk]);
+                const int f = cnorm(A.legs[0].dir * (qs[sb] - qs[sk]), charge_mod(A.group));
                 if (any && f != flux) fail(SYMTEN_E_SYM, "double_layer: operator does not move the charge by one amount");
                 flux = f;
                 any = true;
@@ -1188,13 +1191,13 @@ TensorPtr double_layer(const Tensor& A, hipStream_t stream, const double* op) {
     }
     // fused legs: Q = q_ket - q_bra, states ordered by Q, q_ket, (i_ket, i_bra)
     auto out = std::make_shared<Tensor>();
-    out->group = SYMTEN_U1;
+    out->group = A.group;
     out->flux = flux;
     out->dtype = A.dtype;
     std::vector<std::vector<int>> ket_of(4), bra_of(4);
     for (int l = 0; l < 4; ++l) {
         Leg F;
-        double_layer_states(A.legs[l + 1], ket_of[l], bra_of[l], F);
+        double_layer_states(A.legs[l + 1], ket_of[l], bra_of[l], F, charge_mod(A.group));
         out->legs.push_back(F);
     }
     const int64_t total = enumerate_blocks(*out);

@@ -55,14 +55,16 @@ class Tensor:
     @staticmethod
     def _desc(legs, flux, dtype, group="u1"):
         """legs: list of (sectors dict {label: dim}, direction); labels are
-        U(1) charges or, for group "su2", doubled spins."""
+        U(1) charges, for group "su2" doubled spins, for group "z2" parities."""
         dirs = [int(d) for _, d in legs]
         nsec = [len(s) for s, _ in legs]
         labels = [int(q) for s, _ in legs for q in s]
         dims = [int(s[q]) for s, _ in legs for q in s]
         keep = (_ints(dirs), _ints(nsec), _ints(labels), _ints(dims))
         dt = _lib.F64 if dtype in ("f64", _lib.F64) else _lib.F32
-        g = _lib.SU2 if group in ("su2", _lib.SU2) else _lib.U1
+        g = {"u1": _lib.U1, "su2": _lib.SU2, "z2": _lib.Z2}.get(group, group)
+        if g not in (_lib.U1, _lib.SU2, _lib.Z2):
+            raise ValueError(f"unknown symmetry group {group!r}")
         d = _lib.Desc(g, len(legs), keep[0], keep[1], keep[2], keep[3], int(flux), dt)
         return d, keep
 

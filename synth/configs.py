@@ -60,6 +60,10 @@ CONFIGS = {
             virt={-2: 2, 0: 4, 2: 2}, chi=binomial_sectors(200, 7), chi_target=200,
             prec="sweep", seed=1812,
             what="one CTM move, GEMMs in f64/f32/bf16/bf16x3"),
+    6: dict(name="z2_leftmove_D6_chi64_f32", group="Z2", phys={0: 1, 1: 1}, flux=0,
+            virt={0: 3, 1: 3}, chi={0: 32, 1: 32}, chi_target=64,
+            prec="f32", seed=1814,
+            what="full CTM left move, Z2 parities (the D = 6, chi = 64 move of config 2 with charges mod 2)"),
     5: dict(name="u1_batched64_corners", group="U1", phys=PHYS_U1, flux=1,
             batch=64, D_choices=(4, 5, 6, 7, 8), chi_range=(32, 160),
             prec="bf16x3", seed=1813,

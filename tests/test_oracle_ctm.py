@@ -255,3 +255,53 @@ def test_expectation_sums_over_a_decomposition():
     parts = [ctm.vertex_tensor({k: 1.0}) for k in w]
     assert np.isclose(sum(ctm.expectation(C, T, a, [p], 1, 1) for p in parts), 1.0, rtol=1e-12)
     assert np.isclose(sum(ctm.expectation(C, T, a, [p, q], 2, 1) for p in parts for q in parts), 1.0, rtol=1e-12)
+
+
+# ------------------------------------------------ Z2 charges and the Ising model
+def test_z2_mask_and_fusion_counts():
+    """Parity conservation: with legs {0: d0, 1: d1} the number of allowed
+    entries is ((d0 + d1)^R + s (d0 - d1)^R) / 2 (s = +1 for flux 0, -1 for
+    flux 1: the parity generating function); fusing two such legs gives
+    sectors {0: a0 b0 + a1 b1, 1: a0 b1 + a1 b0}."""
+    d0, d1 = 2, 3
+    for R in (2, 3, 4):
+        legs = [u1.Leg({0: d0, 1: d1}, (+1, -1)[k % 2]) for k in range(R)]
+        for flux, sgn in ((0, 1), (1, -1)):
+            n = int(np.count_nonzero(u1.conserving_mask(legs, flux, modulus=2)))
+            assert n == ((d0 + d1) ** R + sgn * (d0 - d1) ** R) // 2
+    F, perm = u1.fuse(u1.Leg({0: 2, 1: 3}, u1.IN), u1.Leg({0: 4, 1: 1}, u1.IN), +1, -1, u1.IN, modulus=2)
+    assert F.sectors() == {0: 2 * 4 + 3 * 1, 1: 2 * 1 + 3 * 4}
+    assert sorted(perm) == list(range(25))
+
+
+def test_onsager_formula_limits():
+    """beta -> 0: ln 2; small beta: the high-temperature expansion
+    ln 2 + 2 ln cosh(beta) + tanh(beta)^4 + O(tanh^6)."""
+    assert np.isclose(ctm.onsager_log_z(0.0), np.log(2.0), rtol=0, atol=1e-15)
+    b = 0.05
+    ht = np.log(2.0) + 2 * np.log(np.cosh(b)) + np.tanh(b) ** 4
+    assert abs(ctm.onsager_log_z(b) - ht) < 5 * np.tanh(b) ** 6
+    # n-independence away from the critical point
+    assert abs(ctm.onsager_log_z(0.3, 256) - ctm.onsager_log_z(0.3, 512)) < 1e-14
+
+
+def test_ising_tensor_pins():
+    """Parity conservation of the site tensor, and a 1 x 1 torus: the 2 x 2
+    spin sum of exp(beta s s') over the bonds of one site with itself, i.e.
+    sum_s exp(2 beta) = 2 exp(2 beta), equals the trace of a over (l, r) and
+    (u, d)."""
+    beta = 0.37
+    a = ctm.ising_tensor(beta)
+    legs = [u1.Leg({0: 1, 1: 1}, d) for d in (u1.IN, u1.IN, u1.OUT, u1.OUT)]
+    assert np.all(a[~u1.conserving_mask(legs, 0, modulus=2)] == 0)
+    assert np.isclose(np.einsum("abab->", a), 2 * np.exp(2 * beta), rtol=1e-14)
+
+
+@pytest.mark.parametrize("beta", [0.3, 0.6])
+def test_ising_free_energy(beta):
+    """The dense CTM on the Ising tensor reproduces Onsager's ln Z per site
+    away from the critical point (beta_c = 0.4407)."""
+    a = ctm.ising_tensor(beta)
+    C, T = ctm.ising_initial_environment()
+    _, _, r = ctm.run(C, T, a, 16, block=1, max_steps=100, tol=1e-13)
+    assert abs(np.log(r["kappa"]) - ctm.onsager_log_z(beta)) < 1e-9

@@ -64,10 +64,11 @@ def rel(x, y):
     return np.linalg.norm(x - y) / (den if den > 0 else 1.0)
 
 
-def from_dense(dense, legs, flux=0, dtype="f64"):
-    """Device tensor with U(1) legs [(sectors, dir)] holding the blocks of a
-    dense array laid out with the oracle's leg offsets."""
-    t = st.Tensor.create(legs, flux=flux, dtype=dtype)
+def from_dense(dense, legs, flux=0, dtype="f64", group="u1"):
+    """Device tensor with abelian legs [(sectors, dir)] (U(1) charges or Z2
+    parities) holding the blocks of a dense array laid out with the oracle's
+    leg offsets."""
+    t = st.Tensor.create(legs, flux=flux, dtype=dtype, group=group)
     L = [u1.Leg(s, d) for s, d in legs]
     parts = [np.asarray(dense[u1.block_slices(L, lab)]).ravel() for lab, _, _, _ in t.blocks()]
     t.upload(np.concatenate(parts) if parts else np.zeros(0))
