@@ -353,6 +353,58 @@ def bench_su2(args):
     print(json.dumps(out))
 
 
+def bench_corners(args):
+    """The four enlarged corners of a workload through the single-layer route
+    (A and A* absorbed separately) against the double-layer route (a = A A*
+    built once, as in a CTM run), one corner call at a time on one stream."""
+    import torch
+    import paper_1808_10804_amd as st
+    from synth import config, draw, TENSOR_INDEX
+    cfgd = config(args.config)
+    prec = args.prec or {"sweep": "f32"}.get(cfgd["prec"], cfgd["prec"])
+    dtype = "f64" if prec == "f64" else "f32"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    T = build_workload(cfgd, cfgd["seed"], dtype, st, draw, TENSOR_INDEX)
+    names = {1: ("C1", "T1", "T4"), 2: ("C2", "T1", "T2"), 3: ("C3", "T3", "T2"), 4: ("C4", "T3", "T4")}
+
+    def single():
+        fl = 0
+        for w, n in names.items():
+            _, inf = st.enlarged_corner_single_layer(w, T[n[0]], T[n[1]], T[n[2]], T["A"], prec=prec, stream=stream)
+            fl += inf["useful_flops"]
+        return fl
+
+    def double():
+        fl = 0
+        for w, n in names.items():
+            _, inf = st.enlarged_corner(w, T[n[0]], T[n[1]], T[n[2]], T["a"], prec=prec, stream=stream)
+            fl += inf["useful_flops"]
+        return fl
+
+    res = {}
+    for name, fn in (("single", single), ("double", double)):
+        for _ in range(args.warmup):
+            fl = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = ((time.perf_counter() - t0) * 1e3 / args.steps, fl)
+    out = {
+        "metric": "ms per four enlarged corners, single-layer route (A and A* absorbed separately)",
+        "value": res["single"][0], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["single"][0], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic (seeded Gaussian blocks)",
+        "config": {"workload": cfgd["name"], "what": "the four enlarged corners of the move", "D_virtual": cfgd["virt"],
+                   "chi_sectors": cfgd["chi"], "parallelism": "single GPU"},
+        "double_layer_ms": res["double"][0], "speedup_vs_double_layer": res["double"][0] / res["single"][0],
+        "useful_flops_single": res["single"][1], "useful_flops_double": res["double"][1],
+    }
+    print(json.dumps(out))
+
+
 def use_recorded_tiles(workload):
     """GEMM tile choices recorded with the committed counter runs: when
     profiles/tune_<workload>.txt exists (and SYMTEN_TUNE_CACHE is not set),
@@ -419,11 +471,16 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--corners", action="store_true",
+                    help="time the four enlarged corners, single-layer against double-layer route")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "the move's multi-GPU sharding is described, not implemented.", file=sys.stderr)
         sys.exit(2)
+    if args.corners:
+        bench_corners(args)
+        return
     if args.config == 5:
         bench_batched(args)
         return

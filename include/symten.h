@@ -232,6 +232,19 @@ int symten_enlarged_corner(symten_t* out, int which, symten_t C, symten_t Ta,
                            symten_t Tb, symten_t a, int prec,
                            symten_plan_stats* info, void* stream);
 
+/* The same corner with the site tensor absorbed as two layers (the
+ * single-layer alternative of Sec. 3.2, asymptotically cheaper than the
+ * double layer): A[phys, l, u, r, d] replaces a; the two D^2 legs of the
+ * second step that meet a are split into (ket, bra) legs by a gather, A
+ * takes the ket legs, A* (A with every leg direction reversed; A is real)
+ * the bra legs and the physical leg, and the free (ket, bra) pairs are
+ * fused back (a gather) into a's legs.  Same legs, order and values as
+ * symten_enlarged_corner with a = symten_double_layer(A); info counts the
+ * contractions' flops.  U(1) and Z2.  Synchronises `stream` at the gathers. */
+int symten_enlarged_corner_single_layer(symten_t* out, int which, symten_t C, symten_t Ta,
+                                        symten_t Tb, symten_t A, int prec,
+                                        symten_plan_stats* info, void* stream);
+
 /* Batched corners: n independent corner-1 contractions ((C T1) T4) a, each
  * step of all n fused into one grouped-GEMM launch.  use_graph != 0 records
  * the whole batch into a HIP graph on first use and replays it afterwards

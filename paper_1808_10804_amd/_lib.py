@@ -105,6 +105,8 @@ SIGNATURES = {
     "symten_double_layer": (C.c_int, [C.POINTER(H), H, P]),
     "symten_enlarged_corner": (C.c_int, [C.POINTER(H), C.c_int, H, H, H, H, C.c_int,
                                          C.POINTER(PlanStats), P]),
+    "symten_enlarged_corner_single_layer": (C.c_int, [C.POINTER(H), C.c_int, H, H, H, H, C.c_int,
+                                                      C.POINTER(PlanStats), P]),
     "symten_enlarged_corners_batched": (C.c_int, [C.c_int, C.POINTER(H), C.POINTER(H), C.POINTER(H),
                                                   C.POINTER(H), C.POINTER(H), C.c_int, C.c_int,
                                                   C.POINTER(PlanStats), P]),

@@ -184,6 +184,108 @@ CornerResult corner(int which, const Tensor& C, const Tensor& Ta, const Tensor& 
     return r;
 }
 
+// The same corner with the site tensor absorbed as two layers (the paper's
+// single-layer alternative, Sec. 3.2): the two D^2 legs of step 2 that meet a
+// are split into (ket, bra) legs, A takes the ket legs, A* (A with every leg
+// direction reversed, same data: A is real) the bra legs and the physical leg,
+// and the two free (ket, bra) pairs are fused back into the double-layer legs
+// of a.  Same legs, order and values as corner().
+// The planned steps of one single-layer corner, reused while the inputs'
+// layouts repeat (as in a CTM run): no host planning or synchronisation on
+// later calls.
+struct SingleLayerPipe {
+    std::shared_ptr<ContractPlan> p[4];        // C.Ta, .Tb, .A (ket), .A* (bra, phys)
+    std::shared_ptr<GatherPlan> split[2], fuse[2];
+    symten_plan_stats info{};
+};
+std::mutex g_sl_mu;
+std::map<std::string, std::shared_ptr<SingleLayerPipe>> g_sl_cache;
+
+CornerResult corner_single_layer(int which, const Tensor& C, const Tensor& Ta, const Tensor& Tb, const Tensor& A,
+                                 int prec, hipStream_t s) {
+    if (A.rank() != 5 || !abelian(A.group)) fail(SYMTEN_E_INVAL, "single-layer corner: A is a rank-5 abelian tensor");
+    for (const Tensor* t : {&C, &Ta, &Tb, &A}) check_device_tensor(*t, "single-layer corner");
+    const int cm = charge_mod(A.group);
+    // A* = A with every leg direction reversed: the bra leg of a bond carries
+    // the ket's labels, so the data and labels stay and the flux changes sign
+    auto As = std::make_shared<Tensor>(A);
+    for (auto& L : As->legs) L.dir = -L.dir;
+    As->flux = cnorm(-A.flux, cm);
+    const std::string key = std::to_string(which) + "#" + std::to_string(prec) + "#" + tensor_signature(C) + "#" +
+                            tensor_signature(Ta) + "#" + tensor_signature(Tb) + "#" + tensor_signature(A);
+    std::shared_ptr<SingleLayerPipe> pipe;
+    {
+        std::lock_guard<std::mutex> lk(g_sl_mu);
+        auto it = g_sl_cache.find(key);
+        if (it != g_sl_cache.end()) pipe = it->second;
+    }
+    CornerResult r;
+    if (pipe) {
+        r.step1 = run_contraction(*pipe->p[0], C, Ta, s);
+        r.step2 = run_contraction(*pipe->p[1], *r.step1, Tb, s);
+        TensorPtr X1 = run_gather_plan(*pipe->split[1], *run_gather_plan(*pipe->split[0], *r.step2, s), s);
+        TensorPtr Y = run_contraction(*pipe->p[2], *X1, A, s);
+        TensorPtr Z = run_contraction(*pipe->p[3], *Y, *As, s);
+        r.corner = run_gather_plan(*pipe->fuse[1], *run_gather_plan(*pipe->fuse[0], *Z, s), s);
+        r.info = pipe->info;
+        return r;
+    }
+    pipe = std::make_shared<SingleLayerPipe>();
+    CornerSpec sp = corner_spec(which);
+    int np = 0;
+    auto run = [&](const Tensor& X, const Tensor& Y, const std::vector<int>& la, const std::vector<int>& lb) {
+        auto p = get_plan(X, Y, (int)la.size(), la.data(), lb.data(), nullptr, prec);
+        add_info(r.info, p->info);
+        pipe->p[np++] = p;
+        return run_contraction(*p, X, Y, s);
+    };
+    r.step1 = run(C, Ta, sp.l1a, sp.l1b);
+    r.step2 = run(*r.step1, Tb, sp.l2a, sp.l2b);
+    // split the two legs that meet a, the later one first
+    const int nX = r.step2->rank();
+    const std::vector<int> xs = sp.l3a, as = sp.l3b;   // X leg xs[i] meets a leg as[i]
+    const int first = xs[0] > xs[1] ? 0 : 1;
+    TensorPtr X1 = r.step2;
+    int ns = 0;
+    for (int i : {first, 1 - first}) {
+        pipe->split[ns] = plan_unfuse(*X1, xs[i], A.legs[as[i] + 1]);
+        X1 = run_gather_plan(*pipe->split[ns++], *X1, s);
+    }
+    // ket position of absorbed leg i in X1: one further per split leg before it
+    auto ket_pos = [&](int i) { return xs[i] + (xs[1 - i] < xs[i] ? 1 : 0); };
+    const std::vector<int> kx = {ket_pos(0), ket_pos(1)};
+    // Y = X1 . A over the ket legs: [X1's other legs, phys, A's free virtual legs]
+    TensorPtr Y = run(*X1, A, kx, {as[0] + 1, as[1] + 1});
+    std::vector<int> x1free;
+    for (int l = 0; l < X1->rank(); ++l)
+        if (l != kx[0] && l != kx[1]) x1free.push_back(l);
+    auto ypos = [&](int x1leg) { return (int)(std::find(x1free.begin(), x1free.end(), x1leg) - x1free.begin()); };
+    const int ysig = (int)x1free.size();
+    // Z = Y . A* over the bra legs and the physical leg:
+    // [X's other legs, ket_0, ket_1, bra_0, bra_1] for a's free legs 0, 1
+    TensorPtr Z = run(*Y, *As, {ypos(kx[0] + 1), ypos(kx[1] + 1), ysig}, {as[0] + 1, as[1] + 1, 0});
+    std::vector<int> afree;
+    for (int l = 0; l < 4; ++l)
+        if (l != as[0] && l != as[1]) afree.push_back(l);
+    const int nXf = nX - 2;
+    TensorPtr out = Z;
+    for (int i = 0; i < 2; ++i) {
+        std::vector<int> ket, bra;
+        Leg F;
+        double_layer_states(A.legs[afree[i] + 1], ket, bra, F, cm);
+        F.dir = A.legs[afree[i] + 1].dir;
+        // after i fusions: [X's other legs, F_0 .. F_(i-1), ket_i .. ket_1, bra_i .. bra_1]
+        pipe->fuse[i] = plan_refuse(*out, nXf + i, nXf + 2, F);
+        out = run_gather_plan(*pipe->fuse[i], *out, s);
+    }
+    r.corner = out;
+    pipe->info = r.info;
+    std::lock_guard<std::mutex> lk(g_sl_mu);
+    if (g_sl_cache.size() > 64) g_sl_cache.clear();   // plans keep their own references
+    g_sl_cache[key] = pipe;
+    return r;
+}
+
 // Several independent contractions in one gather + one grouped-GEMM launch.
 struct ContractSpec {
     const Tensor* A;
@@ -1573,6 +1675,16 @@ int symten_enlarged_corner(symten_t* out, int which, symten_t C, symten_t Ta, sy
     return guard([&] {
         if (!out) fail(SYMTEN_E_INVAL, "null output");
         CornerResult r = corner(which, T(C), T(Ta), T(Tb), T(a), prec, S(stream));
+        if (info) *info = r.info;
+        *out = wrap(r.corner);
+    });
+}
+
+int symten_enlarged_corner_single_layer(symten_t* out, int which, symten_t C, symten_t Ta, symten_t Tb, symten_t A,
+                                        int prec, symten_plan_stats* info, void* stream) {
+    return guard([&] {
+        if (!out) fail(SYMTEN_E_INVAL, "null output");
+        CornerResult r = corner_single_layer(which, T(C), T(Ta), T(Tb), T(A), prec, S(stream));
         if (info) *info = r.info;
         *out = wrap(r.corner);
     });

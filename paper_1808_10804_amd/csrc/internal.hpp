@@ -258,6 +258,30 @@ TensorPtr double_layer_su2(const Tensor& A, hipStream_t stream);
 // ordered by that charge, then q_ket, then (i_ket, i_bra); ket/bra are state
 // indices of the leg (charge-major order).
 void double_layer_states(const Leg& v, std::vector<int>& ket, std::vector<int>& bra, Leg& fused, int cm = 0);
+// The (ket, bra) parts of each sector Q of a double-layer leg fused from v:
+// ket charge ascending, each a contiguous run of dk * db fused states.
+struct FusedPart { int qk, qb, dk, db, off; };
+std::map<int, std::vector<FusedPart>> fused_parts(const Leg& v, int cm);
+// Leg p of X (a double-layer leg fused from v) split into a ket leg (v, the
+// leg's direction) at p and a bra leg (v, reversed) at p + 1; the result's
+// blocks are strided views of X's buffer.
+TensorPtr unfuse_leg(const Tensor& X, int p, const Leg& v, hipStream_t s);
+// The ket leg pk and bra leg pb of Z fused into F (the double-layer fusion of
+// the ket leg) at position pk, pb removed; one gather into a zeroed buffer.
+TensorPtr refuse_legs(const Tensor& Z, int pk, int pb, const Leg& F, hipStream_t s);
+// The two as reusable plans (output layout + device task table, cached by
+// source layout and arguments) and their execution into a new tensor.
+struct GatherPlan {
+    TensorPtr meta;            // output tensor without storage
+    BufferPtr tasks, prefix;   // device copy tasks (buffer 0: source, 1: output)
+    int ntasks = 0;
+    int64_t nchunks = 0;
+    bool zero = false;         // output parts not covered by a task are zero
+    bool view = false;         // the output's blocks are views of the source's buffer
+};
+std::shared_ptr<GatherPlan> plan_unfuse(const Tensor& X, int p, const Leg& v);
+std::shared_ptr<GatherPlan> plan_refuse(const Tensor& Z, int pk, int pb, const Leg& F);
+TensorPtr run_gather_plan(const GatherPlan& g, const Tensor& src, hipStream_t s);
 // SU(2) tensor with legs `legs` from the U(1) tensor of its S^z components
 // (the inverse of su2_to_u1 on invariant tensors): projection of every block
 // onto its basis tensor.

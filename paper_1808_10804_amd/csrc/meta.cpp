@@ -1290,3 +1290,231 @@ TensorPtr double_layer(const Tensor& A, hipStream_t stream, const double* op) {
 }
 
 }  // namespace symten
+
+// ------------------------------------------- unfusing / refusing (ket, bra)
+namespace symten {
+std::map<int, std::vector<FusedPart>> fused_parts(const Leg& v, int cm) {
+    std::map<int, std::vector<FusedPart>> out;
+    std::map<int, int> next;
+    for (size_t a = 0; a < v.q.size(); ++a)
+        for (size_t b = 0; b < v.q.size(); ++b) {
+            const int Q = cnorm(v.q[a] - v.q[b], cm);
+            FusedPart fp{v.q[a], v.q[b], v.d[a], v.d[b], next[Q]};
+            next[Q] += v.d[a] * v.d[b];
+            out[Q].push_back(fp);
+        }
+    return out;
+}
+
+namespace {
+// Metadata of a tensor with the given legs holding exactly the listed blocks
+// (canonical order, contiguous row-major).
+TensorPtr tensor_with_blocks(int group, int flux, int dtype, const std::vector<Leg>& legs,
+                             std::vector<Block> blocks) {
+    auto t = std::make_shared<Tensor>();
+    t->group = group;
+    t->flux = flux;
+    t->dtype = dtype;
+    t->legs = legs;
+    std::sort(blocks.begin(), blocks.end(), [](const Block& x, const Block& y) { return x.q < y.q; });
+    int64_t off = 0;
+    for (Block& b : blocks) {
+        const int R = (int)b.shape.size();
+        b.stride.assign(R, 1);
+        for (int l = R - 2; l >= 0; --l) b.stride[l] = b.stride[l + 1] * b.shape[l + 1];
+        b.size = 1;
+        for (int x : b.shape) b.size *= x;
+        b.offset = off;
+        off += b.size;
+    }
+    t->blocks = std::move(blocks);
+    t->rebuild_index();
+    t->elems = off;
+    return t;
+}
+
+std::mutex g_gather_mu;
+std::map<std::string, std::shared_ptr<GatherPlan>> g_gather_cache;
+
+std::shared_ptr<GatherPlan> make_gather_plan(std::vector<CopyTask>& tasks, const Tensor& src, TensorPtr out,
+                                             bool zero) {
+    auto g = std::make_shared<GatherPlan>();
+    validate_tasks(tasks, {src.elems, out->elems});
+    g->ntasks = (int)tasks.size();
+    if (!tasks.empty()) {
+        std::vector<int64_t> prefix;
+        copy_prefix(tasks, prefix);
+        upload_sync(g->tasks, tasks.data(), tasks.size() * sizeof(CopyTask));
+        upload_sync(g->prefix, prefix.data(), prefix.size() * sizeof(int64_t));
+        g->nchunks = prefix.back();
+    }
+    out->buf.reset();
+    out->meta_only = true;
+    g->meta = out;
+    g->zero = zero;
+    return g;
+}
+
+}  // namespace
+
+TensorPtr run_gather_plan(const GatherPlan& g, const Tensor& src, hipStream_t s) {
+    auto out = std::make_shared<Tensor>(*g.meta);
+    out->meta_only = false;
+    if (g.view) {
+        out->buf = src.buf;
+        return out;
+    }
+    out->buf = device_alloc(std::max<int64_t>(out->elems, 1) * out->esize());
+    if (g.zero) launch_fill_zero(out->data(), ((std::max<int64_t>(out->elems, 1) * out->esize() + 3) / 4) * 4, s);
+    if (g.ntasks > 0) {
+        const bool f64 = src.dtype == SYMTEN_F64;
+        copy_launch_arg((const CopyTask*)g.tasks->ptr, (const int64_t*)g.prefix->ptr, g.ntasks, g.nchunks,
+                        {src.data(), out->data()}, f64, f64 ? 1 : 0, s);
+    }
+    return out;
+}
+
+namespace {
+std::string leg_key(const Leg& l) {
+    std::string k = std::to_string(l.dir) + ":";
+    for (size_t i = 0; i < l.q.size(); ++i) k += std::to_string(l.q[i]) + "x" + std::to_string(l.d[i]) + ",";
+    return k;
+}
+
+std::shared_ptr<GatherPlan> cached(const std::string& key) {
+    std::lock_guard<std::mutex> lk(g_gather_mu);
+    auto it = g_gather_cache.find(key);
+    return it == g_gather_cache.end() ? nullptr : it->second;
+}
+void remember(const std::string& key, std::shared_ptr<GatherPlan> g) {
+    std::lock_guard<std::mutex> lk(g_gather_mu);
+    if (g_gather_cache.size() > 512) {
+        // launches in flight may still read the task tables
+        HIPCHK(hipDeviceSynchronize());
+        g_gather_cache.clear();
+    }
+    g_gather_cache[key] = std::move(g);
+}
+}  // namespace
+
+TensorPtr unfuse_leg(const Tensor& X, int p, const Leg& v, hipStream_t s) {
+    check_device_tensor(X, "unfuse");
+    return run_gather_plan(*plan_unfuse(X, p, v), X, s);
+}
+
+std::shared_ptr<GatherPlan> plan_unfuse(const Tensor& X, int p, const Leg& v) {
+    const std::string key = "u|" + tensor_signature(X) + "|" + std::to_string(p) + "|" + leg_key(v);
+    if (auto g = cached(key)) return g;
+    const int cm = charge_mod(X.group);
+    if (p < 0 || p >= X.rank() || X.rank() + 1 > SYMTEN_MAX_RANK) fail(SYMTEN_E_INVAL, "unfuse: bad leg");
+    auto parts = fused_parts(v, cm);
+    {
+        Leg F;
+        for (auto& kv : parts) {
+            F.q.push_back(kv.first);
+            int n = 0;
+            for (auto& fp : kv.second) n += fp.dk * fp.db;
+            F.d.push_back(n);
+        }
+        if (!F.same_sectors(X.legs[p])) fail(SYMTEN_E_LEGS, "unfuse: the leg is not the (ket, bra) fusion of v");
+    }
+    // Every (ket, bra) part of a fused block is a contiguous run of the fused
+    // index, (i_ket, i_bra) row-major: a strided view of the block, so the
+    // split tensor shares the source's buffer and nothing is copied.
+    auto out = std::make_shared<Tensor>();
+    out->group = X.group;
+    out->flux = X.flux;
+    out->dtype = X.dtype;
+    out->legs = X.legs;
+    Leg ket = v, bra = v;
+    ket.dir = X.legs[p].dir;
+    bra.dir = -X.legs[p].dir;
+    out->legs[p] = ket;
+    out->legs.insert(out->legs.begin() + p + 1, bra);
+    for (const Block& b : X.blocks)
+        for (const FusedPart& fp : parts.at(b.q[p])) {
+            Block n;
+            n.q = b.q;
+            n.q[p] = fp.qk;
+            n.q.insert(n.q.begin() + p + 1, fp.qb);
+            n.shape = b.shape;
+            n.shape[p] = fp.dk;
+            n.shape.insert(n.shape.begin() + p + 1, fp.db);
+            n.stride = b.stride;
+            n.stride[p] = (int64_t)fp.db * b.stride[p];
+            n.stride.insert(n.stride.begin() + p + 1, b.stride[p]);
+            n.offset = b.offset + (int64_t)fp.off * b.stride[p];
+            n.size = 1;
+            for (int x : n.shape) n.size *= x;
+            out->blocks.push_back(n);
+        }
+    std::sort(out->blocks.begin(), out->blocks.end(), [](const Block& x, const Block& y) { return x.q < y.q; });
+    out->rebuild_index();
+    out->elems = X.elems;
+    auto g = std::make_shared<GatherPlan>();
+    g->meta = out;
+    g->view = true;
+    remember(key, g);
+    return g;
+}
+
+TensorPtr refuse_legs(const Tensor& Z, int pk, int pb, const Leg& F, hipStream_t s) {
+    check_device_tensor(Z, "refuse");
+    return run_gather_plan(*plan_refuse(Z, pk, pb, F), Z, s);
+}
+
+std::shared_ptr<GatherPlan> plan_refuse(const Tensor& Z, int pk, int pb, const Leg& F) {
+    const std::string key = "f|" + tensor_signature(Z) + "|" + std::to_string(pk) + "," + std::to_string(pb) + "|" +
+                            leg_key(F);
+    if (auto g = cached(key)) return g;
+    const int cm = charge_mod(Z.group);
+    const int R = Z.rank();
+    if (pk < 0 || pb < 0 || pk >= R || pb >= R || pk == pb) fail(SYMTEN_E_INVAL, "refuse: bad legs");
+    const Leg &lk = Z.legs[pk], &lb = Z.legs[pb];
+    if (!lk.same_sectors(lb) || lk.dir != -lb.dir || F.dir != lk.dir)
+        fail(SYMTEN_E_LEGS, "refuse: ket and bra legs must be the same sectors, opposite directions");
+    auto parts = fused_parts(lk, cm);
+    auto newpos = [&](int l) { return l < pb ? l : l - 1; };
+    std::vector<Leg> legs;
+    for (int l = 0; l < R; ++l)
+        if (l != pb) legs.push_back(l == pk ? F : Z.legs[l]);
+    std::map<std::vector<int>, Block> targets;
+    struct Src { const Block* b; std::vector<int> key; int off, db; };
+    std::vector<Src> srcs;
+    for (const Block& b : Z.blocks) {
+        const int Q = cnorm(b.q[pk] - b.q[pb], cm);
+        int off = -1, db = 0;
+        for (const FusedPart& fp : parts.at(Q))
+            if (fp.qk == b.q[pk]) { off = fp.off; db = fp.db; }
+        if (off < 0 || F.dim_of(Q) == 0) fail(SYMTEN_E_LEGS, "refuse: fused sector missing");
+        Block t;
+        for (int l = 0; l < R; ++l) {
+            if (l == pb) continue;
+            t.q.push_back(l == pk ? Q : b.q[l]);
+            t.shape.push_back(l == pk ? F.dim_of(Q) : b.shape[l]);
+        }
+        targets[t.q] = t;
+        srcs.push_back({&b, t.q, off, db});
+    }
+    std::vector<Block> tb;
+    for (auto& kv : targets) tb.push_back(kv.second);
+    TensorPtr out = tensor_with_blocks(Z.group, Z.flux, Z.dtype, legs, tb);
+    std::vector<CopyTask> tasks;
+    for (const Src& sr : srcs) {
+        const Block& d = out->blocks[out->index.at(sr.key)];
+        std::vector<int64_t> ds(R);
+        const int pkn = newpos(pk);
+        for (int l = 0; l < R; ++l) {
+            if (l == pk) ds[l] = (int64_t)sr.db * d.stride[pkn];
+            else if (l == pb) ds[l] = d.stride[pkn];
+            else ds[l] = d.stride[newpos(l)];
+        }
+        std::vector<int64_t> ss(sr.b->stride.begin(), sr.b->stride.end());
+        tasks.push_back(make_copy_task(0, sr.b->offset, 1, d.offset + (int64_t)sr.off * d.stride[pkn], sr.b->shape, ss,
+                                       ds));
+    }
+    auto g = make_gather_plan(tasks, Z, out, true);
+    remember(key, g);
+    return g;
+}
+}  // namespace symten

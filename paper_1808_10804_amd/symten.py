@@ -229,6 +229,16 @@ def enlarged_corner(which, Cc, Ta, Tb, a, prec="f32", stream=None):
     return Tensor(h), st.to_dict()
 
 
+def enlarged_corner_single_layer(which, Cc, Ta, Tb, A, prec="f32", stream=None):
+    """The enlarged corner with A and A* absorbed separately (same result as
+    enlarged_corner with a = double_layer(A))."""
+    h = C.c_void_p()
+    st = _lib.PlanStats()
+    check(lib().symten_enlarged_corner_single_layer(C.byref(h), int(which), Cc._h, Ta._h, Tb._h, A._h, _prec(prec),
+                                                    C.byref(st), _stream(stream)))
+    return Tensor(h), st.to_dict()
+
+
 def enlarged_corners_batched(Cs, Tas, Tbs, As, prec="bf16x3", use_graph=False, stream=None):
     n = len(Cs)
     arr = lambda xs: (C.c_void_p * n)(*[x._h for x in xs])
