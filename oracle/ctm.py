@@ -285,3 +285,108 @@ def ising_initial_environment():
     t = np.zeros((1, 2, 1))
     t[0, 0, 0] = 1.0
     return [np.ones((1, 1))] * 4, [t] * 4
+
+
+# --------------------------------------------------------------------------
+# Unit cells of Lx x Ly sites (the paper times a 2 x 2 cell)
+# --------------------------------------------------------------------------
+# cell[x][y] = (C, T): the environment of site (x, y) as in the 1 x 1 case
+# (C1 top-left .. C4 bottom-left, T1 top .. T4 left); a[x][y] its site tensor.
+# x grows to the right, y downwards; indices are periodic.  The cut y lies
+# between site rows y and y + 1.
+
+def _corners(C, T, a, which):
+    """Enlarged corner `which` (1..4) of one site's environment as a matrix,
+    with the rows and columns of left_move."""
+    C1, C2, C3, C4 = C
+    T1, T2, T3, T4 = T
+    if which == 1:
+        c = _e("yxlu,lurd->ydxr", _e("aux,yla->yxlu", _e("ab,bux->aux", C1, T1), T4), a)
+    elif which == 2:
+        c = _e("xzur,lurd->xlzd", _e("cxu,crz->xzur", _e("bc,xub->cxu", C2, T1), T2), a)
+    elif which == 3:
+        c = _e("zydr,lurd->yuzl", _e("edz,yre->zydr", _e("ef,fdz->edz", C3, T3), T2), a)
+    else:
+        c = _e("zDly,lurD->yuzr", _e("qzD,qly->zDly", _e("pq,zDp->qzD", C4, T3), T4), a)
+    return c.reshape(c.shape[0] * c.shape[1], -1)
+
+
+def _cut_projectors(m1, m2, m3, m4, chi):
+    """P, P~ and the kept singular values of one horizontal cut from the four
+    enlarged corners around it (the scheme of left_move)."""
+    Hu = m1 @ m2
+    Hd = m4 @ m3.T
+    _, Ru = np.linalg.qr(Hu.T)
+    _, Rd = np.linalg.qr(Hd.T)
+    U, s, Vt = np.linalg.svd(Ru @ Rd.T)
+    k = int(min(chi, np.sum(s > CUTOFF * s[0])))
+    while 1 < k < len(s) and s[k] >= (1.0 - DEGENERATE_REL) * s[k - 1]:
+        k -= 1
+    sq = np.sqrt(s[:k])
+    return Rd.T @ Vt[:k].T / sq, (U[:, :k] / sq).T @ Ru, s[:k]
+
+
+def cell_left_move(cell, a, chi):
+    """Left move of a unit cell: column by column (x = 0 .. Lx - 1), the
+    projectors of every cut y from the 2 x 2 block of sites (x, y) .. (x + 1,
+    y + 1), then the left column of the sites (x + 1, y) renormalised:
+    C1'(x+1, y) = P(y-1)^T C1 T1 (x, y), T4'(x+1, y) = P~(y-1) T4 a (x, y) P(y),
+    C4'(x+1, y) = C4 T3 (x, y) P~(y)^T, each to unit norm.  Returns the new
+    cell and the kept singular values of every cut."""
+    Lx, Ly = len(cell), len(cell[0])
+    cell = [[(list(C), list(T)) for (C, T) in col] for col in cell]
+    svals = []
+    for x in range(Lx):
+        x1 = (x + 1) % Lx
+        P, Pt = {}, {}
+        for y in range(Ly):
+            y1 = (y + 1) % Ly
+            m1 = _corners(*cell[x][y], a[x][y], 1)
+            m2 = _corners(*cell[x1][y], a[x1][y], 2)
+            m3 = _corners(*cell[x1][y1], a[x1][y1], 3)
+            m4 = _corners(*cell[x][y1], a[x][y1], 4)
+            P[y], Pt[y], s = _cut_projectors(m1, m2, m3, m4, chi)
+            svals.append(s)
+        new = []
+        for y in range(Ly):
+            (C1, C2, C3, C4), (T1, T2, T3, T4) = cell[x][y]
+            ym = (y - 1) % Ly
+            CT = _e("ab,bux->aux", C1, T1)
+            C1n = P[ym].T @ CT.reshape(CT.shape[0] * CT.shape[1], -1)
+            T4a = _e("ylx,lurd->ydxur", T4, a[x][y])
+            T4a = T4a.reshape(T4.shape[0] * a[x][y].shape[3], T4.shape[2] * a[x][y].shape[1], a[x][y].shape[2])
+            T4n = _e("fk,fgr,hg->krh", P[y], T4a, Pt[ym])
+            C4T3 = _e("pq,zDp->zqD", C4, T3)
+            C4n = C4T3.reshape(C4T3.shape[0], -1) @ Pt[y].T
+            new.append((C1n, T4n, C4n))
+        nrm = lambda t: t / np.linalg.norm(t)
+        for y in range(Ly):
+            C, T = cell[x1][y]
+            C[0], T[3], C[3] = (nrm(t) for t in new[y])
+    return cell, svals
+
+
+def cell_rotate(cell, a):
+    """The cell turned a quarter counterclockwise: site (x, y) moves to
+    (y, Lx - 1 - x), and every site's environment and tensor turn as in
+    rotate."""
+    Lx, Ly = len(cell), len(cell[0])
+    nc = [[None] * Lx for _ in range(Ly)]
+    na = [[None] * Lx for _ in range(Ly)]
+    for x in range(Lx):
+        for y in range(Ly):
+            C, T, ar = rotate(*cell[x][y], a[x][y])
+            nc[y][Lx - 1 - x] = (C, T)
+            na[y][Lx - 1 - x] = ar
+    return nc, na
+
+
+def cell_move(cell, a, chi, direction):
+    """Move toward `direction` (0 left .. 3 bottom) of a unit cell: the left
+    move of the cell turned `direction` quarter turns, turned back."""
+    for _ in range(direction):
+        cell, a = cell_rotate(cell, a)
+    cell, s = cell_left_move(cell, a, chi)
+    for _ in range(4 - direction):
+        cell, a = cell_rotate(cell, a)
+    return cell, s

@@ -305,3 +305,89 @@ def test_ising_free_energy(beta):
     C, T = ctm.ising_initial_environment()
     _, _, r = ctm.run(C, T, a, 16, block=1, max_steps=100, tol=1e-13)
     assert abs(np.log(r["kappa"]) - ctm.onsager_log_z(beta)) < 1e-9
+
+
+# ------------------------------------------------ unit cells
+def test_cell_of_one_site_is_the_1x1_move():
+    c = config(1)
+    w, T, a, _ = oracle_side(c, c["seed"])
+    C0 = [T["C1"], T["C2"], T["C3"], T["C4"]]
+    T0 = [T["T1"], T["T2"], T["T3"], T["T4"]]
+    for d in range(4):
+        Co, To, s = ctm.move(C0, T0, a, 16, d)
+        cell, sv = ctm.cell_move([[(C0, T0)]], [[a]], 16, d)
+        Cc, Tc = cell[0][0]
+        i, j = d, (d + 3) % 4
+        L1, L2 = u1.left_column(Co[i], To[j], Co[j]), u1.left_column(Cc[i], Tc[j], Cc[j])
+        assert np.linalg.norm(L1 - L2) <= 1e-12 * np.linalg.norm(L1)
+        assert np.allclose(sv[0], s, rtol=0, atol=1e-13 * s[0])
+
+
+def test_uniform_2x2_cell_left_move_is_sequential():
+    """Four copies of one site and its environment.  The columns are moved one
+    after the other: column 1 absorbs column 0 (one 1 x 1 left move), then
+    column 0 absorbs the updated column 1 (two 1 x 1 left moves); the rows of
+    each column stay equal, and every cut's spectrum is the 1 x 1 one of the
+    same step."""
+    c = config(1)
+    w, T, a, _ = oracle_side(c, c["seed"])
+    C, Tt = [T["C1"], T["C2"], T["C3"], T["C4"]], [T["T1"], T["T2"], T["T3"], T["T4"]]
+    cell = [[(C, Tt), (C, Tt)], [(C, Tt), (C, Tt)]]
+    cell, sv = ctm.cell_move(cell, [[a, a], [a, a]], 12, 0)
+    C1, T1, s1 = ctm.move(C, Tt, a, 12, 0)
+    C2, T2, s2 = ctm.move(C1, T1, a, 12, 0)
+    col = lambda Cs, Ts: u1.left_column(Cs[0], Ts[3], Cs[3])
+    for x, (Cr, Tr) in ((1, (C1, T1)), (0, (C2, T2))):
+        for y in range(2):
+            L = col(*cell[x][y])
+            assert np.linalg.norm(L - col(Cr, Tr)) <= 1e-11 * np.linalg.norm(L)
+    for v, ref in zip(sv, [s1, s1, s2, s2]):
+        assert np.allclose(v, ref, rtol=0, atol=1e-12 * ref[0])
+
+
+def test_cell_rotation_four_turns_is_identity():
+    rng = np.random.default_rng(4)
+    cell = [[([rng.standard_normal((2, 2)) for _ in range(4)], [rng.standard_normal((2, 3, 2)) for _ in range(4)])
+             for _ in range(3)] for _ in range(2)]
+    A = [[rng.standard_normal((3, 3, 3, 3)) for _ in range(3)] for _ in range(2)]
+    c2, a2 = cell, A
+    for _ in range(4):
+        c2, a2 = ctm.cell_rotate(c2, a2)
+    for x in range(2):
+        for y in range(3):
+            assert np.array_equal(a2[x][y], A[x][y])
+            for u, v in zip(c2[x][y][0] + c2[x][y][1], cell[x][y][0] + cell[x][y][1]):
+                assert np.array_equal(u, v)
+    c1, a1 = ctm.cell_rotate(cell, A)
+    assert len(c1) == 3 and len(c1[0]) == 2                       # Lx' = Ly, Ly' = Lx
+    assert np.array_equal(a1[0][1], A[0][0].transpose(1, 2, 3, 0))   # top-left goes to bottom-left
+
+
+@pytest.mark.parametrize("beta", [0.3, 0.38])
+def test_ising_cell_from_unequal_starts(beta):
+    """The Ising model (disordered phase, beta < beta_c = 0.4407, where the
+    fixed point is unique) on a 2 x 2 cell whose four sites start from
+    different environments (chi = 2, positive random entries on the allowed
+    parity blocks): every site's environment converges to the fixed point
+    and reproduces Onsager's ln Z per site."""
+    a = ctm.ising_tensor(beta)
+    rng = np.random.default_rng(8)
+    par = np.array([0, 1])
+
+    def env():
+        C = [np.diag(rng.uniform(0.5, 1.5, 2)) for _ in range(4)]
+        T = []
+        for _ in range(4):
+            t = rng.uniform(0.5, 1.5, (2, 2, 2))
+            t[(par[:, None, None] + par[None, :, None] + par[None, None, :]) % 2 == 1] = 0.0
+            T.append(t)
+        return C, T
+    cell = [[env() for _ in range(2)] for _ in range(2)]
+    A = [[a, a], [a, a]]
+    for _ in range(40):
+        for d in range(4):
+            cell, _ = ctm.cell_move(cell, A, 12, d)
+    for x in range(2):
+        for y in range(2):
+            k, _ = ctm.site_partition(*cell[x][y], a)
+            assert abs(np.log(k) - ctm.onsager_log_z(beta)) < 1e-8
