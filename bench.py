@@ -405,6 +405,50 @@ def bench_corners(args):
     print(json.dumps(out))
 
 
+def bench_cell(args):
+    """A 2 x 2 unit cell of the workload's site (four independent draws of
+    the site and its environment): one left move of the cell = four cuts,
+    each from the enlarged corners of its 2 x 2 block, and eight
+    renormalised tensors per column."""
+    import torch
+    import paper_1808_10804_amd as st
+    from synth import config, draw, TENSOR_INDEX
+    cfgd = config(args.config)
+    prec = args.prec or {"sweep": "f32"}.get(cfgd["prec"], cfgd["prec"])
+    dtype = "f64" if prec == "f64" else "f32"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    env_names = ("C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4")
+    sites = [[build_workload(cfgd, cfgd["seed"] + 100 * (2 * x + y), dtype, st, draw, TENSOR_INDEX) for y in range(2)]
+             for x in range(2)]
+
+    def fresh():
+        return st.CtmCell([[([s[k] for k in env_names[:4]], [s[k] for k in env_names[4:]]) for s in col]
+                           for col in sites])
+    a = [[s["a"] for s in col] for col in sites]
+    cell = fresh()
+    for _ in range(args.warmup):
+        cell = fresh()
+        cell.move(a, cfgd["chi_target"], prec=prec, stream=stream)
+    torch.cuda.synchronize()
+    cells = [fresh() for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for c in cells:
+        c.move(a, cfgd["chi_target"], prec=prec, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    out = {
+        "metric": "ms per left move of a 2 x 2 unit cell (four cuts, one projector pair each)",
+        "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+        "data": "synthetic (seeded Gaussian blocks, four draws)",
+        "config": {"workload": cfgd["name"] + "_cell2x2", "D_virtual": cfgd["virt"], "chi": cfgd["chi_target"],
+                   "chi_sectors": cfgd["chi"], "parallelism": "single GPU"},
+        "ms_per_cut": ms / 4,
+    }
+    print(json.dumps(out))
+
+
 def use_recorded_tiles(workload):
     """GEMM tile choices recorded with the committed counter runs: when
     profiles/tune_<workload>.txt exists (and SYMTEN_TUNE_CACHE is not set),
@@ -471,6 +515,7 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cell", action="store_true", help="time the left move of a 2 x 2 unit cell")
     ap.add_argument("--corners", action="store_true",
                     help="time the four enlarged corners, single-layer against double-layer route")
     args = ap.parse_args()
@@ -480,6 +525,9 @@ def main():
         sys.exit(2)
     if args.corners:
         bench_corners(args)
+        return
+    if args.cell:
+        bench_cell(args)
         return
     if args.config == 5:
         bench_batched(args)

@@ -326,6 +326,32 @@ int ctm_move(ctm_env_t env, symten_t a, int dir, int chi, int prec,
  * Z_00, Z_b0, Z_0b, Z_bb.  Synchronous.                                      */
 int ctm_site_partition(ctm_env_t env, symten_t a, int block, double* kappa, double* z, void* stream);
 
+/* ---- unit cells (Lx x Ly sites, the paper's 2 x 2 geometry) ----------
+ * Every site (x, y) (x to the right, y downwards, periodic) has its own
+ * environment C1..C4, T1..T4 with the conventions of the 1x1 case, passed
+ * as C[4 (x Ly + y) + i], T[4 (x Ly + y) + i] (the environment keeps
+ * references to them), and its own site tensor a[x Ly + y].  U(1) and Z2.  */
+int ctm_cell_create(ctm_env_t* env, int Lx, int Ly, const symten_t* C, const symten_t* T);
+/* Current tensor k (0..3 = C1..C4, 4..7 = T1..T4) of site (x, y); a new
+ * handle sharing the storage.                                               */
+int ctm_cell_get(ctm_env_t env, int x, int y, int k, symten_t* t);
+/* One move of the cell toward `dir` (Sec. 3, the scheme it cites, with one
+ * projector pair per cut).  The left move runs column by column
+ * (x = 0 .. Lx-1): for every cut y (between site rows y and y+1) the
+ * projectors of the 1x1 move are computed from the enlarged corners of the
+ * 2 x 2 block of sites (x, y), (x+1, y), (x+1, y+1), (x, y+1), each from its
+ * own site's environment; then the left column of the sites (x+1, y) is
+ * renormalised: C1' = P(y-1)^T C1 T1 (x, y), T4' = P~(y-1) T4 a (x, y) P(y),
+ * C4' = C4 T3 (x, y) P~(y)^T, each to unit norm.  Column x+1 changes before
+ * the next column is processed.  Other directions turn the cell (site
+ * (x, y) -> (y, Lx-1-x), every site as in ctm_move) and back.
+ * ctm_move_singular_values returns the kept values of every cut of the
+ * move, cut after cut, each cut's descending.                              */
+int ctm_cell_move(ctm_env_t env, const symten_t* a, int dir, int chi, int prec, void* stream);
+/* ctm_site_partition on the environment of site (x, y).                   */
+int ctm_cell_site_partition(ctm_env_t env, int x, int y, symten_t a, int block, double* kappa, double* z,
+                            void* stream);
+
 /* Expectation value on an n x m patch (n columns, m rows; 1 <= n, m <= 2)
  * of the 1x1-cell environment, FP64: value = Z_nm(sites) / Z_nm(a), where
  * Z_nm(sites) is the closed network of ctm_site_partition with the site

@@ -119,6 +119,11 @@ SIGNATURES = {
     "ctm_expectation": (C.c_int, [H, H, C.c_int, C.c_int, C.POINTER(H), C.POINTER(C.c_double), P]),
     "ctm_heisenberg_bond_energy": (C.c_int, [H, H, C.POINTER(C.c_double), C.POINTER(C.c_double), P]),
     "symten_double_layer_op": (C.c_int, [C.POINTER(H), H, C.POINTER(C.c_double), P]),
+    "ctm_cell_create": (C.c_int, [C.POINTER(H), C.c_int, C.c_int, C.POINTER(H), C.POINTER(H)]),
+    "ctm_cell_get": (C.c_int, [H, C.c_int, C.c_int, C.c_int, C.POINTER(H)]),
+    "ctm_cell_move": (C.c_int, [H, C.POINTER(H), C.c_int, C.c_int, C.c_int, P]),
+    "ctm_cell_site_partition": (C.c_int, [H, C.c_int, C.c_int, H, C.c_int, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double), P]),
     "ctm_move_singular_values": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64, I64P]),
     "ctm_move_projectors": (C.c_int, [H, C.POINTER(H), C.POINTER(H)]),
     "ctm_env_set": (C.c_int, [H, C.c_int, H]),

@@ -310,7 +310,7 @@ std::vector<Contracted> contract_batched(const std::vector<ContractSpec>& specs,
 // Corners `which` (inputs C, Ta, Tb each), step by step across all of them.
 std::vector<CornerResult> corners_batched(const std::vector<int>& which,
                                           const std::vector<std::array<const Tensor*, 3>>& in, const Tensor& a,
-                                          int prec, hipStream_t s) {
+                                          int prec, hipStream_t s, const std::vector<const Tensor*>* as = nullptr) {
     const size_t n = which.size();
     std::vector<CornerResult> res(n);
     std::vector<CornerSpec> sp;
@@ -320,7 +320,7 @@ std::vector<CornerResult> corners_batched(const std::vector<int>& which,
         for (size_t i = 0; i < n; ++i) {
             if (step == 0) cs.push_back({in[i][0], in[i][1], sp[i].l1a, sp[i].l1b, {}});
             else if (step == 1) cs.push_back({res[i].step1.get(), in[i][2], sp[i].l2a, sp[i].l2b, {}});
-            else cs.push_back({res[i].step2.get(), &a, sp[i].l3a, sp[i].l3b, {}});
+            else cs.push_back({res[i].step2.get(), as ? (*as)[i] : &a, sp[i].l3a, sp[i].l3b, {}});
         }
         std::vector<Contracted> r = contract_batched(cs, prec, s);
         for (size_t i = 0; i < n; ++i) {
@@ -367,6 +367,10 @@ using namespace symten;
 struct ctm_env {
     TensorPtr C[4], T[4];
     std::vector<double> svals;
+    // unit cell of Lx x Ly sites (0: the 1x1 environment above); site (x, y)
+    // holds cC[4 (x Ly + y) + i] = C_(i+1) and cT likewise
+    int Lx = 0, Ly = 0;
+    std::vector<TensorPtr> cC, cT;
     symten_tensor P, Pt;
     rocblas_handle rb = nullptr;
     // side streams for the size classes of the projector eigensolves, which
@@ -1062,6 +1066,7 @@ void move_su2(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st, hi
         st->ms_total = tm.ms(0, 4);
     }
 }
+
 }  // namespace
 }  // namespace symten
 
@@ -1262,35 +1267,34 @@ double expectation(ctm_env* env, const TensorPtr& a, int n, int m, const std::ve
 namespace symten {
 namespace {
 // One U(1) left move on the environment's current tensors (see ctm_move).
-void move_u1_left(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st, hipStream_t s) {
+// The projectors of one horizontal cut from the four enlarged corners
+// around it (the halves H_u = C~1 C~2, H_d = C~4 C~3, then the FP64 stage):
+// P[chi out, D in, k in] below the upper half, P~[k out, chi in, D out]
+// above the lower half; chiL and dL are the chi and D legs of the cut (the
+// lower legs of C~1).  Pc, Ptc: the same in the storage precision.
+struct CutResult {
+    TensorPtr P, Pt, Pc, Ptc;
+    ProjOut po;
+    std::vector<CutSector> secs;
+    std::vector<Contracted> halves;
+};
+CutResult cut_from_corners(ctm_env* env, const CornerResult& k1, const CornerResult& k2, const CornerResult& k3,
+                           const CornerResult& k4, const Leg& chiL, const Leg& dL, int group, int chi, int prec,
+                           Timer* tm, hipStream_t s) {
     const bool f64 = prec == SYMTEN_PREC_F64;
-    Timer tm;
-    tm.init(st != nullptr);
-    tm.mark(s);
-    Tensor &C1 = *env->C[0], &C2 = *env->C[1], &C3 = *env->C[2], &C4 = *env->C[3];
-    Tensor &T1 = *env->T[0], &T2 = *env->T[1], &T3 = *env->T[2], &T4 = *env->T[3];
-    // the four corners are independent: each of their three steps is one
-    // gather launch and one grouped-GEMM launch for all four
-    std::vector<CornerResult> ks =
-        corners_batched({1, 2, 3, 4}, {{&C1, &T1, &T4}, {&C2, &T1, &T2}, {&C3, &T3, &T2}, {&C4, &T3, &T4}}, a,
-                        prec, s);
-    CornerResult &k1 = ks[0], &k2 = ks[1], &k3 = ks[2], &k4 = ks[3];
-    tm.mark(s);
+    CutResult cr;
     // halves: H_u = C~1 C~2 -> [x4, d, x2, d2]; H_d = C~4 C~3 -> [x4, u, x2, u3]
-    std::vector<Contracted> hh = contract_batched({{k1.corner.get(), k2.corner.get(), {0, 2}, {0, 2}, {}},
-                                                   {k4.corner.get(), k3.corner.get(), {0, 3}, {0, 2}, {}}},
-                                                  prec, s);
-    Contracted &hu = hh[0], &hd = hh[1];
-    tm.mark(s);
-
+    cr.halves = contract_batched({{k1.corner.get(), k2.corner.get(), {0, 2}, {0, 2}, {}},
+                                  {k4.corner.get(), k3.corner.get(), {0, 3}, {0, 2}, {}}},
+                                 prec, s);
+    Contracted &hu = cr.halves[0], &hd = cr.halves[1];
+    if (tm) tm->mark(s);
     // ---- projectors, per fused charge Q of the left cut (FP64) ----------
     std::map<int, const GroupPlan*> gu_of, gd_of;
-    const int cm = charge_mod(a.group);
+    const int cm = charge_mod(group);
     for (auto& g : hu.plan->groups) gu_of[cnorm(g.rows[0][0] - g.rows[0][1], cm)] = &g;
     for (auto& g : hd.plan->groups) gd_of[cnorm(g.rows[0][0] - g.rows[0][1], cm)] = &g;
     const size_t es = f64 ? 8 : 4;
-    const Leg& chiL = T4.legs[0];
-    const Leg& dL = a.legs[3];
     // The rows of both halves are the (q_chi, q_D) blocks of the cut reached
     // by their contractions; where the two sets differ, both halves are laid
     // out over the union (rows missing on one side are zero).
@@ -1375,7 +1379,7 @@ void move_u1_left(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st
     auto P = std::make_shared<Tensor>();
     auto Pt = std::make_shared<Tensor>();
     for (auto* X : {P.get(), Pt.get()}) {
-        X->group = a.group;
+        X->group = group;
         X->flux = 0;
         X->dtype = SYMTEN_F64;
     }
@@ -1436,45 +1440,136 @@ void move_u1_left(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st
         launch_cast(P->buf->ptr, true, Pc->buf->ptr, false, ptot, s);
         launch_cast(Pt->buf->ptr, true, Ptc->buf->ptr, false, ptot, s);
     }
-    tm.mark(s);
-    // ---- renormalise -----------------------------------------------------
+    cr.P = P;
+    cr.Pt = Pt;
+    cr.Pc = Pc;
+    cr.Ptc = Ptc;
+    cr.po = po;
+    cr.secs = secs;
+    return cr;
+}
+
+// C1' = (C1 T1) P_above, T4' = P~_above (T4 a) P_below, C4' = (C4 T3) P~_below^T,
+// each scaled to unit Frobenius norm in FP64; c1t1 and c4t3 are the first
+// steps of enlarged corners 1 and 4 (C1 T1 and C4 T3).
+struct Renormalised {
+    TensorPtr C1, T4, C4;
+    symten_plan_stats info{};
+};
+Renormalised renormalise_left(const Tensor& c1t1, const Tensor& c4t3, const Tensor& T4, const Tensor& a,
+                              const CutResult& above, const CutResult& below, int prec, hipStream_t s) {
+    const bool f64 = prec == SYMTEN_PREC_F64;
     // T4' = ((P~ T4) a) P: absorbing P~ first keeps the intermediates at
     // chi' chi D^4 instead of the chi^2 D^6 of T4 a.
     std::vector<Contracted> r3 =
-        contract_batched({{k1.step1.get(), Pc.get(), {0, 1}, {0, 1}, {1, 0}},      // C1' = [k, x1]
-                          {k4.step1.get(), Ptc.get(), {0, 2}, {1, 2}, {}},         // C4' = [x3, k]
-                          {Ptc.get(), &T4, {1}, {2}, {}}},                         // P~ T4 = [k_hi, u, y, l]
+        contract_batched({{&c1t1, above.Pc.get(), {0, 1}, {0, 1}, {1, 0}},      // C1' = [k, x1]
+                          {&c4t3, below.Ptc.get(), {0, 2}, {1, 2}, {}},         // C4' = [x3, k]
+                          {above.Ptc.get(), &T4, {1}, {2}, {}}},                // P~ T4 = [k_hi, u, y, l]
                          prec, s);
     Contracted &c1n = r3[0], &c4n = r3[1], &t4a = r3[2];
     Contracted xx = contract(*t4a.t, a, {1, 3}, {1, 0}, {}, prec, s);               // [k_hi, y, r, d]
-    Contracted t4n = contract(*xx.t, *Pc, {1, 3}, {0, 1}, {2, 1, 0}, prec, s);      // [k_lo, r, k_hi]
-    // ---- normalise in FP64 ----------------------------------------------
+    Contracted t4n = contract(*xx.t, *below.Pc, {1, 3}, {0, 1}, {2, 1, 0}, prec, s);  // [k_lo, r, k_hi]
     BufferPtr red = device_alloc(8 * (1 + 512));
     for (TensorPtr X : {c1n.t, t4n.t, c4n.t}) {
         launch_sumsq(X->data(), f64, X->elems, (double*)red->ptr, s);
         launch_scale_by_inv_sqrt(X->data(), f64, X->elems, (const double*)red->ptr, s);
     }
+    Renormalised r;
+    r.C1 = c1n.t;
+    r.T4 = t4n.t;
+    r.C4 = c4n.t;
+    for (auto* c : {&c1n, &t4a, &xx, &t4n, &c4n}) add_info(r.info, c->plan->info);
+    return r;
+}
+
+void move_u1_left(ctm_env* env, Tensor& a, int chi, int prec, ctm_move_stats* st, hipStream_t s) {
+    Timer tm;
+    tm.init(st != nullptr);
     tm.mark(s);
-    env->C[0] = c1n.t;
-    env->T[3] = t4n.t;
-    env->C[3] = c4n.t;
-    env->P.t = P;
-    env->Pt.t = Pt;
-    env->svals = po.sv;
+    Tensor &C1 = *env->C[0], &C2 = *env->C[1], &C3 = *env->C[2], &C4 = *env->C[3];
+    Tensor &T1 = *env->T[0], &T2 = *env->T[1], &T3 = *env->T[2], &T4 = *env->T[3];
+    // the four corners are independent: each of their three steps is one
+    // gather launch and one grouped-GEMM launch for all four
+    std::vector<CornerResult> ks =
+        corners_batched({1, 2, 3, 4}, {{&C1, &T1, &T4}, {&C2, &T1, &T2}, {&C3, &T3, &T2}, {&C4, &T3, &T4}}, a,
+                        prec, s);
+    CornerResult &k1 = ks[0], &k2 = ks[1], &k3 = ks[2], &k4 = ks[3];
+    tm.mark(s);
+    CutResult cr = cut_from_corners(env, k1, k2, k3, k4, T4.legs[0], a.legs[3], a.group, chi, prec, &tm, s);
+    tm.mark(s);
+    // ---- renormalise (one cut above and below: the 1x1 cell) ------------
+    Renormalised rn = renormalise_left(*k1.step1, *k4.step1, T4, a, cr, cr, prec, s);
+    tm.mark(s);
+    env->C[0] = rn.C1;
+    env->T[3] = rn.T4;
+    env->C[3] = rn.C4;
+    env->P.t = cr.P;
+    env->Pt.t = cr.Pt;
+    env->svals = cr.po.sv;
     if (st) {
         std::memset(st, 0, sizeof(*st));
         HIPCHK(hipStreamSynchronize(s));
-        fill_cut_stats(st, secs, po);
+        fill_cut_stats(st, cr.secs, cr.po);
         st->flops_corners = k1.info.useful_flops + k2.info.useful_flops + k3.info.useful_flops + k4.info.useful_flops;
-        st->flops_halves = hu.plan->info.useful_flops + hd.plan->info.useful_flops;
-        st->flops_renorm = c1n.plan->info.useful_flops + t4a.plan->info.useful_flops + xx.plan->info.useful_flops +
-                           t4n.plan->info.useful_flops + c4n.plan->info.useful_flops;
+        st->flops_halves = cr.halves[0].plan->info.useful_flops + cr.halves[1].plan->info.useful_flops;
+        st->flops_renorm = rn.info.useful_flops;
 
         st->ms_corners = tm.ms(0, 1);
         st->ms_halves = tm.ms(1, 2);
         st->ms_proj = tm.ms(2, 3);
         st->ms_renorm = tm.ms(3, 4);
         st->ms_total = tm.ms(0, 4);
+    }
+}
+
+// Left move of a unit cell, column by column (x = 0 .. Lx-1): the projectors
+// of every cut y (between site rows y and y+1) from the 2 x 2 block of sites
+// (x, y) .. (x+1, y+1), each site's enlarged corner built from its own
+// environment, then the left column of the sites (x+1, y):
+// C1' = P(y-1)^T C1 T1 (x, y), T4' = P~(y-1) T4 a (x, y) P(y),
+// C4' = C4 T3 (x, y) P~(y)^T.  Column x+1 is updated before column x+1 is
+// used (the moves run one after another).  a[x Ly + y] are the site tensors.
+void cell_left_move(ctm_env* env, const std::vector<TensorPtr>& a, int chi, int prec, hipStream_t s) {
+    const int Lx = env->Lx, Ly = env->Ly;
+    auto C = [&](int x, int y, int i) -> Tensor& { return *env->cC[4 * (((x % Lx) + Lx) % Lx * Ly + ((y % Ly) + Ly) % Ly) + i]; };
+    auto T = [&](int x, int y, int i) -> Tensor& { return *env->cT[4 * (((x % Lx) + Lx) % Lx * Ly + ((y % Ly) + Ly) % Ly) + i]; };
+    auto A = [&](int x, int y) -> Tensor& { return *a[((x % Lx) + Lx) % Lx * Ly + ((y % Ly) + Ly) % Ly]; };
+    env->svals.clear();
+    for (int x = 0; x < Lx; ++x) {
+        const int x1 = x + 1;
+        std::vector<CutResult> cuts(Ly);
+        std::vector<TensorPtr> c1t1(Ly), c4t3(Ly);
+        for (int y = 0; y < Ly; ++y) {
+            const int y1 = y + 1;
+            std::vector<const Tensor*> as = {&A(x, y), &A(x1, y), &A(x1, y1), &A(x, y1)};
+            std::vector<CornerResult> ks = corners_batched(
+                {1, 2, 3, 4},
+                {{&C(x, y, 0), &T(x, y, 0), &T(x, y, 3)}, {&C(x1, y, 1), &T(x1, y, 0), &T(x1, y, 1)},
+                 {&C(x1, y1, 2), &T(x1, y1, 2), &T(x1, y1, 1)}, {&C(x, y1, 3), &T(x, y1, 2), &T(x, y1, 3)}},
+                A(x, y), prec, s, &as);
+            cuts[y] = cut_from_corners(env, ks[0], ks[1], ks[2], ks[3], T(x, y, 3).legs[0], A(x, y).legs[3],
+                                       A(x, y).group, chi, prec, nullptr, s);
+            c1t1[y] = ks[0].step1;             // C1 T1 of site (x, y)
+            c4t3[y1 % Ly] = ks[3].step1;       // C4 T3 of site (x, y+1)
+            // the kept values of the cut, descending
+            std::vector<double> sv = cuts[y].po.sv;
+            std::sort(sv.begin(), sv.end(), std::greater<double>());
+            int kept = 0;
+            for (auto& c : cuts[y].secs) kept += c.k * c.weight;
+            env->svals.insert(env->svals.end(), sv.begin(), sv.begin() + std::min<size_t>(kept, sv.size()));
+        }
+        std::vector<Renormalised> rn;
+        for (int y = 0; y < Ly; ++y)
+            rn.push_back(renormalise_left(*c1t1[y], *c4t3[y], T(x, y, 3), A(x, y), cuts[(y + Ly - 1) % Ly], cuts[y],
+                                          prec, s));
+        const int xn = x1 % Lx;
+        for (int y = 0; y < Ly; ++y) {
+            env->cC[4 * (xn * Ly + y) + 0] = rn[y].C1;
+            env->cT[4 * (xn * Ly + y) + 3] = rn[y].T4;
+            env->cC[4 * (xn * Ly + y) + 3] = rn[y].C4;
+        }
+        env->P.t = cuts[Ly - 1].P;
+        env->Pt.t = cuts[Ly - 1].Pt;
     }
 }
 }  // namespace
@@ -2089,6 +2184,114 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         for (int i = 0; i < 4; ++i) { C[i] = env->C[i]; Tt[i] = env->T[i]; }
         for (int r = dir; r < 4; ++r) rotate_ccw(C, Tt, ar);
         for (int i = 0; i < 4; ++i) { env->C[i] = C[i]; env->T[i] = Tt[i]; }
+    });
+}
+
+int ctm_cell_create(ctm_env_t* env, int Lx, int Ly, const symten_t* C, const symten_t* Tt) {
+    return guard([&] {
+        if (!env || !C || !Tt || Lx < 1 || Ly < 1 || Lx > 16 || Ly > 16) fail(SYMTEN_E_INVAL, "bad argument");
+        // the handles and side streams of a 1x1 environment on site (0, 0)
+        ctm_env_t e = nullptr;
+        const int rc = ctm_env_create(&e, C, Tt);
+        if (rc != SYMTEN_OK) fail(rc, g_err);
+        e->Lx = Lx;
+        e->Ly = Ly;
+        for (int i = 0; i < 4 * Lx * Ly; ++i) {
+            Tensor &c = T(C[i]), &t = T(Tt[i]);
+            if (!c.buf || !t.buf || c.rank() != 2 || t.rank() != 3 || c.group != e->C[0]->group ||
+                t.group != e->C[0]->group || !abelian(c.group)) {
+                delete e;
+                fail(SYMTEN_E_INVAL, "cell: C rank 2 and T rank 3 with device storage, one abelian group");
+            }
+            e->cC.push_back(C[i]->t);
+            e->cT.push_back(Tt[i]->t);
+        }
+        *env = e;
+    });
+}
+
+int ctm_cell_get(ctm_env_t env, int x, int y, int k, symten_t* t) {
+    return guard([&] {
+        if (!env || !t || env->Lx < 1) fail(SYMTEN_E_INVAL, "not a unit-cell environment");
+        if (x < 0 || y < 0 || x >= env->Lx || y >= env->Ly || k < 0 || k > 7) fail(SYMTEN_E_INVAL, "bad index");
+        const int i = 4 * (x * env->Ly + y) + (k & 3);
+        *t = wrap(k < 4 ? env->cC[i] : env->cT[i]);
+    });
+}
+
+int ctm_cell_move(ctm_env_t env, const symten_t* a_h, int dir, int chi, int prec, void* stream) {
+    return guard([&] {
+        if (!env || !a_h || env->Lx < 1) fail(SYMTEN_E_INVAL, "not a unit-cell environment");
+        if (dir < CTM_LEFT || dir > CTM_BOTTOM) fail(SYMTEN_E_INVAL, "ctm_cell_move: direction must be 0..3");
+        if (chi < 1) fail(SYMTEN_E_INVAL, "chi must be positive");
+        const bool f64 = prec == SYMTEN_PREC_F64;
+        int Lx = env->Lx, Ly = env->Ly;
+        std::vector<TensorPtr> a;
+        for (int i = 0; i < Lx * Ly; ++i) {
+            Tensor& t = T(a_h[i]);
+            check_device_tensor(t, "ctm_cell_move(a)");
+            if (t.rank() != 4 || t.group != env->cC[0]->group) fail(SYMTEN_E_INVAL, "cell: a is rank 4, the cell's group");
+            if ((t.dtype == SYMTEN_F64) != f64) fail(SYMTEN_E_INVAL, "cell: storage types do not match the precision");
+            a.push_back(a_h[i]->t);
+        }
+        for (auto& x : env->cC)
+            if ((x->dtype == SYMTEN_F64) != f64) fail(SYMTEN_E_INVAL, "cell: storage types do not match the precision");
+        // turn the cell `dir` quarter turns: site (x, y) -> (y, Lx - 1 - x),
+        // every site's environment and tensor turned as in the 1x1 case
+        auto turn = [&](int times) {
+            for (int r = 0; r < times; ++r) {
+                std::vector<TensorPtr> nC(4 * Lx * Ly), nT(4 * Lx * Ly), na(Lx * Ly);
+                for (int x = 0; x < Lx; ++x)
+                    for (int y = 0; y < Ly; ++y) {
+                        std::array<TensorPtr, 4> Cs, Ts;
+                        for (int i = 0; i < 4; ++i) {
+                            Cs[i] = env->cC[4 * (x * Ly + y) + i];
+                            Ts[i] = env->cT[4 * (x * Ly + y) + i];
+                        }
+                        TensorPtr ar = a[x * Ly + y];
+                        rotate_ccw(Cs, Ts, ar);
+                        const int nx = y, ny = Lx - 1 - x, nLy = Lx;
+                        for (int i = 0; i < 4; ++i) {
+                            nC[4 * (nx * nLy + ny) + i] = Cs[i];
+                            nT[4 * (nx * nLy + ny) + i] = Ts[i];
+                        }
+                        na[nx * nLy + ny] = ar;
+                    }
+                std::swap(Lx, Ly);
+                env->Lx = Lx;
+                env->Ly = Ly;
+                env->cC = nC;
+                env->cT = nT;
+                a = na;
+            }
+        };
+        turn(dir);
+        try {
+            cell_left_move(env, a, chi, prec, S(stream));
+        } catch (...) {
+            turn((4 - dir) % 4);
+            throw;
+        }
+        turn((4 - dir) % 4);
+    });
+}
+
+int ctm_cell_site_partition(ctm_env_t env, int x, int y, symten_t a, int block, double* kappa, double* z,
+                            void* stream) {
+    return guard([&] {
+        if (!env || !kappa || env->Lx < 1) fail(SYMTEN_E_INVAL, "not a unit-cell environment");
+        if (x < 0 || y < 0 || x >= env->Lx || y >= env->Ly) fail(SYMTEN_E_INVAL, "bad site");
+        if (block != 1 && block != 2) fail(SYMTEN_E_INVAL, "block must be 1 or 2");
+        Tensor& at = T(a);
+        check_device_tensor(at, "ctm_cell_site_partition(a)");
+        ctm_env site;                     // a view of site (x, y)'s environment
+        for (int i = 0; i < 4; ++i) {
+            site.C[i] = env->cC[4 * (x * env->Ly + y) + i];
+            site.T[i] = env->cT[4 * (x * env->Ly + y) + i];
+        }
+        double zz[4];
+        *kappa = site_partition(&site, a->t, block, zz, S(stream));
+        if (z) std::copy(zz, zz + 4, z);
     });
 }
 

@@ -346,3 +346,52 @@ class CtmEnv:
         p, pt = C.c_void_p(), C.c_void_p()
         check(lib().ctm_move_projectors(self._h, C.byref(p), C.byref(pt)))
         return Tensor(p), Tensor(pt)
+
+
+class CtmCell:
+    """Environment of a unit cell of Lx x Ly sites: sites[x][y] = (Cs, Ts),
+    the four corners and four edges of site (x, y) (x to the right, y down)."""
+
+    def __init__(self, sites):
+        self.Lx, self.Ly = len(sites), len(sites[0])
+        cs = [c for col in sites for (Cs, _) in col for c in Cs]
+        ts = [t for col in sites for (_, Ts) in col for t in Ts]
+        n = 4 * self.Lx * self.Ly
+        self._h = C.c_void_p()
+        check(lib().ctm_cell_create(C.byref(self._h), self.Lx, self.Ly, (C.c_void_p * n)(*[c._h for c in cs]),
+                                    (C.c_void_p * n)(*[t._h for t in ts])))
+        self._keep = cs + ts
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().ctm_env_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def get(self, x, y, k):
+        """Tensor k (0..3: C1..C4, 4..7: T1..T4) of site (x, y)."""
+        h = C.c_void_p()
+        check(lib().ctm_cell_get(self._h, int(x), int(y), int(k), C.byref(h)))
+        return Tensor(h)
+
+    def move(self, a, chi, prec="f64", direction=0, stream=None):
+        """a[x][y]: the site tensors."""
+        flat = [t for col in a for t in col]
+        check(lib().ctm_cell_move(self._h, (C.c_void_p * len(flat))(*[t._h for t in flat]), int(direction), int(chi),
+                                  _prec(prec), _stream(stream)))
+
+    def site_partition(self, x, y, a, block=1, stream=None):
+        k = C.c_double()
+        z = (C.c_double * 4)()
+        check(lib().ctm_cell_site_partition(self._h, int(x), int(y), a._h, int(block), C.byref(k), z,
+                                            _stream(stream)))
+        return k.value, list(z)
+
+    def singular_values(self):
+        n = C.c_int64()
+        check(lib().ctm_move_singular_values(self._h, None, 0, C.byref(n)))
+        buf = (C.c_double * max(1, n.value))()
+        check(lib().ctm_move_singular_values(self._h, buf, n.value, C.byref(n)))
+        return np.array(buf[:n.value])
