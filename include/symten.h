@@ -293,7 +293,11 @@ int ctm_env_get(ctm_env_t env, int k, symten_t* t);
  * counterclockwise (C1' = C2, ..., T4' = T1, a'[l,u,r,d] = a[u,r,d,l], the
  * legs that land against the (in, in, out, out) convention reversed: a U(1)
  * relabelling, no data moves) and update C1, T1, C2 / C2, T2, C3 / C3, T3, C4.
- * SU(2) environments take CTM_LEFT only (SYMTEN_E_UNSUPPORTED otherwise).
+ * SU(2): the reversed legs of the turned network go through the S^z
+ * components (a reversed leg maps (j, m) to (j, -m) with the phase
+ * (-1)^(j-m), then the result is projected back onto reduced blocks); the
+ * half-integer spins of the T's D^2 legs, which four turns multiply by -1,
+ * are set back, so the environment stays that of the caller's a.
  * The left move:
  * four enlarged corners, halves H_u = C~1 C~2 and H_d = C~4 C~3, per fused
  * sector of the left cut the singular triplets of M = R_u R_d^T (QR

@@ -2159,8 +2159,41 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
                 fail(SYMTEN_E_SYM, "ctm_move: environment and site tensor have different symmetry groups");
         }
         if (a.group == SYMTEN_SU2) {
-            if (dir != CTM_LEFT) fail(SYMTEN_E_UNSUPPORTED, "ctm_move: SU(2) moves are left moves only");
-            move_su2(env, a, chi, prec, st, s);
+            if (dir == CTM_LEFT) {
+                move_su2(env, a, chi, prec, st, s);
+                return;
+            }
+            // the network turned as in the U(1) case; the reversed legs go
+            // through the S^z basis (su2_permute_flip).  Over four turns every
+            // T's D^2 leg is reversed twice, which multiplies its half-integer
+            // spins by -1: undone at the end so that the environment matches
+            // the caller's a again.
+            auto turn = [&](std::array<TensorPtr, 4>& C, std::array<TensorPtr, 4>& Tt, TensorPtr& ar) {
+                const std::array<TensorPtr, 4> Cn{C[1], C[2], C[3], C[0]};
+                const std::array<TensorPtr, 4> Tn{su2_permute_flip(*Tt[1], {0, 1, 2}, {1}, s), Tt[2],
+                                                  su2_permute_flip(*Tt[3], {0, 1, 2}, {1}, s), Tt[0]};
+                ar = su2_permute_flip(*ar, {1, 2, 3, 0}, {1, 3}, s);
+                C = Cn;
+                Tt = Tn;
+            };
+            std::array<TensorPtr, 4> C{env->C[0], env->C[1], env->C[2], env->C[3]};
+            std::array<TensorPtr, 4> Tt{env->T[0], env->T[1], env->T[2], env->T[3]};
+            const std::array<TensorPtr, 4> C0 = C, T0 = Tt;
+            TensorPtr ar = a_h->t;
+            for (int r = 0; r < dir; ++r) turn(C, Tt, ar);
+            for (int i = 0; i < 4; ++i) { env->C[i] = C[i]; env->T[i] = Tt[i]; }
+            try {
+                move_su2(env, *ar, chi, prec, st, s);
+            } catch (...) {
+                for (int i = 0; i < 4; ++i) { env->C[i] = C0[i]; env->T[i] = T0[i]; }
+                throw;
+            }
+            for (int i = 0; i < 4; ++i) { C[i] = env->C[i]; Tt[i] = env->T[i]; }
+            for (int r = dir; r < 4; ++r) turn(C, Tt, ar);
+            for (int i = 0; i < 4; ++i) {
+                env->C[i] = C[i];
+                env->T[i] = su2_sign_half_integer(*Tt[i], 1, s);
+            }
             return;
         }
         if (dir == CTM_LEFT) {

@@ -286,6 +286,15 @@ TensorPtr run_gather_plan(const GatherPlan& g, const Tensor& src, hipStream_t s)
 // (the inverse of su2_to_u1 on invariant tensors): projection of every block
 // onto its basis tensor.
 TensorPtr u1_to_su2(const Tensor& U, const std::vector<Leg>& legs, hipStream_t stream);
+// SU(2) tensor with its legs permuted (new leg j = old leg perm[j]) and the
+// legs `flip` (new positions) reversed, through the S^z components: a
+// reversed leg maps the state (j, m) to (j, -m) with the phase (-1)^(j-m).
+// Reversing both ends of a bond leaves a network unchanged; reversing a leg
+// twice multiplies its half-integer spins by -1.
+TensorPtr su2_permute_flip(const Tensor& X, const std::vector<int>& perm, const std::vector<int>& flip,
+                           hipStream_t s);
+// X with the blocks of half-integer spin on `leg` multiplied by -1.
+TensorPtr su2_sign_half_integer(const Tensor& X, int leg, hipStream_t s);
 
 // GEMM tile shapes and the autotuner that picks one per launch
 constexpr int kNumTileCfg = 5;

@@ -823,3 +823,124 @@ TensorPtr double_layer_su2(const Tensor& A, hipStream_t s) {
 }
 
 }  // namespace symten
+
+// ------------------------------------------- leg permutation and reversal
+namespace symten {
+TensorPtr su2_permute_flip(const Tensor& X, const std::vector<int>& perm, const std::vector<int>& flip,
+                           hipStream_t s) {
+    if (X.group != SYMTEN_SU2) fail(SYMTEN_E_INVAL, "su2_permute_flip: tensor is not SU(2)");
+    const int R = X.rank();
+    if ((int)perm.size() != R) fail(SYMTEN_E_INVAL, "su2_permute_flip: bad permutation");
+    TensorPtr U = su2_to_u1(X, s);
+    // the permuted SU(2) legs, the flipped ones reversed
+    std::vector<Leg> legs(R);
+    for (int j = 0; j < R; ++j) legs[j] = X.legs[perm[j]];
+    std::vector<char> fl(R, 0);
+    for (int l : flip) {
+        if (l < 0 || l >= R) fail(SYMTEN_E_INVAL, "su2_permute_flip: bad leg");
+        fl[l] = 1;
+    }
+    std::vector<SzLeg> szo(R);             // S^z legs before the reversal (after the permutation)
+    for (int j = 0; j < R; ++j) szo[j] = sz_leg(legs[j]);
+    for (int j = 0; j < R; ++j)
+        if (fl[j]) legs[j].dir = -legs[j].dir;
+    // target U(1) tensor: S^z legs of the new SU(2) legs, flux 0
+    auto V = std::make_shared<Tensor>();
+    V->group = SYMTEN_U1;
+    V->flux = 0;
+    V->dtype = U->dtype;
+    for (int j = 0; j < R; ++j) V->legs.push_back(sz_leg(legs[j]).u1);
+    V->elems = enumerate_blocks(*V);
+    V->meta_only = false;
+    V->buf = device_alloc(std::max<int64_t>(V->elems, 1) * V->esize());
+    launch_fill_zero(V->data(), ((std::max<int64_t>(V->elems, 1) * V->esize() + 3) / 4) * 4, s);
+    // a reversed leg takes the state (j, a, m) to (j, a, -m) with the phase
+    // (-1)^(j-m), which keeps the tensor invariant under the reversed law;
+    // the two ends of a bond take the same phase, so networks are unchanged.
+    // Inside a charge the states run over spins ascending, then multiplets,
+    // and charges m and -m hold the same spins at the same positions.
+    std::vector<CopyTask> tasks;
+    for (const Block& b0 : U->blocks) {
+        Block b = b0;                       // the block seen through the permutation
+        for (int j = 0; j < R; ++j) {
+            b.q[j] = b0.q[perm[j]];
+            b.shape[j] = b0.shape[perm[j]];
+            b.stride[j] = b0.stride[perm[j]];
+        }
+        std::vector<int> key = b.q;
+        for (int j = 0; j < R; ++j)
+            if (fl[j]) key[j] = -key[j];
+        const Block& d = V->blocks[V->index.at(key)];
+        // ranges of the reversed legs: one per spin present in the charge
+        struct Rg { int start, len, sign; };
+        std::vector<std::vector<Rg>> rg(R);
+        for (int j = 0; j < R; ++j) {
+            if (!fl[j]) { rg[j].push_back({0, b.shape[j], 1}); continue; }
+            const int m = b.q[j];
+            for (size_t i = 0; i < legs[j].q.size(); ++i) {
+                const int t = legs[j].q[i];
+                if (t < std::abs(m) || (t - m) % 2 != 0) continue;
+                const int sign = (((t - m) / 2) % 2 == 0) ? 1 : -1;
+                rg[j].push_back({szo[j].pos.at({t, m}), legs[j].d[i], sign});
+            }
+        }
+        std::vector<size_t> it(R, 0);
+        while (true) {
+            std::vector<int> dims(R);
+            int64_t so = b.offset, dof = d.offset;
+            int sign = 1;
+            for (int j = 0; j < R; ++j) {
+                const Rg& r = rg[j][it[j]];
+                dims[j] = r.len;
+                so += (int64_t)r.start * b.stride[j];
+                dof += (int64_t)r.start * d.stride[j];
+                sign *= r.sign;
+            }
+            std::vector<int64_t> ss(b.stride.begin(), b.stride.end()), ds(d.stride.begin(), d.stride.end());
+            tasks.push_back(make_copy_task(0, so, 1, dof, dims, ss, ds, (double)sign));
+            int j = R - 1;
+            while (j >= 0 && ++it[j] == rg[j].size()) it[j--] = 0;
+            if (j < 0) break;
+        }
+    }
+    if (!tasks.empty()) {
+        validate_tasks(tasks, {U->elems, V->elems});
+        std::vector<int64_t> prefix;
+        copy_prefix(tasks, prefix);
+        BufferPtr dt, dp;
+        upload_sync(dt, tasks.data(), tasks.size() * sizeof(CopyTask));
+        upload_sync(dp, prefix.data(), prefix.size() * sizeof(int64_t));
+        const bool f64 = U->dtype == SYMTEN_F64;
+        copy_launch_arg((const CopyTask*)dt->ptr, (const int64_t*)dp->ptr, (int)tasks.size(), prefix.back(),
+                        {U->data(), V->data()}, f64, f64 ? 1 : 0, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return u1_to_su2(*V, legs, s);
+}
+
+TensorPtr su2_sign_half_integer(const Tensor& X, int leg, hipStream_t s) {
+    if (X.group != SYMTEN_SU2) fail(SYMTEN_E_INVAL, "su2_sign_half_integer: tensor is not SU(2)");
+    auto out = std::make_shared<Tensor>(X);
+    out->meta_only = false;
+    out->buf = device_alloc(std::max<int64_t>(X.elems, 1) * X.esize());
+    std::vector<CopyTask> tasks;
+    for (size_t i = 0; i < X.blocks.size(); ++i) {
+        const Block& b = X.blocks[i];
+        std::vector<int64_t> st(b.stride.begin(), b.stride.end());
+        tasks.push_back(make_copy_task(0, b.offset, 1, b.offset, b.shape, st, st, (b.q[leg] % 2) ? -1.0 : 1.0));
+    }
+    if (!tasks.empty()) {
+        validate_tasks(tasks, {X.elems, X.elems});
+        std::vector<int64_t> prefix;
+        copy_prefix(tasks, prefix);
+        BufferPtr dt, dp;
+        upload_sync(dt, tasks.data(), tasks.size() * sizeof(CopyTask));
+        upload_sync(dp, prefix.data(), prefix.size() * sizeof(int64_t));
+        const bool f64 = X.dtype == SYMTEN_F64;
+        copy_launch_arg((const CopyTask*)dt->ptr, (const int64_t*)dp->ptr, (int)tasks.size(), prefix.back(),
+                        {X.data(), out->data()}, f64, f64 ? 1 : 0, s);
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return out;
+}
+}  // namespace symten

@@ -298,3 +298,48 @@ def test_cfg3_double_layer_legs_and_norm():
     Ad = su2.expand(L, vals).reshape(L[0].size, -1)
     G = Ad @ Ad.T
     assert np.isclose(n2, np.sum(G * G), rtol=1e-12)
+
+
+def test_su2_moves_in_every_direction_vs_oracle():
+    """SU(2) moves toward the top, right, bottom and then left again (the
+    turned network's reversed legs go through the S^z basis), each against
+    the whole-environment oracle's move on the CG-expanded tensors truncated
+    to the states the SU(2) move kept: spectrum, the closed networks Z_00 ..
+    Z_11 of the whole environment after every move, and the updated edge
+    after the first (later edges have open legs on bonds whose gauge the two
+    sides choose differently), FP64.  The sequence checks that the
+    environment stays consistent with the caller's site tensor (half-integer
+    spins on the D^2 legs)."""
+    from oracle import ctm, u1
+    legs = _env_legs(SMALL_MOVE["chi"], SMALL_MOVE["dd"])
+    vals = su2_values(legs, 1811)
+    env, dev = _su2_env(legs, vals, "f64")
+    D, _, _ = _expanded_u1(legs, vals)
+    C = [D[k] for k in ("C1", "C2", "C3", "C4")]
+    T = [D[k] for k in ("T1", "T2", "T3", "T4")]
+    first = True
+    for d in (1, 2, 3, 0):
+        print(f"su2 move direction {d}", flush=True)
+        stats = env.move(dev["a"], SMALL_MOVE["chi_target"], prec="f64", direction=d)
+        kept_states = sum((tj + 1) * k for tj, k in stats["kept"].items())
+        C, T, s = ctm.move(C, T, D["a"], kept_states, d)
+        assert len(s) == kept_states
+        got = _spectrum_states(env.singular_values(), stats)
+        assert np.max(np.abs(got[:len(s)] - s)) <= 1e-11 * s[0]
+        Cg = [_dense_u1(env.get(k)) for k in range(4)]
+        Tg = [_dense_u1(env.get(4 + k)) for k in range(4)]
+        # the closed networks of the whole environment (every bond summed, so
+        # the gauge of the new bonds drops out)
+        kg, zg = ctm.site_partition(Cg, Tg, D["a"])
+        ko, zo = ctm.site_partition(C, T, D["a"])
+        msg = f"  kept states {kept_states}, kappa {kg:.12f} / {ko:.12f}"
+        if first:
+            # after the first move the updated edge's open legs are old bonds
+            i, j = d, (d + 3) % 4
+            err = rel(u1.left_column(Cg[i], Tg[j], Cg[j]), u1.left_column(C[i], T[j], C[j]))
+            msg += f", updated edge rel err {err:.2e}"
+            assert err <= 1e-10
+        print(msg)
+        assert abs(kg - ko) <= 1e-10 * abs(ko)
+        assert np.allclose(zg, zo, rtol=1e-10)
+        first = False
