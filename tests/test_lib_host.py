@@ -190,3 +190,34 @@ def test_ctm_entry_points_reject_bad_arguments():
     assert L.ctm_run(None, None, None, None, None) == -1
     o, r = _lib.RunOpts(8, 8, 0, 3, 15, 1e-8), _lib.RunResult()
     assert L.ctm_run(None, None, C.byref(o), C.byref(r), None) == -1
+
+
+def test_cell_and_corner_entry_points_reject_bad_arguments():
+    """Argument checks of the unit-cell, single-layer corner and operator
+    double-layer entry points run before any device work."""
+    import ctypes as C
+    from paper_1808_10804_amd import _lib
+    L = _lib.lib()
+    h = C.c_void_p()
+    assert L.ctm_cell_create(None, 2, 2, None, None) == -1
+    assert L.ctm_cell_create(C.byref(h), 0, 2, None, None) == -1
+    assert L.ctm_cell_get(None, 0, 0, 0, C.byref(h)) == -1
+    assert L.ctm_cell_move(None, None, 0, 8, 0, None) == -1
+    k = C.c_double()
+    assert L.ctm_cell_site_partition(None, 0, 0, None, 1, C.byref(k), None, None) == -1
+    assert L.symten_enlarged_corner_single_layer(None, 1, None, None, None, None, 0, None, None) == -1
+    assert L.symten_double_layer_op(None, None, None, None) == -1
+    assert L.ctm_expectation(None, None, 1, 1, None, C.byref(k), None) == -1
+    assert L.ctm_heisenberg_bond_energy(None, None, C.byref(k), C.byref(k), None) == -1
+
+
+def test_z2_descriptors():
+    """Z2 labels are parities 0, 1 and the flux a parity; blocks obey the sum
+    rule mod 2 (the parity generating function: 2 x 2 legs of {0: 1, 1: 1}
+    give half of the 2^4 entries)."""
+    t = st.Tensor.meta([({0: 1, 1: 1}, 1)] * 2 + [({0: 1, 1: 1}, -1)] * 2, flux=1, group="z2")
+    assert t.nnz == 8 and all(sum(q) % 2 == 1 for q, _, _, _ in t.blocks())
+    with pytest.raises(st.SymtenError):
+        st.Tensor.meta([({0: 1, 2: 1}, 1)], flux=0, group="z2")
+    with pytest.raises(st.SymtenError):
+        st.Tensor.meta([({0: 1, 1: 1}, 1)], flux=2, group="z2")
