@@ -157,6 +157,23 @@ int symten_su2_cg(int tj1, int tm1, int tj2, int tm2, int tJ, int tM, double* va
 int symten_su2_to_u1(symten_t* out, symten_t in, void* stream);
 /* device buffer and its size in elements (>= nnz when blocks are strided). */
 int symten_device_ptr(symten_t t, void** ptr, int64_t* elems);
+/* Bytes of t's device buffer (elements times the storage size).           */
+int symten_nbytes(symten_t t, int64_t* bytes);
+
+/* Device memory from a caller's allocator (e.g. a framework's caching
+ * allocator): alloc(bytes, ctx) returns device memory of at least `bytes`
+ * (null: SYMTEN_E_NOMEM), free(ptr, bytes, ctx) releases it with the same
+ * byte count.  Buffers live until their last tensor or cached plan lets go,
+ * and are used on the streams passed to the library's calls, in stream
+ * order, so an allocator that tracks streams should serve those streams.
+ * Pass two nulls to return to the library's own caching pool.  A buffer is
+ * handed back only while the registration that made it is the current one;
+ * after any later call of this function it is kept until the process ends
+ * (so the caller can drop an allocator that is going away, e.g. at
+ * interpreter exit, by registering nulls first).  Errors: SYMTEN_E_INVAL
+ * when only one of alloc and free is null.  Not for calls in flight.       */
+int symten_set_allocator(void* (*alloc)(size_t bytes, void* ctx),
+                         void (*free_fn)(void* ptr, size_t bytes, void* ctx), void* ctx);
 
 /* Host FP64 values in canonical block order, row-major inside each block,
  * `n` = nnz.  Values are rounded to the storage type (round to nearest).

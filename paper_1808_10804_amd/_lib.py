@@ -14,6 +14,10 @@ PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 MAX_SECTORS = 64
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
 class SymtenError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -98,6 +102,8 @@ SIGNATURES = {
     "symten_su2_to_u1": (C.c_int, [C.POINTER(H), H, P]),
     "symten_su2_cg": (C.c_int, [C.c_int] * 6 + [C.POINTER(C.c_double)]),
     "symten_device_ptr": (C.c_int, [H, C.POINTER(P), I64P]),
+    "symten_nbytes": (C.c_int, [H, I64P]),
+    "symten_set_allocator": (C.c_int, [P, P, P]),
     "symten_upload": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64, P]),
     "symten_download": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64, P]),
     "symten_contract": (C.c_int, [C.POINTER(H), H, H, C.c_int, IP, IP, IP, C.c_int, P]),

@@ -565,8 +565,8 @@ struct ProjOut {
 // sectors are grouped into size classes and each class is solved in one
 // strided-batched call: a block (col-major m x n = H^T) is zero-padded to the
 // class size N, which leaves Y = diag(Y_A, 0) exact; the padding adds only
-// zero singular values.  The largest class runs on the caller's stream, the
-// others on the side streams.  FP64 moves use the Jordan-Wielandt matrix
+// zero singular values.  The classes go round robin over the caller's stream
+// and the side streams.  FP64 moves use the Jordan-Wielandt matrix
 // [[0, Y], [Y^T, 0]] (eigenpairs +-s, [u; +-v]/sqrt2, no squaring of the
 // condition number); the other precisions use Y Y^T (eigenvalues s^2), whose
 // extra rounding is far below their own error budget.
@@ -577,111 +577,132 @@ struct ProjOut {
 // (a multiplet is never split) and at values <= 1e-14 s_max.  P~ rows get
 // the sign gauge (largest-magnitude entry positive).  One host
 // synchronisation (the singular values).
-ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool f64, hipStream_t s) {
+
+// Work buffers of one cut's eigensolves, enqueued but not yet read back.
+struct ProjWork {
+    int ru = 0, rd = 0, ld = 0;
+    double *HuT = nullptr, *HdT = nullptr, *Y = nullptr;
+    int* info = nullptr;
+    BufferPtr U, V, S;
+};
+struct ProjPending {
+    std::vector<ProjWork> w;
+    std::vector<BufferPtr> keep_alive;
+    bool aux_used[ctm_env::kAux] = {};
+};
+
+// Enqueues the eigensolves of every sector of a cut (no host
+// synchronisation).  `start` is recorded on s by the caller once the halves
+// of every cut it issues are enqueued; *rr carries the stream round robin
+// from one cut to the next, so that the largest classes of several cuts land
+// on different streams and overlap.
+ProjPending issue_solves(ctm_env* env, std::vector<CutSector>& secs, bool f64, hipStream_t s, hipEvent_t start,
+                         int* rr) {
     if (secs.empty()) fail(SYMTEN_E_LINALG, "ctm_move: the halves have no common sector");
     rb_check(rocblas_set_stream(env->rb, s), "rocblas_set_stream");
-    struct Work {
-        int ru = 0, rd = 0, ld = 0;
-        double *HuT = nullptr, *HdT = nullptr, *Y = nullptr;
-        int* info = nullptr;
-        BufferPtr U, V, S;
-    };
-    std::vector<Work> w(secs.size());
+    ProjPending pend;
+    pend.w.resize(secs.size());
+    std::vector<int> order(secs.size());
+    std::iota(order.begin(), order.end(), 0);
+    for (size_t i = 0; i < secs.size(); ++i) {
+        pend.w[i].ru = secs[i].mu;                                // rows of U_Y
+        pend.w[i].rd = secs[i].md;                                // rows of V_Y
+        secs[i].mn = std::min(secs[i].n, std::min(secs[i].mu, secs[i].md));   // rank bound
+    }
+    auto dim = [&](int i) { return std::max(secs[i].n, std::max(secs[i].mu, secs[i].md)); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return dim(x) > dim(y); });
+    const double one = 1.0, zero = 0.0;
+    size_t pos = 0;
+    while (pos < order.size()) {
+        const int N = dim(order[pos]);
+        std::vector<int> cls;
+        while (pos < order.size() && (int)cls.size() < kMaxPadBatch / 2 && 2 * dim(order[pos]) >= N)
+            cls.push_back(order[pos++]);
+        const int B = (int)cls.size();
+        // classes go round robin over the caller's stream and the side
+        // streams, continuing where the previous cut of a batch stopped;
+        // side streams start after `start`
+        const int c = (*rr)++ % (ctm_env::kAux + 1);
+        hipStream_t cs = s;
+        rocblas_handle rh = env->rb;
+        if (c > 0) {
+            const int a = c - 1;
+            cs = env->aux[a];
+            rh = env->rb_aux[a];
+            if (!pend.aux_used[a]) HIPCHK(hipStreamWaitEvent(cs, start, 0));
+            pend.aux_used[a] = true;
+        }
+        const size_t N2 = (size_t)N * N;
+        // H^T blocks (u, d interleaved) -> padded FP64 matrices
+        BufferPtr Hb = device_alloc(8 * N2 * 2 * B);
+        PadArgs pa{};
+        pa.count = 2 * B;
+        pa.N = N;
+        pa.src_f64 = f64;
+        for (int i = 0; i < B; ++i) {
+            const CutSector& b = secs[cls[i]];
+            for (int side = 0; side < 2; ++side) {
+                pa.src[2 * i + side] = side == 0 ? b.hu : b.hd;
+                pa.rows[2 * i + side] = side == 0 ? b.mu : b.md;   // col-major m x n (ld m)
+                pa.cols[2 * i + side] = b.n;
+            }
+        }
+        launch_pad_blocks(pa, (double*)Hb->ptr, cs);
+        // Y = H_u^T H_d for every block of the class
+        BufferPtr Mb = device_alloc(8 * N2 * B);
+        rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N, N,
+                                               &one, (const double*)Hb->ptr, N, 2 * N2,
+                                               (const double*)Hb->ptr + N2, N, 2 * N2, &zero, (double*)Mb->ptr, N,
+                                               N2, B),
+                 "rocblas_dgemm_strided_batched(Y)");
+        const int NE = f64 ? 2 * N : N;
+        const size_t NE2 = (size_t)NE * NE;
+        BufferPtr Zb = device_alloc(8 * NE2 * B);
+        BufferPtr wb = device_alloc(8 * (size_t)NE * B);
+        BufferPtr Eb = device_alloc(8 * (size_t)NE * B);
+        BufferPtr ib = device_alloc(8 * (size_t)B);
+        if (f64)
+            launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, cs);
+        else
+            rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N,
+                                                   N, &one, (const double*)Mb->ptr, N, N2,
+                                                   (const double*)Mb->ptr, N, N2, &zero, (double*)Zb->ptr, N, N2,
+                                                   B),
+                     "rocblas_dgemm_strided_batched(YY^T)");
+        rb_check(rocsolver_dsyevd_strided_batched(rh, rocblas_evect_original, rocblas_fill_upper, NE,
+                                                  (double*)Zb->ptr, NE, NE2, (double*)wb->ptr, NE,
+                                                  (double*)Eb->ptr, NE, (rocblas_int*)ib->ptr, B),
+                 "rocsolver_dsyevd_strided_batched");
+        for (int i = 0; i < B; ++i) {
+            const CutSector& b = secs[cls[i]];
+            ProjWork& x = pend.w[cls[i]];
+            x.HuT = (double*)Hb->ptr + 2 * i * N2;          // H_u^T, col-major m x n
+            x.HdT = (double*)Hb->ptr + (2 * i + 1) * N2;    // H_d^T
+            x.Y = (double*)Mb->ptr + i * N2;
+            x.ld = N;
+            x.info = (int*)ib->ptr + i;
+            x.S = device_alloc(8 * std::max(1, b.mn));
+            x.U = device_alloc(8 * std::max<size_t>(1, (size_t)x.ru * b.mn));
+            x.V = device_alloc(8 * std::max<size_t>(1, (size_t)x.rd * b.mn));
+            launch_eig_to_svd((const double*)Zb->ptr + i * NE2, NE, (const double*)wb->ptr + (size_t)i * NE, N,
+                              b.mn, x.ru, x.rd, f64, (double*)x.S->ptr, (double*)x.U->ptr, (double*)x.V->ptr, cs);
+        }
+        for (auto& x : {Hb, Mb, Zb, wb, Eb, ib}) pend.keep_alive.push_back(x);
+    }
+    return pend;
+}
+
+// Joins the side streams, reads the singular values back (the one host
+// synchronisation), truncates and forms P and P~ on s.
+ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPending& pend, int chi, bool f64,
+                          hipStream_t s) {
+    rb_check(rocblas_set_stream(env->rb, s), "rocblas_set_stream");
+    std::vector<ProjWork>& w = pend.w;
     ProjOut out;
     std::vector<int> sv_off;
-    std::vector<BufferPtr> keep_alive;
     {
-        std::vector<int> order(secs.size());
-        std::iota(order.begin(), order.end(), 0);
-        for (size_t i = 0; i < secs.size(); ++i) {
-            w[i].ru = secs[i].mu;                                // rows of U_Y
-            w[i].rd = secs[i].md;                                // rows of V_Y
-            secs[i].mn = std::min(secs[i].n, std::min(secs[i].mu, secs[i].md));   // rank bound
-        }
-        auto dim = [&](int i) { return std::max(secs[i].n, std::max(secs[i].mu, secs[i].md)); };
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return dim(x) > dim(y); });
-        const double one = 1.0, zero = 0.0;
-        size_t pos = 0;
-        int ncls = 0;
-        bool aux_used[ctm_env::kAux] = {};
-        HIPCHK(hipEventRecord(env->ev_start, s));
-        while (pos < order.size()) {
-            const int N = dim(order[pos]);
-            std::vector<int> cls;
-            while (pos < order.size() && (int)cls.size() < kMaxPadBatch / 2 && 2 * dim(order[pos]) >= N)
-                cls.push_back(order[pos++]);
-            const int B = (int)cls.size();
-            // the largest class runs on the caller's stream, the others on the
-            // side streams (round robin), all after the halves
-            const int c = ncls++;
-            hipStream_t cs = s;
-            rocblas_handle rh = env->rb;
-            if (c > 0) {
-                const int a = (c - 1) % ctm_env::kAux;
-                cs = env->aux[a];
-                rh = env->rb_aux[a];
-                if (!aux_used[a]) HIPCHK(hipStreamWaitEvent(cs, env->ev_start, 0));
-                aux_used[a] = true;
-            }
-            const size_t N2 = (size_t)N * N;
-            // H^T blocks (u, d interleaved) -> padded FP64 matrices
-            BufferPtr Hb = device_alloc(8 * N2 * 2 * B);
-            PadArgs pa{};
-            pa.count = 2 * B;
-            pa.N = N;
-            pa.src_f64 = f64;
-            for (int i = 0; i < B; ++i) {
-                const CutSector& b = secs[cls[i]];
-                for (int side = 0; side < 2; ++side) {
-                    pa.src[2 * i + side] = side == 0 ? b.hu : b.hd;
-                    pa.rows[2 * i + side] = side == 0 ? b.mu : b.md;   // col-major m x n (ld m)
-                    pa.cols[2 * i + side] = b.n;
-                }
-            }
-            launch_pad_blocks(pa, (double*)Hb->ptr, cs);
-            // Y = H_u^T H_d for every block of the class
-            BufferPtr Mb = device_alloc(8 * N2 * B);
-            rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N, N,
-                                                   &one, (const double*)Hb->ptr, N, 2 * N2,
-                                                   (const double*)Hb->ptr + N2, N, 2 * N2, &zero, (double*)Mb->ptr, N,
-                                                   N2, B),
-                     "rocblas_dgemm_strided_batched(Y)");
-            const int NE = f64 ? 2 * N : N;
-            const size_t NE2 = (size_t)NE * NE;
-            BufferPtr Zb = device_alloc(8 * NE2 * B);
-            BufferPtr wb = device_alloc(8 * (size_t)NE * B);
-            BufferPtr Eb = device_alloc(8 * (size_t)NE * B);
-            BufferPtr ib = device_alloc(8 * (size_t)B);
-            if (f64)
-                launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, cs);
-            else
-                rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N,
-                                                       N, &one, (const double*)Mb->ptr, N, N2,
-                                                       (const double*)Mb->ptr, N, N2, &zero, (double*)Zb->ptr, N, N2,
-                                                       B),
-                         "rocblas_dgemm_strided_batched(YY^T)");
-            rb_check(rocsolver_dsyevd_strided_batched(rh, rocblas_evect_original, rocblas_fill_upper, NE,
-                                                      (double*)Zb->ptr, NE, NE2, (double*)wb->ptr, NE,
-                                                      (double*)Eb->ptr, NE, (rocblas_int*)ib->ptr, B),
-                     "rocsolver_dsyevd_strided_batched");
-            for (int i = 0; i < B; ++i) {
-                const CutSector& b = secs[cls[i]];
-                Work& x = w[cls[i]];
-                x.HuT = (double*)Hb->ptr + 2 * i * N2;          // H_u^T, col-major m x n
-                x.HdT = (double*)Hb->ptr + (2 * i + 1) * N2;    // H_d^T
-                x.Y = (double*)Mb->ptr + i * N2;
-                x.ld = N;
-                x.info = (int*)ib->ptr + i;
-                x.S = device_alloc(8 * std::max(1, b.mn));
-                x.U = device_alloc(8 * std::max<size_t>(1, (size_t)x.ru * b.mn));
-                x.V = device_alloc(8 * std::max<size_t>(1, (size_t)x.rd * b.mn));
-                launch_eig_to_svd((const double*)Zb->ptr + i * NE2, NE, (const double*)wb->ptr + (size_t)i * NE, N,
-                                  b.mn, x.ru, x.rd, f64, (double*)x.S->ptr, (double*)x.U->ptr, (double*)x.V->ptr, cs);
-            }
-            for (auto& x : {Hb, Mb, Zb, wb, Eb, ib}) keep_alive.push_back(x);
-        }
         for (int a = 0; a < ctm_env::kAux; ++a)
-            if (aux_used[a]) {
+            if (pend.aux_used[a]) {
                 HIPCHK(hipEventRecord(env->ev_done[a], env->aux[a]));
                 HIPCHK(hipStreamWaitEvent(s, env->ev_done[a], 0));
             }
@@ -692,8 +713,8 @@ ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool
         std::vector<int> infos(secs.size());
         for (size_t i = 0; i < secs.size(); ++i) {
             if (secs[i].mn)
-                HIPCHK(hipMemcpyAsync(out.sv.data() + sv_off[i], w[i].S->ptr, 8 * secs[i].mn, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(&infos[i], w[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(out.sv.data() + sv_off[i], pend.w[i].S->ptr, 8 * secs[i].mn, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&infos[i], pend.w[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
         }
         HIPCHK(hipStreamSynchronize(s));
         for (size_t i = 0; i < secs.size(); ++i)
@@ -743,7 +764,7 @@ ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool
     const double one = 1.0, zero = 0.0;
     for (size_t i = 0; i < secs.size(); ++i) {
         const CutSector& c = secs[i];
-        Work& x = w[i];
+        ProjWork& x = w[i];
         out.flops += 2LL * x.ru * x.rd * c.n;
         if (c.k == 0) continue;
         const int n = c.n, k = c.k;
@@ -772,6 +793,13 @@ ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool
     // the work buffers go back to the pool here; later launches that reuse
     // them are ordered after these on the same stream
     return out;
+}
+
+ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool f64, hipStream_t s) {
+    HIPCHK(hipEventRecord(env->ev_start, s));
+    int rr = 0;
+    ProjPending pend = issue_solves(env, secs, f64, s, env->ev_start, &rr);
+    return finish_projectors(env, secs, pend, chi, f64, s);
 }
 
 void fill_cut_stats(ctm_move_stats* st, const std::vector<CutSector>& secs, const ProjOut& po) {
@@ -1278,11 +1306,23 @@ struct CutResult {
     std::vector<CutSector> secs;
     std::vector<Contracted> halves;
 };
-CutResult cut_from_corners(ctm_env* env, const CornerResult& k1, const CornerResult& k2, const CornerResult& k3,
-                           const CornerResult& k4, const Leg& chiL, const Leg& dL, int group, int chi, int prec,
-                           Timer* tm, hipStream_t s) {
-    const bool f64 = prec == SYMTEN_PREC_F64;
+// A cut up to its eigensolves: the halves and the sector matrices H_u^T,
+// H_d^T over the union of their row blocks.
+struct CutPrep {
     CutResult cr;
+    std::vector<CutSector> secs;
+    std::map<int, std::vector<std::vector<int>>> rows_of;      // Q -> union rows
+    std::map<int, std::map<std::vector<int>, int>> row_off_of;
+    std::vector<BufferPtr> row_bufs;                           // read by the solves
+    Leg chiL, dL;
+    int group = 0;
+    bool f64 = false;
+};
+CutPrep cut_prepare(const CornerResult& k1, const CornerResult& k2, const CornerResult& k3, const CornerResult& k4,
+                    const Leg& chiL, const Leg& dL, int group, int prec, Timer* tm, hipStream_t s) {
+    const bool f64 = prec == SYMTEN_PREC_F64;
+    CutPrep cp;
+    CutResult& cr = cp.cr;
     // halves: H_u = C~1 C~2 -> [x4, d, x2, d2]; H_d = C~4 C~3 -> [x4, u, x2, u3]
     cr.halves = contract_batched({{k1.corner.get(), k2.corner.get(), {0, 2}, {0, 2}, {}},
                                   {k4.corner.get(), k3.corner.get(), {0, 3}, {0, 2}, {}}},
@@ -1374,7 +1414,26 @@ CutResult cut_from_corners(ctm_env* env, const CornerResult& k1, const CornerRes
         for (auto& pd : pending)
             (pd.side == 0 ? secs[pd.sec].hu : secs[pd.sec].hd) = (const char*)ub[pd.side]->ptr + pd.off * es;
     }
-    ProjOut po = cut_projectors(env, secs, chi, f64, s);
+    cp.secs = std::move(secs);
+    cp.rows_of = std::move(rows_of);
+    cp.row_off_of = std::move(row_off_of);
+    cp.row_bufs = std::move(row_bufs);
+    cp.chiL = chiL;
+    cp.dL = dL;
+    cp.group = group;
+    cp.f64 = f64;
+    return cp;
+}
+
+// The projector tensors of a prepared cut whose eigensolves are finished.
+CutResult cut_complete(CutPrep& cp, const ProjOut& po, hipStream_t s) {
+    CutResult& cr = cp.cr;
+    std::vector<CutSector>& secs = cp.secs;
+    auto& rows_of = cp.rows_of;
+    auto& row_off_of = cp.row_off_of;
+    const Leg &chiL = cp.chiL, &dL = cp.dL;
+    const int group = cp.group;
+    const bool f64 = cp.f64;
     // ---- projector tensors P[chi out, D in, k in], P~[k out, chi in, D out]
     auto P = std::make_shared<Tensor>();
     auto Pt = std::make_shared<Tensor>();
@@ -1447,6 +1506,14 @@ CutResult cut_from_corners(ctm_env* env, const CornerResult& k1, const CornerRes
     cr.po = po;
     cr.secs = secs;
     return cr;
+}
+
+CutResult cut_from_corners(ctm_env* env, const CornerResult& k1, const CornerResult& k2, const CornerResult& k3,
+                           const CornerResult& k4, const Leg& chiL, const Leg& dL, int group, int chi, int prec,
+                           Timer* tm, hipStream_t s) {
+    CutPrep cp = cut_prepare(k1, k2, k3, k4, chiL, dL, group, prec, tm, s);
+    ProjOut po = cut_projectors(env, cp.secs, chi, cp.f64, s);
+    return cut_complete(cp, po, s);
 }
 
 // C1' = (C1 T1) P_above, T4' = P~_above (T4 a) P_below, C4' = (C4 T3) P~_below^T,
@@ -1538,6 +1605,7 @@ void cell_left_move(ctm_env* env, const std::vector<TensorPtr>& a, int chi, int 
     for (int x = 0; x < Lx; ++x) {
         const int x1 = x + 1;
         std::vector<CutResult> cuts(Ly);
+        std::vector<CutPrep> preps(Ly);
         std::vector<TensorPtr> c1t1(Ly), c4t3(Ly);
         for (int y = 0; y < Ly; ++y) {
             const int y1 = y + 1;
@@ -1547,10 +1615,21 @@ void cell_left_move(ctm_env* env, const std::vector<TensorPtr>& a, int chi, int 
                 {{&C(x, y, 0), &T(x, y, 0), &T(x, y, 3)}, {&C(x1, y, 1), &T(x1, y, 0), &T(x1, y, 1)},
                  {&C(x1, y1, 2), &T(x1, y1, 2), &T(x1, y1, 1)}, {&C(x, y1, 3), &T(x, y1, 2), &T(x, y1, 3)}},
                 A(x, y), prec, s, &as);
-            cuts[y] = cut_from_corners(env, ks[0], ks[1], ks[2], ks[3], T(x, y, 3).legs[0], A(x, y).legs[3],
-                                       A(x, y).group, chi, prec, nullptr, s);
+            preps[y] = cut_prepare(ks[0], ks[1], ks[2], ks[3], T(x, y, 3).legs[0], A(x, y).legs[3], A(x, y).group,
+                                   prec, nullptr, s);
             c1t1[y] = ks[0].step1;             // C1 T1 of site (x, y)
             c4t3[y1 % Ly] = ks[3].step1;       // C4 T3 of site (x, y+1)
+        }
+        // the cuts of a column are independent: their eigensolves are all
+        // enqueued before the first read-back, spread over the streams
+        HIPCHK(hipEventRecord(env->ev_start, s));
+        int rr = 0;
+        std::vector<ProjPending> pend;
+        for (int y = 0; y < Ly; ++y)
+            pend.push_back(issue_solves(env, preps[y].secs, preps[y].f64, s, env->ev_start, &rr));
+        for (int y = 0; y < Ly; ++y) {
+            ProjOut po = finish_projectors(env, preps[y].secs, pend[y], chi, preps[y].f64, s);
+            cuts[y] = cut_complete(preps[y], po, s);
             // the kept values of the cut, descending
             std::vector<double> sv = cuts[y].po.sv;
             std::sort(sv.begin(), sv.end(), std::greater<double>());
@@ -1675,6 +1754,21 @@ int symten_su2_cg(int tj1, int tm1, int tj2, int tm2, int tJ, int tM, double* va
         *value = cg_coeff(tj1, tm1, tj2, tm2, tJ, tM);
     });
 }
+int symten_set_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, size_t, void*), void* ctx) {
+    return guard([&] {
+        if ((alloc == nullptr) != (free_fn == nullptr)) fail(SYMTEN_E_INVAL, "allocator and free come as a pair");
+        set_user_allocator(alloc, free_fn, ctx);
+    });
+}
+
+int symten_nbytes(symten_t t, int64_t* bytes) {
+    return guard([&] {
+        if (!bytes) fail(SYMTEN_E_INVAL, "null output");
+        Tensor& x = T(t);
+        *bytes = x.elems * (int64_t)x.esize();
+    });
+}
+
 int symten_device_ptr(symten_t t, void** ptr, int64_t* elems) {
     return guard([&] {
         Tensor& x = T(t);

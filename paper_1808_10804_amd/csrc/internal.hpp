@@ -58,8 +58,14 @@ struct DeviceBuffer {
     void* ptr = nullptr;
     size_t bytes = 0;
     size_t cap = 0;
+    // set when a caller-registered allocator made the buffer
+    void (*user_free)(void* ptr, size_t bytes, void* ctx) = nullptr;
+    void* user_ctx = nullptr;
+    uint64_t user_gen = 0;  // registration that made it; a later one leaks it
     ~DeviceBuffer();
 };
+// Caller-registered device allocator (null fns: the library's own pool).
+void set_user_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, size_t, void*), void* ctx);
 
 struct Tensor {
     int group = SYMTEN_U1;

@@ -71,11 +71,47 @@ size_t round_cap(size_t b) {
 }
 }  // namespace
 
+namespace {
+struct UserAllocator {
+    std::mutex mu;
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*free_fn)(void*, size_t, void*) = nullptr;
+    void* ctx = nullptr;
+    uint64_t gen = 0;  // bumped by every registration
+};
+UserAllocator& user_allocator() {
+    static UserAllocator* u = new UserAllocator();
+    return *u;
+}
+}  // namespace
+
+void set_user_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, size_t, void*), void* ctx) {
+    UserAllocator& u = user_allocator();
+    std::lock_guard<std::mutex> lk(u.mu);
+    u.alloc = alloc;
+    u.free_fn = free_fn;
+    u.ctx = ctx;
+    ++u.gen;
+}
+
 BufferPtr device_alloc(size_t bytes) {
     auto b = std::make_shared<DeviceBuffer>();
     b->bytes = bytes;
     if (bytes == 0) return b;
     const size_t cap = round_cap(bytes);
+    {
+        UserAllocator& u = user_allocator();
+        std::lock_guard<std::mutex> lk(u.mu);
+        if (u.alloc) {
+            b->ptr = u.alloc(cap, u.ctx);
+            if (!b->ptr) fail(SYMTEN_E_NOMEM, "registered allocator returned null for " + std::to_string(cap) + " bytes");
+            b->cap = cap;
+            b->user_free = u.free_fn;
+            b->user_ctx = u.ctx;
+            b->user_gen = u.gen;
+            return b;
+        }
+    }
     {
         Pool& P = pool();
         std::lock_guard<std::mutex> lk(P.mu);
@@ -114,6 +150,16 @@ BufferPtr device_alloc(size_t bytes) {
 
 DeviceBuffer::~DeviceBuffer() {
     if (!ptr) return;
+    if (user_free) {
+        // A buffer outliving its allocator's registration is not handed back:
+        // the caller may have torn that allocator down (interpreter exit).
+        UserAllocator& u = user_allocator();
+        std::unique_lock<std::mutex> lk(u.mu);
+        const bool current = u.gen == user_gen;
+        lk.unlock();
+        if (current) user_free(ptr, cap, user_ctx);
+        return;
+    }
     Pool& P = pool();
     std::lock_guard<std::mutex> lk(P.mu);
     P.free_.emplace(cap, ptr);

@@ -159,6 +159,12 @@ class Tensor:
         check(lib().symten_device_ptr(self._h, C.byref(p), C.byref(n)))
         return p.value, n.value
 
+    @property
+    def nbytes(self):
+        n = C.c_int64()
+        check(lib().symten_nbytes(self._h, C.byref(n)))
+        return n.value
+
     # ---- data -------------------------------------------------------------
     def upload(self, values, stream=None):
         v = np.ascontiguousarray(values, dtype=np.float64)
@@ -179,6 +185,48 @@ class Tensor:
             out[lab] = vals[pos:pos + n].reshape(shp)
             pos += n
         return out
+
+
+# Callback objects handed to the library stay referenced for the life of the
+# process: a buffer may outlive the registration that made it.
+_ALLOC_KEEP = []
+_ALLOC_ATEXIT = []
+
+
+def set_allocator(alloc, free):
+    """Device memory from alloc(nbytes) -> int address, released by free(address, nbytes).
+
+    Both None: back to the library's own caching pool.  Buffers made under an
+    earlier registration are kept, not freed, once another one is made.
+    """
+    if alloc is None and free is None:
+        check(lib().symten_set_allocator(None, None, None))
+        return
+    if alloc is None or free is None:
+        raise ValueError("alloc and free come as a pair")
+    a = _lib.ALLOC_FN(lambda n, ctx: alloc(n) or None)
+    f = _lib.FREE_FN(lambda ptr, n, ctx: free(ptr, n))
+    _ALLOC_KEEP.append((a, f))
+    check(lib().symten_set_allocator(C.cast(a, C.c_void_p), C.cast(f, C.c_void_p), None))
+    if not _ALLOC_ATEXIT:
+        # Before the interpreter (and torch) shut down, stop handing buffers
+        # back to Python callables.
+        import atexit
+        atexit.register(lambda: lib().symten_set_allocator(None, None, None))
+        _ALLOC_ATEXIT.append(True)
+
+
+def use_torch_allocator(device=None, stream=None):
+    """Route libsymten's device memory through torch's caching allocator.
+
+    Blocks are tied to `stream` (default: torch's current stream now), so the
+    library's calls should be issued on that stream.
+    """
+    import torch
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev, st),
+                  lambda ptr, n: torch.cuda.caching_allocator_delete(ptr))
 
 
 def su2_cg(tj1, tm1, tj2, tm2, tJ, tM):

@@ -221,3 +221,18 @@ def test_z2_descriptors():
         st.Tensor.meta([({0: 1, 2: 1}, 1)], flux=0, group="z2")
     with pytest.raises(st.SymtenError):
         st.Tensor.meta([({0: 1, 1: 1}, 1)], flux=2, group="z2")
+
+
+def test_allocator_registration():
+    """The allocator pair: both or neither; nulls return to the library pool."""
+    L = _lib.lib()
+    a = _lib.ALLOC_FN(lambda n, ctx: None)
+    f = _lib.FREE_FN(lambda p, n, ctx: None)
+    assert L.symten_set_allocator(C.cast(a, C.c_void_p), None, None) == _lib.OK - 1
+    assert L.symten_set_allocator(C.cast(a, C.c_void_p), C.cast(f, C.c_void_p), None) == _lib.OK
+    assert L.symten_set_allocator(None, None, None) == _lib.OK
+
+
+def test_nbytes_of_metadata_tensor():
+    t = st.Tensor.meta([({0: 3, 1: 5}, 1), ({0: 3, 1: 5}, -1)], flux=0, dtype="f64")
+    assert t.nbytes == t.nnz * 8 == 34 * 8
