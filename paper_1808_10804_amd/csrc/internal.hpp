@@ -303,15 +303,16 @@ TensorPtr su2_permute_flip(const Tensor& X, const std::vector<int>& perm, const 
 TensorPtr su2_sign_half_integer(const Tensor& X, int leg, hipStream_t s);
 
 // GEMM tile shapes and the autotuner that picks one per launch
-constexpr int kNumTileCfg = 5;
+constexpr int kNumTileCfg = 8;
 int gemm_tile_bm(Prec p, int cfg);
 int gemm_tile_bn(Prec p, int cfg);
+int gemm_tile_bk(Prec p, int cfg);
 bool gemm_tile_ok(Prec p, int cfg);
 struct TileChoice {
     int cfg = -1;                          // chosen configuration (-1: not tuned)
     BufferPtr tiles[kNumTileCfg];          // device tile lists per configuration
-    int ntiles[kNumTileCfg] = {0, 0, 0, 0, 0};
-    float ms[kNumTileCfg] = {0, 0, 0, 0, 0};
+    int ntiles[kNumTileCfg] = {};
+    float ms[kNumTileCfg] = {};
 };
 // Picks the tile configuration for this set of GEMM groups: a cached
 // decision for the same shapes, else each available configuration is timed

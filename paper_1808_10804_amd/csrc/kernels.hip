@@ -827,11 +827,15 @@ void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntask
 }
 
 // Tile shapes (BM x BN): 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128,
-// 4 = 256x128 (FP32/BF16 kernels only).
-static const int kTileBM[kNumTileCfg] = {64, 128, 128, 64, 256};
-static const int kTileBN[kNumTileCfg] = {64, 128, 64, 128, 128};
+// 4 = 256x128 (FP32/BF16 kernels only), and with twice the K depth per
+// stage (more MFMA work between a stage's loads and their use, for launches
+// of few tiles per CU): 5 = 64x64, 6 = 128x64, 7 = 64x128.  K depth: FP64
+// 16 (32 for 5-7), FP32/BF16 32 (64 for 5-7).
+static const int kTileBM[kNumTileCfg] = {64, 128, 128, 64, 256, 64, 128, 64};
+static const int kTileBN[kNumTileCfg] = {64, 128, 64, 128, 128, 64, 64, 128};
 int gemm_tile_bm(Prec p, int cfg) { (void)p; return kTileBM[cfg]; }
 int gemm_tile_bn(Prec p, int cfg) { (void)p; return kTileBN[cfg]; }
+int gemm_tile_bk(Prec p, int cfg) { return (p == Prec::F64 ? 16 : 32) * (cfg >= 5 ? 2 : 1); }
 bool gemm_tile_ok(Prec p, int cfg) { return cfg >= 0 && cfg < kNumTileCfg && !(p == Prec::F64 && cfg == 4); }
 
 template <class Ptrs>
@@ -842,7 +846,10 @@ static void launch_f32_family(int cfg, dim3 grid, hipStream_t s, const TileWork*
         case 1: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
         case 2: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 32>, 1>), grid, block, 0, s, t, g, P); break;
         case 3: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
-        default: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<256, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
+        case 4: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<256, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
+        case 5: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 64>, 1>), grid, block, 0, s, t, g, P); break;
+        case 6: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 64>, 1>), grid, block, 0, s, t, g, P); break;
+        default: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 64>, 1>), grid, block, 0, s, t, g, P); break;
     }
 }
 
@@ -854,7 +861,10 @@ static void launch_bf16_family(int cfg, dim3 grid, hipStream_t s, const TileWork
         case 1: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
         case 2: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 64, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
         case 3: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
-        default: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<256, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
+        case 4: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<256, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
+        case 5: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 64, 64>, SPLIT>), grid, block, 0, s, t, g, P); break;
+        case 6: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 64, 64>, SPLIT>), grid, block, 0, s, t, g, P); break;
+        default: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 128, 64>, SPLIT>), grid, block, 0, s, t, g, P); break;
     }
 }
 
@@ -869,7 +879,10 @@ static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* 
                 case 0: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 64, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
                 case 1: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
                 case 2: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 64, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
-                default: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
+                case 3: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
+                case 5: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 64, 32>>), grid, block, 0, s, d_tiles, d_groups, P); break;
+                case 6: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 64, 32>>), grid, block, 0, s, d_tiles, d_groups, P); break;
+                default: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 128, 32>>), grid, block, 0, s, d_tiles, d_groups, P); break;
             }
             break;
         case Prec::F32: launch_f32_family<Ptrs>(cfg, grid, s, d_tiles, d_groups, P); break;

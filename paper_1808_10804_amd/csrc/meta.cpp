@@ -695,12 +695,13 @@ std::vector<symten_kernel_stat> profile_end() {
 }
 
 std::string gemm_kernel_name(Prec p, int cfg) {
-    const std::string t = std::to_string(gemm_tile_bm(p, cfg)) + "x" + std::to_string(gemm_tile_bn(p, cfg));
+    const std::string t = std::to_string(gemm_tile_bm(p, cfg)) + "x" + std::to_string(gemm_tile_bn(p, cfg)) + "x" +
+                          std::to_string(gemm_tile_bk(p, cfg));
     switch (p) {
-        case Prec::F64: return "gemm_f64_kernel<" + t + "x16>";
-        case Prec::F32: return "gemm_f32_kernel<" + t + "x32,f32>";
-        case Prec::BF16: return "gemm_bf16_kernel<" + t + "x32,bf16>";
-        default: return "gemm_bf16_kernel<" + t + "x32,bf16x3>";
+        case Prec::F64: return "gemm_f64_kernel<" + t + ">";
+        case Prec::F32: return "gemm_f32_kernel<" + t + ",f32>";
+        case Prec::BF16: return "gemm_bf16_kernel<" + t + ",bf16>";
+        default: return "gemm_bf16_kernel<" + t + ",bf16x3>";
     }
 }
 

@@ -38,6 +38,48 @@ def test_single_sector_gemm(prec, mnk):
     assert rel(got, ref) <= TOL[prec], rel(got, ref)
 
 
+TILES = {0: (64, 64, 1), 1: (128, 128, 1), 2: (128, 64, 1), 3: (64, 128, 1), 4: (256, 128, 1),
+         5: (64, 64, 2), 6: (128, 64, 2), 7: (64, 128, 2)}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("cfg", sorted(TILES))
+def test_every_tile_configuration(prec, cfg, monkeypatch):
+    """Each tile shape forced in turn (the autotuner would pick only one per
+    shape): a three-sector product with ragged M, N and K tails in every
+    sector, shapes unique per case so that each gets a fresh plan, against
+    numpy in FP64; the launched kernel is the forced shape."""
+    if prec == "f64" and cfg == 4:
+        pytest.skip("256x128 is not built for FP64")
+    monkeypatch.setenv("SYMTEN_TILE_CFG", str(cfg))
+    dt = "f64" if prec == "f64" else "f32"
+    bump = cfg + 8 * ["f64", "f32", "bf16x3", "bf16"].index(prec)
+    m = {0: 70 + bump, 1: 131 + bump, 2: 9}
+    k = {0: 97 + 3 * bump, 1: 40 + bump, 2: 150}
+    n = {0: 66 + 2 * bump, 1: 129, 2: 31 + bump}
+    rng = np.random.default_rng(1000 + bump)
+    A = st.Tensor.create([(m, 1), (k, -1)], 0, dt)
+    B = st.Tensor.create([(k, 1), (n, -1)], 0, dt)
+    a = {q: rng.standard_normal(sh) for q, sh, _, _ in A.blocks()}
+    b = {q: rng.standard_normal(sh) for q, sh, _, _ in B.blocks()}
+    A.upload(np.concatenate([a[q].ravel() for q, _, _, _ in A.blocks()]))
+    B.upload(np.concatenate([b[q].ravel() for q, _, _, _ in B.blocks()]))
+    st.profile_begin()
+    Cc = st.contract(A, B, [1], [0], prec=prec)
+    st.sync()
+    names = [r["name"] for r in st.profile_end() if r["name"].startswith("gemm")]
+    bm, bn, kx = TILES[cfg]
+    bk = (16 if prec == "f64" else 32) * kx
+    assert any(f"<{bm}x{bn}x{bk}" in nm for nm in names), names
+    got = Cc.block_dict()
+    for q in range(3):
+        x, y = a[(q, q)], b[(q, q)]
+        if dt == "f32":
+            x, y = x.astype(np.float32).astype(np.float64), y.astype(np.float32).astype(np.float64)
+        err = rel(got[(q, q)], x @ y)
+        assert err <= TOL[prec], (q, err)
+
+
 def test_zero_pair_contraction_on_device():
     A = st.Tensor.create([({0: 2}, 1), ({2: 3}, -1)], -2, "f32")
     B = st.Tensor.create([({2: 3}, 1), ({4: 1}, -1)], 0, "f32")
