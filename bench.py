@@ -449,6 +449,61 @@ def bench_cell(args):
     print(json.dumps(out))
 
 
+def bench_unit(args):
+    """The CTM part of the paper's timed optimisation unit (Sec. 4): a 2 x 2
+    unit cell re-converged with 8 steps, each one move toward every side
+    (left, top, right, bottom), at bond dimension 3 and chi = 10 (3 + 1) = 40
+    in FP64 -- the geometry of the paper's U(1) timing at d = 3 -- with
+    seeded Gaussian site tensors
+    (four draws) and environments in place of an optimised state.  A timed
+    step is one whole re-initialisation (32 cell moves) from a fresh cell."""
+    import torch
+    import paper_1808_10804_amd as st
+    from synth import config, draw, TENSOR_INDEX, binomial_sectors
+    cfgd = config(1)
+    prec = args.prec or "f64"
+    cfgd.update(name="u1_ctm_unit_D3_chi40_" + prec, virt={-2: 1, 0: 1, 2: 1}, chi=binomial_sectors(40, 5),
+                chi_target=40)
+    dtype = "f64" if prec == "f64" else "f32"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    env_names = ("C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4")
+    sites = [[build_workload(cfgd, cfgd["seed"] + 100 * (2 * x + y), dtype, st, draw, TENSOR_INDEX) for y in range(2)]
+             for x in range(2)]
+    a = [[s["a"] for s in col] for col in sites]
+
+    def fresh():
+        return st.CtmCell([[([s[k] for k in env_names[:4]], [s[k] for k in env_names[4:]]) for s in col]
+                           for col in sites])
+
+    def unit(cell):
+        for _ in range(8):
+            for direction in range(4):
+                cell.move(a, cfgd["chi_target"], prec=prec, direction=direction, stream=stream)
+
+    for _ in range(args.warmup):
+        unit(fresh())
+    torch.cuda.synchronize()
+    cells = [fresh() for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for c in cells:
+        unit(c)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kept = len(cells[-1].singular_values())
+    out = {
+        "metric": "ms per CTM re-initialisation of a 2 x 2 unit cell (8 steps of one move toward each side)",
+        "value": ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+        "data": "synthetic (seeded Gaussian blocks, four draws)",
+        "config": {"workload": cfgd["name"] + "_cell2x2", "D_virtual": cfgd["virt"], "chi": cfgd["chi_target"],
+                   "chi_sectors": cfgd["chi"], "moves": 32, "parallelism": "single GPU"},
+        "ms_per_cell_move": ms / 32,
+        "kept_values_last_move": kept,
+    }
+    print(json.dumps(out))
+
+
 def use_recorded_tiles(workload):
     """GEMM tile choices recorded with the committed counter runs: when
     profiles/tune_<workload>.txt exists (and SYMTEN_TUNE_CACHE is not set),
@@ -516,6 +571,8 @@ def main():
     ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cell", action="store_true", help="time the left move of a 2 x 2 unit cell")
+    ap.add_argument("--unit", action="store_true",
+                    help="time a CTM re-initialisation of a 2 x 2 cell (8 steps per direction, D=3, chi=40)")
     ap.add_argument("--corners", action="store_true",
                     help="time the four enlarged corners, single-layer against double-layer route")
     args = ap.parse_args()
@@ -528,6 +585,9 @@ def main():
         return
     if args.cell:
         bench_cell(args)
+        return
+    if args.unit:
+        bench_unit(args)
         return
     if args.config == 5:
         bench_batched(args)
