@@ -12,7 +12,9 @@
 #include <list>
 #include <map>
 #include <sstream>
+#include <exception>
 #include <mutex>
+#include <thread>
 #include <numeric>
 #include <unordered_map>
 
@@ -591,104 +593,154 @@ struct ProjPending {
     bool aux_used[ctm_env::kAux] = {};
 };
 
-// Enqueues the eigensolves of every sector of a cut (no host
-// synchronisation).  `start` is recorded on s by the caller once the halves
-// of every cut it issues are enqueued; *rr carries the stream round robin
-// from one cut to the next, so that the largest classes of several cuts land
-// on different streams and overlap.
-ProjPending issue_solves(ctm_env* env, std::vector<CutSector>& secs, bool f64, hipStream_t s, hipEvent_t start,
-                         int* rr) {
-    if (secs.empty()) fail(SYMTEN_E_LINALG, "ctm_move: the halves have no common sector");
-    rb_check(rocblas_set_stream(env->rb, s), "rocblas_set_stream");
-    ProjPending pend;
-    pend.w.resize(secs.size());
-    std::vector<int> order(secs.size());
-    std::iota(order.begin(), order.end(), 0);
-    for (size_t i = 0; i < secs.size(); ++i) {
-        pend.w[i].ru = secs[i].mu;                                // rows of U_Y
-        pend.w[i].rd = secs[i].md;                                // rows of V_Y
-        secs[i].mn = std::min(secs[i].n, std::min(secs[i].mu, secs[i].md));   // rank bound
-    }
-    auto dim = [&](int i) { return std::max(secs[i].n, std::max(secs[i].mu, secs[i].md)); };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return dim(x) > dim(y); });
+// One size class of a cut: its blocks zero-padded to N, Y = H_u^T H_d, the
+// Jordan-Wielandt (FP64) or Gram matrix, one strided-batched eigensolve and
+// the singular triplets, all on stream cs with handle rh.
+void solve_class(const std::vector<CutSector>& secs, std::vector<ProjWork>& w, const std::vector<int>& cls, int N,
+                 bool f64, hipStream_t cs, rocblas_handle rh, std::vector<BufferPtr>& keep) {
     const double one = 1.0, zero = 0.0;
-    size_t pos = 0;
-    while (pos < order.size()) {
-        const int N = dim(order[pos]);
-        std::vector<int> cls;
-        while (pos < order.size() && (int)cls.size() < kMaxPadBatch / 2 && 2 * dim(order[pos]) >= N)
-            cls.push_back(order[pos++]);
-        const int B = (int)cls.size();
-        // classes go round robin over the caller's stream and the side
-        // streams, continuing where the previous cut of a batch stopped;
-        // side streams start after `start`
-        const int c = (*rr)++ % (ctm_env::kAux + 1);
-        hipStream_t cs = s;
-        rocblas_handle rh = env->rb;
-        if (c > 0) {
-            const int a = c - 1;
-            cs = env->aux[a];
-            rh = env->rb_aux[a];
-            if (!pend.aux_used[a]) HIPCHK(hipStreamWaitEvent(cs, start, 0));
-            pend.aux_used[a] = true;
+    const int B = (int)cls.size();
+    const size_t N2 = (size_t)N * N;
+    // H^T blocks (u, d interleaved) -> padded FP64 matrices
+    BufferPtr Hb = device_alloc(8 * N2 * 2 * B);
+    PadArgs pa{};
+    pa.count = 2 * B;
+    pa.N = N;
+    pa.src_f64 = f64;
+    for (int i = 0; i < B; ++i) {
+        const CutSector& b = secs[cls[i]];
+        for (int side = 0; side < 2; ++side) {
+            pa.src[2 * i + side] = side == 0 ? b.hu : b.hd;
+            pa.rows[2 * i + side] = side == 0 ? b.mu : b.md;   // col-major m x n (ld m)
+            pa.cols[2 * i + side] = b.n;
         }
-        const size_t N2 = (size_t)N * N;
-        // H^T blocks (u, d interleaved) -> padded FP64 matrices
-        BufferPtr Hb = device_alloc(8 * N2 * 2 * B);
-        PadArgs pa{};
-        pa.count = 2 * B;
-        pa.N = N;
-        pa.src_f64 = f64;
-        for (int i = 0; i < B; ++i) {
-            const CutSector& b = secs[cls[i]];
-            for (int side = 0; side < 2; ++side) {
-                pa.src[2 * i + side] = side == 0 ? b.hu : b.hd;
-                pa.rows[2 * i + side] = side == 0 ? b.mu : b.md;   // col-major m x n (ld m)
-                pa.cols[2 * i + side] = b.n;
-            }
-        }
-        launch_pad_blocks(pa, (double*)Hb->ptr, cs);
-        // Y = H_u^T H_d for every block of the class
-        BufferPtr Mb = device_alloc(8 * N2 * B);
-        rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N, N,
-                                               &one, (const double*)Hb->ptr, N, 2 * N2,
-                                               (const double*)Hb->ptr + N2, N, 2 * N2, &zero, (double*)Mb->ptr, N,
-                                               N2, B),
-                 "rocblas_dgemm_strided_batched(Y)");
-        const int NE = f64 ? 2 * N : N;
-        const size_t NE2 = (size_t)NE * NE;
-        BufferPtr Zb = device_alloc(8 * NE2 * B);
-        BufferPtr wb = device_alloc(8 * (size_t)NE * B);
-        BufferPtr Eb = device_alloc(8 * (size_t)NE * B);
-        BufferPtr ib = device_alloc(8 * (size_t)B);
-        if (f64)
-            launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, cs);
-        else
-            rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N,
-                                                   N, &one, (const double*)Mb->ptr, N, N2,
-                                                   (const double*)Mb->ptr, N, N2, &zero, (double*)Zb->ptr, N, N2,
-                                                   B),
-                     "rocblas_dgemm_strided_batched(YY^T)");
-        rb_check(rocsolver_dsyevd_strided_batched(rh, rocblas_evect_original, rocblas_fill_upper, NE,
-                                                  (double*)Zb->ptr, NE, NE2, (double*)wb->ptr, NE,
-                                                  (double*)Eb->ptr, NE, (rocblas_int*)ib->ptr, B),
-                 "rocsolver_dsyevd_strided_batched");
-        for (int i = 0; i < B; ++i) {
-            const CutSector& b = secs[cls[i]];
-            ProjWork& x = pend.w[cls[i]];
-            x.HuT = (double*)Hb->ptr + 2 * i * N2;          // H_u^T, col-major m x n
-            x.HdT = (double*)Hb->ptr + (2 * i + 1) * N2;    // H_d^T
-            x.Y = (double*)Mb->ptr + i * N2;
-            x.ld = N;
-            x.info = (int*)ib->ptr + i;
-            x.S = device_alloc(8 * std::max(1, b.mn));
-            x.U = device_alloc(8 * std::max<size_t>(1, (size_t)x.ru * b.mn));
-            x.V = device_alloc(8 * std::max<size_t>(1, (size_t)x.rd * b.mn));
-            launch_eig_to_svd((const double*)Zb->ptr + i * NE2, NE, (const double*)wb->ptr + (size_t)i * NE, N,
-                              b.mn, x.ru, x.rd, f64, (double*)x.S->ptr, (double*)x.U->ptr, (double*)x.V->ptr, cs);
-        }
-        for (auto& x : {Hb, Mb, Zb, wb, Eb, ib}) pend.keep_alive.push_back(x);
     }
+    launch_pad_blocks(pa, (double*)Hb->ptr, cs);
+    // Y = H_u^T H_d for every block of the class
+    BufferPtr Mb = device_alloc(8 * N2 * B);
+    rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N, N,
+                                           &one, (const double*)Hb->ptr, N, 2 * N2,
+                                           (const double*)Hb->ptr + N2, N, 2 * N2, &zero, (double*)Mb->ptr, N,
+                                           N2, B),
+             "rocblas_dgemm_strided_batched(Y)");
+    const int NE = f64 ? 2 * N : N;
+    const size_t NE2 = (size_t)NE * NE;
+    BufferPtr Zb = device_alloc(8 * NE2 * B);
+    BufferPtr wb = device_alloc(8 * (size_t)NE * B);
+    BufferPtr Eb = device_alloc(8 * (size_t)NE * B);
+    BufferPtr ib = device_alloc(8 * (size_t)B);
+    if (f64)
+        launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, cs);
+    else
+        rb_check(rocblas_dgemm_strided_batched(rh, rocblas_operation_none, rocblas_operation_transpose, N, N,
+                                               N, &one, (const double*)Mb->ptr, N, N2,
+                                               (const double*)Mb->ptr, N, N2, &zero, (double*)Zb->ptr, N, N2,
+                                               B),
+                 "rocblas_dgemm_strided_batched(YY^T)");
+    rb_check(rocsolver_dsyevd_strided_batched(rh, rocblas_evect_original, rocblas_fill_upper, NE,
+                                              (double*)Zb->ptr, NE, NE2, (double*)wb->ptr, NE,
+                                              (double*)Eb->ptr, NE, (rocblas_int*)ib->ptr, B),
+             "rocsolver_dsyevd_strided_batched");
+    for (int i = 0; i < B; ++i) {
+        const CutSector& b = secs[cls[i]];
+        ProjWork& x = w[cls[i]];
+        x.HuT = (double*)Hb->ptr + 2 * i * N2;          // H_u^T, col-major m x n
+        x.HdT = (double*)Hb->ptr + (2 * i + 1) * N2;    // H_d^T
+        x.Y = (double*)Mb->ptr + i * N2;
+        x.ld = N;
+        x.info = (int*)ib->ptr + i;
+        x.S = device_alloc(8 * std::max(1, b.mn));
+        x.U = device_alloc(8 * std::max<size_t>(1, (size_t)x.ru * b.mn));
+        x.V = device_alloc(8 * std::max<size_t>(1, (size_t)x.rd * b.mn));
+        launch_eig_to_svd((const double*)Zb->ptr + i * NE2, NE, (const double*)wb->ptr + (size_t)i * NE, N,
+                          b.mn, x.ru, x.rd, f64, (double*)x.S->ptr, (double*)x.U->ptr, (double*)x.V->ptr, cs);
+    }
+    for (auto& x : {Hb, Mb, Zb, wb, Eb, ib}) keep.push_back(x);
+}
+
+// Enqueues the eigensolves of every sector of the given cuts (no host
+// synchronisation).  Each cut's sectors are grouped into size classes
+// (largest first); the classes of all cuts go round robin over the caller's
+// stream and the side streams, so that the largest classes of several cuts
+// land on different streams.  `start` is recorded on s by the caller once the
+// halves of every cut are enqueued; side streams wait for it.  Enqueueing
+// rocSOLVER's eigensolver is host-bound (about two thirds of its device time
+// at n = 696), so every stream's classes are enqueued by a host thread of
+// their own, each with the stream's own rocBLAS handle.
+std::vector<ProjPending> issue_solves(ctm_env* env, const std::vector<std::vector<CutSector>*>& cuts, bool f64,
+                                      hipStream_t s, hipEvent_t start) {
+    rb_check(rocblas_set_stream(env->rb, s), "rocblas_set_stream");
+    constexpr int kSlots = ctm_env::kAux + 1;
+    struct SolveClass {
+        int cut, N, slot;
+        std::vector<int> cls;
+        std::vector<BufferPtr> keep;
+    };
+    std::vector<ProjPending> pend(cuts.size());
+    std::vector<SolveClass> classes;
+    int rr = 0;
+    for (size_t c = 0; c < cuts.size(); ++c) {
+        std::vector<CutSector>& secs = *cuts[c];
+        if (secs.empty()) fail(SYMTEN_E_LINALG, "ctm_move: the halves have no common sector");
+        pend[c].w.resize(secs.size());
+        std::vector<int> order(secs.size());
+        std::iota(order.begin(), order.end(), 0);
+        for (size_t i = 0; i < secs.size(); ++i) {
+            pend[c].w[i].ru = secs[i].mu;                                // rows of U_Y
+            pend[c].w[i].rd = secs[i].md;                                // rows of V_Y
+            secs[i].mn = std::min(secs[i].n, std::min(secs[i].mu, secs[i].md));   // rank bound
+        }
+        auto dim = [&](int i) { return std::max(secs[i].n, std::max(secs[i].mu, secs[i].md)); };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return dim(x) > dim(y); });
+        size_t pos = 0;
+        while (pos < order.size()) {
+            SolveClass k;
+            k.cut = (int)c;
+            k.N = dim(order[pos]);
+            while (pos < order.size() && (int)k.cls.size() < kMaxPadBatch / 2 && 2 * dim(order[pos]) >= k.N)
+                k.cls.push_back(order[pos++]);
+            k.slot = rr++ % kSlots;
+            if (k.slot > 0) pend[c].aux_used[k.slot - 1] = true;
+            classes.push_back(std::move(k));
+        }
+    }
+    bool waiting[ctm_env::kAux] = {};
+    for (auto& k : classes)
+        if (k.slot > 0 && !waiting[k.slot - 1]) {
+            HIPCHK(hipStreamWaitEvent(env->aux[k.slot - 1], start, 0));
+            waiting[k.slot - 1] = true;
+        }
+    auto run_slot = [&](int slot) {
+        hipStream_t cs = slot == 0 ? s : env->aux[slot - 1];
+        rocblas_handle rh = slot == 0 ? env->rb : env->rb_aux[slot - 1];
+        for (auto& k : classes)
+            if (k.slot == slot) solve_class(*cuts[k.cut], pend[k.cut].w, k.cls, k.N, f64, cs, rh, k.keep);
+    };
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::exception_ptr err[kSlots];
+    std::vector<std::thread> workers;
+    for (int slot = 1; slot < kSlots; ++slot) {
+        if (!waiting[slot - 1]) continue;
+        workers.emplace_back([&, slot] {
+            try {
+                HIPCHK(hipSetDevice(dev));
+                run_slot(slot);
+            } catch (...) {
+                err[slot] = std::current_exception();
+            }
+        });
+    }
+    try {
+        run_slot(0);
+    } catch (...) {
+        err[0] = std::current_exception();
+    }
+    for (auto& t : workers) t.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+    for (auto& k : classes)
+        for (auto& x : k.keep) pend[k.cut].keep_alive.push_back(x);
     return pend;
 }
 
@@ -797,9 +849,8 @@ ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPendin
 
 ProjOut cut_projectors(ctm_env* env, std::vector<CutSector>& secs, int chi, bool f64, hipStream_t s) {
     HIPCHK(hipEventRecord(env->ev_start, s));
-    int rr = 0;
-    ProjPending pend = issue_solves(env, secs, f64, s, env->ev_start, &rr);
-    return finish_projectors(env, secs, pend, chi, f64, s);
+    std::vector<ProjPending> pend = issue_solves(env, {&secs}, f64, s, env->ev_start);
+    return finish_projectors(env, secs, pend[0], chi, f64, s);
 }
 
 void fill_cut_stats(ctm_move_stats* st, const std::vector<CutSector>& secs, const ProjOut& po) {
@@ -1623,10 +1674,9 @@ void cell_left_move(ctm_env* env, const std::vector<TensorPtr>& a, int chi, int 
         // the cuts of a column are independent: their eigensolves are all
         // enqueued before the first read-back, spread over the streams
         HIPCHK(hipEventRecord(env->ev_start, s));
-        int rr = 0;
-        std::vector<ProjPending> pend;
-        for (int y = 0; y < Ly; ++y)
-            pend.push_back(issue_solves(env, preps[y].secs, preps[y].f64, s, env->ev_start, &rr));
+        std::vector<std::vector<CutSector>*> cut_secs;
+        for (int y = 0; y < Ly; ++y) cut_secs.push_back(&preps[y].secs);
+        std::vector<ProjPending> pend = issue_solves(env, cut_secs, preps[0].f64, s, env->ev_start);
         for (int y = 0; y < Ly; ++y) {
             ProjOut po = finish_projectors(env, preps[y].secs, pend[y], chi, preps[y].f64, s);
             cuts[y] = cut_complete(preps[y], po, s);

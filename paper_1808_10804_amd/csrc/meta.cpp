@@ -100,15 +100,23 @@ BufferPtr device_alloc(size_t bytes) {
     if (bytes == 0) return b;
     const size_t cap = round_cap(bytes);
     {
+        // the registration is copied under the lock and the allocator called
+        // outside it: the allocator may free library buffers (a garbage
+        // collector running in it), whose release takes the same lock
         UserAllocator& u = user_allocator();
-        std::lock_guard<std::mutex> lk(u.mu);
-        if (u.alloc) {
-            b->ptr = u.alloc(cap, u.ctx);
+        std::unique_lock<std::mutex> lk(u.mu);
+        void* (*alloc)(size_t, void*) = u.alloc;
+        void (*free_fn)(void*, size_t, void*) = u.free_fn;
+        void* ctx = u.ctx;
+        const uint64_t gen = u.gen;
+        lk.unlock();
+        if (alloc) {
+            b->ptr = alloc(cap, ctx);
             if (!b->ptr) fail(SYMTEN_E_NOMEM, "registered allocator returned null for " + std::to_string(cap) + " bytes");
             b->cap = cap;
-            b->user_free = u.free_fn;
-            b->user_ctx = u.ctx;
-            b->user_gen = u.gen;
+            b->user_free = free_fn;
+            b->user_ctx = ctx;
+            b->user_gen = gen;
             return b;
         }
     }
