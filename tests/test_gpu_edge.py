@@ -1,0 +1,113 @@
+"""Edge cases of the truncation in one FP64 left move, against the dense
+oracle: a cut that falls inside a degenerate pair of singular values (the
+pair is dropped whole: the U(1) counterpart of keeping SU(2) multiplets
+whole, as the paper's reduced truncation does), chi above the number of
+non-negligible values (everything is kept), and chi = 1."""
+import numpy as np
+import pytest
+
+import paper_1808_10804_amd as st
+from oracle import ctm, u1
+from synth import config
+from workload import oracle_side, to_dense, rel, from_dense
+
+pytestmark = pytest.mark.gpu
+
+
+def _mirror(sectors):
+    """Index map of a leg under charge conjugation q -> -q (sectors laid
+    out by ascending charge, the same offset inside the sector)."""
+    qs = sorted(sectors)
+    off, pos = {}, 0
+    for q in qs:
+        off[q] = pos
+        pos += sectors[q]
+    m = np.empty(pos, dtype=int)
+    for q in qs:
+        assert sectors[-q] == sectors[q]
+        m[off[q]:off[q] + sectors[q]] = off[-q] + np.arange(sectors[q])
+    return m
+
+
+def _symmetrise(x, maps):
+    """(x + x with every index mirrored) / 2: invariant under q -> -q."""
+    return 0.5 * (x + x[np.ix_(*maps)])
+
+
+def _workload(conjugation_symmetric):
+    c = config(1)
+    w, T, a, _ = oracle_side(c, c["seed"])
+    if conjugation_symmetric:
+        mc, md = _mirror(w.chi), _mirror(w.dd)
+        for k in ("C1", "C2", "C3", "C4"):
+            T[k] = _symmetrise(T[k], [mc, mc])
+        for k in ("T1", "T2", "T3", "T4"):
+            T[k] = _symmetrise(T[k], [mc, md, mc])
+        a = _symmetrise(a, [md, md, md, md])
+    chi_l, dd_l = w.chi, w.dd
+    dev = {k: from_dense(T[k], [(chi_l, 1), (chi_l, -1)]) for k in ("C1", "C2", "C3", "C4")}
+    for k, d in (("T1", -1), ("T4", -1), ("T2", 1), ("T3", 1)):
+        dev[k] = from_dense(T[k], [(chi_l, 1), (dd_l, d), (chi_l, -1)])
+    dev["a"] = from_dense(a, [(dd_l, 1), (dd_l, 1), (dd_l, -1), (dd_l, -1)])
+    return w, T, a, dev
+
+
+def _move_both(w, T, a, dev, chi):
+    C0 = [T["C1"], T["C2"], T["C3"], T["C4"]]
+    T0 = [T["T1"], T["T2"], T["T3"], T["T4"]]
+    C1o, T4o, C4o, so = ctm.left_move(C0, T0, a, chi)
+    env = st.CtmEnv([dev[k] for k in ("C1", "C2", "C3", "C4")], [dev[k] for k in ("T1", "T2", "T3", "T4")])
+    stats = env.move(dev["a"], chi, prec="f64")
+    # the whole spectrum of the cut, descending; the kept values lead it
+    sg = np.sort(env.singular_values())[::-1][:sum(stats["kept"].values())]
+    # the new legs laid out by charge on the device, by value in the oracle:
+    # the left column contracts them away
+    C1g, T4g, C4g = (to_dense(env.get(k)) for k in (0, 7, 3))
+    return so, sg, stats, u1.left_column(C1o, T4o, C4o), u1.left_column(C1g, T4g, C4g)
+
+
+def test_cut_inside_a_degenerate_pair():
+    """With the network invariant under q -> -q, the cut sectors Q and -Q have
+    the same spectrum.  chi is put between the two members of such a pair:
+    both sides drop the pair and keep chi - 1 states, with the same values
+    and the same (gauge-invariant) left column."""
+    w, T, a, dev = _workload(True)
+    C0 = [T["C1"], T["C2"], T["C3"], T["C4"]]
+    T0 = [T["T1"], T["T2"], T["T3"], T["T4"]]
+    s_all = ctm.left_move(C0, T0, a, 10 ** 6)[3]
+    pairs = [p for p in range(4, len(s_all) - 1)
+             if abs(s_all[p] - s_all[p + 1]) <= 1e-12 * s_all[0]
+             and s_all[p - 1] - s_all[p] > 1e-6 * s_all[0]]
+    assert pairs, "no degenerate pair in the symmetric spectrum"
+    p = pairs[0]
+    chi = p + 1                                  # keeps s[p], not its partner s[p + 1]
+    print(f"degenerate pair at {p}, {p + 1}: {s_all[p]:.15e} {s_all[p + 1]:.15e}; chi {chi}", flush=True)
+    so, sg, stats, Lo, Lg = _move_both(w, T, a, dev, chi)
+    assert len(so) == chi - 1                    # the oracle dropped the pair
+    assert sum(stats["kept"].values()) == chi - 1
+    assert np.allclose(sg, so, rtol=0, atol=1e-12 * so[0])
+    assert rel(Lg, Lo) <= 1e-10
+
+
+def test_chi_above_the_available_states():
+    """chi far above the cut's rank: every value above the cutoff is kept,
+    the same number on both sides."""
+    w, T, a, dev = _workload(False)
+    so, sg, stats, Lo, Lg = _move_both(w, T, a, dev, 100000)
+    err = rel(Lg, Lo)
+    print(f"kept {len(so)} of chi 100000, s_min/s_max {so[-1] / so[0]:.3e}, left column {err:.3e}", flush=True)
+    assert sum(stats["kept"].values()) == len(so) == len(sg)
+    assert np.allclose(sg, so, rtol=0, atol=1e-12 * so[0])
+    # the projectors carry s^-1/2: FP64 errors of order 1e-16 s_max in the
+    # smallest kept triplets grow by s_max / s_min in the column
+    assert err <= max(1e-10, 1e-13 * so[0] / so[-1])
+
+
+def test_chi_one():
+    """chi = 1 keeps the largest value alone (the random workload has no
+    degeneracy at the top)."""
+    w, T, a, dev = _workload(False)
+    so, sg, stats, Lo, Lg = _move_both(w, T, a, dev, 1)
+    assert len(so) == 1 and sum(stats["kept"].values()) == 1
+    assert abs(sg[0] - so[0]) <= 1e-12 * so[0]
+    assert rel(Lg, Lo) <= 1e-10
