@@ -111,3 +111,24 @@ def test_chi_one():
     assert len(so) == 1 and sum(stats["kept"].values()) == 1
     assert abs(sg[0] - so[0]) <= 1e-12 * so[0]
     assert rel(Lg, Lo) <= 1e-10
+
+
+def test_many_sectors_split_size_classes():
+    """Seventeen chi sectors of dimension 2 at bond dimension 3: the cut has 21
+    charge sectors, seventeen of them within a factor 2 of the largest (18),
+    more than one batched eigensolve takes (16), so the size class is split.  Spectrum, kept count
+    and left column against the dense oracle, in FP64."""
+    from workload import device_side
+    c = config(1)
+    c.update(virt={-2: 1, 0: 1, 2: 1}, chi={q: 2 for q in range(-16, 18, 2)}, chi_target=40)
+    w, T, a, _ = oracle_side(c, 4242)
+    dev = device_side(c, 4242, "f64")
+    n_cut = len({qc + qd for qc in w.chi for qd in w.dd})
+    assert n_cut == 21
+    so, sg, stats, Lo, Lg = _move_both(w, T, a, dev, c["chi_target"])
+    err = rel(Lg, Lo)
+    print(f"{n_cut} cut sectors, kept {len(so)}, left column {err:.3e}", flush=True)
+    assert len(stats["sv_sectors"]) == n_cut
+    assert sum(stats["kept"].values()) == len(so)
+    assert np.allclose(sg, so, rtol=0, atol=1e-12 * so[0])
+    assert err <= 1e-10
