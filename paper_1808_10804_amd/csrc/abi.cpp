@@ -738,7 +738,15 @@ std::vector<ProjPending> issue_solves(ctm_env* env, const std::vector<std::vecto
     }
     for (auto& t : workers) t.join();
     for (auto& e : err)
-        if (e) std::rethrow_exception(e);
+        if (e) {
+            // solves enqueued by the other threads may still run: drain the
+            // streams before their work buffers go back to the pool
+            (void)hipStreamSynchronize(s);
+            for (int a = 0; a < ctm_env::kAux; ++a)
+                if (waiting[a]) (void)hipStreamSynchronize(env->aux[a]);
+            (void)hipGetLastError();
+            std::rethrow_exception(e);
+        }
     for (auto& k : classes)
         for (auto& x : k.keep) pend[k.cut].keep_alive.push_back(x);
     return pend;
