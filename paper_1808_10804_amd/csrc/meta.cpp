@@ -292,12 +292,23 @@ static void simplify_task(CopyTask& t) {
             if (t.sstride[k] == 1) din = k;
             if (t.dstride[k] == 1) dout = k;
         }
-        // only when both dims fill a 32 x 32 tile: for smaller dims the idle
-        // part of the tile costs more than the uncoalesced reads save
-        if (din >= 0 && dout >= 0 && din != dout && t.dims[din] >= 32 && t.dims[dout] >= 32) {
-            t.tr_in = din;
-            t.tr_out = dout;
-            t.lg_out = 5;
+        // tiles of 1024 elements, 16 x 64, 32 x 32 or 64 x 16 (destination-
+        // contiguous x source-contiguous): the shape whose first tile leaves
+        // the smallest part idle, used when that part is at most a quarter
+        // (an idle part costs more than the uncoalesced reads save)
+        if (din >= 0 && dout >= 0 && din != dout && t.dims[din] >= 16 && t.dims[dout] >= 16) {
+            int best = -1;
+            double best_used = 0.0;
+            for (int lg : {5, 4, 6}) {           // 32 x 32 first: it wins ties
+                const int to = 1 << lg, ti = 1024 >> lg;
+                const double used = (double)std::min(to, t.dims[dout]) * std::min(ti, t.dims[din]) / 1024.0;
+                if (used > best_used + 1e-12) { best = lg; best_used = used; }
+            }
+            if (best >= 0 && best_used >= 0.75) {
+                t.tr_in = din;
+                t.tr_out = dout;
+                t.lg_out = best;
+            }
         }
     }
 }
