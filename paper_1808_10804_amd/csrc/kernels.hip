@@ -270,10 +270,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restric
         }
 }
 
-// ---- FP32 and BF16 variants on 32x32 MFMA tiles ---------------------------
+// ---- FP32: v_mfma_f32_32x32x2f32 -------------------------------------------
 // f32 32x32x2: lane l: A[row l%32][k l/32]; bf16 32x32x16: A[row l%32][k 8*(l/32)+0..7]
 // acc i (16 values): row 8*(i/4) + 4*(l/32) + i%4, col l%32
-template <class Ptrs, class S, int MODE>
+// One LDS stage with the next K stage prefetched into registers during the
+// MFMAs (two LDS stages, one barrier each, measured slower: the doubled LDS
+// lowers occupancy).
+template <class Ptrs, class S>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restrict__ tiles,
                                                        const GemmGroup* __restrict__ groups,
                                                        Ptrs ptrs) {
@@ -281,23 +284,9 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int TI = WM / 32, TJ = WN / 32;
     static_assert(TI >= 1 && TJ >= 1, "tile too small");
-    // f32 LDS: row stride BK+1 floats; bf16 LDS: row stride BK+8 halves
-    constexpr int LDF = BK + 1;
-    constexpr int LDH = BK + 8;
-    constexpr bool BF = (MODE != 1);
-    constexpr bool SPLIT = (MODE == 3);
-    constexpr int ASZ = BF ? 1 : BM * LDF;
-    constexpr int BSZ = BF ? 1 : BN * LDF;
-    constexpr int AHS = BF ? BM * LDH : 1;
-    constexpr int BHS = BF ? BN * LDH : 1;
-    constexpr int ALS = SPLIT ? BM * LDH : 1;
-    constexpr int BLS = SPLIT ? BN * LDH : 1;
-    __shared__ float Af[ASZ];
-    __shared__ float Bf[BSZ];
-    __shared__ __attribute__((aligned(16))) unsigned short Ah[AHS];
-    __shared__ __attribute__((aligned(16))) unsigned short Bh[BHS];
-    __shared__ __attribute__((aligned(16))) unsigned short Al[ALS];
-    __shared__ __attribute__((aligned(16))) unsigned short Bl[BLS];
+    constexpr int LDF = BK + 1;   // LDS row stride in floats
+    __shared__ float As[BM * LDF];
+    __shared__ float Bs[BN * LDF];
 
     const TileWork tw = tiles[blockIdx.x];
     if (tw.group < 0) return;   // padding of the per-XCD tile lists
@@ -332,45 +321,26 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
                                              : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
-    auto store_split = [&](unsigned short* hi, unsigned short* lo, int off, float x) {
-        const unsigned short h = f32_to_bf16_rn(x);
-        hi[off] = h;
-        if constexpr (SPLIT) lo[off] = f32_to_bf16_rn(x - bf16_to_f32(h));
-    };
     auto sstore = [&]() {
 #pragma unroll
         for (int v = 0; v < VA; ++v) {
             const int idx = tid + v * 256;
             const int r = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
-            if constexpr (!BF) {
-                Af[r * LDF + kq + 0] = ra[v].x;
-                Af[r * LDF + kq + 1] = ra[v].y;
-                Af[r * LDF + kq + 2] = ra[v].z;
-                Af[r * LDF + kq + 3] = ra[v].w;
-            } else {
-                const int o = r * LDH + kq;
-                store_split(Ah, Al, o + 0, ra[v].x);
-                store_split(Ah, Al, o + 1, ra[v].y);
-                store_split(Ah, Al, o + 2, ra[v].z);
-                store_split(Ah, Al, o + 3, ra[v].w);
-            }
+            float* d = &As[r * LDF + kq];
+            d[0] = ra[v].x;
+            d[1] = ra[v].y;
+            d[2] = ra[v].z;
+            d[3] = ra[v].w;
         }
 #pragma unroll
         for (int v = 0; v < VB; ++v) {
             const int idx = tid + v * 256;
             const int r = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
-            if constexpr (!BF) {
-                Bf[r * LDF + kq + 0] = rb[v].x;
-                Bf[r * LDF + kq + 1] = rb[v].y;
-                Bf[r * LDF + kq + 2] = rb[v].z;
-                Bf[r * LDF + kq + 3] = rb[v].w;
-            } else {
-                const int o = r * LDH + kq;
-                store_split(Bh, Bl, o + 0, rb[v].x);
-                store_split(Bh, Bl, o + 1, rb[v].y);
-                store_split(Bh, Bl, o + 2, rb[v].z);
-                store_split(Bh, Bl, o + 3, rb[v].w);
-            }
+            float* d = &Bs[r * LDF + kq];
+            d[0] = rb[v].x;
+            d[1] = rb[v].y;
+            d[2] = rb[v].z;
+            d[3] = rb[v].w;
         }
     };
 
@@ -388,48 +358,18 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
         sstore();
         __syncthreads();
         if (k0 + BK < K) gload(k0 + BK);
-        if constexpr (!BF) {
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += 2) {
-                float a[TI], b[TJ];
+        for (int kk = 0; kk < BK; kk += 2) {
+            float a[TI], b[TJ];
 #pragma unroll
-                for (int i = 0; i < TI; ++i) a[i] = Af[(wm + i * 32 + (lane & 31)) * LDF + kk + (lane >> 5)];
+            for (int i = 0; i < TI; ++i) a[i] = As[(wm + i * 32 + (lane & 31)) * LDF + kk + (lane >> 5)];
 #pragma unroll
-                for (int j = 0; j < TJ; ++j) b[j] = Bf[(wn + j * 32 + (lane & 31)) * LDF + kk + (lane >> 5)];
+            for (int j = 0; j < TJ; ++j) b[j] = Bs[(wn + j * 32 + (lane & 31)) * LDF + kk + (lane >> 5)];
 #pragma unroll
-                for (int i = 0; i < TI; ++i)
+            for (int i = 0; i < TI; ++i)
 #pragma unroll
-                    for (int j = 0; j < TJ; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
-            }
-        } else {
-#pragma unroll
-            for (int kk = 0; kk < BK; kk += 16) {
-                bf8_t ah[TI], bh[TJ], al[TI], bl[TJ];
-#pragma unroll
-                for (int i = 0; i < TI; ++i) {
-                    const int o = (wm + i * 32 + (lane & 31)) * LDH + kk + 8 * (lane >> 5);
-                    ah[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(Ah + o));
-                    if constexpr (SPLIT) al[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(Al + o));
-                }
-#pragma unroll
-                for (int j = 0; j < TJ; ++j) {
-                    const int o = (wn + j * 32 + (lane & 31)) * LDH + kk + 8 * (lane >> 5);
-                    bh[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(Bh + o));
-                    if constexpr (SPLIT) bl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(Bl + o));
-                }
-#pragma unroll
-                for (int i = 0; i < TI; ++i)
-#pragma unroll
-                    for (int j = 0; j < TJ; ++j) {
-                        if constexpr (SPLIT) {
-                            // small terms first, then the leading product
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-                        }
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                    }
-            }
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
@@ -842,14 +782,14 @@ template <class Ptrs>
 static void launch_f32_family(int cfg, dim3 grid, hipStream_t s, const TileWork* t, const GemmGroup* g, Ptrs P) {
     dim3 block(256);
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>, 1>), grid, block, 0, s, t, g, P); break;
-        case 1: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
-        case 2: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 32>, 1>), grid, block, 0, s, t, g, P); break;
-        case 3: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
-        case 4: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<256, 128, 32>, 1>), grid, block, 0, s, t, g, P); break;
-        case 5: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 64>, 1>), grid, block, 0, s, t, g, P); break;
-        case 6: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 64>, 1>), grid, block, 0, s, t, g, P); break;
-        default: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 64>, 1>), grid, block, 0, s, t, g, P); break;
+        case 0: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>>), grid, block, 0, s, t, g, P); break;
+        case 1: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>>), grid, block, 0, s, t, g, P); break;
+        case 2: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 32>>), grid, block, 0, s, t, g, P); break;
+        case 3: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 32>>), grid, block, 0, s, t, g, P); break;
+        case 4: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<256, 128, 32>>), grid, block, 0, s, t, g, P); break;
+        case 5: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 64>>), grid, block, 0, s, t, g, P); break;
+        case 6: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 64>>), grid, block, 0, s, t, g, P); break;
+        default: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 64>>), grid, block, 0, s, t, g, P); break;
     }
 }
 
