@@ -82,15 +82,16 @@ def profile_name(rocprof_name):
     if fam == "gemm_f32_kernel":
         return "gemm_f32_kernel<%sx%sx%s,f32>" % t.groups()
     if fam == "gemm_bf16_kernel":
-        return "gemm_bf16_kernel<%sx%sx%s,%s>" % (t.groups() + ("bf16x3" if last == "1" else "bf16",))
+        return "gemm_bf16_kernel<%sx%sx%s,%s>" % (t.groups() + ("bf16x3" if last in ("1", "true") else "bf16",))
     src = "f64" if "double" in args else "f32"
     dst = {"0": "f32", "1": "f64", "2": "bf16", "3": "bf16x2", "4": "acc"}.get(last, last)
     return "copy_kernel<%s,%s>" % (src, dst)
 
 
-def write_traffic(base, workload, command):
-    """profiles/traffic.json from the FETCH_SIZE / WRITE_SIZE summaries under
-    `base` (bench and calibration copy), scaled by the calibration copy."""
+def write_traffic(base, workload, command, out=None):
+    """profiles/traffic.json (or `out`) from the FETCH_SIZE / WRITE_SIZE
+    summaries under `base` (bench and calibration copy), scaled by the
+    calibration copy."""
     load = lambda n: json.load(open(os.path.join(base, n + ".summary.json")))
     cal = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
@@ -113,8 +114,8 @@ def write_traffic(base, workload, command):
            "calibration": {"copy_bytes_each_way": 256 << 20, "fetch_counter_per_byte": cal["FETCH_SIZE"],
                            "write_counter_per_byte": cal["WRITE_SIZE"]},
            "kernels": kern}
-    json.dump(rec, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
-    print(json.dumps(rec, indent=1))
+    json.dump(rec, open(out or os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+    return rec
 
 
 CPU_SAMPLE_SECONDS = 10.0    # the oracle's moves are repeated until this much CPU work
@@ -564,7 +565,7 @@ def pmc_summary(path):
     out = []
     for (kern, ctr), d in sorted(acc.items()):
         out.append({"kernel": kern, "counter": ctr, "dispatches": len(d), "avg_per_dispatch": sum(d.values()) / len(d)})
-    print(json.dumps(out, indent=1))
+    return out
 
 
 def main():
@@ -572,11 +573,11 @@ def main():
         calibrate_copy()
         return
     if "--pmc-summary" in sys.argv:
-        pmc_summary(sys.argv[sys.argv.index("--pmc-summary") + 1])
+        print(json.dumps(pmc_summary(sys.argv[sys.argv.index("--pmc-summary") + 1]), indent=1))
         return
     if "--write-traffic" in sys.argv:
         i = sys.argv.index("--write-traffic")
-        write_traffic(sys.argv[i + 1], sys.argv[i + 2], " ".join(sys.argv[i + 3:]))
+        print(json.dumps(write_traffic(sys.argv[i + 1], sys.argv[i + 2], " ".join(sys.argv[i + 3:])), indent=1))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
