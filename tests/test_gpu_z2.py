@@ -127,3 +127,43 @@ def test_ising_free_energy(prec, beta, tol):
     print(f"  beta {beta} {prec}: ln kappa {np.log(r['kappa']):.14f} Onsager {exact:.14f} "
           f"diff {np.log(r['kappa']) - exact:.1e}, steps {r['steps']}, error estimate {r['error']:.1e}")
     assert abs(np.log(r["kappa"]) - exact) <= tol
+
+
+def test_z2_bench_workload_move_full_size():
+    """The Z2 bench workload at full size (D = 6, chi = 64: a cut of 2304
+    states in two parity sectors), one FP32 move against the dense FP64
+    oracle on the same seeded draws: kept count and values, and the
+    gauge-invariant left column, to the FP32 bound; the kept table is
+    asserted only because the oracle's gap at the cut exceeds 100x it."""
+    from synth import config, draw, TENSOR_INDEX
+    c = config(6)
+    phys, virt, chi, seed = c["phys"], c["virt"], c["chi"], c["seed"]
+    L = lambda s, d: u1.Leg(s, d)
+    A_legs = [L(phys, 1), L(virt, 1), L(virt, 1), L(virt, -1), L(virt, -1)]
+    A = u1.embed(A_legs, c["flux"], draw((seed, TENSOR_INDEX["A"]), u1.nnz(A_legs, c["flux"], 2)), 2)
+    a, a_legs = u1.double_layer(A, A_legs, modulus=2)
+    dd = a_legs[0].sectors()
+    legs = {"C": [(chi, 1), (chi, -1)], "T1": [(chi, 1), (dd, -1), (chi, -1)], "T2": [(chi, 1), (dd, 1), (chi, -1)]}
+    legs.update(C1=legs["C"], C2=legs["C"], C3=legs["C"], C4=legs["C"], T3=legs["T2"], T4=legs["T1"])
+    D = {n: u1.embed([L(*x) for x in legs[n]], 0,
+                     draw((seed, TENSOR_INDEX[n]), u1.nnz([L(*x) for x in legs[n]], 0, 2)), 2)
+         for n in ("C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4")}
+    C0 = [D["C1"], D["C2"], D["C3"], D["C4"]]
+    T0 = [D["T1"], D["T2"], D["T3"], D["T4"]]
+    print("oracle: full spectrum and chi = 64 move", flush=True)
+    s_all = ctm.left_move(C0, T0, a, 10 ** 6)[3]
+    C1o, T4o, C4o, so = ctm.left_move(C0, T0, a, c["chi_target"])
+    k = len(so)
+    gap = (s_all[k - 1] - s_all[k]) / s_all[0]
+    print(f"kept {k}, gap {gap:.3e}", flush=True)
+    assert gap > 100 * 1e-5
+    A_dev = _dev(A, [(phys, 1), (virt, 1), (virt, 1), (virt, -1), (virt, -1)], c["flux"], "f32")
+    env = st.CtmEnv([_dev(D[n], legs[n], 0, "f32") for n in ("C1", "C2", "C3", "C4")],
+                    [_dev(D[n], legs[n], 0, "f32") for n in ("T1", "T2", "T3", "T4")])
+    stats = env.move(st.double_layer(A_dev), c["chi_target"], prec="f32")
+    sg = np.sort(env.singular_values())[::-1][:sum(stats["kept"].values())]
+    assert sum(stats["kept"].values()) == k
+    e_sv = rel(sg, so)
+    e_L = rel(u1.left_column(*(to_dense(env.get(i)) for i in (0, 7, 3))), u1.left_column(C1o, T4o, C4o))
+    print(f"Z2 D=6 chi=64 FP32 move: spectrum {e_sv:.2e}, left column {e_L:.2e}", flush=True)
+    assert e_sv <= 1e-5 and e_L <= 1e-5
