@@ -335,8 +335,11 @@ int ctm_env_get(ctm_env_t env, int k, symten_t* t);
 int ctm_move(ctm_env_t env, symten_t a, int dir, int chi, int prec,
              ctm_move_stats* st, void* stream);
 
-/* Partition function per site of a classical model (U(1)), FP64, from
- * the environment of a 1x1 cell, on a block x block patch (block 1 or 2):
+/* Partition function per site of a classical model (U(1), Z2 or SU(2);
+ * SU(2) networks are contracted on reduced blocks, the closing trace counting
+ * a spin-j block 2j+1 times), FP64, from the environment of a 1x1 cell
+ * (SYMTEN_E_INVAL for a unit cell: ctm_cell_site_partition), on a
+ * block x block patch (block 1 or 2):
  * kappa^(block^2) = Z_bb Z_00 / (Z_b0 Z_0b), Z_nm the closed network of the
  * four corners with n columns and m rows of edge tensors and the n x m site
  * tensors a between them (Z_00 = Tr C1 C2 C3 C4); the boundary factors cancel
@@ -394,7 +397,8 @@ int ctm_expectation(ctm_env_t env, symten_t a, int n, int m, const symten_t* sit
  * device (symten_double_layer_op).  Synchronous.                           */
 int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e_v, void* stream);
 
-/* CTM iteration with the error estimate of Sec. 3 (U(1)).  A step is one
+/* CTM iteration with the error estimate of Sec. 3 (U(1), Z2 or SU(2); 1x1
+ * environments).  A step is one
  * move toward each of the four sides (left, top, right, bottom).  At fixed
  * chi, steps run until kappa changes by less than tol from one step to the
  * next, or max_steps steps (the value before the first step is measured

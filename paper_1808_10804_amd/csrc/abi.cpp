@@ -1214,18 +1214,23 @@ void rotate_ccw(std::array<TensorPtr, 4>& C, std::array<TensorPtr, 4>& T, Tensor
     T = Tn;
 }
 
-// Full trace of a rank-2 U(1) tensor whose two legs are the two ends of one
-// bond (FP64 on the host).
-double trace_u1(const Tensor& X) {
+// Full trace of a rank-2 tensor whose two legs are the two ends of one bond
+// (FP64 on the host).  An SU(2) block of spin j stands for its reduced
+// matrix times the identity on the 2j+1 states of the multiplet (the basis
+// tensor of one incoming and one outgoing leg of spin j), so its trace
+// counts 2j+1 times.
+double trace_bond(const Tensor& X) {
     if (X.rank() != 2) fail(SYMTEN_E_INVAL, "internal: trace of a non-matrix");
     std::vector<char> host((size_t)std::max<int64_t>(X.elems, 1) * X.esize());
     HIPCHK(hipMemcpy(host.data(), X.data(), X.elems * X.esize(), hipMemcpyDeviceToHost));
     double t = 0.0;
     for (const Block& b : X.blocks) {
         if (b.q[0] != b.q[1] || b.shape[0] != b.shape[1]) continue;
+        const double mult = X.group == SYMTEN_SU2 ? (double)(b.q[0] + 1) : 1.0;
         for (int i = 0; i < b.shape[0]; ++i) {
             const int64_t o = b.offset + i * (b.stride[0] + b.stride[1]);
-            t += X.dtype == SYMTEN_F64 ? ((const double*)host.data())[o] : (double)((const float*)host.data())[o];
+            t += mult * (X.dtype == SYMTEN_F64 ? ((const double*)host.data())[o]
+                                               : (double)((const float*)host.data())[o]);
         }
     }
     return t;
@@ -1301,7 +1306,7 @@ double zblock(const std::array<TensorPtr, 4>& C, const std::array<TensorPtr, 4>&
     for (int j = n; j >= 1; --j) X = join(X, {T[2], {g(n - j), vert(m, j), g(n - j + 1)}}, keep, s);
     X = join(X, {C[3], {g(n), w(0)}}, keep, s);
     if (X.t->rank() != 2 || X.lab[0] != keep || X.lab[1] != keep) fail(SYMTEN_E_INVAL, "internal: network not closed");
-    return trace_u1(*X.t);
+    return trace_bond(*X.t);
 }
 
 // Partition function per site of a classical model from the environment of a
@@ -2486,8 +2491,8 @@ int ctm_site_partition(ctm_env_t env, symten_t a, int block, double* kappa, doub
         if (block != 1 && block != 2) fail(SYMTEN_E_INVAL, "block must be 1 or 2");
         Tensor& at = T(a);
         check_device_tensor(at, "ctm_site_partition(a)");
-        if (!abelian(at.group) || env->C[0]->group != at.group)
-            fail(SYMTEN_E_UNSUPPORTED, "ctm_site_partition: U(1) or Z2 tensors only");
+        if (env->C[0]->group != at.group || env->Lx > 0)
+            fail(SYMTEN_E_INVAL, "ctm_site_partition: a 1x1 environment of a's symmetry group");
         if (at.rank() != 4) fail(SYMTEN_E_INVAL, "a must have rank 4");
         double zz[4];
         *kappa = site_partition(env, a->t, block, zz, S(stream));
@@ -2570,8 +2575,8 @@ int ctm_run(ctm_env_t env, symten_t a, const ctm_run_opts* o, ctm_run_result* r,
             fail(SYMTEN_E_INVAL, "ctm_run: bad options");
         Tensor& at = T(a);
         check_device_tensor(at, "ctm_run(a)");
-        if (!abelian(at.group) || env->C[0]->group != at.group)
-            fail(SYMTEN_E_UNSUPPORTED, "ctm_run: U(1) or Z2 tensors only");
+        if (env->C[0]->group != at.group || env->Lx > 0)
+            fail(SYMTEN_E_INVAL, "ctm_run: a 1x1 environment of a's symmetry group");
         ctm_run_result res{};
         double z[4], prev_level = 0.0;
         for (int chi = o->chi;; chi *= 2) {

@@ -343,3 +343,50 @@ def test_su2_moves_in_every_direction_vs_oracle():
         assert abs(kg - ko) <= 1e-10 * abs(ko)
         assert np.allclose(zg, zo, rtol=1e-10)
         first = False
+
+
+@pytest.mark.parametrize("block", [1, 2])
+def test_su2_site_partition_vs_oracle(block):
+    """kappa of an SU(2) environment contracted on reduced blocks (the closing
+    trace counts a spin-j block 2j+1 times) against the oracle's kappa of the
+    CG-expanded dense tensors, before and after one left move (the oracle's
+    move truncated to the states the SU(2) move kept), FP64.  The draws
+    (seed 1813) give positive 2 x 2 ratios, whose fourth root kappa is."""
+    from oracle import ctm
+    legs = _env_legs(SMALL_MOVE["chi"], SMALL_MOVE["dd"])
+    vals = su2_values(legs, 1813)
+    env, dev = _su2_env(legs, vals, "f64")
+    D, _, _ = _expanded_u1(legs, vals)
+    C = [D[k] for k in ("C1", "C2", "C3", "C4")]
+    T = [D[k] for k in ("T1", "T2", "T3", "T4")]
+    for stage in ("initial", "after a move"):
+        if stage != "initial":
+            stats = env.move(dev["a"], SMALL_MOVE["chi_target"], prec="f64")
+            kept_states = sum((tj + 1) * k for tj, k in stats["kept"].items())
+            C, T, _ = ctm.move(C, T, D["a"], kept_states, 0)
+        kg, zg = env.site_partition(dev["a"], block=block)
+        ko, zo = ctm.site_partition_block(C, T, D["a"], block)
+        print(f"{stage}: kappa {kg:.14e} / {ko:.14e}", flush=True)
+        assert abs(kg - ko) <= 1e-10 * abs(ko)
+        assert np.allclose(zg, zo, rtol=1e-10)
+
+
+def test_su2_run_vs_oracle():
+    """ctm_run on an SU(2) environment (chi in states, whole multiplets kept)
+    against the oracle's run on the CG-expanded dense tensors (its truncation
+    never splits a degenerate set, so it keeps the same multiplets): two
+    steps of four moves, step counts, kappa and the step error, FP64."""
+    from oracle import ctm
+    legs = _env_legs(SMALL_MOVE["chi"], SMALL_MOVE["dd"])
+    vals = su2_values(legs, 1811)
+    env, dev = _su2_env(legs, vals, "f64")
+    D, _, _ = _expanded_u1(legs, vals)
+    C = [D[k] for k in ("C1", "C2", "C3", "C4")]
+    T = [D[k] for k in ("T1", "T2", "T3", "T4")]
+    chi = SMALL_MOVE["chi_target"]
+    r = env.run(dev["a"], chi=chi, prec="f64", max_steps=2, tol=0.0)
+    _, _, ro = ctm.run(C, T, D["a"], chi, max_steps=2, tol=0.0)
+    print(r, ro, flush=True)
+    assert r["steps"] == ro["steps"] == 2 and r["levels"] == ro["levels"] == 1
+    assert abs(r["kappa"] - ro["kappa"]) <= 1e-9 * abs(ro["kappa"])
+    assert abs(r["err_steps"] - ro["err_steps"]) <= 1e-9 * abs(ro["kappa"])
