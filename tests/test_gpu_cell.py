@@ -108,3 +108,21 @@ def test_ising_2x2_cell(beta):
             k, _ = cell.site_partition(x, y, adev)
             print(f"  beta {beta} site ({x},{y}): ln kappa - Onsager = {np.log(k) - exact:.1e}")
             assert abs(np.log(k) - exact) < 1e-10
+
+
+def test_1x1_entry_points_refuse_a_cell():
+    """A unit-cell environment goes through the cell entry points only: the
+    1x1 partition function and run refuse it (SYMTEN_E_INVAL) instead of
+    reading the tensors the cell was created with."""
+    import ctypes as C
+    from paper_1808_10804_amd import _lib
+    c = config(1)
+    dev, _, _ = _site(c, 0)
+    cell = st.CtmCell([[([dev[k] for k in ENV[:4]], [dev[k] for k in ENV[4:]])]])
+    k = C.c_double()
+    assert _lib.lib().ctm_site_partition(cell._h, dev["a"]._h, 1, C.byref(k), None, None) == -1
+    o, r = _lib.RunOpts(16, 16, 0, 1, 1, 0.0), _lib.RunResult()
+    assert _lib.lib().ctm_run(cell._h, dev["a"]._h, C.byref(o), C.byref(r), None) == -1
+    # the cell's own entry point still works
+    kappa, _ = cell.site_partition(0, 0, dev["a"])
+    assert np.isfinite(kappa)
