@@ -2527,10 +2527,22 @@ int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e
         if (!env || !e_h || !e_v) fail(SYMTEN_E_INVAL, "null argument");
         Tensor& At = T(A);
         check_device_tensor(At, "ctm_heisenberg_bond_energy(A)");
-        if (At.group != SYMTEN_U1 || At.rank() != 5)
-            fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: A is a rank-5 U(1) tensor");
+        if ((At.group != SYMTEN_U1 && At.group != SYMTEN_SU2) || At.rank() != 5 || env->C[0]->group != At.group ||
+            env->Lx > 0)
+            fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: A is a rank-5 U(1) or SU(2) tensor of a 1x1 "
+                                 "environment's group");
+        const bool su2 = At.group == SYMTEN_SU2;
+        if (su2 && (At.legs[0].q.size() != 1 || At.legs[0].d[0] != 1))
+            fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: the SU(2) physical leg is one multiplet");
         // physical states: charges 2m = -2S, -2S+2, ..., 2S, one state each
-        const Leg& ph = At.legs[0];
+        // (for SU(2): the S^z states of the physical multiplet)
+        Leg ph = At.legs[0];
+        if (su2) {
+            const int tS = ph.q[0];
+            ph.q.clear();
+            ph.d.clear();
+            for (int tm = -tS; tm <= tS; tm += 2) { ph.q.push_back(tm); ph.d.push_back(1); }
+        }
         const int np = ph.size();
         if (np < 2 || np > kMaxOpStates) fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: spin 1/2 .. 7/2");
         for (int k = 0; k < np; ++k)
@@ -2548,13 +2560,33 @@ int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e
             }
         }
         hipStream_t s = S(stream);
-        TensorPtr a = double_layer(At, s);
-        TensorPtr bz = double_layer(At, s, sz.data()), bp = double_layer(At, s, sp.data()),
-                  bm = double_layer(At, s, sm.data());
+        // SU(2): the spin operators are not invariant, so the state is
+        // measured through its S^z components -- the environment expanded
+        // (su2_to_u1) and the double layers built in the same S^z basis of
+        // the fused multiplets -- on the U(1) path; the value is the same
+        ctm_env expanded;
+        ctm_env* e = env;
+        TensorPtr a, bz, bp, bm;
+        if (su2) {
+            for (int i = 0; i < 4; ++i) {
+                expanded.C[i] = su2_to_u1(*env->C[i], s);
+                expanded.T[i] = su2_to_u1(*env->T[i], s);
+            }
+            e = &expanded;
+            a = double_layer_su2_sz(At, nullptr, s);
+            bz = double_layer_su2_sz(At, sz.data(), s);
+            bp = double_layer_su2_sz(At, sp.data(), s);
+            bm = double_layer_su2_sz(At, sm.data(), s);
+        } else {
+            a = double_layer(At, s);
+            bz = double_layer(At, s, sz.data());
+            bp = double_layer(At, s, sp.data());
+            bm = double_layer(At, s, sm.data());
+        }
         // S_i . S_j = Sz Sz + (S+ S- + S- S+) / 2 on the pair (left, right) or (top, bottom)
         auto bond = [&](int n, int m) {
-            return expectation(env, a, n, m, {bz, bz}, s) +
-                   0.5 * (expectation(env, a, n, m, {bp, bm}, s) + expectation(env, a, n, m, {bm, bp}, s));
+            return expectation(e, a, n, m, {bz, bz}, s) +
+                   0.5 * (expectation(e, a, n, m, {bp, bm}, s) + expectation(e, a, n, m, {bm, bp}, s));
         };
         *e_h = bond(2, 1);
         *e_v = bond(1, 2);

@@ -224,6 +224,10 @@ CopyTask make_copy_task(int src_buf, int64_t src_off, int dst_buf, int64_t dst_o
 
 // Expansion of an SU(2) tensor into the U(1) tensor of its S^z components
 // (charges 2m; within a charge, states by spin then multiplet index).
+// The SU(2) double layer of A with `op` (null: identity) between the layers
+// on the physical S^z states, left as a U(1) tensor in the S^z basis of the
+// fused multiplets (the basis su2_to_u1 gives an environment's D^2 legs).
+TensorPtr double_layer_su2_sz(const Tensor& A, const double* op, hipStream_t stream);
 TensorPtr su2_to_u1(const Tensor& in, hipStream_t stream);
 
 // SU(2) part of plan_contraction, called after the leg checks.

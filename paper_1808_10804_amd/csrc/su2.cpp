@@ -726,13 +726,18 @@ TensorPtr u1_to_su2(const Tensor& U, const std::vector<Leg>& legs, hipStream_t s
 // change of basis on each fused leg (a U(1) contraction with F written as a
 // charge-diagonal matrix), then the projection onto a's multiplet blocks.
 // This runs once per site tensor, not per move.
-TensorPtr double_layer_su2(const Tensor& A, hipStream_t s) {
+//
+// With `op` (a matrix on the physical S^z states, as for the U(1) double
+// layer) and project = false, the result stays a U(1) tensor in the S^z basis
+// of the fused multiplets: an operator double layer that is not invariant,
+// in the basis of an expanded SU(2) environment (su2_to_u1).
+TensorPtr double_layer_su2_impl(const Tensor& A, const double* op, bool project, hipStream_t s) {
     check_device_tensor(A, "double_layer");
     if (A.rank() != 5) fail(SYMTEN_E_INVAL, "double_layer: A must have rank 5 (phys, l, u, r, d)");
     const bool f64 = A.dtype == SYMTEN_F64;
     const int prec = f64 ? SYMTEN_PREC_F64 : SYMTEN_PREC_F32;
     TensorPtr Au = su2_to_u1(A, s);
-    TensorPtr au = double_layer(*Au, s);
+    TensorPtr au = double_layer(*Au, s, op);
     std::vector<Leg> fused(4);
     std::vector<TensorPtr> W(4);
     for (int x = 0; x < 4; ++x) {
@@ -817,9 +822,19 @@ TensorPtr double_layer_su2(const Tensor& A, hipStream_t s) {
         keep.push_back(p);
         cur = run_contraction(*p, *cur, *W[x], s);
     }
+    if (!project) {
+        HIPCHK(hipStreamSynchronize(s));
+        return cur;
+    }
     TensorPtr a = u1_to_su2(*cur, fused, s);
     HIPCHK(hipStreamSynchronize(s));
     return a;
+}
+
+TensorPtr double_layer_su2(const Tensor& A, hipStream_t s) { return double_layer_su2_impl(A, nullptr, true, s); }
+
+TensorPtr double_layer_su2_sz(const Tensor& A, const double* op, hipStream_t s) {
+    return double_layer_su2_impl(A, op, false, s);
 }
 
 }  // namespace symten

@@ -390,3 +390,48 @@ def test_su2_run_vs_oracle():
     assert r["steps"] == ro["steps"] == 2 and r["levels"] == ro["levels"] == 1
     assert abs(r["kappa"] - ro["kappa"]) <= 1e-9 * abs(ro["kappa"])
     assert abs(r["err_steps"] - ro["err_steps"]) <= 1e-9 * abs(ro["kappa"])
+
+
+def test_su2_heisenberg_energy_vs_oracle():
+    """Bond energies of an SU(2) state (spin 1/2, virtual multiplets j = 0, 1/2)
+    in an SU(2) environment: the library measures the S^z components (the
+    environment expanded, the double layers with Sz, S+, S- built in the same
+    S^z basis of the fused multiplets); the oracle contracts dense tensors in
+    SU(2) state order with operator double layers from its own fusion
+    isometries.  Both bonds, FP64."""
+    from oracle import ctm
+    virt = {0: 1, 1: 1}
+    A_spec = {"A": [({1: 1}, IN), (virt, IN), (virt, IN), (virt, OUT), (virt, OUT)]}
+    A_vals = su2_values(A_spec, 1815)
+    A_dev = device(A_spec, A_vals, "f64")["A"]
+    A_legs = [su2.Leg(s, d) for s, d in A_spec["A"]]
+    Ad = su2.expand(A_legs, A_vals["A"])
+    dd = su2.double_layer(A_legs, A_vals["A"])[0][0].sectors()
+    assert dd == SMALL_MOVE["dd"]
+    legs = _env_legs(SMALL_MOVE["chi"], dd)
+    legs.pop("a")
+    vals = su2_values(legs, 1815)
+    dev = device(legs, vals, "f64")
+    env = st.CtmEnv([dev[k] for k in ("C1", "C2", "C3", "C4")], [dev[k] for k in ("T1", "T2", "T3", "T4")])
+    e_h, e_v = env.heisenberg_bond_energy(A_dev)
+
+    def layer(op):
+        out = np.einsum("tk,klurd,tmvse->lmuvrsde", op, Ad, Ad)    # (ket, bra) pairs per bond
+        for v in A_legs[1:]:
+            Fl, Fv = su2.fusion_isometry(su2.Leg(v.sectors(), -v.dir), su2.Leg(v.sectors(), v.dir), v.dir)
+            out = np.tensordot(out, su2.expand(Fl, Fv), axes=([0, 1], [0, 1]))
+        return out
+    sz = np.diag([-0.5, 0.5])
+    sp = np.array([[0.0, 0.0], [1.0, 0.0]])     # <+1/2| S+ |-1/2> = 1 (rows: bra)
+    sm = sp.T.copy()
+    a, bz, bp, bm = layer(np.eye(2)), layer(sz), layer(sp), layer(sm)
+    C = [su2.expand([su2.Leg(s, d) for s, d in legs[k]], vals[k]) for k in ("C1", "C2", "C3", "C4")]
+    T = [su2.expand([su2.Leg(s, d) for s, d in legs[k]], vals[k]) for k in ("T1", "T2", "T3", "T4")]
+
+    def bond(n, m):
+        x = lambda s1, s2: ctm.expectation(C, T, a, [s1, s2], n, m)
+        return x(bz, bz) + 0.5 * (x(bp, bm) + x(bm, bp))
+    eo_h, eo_v = bond(2, 1), bond(1, 2)
+    print(f"energies: horizontal {e_h:.14e} / {eo_h:.14e}, vertical {e_v:.14e} / {eo_v:.14e}", flush=True)
+    assert abs(e_h - eo_h) <= 1e-10 * max(1.0, abs(eo_h))
+    assert abs(e_v - eo_v) <= 1e-10 * max(1.0, abs(eo_v))
