@@ -47,26 +47,43 @@ def test_cg_orthogonality(tj1, tj2):
 
 
 def test_rank2_example_sec2():
-    """Sec. 2's rank-2 example: an (in, out) tensor on spins 0, 1/2, 1 is block
-    diagonal, each block a reduced matrix times the identity of size 2j+1, so
-    it holds 1, 4 and 9 times as many elements as its reduced block; one spin-1/2
-    multiplet has total dimension 2 and reduced dimension 1."""
+    """Sec. 2's rank-2 example (values in tests/golden/sec2_rank2_example.json,
+    as the paper prints them): an (in, out) tensor on spins 0, 1/2, 1 is block
+    diagonal, each block a reduced matrix times an identity of size 2j+1, so
+    it holds 1, 4 and 9 times as many elements as its reduced block, and the
+    block (1/2, 0) is zero; one spin-1/2 multiplet has total dimension 2 and
+    reduced dimension 1.  With S^z alone, the S^z = 0 block gathers the
+    S = 0 and S = 1 states and S = 1/2 splits into the blocks S^z = +-1/2."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sec2_rank2_example.json")))
     leg = {0: 2, 1: 1, 2: 3}
     legs = [su2.Leg(leg, IN), su2.Leg(leg, OUT)]
-    assert [tj for tj, _ in su2.blocks(legs)] == [(0, 0), (1, 1), (2, 2)]
+    assert [tj for tj, _ in su2.blocks(legs)] == [(t, t) for t in g["doubled_spins"]]
     v = _rand(legs, 1)
     dense = su2.expand(legs, v)
     pos, seen = 0, 0
-    for tj, n in sorted(leg.items()):
+    for tj, size, ratio in zip(g["doubled_spins"], g["cgc_identity_size"], g["elements_per_reduced_element"]):
+        n = leg[tj]
         m = v[pos:pos + n * n].reshape(n, n)
         pos += n * n
         o = legs[0].offsets()[tj]
-        blk = dense[o:o + n * (tj + 1), o:o + n * (tj + 1)]
-        assert np.allclose(blk, np.kron(m, np.eye(tj + 1)), atol=0)
-        assert blk.size == (tj + 1) ** 2 * m.size
+        blk = dense[o:o + n * size, o:o + n * size]
+        assert np.allclose(blk, np.kron(m, np.eye(size)), atol=0)
+        assert blk.size == ratio * m.size
         seen += blk.size
     assert np.count_nonzero(dense) <= seen    # nothing off the diagonal blocks
+    fb = [int(round(2 * x)) for x in g["forbidden_block"]]
+    o1, o0 = legs[0].offsets()[fb[0]], legs[1].offsets()[fb[1]]
+    assert not dense[o1:o1 + leg[fb[0]] * (fb[0] + 1), o0:o0 + leg[fb[1]] * (fb[1] + 1)].any()
     assert su2.Leg({1: 1}, IN).size == 2 and su2.Leg({1: 1}, IN).reduced_size == 1
+    # the abelian alternative: S^z sectors of the same leg
+    sz = su2.Leg(leg, IN).u1_leg().sectors()
+    zero_spins = [tj for tj in leg if tj % 2 == 0]
+    assert [tj / 2 for tj in zero_spins] == g["abelian_sz_blocks"]["sz_zero_block_spins"]
+    assert sz[0] == sum(leg[tj] for tj in zero_spins)
+    assert sorted(q / 2 for q in sz if q % 2) == g["abelian_sz_blocks"]["half_integer_blocks"]
+    assert sz[1] == sz[-1] == leg[1]
 
 
 LEGSETS = [
