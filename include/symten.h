@@ -170,8 +170,11 @@ int symten_nbytes(symten_t t, int64_t* bytes);
  * handed back only while the registration that made it is the current one;
  * after any later call of this function it is kept until the process ends
  * (so the caller can drop an allocator that is going away, e.g. at
- * interpreter exit, by registering nulls first).  Errors: SYMTEN_E_INVAL
- * when only one of alloc and free is null.  Not for calls in flight.       */
+ * interpreter exit, by registering nulls first).  alloc and free may be
+ * called from the library's own host threads (the projector stage of a move
+ * enqueues from several), so they must be thread-safe.  Errors:
+ * SYMTEN_E_INVAL when only one of alloc and free is null.  Not for calls in
+ * flight.                                                                   */
 int symten_set_allocator(void* (*alloc)(size_t bytes, void* ctx),
                          void (*free_fn)(void* ptr, size_t bytes, void* ctx), void* ctx);
 
@@ -331,7 +334,10 @@ int ctm_env_get(ctm_env_t env, int k, symten_t* t);
  * 2J+1 states and multiplets are kept whole (descending, stopping at the
  * first that does not fit).  Synchronises `stream` once (truncation needs
  * the singular values on the host) and again at the end when `st` is not
- * NULL.                                                                     */
+ * NULL.  The eigensolves of the projector stage run on three side streams of
+ * the environment beside `stream`, each enqueued by a short-lived host thread
+ * of the library; all of them are joined to `stream` before the call
+ * returns.  Calls on one environment must not overlap.                      */
 int ctm_move(ctm_env_t env, symten_t a, int dir, int chi, int prec,
              ctm_move_stats* st, void* stream);
 
