@@ -14,6 +14,7 @@
 #include <sstream>
 #include <exception>
 #include <mutex>
+#include <system_error>
 #include <thread>
 #include <numeric>
 #include <unordered_map>
@@ -720,21 +721,29 @@ std::vector<ProjPending> issue_solves(ctm_env* env, const std::vector<std::vecto
     HIPCHK(hipGetDevice(&dev));
     std::exception_ptr err[kSlots];
     std::vector<std::thread> workers;
+    std::vector<int> inline_slots = {0};
     for (int slot = 1; slot < kSlots; ++slot) {
         if (!waiting[slot - 1]) continue;
-        workers.emplace_back([&, slot] {
-            try {
-                HIPCHK(hipSetDevice(dev));
-                run_slot(slot);
-            } catch (...) {
-                err[slot] = std::current_exception();
-            }
-        });
+        try {
+            workers.emplace_back([&, slot] {
+                try {
+                    HIPCHK(hipSetDevice(dev));
+                    run_slot(slot);
+                } catch (...) {
+                    err[slot] = std::current_exception();
+                }
+            });
+        } catch (const std::system_error&) {
+            inline_slots.push_back(slot);   // no thread to spare: enqueue it from this one
+        }
     }
-    try {
-        run_slot(0);
-    } catch (...) {
-        err[0] = std::current_exception();
+    for (int slot : inline_slots) {
+        try {
+            run_slot(slot);
+        } catch (...) {
+            err[slot] = std::current_exception();
+            break;
+        }
     }
     for (auto& t : workers) t.join();
     for (auto& e : err)
