@@ -258,3 +258,28 @@ def test_heisenberg_ferromagnet_product_state():
     env = st.CtmEnv(Cs, Ts)
     eh, ev = env.heisenberg_bond_energy(Adev)
     assert abs(eh - 0.25) <= 1e-14 and abs(ev - 0.25) <= 1e-14
+
+
+def test_move_on_a_torch_stream_equals_the_null_stream():
+    """The same FP32 move (cfg 2 shape at D = 4, chi = 16) issued on a torch
+    stream of default priority and on the null stream: the side streams of
+    the projector stage join whichever stream the caller passes, so the
+    results are identical."""
+    import torch
+    c = config(1)
+    out = []
+    for use_stream in (False, True):
+        dev = device_side(c, c["seed"], "f32")
+        env = _env(dev)
+        torch.cuda.synchronize()        # the inputs were built on the null stream
+        if use_stream:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                env.move(dev["a"], c["chi_target"], prec="f32", stream=s.cuda_stream)
+            s.synchronize()
+        else:
+            env.move(dev["a"], c["chi_target"], prec="f32")
+        out.append(([to_dense(env.get(k)) for k in range(8)], np.sort(env.singular_values())))
+    for x, y in zip(out[0][0], out[1][0]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(out[0][1], out[1][1])
