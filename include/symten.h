@@ -397,14 +397,17 @@ int ctm_expectation(ctm_env_t env, symten_t a, int n, int m, const symten_t* sit
 /* Nearest-neighbour Heisenberg energy per bond, S_i . S_j = Sz Sz +
  * (S+ S- + S- S+)/2 (J = 1), FP64, of the state A[phys, l, u, r, d]
  * (U(1): physical charges 2m for m = -S..S, one state each; SU(2): one
- * physical multiplet of spin S; S <= 7/2) in the current 1x1 environment,
+ * physical multiplet of spin S; S <= 7/2; Z2: spin 1/2 with the physical
+ * leg {0: 1, 1: 1} in the spin-flip parity basis (|up> +- |down>)/sqrt2,
+ * where Sx keeps the parity and Sy, Sz flip it) in the current 1x1 environment,
  * which must be the environment of A's double layer: *e_h on a horizontal
  * bond (2 x 1 patch), *e_v on a vertical one.  The double layers with Sz,
  * S+, S- between the layers are built on the device
  * (symten_double_layer_op); for SU(2), whose spin operators are not
  * invariant, the state is measured through its S^z components: the
  * environment is expanded and the double layers are built in the S^z basis
- * of its fused multiplets.  Synchronous.                                    */
+ * of its fused multiplets; for Z2 the three components are summed as
+ * Sx Sx + Sz Sz - J J with the real J = -i Sy.  Synchronous.               */
 int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e_v, void* stream);
 
 /* CTM iteration with the error estimate of Sec. 3 (U(1), Z2 or SU(2); 1x1

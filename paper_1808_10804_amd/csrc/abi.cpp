@@ -2536,10 +2536,30 @@ int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e
         if (!env || !e_h || !e_v) fail(SYMTEN_E_INVAL, "null argument");
         Tensor& At = T(A);
         check_device_tensor(At, "ctm_heisenberg_bond_energy(A)");
-        if ((At.group != SYMTEN_U1 && At.group != SYMTEN_SU2) || At.rank() != 5 || env->C[0]->group != At.group ||
-            env->Lx > 0)
-            fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: A is a rank-5 U(1) or SU(2) tensor of a 1x1 "
+        if ((At.group != SYMTEN_U1 && At.group != SYMTEN_SU2 && At.group != SYMTEN_Z2) || At.rank() != 5 ||
+            env->C[0]->group != At.group || env->Lx > 0)
+            fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: A is a rank-5 U(1), SU(2) or Z2 tensor of a 1x1 "
                                  "environment's group");
+        hipStream_t s = S(stream);
+        if (At.group == SYMTEN_Z2) {
+            // spin 1/2 in the spin-flip parity basis |+-> = (|up> +- |down>)/sqrt2
+            // (labels 0, 1): Sx = diag(1/2, -1/2) keeps the parity, Sz and
+            // Sy = i J with J = [[0, 1/2], [-1/2, 0]] flip it, so
+            // S_i . S_j = Sx Sx + Sz Sz - J J with real operators
+            const Leg& p = At.legs[0];
+            if (p.q != std::vector<int>{0, 1} || p.d != std::vector<int>{1, 1})
+                fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: the Z2 physical leg is {0: 1, 1: 1} (spin 1/2)");
+            const double sx[4] = {0.5, 0.0, 0.0, -0.5}, sz[4] = {0.0, 0.5, 0.5, 0.0}, jy[4] = {0.0, 0.5, -0.5, 0.0};
+            TensorPtr a = double_layer(At, s);
+            TensorPtr bx = double_layer(At, s, sx), bz = double_layer(At, s, sz), bj = double_layer(At, s, jy);
+            auto bond = [&](int n, int m) {
+                return expectation(env, a, n, m, {bx, bx}, s) + expectation(env, a, n, m, {bz, bz}, s) -
+                       expectation(env, a, n, m, {bj, bj}, s);
+            };
+            *e_h = bond(2, 1);
+            *e_v = bond(1, 2);
+            return;
+        }
         const bool su2 = At.group == SYMTEN_SU2;
         if (su2 && (At.legs[0].q.size() != 1 || At.legs[0].d[0] != 1))
             fail(SYMTEN_E_INVAL, "ctm_heisenberg_bond_energy: the SU(2) physical leg is one multiplet");
@@ -2568,7 +2588,6 @@ int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e
                 sm[k * np + (k + 1)] = c;       // <m| S- |m+1>
             }
         }
-        hipStream_t s = S(stream);
         // SU(2): the spin operators are not invariant, so the state is
         // measured through its S^z components -- the environment expanded
         // (su2_to_u1) and the double layers built in the same S^z basis of

@@ -167,3 +167,91 @@ def test_z2_bench_workload_move_full_size():
     e_L = rel(u1.left_column(*(to_dense(env.get(i)) for i in (0, 7, 3))), u1.left_column(C1o, T4o, C4o))
     print(f"Z2 D=6 chi=64 FP32 move: spectrum {e_sv:.2e}, left column {e_L:.2e}", flush=True)
     assert e_sv <= 1e-5 and e_L <= 1e-5
+
+
+# spin 1/2 in the (up, down) basis, matrices [bra, ket]
+_SX = 0.5 * np.array([[0.0, 1.0], [1.0, 0.0]])
+_SY = 0.5 * np.array([[0.0, -1.0j], [1.0j, 0.0]])
+_SZ = 0.5 * np.array([[1.0, 0.0], [0.0, -1.0]])
+# columns: the parity states |+> = (|up> + |down>)/sqrt2 (label 0) and |->
+_R = np.array([[1.0, 1.0], [1.0, -1.0]]) / np.sqrt(2.0)
+
+
+def _z2_identity_boundary(A_legs):
+    """chi = 1 environment pairing ket and bra states on every fused leg."""
+    Ts = []
+    for l in (A_legs[2], A_legs[3], A_legs[4], A_legs[1]):
+        F, perm = u1.fuse(l, l, +1, -1, l.dir, 2)
+        n = l.size
+        t = np.zeros((1, F.size, 1))
+        t[0, [f for f, p in enumerate(perm) if p // n == p % n], 0] = 1.0
+        Ts.append(t)
+    return [np.ones((1, 1))] * 4, Ts
+
+
+def _energy_up_down(Cd, Td, A, legs):
+    """<S_i . S_j> on both bonds with the site tensor's physical leg turned
+    to the (up, down) basis and the textbook spin matrices.  The networks
+    are real, so a complex operator O = R + iI enters through the two-site
+    value being linear in each site: <O O> = <R R> - <I I> + i(<R I> + <I R>)."""
+    Aud = np.tensordot(_R, A, axes=([1], [0]))
+    a = u1.double_layer(Aud, legs, modulus=2)[0]
+    out = []
+    for n, m in ((2, 1), (1, 2)):
+        e = 0.0
+        for op in (_SX, _SY, _SZ):
+            br, bi = (u1.double_layer_op(Aud, legs, np.ascontiguousarray(x), modulus=2) for x in (op.real, op.imag))
+            z = lambda x, y: ctm.expectation(Cd, Td, a, [x, y], n, m)
+            e = e + (z(br, br) - z(bi, bi)) + 1j * (z(br, bi) + z(bi, br))
+        assert abs(e.imag) <= 1e-12 * abs(e.real)
+        out.append(e.real)
+    return out
+
+
+def test_z2_heisenberg_energy_vs_oracle():
+    """A random parity-even spin-1/2 state (virtual {0: 2, 1: 1}): the bond
+    energies in the traced open boundary and after one CTM step (chi = 16,
+    FP64) against the dense networks with the physical leg turned back to
+    the (up, down) basis and all three spin components, S^y complex."""
+    Al = [({0: 1, 1: 1}, 1)] + [({0: 2, 1: 1}, d) for d in (1, 1, -1, -1)]
+    A, legs = _rand_z2(Al, 0, 1816)
+    Adev = _dev(A, Al, 0)
+    adev = st.double_layer(Adev)
+    aleg = adev.legs()
+    Cd, Td = _z2_identity_boundary(legs)
+    one = {0: 1}
+    Cs = [_dev(Cd[k], [(one, 1), (one, -1)], 0) for k in range(4)]
+    Tlegs = [aleg[1], aleg[2], aleg[3], aleg[0]]
+    Ts = [_dev(Td[k], [(one, 1), (Tlegs[k][0], d), (one, -1)], 0) for k, d in enumerate((-1, 1, 1, -1))]
+    env = st.CtmEnv(Cs, Ts)
+    for stage in ("open boundary", "after one step"):
+        if stage != "open boundary":
+            for d in range(4):
+                env.move(adev, 16, prec="f64", direction=d)
+        Cg = [to_dense(env.get(k)) for k in range(4)]
+        Tg = [to_dense(env.get(4 + k)) for k in range(4)]
+        oh, ov = _energy_up_down(Cg, Tg, A, legs)
+        eh, ev = env.heisenberg_bond_energy(Adev)
+        print(f"  {stage}: h {eh:.12e} ({oh:.12e}), v {ev:.12e} ({ov:.12e})")
+        assert abs(oh) > 1e-3 and abs(ov) > 1e-3
+        assert abs(eh - oh) <= 1e-10 * abs(oh) and abs(ev - ov) <= 1e-10 * abs(ov)
+
+
+def test_z2_heisenberg_x_polarised_product_state():
+    """D = 1, every spin along +x (parity label 0): <S_i . S_j> = 1/4 on both
+    bonds; a physical leg other than one state of each parity is refused."""
+    A = np.zeros((2, 1, 1, 1, 1))
+    A[0] = 1.3
+    one = {0: 1}
+    Al = [({0: 1, 1: 1}, 1)] + [(one, d) for d in (1, 1, -1, -1)]
+    Adev = _dev(A, Al, 0)
+    Cs = [_dev(np.ones((1, 1)), [(one, 1), (one, -1)], 0) for _ in range(4)]
+    Ts = [_dev(np.ones((1, 1, 1)), [(one, 1), (one, d), (one, -1)], 0) for d in (-1, 1, 1, -1)]
+    env = st.CtmEnv(Cs, Ts)
+    eh, ev = env.heisenberg_bond_energy(Adev)
+    assert abs(eh - 0.25) <= 1e-14 and abs(ev - 0.25) <= 1e-14
+    B = np.zeros((3, 1, 1, 1, 1))
+    B[0] = 1.0
+    Bdev = _dev(B, [({0: 2, 1: 1}, 1)] + [(one, d) for d in (1, 1, -1, -1)], 0)
+    with pytest.raises(st.SymtenError):
+        env.heisenberg_bond_energy(Bdev)
