@@ -24,13 +24,17 @@
  * operands (Sec. 2, reduction of blocks with parallel CGCs).
  *
  * Conventions shared by every entry point:
- *  - U(1) charges are integers in units of 2*S^z; SU(2) labels are doubled
- *    spins 2j (0..64) and an SU(2) tensor's flux must be 0 (Sec. 2: no
- *    quantum-number shift inside a tensor), else SYMTEN_E_SYM.
+ *  - U(1) charges are integers in units of 2*S^z; Z2 labels are parities
+ *    0, 1 (every charge sum taken mod 2; flux 0 or 1); SU(2) labels are
+ *    doubled spins 2j (0..64) and an SU(2) tensor's flux must be 0 (Sec. 2:
+ *    no quantum-number shift inside a tensor), else SYMTEN_E_SYM.
  *  - SU(2) sector dims are multiplet counts (reduced dims); a multiplet of
- *    spin j holds 2j+1 states.  Every entry point takes both groups except
- *    the batched corners (U(1) only, SYMTEN_E_UNSUPPORTED otherwise); all
- *    operands of one call must share the group (SYMTEN_E_SYM otherwise).
+ *    spin j holds 2j+1 states.  Tensor algebra, the double layer, the
+ *    corner and the move take all three groups; the entry points that say
+ *    otherwise below (the batched corners, expectation values, unit cells,
+ *    the single-layer corner: U(1) and Z2) return SYMTEN_E_UNSUPPORTED or
+ *    SYMTEN_E_INVAL for SU(2); all operands of one call must share the group
+ *    (SYMTEN_E_SYM otherwise).
  *  - A leg's sectors are given as parallel arrays (label, reduced dim); the
  *    library sorts them by label ascending, which fixes the state order.
  *  - Canonical block order is lexicographic in the labels, leg 0 slowest.
@@ -105,10 +109,11 @@ typedef struct {
     int rank;           /* 1 .. SYMTEN_MAX_RANK                             */
     const int* dirs;    /* [rank] SYMTEN_IN / SYMTEN_OUT                    */
     const int* nsec;    /* [rank] number of sectors per leg                 */
-    const int* labels;  /* [sum nsec] U(1) charge (units of 2 S^z);
-                           SU(2) doubled spin 2j                            */
+    const int* labels;  /* [sum nsec] U(1) charge (units of 2 S^z); Z2
+                           parity 0, 1; SU(2) doubled spin 2j              */
     const int* dims;    /* [sum nsec] reduced sector dimension (>= 0)       */
-    int flux;           /* U(1): sum dir*q of every block; SU(2): 0         */
+    int flux;           /* U(1): sum dir*q of every block; Z2: that sum
+                           mod 2 (0 or 1); SU(2): 0                         */
     int dtype;          /* SYMTEN_F64 or SYMTEN_F32                         */
 } symten_desc;
 
@@ -269,7 +274,7 @@ int symten_enlarged_corner_single_layer(symten_t* out, int which, symten_t C, sy
  * step of all n fused into one grouped-GEMM launch.  use_graph != 0 records
  * the whole batch into a HIP graph on first use and replays it afterwards
  * (inputs must keep their structures and buffers).  out[i] receive the
- * corners; info (may be NULL) the summed statistics.                       */
+ * corners; info (may be NULL) the summed statistics.  U(1) and Z2.          */
 int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* C,
                                     const symten_t* Ta, const symten_t* Tb,
                                     const symten_t* a, int prec, int use_graph,
@@ -386,8 +391,8 @@ int ctm_cell_site_partition(ctm_env_t env, int x, int y, symten_t a, int block, 
  * of the 1x1-cell environment, FP64: value = Z_nm(sites) / Z_nm(a), where
  * Z_nm(sites) is the closed network of ctm_site_partition with the site
  * tensors replaced by sites[n*m] (row-major: row 0 on top, column 0 on the
- * left; each a rank-4 U(1) tensor with a's legs, any flux; a patch whose
- * fluxes do not add up to 0 gives 0).  For a PEPS, sites are double layers
+ * left; each a rank-4 tensor of a's group (U(1) or Z2) with a's legs, any
+ * flux; a patch whose fluxes do not add up to 0 gives 0).  For a PEPS, sites are double layers
  * with one-site operators between the layers (symten_double_layer_op) and
  * the value is <O_1 O_2 ...> of Sec. 3's energy evaluation; for a classical
  * model they are impurity weights.  Synchronous.                            */
