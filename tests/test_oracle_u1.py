@@ -340,3 +340,69 @@ def test_truncation_never_splits_a_degenerate_set():
     assert kept(2.0, 3) == {0: 2, 1: 1}
     assert kept(2.0 * (1 - 1e-6), 2) == {0: 2}
     assert kept(2.0 * (1 - 1e-6), 1) == {0: 1}
+
+
+# ------------------------------------------------------ move flop counts ---
+
+def _sector_move_flops(chi, dd, kept):
+    """Useful flops of the halves and of the renormalisation of one left
+    move, summed over sector labels instead of enumerated block pairs.
+
+    Charge rules (clockwise bonds): a left-cut state (x, u) has fused charge
+    Q = q_x - q_u, so n_Q = sum_{x - u = Q} chi_x dd_u.  Each half multiplies
+    two block-diagonal corner matrices whose three fat bonds all have sizes
+    n_Q when the legs are symmetric under q -> -q: 2 sum_Q n_Q^3 per half.
+    C1' = (C1 T1) P and C4' = (C4 T3) P~ each cost 2 sum_Q chi_Q k_Q n_Q.
+    T4' = ((P~ T4) a) P in three steps:
+      P~[K,c,e] T4[y,l,c]    K = c - e, y = l + c     m = k_K dd_e, k = chi_c, n = chi_y dd_l
+      X1[K,e,y,l] a[l,e,r,d] l + e = r + d            m = k_K chi_y, k = dd_e dd_l, n = dd_r dd_d
+      X2[K,y,r,d] P[y,d,K']  K' = y - d               m = k_K dd_r, k = chi_y dd_d, n = k_K'
+    where X2 block (K, y, r, d) exists when some (l, e) with l + e = r + d,
+    chi_{y-l} > 0 reaches it (then K = y - r - d).
+    """
+    g = lambda m, q: m.get(q, 0)
+    nQ = {}
+    for x, cx in chi.items():
+        for u, du in dd.items():
+            nQ[x - u] = nQ.get(x - u, 0) + cx * du
+    assert all(nQ[q] == nQ.get(-q, 0) for q in nQ), "closed form needs symmetric legs"
+    halves = 4 * sum(n ** 3 for n in nQ.values())
+    c1 = c4 = 2 * sum(g(chi, Q) * k * g(nQ, Q) for Q, k in kept.items())
+    x1 = 2 * sum(g(kept, c - e) * de * cc * g(chi, l + c) * dl
+                 for c, cc in chi.items() for e, de in dd.items() for l, dl in dd.items())
+    x2 = 0
+    for y, cy in chi.items():
+        for l, dl in dd.items():
+            if not g(chi, y - l):
+                continue
+            for e, de in dd.items():
+                K = y - l - e
+                for r, dr in dd.items():
+                    x2 += 2 * g(kept, K) * cy * de * dl * dr * g(dd, l + e - r)
+    t4 = 0
+    for y, cy in chi.items():
+        for r, dr in dd.items():
+            for d, dd_d in dd.items():
+                reached = any(g(chi, y - l) and g(dd, r + d - l) for l in dd)
+                if reached:
+                    t4 += 2 * g(kept, y - r - d) * dr * cy * dd_d * g(kept, y - d)
+    return halves, c1 + c4 + x1 + x2 + t4
+
+
+@pytest.mark.parametrize("ci", [1, 2])
+def test_move_flops_match_sector_sums(ci):
+    """The oracle's halves and renormalisation flop counts (block-pair
+    enumeration) equal sums over sector labels; cfg 1's halves are
+    4 sum_Q n_Q^3 = 4 * 971776."""
+    c = config(ci)
+    w = Workload(c["phys"], c["virt"], c["chi"], c["flux"])
+    nL = u1.fused_sectors(w, "diff")
+    kept_tables = [{0: min(16, nL[0])}, {q: min(4, n) for q, n in nL.items() if abs(q) <= 2},
+                   {-2: 3, 0: 7, 4: 1}]
+    for kept in kept_tables:
+        fl = u1.move_gemm_flops(w, kept)
+        halves, renorm = _sector_move_flops(w.chi, w.dd, kept)
+        assert fl["halves"] == halves
+        assert fl["renorm"] == renorm
+    if ci == 1:
+        assert halves == 4 * 971776 == 3887104
