@@ -372,9 +372,20 @@ def renormalise(w, T, a, P, Pt):
     CT = np.einsum("ab,bux->aux", T["C1"], T["T1"])
     CTm = CT.reshape(nX * nD, nX)[pd]
     C1n = P.T @ CTm
-    T4a = np.einsum("ylx,lurd->ydxur", T["T4"], a).reshape(nX * nD, nX * nD, nD)
-    T4a = T4a[np.ix_(pd, pd, np.arange(nD))]
-    T4n = np.einsum("fk,fgr,hg->krh", P, T4a, Pt, optimize=True)
+    # T4' = P~ (T4 a) P with the fat bonds unfused: rows of P and columns of
+    # P~ back in (chi, D2) product order; the pairwise contractions take P~
+    # first, so that no (chi D2)^2 D2 array is formed (84 GB at D = 8,
+    # chi = 200)
+    k = P.shape[1]
+    P3 = np.zeros((nX * nD, k))
+    P3[pd] = P
+    P3 = P3.reshape(nX, nD, k)                 # [y, d, k]
+    Pt3 = np.zeros((k, nX * nD))
+    Pt3[:, pd] = Pt
+    Pt3 = Pt3.reshape(k, nX, nD)               # [h, x, u]
+    Z1 = np.einsum("hxu,ylx->huyl", Pt3, T["T4"], optimize=True)
+    Z2 = np.einsum("huyl,lurd->hyrd", Z1, a, optimize=True)
+    T4n = np.einsum("hyrd,ydk->krh", Z2, P3, optimize=True)
     C4T3 = np.einsum("pq,zDp->zqD", T["C4"], T["T3"]).reshape(nX, nX * nD)[:, pd]
     C4n = C4T3 @ Pt.T
     norms = [np.linalg.norm(C1n), np.linalg.norm(T4n), np.linalg.norm(C4n)]
