@@ -1,15 +1,21 @@
 #!/usr/bin/env python3
-"""Throughput of one U(1)-symmetric CTM left move on one MI355X.
+"""Throughput of the block-sparse contractions of symmetric CTM on one MI355X.
 
-A step is one whole move on resident synthetic tensors: the four enlarged
-corners C.T.T.a, the halves, the FP64 QR/SVD projectors with truncation to
-chi, the renormalised C1', T4', C4' and their FP64 normalisation.  Default
-workload: D = 6 (virtual charges {-2:1, 0:4, +2:1}), chi = 64 (charges
-{-4:4,-2:16,0:24,2:16,4:4}), sector GEMMs in FP32.
+Default (no flags): the batched workload, 64 independent U(1) enlarged
+corners C.T.T.a with D drawn from {4..8} and chi from {32..160}: a step is
+the three contraction steps of all 64 corners, each step one grouped
+bf16x3 GEMM launch (with its gather), replayed from a HIP graph, on
+resident synthetic tensors.  `value` = useful flops (sum over matched block
+pairs of 2 m n k, a split product counted once) per second.  Beside it: the
+same corners as per-contraction FP32 launches (the speedup), the dominant
+GEMM's fraction of the bf16x3 MFMA ceiling (BF16 peak / 3), the FP64 oracle
+timed on a bounded sample of the corners (`cpu_baseline`), and the full CTM
+left move of the D = 6, chi = 64 workload in FP32 (`move_D6_chi64_f32`).
 
-Prints one JSON line.  `value` = useful GEMM flops of the move (sum over
-matched block pairs of 2 m n k in the corners, halves and renormalisation)
-divided by the wall time of the whole move.
+`--config N` times one workload on its own: 1, 2, 4, 6 a full left move
+(the four corners, halves, FP64 projectors with truncation to chi,
+renormalised and normalised C1', T4', C4'), 3 the SU(2) move, 5 the batched
+corners.  Prints one JSON line.
 """
 import argparse
 import hashlib
@@ -21,7 +27,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "bf16x3": 2516.6 / 3}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6, "bf16x3": 2516.6 / 3, "bf16x6": 2516.6 / 6}
+HEADLINE_METRIC = "useful GFLOP/s per CTM move + % MFMA peak; bf16x3 batched vs FP32 per-block"
 HBM_PEAK_GBS = 8000.0
 
 
@@ -64,7 +71,8 @@ def traffic_for(kernel_name, workload):
     rec = json.load(open(path))
     if rec.get("sources_sha256") != sources_sha256() or rec.get("workload") != workload:
         return None
-    k = rec.get("kernels", {}).get(kernel_name)
+    # batched launches carry a ",batched" suffix in libsymten's own timing
+    k = rec.get("kernels", {}).get(kernel_name.replace(",batched", ""))
     return None if k is None else k.get("bytes_per_launch")
 
 
@@ -82,9 +90,11 @@ def profile_name(rocprof_name):
     if fam == "gemm_f32_kernel":
         return "gemm_f32_kernel<%sx%sx%s,f32>" % t.groups()
     if fam == "gemm_bf16_kernel":
-        return "gemm_bf16_kernel<%sx%sx%s,%s>" % (t.groups() + ("bf16x3" if last in ("1", "true") else "bf16",))
+        # the last template argument is the number of bf16 planes
+        kind = {"1": "bf16", "2": "bf16x3", "3": "bf16x6"}.get(last, last)
+        return "gemm_bf16_kernel<%sx%sx%s,%s>" % (t.groups() + (kind,))
     src = "f64" if "double" in args else "f32"
-    dst = {"0": "f32", "1": "f64", "2": "bf16", "3": "bf16x2", "4": "acc"}.get(last, last)
+    dst = {"0": "f32", "1": "f64", "2": "bf16", "3": "bf16x2", "4": "acc", "5": "bf16x3"}.get(last, last)
     return "copy_kernel<%s,%s>" % (src, dst)
 
 
@@ -200,6 +210,58 @@ def build_corner_inputs(cfgd, key, dtype, st, draw, TENSOR_INDEX):
     return T
 
 
+def cpu_baseline_corners(c5, draws):
+    """The FP64 dense oracle timed on the host on the corners of the batched
+    workload (the oracle as it stands, BLAS threads = host cores): corners in
+    draw order until about CPU_SAMPLE_SECONDS of work.  The oracle builds all
+    four enlarged corners of a draw, so the sample counts the useful flops of
+    all four."""
+    from oracle import u1
+    from synth import draw, TENSOR_INDEX, SITE_AND_ENV
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    dt, fl, done = 0.0, 0, []
+    for b, d in enumerate(draws):
+        if dt >= CPU_SAMPLE_SECONDS:
+            break
+        w = u1.Workload(c5["phys"], d["virt"], d["chi"], c5["flux"])
+        vals = {n: draw((c5["seed"], b, TENSOR_INDEX[n]), w.nnz_of(n)) for n in SITE_AND_ENV}
+        t0 = time.perf_counter()
+        T = w.dense_tensors(vals)
+        a, _ = u1.double_layer(T["A"], w.A_legs)
+        u1.enlarged_corners(w, T, a)
+        dt += time.perf_counter() - t0
+        fl += sum(s["flops"] for k in (1, 2, 3, 4) for s in u1.corner_tables(w, k))
+        done.append((d["D"], d["chi_total"]))
+    return {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"the four enlarged corners of the first {len(done)} draws of the batched workload "
+                      f"(D, chi) = {done} (dense FP64, {dt:.1f} s in all)",
+            "seconds": dt, "draws": len(done)}
+
+
+def roofline_of(k, steps, prec=None, workload=None):
+    """Roofline entry of one kernel's libsymten timing record: a GEMM against
+    its precision's MFMA peak (useful flops), a gather against HBM
+    (algorithmic bytes), both per launch over the launch's average time."""
+    avg = k["ms"] / k["launches"]
+    if k["name"].startswith("gemm"):
+        kp = prec or next(x for x in ("bf16x6", "bf16x3", "bf16", "f64", "f32") if x in k["name"])
+        ach = k["useful_flops"] / k["launches"] / (avg * 1e-3) / 1e12
+        r = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[kp], "unit": "TFLOP/s",
+             "frac": ach / PEAK_TFLOPS[kp]}
+    else:
+        ach = k["bytes"] / k["launches"] / (avg * 1e-3) / 1e9
+        r = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+    r.update({"traffic": traffic_for(k["name"], workload) if workload else None, "kernel": k["name"],
+              "avg_launch_ms": avg, "launches_per_step": k["launches"] / steps,
+              "algorithmic_bytes_per_launch": k["bytes"] / k["launches"],
+              "useful_flops_per_launch": k["useful_flops"] / k["launches"]})
+    return r
+
+
 def bench_batched(args):
     """64 independent corner contractions: one grouped launch per step in
     bf16x3 (HIP graph) against per-contraction FP32 launches."""
@@ -208,6 +270,8 @@ def bench_batched(args):
     from synth import config, draw, batched_draws, TENSOR_INDEX
 
     c5 = config(5)
+    prec = args.prec or "bf16x3"
+    use_recorded_tiles(c5["name"])
     draws = batched_draws(c5["seed"], c5["batch"], c5["D_choices"], c5["chi_range"])
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
@@ -216,8 +280,7 @@ def bench_batched(args):
     Cs, T1s, T4s, As = ([x[k] for x in ins] for k in ("C1", "T1", "T4", "a"))
 
     def run_batched():
-        return st.enlarged_corners_batched(Cs, T1s, T4s, As, prec=args.prec or "bf16x3", use_graph=True,
-                                           stream=stream)
+        return st.enlarged_corners_batched(Cs, T1s, T4s, As, prec=prec, use_graph=True, stream=stream)
 
     def run_single():
         fl = 0
@@ -237,43 +300,40 @@ def bench_batched(args):
         return (time.perf_counter() - t0) * 1e3 / steps, r
 
     ms_b, (outs, info) = timed(run_batched, args.steps)
+    del outs
     ms_s, fl_s = timed(run_single, max(1, args.steps // 2))
     flops = info["useful_flops"]
-    # per-kernel durations: the same batched launches run eagerly (a graph
-    # replay carries no per-launch events)
+    # per-kernel durations: the same batched launches run eagerly, each
+    # bracketed by HIP events on its stream (a graph replay carries no
+    # per-launch events)
     st.profile_begin()
     for _ in range(args.steps):
-        st.enlarged_corners_batched(Cs, T1s, T4s, As, prec=args.prec or "bf16x3", use_graph=False, stream=stream)
+        st.enlarged_corners_batched(Cs, T1s, T4s, As, prec=prec, use_graph=False, stream=stream)
     torch.cuda.synchronize()
     kst = st.profile_end()
-    prec = args.prec or "bf16x3"
-    dom = max(kst, key=lambda k: k["ms"]) if kst else None
-    roof = None
-    if dom is not None:
-        avg = dom["ms"] / dom["launches"]
-        if dom["name"].startswith("gemm"):
-            ach = dom["useful_flops"] / dom["launches"] / (avg * 1e-3) / 1e12
-            roof = {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                    "frac": ach / PEAK_TFLOPS[prec]}
-        else:
-            ach = dom["bytes"] / dom["launches"] / (avg * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS}
-        roof.update({"traffic": traffic_for(dom["name"], c5["name"]), "kernel": dom["name"], "avg_launch_ms": avg,
-                     "launches_per_step": dom["launches"] / args.steps})
+    gemms = [k for k in kst if k["name"].startswith("gemm")]
+    gathers = [k for k in kst if k["name"].startswith("copy")]
+    dom = max(gemms, key=lambda k: k["ms"]) if gemms else None
+    value = flops / (ms_b * 1e-3) / 1e9
     out = {
-        "metric": "useful GFLOP/s of 64 batched enlarged corners (bf16x3, one grouped launch per step, HIP graph)",
-        "value": flops / (ms_b * 1e-3) / 1e9, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "metric": HEADLINE_METRIC,
+        "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": args.prec or "bf16x3", "data": "synthetic (seeded Gaussian blocks)",
-        "config": {"workload": c5["name"], "batch": c5["batch"], "D": [d["D"] for d in draws],
-                   "chi": [d["chi_total"] for d in draws]},
-        "roofline": roof,
-        "useful_flops": flops, "per_contraction_f32": {"ms": ms_s, "gflops": fl_s / (ms_s * 1e-3) / 1e9},
+        "vs_baseline": None, "dtype": prec, "data": "synthetic (seeded Gaussian blocks)",
+        "config": {"workload": c5["name"], "what": c5["what"] + ": three grouped steps, HIP graph",
+                   "batch": c5["batch"], "D": [d["D"] for d in draws], "chi": [d["chi_total"] for d in draws]},
+        "roofline": roofline_of(dom, args.steps, prec, c5["name"]) if dom else None,
+        "step_mfma_frac": value / 1e3 / PEAK_TFLOPS[prec],
+        "useful_flops": flops,
+        "per_contraction_f32": {"ms": ms_s, "gflops": fl_s / (ms_s * 1e-3) / 1e9,
+                                "step_mfma_frac": fl_s / (ms_s * 1e-3) / 1e12 / PEAK_TFLOPS["f32"]},
         "speedup_vs_per_contraction_f32": ms_s / ms_b,
+        "gather": roofline_of(max(gathers, key=lambda k: k["ms"]), args.steps, None, c5["name"]) if gathers else None,
         "kernels": sorted(kst, key=lambda k: -k["ms"])[:6],
     }
-    print(json.dumps(out))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_corners(c5, draws)
+    return out
 
 
 def bench_su2(args):
@@ -583,9 +643,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5, 6])
-    ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16", "bf16x3"])
+    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5, 6])
+    ap.add_argument("--prec", default=None, choices=[None, "f64", "f32", "bf16", "bf16x3", "bf16x6"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-move", action="store_true",
+                    help="config 5: leave out the D = 6, chi = 64 left move reported beside the batched corners")
     ap.add_argument("--cell", action="store_true", help="time the left move of a 2 x 2 unit cell")
     ap.add_argument("--unit", action="store_true",
                     help="time a CTM re-initialisation of a 2 x 2 cell (8 steps per direction, D=3, chi=40)")
@@ -605,19 +667,32 @@ def main():
     if args.unit:
         bench_unit(args)
         return
-    if args.config == 5:
-        bench_batched(args)
-        return
     if args.config == 3:
         bench_su2(args)
         return
 
+    if args.config == 5:
+        out = bench_batched(args)
+        if not args.no_move:
+            mv = bench_move(args, 2, "f32", min(args.steps, 10), min(args.warmup, 2), with_cpu=False)
+            out["move_D6_chi64_f32"] = {k: mv[k] for k in ("value", "unit", "ms_per_step", "steps", "config",
+                                                          "roofline", "useful_flops_per_move", "gemm_phase_gflops",
+                                                          "phase_ms", "kept", "trunc_err")}
+        print(json.dumps(out))
+        return
+    print(json.dumps(bench_move(args, args.config, args.prec, args.steps, args.warmup,
+                                with_cpu=not args.no_cpu_baseline)))
+
+
+def bench_move(args, config_no, prec, steps, warmup, with_cpu):
+    """One full left move of workload `config_no` per step (the environment
+    reset to the same C1, C4, T4 before every move)."""
     import torch
     import paper_1808_10804_amd as st
     from synth import config, draw, TENSOR_INDEX
 
-    cfgd = config(args.config)
-    prec = args.prec or {"sweep": "f32"}.get(cfgd["prec"], cfgd["prec"])
+    cfgd = config(config_no)
+    prec = prec or {"sweep": "f32"}.get(cfgd["prec"], cfgd["prec"])
     use_recorded_tiles(cfgd["name"])
     dtype = "f64" if prec == "f64" else "f32"
     chi = cfgd["chi_target"]
@@ -633,20 +708,20 @@ def main():
         env.set(7, T["T4"])
         return env.move(T["a"], chi, prec=prec, stats=stats, stream=stream)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_per_step = (t1 - t0) * 1e3 / steps
 
     # per-kernel durations: the same steps again with HIP events around
     # every launch on the launch stream
     st.profile_begin()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     kstats = st.profile_end()
@@ -655,48 +730,24 @@ def main():
     flops = stats["flops_corners"] + stats["flops_halves"] + stats["flops_renorm"]
     value = flops / (ms_per_step * 1e-3) / 1e9
     gemm_ms = stats["ms_corners"] + stats["ms_halves"] + stats["ms_renorm"]
-
     dom = max(kstats, key=lambda k: k["ms"]) if kstats else None
-    roof = None
-    if dom:
-        avg_ms = dom["ms"] / dom["launches"]
-        is_gemm = dom["name"].startswith("gemm")
-        if is_gemm:
-            kprec = "f64" if "f64" in dom["name"] else ("bf16x3" if "bf16x3" in dom["name"]
-                                                       else ("bf16" if "bf16" in dom["name"] else "f32"))
-            achieved = dom["useful_flops"] / dom["launches"] / (avg_ms * 1e-3) / 1e12
-            peak = PEAK_TFLOPS[kprec]
-            roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                    "frac": achieved / peak}
-        else:
-            achieved = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS}
-        tb = traffic_for(dom["name"], cfgd["name"])
-        roof["traffic"] = tb
-        roof["kernel"] = dom["name"]
-        roof["launches_per_step"] = dom["launches"] / args.steps
-        roof["avg_launch_ms"] = avg_ms
-        roof["algorithmic_bytes_per_launch"] = dom["bytes"] / dom["launches"]
-        roof["useful_flops_per_launch"] = dom["useful_flops"] / dom["launches"]
-
     out = {
         "metric": f"useful GFLOP/s per CTM move ({cfgd['group'].replace('U1', 'U(1)')} left move, sector GEMMs on MFMA)",
-        "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": value, "unit": "GFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": prec, "data": "synthetic (seeded Gaussian blocks)",
         "config": {"workload": cfgd["name"], "what": cfgd["what"], "D_virtual": cfgd["virt"],
                    "chi": chi, "chi_sectors": cfgd["chi"], "parallelism": "single GPU"},
-        "roofline": roof,
+        "roofline": roofline_of(dom, steps, None, cfgd["name"]) if dom else None,
         "useful_flops_per_move": flops,
         "gemm_phase_gflops": flops / (gemm_ms * 1e-3) / 1e9 if gemm_ms > 0 else None,
         "phase_ms": {k: stats[k] for k in ("ms_corners", "ms_halves", "ms_proj", "ms_renorm", "ms_total")},
         "kept": stats["kept"], "trunc_err": stats["trunc_err"],
         "kernels": sorted(kstats, key=lambda k: -k["ms"])[:6],
     }
-    if not args.no_cpu_baseline:
+    if with_cpu:
         out["cpu_baseline"] = cpu_baseline(cfgd, flops)
-    print(json.dumps(out))
+    return out
 
 
 if __name__ == "__main__":

@@ -46,6 +46,12 @@
  *  - Every call that takes a `stream` enqueues its device work on that HIP
  *    stream (NULL = the default stream) and returns without waiting, unless
  *    documented otherwise.  Calls that overlap on one tensor race.
+ *  - Work buffers of the library's own pool that a call releases (panels,
+ *    intermediates, freed tensors) go to a later call on another stream
+ *    only behind an event recorded on the releasing stream, so calls on
+ *    different streams never share a buffer in flight.  A tensor made on one
+ *    stream and read on another is ordered by the caller, as any
+ *    stream-ordered data.
  *  - Every function returns 0 (SYMTEN_OK) or a negative status; the message
  *    of the last failure on the calling thread is symten_last_error().  No
  *    C++ exception crosses this interface.
@@ -90,11 +96,18 @@ extern "C" {
  * BF16   - operands rounded to bf16, FP32 accumulation (storage F32)
  * BF16X3 - each FP32 operand split x = hi + lo (hi = bf16(x),
  *          lo = bf16(x - hi)); product hi*hi + hi*lo + lo*hi on bf16 MFMA
- *          with FP32 accumulation (storage F32)                           */
+ *          with FP32 accumulation (storage F32); about 2^-16 relative per
+ *          product, which meets 1e-5 on corners but not on a whole move
+ * BF16X6 - each FP32 operand split x = hi + mid + lo (mid = bf16(x - hi),
+ *          lo = bf16(x - hi - mid), an exact split of the FP32 value);
+ *          product hi*hi + hi*mid + mid*hi + mid*mid + hi*lo + lo*hi on
+ *          bf16 MFMA with FP32 accumulation (storage F32): FP32-level
+ *          accuracy at six bf16 products                                    */
 #define SYMTEN_PREC_F64     0
 #define SYMTEN_PREC_F32     1
 #define SYMTEN_PREC_BF16    2
 #define SYMTEN_PREC_BF16X3  3
+#define SYMTEN_PREC_BF16X6  4
 
 #define SYMTEN_MAX_RANK 8
 
@@ -273,8 +286,12 @@ int symten_enlarged_corner_single_layer(symten_t* out, int which, symten_t C, sy
 /* Batched corners: n independent corner-1 contractions ((C T1) T4) a, each
  * step of all n fused into one grouped-GEMM launch.  use_graph != 0 records
  * the whole batch into a HIP graph on first use and replays it afterwards
- * (inputs must keep their structures and buffers).  out[i] receive the
- * corners; info (may be NULL) the summed statistics.  U(1) and Z2.          */
+ * (a change of input buffers drains the device and records it again).
+ * out[i] receive the corners, views of one new buffer per call: results of
+ * earlier calls stay valid.  The plans, panels, intermediate results and
+ * the graph are cached per (n, prec, leg structures) and shared by the
+ * calls with that key, so such calls must not overlap on different streams.
+ * info (may be NULL) receives the summed statistics.  U(1) and Z2.          */
 int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* C,
                                     const symten_t* Ta, const symten_t* Tb,
                                     const symten_t* a, int prec, int use_graph,
@@ -299,6 +316,8 @@ typedef struct {
                                         SU(2) value counted 2J+1 times     */
     double gap;                      /* (s_last_kept - s_first_dropped)/s_max */
     double s_max;
+    double cutoff;                   /* relative truncation floor: values
+                                        <= cutoff * s_max were dropped      */
     int64_t flops_corners, flops_halves, flops_renorm; /* useful flops     */
     int64_t flops_proj;              /* FP64 flops of Y = H_u^T H_d        */
     double ms_corners, ms_halves, ms_proj, ms_renorm, ms_total;
@@ -328,8 +347,13 @@ int ctm_env_get(ctm_env_t env, int k, symten_t* t);
  * sector of the left cut the singular triplets of M = R_u R_d^T (QR
  * H_u^T = Q_u R_u, H_d^T = Q_d R_d; taken from Y = H_u^T H_d, which has the
  * same singular values, with V_Y = Q_d V and U_Y = Q_u U), global truncation
- * to chi states (ties: sector, then index ascending; s <= 1e-14 s_max
- * dropped), projectors P = R_d^T V S^-1/2 = H_d V_Y S^-1/2 and
+ * to chi states (ties: sector, then index ascending; s <= c s_max dropped,
+ * c = 1e-14 for PREC_F64; the other precisions take s from the Gram matrix
+ * Y Y^T and drop s <= sqrt(N eps) s_max, eps = 2^-52 and N the order of the
+ * largest block, below which that route does not resolve s; a degenerate
+ * set is never split: values within a relative 1e-8 (F64), 1e-5 (F32,
+ * BF16X6) or 1e-4 (BF16X3, BF16) of the last kept one are dropped with it),
+ * projectors P = R_d^T V S^-1/2 = H_d V_Y S^-1/2 and
  * P~ = S^-1/2 U^T R_u = S^-1/2 U_Y^T H_u^T (largest-magnitude entry of every
  * P~ row made positive), then C1' = (C1 T1) P, T4' = P~ (T4 a) P,
  * C4' = P~ (C4 T3), each scaled to unit Frobenius norm in FP64.  `chi`

@@ -10,7 +10,7 @@ ERRORS = {-1: "E_INVAL", -2: "E_LEGS", -3: "E_SYM", -4: "E_NOMEM", -5: "E_HIP",
           -6: "E_LINALG", -7: "E_CAPACITY", -8: "E_UNSUPPORTED", -9: "E_NODEVICE"}
 U1, SU2, Z2 = 1, 2, 3
 F64, F32 = 0, 1
-PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3, "bf16x6": 4}
 MAX_SECTORS = 64
 
 
@@ -42,7 +42,7 @@ class MoveStats(C.Structure):
     _fields_ = [("nsec", C.c_int), ("charge", C.c_int * MAX_SECTORS), ("kept", C.c_int * MAX_SECTORS),
                 ("n_sv_sectors", C.c_int), ("sv_charge", C.c_int * MAX_SECTORS),
                 ("sv_count", C.c_int * MAX_SECTORS),
-                ("trunc_err", C.c_double), ("gap", C.c_double), ("s_max", C.c_double),
+                ("trunc_err", C.c_double), ("gap", C.c_double), ("s_max", C.c_double), ("cutoff", C.c_double),
                 ("flops_corners", C.c_int64), ("flops_halves", C.c_int64), ("flops_renorm", C.c_int64),
                 ("flops_proj", C.c_int64),
                 ("ms_corners", C.c_double), ("ms_halves", C.c_double), ("ms_proj", C.c_double),

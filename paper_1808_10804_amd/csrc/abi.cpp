@@ -28,8 +28,6 @@ struct symten_tensor {
 namespace symten {
 
 void upload_sync(BufferPtr& buf, const void* host, size_t bytes);
-void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems);
-void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw);
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix);
 void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles);
 void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
@@ -52,6 +50,7 @@ struct PadArgs {
 };
 void launch_pad_blocks(const PadArgs& a, double* dst, hipStream_t st);
 void launch_jw_build_batched(const double* M, int N, int count, double* J, hipStream_t st);
+void launch_nonfinite_guard(double* X, int64_t n, int* flag, hipStream_t st);
 
 namespace {
 thread_local std::string g_err;
@@ -63,6 +62,25 @@ int set_err(int code, const std::string& m) {
 
 template <class F>
 int guard(F&& f) {
+    try {
+        f();
+        return SYMTEN_OK;
+    } catch (const Error& e) {
+        return set_err(e.code, e.what());
+    } catch (const std::bad_alloc&) {
+        return set_err(SYMTEN_E_NOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return set_err(SYMTEN_E_INVAL, e.what());
+    } catch (...) {
+        return set_err(SYMTEN_E_INVAL, "unknown error");
+    }
+}
+
+// guard() for entry points that enqueue on `stream`: the library's buffers
+// taken and released during the call are ordered on that stream.
+template <class F>
+int guard_on(void* stream, F&& f) {
+    StreamScope scope((hipStream_t)stream);
     try {
         f();
         return SYMTEN_OK;
@@ -382,6 +400,18 @@ struct ctm_env {
     hipStream_t aux[kAux] = {};
     rocblas_handle rb_aux[kAux] = {};
     hipEvent_t ev_start = nullptr, ev_done[kAux] = {};
+    // relative spread within which singular values count as one degenerate
+    // set at the cut, about ten times the per-value error of the move's
+    // precision (set by every move)
+    double degen_tol = 1e-8;
+    static double degenerate_tol(int prec) {
+        switch (prec) {
+            case SYMTEN_PREC_F64: return 1e-8;
+            case SYMTEN_PREC_F32:
+            case SYMTEN_PREC_BF16X6: return 1e-5;
+            default: return 1e-4;   // bf16x3, bf16
+        }
+    }
     ~ctm_env() {
         if (rb) rocblas_destroy_handle(rb);
         for (int i = 0; i < kAux; ++i) {
@@ -431,6 +461,18 @@ __global__ void eig_to_svd_kernel(const double* __restrict__ Z, int NE, const do
         for (int r = threadIdx.x; r < rd; r += blockDim.x)
             V[r + (int64_t)j * rd] = f * Z[voff + r + (int64_t)idx * NE];
 }
+// Non-finite entries of X (NaN, Inf) are replaced by 0 and reported in
+// *flag, so that the eigensolver only ever sees finite matrices; the move
+// then fails after the read-back (SYMTEN_E_LINALG).
+__global__ void nonfinite_guard_kernel(double* __restrict__ X, int64_t n, int* __restrict__ flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = X[i];
+        if (!isfinite(v)) {
+            X[i] = 0.0;
+            *flag = 1;
+        }
+    }
+}
 // Zero-padded FP64 copies of col-major blocks: dst[j] is N x N.
 __global__ void pad_blocks_kernel(PadArgs a, double* __restrict__ dst) {
     const int j = blockIdx.y;
@@ -460,6 +502,11 @@ __global__ void jw_build_batched_kernel(const double* __restrict__ M, int N, dou
     }
 }
 static int g1d(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+void launch_nonfinite_guard(double* X, int64_t n, int* flag, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(nonfinite_guard_kernel, dim3(g1d(n)), dim3(256), 0, st, X, n, flag);
+    HIPCHK(hipGetLastError());
+}
 void launch_scale_cols(double* X, int ld, int rows, int cols, const double* sv, double e, hipStream_t st) {
     if ((int64_t)rows * cols == 0) return;
     hipLaunchKernelGGL(scale_cols_kernel, dim3(g1d((int64_t)rows * cols)), dim3(256), 0, st, X, ld, rows, cols, sv, e);
@@ -552,6 +599,7 @@ struct ProjOut {
     BufferPtr P, Pt;             // FP64, column-major per sector at CutSector::pbase
     int64_t ptot = 0;
     double tot2 = 0, disc2 = 0, smax = 0, gap = 0;
+    double cutoff = 0;           // relative truncation floor used (s <= cutoff s_max dropped)
     int64_t flops = 0;
 };
 
@@ -577,7 +625,8 @@ struct ProjOut {
 // Truncation (global over sectors): values in descending order (ties: key
 // ascending, then index), each kept while the kept states, counted with the
 // sector's weight, stay within chi, stopping at the first that does not fit
-// (a multiplet is never split) and at values <= 1e-14 s_max.  P~ rows get
+// (a multiplet is never split) and at values <= cutoff s_max (1e-14 on the
+// FP64 route, sqrt(N eps) on the Gram route).  P~ rows get
 // the sign gauge (largest-magnitude entry positive).  One host
 // synchronisation (the singular values).
 
@@ -586,6 +635,7 @@ struct ProjWork {
     int ru = 0, rd = 0, ld = 0;
     double *HuT = nullptr, *HdT = nullptr, *Y = nullptr;
     int* info = nullptr;
+    int* nonfinite = nullptr;    // set when Y held NaN or Inf (zeroed before the solve)
     BufferPtr U, V, S;
 };
 struct ProjPending {
@@ -630,6 +680,9 @@ void solve_class(const std::vector<CutSector>& secs, std::vector<ProjWork>& w, c
     BufferPtr wb = device_alloc(8 * (size_t)NE * B);
     BufferPtr Eb = device_alloc(8 * (size_t)NE * B);
     BufferPtr ib = device_alloc(8 * (size_t)B);
+    BufferPtr fb = device_alloc(4);
+    launch_fill_zero(fb->ptr, 4, cs);
+    launch_nonfinite_guard((double*)Mb->ptr, (int64_t)N2 * B, (int*)fb->ptr, cs);
     if (f64)
         launch_jw_build_batched((const double*)Mb->ptr, N, B, (double*)Zb->ptr, cs);
     else
@@ -650,13 +703,14 @@ void solve_class(const std::vector<CutSector>& secs, std::vector<ProjWork>& w, c
         x.Y = (double*)Mb->ptr + i * N2;
         x.ld = N;
         x.info = (int*)ib->ptr + i;
+        x.nonfinite = (int*)fb->ptr;
         x.S = device_alloc(8 * std::max(1, b.mn));
         x.U = device_alloc(8 * std::max<size_t>(1, (size_t)x.ru * b.mn));
         x.V = device_alloc(8 * std::max<size_t>(1, (size_t)x.rd * b.mn));
         launch_eig_to_svd((const double*)Zb->ptr + i * NE2, NE, (const double*)wb->ptr + (size_t)i * NE, N,
                           b.mn, x.ru, x.rd, f64, (double*)x.S->ptr, (double*)x.U->ptr, (double*)x.V->ptr, cs);
     }
-    for (auto& x : {Hb, Mb, Zb, wb, Eb, ib}) keep.push_back(x);
+    for (auto& x : {Hb, Mb, Zb, wb, Eb, ib, fb}) keep.push_back(x);
 }
 
 // Enqueues the eigensolves of every sector of the given cuts (no host
@@ -713,6 +767,7 @@ std::vector<ProjPending> issue_solves(ctm_env* env, const std::vector<std::vecto
         }
     auto run_slot = [&](int slot) {
         hipStream_t cs = slot == 0 ? s : env->aux[slot - 1];
+        StreamScope scope(cs);   // work buffers of this slot are used on cs
         rocblas_handle rh = slot == 0 ? env->rb : env->rb_aux[slot - 1];
         for (auto& k : classes)
             if (k.slot == slot) solve_class(*cuts[k.cut], pend[k.cut].w, k.cls, k.N, f64, cs, rh, k.keep);
@@ -779,13 +834,16 @@ ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPendin
         int tot = 0;
         for (auto& c : secs) { sv_off.push_back(tot); tot += c.mn; }
         out.sv.resize(tot);
-        std::vector<int> infos(secs.size());
+        std::vector<int> infos(secs.size()), bad(secs.size());
         for (size_t i = 0; i < secs.size(); ++i) {
             if (secs[i].mn)
                 HIPCHK(hipMemcpyAsync(out.sv.data() + sv_off[i], pend.w[i].S->ptr, 8 * secs[i].mn, hipMemcpyDeviceToHost, s));
             HIPCHK(hipMemcpyAsync(&infos[i], pend.w[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&bad[i], pend.w[i].nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
         }
         HIPCHK(hipStreamSynchronize(s));
+        for (size_t i = 0; i < secs.size(); ++i)
+            if (bad[i]) fail(SYMTEN_E_LINALG, "ctm_move: NaN or Inf in the halves of the cut");
         for (size_t i = 0; i < secs.size(); ++i)
             if (infos[i] != 0) fail(SYMTEN_E_LINALG, "rocsolver_dsyevd did not converge");
         for (double v : out.sv)
@@ -802,15 +860,27 @@ ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPendin
         return x.j < y.j;
     });
     out.smax = all.empty() ? 0.0 : all[0].s;
+    // values at or below the route's noise floor are dropped: the FP64
+    // (Jordan-Wielandt) route keeps the reading's 1e-14 s_max; the Gram route
+    // takes s = sqrt(eig(Y Y^T)), whose eigenvalues carry an absolute error of
+    // about N eps s_max^2 (N the order of the largest solve), so singular
+    // values below sqrt(N eps) s_max are not resolved there
+    double cutoff = 1e-14;
+    if (!f64) {
+        int nmax = 1;
+        for (auto& c : secs) nmax = std::max(nmax, std::max(c.mu, c.md));
+        cutoff = std::sqrt(nmax * 0x1p-52);
+    }
+    out.cutoff = cutoff;
     int nkeep = 0, states = 0;
-    while (nkeep < (int)all.size() && all[nkeep].s > 1e-14 * out.smax &&
+    while (nkeep < (int)all.size() && all[nkeep].s > cutoff * out.smax &&
            states + secs[all[nkeep].sec].weight <= chi) {
         states += secs[all[nkeep].sec].weight;
         ++nkeep;
     }
     // a set of (near-)degenerate values is never split at the cut: values
-    // within 1e-8 (relative) of the last kept one are dropped with it
-    while (nkeep > 1 && nkeep < (int)all.size() && all[nkeep].s >= (1.0 - 1e-8) * all[nkeep - 1].s) {
+    // within env->degen_tol (relative) of the last kept one are dropped with it
+    while (nkeep > 1 && nkeep < (int)all.size() && all[nkeep].s >= (1.0 - env->degen_tol) * all[nkeep - 1].s) {
         states -= secs[all[nkeep - 1].sec].weight;
         --nkeep;
     }
@@ -879,6 +949,7 @@ void fill_cut_stats(ctm_move_stats* st, const std::vector<CutSector>& secs, cons
     for (int i = 0; i < st->n_sv_sectors; ++i) { st->sv_charge[i] = secs[i].key; st->sv_count[i] = secs[i].mn; }
     st->trunc_err = po.tot2 > 0 ? po.disc2 / po.tot2 : 0.0;
     st->s_max = po.smax;
+    st->cutoff = po.cutoff;
     st->gap = po.gap;
     st->flops_proj = po.flops;
 }
@@ -1733,7 +1804,7 @@ const char* symten_last_error(void) { return g_err.c_str(); }
 int symten_version(void) { return 1; }
 
 int symten_sync(void* stream) {
-    return guard([&] { HIPCHK(hipStreamSynchronize(S(stream))); });
+    return guard_on(stream, [&] { HIPCHK(hipStreamSynchronize(S(stream))); });
 }
 
 int symten_create_meta(symten_t* out, const symten_desc* d) {
@@ -1744,7 +1815,7 @@ int symten_create_meta(symten_t* out, const symten_desc* d) {
 }
 
 int symten_create(symten_t* out, const symten_desc* d, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!out) fail(SYMTEN_E_INVAL, "null output");
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
@@ -1813,7 +1884,7 @@ int symten_block_tree(symten_t t, int64_t i, int* ntree, int* tree) {
     });
 }
 int symten_su2_to_u1(symten_t* out, symten_t in, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!out) fail(SYMTEN_E_INVAL, "null output");
         *out = wrap(su2_to_u1(T(in), S(stream)));
     });
@@ -1850,7 +1921,7 @@ int symten_device_ptr(symten_t t, void** ptr, int64_t* elems) {
 }
 
 int symten_upload(symten_t t, const double* values, int64_t n, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         Tensor& x = T(t);
         check_device_tensor(x, "upload");
         if (n != x.nnz()) fail(SYMTEN_E_INVAL, "upload: value count differs from nnz");
@@ -1880,7 +1951,7 @@ int symten_upload(symten_t t, const double* values, int64_t n, void* stream) {
 }
 
 int symten_download(symten_t t, double* values, int64_t n, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         Tensor& x = T(t);
         check_device_tensor(x, "download");
         if (n != x.nnz()) fail(SYMTEN_E_INVAL, "download: value count differs from nnz");
@@ -1917,7 +1988,7 @@ int symten_plan_info(symten_t A, symten_t B, int ncon, const int* legsA, const i
 
 int symten_contract(symten_t* out, symten_t A, symten_t B, int ncon, const int* legsA, const int* legsB,
                     const int* out_perm, int prec, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!out) fail(SYMTEN_E_INVAL, "null output");
         auto p = get_plan(T(A), T(B), ncon, legsA, legsB, out_perm, prec);
         *out = wrap(run_contraction(*p, T(A), T(B), S(stream)));
@@ -1925,7 +1996,7 @@ int symten_contract(symten_t* out, symten_t A, symten_t B, int ncon, const int* 
 }
 
 int symten_double_layer(symten_t* a_out, symten_t A, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!a_out) fail(SYMTEN_E_INVAL, "null output");
         *a_out = wrap(double_layer(T(A), S(stream)));
     });
@@ -1933,7 +2004,7 @@ int symten_double_layer(symten_t* a_out, symten_t A, void* stream) {
 
 int symten_enlarged_corner(symten_t* out, int which, symten_t C, symten_t Ta, symten_t Tb, symten_t a, int prec,
                            symten_plan_stats* info, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!out) fail(SYMTEN_E_INVAL, "null output");
         CornerResult r = corner(which, T(C), T(Ta), T(Tb), T(a), prec, S(stream));
         if (info) *info = r.info;
@@ -1943,7 +2014,7 @@ int symten_enlarged_corner(symten_t* out, int which, symten_t C, symten_t Ta, sy
 
 int symten_enlarged_corner_single_layer(symten_t* out, int which, symten_t C, symten_t Ta, symten_t Tb, symten_t A,
                                         int prec, symten_plan_stats* info, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!out) fail(SYMTEN_E_INVAL, "null output");
         CornerResult r = corner_single_layer(which, T(C), T(Ta), T(Tb), T(A), prec, S(stream));
         if (info) *info = r.info;
@@ -2031,7 +2102,7 @@ void build_step(BatchStep& B, const std::vector<const Tensor*>& As, const std::v
         if (B.plans[i]->prec != B.prec || (As[i]->dtype == SYMTEN_F64) != B.src_f64)
             fail(SYMTEN_E_INVAL, "batched corners: inputs differ in storage type");
     const int pl = panel_planes(B.prec);
-    if (B.prec == Prec::BF16X3) {   // lo planes follow the concatenated hi planes
+    if (pl > 1) {   // the lower planes follow the concatenated hi planes
         for (auto& t : tasks) t.lo_off = t.dst_buf == 2 * n ? ap : bp;
         for (auto& g : groups) {
             g.a_lo = ap;
@@ -2044,8 +2115,8 @@ void build_step(BatchStep& B, const std::vector<const Tensor*>& As, const std::v
         sizes[2 * n] = pl * ap;
         sizes[2 * n + 1] = pl * bp;
         sizes[2 * n + 2] = cp;
-        validate_tasks(tasks, sizes);
-        validate_groups(groups, sizes, panel_vw(B.prec));
+        validate_tasks(tasks, sizes, pl);
+        validate_groups(groups, sizes, panel_vw(B.prec), pl);
     }
     const size_t pe = panel_esize(B.prec) * pl;
     const size_t oe = B.src_f64 ? 8 : 4;
@@ -2095,18 +2166,16 @@ void run_step(BatchStep& B, hipStream_t s, bool tune = false) {
                    s, [&] { launch(cfg, (const TileWork*)B.tc.tiles[cfg]->ptr, B.tc.ntiles[cfg]); });
 }
 
-std::vector<TensorPtr> step_outputs(const BatchStep& B, int n) {
+// The n outputs of a step as views into one buffer laid out like B.out.
+std::vector<TensorPtr> step_outputs(const BatchStep& B, int n, const BufferPtr& buf) {
     std::vector<TensorPtr> outs(n);
-    const size_t es = B.src_f64 ? 8 : 4;
     for (int i = 0; i < n; ++i) {
         auto t = std::make_shared<Tensor>(*B.plans[i]->out_meta);
-        // a view into the step's shared output buffer
         for (auto& b : t->blocks) b.offset += B.c_base[i];
         t->elems = B.c_base[i] + B.plans[i]->out_elems;
-        t->buf = B.out;
+        t->buf = buf;
         t->meta_only = false;
         outs[i] = t;
-        (void)es;
     }
     return outs;
 }
@@ -2117,7 +2186,7 @@ extern "C" {
 int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, const symten_t* Tas,
                                     const symten_t* Tbs, const symten_t* as, int prec, int use_graph,
                                     symten_plan_stats* info, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (n <= 0 || !out || !Cs || !Tas || !Tbs || !as) fail(SYMTEN_E_INVAL, "batched corners: bad arguments");
         const hipStream_t s = S(stream);
         std::string key = std::to_string(n) + "|" + std::to_string(prec) + "|";
@@ -2150,27 +2219,28 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, co
             for (int i = 0; i < n; ++i)
                 st->step[0].plans.push_back(get_plan(*A1[i], *B1[i], 1, sp.l1a.data(), sp.l1b.data(), nullptr, prec));
             build_step(st->step[0], A1, B1, n);
-            st->outs[0] = step_outputs(st->step[0], n);
+            st->outs[0] = step_outputs(st->step[0], n, st->step[0].out);
             std::vector<const Tensor*> A2;
             for (int i = 0; i < n; ++i) {
                 A2.push_back(st->outs[0][i].get());
                 st->step[1].plans.push_back(get_plan(*A2[i], *B2[i], 1, sp.l2a.data(), sp.l2b.data(), nullptr, prec));
             }
             build_step(st->step[1], A2, B2, n);
-            st->outs[1] = step_outputs(st->step[1], n);
+            st->outs[1] = step_outputs(st->step[1], n, st->step[1].out);
             std::vector<const Tensor*> A3;
             for (int i = 0; i < n; ++i) {
                 A3.push_back(st->outs[1][i].get());
                 st->step[2].plans.push_back(get_plan(*A3[i], *B3[i], 2, sp.l3a.data(), sp.l3b.data(), nullptr, prec));
             }
             build_step(st->step[2], A3, B3, n);
-            st->outs[2] = step_outputs(st->step[2], n);
             std::lock_guard<std::mutex> lk(g_batch_mu);
             if (g_batch.size() > 16) g_batch.clear();
             g_batch[key] = st;
         }
         if (st->inputs != inputs) {
-            // (re)point the tables at the current input buffers
+            // (re)point the tables at the current input buffers; earlier calls
+            // on any stream may still read them, so the device is drained first
+            HIPCHK(hipDeviceSynchronize());
             std::vector<void*> c(n), t1(n), t4(n), a(n), o1(n), o2(n);
             const size_t es = st->step[0].src_f64 ? 8 : 4;
             for (int i = 0; i < n; ++i) {
@@ -2193,6 +2263,13 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, co
                 st->graph = nullptr;
             }
         }
+        // every call writes its corners into a buffer of its own (earlier
+        // results stay valid): the last step's output entry of the pointer
+        // table is set on s before the launches that read it
+        BatchStep& last = st->step[2];
+        BufferPtr result = device_alloc(std::max<int64_t>(last.out->bytes, 1));
+        launch_set_pointer((void**)last.ptrs->ptr, 2 * n + 2, result->ptr, s);
+        last.table[2 * n + 2] = result->ptr;
         bool tuned = true;
         for (int k = 0; k < 3; ++k) tuned = tuned && st->step[k].tc.cfg >= 0;
         if (!tuned) {
@@ -2225,7 +2302,8 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, co
             *info = {};
             for (int k = 0; k < 3; ++k) add_info(*info, st->step[k].info);
         }
-        for (int i = 0; i < n; ++i) out[i] = wrap(st->outs[2][i]);
+        std::vector<TensorPtr> res = step_outputs(last, n, result);
+        for (int i = 0; i < n; ++i) out[i] = wrap(res[i]);
     });
 }
 
@@ -2308,7 +2386,7 @@ int ctm_move_projectors(ctm_env_t env, symten_t* P, symten_t* Pt) {
 }
 
 int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_stats* st, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!env) fail(SYMTEN_E_INVAL, "null environment");
         if (dir < CTM_LEFT || dir > CTM_BOTTOM) fail(SYMTEN_E_INVAL, "ctm_move: direction must be 0..3");
         if (chi < 1) fail(SYMTEN_E_INVAL, "chi must be positive");
@@ -2317,6 +2395,7 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         if (a.rank() != 4) fail(SYMTEN_E_INVAL, "a must have rank 4");
         const hipStream_t s = S(stream);
         const bool f64 = prec == SYMTEN_PREC_F64;
+        env->degen_tol = ctm_env::degenerate_tol(prec);
         for (int i = 0; i < 4; ++i) {
             if ((env->C[i]->dtype == SYMTEN_F64) != f64 || (env->T[i]->dtype == SYMTEN_F64) != f64 ||
                 (a.dtype == SYMTEN_F64) != f64)
@@ -2419,11 +2498,12 @@ int ctm_cell_get(ctm_env_t env, int x, int y, int k, symten_t* t) {
 }
 
 int ctm_cell_move(ctm_env_t env, const symten_t* a_h, int dir, int chi, int prec, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!env || !a_h || env->Lx < 1) fail(SYMTEN_E_INVAL, "not a unit-cell environment");
         if (dir < CTM_LEFT || dir > CTM_BOTTOM) fail(SYMTEN_E_INVAL, "ctm_cell_move: direction must be 0..3");
         if (chi < 1) fail(SYMTEN_E_INVAL, "chi must be positive");
         const bool f64 = prec == SYMTEN_PREC_F64;
+        env->degen_tol = ctm_env::degenerate_tol(prec);
         int Lx = env->Lx, Ly = env->Ly;
         std::vector<TensorPtr> a;
         for (int i = 0; i < Lx * Ly; ++i) {
@@ -2477,7 +2557,7 @@ int ctm_cell_move(ctm_env_t env, const symten_t* a_h, int dir, int chi, int prec
 
 int ctm_cell_site_partition(ctm_env_t env, int x, int y, symten_t a, int block, double* kappa, double* z,
                             void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!env || !kappa || env->Lx < 1) fail(SYMTEN_E_INVAL, "not a unit-cell environment");
         if (x < 0 || y < 0 || x >= env->Lx || y >= env->Ly) fail(SYMTEN_E_INVAL, "bad site");
         if (block != 1 && block != 2) fail(SYMTEN_E_INVAL, "block must be 1 or 2");
@@ -2495,7 +2575,7 @@ int ctm_cell_site_partition(ctm_env_t env, int x, int y, symten_t a, int block, 
 }
 
 int ctm_site_partition(ctm_env_t env, symten_t a, int block, double* kappa, double* z, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!env || !kappa) fail(SYMTEN_E_INVAL, "null argument");
         if (block != 1 && block != 2) fail(SYMTEN_E_INVAL, "block must be 1 or 2");
         Tensor& at = T(a);
@@ -2510,7 +2590,7 @@ int ctm_site_partition(ctm_env_t env, symten_t a, int block, double* kappa, doub
 }
 
 int ctm_expectation(ctm_env_t env, symten_t a, int n, int m, const symten_t* sites, double* value, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!env || !sites || !value) fail(SYMTEN_E_INVAL, "null argument");
         if (n < 1 || m < 1 || n > 2 || m > 2) fail(SYMTEN_E_INVAL, "ctm_expectation: patch of 1 or 2 columns and rows");
         Tensor& at = T(a);
@@ -2532,7 +2612,7 @@ int ctm_expectation(ctm_env_t env, symten_t a, int n, int m, const symten_t* sit
 }
 
 int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e_v, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!env || !e_h || !e_v) fail(SYMTEN_E_INVAL, "null argument");
         Tensor& At = T(A);
         check_device_tensor(At, "ctm_heisenberg_bond_energy(A)");
@@ -2622,14 +2702,14 @@ int ctm_heisenberg_bond_energy(ctm_env_t env, symten_t A, double* e_h, double* e
 }
 
 int symten_double_layer_op(symten_t* b_out, symten_t A, const double* op, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!b_out || !op) fail(SYMTEN_E_INVAL, "null argument");
         *b_out = wrap(double_layer(T(A), S(stream), op));
     });
 }
 
 int ctm_run(ctm_env_t env, symten_t a, const ctm_run_opts* o, ctm_run_result* r, void* stream) {
-    return guard([&] {
+    return guard_on(stream, [&] {
         if (!env || !o || !r) fail(SYMTEN_E_INVAL, "null argument");
         if (o->chi < 1 || o->max_steps < 1 || (o->block != 1 && o->block != 2) || !(o->tol >= 0.0))
             fail(SYMTEN_E_INVAL, "ctm_run: bad options");

@@ -50,7 +50,23 @@ struct Block {
     int64_t size = 0;
 };
 
-// Caching device allocator (size-bucketed free lists, stream-ordered reuse).
+// Stream of the library call running on this thread (entry points that take
+// a stream set it for their duration; host threads of the library set their
+// own).  Outside a call it is unset.
+struct StreamScope {
+    hipStream_t prev;
+    bool prev_set;
+    explicit StreamScope(hipStream_t s);
+    ~StreamScope();
+};
+bool call_stream_set();
+hipStream_t call_stream();
+
+// Caching device allocator (size-bucketed free lists).  A released block
+// records an event on the stream that released it: the stream of the call
+// running on the releasing thread, else the stream the block was allocated
+// on.  Handing the block to a call on another stream makes that stream wait
+// for the event, so work queued on two streams never shares a block.
 struct DeviceBuffer;
 using BufferPtr = std::shared_ptr<DeviceBuffer>;
 BufferPtr device_alloc(size_t bytes);
@@ -58,6 +74,7 @@ struct DeviceBuffer {
     void* ptr = nullptr;
     size_t bytes = 0;
     size_t cap = 0;
+    hipStream_t stream = nullptr;   // stream of the call that allocated it
     // set when a caller-registered allocator made the buffer
     void (*user_free)(void* ptr, size_t bytes, void* ctx) = nullptr;
     void* user_ctx = nullptr;
@@ -120,7 +137,7 @@ struct CopyTask {
     int src_buf, dst_buf;
     int count;          // product of dims (< 2^31)
     double scale;       // multiplies the copied value (SU(2) recoupling scalar)
-    int64_t lo_off;     // split panels: the lo plane starts lo_off elements after the hi plane
+    int64_t lo_off;     // split panels: plane p starts p * lo_off elements after the hi plane
     int nextra;         // number of extra sources (0 .. kMaxExtraSrc)
     int pad_;
     int64_t xsrc_off[kMaxExtraSrc];
@@ -140,7 +157,7 @@ struct GemmGroup {
     int a_buf, b_buf, c_buf;
     int tiles_n;                   // tiles along N (for tile decoding)
     int pad_;
-    int64_t a_lo, b_lo;            // split panels: offset of the lo plane from the hi plane
+    int64_t a_lo, b_lo;            // split panels: plane p starts p * a_lo (p * b_lo) elements in
 };
 
 
@@ -152,22 +169,26 @@ struct TileWork {
 constexpr int kMaxBufs = 512;
 
 // Element type of a panel / buffer in a GEMM launch.
-enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X3 = 3 };
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2, BF16X3 = 3, BF16X6 = 4 };
 
 // Panel element type per precision: FP64 -> double, FP32 -> float,
-// BF16 -> one bf16 plane, BF16X3 -> bf16 hi and lo planes.
+// BF16 -> one bf16 plane, BF16X3 -> bf16 hi and lo planes, BF16X6 -> bf16
+// hi, mid and lo planes.  The planes of a panel buffer are consecutive
+// copies of its layout, plane p starting p * (plane stride) elements in.
 inline size_t panel_esize(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
-inline int panel_planes(Prec p) { return p == Prec::BF16X3 ? 2 : 1; }
+inline int panel_planes(Prec p) { return p == Prec::BF16X3 ? 2 : (p == Prec::BF16X6 ? 3 : 1); }
 inline int panel_vw(Prec p) { return p == Prec::F64 ? 2 : (p == Prec::F32 ? 4 : 8); }   // 16-byte vectors
 
 // Gather launch over a task list already on the device (at most 16 buffers).
 // dst_kind: 0 float, 1 double, 2 bf16, 3 bf16 hi/lo split, 4 accumulate
-// (dst += scale * src, source type).
+// (dst += scale * src, source type), 5 bf16 hi/mid/lo split.
 void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
                      const std::vector<void*>& ptrs, bool src_f64, int dst_kind, hipStream_t s);
 
 void launch_cast(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n, hipStream_t s);
 void launch_fill_zero(void* dst, int64_t bytes, hipStream_t s);
+// table[idx] = p on the device, ordered on stream s.
+void launch_set_pointer(void** table, int idx, void* p, hipStream_t s);
 // FP64 sum of squares of n elements into *out (device double), then scale.
 void launch_sumsq(const void* x, bool f64, int64_t n, double* out, hipStream_t s);
 void launch_scale_by_inv_sqrt(void* x, bool f64, int64_t n, const double* sumsq, hipStream_t s);
@@ -254,8 +275,10 @@ std::vector<TensorPtr> run_contractions_batched(
 void upload_sync(BufferPtr& buf, const void* host, size_t bytes);
 void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles);
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix);
-void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems);
-void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw);
+// planes: panel planes a split destination writes (plane p at p * lo_off)
+void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems, int planes = 1);
+void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw,
+                     int planes = 1);
 
 // op (may be null): nphys x nphys row-major over A's physical states,
 // op[s_bra][s_ket]; every non-zero entry must move the charge by the same

@@ -54,9 +54,11 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
 }
 
 // Destination kinds of the gather: float, double, one bf16 plane, the
-// split x = hi + lo with hi = bf16(x), lo = bf16(x - hi) in two planes, or
-// accumulation (dst += scale * src) in the source type.
-enum : int { kDstF32 = 0, kDstF64 = 1, kDstBF16 = 2, kDstSplit = 3, kDstAcc = 4 };
+// split x = hi + lo with hi = bf16(x), lo = bf16(x - hi) in two planes,
+// accumulation (dst += scale * src) in the source type, or the split
+// x = hi + mid + lo with mid = bf16(x - hi), lo = bf16(x - hi - mid) in three
+// planes (each plane lo_off elements after the previous one).
+enum : int { kDstF32 = 0, kDstF64 = 1, kDstBF16 = 2, kDstSplit = 3, kDstAcc = 4, kDstSplit3 = 5 };
 
 // One destination element of the gather: conversion to the destination kind.
 template <typename TS, int DK, typename AT>
@@ -72,6 +74,14 @@ __device__ __forceinline__ void copy_store(void* dstv, int64_t dofs, int64_t lo_
         const unsigned short h = f32_to_bf16_rn(v);
         ((unsigned short*)dstv)[dofs] = h;
         if constexpr (DK == kDstSplit) ((unsigned short*)dstv)[dofs + lo_off] = f32_to_bf16_rn(v - bf16_to_f32(h));
+        if constexpr (DK == kDstSplit3) {
+            // both differences are exact in FP32: hi and mid take the leading
+            // 8 + 8 significand bits of v
+            const float r1 = v - bf16_to_f32(h);
+            const unsigned short m = f32_to_bf16_rn(r1);
+            ((unsigned short*)dstv)[dofs + lo_off] = m;
+            ((unsigned short*)dstv)[dofs + 2 * lo_off] = f32_to_bf16_rn(r1 - bf16_to_f32(m));
+        }
     }
 }
 
@@ -387,18 +397,21 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
 }
 
 // ---- BF16 panels: v_mfma_f32_32x32x16_bf16 ---------------------------------
-// The gather has already rounded (BF16) or split (BF16X3: hi plane, lo plane
-// a_lo / b_lo elements later) the operands, so tiles go global -> LDS as
-// 16-byte vectors with no conversion.  bf16x3 accumulates lo*hi and hi*lo
-// before hi*hi, all in FP32.
-template <class Ptrs, class S, bool SPLIT>
+// The gather has already rounded (BF16, PL = 1) or split (BF16X3, PL = 2:
+// hi and lo planes; BF16X6, PL = 3: hi, mid and lo planes, plane p at
+// p * a_lo / p * b_lo elements) the operands, so tiles go global -> LDS as
+// 16-byte vectors with no conversion.  The split products are accumulated in
+// FP32, smallest terms first: bf16x3 = lo*hi + hi*lo + hi*hi; bf16x6 =
+// lo*hi + hi*lo + mid*mid + mid*hi + hi*mid + hi*hi (the dropped mid*lo,
+// lo*mid, lo*lo are below FP32 rounding of the product).
+template <class Ptrs, class S, int PL>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restrict__ tiles,
                                                         const GemmGroup* __restrict__ groups, Ptrs ptrs) {
     constexpr int BM = S::BM, BN = S::BN, BK = S::BK;
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int TI = WM / 32, TJ = WN / 32;
     constexpr int LDH = BK + 8;
-    constexpr int PL = SPLIT ? 2 : 1;
+    static_assert(PL >= 1 && PL <= 3, "one to three bf16 planes");
     static_assert(TI >= 1 && TJ >= 1 && BK % 16 == 0, "tile shape");
     __shared__ __attribute__((aligned(16))) unsigned short As[PL][BM * LDH];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[PL][BN * LDH];
@@ -428,7 +441,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
                 const int r = idx / (BK / 8), kq = (idx % (BK / 8)) * 8;
                 const int gr = m0 + r, gk = k0 + kq;
                 ra[p][v] = (gr < g.M && gk < g.lda)
-                               ? *(const us8_t*)(A + (p ? g.a_lo : 0) + (int64_t)gr * g.lda + gk)
+                               ? *(const us8_t*)(A + p * g.a_lo + (int64_t)gr * g.lda + gk)
                                : zero8;
             }
 #pragma unroll
@@ -437,7 +450,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
                 const int r = idx / (BK / 8), kq = (idx % (BK / 8)) * 8;
                 const int gr = n0 + r, gk = k0 + kq;
                 rb[p][v] = (gr < g.N && gk < g.ldb)
-                               ? *(const us8_t*)(B + (p ? g.b_lo : 0) + (int64_t)gr * g.ldb + gk)
+                               ? *(const us8_t*)(B + p * g.b_lo + (int64_t)gr * g.ldb + gk)
                                : zero8;
             }
         }
@@ -476,26 +489,34 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
         if (k0 + BK < K) gload(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
-            bf8_t ah[TI], bh[TJ], al[TI], bl[TJ];
+            // plane 0 = hi, PL - 1 = lo, 1 = mid (PL = 3)
+            bf8_t ah[TI], bh[TJ], al[TI], bl[TJ], am[TI], bm[TJ];
 #pragma unroll
             for (int i = 0; i < TI; ++i) {
                 const int o = (wm + i * 32 + (lane & 31)) * LDH + kk + 8 * (lane >> 5);
                 ah[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&As[0][o]));
-                if constexpr (SPLIT) al[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&As[PL - 1][o]));
+                if constexpr (PL > 1) al[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&As[PL - 1][o]));
+                if constexpr (PL > 2) am[i] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&As[1][o]));
             }
 #pragma unroll
             for (int j = 0; j < TJ; ++j) {
                 const int o = (wn + j * 32 + (lane & 31)) * LDH + kk + 8 * (lane >> 5);
                 bh[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&Bs[0][o]));
-                if constexpr (SPLIT) bl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&Bs[PL - 1][o]));
+                if constexpr (PL > 1) bl[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&Bs[PL - 1][o]));
+                if constexpr (PL > 2) bm[j] = __builtin_bit_cast(bf8_t, *(const us8_t*)(&Bs[1][o]));
             }
 #pragma unroll
             for (int i = 0; i < TI; ++i)
 #pragma unroll
                 for (int j = 0; j < TJ; ++j) {
-                    if constexpr (SPLIT) {
+                    if constexpr (PL > 1) {
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    }
+                    if constexpr (PL > 2) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[i], bm[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am[i], bh[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bm[j], acc[i][j], 0, 0, 0);
                     }
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
                 }
@@ -523,6 +544,11 @@ __global__ void cast_kernel_d2f(const double* __restrict__ s, float* __restrict_
 __global__ void cast_kernel_f2d(const float* __restrict__ s, double* __restrict__ d, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         d[i] = (double)s[i];
+}
+// One entry of a device pointer table, written in stream order (a replayed
+// HIP graph reads its buffers through such a table).
+__global__ void set_pointer_kernel(void** __restrict__ table, int idx, void* p) {
+    if (threadIdx.x == 0) table[idx] = p;
 }
 __global__ void fill_zero_kernel(uint32_t* __restrict__ d, int64_t nwords) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * blockDim.x)
@@ -678,6 +704,11 @@ void launch_cast(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t
     HIPCHK(hipGetLastError());
 }
 
+void launch_set_pointer(void** table, int idx, void* p, hipStream_t s) {
+    hipLaunchKernelGGL(set_pointer_kernel, dim3(1), dim3(64), 0, s, table, idx, p);
+    HIPCHK(hipGetLastError());
+}
+
 void launch_fill_zero(void* dst, int64_t bytes, hipStream_t s) {
     if (bytes <= 0) return;
     if (bytes % 4) fail(SYMTEN_E_INVAL, "fill_zero: size not a multiple of 4 bytes");
@@ -744,7 +775,9 @@ static void copy_dispatch(const CopyTask* d_tasks, const int64_t* d_prefix, int 
             case kDstF32: SYMTEN_COPY(float, kDstF32); break;
             case kDstBF16: SYMTEN_COPY(float, kDstBF16); break;
             case kDstAcc: SYMTEN_COPY(float, kDstAcc); break;
-            default: SYMTEN_COPY(float, kDstSplit); break;
+            case kDstSplit: SYMTEN_COPY(float, kDstSplit); break;
+            case kDstSplit3: SYMTEN_COPY(float, kDstSplit3); break;
+            default: fail(SYMTEN_E_INVAL, "copy: unknown destination kind");
         }
     }
 #undef SYMTEN_COPY
@@ -793,18 +826,18 @@ static void launch_f32_family(int cfg, dim3 grid, hipStream_t s, const TileWork*
     }
 }
 
-template <class Ptrs, bool SPLIT>
+template <class Ptrs, int PL>
 static void launch_bf16_family(int cfg, dim3 grid, hipStream_t s, const TileWork* t, const GemmGroup* g, Ptrs P) {
     dim3 block(256);
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 64, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
-        case 1: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
-        case 2: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 64, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
-        case 3: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
-        case 4: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<256, 128, 32>, SPLIT>), grid, block, 0, s, t, g, P); break;
-        case 5: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 64, 64>, SPLIT>), grid, block, 0, s, t, g, P); break;
-        case 6: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 64, 64>, SPLIT>), grid, block, 0, s, t, g, P); break;
-        default: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 128, 64>, SPLIT>), grid, block, 0, s, t, g, P); break;
+        case 0: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 64, 32>, PL>), grid, block, 0, s, t, g, P); break;
+        case 1: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 128, 32>, PL>), grid, block, 0, s, t, g, P); break;
+        case 2: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 64, 32>, PL>), grid, block, 0, s, t, g, P); break;
+        case 3: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 128, 32>, PL>), grid, block, 0, s, t, g, P); break;
+        case 4: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<256, 128, 32>, PL>), grid, block, 0, s, t, g, P); break;
+        case 5: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 64, 64>, PL>), grid, block, 0, s, t, g, P); break;
+        case 6: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 64, 64>, PL>), grid, block, 0, s, t, g, P); break;
+        default: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 128, 64>, PL>), grid, block, 0, s, t, g, P); break;
     }
 }
 
@@ -826,8 +859,9 @@ static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* 
             }
             break;
         case Prec::F32: launch_f32_family<Ptrs>(cfg, grid, s, d_tiles, d_groups, P); break;
-        case Prec::BF16: launch_bf16_family<Ptrs, false>(cfg, grid, s, d_tiles, d_groups, P); break;
-        case Prec::BF16X3: launch_bf16_family<Ptrs, true>(cfg, grid, s, d_tiles, d_groups, P); break;
+        case Prec::BF16: launch_bf16_family<Ptrs, 1>(cfg, grid, s, d_tiles, d_groups, P); break;
+        case Prec::BF16X3: launch_bf16_family<Ptrs, 2>(cfg, grid, s, d_tiles, d_groups, P); break;
+        case Prec::BF16X6: launch_bf16_family<Ptrs, 3>(cfg, grid, s, d_tiles, d_groups, P); break;
     }
     HIPCHK(hipGetLastError());
 }

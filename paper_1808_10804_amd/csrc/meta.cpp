@@ -25,12 +25,13 @@ int panel_dst_kind(Prec p) {
         case Prec::F64: return 1;
         case Prec::F32: return 0;
         case Prec::BF16: return 2;
-        default: return 3;
+        case Prec::BF16X3: return 3;
+        default: return 5;
     }
 }
 
 std::string copy_kernel_name(bool src64, Prec p) {
-    static const char* dst[] = {"f64", "f32", "bf16", "bf16x2"};
+    static const char* dst[] = {"f64", "f32", "bf16", "bf16x2", "bf16x3"};
     return std::string("copy_kernel<") + (src64 ? "f64" : "f32") + "," + dst[(int)p] + ">";
 }
 void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
@@ -52,10 +53,45 @@ void hip_check(hipError_t e, const char* what) {
 
 // ------------------------------------------------------------- device pool
 namespace {
+thread_local hipStream_t tl_stream = nullptr;
+thread_local bool tl_stream_set = false;
+}  // namespace
+
+StreamScope::StreamScope(hipStream_t s) : prev(tl_stream), prev_set(tl_stream_set) {
+    tl_stream = s;
+    tl_stream_set = true;
+}
+StreamScope::~StreamScope() {
+    tl_stream = prev;
+    tl_stream_set = prev_set;
+}
+bool call_stream_set() { return tl_stream_set; }
+hipStream_t call_stream() { return tl_stream; }
+
+namespace {
+struct FreeBlock {
+    void* ptr;
+    hipStream_t stream;   // stream that released it
+    hipEvent_t ev;        // recorded on `stream` at release (null: already idle)
+};
 struct Pool {
     std::mutex mu;
-    std::multimap<size_t, void*> free_;   // capacity -> ptr
+    std::multimap<size_t, FreeBlock> free_;   // capacity -> block
+    std::vector<hipEvent_t> idle_events;
     size_t held = 0;
+    hipEvent_t take_event() {   // under mu
+        if (!idle_events.empty()) {
+            hipEvent_t e = idle_events.back();
+            idle_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    }
 };
 Pool& pool() {
     static Pool* p = new Pool();   // leaked on purpose: buffers may outlive statics
@@ -120,12 +156,21 @@ BufferPtr device_alloc(size_t bytes) {
             return b;
         }
     }
+    const hipStream_t cur = call_stream();
+    b->stream = cur;
     {
         Pool& P = pool();
         std::lock_guard<std::mutex> lk(P.mu);
         auto it = P.free_.lower_bound(cap);
         if (it != P.free_.end() && it->first <= cap * 2) {
-            b->ptr = it->second;
+            const FreeBlock fb = it->second;
+            if (fb.ev) {
+                // the block's last users were queued on fb.stream: a call on
+                // another stream waits for them (same stream: queue order)
+                if (fb.stream != cur) HIPCHK(hipStreamWaitEvent(cur, fb.ev, 0));
+                P.idle_events.push_back(fb.ev);
+            }
+            b->ptr = fb.ptr;
             b->cap = it->first;
             P.free_.erase(it);
             P.held -= b->cap;
@@ -141,7 +186,10 @@ BufferPtr device_alloc(size_t bytes) {
         {
             std::lock_guard<std::mutex> lk(P.mu);
             (void)hipDeviceSynchronize();
-            for (auto& kv : P.free_) (void)hipFree(kv.second);
+            for (auto& kv : P.free_) {
+                (void)hipFree(kv.second.ptr);
+                if (kv.second.ev) P.idle_events.push_back(kv.second.ev);
+            }
             P.free_.clear();
             P.held = 0;
         }
@@ -168,9 +216,21 @@ DeviceBuffer::~DeviceBuffer() {
         if (current) user_free(ptr, cap, user_ctx);
         return;
     }
+    const hipStream_t rs = call_stream_set() ? call_stream() : stream;
     Pool& P = pool();
     std::lock_guard<std::mutex> lk(P.mu);
-    P.free_.emplace(cap, ptr);
+    hipEvent_t ev = P.take_event();
+    if (ev && hipEventRecord(ev, rs) != hipSuccess) {
+        // no event on that stream (e.g. it no longer exists): wait for the
+        // device instead, after which the block is idle
+        (void)hipGetLastError();
+        (void)hipDeviceSynchronize();
+        P.idle_events.push_back(ev);
+        ev = nullptr;
+    } else if (!ev) {
+        (void)hipDeviceSynchronize();
+    }
+    P.free_.emplace(cap, FreeBlock{ptr, rs, ev});
     P.held += cap;
 }
 
@@ -391,6 +451,7 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
         case SYMTEN_PREC_F32: p = Prec::F32; break;
         case SYMTEN_PREC_BF16: p = Prec::BF16; break;
         case SYMTEN_PREC_BF16X3: p = Prec::BF16X3; break;
+        case SYMTEN_PREC_BF16X6: p = Prec::BF16X6; break;
         default: fail(SYMTEN_E_INVAL, "contract: unknown precision");
     }
     if (A.dtype != B.dtype) fail(SYMTEN_E_INVAL, "contract: operands have different storage types");
@@ -641,7 +702,7 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
     plan->b_panel_elems = b_pos;
     plan->out_elems = c_pos;
     plan->info = info;
-    if (p == Prec::BF16X3)   // lo plane follows the whole hi plane of its panel buffer
+    if (panel_planes(p) > 1)   // each lower plane follows the whole plane above it
         for (auto& t : plan->copies) t.lo_off = t.dst_buf == 2 ? a_pos : b_pos;
     return plan;
 }
@@ -720,7 +781,8 @@ std::string gemm_kernel_name(Prec p, int cfg) {
         case Prec::F64: return "gemm_f64_kernel<" + t + ">";
         case Prec::F32: return "gemm_f32_kernel<" + t + ",f32>";
         case Prec::BF16: return "gemm_bf16_kernel<" + t + ",bf16>";
-        default: return "gemm_bf16_kernel<" + t + ",bf16x3>";
+        case Prec::BF16X3: return "gemm_bf16_kernel<" + t + ",bf16x3>";
+        default: return "gemm_bf16_kernel<" + t + ",bf16x6>";
     }
 }
 
@@ -925,7 +987,7 @@ void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefi
 
 // Every element a task or a GEMM group touches must lie inside its buffer;
 // checked on the host before any descriptor reaches the device.
-void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems) {
+void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems, int planes) {
     for (const CopyTask& t : tasks) {
         int64_t smax = t.src_off, dmax = t.dst_off, smin = t.src_off, dmin = t.dst_off;
         for (int k = 0; k < t.rank; ++k) {
@@ -935,9 +997,9 @@ void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_
             (ds >= 0 ? dmax : dmin) += ds;
             (ss >= 0 ? smax : smin) += ss;
         }
-        // split panels also write lo_off elements further (the lo plane)
-        if (t.dst_buf < 0 || t.dst_buf >= (int)buf_elems.size() || dmin < 0 || t.lo_off < 0 ||
-            dmax + t.lo_off >= buf_elems[t.dst_buf])
+        // split panels also write (planes - 1) * lo_off elements further (the lower planes)
+        if (t.dst_buf < 0 || t.dst_buf >= (int)buf_elems.size() || dmin < 0 || t.lo_off < 0 || planes < 1 ||
+            dmax + (planes - 1) * t.lo_off >= buf_elems[t.dst_buf])
             fail(SYMTEN_E_INVAL, "internal: copy destination out of bounds");
         if (t.src_buf >= 0 && (t.src_buf >= (int)buf_elems.size() || smin < 0 || smax >= buf_elems[t.src_buf]))
             fail(SYMTEN_E_INVAL, "internal: copy source out of bounds");
@@ -950,7 +1012,8 @@ void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_
     }
 }
 
-void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw) {
+void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw,
+                     int planes) {
     for (const GemmGroup& g : groups) {
         auto in = [&](int b, int64_t off, int64_t n) {
             return b >= 0 && b < (int)buf_elems.size() && off >= 0 && off + n <= buf_elems[b];
@@ -961,9 +1024,11 @@ void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int
         if (!in(g.a_buf, g.a_off, (int64_t)g.M * g.lda) || !in(g.b_buf, g.b_off, (int64_t)g.N * g.ldb) ||
             !in(g.c_buf, g.c_off, (int64_t)(g.M - 1) * g.ldc + g.N))
             fail(SYMTEN_E_INVAL, "internal: GEMM operand out of bounds");
-        if (g.a_lo % vw || g.b_lo % vw || !in(g.a_buf, g.a_off + g.a_lo, (int64_t)g.M * g.lda) ||
-            !in(g.b_buf, g.b_off + g.b_lo, (int64_t)g.N * g.ldb))
-            fail(SYMTEN_E_INVAL, "internal: GEMM lo plane out of bounds");
+        for (int p = 1; p < planes; ++p)
+            if (g.a_lo % vw || g.b_lo % vw || g.a_lo < 0 || g.b_lo < 0 ||
+                !in(g.a_buf, g.a_off + p * g.a_lo, (int64_t)g.M * g.lda) ||
+                !in(g.b_buf, g.b_off + p * g.b_lo, (int64_t)g.N * g.ldb))
+                fail(SYMTEN_E_INVAL, "internal: GEMM lower plane out of bounds");
     }
 }
 
@@ -992,14 +1057,14 @@ static std::shared_ptr<DevPlan> dev_plan(const ContractPlan& p) {
         x.a_buf = 0;
         x.b_buf = 1;
         x.c_buf = 2;
-        if (p.prec == Prec::BF16X3) {
+        if (panel_planes(p.prec) > 1) {
             x.a_lo = p.a_panel_elems;
             x.b_lo = p.b_panel_elems;
         }
         gg.push_back(x);
     }
     const int pl = panel_planes(p.prec);
-    validate_groups(gg, {pl * p.a_panel_elems, pl * p.b_panel_elems, p.out_elems}, panel_vw(p.prec));
+    validate_groups(gg, {pl * p.a_panel_elems, pl * p.b_panel_elems, p.out_elems}, panel_vw(p.prec), pl);
     d->host_groups = gg;
     upload_sync(d->groups, gg.data(), gg.size() * sizeof(GemmGroup));
     p.dev = d;
@@ -1016,7 +1081,7 @@ TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& 
     auto d = dev_plan(p);
     const int pl = panel_planes(p.prec);
     if (d->checked_a != A.elems || d->checked_b != B.elems) {
-        validate_tasks(p.copies, {A.elems, B.elems, pl * p.a_panel_elems, pl * p.b_panel_elems});
+        validate_tasks(p.copies, {A.elems, B.elems, pl * p.a_panel_elems, pl * p.b_panel_elems}, pl);
         d->checked_a = A.elems;
         d->checked_b = B.elems;
     }
@@ -1104,7 +1169,7 @@ std::shared_ptr<MultiDesc> multi_desc(const std::vector<std::shared_ptr<Contract
         d->info.max_m = std::max(d->info.max_m, p.info.max_m);
         d->info.max_n = std::max(d->info.max_n, p.info.max_n);
     }
-    if (plans[0]->prec == Prec::BF16X3) {   // lo planes follow the concatenated hi planes
+    if (panel_planes(plans[0]->prec) > 1) {   // the lower planes follow the concatenated hi planes
         for (auto& t : d->host_tasks) t.lo_off = t.dst_buf == 2 * n ? d->ap : d->bp;
         for (auto& g : d->host_groups) {
             g.a_lo = d->ap;
@@ -1164,8 +1229,8 @@ std::vector<TensorPtr> run_contractions_batched(const std::vector<std::shared_pt
     sizes[2 * n + 1] = pl * d->bp;
     if (d->host_groups.empty()) return outs;
     if (d->checked != sizes) {
-        validate_tasks(d->host_tasks, sizes);
-        validate_groups(d->host_groups, sizes, panel_vw(prec));
+        validate_tasks(d->host_tasks, sizes, pl);
+        validate_groups(d->host_groups, sizes, panel_vw(prec), pl);
         d->checked = sizes;
     }
     const size_t pe = panel_esize(prec) * pl;

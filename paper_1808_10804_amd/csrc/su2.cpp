@@ -521,7 +521,7 @@ std::shared_ptr<ContractPlan> plan_contraction_su2(const Tensor& A, const Tensor
     plan->b_panel_elems = b_pos;
     plan->out_elems = c_pos;
     plan->info = info;
-    if (p == Prec::BF16X3)
+    if (panel_planes(p) > 1)
         for (auto& t : plan->copies) t.lo_off = t.dst_buf == 2 ? a_pos : b_pos;
     return plan;
 }

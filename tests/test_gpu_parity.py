@@ -1,8 +1,11 @@
 """GPU parity of the libsymten hot path against the FP64 oracle.
 
 Tolerances are relative Frobenius errors: 1e-12 for FP64 sector products,
-1e-5 for FP32 and for the bf16x3 split products; plain BF16 is checked only
-against a loose bound derived from its 8-bit significand.
+1e-5 for FP32 and for the bf16x3 and bf16x6 split products; plain BF16 is
+checked only against a loose bound derived from its 8-bit significand.  The
+two-plane bf16x3 split meets 1e-5 on contractions and corners but not on a
+whole move (its post-SVD left column is about 3e-5 at cfg 2); the
+three-plane bf16x6 split is the split-precision move that meets 1e-5.
 """
 import numpy as np
 import pytest
@@ -14,10 +17,10 @@ from workload import oracle_side, device_side, to_dense, rel
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16x3": 1e-5, "bf16": 2e-2}
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16x3": 1e-5, "bf16x6": 1e-5, "bf16": 2e-2}
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x6", "bf16"])
 @pytest.mark.parametrize("mnk", [(1, 1, 1), (5, 7, 3), (64, 64, 64), (65, 130, 33), (200, 129, 257),
                                  (300, 40, 1000), (17, 300, 5)])
 def test_single_sector_gemm(prec, mnk):
@@ -42,7 +45,7 @@ TILES = {0: (64, 64, 1), 1: (128, 128, 1), 2: (128, 64, 1), 3: (64, 128, 1), 4: 
          5: (64, 64, 2), 6: (128, 64, 2), 7: (64, 128, 2)}
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x6", "bf16"])
 @pytest.mark.parametrize("cfg", sorted(TILES))
 def test_every_tile_configuration(prec, cfg, monkeypatch):
     """Each tile shape forced in turn (the autotuner would pick only one per
@@ -53,7 +56,7 @@ def test_every_tile_configuration(prec, cfg, monkeypatch):
         pytest.skip("256x128 is not built for FP64")
     monkeypatch.setenv("SYMTEN_TILE_CFG", str(cfg))
     dt = "f64" if prec == "f64" else "f32"
-    bump = cfg + 8 * ["f64", "f32", "bf16x3", "bf16"].index(prec)
+    bump = cfg + 8 * ["f64", "f32", "bf16x3", "bf16", "bf16x6"].index(prec)
     m = {0: 70 + bump, 1: 131 + bump, 2: 9}
     k = {0: 97 + 3 * bump, 1: 40 + bump, 2: 150}
     n = {0: 66 + 2 * bump, 1: 129, 2: 31 + bump}
@@ -138,7 +141,7 @@ def cfg2():
     return c, oracle_side(c, c["seed"])
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16x6", "bf16"])
 def test_enlarged_corner_cfg2(cfg2, prec):
     c, (w, T, a, _) = cfg2
     dev = device_side(c, c["seed"], "f32")
@@ -178,15 +181,15 @@ def test_ctm_move_cfg1_f64(cfg1):
     P_o[perm] = pr["P"]
     Pt_o = np.zeros((Ptd.shape[0], Ptd.shape[1] * Ptd.shape[2]))
     Pt_o[:, perm] = pr["Pt"]
-    assert rel(Pd.reshape(-1, Pd.shape[2]), P_o) <= 1e-11
-    assert rel(Ptd.reshape(Ptd.shape[0], -1), Pt_o) <= 1e-11
+    assert rel(Pd.reshape(-1, Pd.shape[2]), P_o) <= TOL["f64"]
+    assert rel(Ptd.reshape(Ptd.shape[0], -1), Pt_o) <= TOL["f64"]
     C1n = to_dense(env.get(0), [kleg, u1.Leg(w.chi, -1)])
     T4n = to_dense(env.get(7), [kleg, u1.Leg(w.dd, -1), kleg.flipped()])
     C4n = to_dense(env.get(3), [u1.Leg(w.chi, 1), kleg.flipped()])
-    assert rel(C1n, mv["C1"]) <= 1e-11
-    assert rel(T4n, mv["T4"]) <= 1e-11
-    assert rel(C4n, mv["C4"]) <= 1e-11
-    assert rel(u1.left_column(C1n, T4n, C4n), mv["L"]) <= 1e-11
+    assert rel(C1n, mv["C1"]) <= TOL["f64"]
+    assert rel(T4n, mv["T4"]) <= TOL["f64"]
+    assert rel(C4n, mv["C4"]) <= TOL["f64"]
+    assert rel(u1.left_column(C1n, T4n, C4n), mv["L"]) <= TOL["f64"]
     # useful flops: corners and halves bit-exact against the brute force
     fl = u1.move_gemm_flops(w, pr["kept"])
     assert stats["flops_corners"] == fl["corners"]
@@ -194,7 +197,7 @@ def test_ctm_move_cfg1_f64(cfg1):
     assert stats["flops_renorm"] == fl["renorm"]
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f32", "bf16x6", "bf16x3"])
 def test_ctm_move_cfg2(cfg2, prec):
     c, (w, T, a, _) = cfg2
     chi = c["chi_target"]
@@ -212,7 +215,14 @@ def test_ctm_move_cfg2(cfg2, prec):
     e_L = rel(u1.left_column(C1n, T4n, C4n), mv["L"])
     print(f"cfg2 move {prec}: sv {e_sv:.3e} L {e_L:.3e} stats {stats['ms_total']:.3f} ms")
     assert e_sv <= TOL[prec]
-    assert e_L <= TOL[prec] if prec == "f32" else e_L <= 5 * TOL[prec]
+    if prec == "bf16x3":
+        # the known miss: the two-plane split's ~2^-16 per product passes three
+        # corner GEMMs, the halves and the projector stage; the test holds the
+        # measured level (3.3e-5) so that a regression is caught, and fails if
+        # the path ever meets the target without the tolerances being revisited
+        assert TOL[prec] < e_L <= 5e-5
+    else:
+        assert e_L <= TOL[prec]
 
 
 def test_batched_corners_match_single_and_oracle():
