@@ -224,6 +224,27 @@ int symten_contract(symten_t* out, symten_t A, symten_t B, int ncon,
                     const int* legsA, const int* legsB, const int* out_perm,
                     int prec, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * contraction of symten_contract written into the caller's tensor `out`,
+ * which holds the output's legs (A's open legs then B's, permuted by
+ * out_perm), flux A.flux + B.flux and storage type, with contiguous blocks
+ * (as symten_create makes them; blocks that no pair reaches are set to 0).
+ * The gathered operand panels, the charge-sector products and the kernels'
+ * descriptors use a fixed work area of SYMTEN_NOALLOC_SCRATCH_BYTES that
+ * each GPU the library runs on holds until the process ends; no device
+ * memory is allocated (the call's host-side planning uses host memory).
+ * The work area's device address is looked up on the first call on each
+ * device.  Every call on one GPU shares the work area and finds it as the
+ * last call left it: calls that overlap on one GPU race, so issue them on
+ * one stream.  The GEMM tiles are chosen without the autotuner.  Errors:
+ * SYMTEN_E_CAPACITY when the contraction needs more work area,
+ * SYMTEN_E_INVAL when out's legs, flux, storage type or layout differ, and
+ * the errors of symten_contract.                                           */
+#define SYMTEN_NOALLOC_SCRATCH_BYTES (64u << 20)
+int symten_contract_noalloc(symten_t out, symten_t A, symten_t B, int ncon, const int* legsA,
+                            const int* legsB, const int* out_perm, int prec, void* stream);
+
 /* Host-only planning of the same contraction: fills `info` and, if `out`
  * is not NULL, a metadata-only output tensor.  No GPU needed.              */
 int symten_plan_info(symten_t A, symten_t B, int ncon, const int* legsA,

@@ -148,6 +148,14 @@ std::shared_ptr<ContractPlan> get_plan(const Tensor& A, const Tensor& B, int nco
     return p;
 }
 
+}  // namespace
+
+std::shared_ptr<ContractPlan> cached_plan(const Tensor& A, const Tensor& B, int ncon, const int* la, const int* lb,
+                                          const int* perm, int prec) {
+    return get_plan(A, B, ncon, la, lb, perm, prec);
+}
+
+namespace {
 struct Contracted {
     TensorPtr t;
     std::shared_ptr<ContractPlan> plan;
@@ -1992,6 +2000,15 @@ int symten_contract(symten_t* out, symten_t A, symten_t B, int ncon, const int* 
         if (!out) fail(SYMTEN_E_INVAL, "null output");
         auto p = get_plan(T(A), T(B), ncon, legsA, legsB, out_perm, prec);
         *out = wrap(run_contraction(*p, T(A), T(B), S(stream)));
+    });
+}
+
+int symten_contract_noalloc(symten_t out, symten_t A, symten_t B, int ncon, const int* legsA, const int* legsB,
+                            const int* out_perm, int prec, void* stream) {
+    return guard_on(stream, [&] {
+        if (!out) fail(SYMTEN_E_INVAL, "contract_noalloc: null output tensor");
+        auto p = cached_plan(T(A), T(B), ncon, legsA, legsB, out_perm, prec);
+        contract_noalloc(T(out), T(A), T(B), p, S(stream));
     });
 }
 

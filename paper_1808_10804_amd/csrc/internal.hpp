@@ -262,6 +262,20 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
                                                const int* legsA, const int* legsB,
                                                const int* out_perm, int prec);
 
+// The plan's GEMM groups launched with a tile list (at most 16 buffers).
+void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
+                     const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s);
+// Tile configuration used without the autotuner.
+int choose_tile_cfg(const ContractPlan& p);
+// The plan of a contraction from the library's plan cache.
+std::shared_ptr<ContractPlan> cached_plan(const Tensor& A, const Tensor& B, int ncon, const int* la, const int* lb,
+                                          const int* perm, int prec);
+// Contraction of a plan into the caller's tensor `out` (contiguous blocks,
+// the plan's legs) through the library's fixed device work area: no device
+// allocation.
+void contract_noalloc(Tensor& out, const Tensor& A, const Tensor& B, const std::shared_ptr<ContractPlan>& plan,
+                      hipStream_t s);
+
 // Execute a plan: allocates the output buffer, gathers panels, runs the GEMMs.
 TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& B,
                           hipStream_t stream);

@@ -244,6 +244,16 @@ def contract(A, B, legsA, legsB, out_perm=None, prec="f32", stream=None):
     return Tensor(h)
 
 
+def contract_noalloc(out, A, B, legsA, legsB, out_perm=None, prec="f32", stream=None):
+    """symten_contract written into the existing tensor `out` (the output's
+    legs, contiguous blocks) through the library's fixed work area, with no
+    device allocation; returns `out`."""
+    perm = _ints(out_perm) if out_perm is not None else None
+    check(lib().symten_contract_noalloc(out._h, A._h, B._h, len(legsA), _ints(legsA), _ints(legsB), perm,
+                                        _prec(prec), _stream(stream)))
+    return out
+
+
 def plan_info(A, B, legsA, legsB, out_perm=None):
     """Host-only planning; returns (stats dict, metadata-only output Tensor)."""
     st = _lib.PlanStats()
