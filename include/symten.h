@@ -245,6 +245,32 @@ int symten_contract(symten_t* out, symten_t A, symten_t B, int ncon,
 int symten_contract_noalloc(symten_t out, symten_t A, symten_t B, int ncon, const int* legsA,
                             const int* legsB, const int* out_perm, int prec, void* stream);
 
+/* Sector matching on the device (Sec. 2, the contraction rule and the
+ * grouping by output labels), from the leg tables of A and B alone: one
+ * workgroup enumerates the allowed blocks of both tensors (canonical order),
+ * the matched pairs (A block i, B block j) whose labels agree on the
+ * contracted legs, in lexicographic (i, j) order, and the output blocks
+ * reached by at least one pair: label tuples of A's open legs then B's open
+ * legs (no permutation), lexicographic.  Results go to device memory and
+ * the call does not wait: pairs[p] for p < min(count, pair_cap);
+ * out_labels[o * rank_out + l] for o < min(count, out_cap); counts[5] =
+ * {A blocks, B blocks, pairs, output blocks, status} with status 1 when a
+ * list was cut at its capacity (the counts are the full ones, so a caller
+ * can size the buffers and call again).  U(1) and Z2 (SYMTEN_E_UNSUPPORTED
+ * otherwise); at most 64 sectors per leg (SYMTEN_E_CAPACITY); contracted
+ * legs must be dual (SYMTEN_E_LEGS).  Tensors may be metadata-only; the
+ * call needs a GPU.                                                        */
+typedef struct {
+    int32_t a_block;    /* index of the A block in A's canonical order      */
+    int32_t b_block;    /* index of the B block in B's canonical order      */
+    int32_t out_block;  /* index of the output block in the output list     */
+    int32_t pad_;
+    int64_t flops;      /* 2 m n k of the pair                              */
+} symten_pair;
+int symten_match_blocks(symten_t A, symten_t B, int ncon, const int* legsA, const int* legsB,
+                        symten_pair* pairs, int64_t pair_cap, int* out_labels, int64_t out_cap,
+                        int64_t* counts, void* stream);
+
 /* Host-only planning of the same contraction: fills `info` and, if `out`
  * is not NULL, a metadata-only output tensor.  No GPU needed.              */
 int symten_plan_info(symten_t A, symten_t B, int ncon, const int* legsA,

@@ -108,6 +108,7 @@ SIGNATURES = {
     "symten_download": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64, P]),
     "symten_contract": (C.c_int, [C.POINTER(H), H, H, C.c_int, IP, IP, IP, C.c_int, P]),
     "symten_contract_noalloc": (C.c_int, [H, H, H, C.c_int, IP, IP, IP, C.c_int, P]),
+    "symten_match_blocks": (C.c_int, [H, H, C.c_int, IP, IP, P, C.c_int64, P, C.c_int64, P, P]),
     "symten_plan_info": (C.c_int, [H, H, C.c_int, IP, IP, IP, C.POINTER(PlanStats), C.POINTER(H)]),
     "symten_double_layer": (C.c_int, [C.POINTER(H), H, P]),
     "symten_enlarged_corner": (C.c_int, [C.POINTER(H), C.c_int, H, H, H, H, C.c_int,

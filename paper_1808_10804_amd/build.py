@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsymten.so")
-SOURCES = ["kernels.hip", "meta.cpp", "su2.cpp", "abi.cpp", "noalloc.hip"]
+SOURCES = ["kernels.hip", "meta.cpp", "su2.cpp", "abi.cpp", "noalloc.hip", "match.hip"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 FLAGS = [

@@ -2012,6 +2012,13 @@ int symten_contract_noalloc(symten_t out, symten_t A, symten_t B, int ncon, cons
     });
 }
 
+int symten_match_blocks(symten_t A, symten_t B, int ncon, const int* legsA, const int* legsB, symten_pair* pairs,
+                        int64_t pair_cap, int* out_labels, int64_t out_cap, int64_t* counts, void* stream) {
+    return guard_on(stream, [&] {
+        match_blocks(T(A), T(B), ncon, legsA, legsB, pairs, pair_cap, out_labels, out_cap, counts, S(stream));
+    });
+}
+
 int symten_double_layer(symten_t* a_out, symten_t A, void* stream) {
     return guard_on(stream, [&] {
         if (!a_out) fail(SYMTEN_E_INVAL, "null output");

@@ -276,6 +276,11 @@ std::shared_ptr<ContractPlan> cached_plan(const Tensor& A, const Tensor& B, int 
 void contract_noalloc(Tensor& out, const Tensor& A, const Tensor& B, const std::shared_ptr<ContractPlan>& plan,
                       hipStream_t s);
 
+// Sector matching of a contraction on the device (see symten_match_blocks).
+void match_blocks(const Tensor& A, const Tensor& B, int ncon, const int* legsA, const int* legsB,
+                  symten_pair* pairs, int64_t pair_cap, int* out_labels, int64_t out_cap, int64_t* counts,
+                  hipStream_t s);
+
 // Execute a plan: allocates the output buffer, gathers panels, runs the GEMMs.
 TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& B,
                           hipStream_t stream);

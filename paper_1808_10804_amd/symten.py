@@ -254,6 +254,33 @@ def contract_noalloc(out, A, B, legsA, legsB, out_perm=None, prec="f32", stream=
     return out
 
 
+def match_blocks(A, B, legsA, legsB, pair_cap=None, out_cap=None, stream=None):
+    """Sector matching of the contraction on the device (symten_match_blocks)
+    into torch-allocated device buffers; waits for the stream and returns
+    (pairs, out_labels, counts): pairs an int64 array of rows (A block,
+    B block, output block, flops), out_labels the output label tuples (A's
+    open legs then B's, unpermuted), counts (A blocks, B blocks, pairs,
+    output blocks, status)."""
+    import numpy as np
+    import torch
+    na, nb = A.num_blocks, B.num_blocks
+    ro = A.rank + B.rank - 2 * len(legsA)
+    pair_cap = na * nb if pair_cap is None else int(pair_cap)
+    out_cap = max(1, pair_cap) if out_cap is None else int(out_cap)
+    pairs = torch.zeros((max(1, pair_cap), 3), dtype=torch.int64, device="cuda")
+    outl = torch.zeros((max(1, out_cap), max(1, ro)), dtype=torch.int32, device="cuda")
+    counts = torch.zeros(5, dtype=torch.int64, device="cuda")
+    check(lib().symten_match_blocks(A._h, B._h, len(legsA), _ints(legsA), _ints(legsB), C.c_void_p(pairs.data_ptr()),
+                                    pair_cap, C.c_void_p(outl.data_ptr()), out_cap, C.c_void_p(counts.data_ptr()),
+                                    _stream(stream)))
+    check(lib().symten_sync(_stream(stream)))
+    cnt = counts.cpu().numpy()
+    raw = pairs.cpu().numpy()[:min(int(cnt[2]), pair_cap)]
+    i32 = raw[:, :2].copy().view(np.int32)          # (a_block, b_block), (out_block, pad)
+    rows = np.stack([i32[:, 0], i32[:, 1], i32[:, 2], raw[:, 2]], axis=1) if len(raw) else np.zeros((0, 4), np.int64)
+    return rows.astype(np.int64), outl.cpu().numpy()[:min(int(cnt[3]), out_cap), :ro], cnt
+
+
 def plan_info(A, B, legsA, legsB, out_perm=None):
     """Host-only planning; returns (stats dict, metadata-only output Tensor)."""
     st = _lib.PlanStats()
