@@ -29,11 +29,8 @@ namespace symten {
 
 void upload_sync(BufferPtr& buf, const void* host, size_t bytes);
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix);
-void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles);
 void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
                      void* const* d_ptrs, bool src_f64, int dst_kind, hipStream_t s);
-void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, void* const* d_ptrs,
-                     Prec prec, int cfg, hipStream_t s);
 int choose_tile_cfg(const ContractPlan& p);
 void launch_scale_cols(double* X, int ld, int rows, int cols, const double* s, double e, hipStream_t st);
 void launch_scale_rows(double* X, int ld, int rows, int cols, const double* s, double e, hipStream_t st);
@@ -2052,7 +2049,7 @@ int symten_enlarged_corner_single_layer(symten_t* out, int which, symten_t C, sy
 namespace {
 struct BatchStep {
     std::vector<std::shared_ptr<ContractPlan>> plans;
-    BufferPtr tasks, prefix, groups, ptrs, apanel, bpanel, out;
+    BufferPtr tasks, prefix, groups, ptrs, apanel, bpanel, out, ws;
     int ntasks = 0;
     int64_t nchunks = 0;
     TileChoice tc;
@@ -2180,14 +2177,21 @@ void run_step(BatchStep& B, hipStream_t s, bool tune = false) {
         copy_launch_dev((const CopyTask*)B.tasks->ptr, (const int64_t*)B.prefix->ptr, B.ntasks, B.nchunks,
                         (void* const*)B.ptrs->ptr, B.src_f64, panel_dst_kind(B.prec), s);
     });
-    auto launch = [&](int cfg, const TileWork* t, int nt) {
-        gemm_launch_dev(t, nt, (const GemmGroup*)B.groups->ptr, (void* const*)B.ptrs->ptr, B.prec, cfg, s);
+    auto launch = [&](int cfg) {
+        // the split-K workspace lives with the step (a captured graph keeps
+        // its address); it only grows while the shapes are being tuned
+        if (B.tc.ws_bytes[cfg] > (B.ws ? (int64_t)B.ws->bytes : 0)) {
+            if (!tune) fail(SYMTEN_E_INVAL, "internal: batched split-K workspace not sized before capture");
+            B.ws = device_alloc(B.tc.ws_bytes[cfg]);
+        }
+        gemm_launch_dev((const TileWork*)B.tc.tiles[cfg]->ptr, B.tc.ntiles[cfg], (const GemmGroup*)B.groups->ptr,
+                        (void* const*)B.ptrs->ptr, B.prec, cfg, s, B.tc.split(cfg, B.ws ? B.ws->ptr : nullptr));
     };
     if (tune) autotune_gemm(B.tc, B.host_groups, B.prec, launch, s);
     if (B.tc.cfg < 0) fail(SYMTEN_E_INVAL, "internal: batched GEMM launched before tuning");
     const int cfg = B.tc.cfg;
     profile_launch(gemm_kernel_name(B.prec, cfg) + ",batched", B.info.useful_flops, B.info.gemm_flops, B.gemm_bytes,
-                   s, [&] { launch(cfg, (const TileWork*)B.tc.tiles[cfg]->ptr, B.tc.ntiles[cfg]); });
+                   s, [&] { launch(cfg); });
 }
 
 // The n outputs of a step as views into one buffer laid out like B.out.

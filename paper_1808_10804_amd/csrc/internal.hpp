@@ -161,8 +161,34 @@ struct GemmGroup {
 };
 
 
+// One work item of a grouped-GEMM launch: output tile (tm, tn) of a group,
+// over the K range [k0, k1).  slot < 0: the item writes its C tile; else the
+// item is one part of a split K and writes its partial tile to slot `slot`
+// of the launch's workspace.  group < 0: padding (no work).
 struct TileWork {
-    int group, tm, tn, kz;
+    int group, tm, tn;
+    int k0, k1;
+    int slot;
+    int pad0, pad1;
+};
+// An output tile computed as nparts K parts: their partial tiles, workspace
+// slots slot0 .. slot0 + nparts - 1, are added in that order into C.
+struct SplitOut {
+    int group, tm, tn, slot0, nparts, pad;
+};
+// The work list of one launch with a tile configuration.
+struct TilePlan {
+    std::vector<TileWork> tiles;
+    std::vector<SplitOut> splits;
+    int64_t partial_tiles = 0;     // workspace slots
+};
+// Workspace of a launch: the persistent grid's per-XCD queue counters
+// (kSplitQueueBytes), then the split-K partial tiles.
+constexpr int64_t kSplitQueueBytes = 256;
+struct SplitK {
+    const SplitOut* splits = nullptr;
+    int nsplits = 0;
+    void* ws = nullptr;            // queue counters, then partial tiles BM x BN (FP64 or FP32 by precision)
 };
 
 // Pointer table handed to the kernels (device addresses).
@@ -262,9 +288,20 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
                                                const int* legsA, const int* legsB,
                                                const int* out_perm, int prec);
 
-// The plan's GEMM groups launched with a tile list (at most 16 buffers).
+// The plan's GEMM groups launched with a tile list (at most 16 buffers):
+// a persistent grid that holds as many workgroups as the chip runs at once
+// walks the list; split-K parts are added afterwards in a fixed order.
 void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
-                     const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s);
+                     const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s, const SplitK& sk = {});
+void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, void* const* d_ptrs,
+                     Prec prec, int cfg, hipStream_t s, const SplitK& sk = {});
+// Workgroups of a tile configuration that the chip holds at once (occupancy
+// times compute units).
+int gemm_capacity(Prec p, int cfg);
+// Lists longer than kPersistentFactor times the capacity run on a persistent
+// grid that takes entries from per-XCD queues.
+constexpr int kPersistentFactor = 4;
+bool gemm_persistent(int ntiles, int capacity);
 // Tile configuration used without the autotuner.
 int choose_tile_cfg(const ContractPlan& p);
 // The plan of a contraction from the library's plan cache.
@@ -292,7 +329,9 @@ std::vector<TensorPtr> run_contractions_batched(
 
 // plan / descriptor helpers shared by the launch paths
 void upload_sync(BufferPtr& buf, const void* host, size_t bytes);
-void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles);
+// Work list of a launch; with allow_split, tiles of a launch that would not
+// fill the chip are split along K (see the definition).
+void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, TilePlan& tp, bool allow_split);
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix);
 // planes: panel planes a split destination writes (plane p at p * lo_off)
 void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems, int planes = 1);
@@ -356,17 +395,24 @@ int gemm_tile_bk(Prec p, int cfg);
 bool gemm_tile_ok(Prec p, int cfg);
 struct TileChoice {
     int cfg = -1;                          // chosen configuration (-1: not tuned)
-    BufferPtr tiles[kNumTileCfg];          // device tile lists per configuration
+    BufferPtr tiles[kNumTileCfg];          // device work lists per configuration
+    BufferPtr splits[kNumTileCfg];         // device split-K output lists
     int ntiles[kNumTileCfg] = {};
+    int nsplits[kNumTileCfg] = {};
+    int64_t ws_bytes[kNumTileCfg] = {};    // split-K workspace a launch needs
     float ms[kNumTileCfg] = {};
+    // split-K arguments of configuration c with workspace ws
+    SplitK split(int c, void* ws) const {
+        return SplitK{nsplits[c] ? (const SplitOut*)splits[c]->ptr : nullptr, nsplits[c], ws};
+    }
 };
 // Picks the tile configuration for this set of GEMM groups: a cached
 // decision for the same shapes, else each available configuration is timed
-// once with HIP events through `launch` (idempotent: C = A B is rewritten).
-// Must not be called while the stream is being captured.
+// once with HIP events through `launch(cfg)` (idempotent: C = A B is
+// rewritten), after ensure_tiles(cfg).  Must not be called while the stream
+// is being captured.
 void autotune_gemm(TileChoice& tc, const std::vector<GemmGroup>& groups, Prec prec,
-                   const std::function<void(int cfg, const TileWork* tiles, int ntiles)>& launch,
-                   hipStream_t s);
+                   const std::function<void(int cfg)>& launch, hipStream_t s);
 void ensure_tiles(TileChoice& tc, const std::vector<GemmGroup>& groups, Prec prec, int cfg);
 
 // kernel timing (events around launches while enabled)

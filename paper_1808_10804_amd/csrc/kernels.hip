@@ -16,6 +16,8 @@
 #include <type_traits>
 #include <cstdio>
 #include <vector>
+#include <mutex>
+#include <algorithm>
 
 #include "internal.hpp"
 
@@ -151,21 +153,41 @@ __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __re
         }
         return;
     }
-    const int64_t base = local * kCopyChunk;
-    for (int e = threadIdx.x; e < kCopyChunk; e += kCopyThreads) {
-        const int64_t idx = base + e;
-        if (idx >= T.count) break;
+    // each thread copies kCopyRun consecutive elements: the multi-index is
+    // decomposed for the first and advanced along the innermost dim
+    constexpr int kCopyRun = kCopyChunk / kCopyThreads;
+    const int64_t idx0 = local * kCopyChunk + (int64_t)threadIdx.x * kCopyRun;
+    if (idx0 >= T.count) return;
+    const int last = rank - 1;
+    const int dl = T.dims[last];
+    const int64_t sl = T.sstride[last], dls = T.dstride[last];
+    int inner = 0;
+    int64_t so = 0, dofs = 0;
+    auto locate = [&](int64_t idx) {
         uint32_t r = (uint32_t)idx;
-        int64_t so = T.src_off, dofs = T.dst_off;
-        for (int k = rank - 1; k >= 0; --k) {
+        so = T.src_off;
+        dofs = T.dst_off;
+        for (int k = last; k >= 0; --k) {
             const uint32_t dk = (uint32_t)T.dims[k];
             const uint32_t q = r / dk;
             const uint32_t ik = r - q * dk;
+            if (k == last) inner = (int)ik;
             r = q;
             so += (int64_t)ik * T.sstride[k];
             dofs += (int64_t)ik * T.dstride[k];
         }
+    };
+    locate(idx0);
+#pragma unroll
+    for (int u = 0; u < kCopyRun; ++u) {
+        if (idx0 + u >= T.count) break;
         copy_store<TS, DK>(dstv, dofs, T.lo_off, src ? gather(so) : (AT)0, src != nullptr);
+        if (++inner < dl) {
+            so += sl;
+            dofs += dls;
+        } else {
+            locate(idx0 + u + 1);
+        }
     }
 }
 
@@ -180,9 +202,10 @@ struct TileShape {
 // ---- FP64: v_mfma_f64_16x16x4f64 -----------------------------------------
 // lane l: A[row l%16][k l/16], B[col l%16][k l/16]; acc e: row l/16 + 4*e, col l%16 (checked on gfx950)
 template <class Ptrs, class S>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restrict__ tiles,
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restrict__ tiles, int ntiles,
+                                                       int* __restrict__ queue,
                                                        const GemmGroup* __restrict__ groups,
-                                                       Ptrs ptrs) {
+                                                       Ptrs ptrs, double* __restrict__ ws) {
     constexpr int BM = S::BM, BN = S::BN, BK = S::BK;
     constexpr int LDK = BK + 1;
     constexpr int WM = BM / 2, WN = BN / 2;
@@ -190,8 +213,14 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restric
     __shared__ double As[BM * LDK];
     __shared__ double Bs[BN * LDK];
 
-    const TileWork tw = tiles[blockIdx.x];
-    if (tw.group < 0) return;   // padding of the per-XCD tile lists
+  // Entry t of the list belongs to XCD t mod 8, and workgroup b runs on XCD
+  // b mod 8.  Each workgroup starts with its own entry; with a queue (a
+  // persistent grid smaller than the list), it then takes the next free row
+  // of its XCD's list from that XCD's counter.
+  __shared__ int next_row;
+  for (int t = blockIdx.x; t < ntiles;) {
+    const TileWork tw = tiles[t];
+    if (tw.group >= 0) {   // group < 0: padding of the per-XCD lists
     const GemmGroup g = groups[tw.group];
     const double* __restrict__ A = (const double*)ptrs.get(g.a_buf) + g.a_off;
     const double* __restrict__ B = (const double*)ptrs.get(g.b_buf) + g.b_off;
@@ -246,12 +275,12 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restric
 #pragma unroll
         for (int j = 0; j < TJ; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-    const int K = g.K;
-    if (K > 0) gload(0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    const int kb = tw.k0, ke = tw.k1;   // this item's K range (whole stages but the last)
+    if (ke > kb) gload(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
         sstore();
         __syncthreads();
-        if (k0 + BK < K) gload(k0 + BK);
+        if (k0 + BK < ke) gload(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double a[TI], b[TJ];
@@ -267,6 +296,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restric
         }
         __syncthreads();
     }
+    // a whole-K item writes C; a split-K part writes its partial tile
+    double* __restrict__ W = ws + (int64_t)(tw.slot < 0 ? 0 : tw.slot) * BM * BN;
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -275,9 +306,17 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restric
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * e;
-                if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
+                if (tw.slot >= 0) W[(row - m0) * BN + (col - n0)] = acc[i][j][e];
+                else if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
             }
         }
+    }
+    if (!queue) break;
+    if (threadIdx.x == 0) next_row = (int)(gridDim.x >> 3) + atomicAdd(&queue[blockIdx.x & 7], 1);
+    __syncthreads();
+    t = next_row * 8 + (int)(blockIdx.x & 7);
+    __syncthreads();
+  }
 }
 
 // ---- FP32: v_mfma_f32_32x32x2f32 -------------------------------------------
@@ -287,9 +326,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const TileWork* __restric
 // MFMAs (two LDS stages, one barrier each, measured slower: the doubled LDS
 // lowers occupancy).
 template <class Ptrs, class S>
-__global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restrict__ tiles,
+__global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restrict__ tiles, int ntiles,
+                                                       int* __restrict__ queue,
                                                        const GemmGroup* __restrict__ groups,
-                                                       Ptrs ptrs) {
+                                                       Ptrs ptrs, float* __restrict__ ws) {
     constexpr int BM = S::BM, BN = S::BN, BK = S::BK;
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int TI = WM / 32, TJ = WN / 32;
@@ -298,8 +338,14 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
     __shared__ float As[BM * LDF];
     __shared__ float Bs[BN * LDF];
 
-    const TileWork tw = tiles[blockIdx.x];
-    if (tw.group < 0) return;   // padding of the per-XCD tile lists
+  // Entry t of the list belongs to XCD t mod 8, and workgroup b runs on XCD
+  // b mod 8.  Each workgroup starts with its own entry; with a queue (a
+  // persistent grid smaller than the list), it then takes the next free row
+  // of its XCD's list from that XCD's counter.
+  __shared__ int next_row;
+  for (int t = blockIdx.x; t < ntiles;) {
+    const TileWork tw = tiles[t];
+    if (tw.group >= 0) {   // group < 0: padding of the per-XCD lists
     const GemmGroup g = groups[tw.group];
     const float* __restrict__ A = (const float*)ptrs.get(g.a_buf) + g.a_off;
     const float* __restrict__ B = (const float*)ptrs.get(g.b_buf) + g.b_off;
@@ -362,12 +408,12 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-    const int K = g.K;
-    if (K > 0) gload(0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    const int kb = tw.k0, ke = tw.k1;   // this item's K range (whole stages but the last)
+    if (ke > kb) gload(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
         sstore();
         __syncthreads();
-        if (k0 + BK < K) gload(k0 + BK);
+        if (k0 + BK < ke) gload(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 2) {
             float a[TI], b[TJ];
@@ -383,6 +429,8 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
         }
         __syncthreads();
     }
+    // a whole-K item writes C; a split-K part writes its partial tile
+    float* __restrict__ W = ws + (int64_t)(tw.slot < 0 ? 0 : tw.slot) * BM * BN;
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -391,9 +439,17 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int row = m0 + wm + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
+                if (tw.slot >= 0) W[(row - m0) * BN + (col - n0)] = acc[i][j][e];
+                else if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
             }
         }
+    }
+    if (!queue) break;
+    if (threadIdx.x == 0) next_row = (int)(gridDim.x >> 3) + atomicAdd(&queue[blockIdx.x & 7], 1);
+    __syncthreads();
+    t = next_row * 8 + (int)(blockIdx.x & 7);
+    __syncthreads();
+  }
 }
 
 // ---- BF16 panels: v_mfma_f32_32x32x16_bf16 ---------------------------------
@@ -405,8 +461,10 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
 // lo*hi + hi*lo + mid*mid + mid*hi + hi*mid + hi*hi (the dropped mid*lo,
 // lo*mid, lo*lo are below FP32 rounding of the product).
 template <class Ptrs, class S, int PL>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restrict__ tiles,
-                                                        const GemmGroup* __restrict__ groups, Ptrs ptrs) {
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restrict__ tiles, int ntiles,
+                                                        int* __restrict__ queue,
+                                                        const GemmGroup* __restrict__ groups, Ptrs ptrs,
+                                                        float* __restrict__ ws) {
     constexpr int BM = S::BM, BN = S::BN, BK = S::BK;
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int TI = WM / 32, TJ = WN / 32;
@@ -416,8 +474,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
     __shared__ __attribute__((aligned(16))) unsigned short As[PL][BM * LDH];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[PL][BN * LDH];
 
-    const TileWork tw = tiles[blockIdx.x];
-    if (tw.group < 0) return;   // padding of the per-XCD tile lists
+  // Entry t of the list belongs to XCD t mod 8, and workgroup b runs on XCD
+  // b mod 8.  Each workgroup starts with its own entry; with a queue (a
+  // persistent grid smaller than the list), it then takes the next free row
+  // of its XCD's list from that XCD's counter.
+  __shared__ int next_row;
+  for (int t = blockIdx.x; t < ntiles;) {
+    const TileWork tw = tiles[t];
+    if (tw.group >= 0) {   // group < 0: padding of the per-XCD lists
     const GemmGroup g = groups[tw.group];
     const unsigned short* __restrict__ A = (const unsigned short*)ptrs.get(g.a_buf) + g.a_off;
     const unsigned short* __restrict__ B = (const unsigned short*)ptrs.get(g.b_buf) + g.b_off;
@@ -481,12 +545,12 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-    const int K = g.K;
-    if (K > 0) gload(0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    const int kb = tw.k0, ke = tw.k1;   // this item's K range (whole stages but the last)
+    if (ke > kb) gload(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
         sstore();
         __syncthreads();
-        if (k0 + BK < K) gload(k0 + BK);
+        if (k0 + BK < ke) gload(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             // plane 0 = hi, PL - 1 = lo, 1 = mid (PL = 3)
@@ -523,6 +587,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
         }
         __syncthreads();
     }
+    // a whole-K item writes C; a split-K part writes its partial tile
+    float* __restrict__ W = ws + (int64_t)(tw.slot < 0 ? 0 : tw.slot) * BM * BN;
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -531,9 +597,36 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const int row = m0 + wm + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-                if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
+                if (tw.slot >= 0) W[(row - m0) * BN + (col - n0)] = acc[i][j][e];
+                else if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
             }
         }
+    }
+    if (!queue) break;
+    if (threadIdx.x == 0) next_row = (int)(gridDim.x >> 3) + atomicAdd(&queue[blockIdx.x & 7], 1);
+    __syncthreads();
+    t = next_row * 8 + (int)(blockIdx.x & 7);
+    __syncthreads();
+  }
+}
+
+// Split K: every output tile of `outs` is the sum of its parts' partial
+// tiles (workspace slots slot0 .. slot0 + nparts - 1), added in part order.
+template <class Ptrs, typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const SplitOut* __restrict__ outs,
+                                                            const GemmGroup* __restrict__ groups, Ptrs ptrs,
+                                                            const T* __restrict__ ws, int BM, int BN) {
+    const SplitOut so = outs[blockIdx.x];
+    const GemmGroup g = groups[so.group];
+    T* __restrict__ C = (T*)ptrs.get(g.c_buf) + g.c_off;
+    const int64_t tile = (int64_t)BM * BN;
+    for (int e = threadIdx.x; e < BM * BN; e += 256) {
+        const int row = so.tm * BM + e / BN, col = so.tn * BN + e % BN;
+        if (row >= g.M || col >= g.N) continue;
+        T sum = ws[so.slot0 * tile + e];
+        for (int p = 1; p < so.nparts; ++p) sum += ws[(so.slot0 + p) * tile + e];
+        C[(int64_t)row * g.ldc + col] = sum;
+    }
 }
 
 // ================================================================ utilities
@@ -811,74 +904,134 @@ int gemm_tile_bn(Prec p, int cfg) { (void)p; return kTileBN[cfg]; }
 int gemm_tile_bk(Prec p, int cfg) { return (p == Prec::F64 ? 16 : 32) * (cfg >= 5 ? 2 : 1); }
 bool gemm_tile_ok(Prec p, int cfg) { return cfg >= 0 && cfg < kNumTileCfg && !(p == Prec::F64 && cfg == 4); }
 
+// Kernel of a (precision, tile configuration); FP32, BF16, bf16x3 and
+// bf16x6 accumulate in FP32, FP64 in FP64.
 template <class Ptrs>
-static void launch_f32_family(int cfg, dim3 grid, hipStream_t s, const TileWork* t, const GemmGroup* g, Ptrs P) {
-    dim3 block(256);
+using GemmF64Fn = void (*)(const TileWork*, int, int*, const GemmGroup*, Ptrs, double*);
+template <class Ptrs>
+using GemmF32Fn = void (*)(const TileWork*, int, int*, const GemmGroup*, Ptrs, float*);
+
+template <class Ptrs>
+static GemmF64Fn<Ptrs> f64_kernel(int cfg) {
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>>), grid, block, 0, s, t, g, P); break;
-        case 1: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>>), grid, block, 0, s, t, g, P); break;
-        case 2: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 32>>), grid, block, 0, s, t, g, P); break;
-        case 3: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 32>>), grid, block, 0, s, t, g, P); break;
-        case 4: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<256, 128, 32>>), grid, block, 0, s, t, g, P); break;
-        case 5: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 64, 64>>), grid, block, 0, s, t, g, P); break;
-        case 6: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<128, 64, 64>>), grid, block, 0, s, t, g, P); break;
-        default: hipLaunchKernelGGL((gemm_f32_kernel<Ptrs, TileShape<64, 128, 64>>), grid, block, 0, s, t, g, P); break;
+        case 0: return gemm_f64_kernel<Ptrs, TileShape<64, 64, 16>>;
+        case 1: return gemm_f64_kernel<Ptrs, TileShape<128, 128, 16>>;
+        case 2: return gemm_f64_kernel<Ptrs, TileShape<128, 64, 16>>;
+        case 3: return gemm_f64_kernel<Ptrs, TileShape<64, 128, 16>>;
+        case 5: return gemm_f64_kernel<Ptrs, TileShape<64, 64, 32>>;
+        case 6: return gemm_f64_kernel<Ptrs, TileShape<128, 64, 32>>;
+        default: return gemm_f64_kernel<Ptrs, TileShape<64, 128, 32>>;
     }
 }
 
 template <class Ptrs, int PL>
-static void launch_bf16_family(int cfg, dim3 grid, hipStream_t s, const TileWork* t, const GemmGroup* g, Ptrs P) {
-    dim3 block(256);
+static GemmF32Fn<Ptrs> bf16_kernel(int cfg) {
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 64, 32>, PL>), grid, block, 0, s, t, g, P); break;
-        case 1: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 128, 32>, PL>), grid, block, 0, s, t, g, P); break;
-        case 2: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 64, 32>, PL>), grid, block, 0, s, t, g, P); break;
-        case 3: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 128, 32>, PL>), grid, block, 0, s, t, g, P); break;
-        case 4: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<256, 128, 32>, PL>), grid, block, 0, s, t, g, P); break;
-        case 5: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 64, 64>, PL>), grid, block, 0, s, t, g, P); break;
-        case 6: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<128, 64, 64>, PL>), grid, block, 0, s, t, g, P); break;
-        default: hipLaunchKernelGGL((gemm_bf16_kernel<Ptrs, TileShape<64, 128, 64>, PL>), grid, block, 0, s, t, g, P); break;
+        case 0: return gemm_bf16_kernel<Ptrs, TileShape<64, 64, 32>, PL>;
+        case 1: return gemm_bf16_kernel<Ptrs, TileShape<128, 128, 32>, PL>;
+        case 2: return gemm_bf16_kernel<Ptrs, TileShape<128, 64, 32>, PL>;
+        case 3: return gemm_bf16_kernel<Ptrs, TileShape<64, 128, 32>, PL>;
+        case 4: return gemm_bf16_kernel<Ptrs, TileShape<256, 128, 32>, PL>;
+        case 5: return gemm_bf16_kernel<Ptrs, TileShape<64, 64, 64>, PL>;
+        case 6: return gemm_bf16_kernel<Ptrs, TileShape<128, 64, 64>, PL>;
+        default: return gemm_bf16_kernel<Ptrs, TileShape<64, 128, 64>, PL>;
     }
 }
 
 template <class Ptrs>
-static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, Ptrs P, Prec prec,
-                          int cfg, hipStream_t s) {
-    if (!gemm_tile_ok(prec, cfg)) fail(SYMTEN_E_INVAL, "gemm: tile configuration not available");
-    dim3 grid((unsigned)ntiles), block(256);
-    switch (prec) {
-        case Prec::F64:
-            switch (cfg) {
-                case 0: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 64, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
-                case 1: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
-                case 2: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 64, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
-                case 3: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 128, 16>>), grid, block, 0, s, d_tiles, d_groups, P); break;
-                case 5: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 64, 32>>), grid, block, 0, s, d_tiles, d_groups, P); break;
-                case 6: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<128, 64, 32>>), grid, block, 0, s, d_tiles, d_groups, P); break;
-                default: hipLaunchKernelGGL((gemm_f64_kernel<Ptrs, TileShape<64, 128, 32>>), grid, block, 0, s, d_tiles, d_groups, P); break;
-            }
-            break;
-        case Prec::F32: launch_f32_family<Ptrs>(cfg, grid, s, d_tiles, d_groups, P); break;
-        case Prec::BF16: launch_bf16_family<Ptrs, 1>(cfg, grid, s, d_tiles, d_groups, P); break;
-        case Prec::BF16X3: launch_bf16_family<Ptrs, 2>(cfg, grid, s, d_tiles, d_groups, P); break;
-        case Prec::BF16X6: launch_bf16_family<Ptrs, 3>(cfg, grid, s, d_tiles, d_groups, P); break;
+static GemmF32Fn<Ptrs> f32_kernel(Prec p, int cfg) {
+    switch (p) {
+        case Prec::BF16: return bf16_kernel<Ptrs, 1>(cfg);
+        case Prec::BF16X3: return bf16_kernel<Ptrs, 2>(cfg);
+        case Prec::BF16X6: return bf16_kernel<Ptrs, 3>(cfg);
+        default: break;
     }
+    switch (cfg) {
+        case 0: return gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>>;
+        case 1: return gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>>;
+        case 2: return gemm_f32_kernel<Ptrs, TileShape<128, 64, 32>>;
+        case 3: return gemm_f32_kernel<Ptrs, TileShape<64, 128, 32>>;
+        case 4: return gemm_f32_kernel<Ptrs, TileShape<256, 128, 32>>;
+        case 5: return gemm_f32_kernel<Ptrs, TileShape<64, 64, 64>>;
+        case 6: return gemm_f32_kernel<Ptrs, TileShape<128, 64, 64>>;
+        default: return gemm_f32_kernel<Ptrs, TileShape<64, 128, 64>>;
+    }
+}
+
+bool gemm_persistent(int ntiles, int capacity) { return ntiles > kPersistentFactor * capacity; }
+
+// Workgroups of a (precision, tile) kernel that the chip runs at once: its
+// occupancy per compute unit times the compute units (a multiple of the 8
+// XCDs), measured once per device and kernel.
+int gemm_capacity(Prec p, int cfg) {
+    if (!gemm_tile_ok(p, cfg)) fail(SYMTEN_E_INVAL, "gemm: tile configuration not available");
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static int cache[kMaxDev][5][kNumTileCfg] = {};
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) fail(SYMTEN_E_CAPACITY, "gemm: device index beyond 63");
+    std::lock_guard<std::mutex> lk(mu);
+    int& c = cache[dev][(int)p][cfg];
+    if (c == 0) {
+        int cus = 0, per_cu = 0;
+        HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const void* fn = p == Prec::F64 ? (const void*)f64_kernel<DevPtrs>(cfg) : (const void*)f32_kernel<DevPtrs>(p, cfg);
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
+        c = std::max(8, std::max(1, per_cu) * std::max(1, cus) / 8 * 8);
+    }
+    return c;
+}
+
+template <class Ptrs>
+static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, Ptrs P, Prec prec,
+                          int cfg, hipStream_t s, const SplitK& sk) {
+    if (!gemm_tile_ok(prec, cfg)) fail(SYMTEN_E_INVAL, "gemm: tile configuration not available");
+    // persistent grid for long lists: as many workgroups as the chip holds at
+    // once, taking further entries from per-XCD counters (the first
+    // kSplitQueueBytes of the workspace, zeroed here in stream order); a list
+    // up to kPersistentFactor times the capacity is left to the
+    // hardware dispatcher (measured as fast, one launch less)
+    const int cap = gemm_capacity(prec, cfg);
+    const bool persistent = gemm_persistent(ntiles, cap);
+    if ((sk.nsplits > 0 || persistent) && !sk.ws) fail(SYMTEN_E_INVAL, "gemm: no workspace for the queue or split K");
+    if (sk.nsplits > 0 && !sk.splits) fail(SYMTEN_E_INVAL, "gemm: split K without its output list");
+    int* queue = persistent ? (int*)sk.ws : nullptr;
+    void* partials = sk.ws ? (char*)sk.ws + kSplitQueueBytes : nullptr;
+    if (persistent) launch_fill_zero(queue, 8 * sizeof(int), s);
+    const dim3 grid((unsigned)(persistent ? cap : ntiles)), block(256);
+    if (prec == Prec::F64)
+        hipLaunchKernelGGL(f64_kernel<Ptrs>(cfg), grid, block, 0, s, d_tiles, ntiles, queue, d_groups, P,
+                           (double*)partials);
+    else
+        hipLaunchKernelGGL(f32_kernel<Ptrs>(prec, cfg), grid, block, 0, s, d_tiles, ntiles, queue, d_groups, P,
+                           (float*)partials);
     HIPCHK(hipGetLastError());
+    if (sk.nsplits > 0) {
+        const int BM = gemm_tile_bm(prec, cfg), BN = gemm_tile_bn(prec, cfg);
+        if (prec == Prec::F64)
+            hipLaunchKernelGGL((splitk_reduce_kernel<Ptrs, double>), dim3(sk.nsplits), dim3(256), 0, s, sk.splits,
+                               d_groups, P, (const double*)partials, BM, BN);
+        else
+            hipLaunchKernelGGL((splitk_reduce_kernel<Ptrs, float>), dim3(sk.nsplits), dim3(256), 0, s, sk.splits,
+                               d_groups, P, (const float*)partials, BM, BN);
+        HIPCHK(hipGetLastError());
+    }
 }
 
 void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
-                     const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s) {
+                     const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s, const SplitK& sk) {
     if (ntiles <= 0) return;
     if (ptrs.size() > 16) fail(SYMTEN_E_CAPACITY, "gemm_launch_arg: more than 16 buffers");
     ArgPtrs P{};
     for (size_t i = 0; i < ptrs.size(); ++i) P.p[i] = ptrs[i];
-    gemm_dispatch(d_tiles, ntiles, d_groups, P, prec, cfg, s);
+    gemm_dispatch(d_tiles, ntiles, d_groups, P, prec, cfg, s, sk);
 }
 
 void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, void* const* d_ptrs,
-                     Prec prec, int cfg, hipStream_t s) {
+                     Prec prec, int cfg, hipStream_t s, const SplitK& sk) {
     if (ntiles <= 0) return;
-    gemm_dispatch(d_tiles, ntiles, d_groups, DevPtrs{d_ptrs}, prec, cfg, s);
+    gemm_dispatch(d_tiles, ntiles, d_groups, DevPtrs{d_ptrs}, prec, cfg, s, sk);
 }
 
 }  // namespace symten

@@ -34,10 +34,6 @@ std::string copy_kernel_name(bool src64, Prec p) {
     static const char* dst[] = {"f64", "f32", "bf16", "bf16x2", "bf16x3"};
     return std::string("copy_kernel<") + (src64 ? "f64" : "f32") + "," + dst[(int)p] + ">";
 }
-void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
-                     const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s);
-int gemm_tile_bm(Prec p, int cfg);
-int gemm_tile_bn(Prec p, int cfg);
 
 // ------------------------------------------------------------------ errors
 [[noreturn]] void fail(int code, const std::string& msg) { throw Error(code, msg); }
@@ -856,14 +852,20 @@ void tune_store_locked(const std::string& key, int cfg) {
 
 void ensure_tiles(TileChoice& tc, const std::vector<GemmGroup>& groups, Prec prec, int cfg) {
     if (tc.tiles[cfg]) return;
-    std::vector<TileWork> tiles;
-    build_tiles(groups, prec, cfg, tiles);
-    tc.ntiles[cfg] = (int)tiles.size();
-    upload_sync(tc.tiles[cfg], tiles.data(), tiles.size() * sizeof(TileWork));
+    TilePlan tp;
+    build_tiles(groups, prec, cfg, tp, true);
+    tc.ntiles[cfg] = (int)tp.tiles.size();
+    upload_sync(tc.tiles[cfg], tp.tiles.data(), tp.tiles.size() * sizeof(TileWork));
+    tc.nsplits[cfg] = (int)tp.splits.size();
+    if (!tp.splits.empty()) upload_sync(tc.splits[cfg], tp.splits.data(), tp.splits.size() * sizeof(SplitOut));
+    const bool persistent = gemm_persistent(tc.ntiles[cfg], gemm_capacity(prec, cfg));
+    tc.ws_bytes[cfg] = tp.partial_tiles * gemm_tile_bm(prec, cfg) * gemm_tile_bn(prec, cfg) *
+                           (prec == Prec::F64 ? 8 : 4) +
+                       (persistent || tp.partial_tiles ? kSplitQueueBytes : 0);
 }
 
 void autotune_gemm(TileChoice& tc, const std::vector<GemmGroup>& groups, Prec prec,
-                   const std::function<void(int, const TileWork*, int)>& launch, hipStream_t s) {
+                   const std::function<void(int)>& launch, hipStream_t s) {
     if (tc.cfg >= 0) return;
     int maxm = 0, maxn = 0;
     for (auto& g : groups) { maxm = std::max(maxm, g.M); maxn = std::max(maxn, g.N); }
@@ -899,11 +901,10 @@ void autotune_gemm(TileChoice& tc, const std::vector<GemmGroup>& groups, Prec pr
     for (int c = 0; c < kNumTileCfg; ++c) {
         if (!gemm_tile_ok(prec, c)) continue;
         ensure_tiles(tc, groups, prec, c);
-        const TileWork* t = (const TileWork*)tc.tiles[c]->ptr;
         HIPCHK(hipEventRecord(e[0], s));
-        launch(c, t, tc.ntiles[c]);   // first run: code-object load, caches
+        launch(c);   // first run: code-object load, caches
         HIPCHK(hipEventRecord(e[1], s));
-        launch(c, t, tc.ntiles[c]);
+        launch(c);
         HIPCHK(hipEventRecord(e[2], s));
         HIPCHK(hipEventSynchronize(e[2]));
         float ms = 0.f;
@@ -922,22 +923,41 @@ int choose_tile_cfg(const ContractPlan& p) {
     return (p.info.max_m >= 128 && p.info.max_n >= 128) ? 1 : 0;
 }
 
-// Tile list of one grouped-GEMM launch, laid out for the 8 XCDs of the chip.
+// Work list of one grouped-GEMM launch, laid out for the 8 XCDs of the chip.
 // Workgroups are dispatched to the XCDs round robin (workgroup p runs on XCD
-// p mod 8), and each XCD has its own L2, so the tiles that share operand
-// panels are kept on one XCD: every group (or, for a group heavier than an
-// eighth of the launch, a contiguous range of its tile rows) goes to one XCD,
-// the XCDs are balanced by greedy longest-first assignment of the work
-// (tiles x K), each XCD's list runs longest K first, and the lists are
-// interleaved with no-op entries (group -1) padding the shorter ones.
-void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::vector<TileWork>& tiles) {
+// p mod 8; the persistent grid is a multiple of 8, so the workgroup that
+// walks entries p, p + G, ... stays on one XCD), and each XCD has its own
+// L2, so the tiles that share operand panels are kept on one XCD: every
+// group (or, for a group heavier than an eighth of the launch, a contiguous
+// range of its tile rows) goes to one XCD, the XCDs are balanced by greedy
+// longest-first assignment of the work (tiles x K), each XCD's list runs
+// longest K first, and the lists are interleaved with no-op entries (group
+// -1) padding the shorter ones.
+//
+// Split K: when the launch has fewer output tiles than the chip holds
+// workgroups at once, the tiles of groups with a long K are cut into parts
+// of at least four K stages (s parts, s <= 8, about enough to fill the chip),
+// each part writing a partial tile to its own workspace slot; a second
+// kernel adds the parts of every tile in part order (deterministic).
+void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, TilePlan& tp, bool allow_split) {
     constexpr int kXcd = 8;
-    const int BM = gemm_tile_bm(prec, cfg), BN = gemm_tile_bn(prec, cfg);
+    const int BM = gemm_tile_bm(prec, cfg), BN = gemm_tile_bn(prec, cfg), BK = gemm_tile_bk(prec, cfg);
     struct Item { int group, r0, r1; double work; };
     double total = 0.0;
+    int64_t ntile = 0;
     for (auto& g : groups) {
         const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
         total += (double)tm * tn * g.K;
+        ntile += (int64_t)tm * tn;
+    }
+    // parts per tile of each group (1: no split)
+    std::vector<int> parts_of(groups.size(), 1);
+    if (allow_split && ntile > 0) {
+        const int64_t cap = gemm_capacity(prec, cfg);
+        const int want = (int)std::min<int64_t>(8, cap / ntile);
+        if (want >= 2)
+            for (size_t gi = 0; gi < groups.size(); ++gi)
+                parts_of[gi] = std::max(1, std::min(want, groups[gi].K / (4 * BK)));
     }
     const double target = total / kXcd;
     std::vector<Item> items;
@@ -962,21 +982,39 @@ void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, std::
     }
     std::vector<std::vector<TileWork>> lists(kXcd);
     size_t longest = 0;
+    int slot = 0;
     for (int x = 0; x < kXcd; ++x) {
         // longest K first inside the XCD so that the heaviest tiles start early
         std::stable_sort(bin[x].begin(), bin[x].end(),
                          [&](const Item& a, const Item& b) { return groups[a.group].K > groups[b.group].K; });
         for (auto& it : bin[x]) {
-            const int tn = (groups[it.group].N + BN - 1) / BN;
+            const GemmGroup& g = groups[it.group];
+            const int tn = (g.N + BN - 1) / BN;
+            const int s = parts_of[it.group];
+            // K parts of equal whole stages; the last one ends at K
+            const int stages = (g.K + BK - 1) / BK;
             for (int i = it.r0; i < it.r1; ++i)
-                for (int j = 0; j < tn; ++j) lists[x].push_back(TileWork{it.group, i, j, 0});
+                for (int j = 0; j < tn; ++j) {
+                    if (s == 1) {
+                        lists[x].push_back(TileWork{it.group, i, j, 0, g.K, -1, 0, 0});
+                        continue;
+                    }
+                    tp.splits.push_back(SplitOut{it.group, i, j, slot, s, 0});
+                    for (int p = 0; p < s; ++p) {
+                        const int k0 = (int)((int64_t)stages * p / s) * BK;
+                        const int k1 = p + 1 == s ? g.K : (int)((int64_t)stages * (p + 1) / s) * BK;
+                        lists[x].push_back(TileWork{it.group, i, j, k0, k1, slot + p, 0, 0});
+                    }
+                    slot += s;
+                }
         }
         longest = std::max(longest, lists[x].size());
     }
-    tiles.reserve(tiles.size() + longest * kXcd);
+    tp.partial_tiles = slot;
+    tp.tiles.reserve(tp.tiles.size() + longest * kXcd);
     for (size_t i = 0; i < longest; ++i)
         for (int x = 0; x < kXcd; ++x)
-            tiles.push_back(i < lists[x].size() ? lists[x][i] : TileWork{-1, 0, 0, 0});
+            tp.tiles.push_back(i < lists[x].size() ? lists[x][i] : TileWork{-1, 0, 0, 0, 0, -1, 0, 0});
 }
 
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix) {
@@ -1095,14 +1133,16 @@ TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& 
         copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->nchunks,
                         {A.data(), B.data(), pa->ptr, pb->ptr}, src64, panel_dst_kind(p.prec), stream);
     });
-    auto launch = [&](int cfg, const TileWork* t, int nt) {
-        gemm_launch_arg(t, nt, (const GemmGroup*)d->groups->ptr, {pa->ptr, pb->ptr, out->data()}, p.prec, cfg, stream);
+    auto launch = [&](int cfg) {
+        const TileChoice& tc = d->tc;
+        BufferPtr ws = tc.ws_bytes[cfg] ? device_alloc(tc.ws_bytes[cfg]) : nullptr;   // split-K partials
+        gemm_launch_arg((const TileWork*)tc.tiles[cfg]->ptr, tc.ntiles[cfg], (const GemmGroup*)d->groups->ptr,
+                        {pa->ptr, pb->ptr, out->data()}, p.prec, cfg, stream, tc.split(cfg, ws ? ws->ptr : nullptr));
     };
     autotune_gemm(d->tc, d->host_groups, p.prec, launch, stream);
     const int cfg = d->tc.cfg;
     profile_launch(gemm_kernel_name(p.prec, cfg), p.info.useful_flops, p.info.gemm_flops,
-                   prof ? gemm_bytes(d->host_groups, pe, out->esize()) : 0, stream,
-                   [&] { launch(cfg, (const TileWork*)d->tc.tiles[cfg]->ptr, d->tc.ntiles[cfg]); });
+                   prof ? gemm_bytes(d->host_groups, pe, out->esize()) : 0, stream, [&] { launch(cfg); });
     // pa/pb return to the pool here; later users are ordered on the same stream
     return out;
 }
@@ -1250,14 +1290,16 @@ std::vector<TensorPtr> run_contractions_batched(const std::vector<std::shared_pt
         copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->nchunks, ptrs,
                         src64, panel_dst_kind(prec), stream);
     });
-    auto launch = [&](int cfg, const TileWork* t, int nt) {
-        gemm_launch_arg(t, nt, (const GemmGroup*)d->groups->ptr, ptrs, prec, cfg, stream);
+    auto launch = [&](int cfg) {
+        const TileChoice& tc = d->tc;
+        BufferPtr ws = tc.ws_bytes[cfg] ? device_alloc(tc.ws_bytes[cfg]) : nullptr;   // split-K partials
+        gemm_launch_arg((const TileWork*)tc.tiles[cfg]->ptr, tc.ntiles[cfg], (const GemmGroup*)d->groups->ptr, ptrs,
+                        prec, cfg, stream, tc.split(cfg, ws ? ws->ptr : nullptr));
     };
     autotune_gemm(d->tc, d->host_groups, prec, launch, stream);
     const int cfg = d->tc.cfg;
     profile_launch(gemm_kernel_name(prec, cfg), d->info.useful_flops, d->info.gemm_flops,
-                   prof ? gemm_bytes(d->host_groups, pe, se) : 0, stream,
-                   [&] { launch(cfg, (const TileWork*)d->tc.tiles[cfg]->ptr, d->tc.ntiles[cfg]); });
+                   prof ? gemm_bytes(d->host_groups, pe, se) : 0, stream, [&] { launch(cfg); });
     return outs;
 }
 

@@ -109,8 +109,9 @@ void contract_noalloc(Tensor& out, const Tensor& A, const Tensor& B, const std::
         groups.push_back(x);
     }
     const int cfg = choose_tile_cfg(p);
-    std::vector<TileWork> tiles;
-    if (!groups.empty()) build_tiles(groups, p.prec, cfg, tiles);
+    TilePlan tp;                 // no split K: no workspace beyond the panels
+    if (!groups.empty()) build_tiles(groups, p.prec, cfg, tp, false);
+    const std::vector<TileWork>& tiles = tp.tiles;
     std::vector<int64_t> prefix;
     copy_prefix(p.copies, prefix);
     // the charge-sector products (buffer 0) scattered into out's blocks (buffer 1)
@@ -135,7 +136,8 @@ void contract_noalloc(Tensor& out, const Tensor& A, const Tensor& B, const std::
     const int64_t o_tiles = blob.put(tiles.data(), tiles.size() * sizeof(TileWork));
     const int64_t o_scat = blob.put(scatter.data(), scatter.size() * sizeof(CopyTask));
     const int64_t o_sprefix = blob.put(sprefix.data(), sprefix.size() * sizeof(int64_t));
-    const int64_t o_pa = align256((int64_t)blob.bytes.size());
+    const int64_t o_queue = align256((int64_t)blob.bytes.size());   // the persistent grid's counters
+    const int64_t o_pa = align256(o_queue + kSplitQueueBytes);
     const int64_t o_pb = align256(o_pa + (int64_t)pe * pl * p.a_panel_elems);
     const int64_t o_c = align256(o_pb + (int64_t)pe * pl * p.b_panel_elems);
     const int64_t need = o_c + (int64_t)oe * p.out_elems;
@@ -156,7 +158,7 @@ void contract_noalloc(Tensor& out, const Tensor& A, const Tensor& B, const std::
     copy_launch_arg((const CopyTask*)(w + o_tasks), (const int64_t*)(w + o_prefix), (int)p.copies.size(),
                     prefix.back(), {A.data(), B.data(), w + o_pa, w + o_pb}, src64, panel_dst_kind(p.prec), s);
     gemm_launch_arg((const TileWork*)(w + o_tiles), (int)tiles.size(), (const GemmGroup*)(w + o_groups),
-                    {w + o_pa, w + o_pb, w + o_c}, p.prec, cfg, s);
+                    {w + o_pa, w + o_pb, w + o_c}, p.prec, cfg, s, SplitK{nullptr, 0, w + o_queue});
     copy_launch_arg((const CopyTask*)(w + o_scat), (const int64_t*)(w + o_sprefix), (int)scatter.size(),
                     sprefix.back(), {w + o_c, out.data()}, src64, src64 ? 1 : 0, s);
 }

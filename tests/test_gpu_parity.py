@@ -230,12 +230,19 @@ def test_batched_corners_match_single_and_oracle():
     cfgs = [dict(phys={-1: 1, 1: 1}, virt=d["virt"], chi=d["chi"], flux=1) for d in draws]
     devs = [device_side(cf, 1813, "f32", batch=b) for b, cf in enumerate(cfgs)]
     args = [[d["C1"] for d in devs], [d["T1"] for d in devs], [d["T4"] for d in devs], [d["a"] for d in devs]]
+    first = None
     for use_graph in (False, True):
         for rep in range(3):
             outs, info = st.enlarged_corners_batched(*args, prec="bf16x3", use_graph=use_graph)
+            vals = [o.download() for o in outs]
+            if first is None:
+                first = vals
+            # replays and eager calls of the batch: bit for bit
+            assert all(np.array_equal(x, y) for x, y in zip(vals, first))
             for b, (cf, dv, o) in enumerate(zip(cfgs, devs, outs)):
                 single, _ = st.enlarged_corner(1, dv["C1"], dv["T1"], dv["T4"], dv["a"], prec="bf16x3")
-                assert np.array_equal(o.download(), single.download())
+                # the single call may add K parts (fewer tiles): FP32 reordering only
+                assert rel(o.download(), single.download()) <= 1e-6
                 if rep == 0 and not use_graph:
                     w, T, a, _ = oracle_side(cf, 1813, batch=b)
                     ref = u1.enlarged_corners(w, T, a)[0].transpose(2, 0, 3, 1)

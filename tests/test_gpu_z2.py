@@ -260,20 +260,27 @@ def test_z2_heisenberg_x_polarised_product_state():
 def test_z2_batched_corners_match_single():
     """Four Z2 corner-1 contractions of different chi in one batched call,
     eagerly and through the recorded graph (replayed): every output equals
-    the single-corner call bit for bit (the same sector products, K swept
-    in the same order), and the FP64 single corner (covered by the Z2 move
-    tests against the dense oracle) to the precision's tolerance."""
+    the single-corner call to FP32 rounding (the same sector products; a
+    launch with few tiles may add K parts, which reorders the sums), every
+    replay equals the first call bit for bit, and the FP64 single corner
+    (covered by the Z2 move tests against the dense oracle) to the
+    precision's tolerance."""
     envs = [_z2_env(60 + 10 * b, chi={0: 4 + b, 1: 3 + 2 * b}) for b in range(4)]
     d64 = [{n: _dev(x, l, 0) for n, (x, l) in e.items()} for e in envs]
     ref = [to_dense(st.enlarged_corner(1, d["C1"], d["T1"], d["T4"], d["a"], prec="f64")[0]) for d in d64]
     devs = [{n: _dev(x, l, 0, "f32") for n, (x, l) in e.items()} for e in envs]
     args = [[d[k] for d in devs] for k in ("C1", "T1", "T4", "a")]
     for prec, tol in (("f32", 1e-6), ("bf16x3", 1e-5)):
+        first = None
         for use_graph in (False, True):
             for rep in range(2):
                 outs, info = st.enlarged_corners_batched(*args, prec=prec, use_graph=use_graph)
+                vals = [o.download() for o in outs]
+                if first is None:
+                    first = vals
+                assert all(np.array_equal(x, y) for x, y in zip(vals, first))
                 for d, o, r in zip(devs, outs, ref):
                     single, _ = st.enlarged_corner(1, d["C1"], d["T1"], d["T4"], d["a"], prec=prec)
                     assert o.legs() == single.legs()
-                    assert np.array_equal(o.download(), single.download())
+                    assert rel(o.download(), single.download()) <= 1e-6
                     assert rel(to_dense(o), r) <= tol
