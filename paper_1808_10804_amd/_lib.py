@@ -3,7 +3,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsymten.so")
+# SYMTEN_LIB selects another build of the same library (the host-sanitized one)
+LIB_PATH = os.environ.get("SYMTEN_LIB") or os.path.join(HERE, "libsymten.so")
 
 OK = 0
 ERRORS = {-1: "E_INVAL", -2: "E_LEGS", -3: "E_SYM", -4: "E_NOMEM", -5: "E_HIP",

@@ -31,6 +31,48 @@ def test_cg_matches_oracle_large_spins(args):
     assert abs(st.su2_cg(*args) - su2.cg(*args)) < 1e-13
 
 
+def _cg_range_points(n, seed):
+    """Coefficients across the library's advertised range (doubled spins
+    0..64, J up to 128): random points plus the extremes (J at either end of
+    the triangle, stretched and zero projections)."""
+    rng = np.random.default_rng(seed)
+    pts = [(64, 64, 64, -64, 0, 0), (64, 64, 64, 64, 128, 128), (64, 0, 64, 0, 128, 0), (64, 0, 64, 0, 64, 0),
+           (64, 2, 64, 0, 2, 2), (63, -63, 1, 1, 62, -62), (64, 30, 62, -31, 96, -1), (1, 1, 64, -64, 63, -63)]
+    while len(pts) < n:
+        tj1, tj2 = (int(x) for x in rng.integers(0, 65, 2))
+        tJ = int(rng.choice(np.arange(abs(tj1 - tj2), tj1 + tj2 + 1, 2)))
+        tm1 = int(rng.choice(su2.ms(tj1)))
+        cands = [m for m in su2.ms(tj2) if abs(tm1 + m) <= tJ]
+        if cands:
+            tm2 = int(rng.choice(cands))
+            pts.append((tj1, tm1, tj2, tm2, tJ, tm1 + tm2))
+    return pts
+
+
+def test_cg_matches_sympy_across_advertised_range():
+    """Racah's alternating sum in extended precision keeps FP64 accuracy up to
+    2j = 64: absolute error at most a few ulps of 1, relative error 1e-12."""
+    worst_abs = worst_rel = 0.0
+    for args in _cg_range_points(300, 11):
+        got, ref = st.su2_cg(*args), su2.cg(*args)
+        worst_abs = max(worst_abs, abs(got - ref))
+        if ref != 0.0:
+            worst_rel = max(worst_rel, abs(got - ref) / abs(ref))
+    assert worst_abs < 4e-15, worst_abs
+    assert worst_rel < 1e-12, worst_rel
+
+
+def test_cg_orthogonality_at_large_spin():
+    """Sum over m1 + m2 = M of <j1 m1; j2 m2|J M><j1 m1; j2 m2|J' M> = delta_JJ'
+    at j1 = 32, j2 = 31 (every J, M = 1 and M = 61)."""
+    tj1, tj2 = 64, 62
+    for tM in (2, 122):
+        Js = [J for J in range(abs(tj1 - tj2), tj1 + tj2 + 1, 2) if J >= abs(tM)]
+        rows = [(m1, tM - m1) for m1 in su2.ms(tj1) if abs(tM - m1) <= tj2]
+        U = np.array([[st.su2_cg(tj1, m1, tj2, m2, J, tM) for J in Js] for m1, m2 in rows])
+        assert np.abs(U.T @ U - np.eye(len(Js))).max() < 1e-13
+
+
 def test_cg_selection_rules():
     assert st.su2_cg(2, 0, 2, 0, 2, 0) == 0.0      # parity zero of <1 0; 1 0 | 1 0>
     assert st.su2_cg(1, 1, 1, 1, 0, 2) == 0.0      # |M| > J
