@@ -29,7 +29,7 @@ namespace symten {
 
 void upload_sync(BufferPtr& buf, const void* host, size_t bytes);
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix);
-void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t npieces,
                      void* const* d_ptrs, bool src_f64, int dst_kind, hipStream_t s);
 int choose_tile_cfg(const ContractPlan& p);
 void launch_scale_cols(double* X, int ld, int rows, int cols, const double* s, double e, hipStream_t st);
@@ -2050,11 +2050,15 @@ namespace {
 struct BatchStep {
     std::vector<std::shared_ptr<ContractPlan>> plans;
     BufferPtr tasks, prefix, groups, ptrs, apanel, bpanel, out, ws;
+    BufferPtr scatter;            // scatter tables when the GEMM writes the next step's A panels
     int ntasks = 0;
-    int64_t nchunks = 0;
+    int64_t npieces = 0;
     TileChoice tc;
     std::vector<GemmGroup> host_groups;
-    std::vector<int64_t> c_base;
+    std::vector<int64_t> c_base, a_base;
+    std::vector<int> group_base;  // first group of each contraction
+    int64_t ap = 0;               // elements of one plane of the A panels
+    void* next_apanel = nullptr;  // the A panels the scatter epilogue writes
     std::vector<void*> table;     // host copy of the pointer table
     bool src_f64 = false, panel_f64 = false;
     Prec prec = Prec::F32;
@@ -2077,29 +2081,42 @@ std::mutex g_batch_mu;
 std::map<std::string, std::shared_ptr<BatchState>> g_batch;
 
 // Concatenate the per-contraction plans of one step into one launch pair.
-void build_step(BatchStep& B, const std::vector<const Tensor*>& As, const std::vector<const Tensor*>& Bs, int n) {
+// fused_in: the previous step's GEMM writes this step's A panels (the A-side
+// gathers are left out); fused_out: this step's GEMM writes the next step's A
+// panels (no output buffer).
+void build_step(BatchStep& B, const std::vector<const Tensor*>& As, const std::vector<const Tensor*>& Bs, int n,
+                bool fused_in = false, bool fused_out = false) {
     std::vector<CopyTask> tasks;
     std::vector<GemmGroup> groups;
     std::vector<int64_t> a_base(n), b_base(n);
     int64_t ap = 0, bp = 0, cp = 0;
     B.c_base.assign(n, 0);
+    B.group_base.assign(n, 0);
     B.info = {};
     for (int i = 0; i < n; ++i) {
         const ContractPlan& p = *B.plans[i];
         a_base[i] = ap;
         b_base[i] = bp;
         B.c_base[i] = cp;
+        B.group_base[i] = (int)groups.size();
         ap += (p.a_panel_elems + 31) / 32 * 32;
         bp += (p.b_panel_elems + 31) / 32 * 32;
         cp += (p.out_elems + 31) / 32 * 32;
         add_info(B.info, p.info);
+        size_t skipped = 0;
         for (CopyTask t : p.copies) {
+            if (fused_in && t.src_buf == 0) {   // written by the previous step's GEMM
+                ++skipped;
+                continue;
+            }
             if (t.src_buf == 0) t.src_buf = i;
             else if (t.src_buf == 1) t.src_buf = n + i;
             if (t.dst_buf == 2) { t.dst_buf = 2 * n; t.dst_off += a_base[i]; }
             else { t.dst_buf = 2 * n + 1; t.dst_off += b_base[i]; }
             tasks.push_back(t);
         }
+        if (fused_in && skipped != p.a_maps.size())
+            fail(SYMTEN_E_INVAL, "internal: fused step without a block map for every A-side gather");
         for (auto& g : p.groups) {
             GemmGroup x{};
             x.a_off = g.a_off + a_base[i];
@@ -2141,29 +2158,66 @@ void build_step(BatchStep& B, const std::vector<const Tensor*>& As, const std::v
     }
     const size_t pe = panel_esize(B.prec) * pl;
     const size_t oe = B.src_f64 ? 8 : 4;
+    B.a_base = a_base;
+    B.ap = ap;
     B.apanel = device_alloc(std::max<int64_t>(ap, 1) * pe);
     B.bpanel = device_alloc(std::max<int64_t>(bp, 1) * pe);
-    B.out = device_alloc(std::max<int64_t>(cp, 1) * oe);
+    B.out = device_alloc(std::max<int64_t>(fused_out ? 1 : cp, 1) * oe);
     std::vector<int64_t> prefix;
     copy_prefix(tasks, prefix);
     B.ntasks = (int)tasks.size();
-    B.nchunks = prefix.back();
+    B.npieces = prefix.back();
     upload_sync(B.tasks, tasks.data(), tasks.size() * sizeof(CopyTask));
     upload_sync(B.prefix, prefix.data(), prefix.size() * sizeof(int64_t));
     B.host_groups = groups;
     upload_sync(B.groups, groups.data(), groups.size() * sizeof(GemmGroup));
-    B.ptrs = device_alloc(sizeof(void*) * (2 * n + 3));
+    B.ptrs = device_alloc(sizeof(void*) * (2 * n + 5));
     B.copy_bytes = symten::copy_bytes(tasks, oe, pe);
     B.gemm_bytes = symten::gemm_bytes(groups, pe, oe);
 }
 
+// Step K's GEMM writes step K1's A panels: the products of every output
+// block that step K1 gathers go, split into bf16 planes, to the panel
+// positions of step K1's A-side block maps (the same values and rounding as
+// the gather of a stored product).  Step K's groups get scatter tables:
+// per row its row block and the multi-index over the A-side free legs, per
+// column the same over the B-side free legs, per (row block, column block)
+// the panel offset and leg strides (d0 < 0: a block step K1 does not read).
+void fuse_steps(BatchStep& K, const std::vector<const Tensor*>& As, const std::vector<const Tensor*>& Bs,
+                const BatchStep& K1, int n) {
+    std::vector<int> tab;
+    const int pl = panel_planes(K.prec);
+    int64_t written = 0;
+    for (int i = 0; i < n; ++i)
+        written += append_scatter_tables(*K.plans[i], *As[i], *Bs[i], *K1.plans[i], K1.a_base[i],
+                                         K.host_groups.data() + K.group_base[i], tab);
+    for (GemmGroup& G : K.host_groups) {
+        G.s_buf = 2 * n + 3;
+        G.c_buf = 2 * n + 4;
+        G.c_lo = K1.ap;
+    }
+    validate_scatter(K.host_groups, tab, pl * std::max<int64_t>(K1.ap, 1), pl);
+    upload_sync(K.scatter, tab.data(), tab.size() * sizeof(int));
+    upload_sync(K.groups, K.host_groups.data(), K.host_groups.size() * sizeof(GemmGroup));
+    K.next_apanel = K1.apanel->ptr;
+    // algorithmic bytes: panels read, products written once in all planes
+    const size_t pe = panel_esize(K.prec) * pl;
+    K.gemm_bytes = 0;
+    for (const GemmGroup& g : K.host_groups) K.gemm_bytes += (int64_t)pe * ((int64_t)g.M * g.K + (int64_t)g.N * g.K);
+    K.gemm_bytes += (int64_t)pe * written;
+}
+
 void set_table(BatchStep& B, const std::vector<void*>& a, const std::vector<void*>& b) {
     const int n = (int)a.size();
-    std::vector<void*> t(2 * n + 3);
+    std::vector<void*> t(2 * n + 5, nullptr);
     for (int i = 0; i < n; ++i) { t[i] = a[i]; t[n + i] = b[i]; }
     t[2 * n] = B.apanel->ptr;
     t[2 * n + 1] = B.bpanel->ptr;
     t[2 * n + 2] = B.out->ptr;
+    if (B.scatter) {
+        t[2 * n + 3] = B.scatter->ptr;
+        t[2 * n + 4] = B.next_apanel;
+    }
     if (t != B.table) {
         HIPCHK(hipMemcpy(B.ptrs->ptr, t.data(), t.size() * sizeof(void*), hipMemcpyHostToDevice));
         B.table = t;
@@ -2174,7 +2228,7 @@ void set_table(BatchStep& B, const std::vector<void*>& a, const std::vector<void
 // (never under graph capture) the tile configuration is chosen first.
 void run_step(BatchStep& B, hipStream_t s, bool tune = false) {
     profile_launch(copy_kernel_name(B.src_f64, B.prec) + ",batched", 0, 0, B.copy_bytes, s, [&] {
-        copy_launch_dev((const CopyTask*)B.tasks->ptr, (const int64_t*)B.prefix->ptr, B.ntasks, B.nchunks,
+        copy_launch_dev((const CopyTask*)B.tasks->ptr, (const int64_t*)B.prefix->ptr, B.ntasks, B.npieces,
                         (void* const*)B.ptrs->ptr, B.src_f64, panel_dst_kind(B.prec), s);
     });
     auto launch = [&](int cfg) {
@@ -2185,7 +2239,8 @@ void run_step(BatchStep& B, hipStream_t s, bool tune = false) {
             B.ws = device_alloc(B.tc.ws_bytes[cfg]);
         }
         gemm_launch_dev((const TileWork*)B.tc.tiles[cfg]->ptr, B.tc.ntiles[cfg], (const GemmGroup*)B.groups->ptr,
-                        (void* const*)B.ptrs->ptr, B.prec, cfg, s, B.tc.split(cfg, B.ws ? B.ws->ptr : nullptr));
+                        (void* const*)B.ptrs->ptr, B.prec, cfg, s, B.tc.split(cfg, B.ws ? B.ws->ptr : nullptr),
+                        B.scatter != nullptr);
     };
     if (tune) autotune_gemm(B.tc, B.host_groups, B.prec, launch, s);
     if (B.tc.cfg < 0) fail(SYMTEN_E_INVAL, "internal: batched GEMM launched before tuning");
@@ -2233,7 +2288,11 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, co
             auto it = g_batch.find(key);
             if (it != g_batch.end()) st = it->second;
         }
-        const CornerSpec sp = corner_spec(1);
+        // The chain of corner 1 with step 1's output ordered [xa, x1, u]:
+        // step 2's products [x1, u, y, l] then reach step 3's A panels
+        // (contracted over (l, u), u fastest) with consecutive rows on
+        // consecutive positions.  Same corners as corner(1, ...).
+        const std::vector<int> l1a{1}, l1b{0}, perm1{0, 2, 1}, l2a{0}, l2b{2}, l3a{3, 1}, l3b{0, 1};
         if (!st) {
             st = std::make_shared<BatchState>();
             st->n = n;
@@ -2245,22 +2304,26 @@ int symten_enlarged_corners_batched(int n, symten_t* out, const symten_t* Cs, co
                 B3.push_back(&T(as[i]));
             }
             for (int i = 0; i < n; ++i)
-                st->step[0].plans.push_back(get_plan(*A1[i], *B1[i], 1, sp.l1a.data(), sp.l1b.data(), nullptr, prec));
+                st->step[0].plans.push_back(get_plan(*A1[i], *B1[i], 1, l1a.data(), l1b.data(), perm1.data(), prec));
             build_step(st->step[0], A1, B1, n);
             st->outs[0] = step_outputs(st->step[0], n, st->step[0].out);
             std::vector<const Tensor*> A2;
             for (int i = 0; i < n; ++i) {
                 A2.push_back(st->outs[0][i].get());
-                st->step[1].plans.push_back(get_plan(*A2[i], *B2[i], 1, sp.l2a.data(), sp.l2b.data(), nullptr, prec));
+                st->step[1].plans.push_back(get_plan(*A2[i], *B2[i], 1, l2a.data(), l2b.data(), nullptr, prec));
             }
-            build_step(st->step[1], A2, B2, n);
+            // bf16 precisions: step 2's GEMM writes step 3's A panels itself
+            const Prec p2 = st->step[1].plans[0]->prec;
+            const bool fuse = p2 == Prec::BF16 || p2 == Prec::BF16X3 || p2 == Prec::BF16X6;
+            build_step(st->step[1], A2, B2, n, false, fuse);
             st->outs[1] = step_outputs(st->step[1], n, st->step[1].out);
             std::vector<const Tensor*> A3;
             for (int i = 0; i < n; ++i) {
                 A3.push_back(st->outs[1][i].get());
-                st->step[2].plans.push_back(get_plan(*A3[i], *B3[i], 2, sp.l3a.data(), sp.l3b.data(), nullptr, prec));
+                st->step[2].plans.push_back(get_plan(*A3[i], *B3[i], 2, l3a.data(), l3b.data(), nullptr, prec));
             }
-            build_step(st->step[2], A3, B3, n);
+            build_step(st->step[2], A3, B3, n, fuse, false);
+            if (fuse) fuse_steps(st->step[1], A2, B2, st->step[2], n);
             std::lock_guard<std::mutex> lk(g_batch_mu);
             if (g_batch.size() > 16) g_batch.clear();
             g_batch[key] = st;

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -84,6 +85,28 @@ struct DeviceBuffer {
 // Caller-registered device allocator (null fns: the library's own pool).
 void set_user_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, size_t, void*), void* ctx);
 
+// A tensor's layout signature, computed on first use and kept: copies start
+// without one (they are usually edited before use) and rebuild_index(), the
+// last step of every layout edit, drops it.
+struct SignatureMemo {
+    std::mutex mu;
+    std::string sig;
+    bool valid = false;
+    SignatureMemo() = default;
+    SignatureMemo(const SignatureMemo&) {}
+    SignatureMemo& operator=(const SignatureMemo&) {
+        std::lock_guard<std::mutex> lk(mu);
+        valid = false;
+        sig.clear();
+        return *this;
+    }
+    void reset() {
+        std::lock_guard<std::mutex> lk(mu);
+        valid = false;
+        sig.clear();
+    }
+};
+
 struct Tensor {
     int group = SYMTEN_U1;
     int flux = 0;
@@ -94,6 +117,7 @@ struct Tensor {
     BufferPtr buf;                           // null for metadata-only handles
     int64_t elems = 0;                       // buffer size in elements
     bool meta_only = true;
+    mutable SignatureMemo memo;              // tensor_signature's result
 
     int rank() const { return (int)legs.size(); }
     int64_t nnz() const { int64_t s = 0; for (auto& b : blocks) s += b.size; return s; }
@@ -139,7 +163,7 @@ struct CopyTask {
     double scale;       // multiplies the copied value (SU(2) recoupling scalar)
     int64_t lo_off;     // split panels: plane p starts p * lo_off elements after the hi plane
     int nextra;         // number of extra sources (0 .. kMaxExtraSrc)
-    int pad_;
+    int nchunks;        // chunks of the task (copy_task_chunks)
     int64_t xsrc_off[kMaxExtraSrc];
     double xscale[kMaxExtraSrc];
     // transposing copy (the destination's unit-stride dim is not the
@@ -147,8 +171,11 @@ struct CopyTask {
     // through LDS, read along dim tr_in, written along dim tr_out; -1: direct
     int tr_in, tr_out, lg_out, pad2_;
 };
-// chunks (workgroups) of a copy task: 1024 elements, or one LDS tile
+// chunks of a copy task: 1024 elements, or one LDS tile of 1024
 int64_t copy_task_chunks(const CopyTask& t);
+// A workgroup of the gather takes up to kCopyGroup consecutive chunks of one
+// task (a piece); the prefix sums handed to the copy launches count pieces.
+constexpr int kCopyGroup = 4;
 
 struct GemmGroup {
     int64_t a_off, b_off, c_off;   // element offsets into their buffers
@@ -156,9 +183,20 @@ struct GemmGroup {
     int lda, ldb, ldc;             // A: [M][lda] (K contiguous); B: [N][ldb]; C: [M][ldc]
     int a_buf, b_buf, c_buf;
     int tiles_n;                   // tiles along N (for tile decoding)
-    int pad_;
+    int scatter;                   // 0: C written at c_off; 1: scatter epilogue (below)
     int64_t a_lo, b_lo;            // split panels: plane p starts p * a_lo (p * b_lo) elements in
+    // Scatter epilogue (bf16 kernels): element (i, j) goes, split into the
+    // kernel's bf16 planes (plane p at p * c_lo), to c_buf at
+    //   d0 + sum_l rows[i].idx[l] * sr[l] + sum_l cols[j].idx[l] * sc[l]
+    // with (d0, sr, sc) the entry (rows[i].blk, cols[j].blk) of the block
+    // table (d0 < 0: the element is dropped).  The tables are int32 records
+    // in buffer s_buf: rows {blk, idx[3]}, cols {blk, idx[3]}, blocks
+    // {d0, sr[3], sc[3], pad}, starting at s_rows, s_cols, s_blocks (in
+    // ints); the block table has s_ncb entries per row block.
+    int s_buf, s_ncb;
+    int64_t s_rows, s_cols, s_blocks, c_lo;
 };
+constexpr int kScatterLegs = 3;   // row (column) legs a scatter epilogue decodes
 
 
 // One work item of a grouped-GEMM launch: output tile (tm, tn) of a group,
@@ -208,7 +246,7 @@ inline int panel_vw(Prec p) { return p == Prec::F64 ? 2 : (p == Prec::F32 ? 4 : 
 // Gather launch over a task list already on the device (at most 16 buffers).
 // dst_kind: 0 float, 1 double, 2 bf16, 3 bf16 hi/lo split, 4 accumulate
 // (dst += scale * src, source type), 5 bf16 hi/mid/lo split.
-void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t npieces,
                      const std::vector<void*>& ptrs, bool src_f64, int dst_kind, hipStream_t s);
 
 void launch_cast(const void* src, bool src_f64, void* dst, bool dst_f64, int64_t n, hipStream_t s);
@@ -253,10 +291,22 @@ struct GroupPlan {
     std::vector<int> row_off, col_off;
 };
 
+// Where the elements of one block of A land in the A panels: element
+// (idx_0 .. idx_{R-1}) of block `block` (legs in A's order) goes to panel
+// offset dst_off + sum_l idx_l * dstride[l].  One entry per A block that a
+// U(1) or Z2 plan gathers (with scale 1 and one source).
+struct PanelMap {
+    int block;
+    int64_t dst_off;
+    std::vector<int64_t> dstride;
+};
+
 struct ContractPlan {
     TensorPtr out_meta;                   // metadata of the output (no buffer)
     std::vector<GroupPlan> groups;
     std::vector<CopyTask> copies;         // bufs: 0 = A data, 1 = B data, 2 = A panels, 3 = B panels
+    std::vector<PanelMap> a_maps;         // the A-side copies of `copies` as block maps (abelian plans)
+    std::vector<int> conA, conB;          // contracted legs (abelian plans)
     int64_t a_panel_elems = 0, b_panel_elems = 0, out_elems = 0;
     symten_plan_stats info{};
     Prec prec = Prec::F32;
@@ -293,8 +343,9 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
 // walks the list; split-K parts are added afterwards in a fixed order.
 void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups,
                      const std::vector<void*>& ptrs, Prec prec, int cfg, hipStream_t s, const SplitK& sk = {});
+// scatter: every group of the launch has the scatter epilogue (bf16 precisions)
 void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, void* const* d_ptrs,
-                     Prec prec, int cfg, hipStream_t s, const SplitK& sk = {});
+                     Prec prec, int cfg, hipStream_t s, const SplitK& sk = {}, bool scatter = false);
 // Workgroups of a tile configuration that the chip holds at once (occupancy
 // times compute units).
 int gemm_capacity(Prec p, int cfg);
@@ -335,6 +386,18 @@ void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, TileP
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix);
 // planes: panel planes a split destination writes (plane p at p * lo_off)
 void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_t>& buf_elems, int planes = 1);
+// Scatter tables (appended to `tab`) for the groups of plan p, whose products
+// are the A operand of plan q: each product goes to the position of q's A
+// panels (offset by a_base) that q's gather would copy it to.  Sets the
+// table fields of groups[0 .. p.groups.size()) (the launch's copies of p's
+// groups, in order); the caller sets s_buf, c_buf and c_lo.  Returns the
+// number of products that reach a panel.
+int64_t append_scatter_tables(const ContractPlan& p, const Tensor& A, const Tensor& B, const ContractPlan& q,
+                              int64_t a_base, GemmGroup* groups, std::vector<int>& tab);
+// The scatter groups' tables (int32 records in `tab`) and every destination
+// they reach, against a destination of dst_elems elements with `planes` planes.
+void validate_scatter(const std::vector<GemmGroup>& groups, const std::vector<int>& tab, int64_t dst_elems,
+                      int planes);
 void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int64_t>& buf_elems, int vw,
                      int planes = 1);
 
@@ -366,7 +429,7 @@ struct GatherPlan {
     TensorPtr meta;            // output tensor without storage
     BufferPtr tasks, prefix;   // device copy tasks (buffer 0: source, 1: output)
     int ntasks = 0;
-    int64_t nchunks = 0;
+    int64_t npieces = 0;
     bool zero = false;         // output parts not covered by a task are zero
     bool view = false;         // the output's blocks are views of the source's buffer
 };

@@ -62,6 +62,20 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
 // planes (each plane lo_off elements after the previous one).
 enum : int { kDstF32 = 0, kDstF64 = 1, kDstBF16 = 2, kDstSplit = 3, kDstAcc = 4, kDstSplit3 = 5 };
 
+// x as PL bf16 planes: plane 0 = bf16(x); with two planes plane 1 =
+// bf16(x - plane 0); with three, plane 1 = bf16(x - plane 0) and plane 2 =
+// bf16(x - plane 0 - plane 1) (the differences are exact in FP32).  The
+// gather's split destinations store the same values.
+template <int PL>
+__device__ __forceinline__ void bf16_planes(float x, unsigned short* h) {
+    h[0] = f32_to_bf16_rn(x);
+    if constexpr (PL >= 2) {
+        const float r1 = x - bf16_to_f32(h[0]);
+        h[1] = f32_to_bf16_rn(r1);
+        if constexpr (PL == 3) h[2] = f32_to_bf16_rn(r1 - bf16_to_f32(h[1]));
+    }
+}
+
 // One destination element of the gather: conversion to the destination kind.
 template <typename TS, int DK, typename AT>
 __device__ __forceinline__ void copy_store(void* dstv, int64_t dofs, int64_t lo_off, AT sv, bool have_src) {
@@ -87,43 +101,38 @@ __device__ __forceinline__ void copy_store(void* dstv, int64_t dofs, int64_t lo_
     }
 }
 
-// Strided gather over a task list.  Each workgroup takes one chunk of one
-// task: 1024 consecutive elements (direct copies), or one tile of a
-// transposing copy, read along the source's unit-stride dim into LDS and
-// written along the destination's unit-stride dim.  A task may sum several
-// equally strided sources with their scalars (SU(2) tree-sibling blocks).
-template <class Ptrs, typename TS, int DK>
-__global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __restrict__ tasks,
-                                                            const int64_t* __restrict__ chunk_prefix,
-                                                            int ntasks, Ptrs ptrs) {
-    using AT = std::conditional_t<DK == kDstF64, double, TS>;   // arithmetic type
-    __shared__ AT tile[kCopyChunk + 128];
-    const int64_t chunk = blockIdx.x;
-    int lo = 0, hi = ntasks - 1;
-    while (lo < hi) {                       // last task with prefix <= chunk
-        int mid = (lo + hi + 1) >> 1;
-        if (chunk_prefix[mid] <= chunk) lo = mid; else hi = mid - 1;
-    }
-    const CopyTask& T = tasks[lo];
-    const int64_t local = chunk - chunk_prefix[lo];
-    const TS* __restrict__ src = T.src_buf >= 0 ? (const TS*)ptrs.get(T.src_buf) : nullptr;
-    void* dstv = ptrs.get(T.dst_buf);
+// Strided gather over a task list.  A task's elements are cut into chunks:
+// 1024 consecutive elements of a direct copy, or one tile of a transposing
+// copy (read along the source's unit-stride dim into LDS, written along the
+// destination's unit-stride dim).  Each workgroup takes one piece, up to
+// kCopyGroup consecutive chunks of one task: it finds the task by bisection
+// over the pieces' prefix sums, decodes it once and issues the loads of all
+// its chunks before the first store.  A task may sum several equally strided
+// sources with their scalars (SU(2) tree-sibling blocks).
+constexpr int kCopyRun = kCopyChunk / kCopyThreads;   // elements per thread and chunk
+constexpr int kTileLds = kCopyChunk + 64;              // LDS elements of one tile
+
+template <typename TS, int DK, typename AT, typename G>
+__device__ __forceinline__ void copy_tiles(const CopyTask& T, int64_t first, int ng, void* dstv, AT* tile,
+                                           G gather) {
+    // TO destination-contiguous x TI source-contiguous elements per tile
     const int rank = T.rank;
-    const double scale = T.scale;
-    auto gather = [&](int64_t so) -> AT {
-        AT sv = (AT)src[so] * (AT)scale;
-        const int64_t rel = so - T.src_off;
-        for (int t = 0; t < T.nextra; ++t) sv += (AT)src[T.xsrc_off[t] + rel] * (AT)T.xscale[t];
-        return sv;
-    };
-    if (T.tr_in >= 0) {
-        // ---- transposing tile: TO destination-contiguous x TI source-contiguous
-        const int din = T.tr_in, dout = T.tr_out;
-        const int lgo = T.lg_out, lgi = 10 - T.lg_out;
-        const int TO = 1 << lgo, TI = 1 << lgi;
-        const int Din = T.dims[din], Dout = T.dims[dout];
-        const int nto = (Dout + TO - 1) >> lgo, nti = (Din + TI - 1) >> lgi;
-        int64_t r = local;
+    const int din = T.tr_in, dout = T.tr_out;
+    const int lgo = T.lg_out, lgi = 10 - T.lg_out;
+    const int TO = 1 << lgo, TI = 1 << lgi;
+    const int LS = TI + 1;   // LDS row stride
+    const int Din = T.dims[din], Dout = T.dims[dout];
+    const int nto = (Dout + TO - 1) >> lgo, nti = (Din + TI - 1) >> lgi;
+    const int64_t ssi = T.sstride[din], sso = T.sstride[dout];
+    const int64_t dsi = T.dstride[din], dso = T.dstride[dout];
+    int64_t dbase[kCopyGroup];
+    int ib[kCopyGroup], ob[kCopyGroup];
+    AT v[kCopyGroup][kCopyRun];
+    // loads of every tile of the piece
+#pragma unroll
+    for (int j = 0; j < kCopyGroup; ++j) {
+        if (j >= ng) break;
+        int64_t r = first + j;
         const int to = (int)(r % nto);
         r /= nto;
         const int ti = (int)(r % nti);
@@ -136,59 +145,144 @@ __global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __re
             so += (int64_t)ik * T.sstride[k];
             dofs += (int64_t)ik * T.dstride[k];
         }
-        const int i0 = ti << lgi, o0 = to << lgo;
-        const int64_t ssi = T.sstride[din], sso = T.sstride[dout];
-        const int64_t dsi = T.dstride[din], dso = T.dstride[dout];
-        for (int e = threadIdx.x; e < kCopyChunk; e += kCopyThreads) {
-            const int ii = e & (TI - 1), oo = e >> lgi;
-            const int gi = i0 + ii, go = o0 + oo;
-            if (gi < Din && go < Dout) tile[oo * (TI + 1) + ii] = gather(so + gi * ssi + go * sso);
+        dbase[j] = dofs;
+        ib[j] = ti << lgi;
+        ob[j] = to << lgo;
+#pragma unroll
+        for (int q = 0; q < kCopyRun; ++q) {
+            const int e = threadIdx.x + q * kCopyThreads;
+            const int gi = ib[j] + (e & (TI - 1)), go = ob[j] + (e >> lgi);
+            if (gi < Din && go < Dout) v[j][q] = gather(so + gi * ssi + go * sso);
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < kCopyChunk; e += kCopyThreads) {
-            const int oo = e & (TO - 1), ii = e >> lgo;
-            const int gi = i0 + ii, go = o0 + oo;
-            if (gi < Din && go < Dout)
-                copy_store<TS, DK>(dstv, dofs + gi * dsi + go * dso, T.lo_off, tile[oo * (TI + 1) + ii], true);
-        }
-        return;
     }
-    // each thread copies kCopyRun consecutive elements: the multi-index is
-    // decomposed for the first and advanced along the innermost dim
-    constexpr int kCopyRun = kCopyChunk / kCopyThreads;
-    const int64_t idx0 = local * kCopyChunk + (int64_t)threadIdx.x * kCopyRun;
-    if (idx0 >= T.count) return;
-    const int last = rank - 1;
+#pragma unroll
+    for (int j = 0; j < kCopyGroup; ++j) {
+        if (j >= ng) break;
+#pragma unroll
+        for (int q = 0; q < kCopyRun; ++q) {
+            const int e = threadIdx.x + q * kCopyThreads;
+            const int ii = e & (TI - 1), oo = e >> lgi;
+            if (ib[j] + ii < Din && ob[j] + oo < Dout) tile[j * kTileLds + oo * LS + ii] = v[j][q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kCopyGroup; ++j) {
+        if (j >= ng) break;
+#pragma unroll
+        for (int q = 0; q < kCopyRun; ++q) {
+            const int e = threadIdx.x + q * kCopyThreads;
+            const int oo = e & (TO - 1), ii = e >> lgo;
+            const int gi = ib[j] + ii, go = ob[j] + oo;
+            if (gi < Din && go < Dout)
+                copy_store<TS, DK>(dstv, dbase[j] + gi * dsi + go * dso, T.lo_off,
+                                   tile[j * kTileLds + oo * LS + ii], true);
+        }
+    }
+}
+
+template <typename TS, int DK, typename AT, typename G>
+__device__ __forceinline__ void copy_runs(const CopyTask& T, int64_t first, int ng, bool have_src, void* dstv,
+                                          G gather) {
+    // per chunk, each thread copies kCopyRun consecutive elements: the
+    // multi-index is decomposed for the first and advanced along the
+    // innermost dim
+    const int last = T.rank - 1;
     const int dl = T.dims[last];
     const int64_t sl = T.sstride[last], dls = T.dstride[last];
-    int inner = 0;
-    int64_t so = 0, dofs = 0;
-    auto locate = [&](int64_t idx) {
-        uint32_t r = (uint32_t)idx;
-        so = T.src_off;
-        dofs = T.dst_off;
-        for (int k = last; k >= 0; --k) {
-            const uint32_t dk = (uint32_t)T.dims[k];
-            const uint32_t q = r / dk;
-            const uint32_t ik = r - q * dk;
-            if (k == last) inner = (int)ik;
-            r = q;
-            so += (int64_t)ik * T.sstride[k];
-            dofs += (int64_t)ik * T.dstride[k];
-        }
-    };
-    locate(idx0);
+    AT v[kCopyGroup][kCopyRun];
+    int64_t dd[kCopyGroup][kCopyRun];
+    int n[kCopyGroup];
 #pragma unroll
-    for (int u = 0; u < kCopyRun; ++u) {
-        if (idx0 + u >= T.count) break;
-        copy_store<TS, DK>(dstv, dofs, T.lo_off, src ? gather(so) : (AT)0, src != nullptr);
-        if (++inner < dl) {
-            so += sl;
-            dofs += dls;
-        } else {
-            locate(idx0 + u + 1);
+    for (int j = 0; j < kCopyGroup; ++j) {
+        n[j] = 0;
+        if (j >= ng) continue;
+        const int64_t idx0 = (first + j) * kCopyChunk + (int64_t)threadIdx.x * kCopyRun;
+        if (idx0 >= T.count) continue;
+        n[j] = (int)min<int64_t>(kCopyRun, T.count - idx0);
+        int inner = 0;
+        int64_t so = 0, dofs = 0;
+        auto locate = [&](int64_t idx) {
+            uint32_t r = (uint32_t)idx;
+            so = T.src_off;
+            dofs = T.dst_off;
+            for (int k = last; k >= 0; --k) {
+                const uint32_t dk = (uint32_t)T.dims[k];
+                const uint32_t q = r / dk;
+                const uint32_t ik = r - q * dk;
+                if (k == last) inner = (int)ik;
+                r = q;
+                so += (int64_t)ik * T.sstride[k];
+                dofs += (int64_t)ik * T.dstride[k];
+            }
+        };
+        locate(idx0);
+#pragma unroll
+        for (int u = 0; u < kCopyRun; ++u) {
+            if (u >= n[j]) break;
+            dd[j][u] = dofs;
+            v[j][u] = have_src ? gather(so) : (AT)0;
+            if (++inner < dl) {
+                so += sl;
+                dofs += dls;
+            } else if (u + 1 < n[j]) {
+                locate(idx0 + u + 1);
+            }
         }
     }
+#pragma unroll
+    for (int j = 0; j < kCopyGroup; ++j) {
+        if constexpr (DK == kDstBF16 || DK == kDstSplit || DK == kDstSplit3) {
+            // four consecutive, aligned destinations: one vector per plane
+            constexpr int PL = DK == kDstBF16 ? 1 : (DK == kDstSplit ? 2 : 3);
+            if (n[j] == kCopyRun && (dd[j][0] & 3) == 0 && dd[j][1] == dd[j][0] + 1 && dd[j][2] == dd[j][0] + 2 &&
+                dd[j][3] == dd[j][0] + 3) {
+                unsigned short h[kCopyRun][3];
+#pragma unroll
+                for (int u = 0; u < kCopyRun; ++u) bf16_planes<PL>((float)v[j][u], h[u]);
+#pragma unroll
+                for (int p = 0; p < PL; ++p) {
+                    const uint2 w = {(uint32_t)h[0][p] | ((uint32_t)h[1][p] << 16),
+                                     (uint32_t)h[2][p] | ((uint32_t)h[3][p] << 16)};
+                    *(uint2*)((unsigned short*)dstv + dd[j][0] + p * T.lo_off) = w;
+                }
+                continue;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyRun; ++u)
+            if (u < n[j]) copy_store<TS, DK>(dstv, dd[j][u], T.lo_off, v[j][u], have_src);
+    }
+}
+
+template <class Ptrs, typename TS, int DK>
+__global__ __launch_bounds__(kCopyThreads) void copy_kernel(const CopyTask* __restrict__ tasks,
+                                                            const int64_t* __restrict__ piece_prefix,
+                                                            int ntasks, Ptrs ptrs) {
+    using AT = std::conditional_t<DK == kDstF64, double, TS>;   // arithmetic type
+    __shared__ AT tile[kCopyGroup * kTileLds];
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {                       // last task with prefix <= w
+        int mid = (lo + hi + 1) >> 1;
+        if (piece_prefix[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    const CopyTask& T = tasks[lo];
+    const int64_t first = (w - piece_prefix[lo]) * kCopyGroup;
+    const int ng = (int)min<int64_t>(kCopyGroup, (int64_t)T.nchunks - first);
+    const TS* __restrict__ src = T.src_buf >= 0 ? (const TS*)ptrs.get(T.src_buf) : nullptr;
+    void* dstv = ptrs.get(T.dst_buf);
+    const double scale = T.scale;
+    auto gather = [&](int64_t so) -> AT {
+        AT sv = (AT)src[so] * (AT)scale;
+        const int64_t rel = so - T.src_off;
+        for (int t = 0; t < T.nextra; ++t) sv += (AT)src[T.xsrc_off[t] + rel] * (AT)T.xscale[t];
+        return sv;
+    };
+    if (T.tr_in >= 0)
+        copy_tiles<TS, DK, AT>(T, first, ng, dstv, tile, gather);
+    else
+        copy_runs<TS, DK, AT>(T, first, ng, src != nullptr, dstv, gather);
 }
 
 // ===================================================================== gemm
@@ -460,7 +554,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const TileWork* __restric
 // FP32, smallest terms first: bf16x3 = lo*hi + hi*lo + hi*hi; bf16x6 =
 // lo*hi + hi*lo + mid*mid + mid*hi + hi*mid + hi*hi (the dropped mid*lo,
 // lo*mid, lo*lo are below FP32 rounding of the product).
-template <class Ptrs, class S, int PL>
+template <class Ptrs, class S, int PL, bool SCAT>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restrict__ tiles, int ntiles,
                                                         int* __restrict__ queue,
                                                         const GemmGroup* __restrict__ groups, Ptrs ptrs,
@@ -587,6 +681,105 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
         }
         __syncthreads();
     }
+    if constexpr (SCAT) {
+        // scatter epilogue (never split along K): each product goes, split
+        // into this kernel's bf16 planes, to the position the next
+        // contraction's A panel holds it at.  The tile's row and column
+        // entries and the block entries they meet are staged in LDS (the A
+        // tile's space, free after the K loop), so that the epilogue's
+        // global memory operations are its stores.  A lane holds four
+        // consecutive rows of a column; where they land on four
+        // consecutive, aligned positions they are stored as one vector per
+        // plane.
+        const int* __restrict__ tab = (const int*)ptrs.get(g.s_buf);
+        const int* __restrict__ rt = tab + g.s_rows;
+        const int* __restrict__ ct = tab + g.s_cols;
+        const int* __restrict__ bt = tab + g.s_blocks;
+        unsigned short* __restrict__ P = (unsigned short*)ptrs.get(g.c_buf);
+        constexpr int kLdsInts = PL * BM * LDH / 2;
+        constexpr int kMaxBlk = (kLdsInts - 4 * (BM + BN)) / 8;
+        static_assert(kMaxBlk >= 16, "LDS too small for the scatter tables");
+        int* srow = (int*)&As[0][0];
+        int* scol = srow + 4 * BM;
+        int* sblk = scol + 4 * BN;
+        const int mlast = min(m0 + BM, g.M) - 1, nlast = min(n0 + BN, g.N) - 1;
+        const int rb_lo = rt[4 * m0], rb_hi = rt[4 * mlast];   // rows are ordered by row block
+        const int cb_lo = ct[4 * n0], cb_hi = ct[4 * nlast];
+        const int ncbt = cb_hi - cb_lo + 1;
+        const bool staged = (rb_hi - rb_lo + 1) * ncbt <= kMaxBlk;
+        __syncthreads();   // every wave is done with the A and B tiles
+        for (int e = tid; e < BM; e += 256)
+            if (m0 + e <= mlast) *(int4*)(srow + 4 * e) = *(const int4*)(rt + 4 * (m0 + e));
+        for (int e = tid; e < BN; e += 256)
+            if (n0 + e <= nlast) *(int4*)(scol + 4 * e) = *(const int4*)(ct + 4 * (n0 + e));
+        if (staged)
+            for (int e = tid; e < (rb_hi - rb_lo + 1) * ncbt; e += 256) {
+                const int* src = bt + 8 * ((rb_lo + e / ncbt) * g.s_ncb + cb_lo + e % ncbt);
+                *(int4*)(sblk + 8 * e) = *(const int4*)src;
+                *(int4*)(sblk + 8 * e + 4) = *(const int4*)(src + 4);
+            }
+        __syncthreads();
+        auto entry = [&](int rb, int cb, int4& b0, int4& b1) {
+            if (staged) {
+                const int* e = sblk + 8 * ((rb - rb_lo) * ncbt + (cb - cb_lo));
+                b0 = *(const int4*)e;
+                b1 = *(const int4*)(e + 4);
+            } else {
+                const int* e = bt + 8 * (rb * g.s_ncb + cb);
+                b0 = *(const int4*)e;
+                b1 = *(const int4*)(e + 4);
+            }
+        };
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+            const int cl = wn + j * 32 + (lane & 31);
+            if (n0 + cl >= g.N) continue;
+            const int4 cr = *(const int4*)(scol + 4 * cl);
+#pragma unroll
+            for (int i = 0; i < TI; ++i) {
+                // the block entry of the sub-tile's first row; rows of another
+                // row block look theirs up
+                const int rl0 = wm + i * 32;
+                const int rb0 = srow[4 * min(rl0, mlast - m0)];
+                int4 c0, c1;
+                entry(rb0, cr.x, c0, c1);
+#pragma unroll
+                for (int eg = 0; eg < 4; ++eg) {
+                    const int rl = rl0 + 8 * eg + 4 * (lane >> 5);
+                    int d[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        d[q] = -1;
+                        if (m0 + rl + q > mlast) continue;
+                        const int4 rr = *(const int4*)(srow + 4 * (rl + q));
+                        int4 b0 = c0, b1 = c1;
+                        if (rr.x != rb0) entry(rr.x, cr.x, b0, b1);
+                        if (b0.x >= 0)
+                            d[q] = b0.x + rr.y * b0.y + rr.z * b0.z + rr.w * b0.w + cr.y * b1.x + cr.z * b1.y +
+                                   cr.w * b1.z;
+                    }
+                    unsigned short h[4][3];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bf16_planes<PL>(acc[i][j][4 * eg + q], h[q]);
+                    if (d[0] >= 0 && (d[0] & 3) == 0 && d[1] == d[0] + 1 && d[2] == d[0] + 2 && d[3] == d[0] + 3) {
+#pragma unroll
+                        for (int p = 0; p < PL; ++p) {
+                            const uint2 v = {(uint32_t)h[0][p] | ((uint32_t)h[1][p] << 16),
+                                             (uint32_t)h[2][p] | ((uint32_t)h[3][p] << 16)};
+                            *(uint2*)(P + d[0] + p * g.c_lo) = v;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (d[q] >= 0)
+#pragma unroll
+                                for (int p = 0; p < PL; ++p) P[d[q] + p * g.c_lo] = h[q][p];
+                    }
+                }
+            }
+        }
+        __syncthreads();   // the LDS tables are read before the next tile's loads
+    } else {
     // a whole-K item writes C; a split-K part writes its partial tile
     float* __restrict__ W = ws + (int64_t)(tw.slot < 0 ? 0 : tw.slot) * BM * BN;
 #pragma unroll
@@ -601,6 +794,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
                 else if (row < g.M && col < g.N) C[(int64_t)row * g.ldc + col] = acc[i][j][e];
             }
         }
+    }
     }
     if (!queue) break;
     if (threadIdx.x == 0) next_row = (int)(gridDim.x >> 3) + atomicAdd(&queue[blockIdx.x & 7], 1);
@@ -850,9 +1044,9 @@ void launch_double_layer(const DoubleLayerArgs& a, hipStream_t s) {
 
 // ---- prepared launches: device descriptors owned by the caller ------------
 template <class Ptrs>
-static void copy_dispatch(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks, Ptrs P,
+static void copy_dispatch(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t npieces, Ptrs P,
                           bool src_f64, int dst_kind, hipStream_t s) {
-    dim3 grid((unsigned)nchunks), block(kCopyThreads);
+    dim3 grid((unsigned)npieces), block(kCopyThreads);
 #define SYMTEN_COPY(TS, DK) \
     hipLaunchKernelGGL((copy_kernel<Ptrs, TS, DK>), grid, block, 0, s, d_tasks, d_prefix, ntasks, P)
     if (src_f64) {
@@ -877,19 +1071,19 @@ static void copy_dispatch(const CopyTask* d_tasks, const int64_t* d_prefix, int 
     HIPCHK(hipGetLastError());
 }
 
-void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+void copy_launch_dev(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t npieces,
                      void* const* d_ptrs, bool src_f64, int dst_kind, hipStream_t s) {
-    if (ntasks <= 0 || nchunks <= 0) return;
-    copy_dispatch(d_tasks, d_prefix, ntasks, nchunks, DevPtrs{d_ptrs}, src_f64, dst_kind, s);
+    if (ntasks <= 0 || npieces <= 0) return;
+    copy_dispatch(d_tasks, d_prefix, ntasks, npieces, DevPtrs{d_ptrs}, src_f64, dst_kind, s);
 }
 
-void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t nchunks,
+void copy_launch_arg(const CopyTask* d_tasks, const int64_t* d_prefix, int ntasks, int64_t npieces,
                      const std::vector<void*>& ptrs, bool src_f64, int dst_kind, hipStream_t s) {
-    if (ntasks <= 0 || nchunks <= 0) return;
+    if (ntasks <= 0 || npieces <= 0) return;
     if (ptrs.size() > 16) fail(SYMTEN_E_CAPACITY, "copy_launch_arg: more than 16 buffers");
     ArgPtrs P{};
     for (size_t i = 0; i < ptrs.size(); ++i) P.p[i] = ptrs[i];
-    copy_dispatch(d_tasks, d_prefix, ntasks, nchunks, P, src_f64, dst_kind, s);
+    copy_dispatch(d_tasks, d_prefix, ntasks, npieces, P, src_f64, dst_kind, s);
 }
 
 // Tile shapes (BM x BN): 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128,
@@ -924,28 +1118,30 @@ static GemmF64Fn<Ptrs> f64_kernel(int cfg) {
     }
 }
 
-template <class Ptrs, int PL>
+template <class Ptrs, int PL, bool SCAT>
 static GemmF32Fn<Ptrs> bf16_kernel(int cfg) {
     switch (cfg) {
-        case 0: return gemm_bf16_kernel<Ptrs, TileShape<64, 64, 32>, PL>;
-        case 1: return gemm_bf16_kernel<Ptrs, TileShape<128, 128, 32>, PL>;
-        case 2: return gemm_bf16_kernel<Ptrs, TileShape<128, 64, 32>, PL>;
-        case 3: return gemm_bf16_kernel<Ptrs, TileShape<64, 128, 32>, PL>;
-        case 4: return gemm_bf16_kernel<Ptrs, TileShape<256, 128, 32>, PL>;
-        case 5: return gemm_bf16_kernel<Ptrs, TileShape<64, 64, 64>, PL>;
-        case 6: return gemm_bf16_kernel<Ptrs, TileShape<128, 64, 64>, PL>;
-        default: return gemm_bf16_kernel<Ptrs, TileShape<64, 128, 64>, PL>;
+        case 0: return gemm_bf16_kernel<Ptrs, TileShape<64, 64, 32>, PL, SCAT>;
+        case 1: return gemm_bf16_kernel<Ptrs, TileShape<128, 128, 32>, PL, SCAT>;
+        case 2: return gemm_bf16_kernel<Ptrs, TileShape<128, 64, 32>, PL, SCAT>;
+        case 3: return gemm_bf16_kernel<Ptrs, TileShape<64, 128, 32>, PL, SCAT>;
+        case 4: return gemm_bf16_kernel<Ptrs, TileShape<256, 128, 32>, PL, SCAT>;
+        case 5: return gemm_bf16_kernel<Ptrs, TileShape<64, 64, 64>, PL, SCAT>;
+        case 6: return gemm_bf16_kernel<Ptrs, TileShape<128, 64, 64>, PL, SCAT>;
+        default: return gemm_bf16_kernel<Ptrs, TileShape<64, 128, 64>, PL, SCAT>;
     }
 }
 
+// scatter: the kernel with the scatter epilogue (bf16 precisions only)
 template <class Ptrs>
-static GemmF32Fn<Ptrs> f32_kernel(Prec p, int cfg) {
+static GemmF32Fn<Ptrs> f32_kernel(Prec p, int cfg, bool scatter = false) {
     switch (p) {
-        case Prec::BF16: return bf16_kernel<Ptrs, 1>(cfg);
-        case Prec::BF16X3: return bf16_kernel<Ptrs, 2>(cfg);
-        case Prec::BF16X6: return bf16_kernel<Ptrs, 3>(cfg);
+        case Prec::BF16: return scatter ? bf16_kernel<Ptrs, 1, true>(cfg) : bf16_kernel<Ptrs, 1, false>(cfg);
+        case Prec::BF16X3: return scatter ? bf16_kernel<Ptrs, 2, true>(cfg) : bf16_kernel<Ptrs, 2, false>(cfg);
+        case Prec::BF16X6: return scatter ? bf16_kernel<Ptrs, 3, true>(cfg) : bf16_kernel<Ptrs, 3, false>(cfg);
         default: break;
     }
+    if (scatter) fail(SYMTEN_E_INVAL, "gemm: the scatter epilogue needs a bf16 precision");
     switch (cfg) {
         case 0: return gemm_f32_kernel<Ptrs, TileShape<64, 64, 32>>;
         case 1: return gemm_f32_kernel<Ptrs, TileShape<128, 128, 32>>;
@@ -985,8 +1181,9 @@ int gemm_capacity(Prec p, int cfg) {
 
 template <class Ptrs>
 static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, Ptrs P, Prec prec,
-                          int cfg, hipStream_t s, const SplitK& sk) {
+                          int cfg, hipStream_t s, const SplitK& sk, bool scatter) {
     if (!gemm_tile_ok(prec, cfg)) fail(SYMTEN_E_INVAL, "gemm: tile configuration not available");
+    if (scatter && sk.nsplits > 0) fail(SYMTEN_E_INVAL, "gemm: the scatter epilogue is not split along K");
     // persistent grid for long lists: as many workgroups as the chip holds at
     // once, taking further entries from per-XCD counters (the first
     // kSplitQueueBytes of the workspace, zeroed here in stream order); a list
@@ -1004,8 +1201,8 @@ static void gemm_dispatch(const TileWork* d_tiles, int ntiles, const GemmGroup* 
         hipLaunchKernelGGL(f64_kernel<Ptrs>(cfg), grid, block, 0, s, d_tiles, ntiles, queue, d_groups, P,
                            (double*)partials);
     else
-        hipLaunchKernelGGL(f32_kernel<Ptrs>(prec, cfg), grid, block, 0, s, d_tiles, ntiles, queue, d_groups, P,
-                           (float*)partials);
+        hipLaunchKernelGGL(f32_kernel<Ptrs>(prec, cfg, scatter), grid, block, 0, s, d_tiles, ntiles, queue, d_groups,
+                           P, (float*)partials);
     HIPCHK(hipGetLastError());
     if (sk.nsplits > 0) {
         const int BM = gemm_tile_bm(prec, cfg), BN = gemm_tile_bn(prec, cfg);
@@ -1025,13 +1222,13 @@ void gemm_launch_arg(const TileWork* d_tiles, int ntiles, const GemmGroup* d_gro
     if (ptrs.size() > 16) fail(SYMTEN_E_CAPACITY, "gemm_launch_arg: more than 16 buffers");
     ArgPtrs P{};
     for (size_t i = 0; i < ptrs.size(); ++i) P.p[i] = ptrs[i];
-    gemm_dispatch(d_tiles, ntiles, d_groups, P, prec, cfg, s, sk);
+    gemm_dispatch(d_tiles, ntiles, d_groups, P, prec, cfg, s, sk, false);
 }
 
 void gemm_launch_dev(const TileWork* d_tiles, int ntiles, const GemmGroup* d_groups, void* const* d_ptrs,
-                     Prec prec, int cfg, hipStream_t s, const SplitK& sk) {
+                     Prec prec, int cfg, hipStream_t s, const SplitK& sk, bool scatter) {
     if (ntiles <= 0) return;
-    gemm_dispatch(d_tiles, ntiles, d_groups, DevPtrs{d_ptrs}, prec, cfg, s, sk);
+    gemm_dispatch(d_tiles, ntiles, d_groups, DevPtrs{d_ptrs}, prec, cfg, s, sk, scatter);
 }
 
 }  // namespace symten

@@ -232,6 +232,7 @@ DeviceBuffer::~DeviceBuffer() {
 
 // ------------------------------------------------------------------ tensors
 void Tensor::rebuild_index() {
+    memo.reset();
     index.clear();
     for (size_t i = 0; i < blocks.size(); ++i) {
         std::vector<int> key = blocks[i].q;
@@ -281,6 +282,10 @@ int64_t enumerate_blocks(Tensor& t) {
 }
 
 std::string tensor_signature(const Tensor& t) {
+    {
+        std::lock_guard<std::mutex> lk(t.memo.mu);
+        if (t.memo.valid) return t.memo.sig;
+    }
     std::ostringstream os;
     os << "g" << t.group << "f" << t.flux << "t" << t.dtype << "|";
     for (auto& l : t.legs) {
@@ -296,7 +301,10 @@ std::string tensor_signature(const Tensor& t) {
         for (auto s : b.stride) os << s << ",";
         os << ";";
     }
-    return os.str();
+    std::lock_guard<std::mutex> lk(t.memo.mu);
+    t.memo.sig = os.str();
+    t.memo.valid = true;
+    return t.memo.sig;
 }
 
 void check_device_tensor(const Tensor& t, const char* what) {
@@ -398,6 +406,7 @@ CopyTask make_copy_task(int src_buf, int64_t src_off, int dst_buf, int64_t dst_o
     t.count = (int)c;
     t.scale = scale;
     simplify_task(t);
+    t.nchunks = (int)copy_task_chunks(t);
     return t;
 }
 
@@ -475,6 +484,8 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
     auto plan = std::make_shared<ContractPlan>();
     plan->prec = p;
     plan->panel_f64 = (p == Prec::F64);
+    plan->conA = conA;
+    plan->conB = conB;
     const int VW = panel_vw(p);   // 16-byte vectors in the GEMM loads
 
     // group blocks by the contracted charge seen from A
@@ -608,7 +619,12 @@ std::shared_ptr<ContractPlan> plan_contraction(const Tensor& A, const Tensor& B,
                 std::vector<int64_t> ds = suffix(adims, lda);
                 std::vector<int64_t> dk = suffix(kd, 1);
                 ds.insert(ds.end(), dk.begin(), dk.end());
-                plan->copies.push_back(make_copy_task(0, b.offset, 2, gp.a_off + gp.row_off[r] * lda + koff[ki], dims, ss, ds));
+                const int64_t doff = gp.a_off + gp.row_off[r] * lda + koff[ki];
+                plan->copies.push_back(make_copy_task(0, b.offset, 2, doff, dims, ss, ds));
+                PanelMap pm{bi, doff, std::vector<int64_t>(A.rank(), 0)};
+                for (size_t c = 0; c < freeA.size(); ++c) pm.dstride[freeA[c]] = ds[c];
+                for (size_t c = 0; c < conA.size(); ++c) pm.dstride[conA[c]] = ds[freeA.size() + c];
+                plan->a_maps.push_back(std::move(pm));
             }
             for (size_t ki = 0; ki < kap.size(); ++ki)
                 if (!present[ki])
@@ -799,7 +815,7 @@ namespace {
 struct DevPlan {
     BufferPtr tasks, prefix, groups;
     int ntasks = 0;
-    int64_t nchunks = 0;
+    int64_t npieces = 0;
     TileChoice tc;
     std::vector<GemmGroup> host_groups;
     int64_t checked_a = -1, checked_b = -1;   // input sizes already validated
@@ -819,8 +835,10 @@ std::map<std::string, int> g_tune;   // shape signature -> tile configuration
 bool g_tune_loaded = false;
 
 std::string shape_key(const std::vector<GemmGroup>& groups, Prec prec) {
+    // the epilogue kind is part of the shape: a scatter epilogue is another kernel
     std::string k = "p" + std::to_string((int)prec) + ":";
-    for (auto& g : groups) k += std::to_string(g.M) + "x" + std::to_string(g.N) + "x" + std::to_string(g.K) + ",";
+    for (auto& g : groups)
+        k += std::to_string(g.M) + "x" + std::to_string(g.N) + "x" + std::to_string(g.K) + (g.scatter ? "s," : ",");
     char h[32];
     std::snprintf(h, sizeof(h), "%016zx", std::hash<std::string>{}(k));
     return std::string(h) + "/" + std::to_string(groups.size());
@@ -957,7 +975,7 @@ void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, TileP
         const int want = (int)std::min<int64_t>(8, cap / ntile);
         if (want >= 2)
             for (size_t gi = 0; gi < groups.size(); ++gi)
-                parts_of[gi] = std::max(1, std::min(want, groups[gi].K / (4 * BK)));
+                parts_of[gi] = groups[gi].scatter ? 1 : std::max(1, std::min(want, groups[gi].K / (4 * BK)));
     }
     const double target = total / kXcd;
     std::vector<Item> items;
@@ -1020,7 +1038,8 @@ void build_tiles(const std::vector<GemmGroup>& groups, Prec prec, int cfg, TileP
 void copy_prefix(const std::vector<CopyTask>& tasks, std::vector<int64_t>& prefix) {
     prefix.resize(tasks.size() + 1);
     prefix[0] = 0;
-    for (size_t i = 0; i < tasks.size(); ++i) prefix[i + 1] = prefix[i] + copy_task_chunks(tasks[i]);
+    for (size_t i = 0; i < tasks.size(); ++i)
+        prefix[i + 1] = prefix[i] + (copy_task_chunks(tasks[i]) + kCopyGroup - 1) / kCopyGroup;
 }
 
 // Every element a task or a GEMM group touches must lie inside its buffer;
@@ -1043,6 +1062,10 @@ void validate_tasks(const std::vector<CopyTask>& tasks, const std::vector<int64_
             fail(SYMTEN_E_INVAL, "internal: copy source out of bounds");
         if (t.nextra < 0 || t.nextra > kMaxExtraSrc || (t.nextra > 0 && t.src_buf < 0))
             fail(SYMTEN_E_INVAL, "internal: bad extra source count");
+        if (t.nchunks != copy_task_chunks(t)) fail(SYMTEN_E_INVAL, "internal: copy task chunk count");
+        if (t.tr_in >= 0 && (t.src_buf < 0 || t.tr_in >= t.rank || t.tr_out < 0 || t.tr_out >= t.rank ||
+                             t.tr_in == t.tr_out || t.lg_out < 4 || t.lg_out > 6))
+            fail(SYMTEN_E_INVAL, "internal: bad transposing copy tile");
         for (int x = 0; x < t.nextra; ++x) {
             const int64_t lo = smin - t.src_off + t.xsrc_off[x], hi = smax - t.src_off + t.xsrc_off[x];
             if (lo < 0 || hi >= buf_elems[t.src_buf]) fail(SYMTEN_E_INVAL, "internal: extra copy source out of bounds");
@@ -1059,14 +1082,148 @@ void validate_groups(const std::vector<GemmGroup>& groups, const std::vector<int
         if (g.M < 1 || g.N < 1 || g.K < 1 || g.lda < g.K || g.ldb < g.K || g.ldc < g.N || g.lda % vw ||
             g.ldb % vw || g.a_off % vw || g.b_off % vw)
             fail(SYMTEN_E_INVAL, "internal: GEMM group shape or alignment");
-        if (!in(g.a_buf, g.a_off, (int64_t)g.M * g.lda) || !in(g.b_buf, g.b_off, (int64_t)g.N * g.ldb) ||
-            !in(g.c_buf, g.c_off, (int64_t)(g.M - 1) * g.ldc + g.N))
+        // a scatter group's destinations are checked with its tables (validate_scatter)
+        const bool c_ok = g.scatter ? (g.scatter == 1 && g.c_buf >= 0 && g.c_buf < (int)buf_elems.size() &&
+                                       g.s_buf >= 0 && g.s_buf < (int)buf_elems.size())
+                                    : in(g.c_buf, g.c_off, (int64_t)(g.M - 1) * g.ldc + g.N);
+        if (!in(g.a_buf, g.a_off, (int64_t)g.M * g.lda) || !in(g.b_buf, g.b_off, (int64_t)g.N * g.ldb) || !c_ok)
             fail(SYMTEN_E_INVAL, "internal: GEMM operand out of bounds");
         for (int p = 1; p < planes; ++p)
             if (g.a_lo % vw || g.b_lo % vw || g.a_lo < 0 || g.b_lo < 0 ||
                 !in(g.a_buf, g.a_off + p * g.a_lo, (int64_t)g.M * g.lda) ||
                 !in(g.b_buf, g.b_off + p * g.b_lo, (int64_t)g.N * g.ldb))
                 fail(SYMTEN_E_INVAL, "internal: GEMM lower plane out of bounds");
+    }
+}
+
+int64_t append_scatter_tables(const ContractPlan& p, const Tensor& A, const Tensor& B, const ContractPlan& q,
+                              int64_t a_base, GemmGroup* groups, std::vector<int>& tab) {
+    const Tensor& out = *p.out_meta;
+    std::vector<int> map_of(out.blocks.size(), -1);
+    for (size_t m = 0; m < q.a_maps.size(); ++m) {
+        const int b = q.a_maps[m].block;
+        if (b < 0 || b >= (int)out.blocks.size() || map_of[b] >= 0 ||
+            (int)q.a_maps[m].dstride.size() != out.rank())
+            fail(SYMTEN_E_INVAL, "internal: scatter tables: bad block map");
+        map_of[b] = (int)m;
+    }
+    std::vector<int> freeA, freeB;
+    for (int l = 0; l < A.rank(); ++l)
+        if (std::find(p.conA.begin(), p.conA.end(), l) == p.conA.end()) freeA.push_back(l);
+    for (int l = 0; l < B.rank(); ++l)
+        if (std::find(p.conB.begin(), p.conB.end(), l) == p.conB.end()) freeB.push_back(l);
+    const int nr = (int)freeA.size(), nc = (int)freeB.size();
+    if (nr > kScatterLegs || nc > kScatterLegs || nr + nc != out.rank())
+        fail(SYMTEN_E_INVAL, "internal: scatter tables: more free legs than the epilogue decodes");
+    auto dims_of = [](const Tensor& T, const std::vector<int>& legs, const std::vector<int>& key) {
+        std::vector<int> d;
+        for (size_t c = 0; c < legs.size(); ++c) d.push_back(T.legs[legs[c]].dim_of(key[c]));
+        return d;
+    };
+    // one entry per row (column): its block and its multi-index, row-major
+    // over the block's free legs
+    auto entries = [&](const std::vector<int>& d, int blk, int nlegs) {
+        int64_t cnt = 1;
+        for (int x : d) cnt *= x;
+        for (int64_t e = 0; e < cnt; ++e) {
+            int idx[kScatterLegs] = {0, 0, 0};
+            int64_t rest = e;
+            for (int l = nlegs - 1; l >= 0; --l) {
+                idx[l] = (int)(rest % d[l]);
+                rest /= d[l];
+            }
+            tab.insert(tab.end(), {blk, idx[0], idx[1], idx[2]});
+        }
+    };
+    int64_t written = 0;
+    for (size_t gi = 0; gi < p.groups.size(); ++gi) {
+        const GroupPlan& gp = p.groups[gi];
+        GemmGroup& G = groups[gi];
+        if (G.M != gp.M || G.N != gp.N) fail(SYMTEN_E_INVAL, "internal: scatter tables: group mismatch");
+        G.s_rows = (int64_t)tab.size();
+        for (size_t r = 0; r < gp.rows.size(); ++r) entries(dims_of(A, freeA, gp.rows[r]), (int)r, nr);
+        G.s_cols = (int64_t)tab.size();
+        for (size_t c = 0; c < gp.cols.size(); ++c) entries(dims_of(B, freeB, gp.cols[c]), (int)c, nc);
+        if ((int64_t)tab.size() - G.s_rows != 4 * ((int64_t)G.M + G.N))
+            fail(SYMTEN_E_INVAL, "internal: scatter tables: row or column count");
+        G.s_blocks = (int64_t)tab.size();
+        for (size_t r = 0; r < gp.rows.size(); ++r)
+            for (size_t c = 0; c < gp.cols.size(); ++c) {
+                std::vector<int> key = gp.rows[r];
+                key.insert(key.end(), gp.cols[c].begin(), gp.cols[c].end());
+                auto it = out.index.find(key);
+                const int m = it == out.index.end() ? -1 : map_of[it->second];
+                if (m < 0) {   // a block the next contraction does not read
+                    tab.insert(tab.end(), {-1, 0, 0, 0, 0, 0, 0, 0});
+                    continue;
+                }
+                const PanelMap& pm = q.a_maps[m];
+                const int64_t d0 = a_base + pm.dst_off;
+                if (d0 >= (1LL << 31)) fail(SYMTEN_E_CAPACITY, "scatter epilogue: A panels beyond 2^31 elements");
+                int sr[kScatterLegs] = {0, 0, 0}, sc[kScatterLegs] = {0, 0, 0};
+                for (int l = 0; l < nr; ++l) sr[l] = (int)pm.dstride[l];
+                for (int l = 0; l < nc; ++l) sc[l] = (int)pm.dstride[nr + l];
+                tab.insert(tab.end(), {(int)d0, sr[0], sr[1], sr[2], sc[0], sc[1], sc[2], 0});
+                written += out.blocks[it->second].size;
+            }
+        G.scatter = 1;
+        G.s_ncb = (int)gp.cols.size();
+        G.c_off = 0;
+    }
+    return written;
+}
+
+void validate_scatter(const std::vector<GemmGroup>& groups, const std::vector<int>& tab, int64_t dst_elems,
+                      int planes) {
+    const int64_t nt = (int64_t)tab.size();
+    for (const GemmGroup& g : groups) {
+        if (!g.scatter) continue;
+        if (g.s_ncb < 1 || g.s_rows < 0 || g.s_cols < 0 || g.s_blocks < 0 || g.s_rows % 4 || g.s_cols % 4 ||
+            g.s_blocks % 4 || g.s_rows + 4 * (int64_t)g.M > nt || g.s_cols + 4 * (int64_t)g.N > nt || g.c_lo < 0)
+            fail(SYMTEN_E_INVAL, "internal: scatter tables out of bounds");
+        int nrb = 0;   // row blocks
+        for (int i = 0; i < g.M; ++i) {
+            const int* r = &tab[g.s_rows + 4 * i];
+            if (r[0] < 0 || r[1] < 0 || r[2] < 0 || r[3] < 0) fail(SYMTEN_E_INVAL, "internal: scatter row entry");
+            nrb = std::max(nrb, r[0] + 1);
+        }
+        for (int j = 0; j < g.N; ++j) {
+            const int* c = &tab[g.s_cols + 4 * j];
+            if (c[0] < 0 || c[0] >= g.s_ncb || c[1] < 0 || c[2] < 0 || c[3] < 0)
+                fail(SYMTEN_E_INVAL, "internal: scatter column entry");
+        }
+        if (g.s_blocks + 8 * (int64_t)nrb * g.s_ncb > nt) fail(SYMTEN_E_INVAL, "internal: scatter block table out of bounds");
+        auto entry = [&](int rb, int cb) { return &tab[g.s_blocks + 8 * ((int64_t)rb * g.s_ncb + cb)]; };
+        // the largest row term and column term each block entry meets
+        const size_t nb = (size_t)nrb * g.s_ncb;
+        std::vector<int64_t> rmax(nb, 0), cmax(nb, 0);
+        for (int i = 0; i < g.M; ++i) {
+            const int* r = &tab[g.s_rows + 4 * i];
+            for (int cb = 0; cb < g.s_ncb; ++cb) {
+                const int* b = entry(r[0], cb);
+                const size_t e = (size_t)r[0] * g.s_ncb + cb;
+                rmax[e] = std::max(rmax[e], (int64_t)r[1] * b[1] + (int64_t)r[2] * b[2] + (int64_t)r[3] * b[3]);
+            }
+        }
+        for (int j = 0; j < g.N; ++j) {
+            const int* c = &tab[g.s_cols + 4 * j];
+            for (int rb = 0; rb < nrb; ++rb) {
+                const int* b = entry(rb, c[0]);
+                const size_t e = (size_t)rb * g.s_ncb + c[0];
+                cmax[e] = std::max(cmax[e], (int64_t)c[1] * b[4] + (int64_t)c[2] * b[5] + (int64_t)c[3] * b[6]);
+            }
+        }
+        for (int rb = 0; rb < nrb; ++rb)
+            for (int cb = 0; cb < g.s_ncb; ++cb) {
+                const int* b = entry(rb, cb);
+                if (b[0] < 0) continue;
+                for (int k = 1; k < 7; ++k)
+                    if (b[k] < 0) fail(SYMTEN_E_INVAL, "internal: negative scatter stride");
+                const size_t e = (size_t)rb * g.s_ncb + cb;
+                const int64_t top = b[0] + rmax[e] + cmax[e];
+                if (top >= (1LL << 31) || top + (planes - 1) * g.c_lo >= dst_elems)
+                    fail(SYMTEN_E_INVAL, "internal: scatter destination out of bounds");
+            }
     }
 }
 
@@ -1077,7 +1234,7 @@ static std::shared_ptr<DevPlan> dev_plan(const ContractPlan& p) {
     std::vector<int64_t> prefix;
     copy_prefix(p.copies, prefix);
     d->ntasks = (int)p.copies.size();
-    d->nchunks = prefix.back();
+    d->npieces = prefix.back();
     upload_sync(d->tasks, p.copies.data(), p.copies.size() * sizeof(CopyTask));
     upload_sync(d->prefix, prefix.data(), prefix.size() * sizeof(int64_t));
     std::vector<GemmGroup> gg;
@@ -1130,7 +1287,7 @@ TensorPtr run_contraction(const ContractPlan& p, const Tensor& A, const Tensor& 
     const size_t se = src64 ? 8 : 4;
     const bool prof = profiling();
     profile_launch(copy_kernel_name(src64, p.prec), 0, 0, prof ? copy_bytes(p.copies, se, pe) : 0, stream, [&] {
-        copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->nchunks,
+        copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->npieces,
                         {A.data(), B.data(), pa->ptr, pb->ptr}, src64, panel_dst_kind(p.prec), stream);
     });
     auto launch = [&](int cfg) {
@@ -1157,7 +1314,7 @@ struct MultiDesc {
     std::vector<std::shared_ptr<ContractPlan>> plans;   // keeps the plans alive
     BufferPtr tasks, prefix, groups;
     int ntasks = 0;
-    int64_t nchunks = 0, ap = 0, bp = 0;
+    int64_t npieces = 0, ap = 0, bp = 0;
     TileChoice tc;
     std::vector<CopyTask> host_tasks;
     std::vector<GemmGroup> host_groups;
@@ -1219,7 +1376,7 @@ std::shared_ptr<MultiDesc> multi_desc(const std::vector<std::shared_ptr<Contract
     std::vector<int64_t> prefix;
     copy_prefix(d->host_tasks, prefix);
     d->ntasks = (int)d->host_tasks.size();
-    d->nchunks = prefix.back();
+    d->npieces = prefix.back();
     upload_sync(d->tasks, d->host_tasks.data(), d->host_tasks.size() * sizeof(CopyTask));
     upload_sync(d->prefix, prefix.data(), prefix.size() * sizeof(int64_t));
     upload_sync(d->groups, d->host_groups.data(), d->host_groups.size() * sizeof(GemmGroup));
@@ -1287,7 +1444,7 @@ std::vector<TensorPtr> run_contractions_batched(const std::vector<std::shared_pt
     const bool prof = profiling();
     const size_t se = src64 ? 8 : 4;
     profile_launch(copy_kernel_name(src64, prec), 0, 0, prof ? copy_bytes(d->host_tasks, se, pe) : 0, stream, [&] {
-        copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->nchunks, ptrs,
+        copy_launch_arg((const CopyTask*)d->tasks->ptr, (const int64_t*)d->prefix->ptr, d->ntasks, d->npieces, ptrs,
                         src64, panel_dst_kind(prec), stream);
     });
     auto launch = [&](int cfg) {
@@ -1519,7 +1676,7 @@ std::shared_ptr<GatherPlan> make_gather_plan(std::vector<CopyTask>& tasks, const
         copy_prefix(tasks, prefix);
         upload_sync(g->tasks, tasks.data(), tasks.size() * sizeof(CopyTask));
         upload_sync(g->prefix, prefix.data(), prefix.size() * sizeof(int64_t));
-        g->nchunks = prefix.back();
+        g->npieces = prefix.back();
     }
     out->buf.reset();
     out->meta_only = true;
@@ -1541,7 +1698,7 @@ TensorPtr run_gather_plan(const GatherPlan& g, const Tensor& src, hipStream_t s)
     if (g.zero) launch_fill_zero(out->data(), ((std::max<int64_t>(out->elems, 1) * out->esize() + 3) / 4) * 4, s);
     if (g.ntasks > 0) {
         const bool f64 = src.dtype == SYMTEN_F64;
-        copy_launch_arg((const CopyTask*)g.tasks->ptr, (const int64_t*)g.prefix->ptr, g.ntasks, g.nchunks,
+        copy_launch_arg((const CopyTask*)g.tasks->ptr, (const int64_t*)g.prefix->ptr, g.ntasks, g.npieces,
                         {src.data(), out->data()}, f64, f64 ? 1 : 0, s);
     }
     return out;
