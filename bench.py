@@ -90,9 +90,12 @@ def profile_name(rocprof_name):
     if fam == "gemm_f32_kernel":
         return "gemm_f32_kernel<%sx%sx%s,f32>" % t.groups()
     if fam == "gemm_bf16_kernel":
-        # the last template argument is the number of bf16 planes
-        kind = {"1": "bf16", "2": "bf16x3", "3": "bf16x6"}.get(last, last)
-        return "gemm_bf16_kernel<%sx%sx%s,%s>" % (t.groups() + (kind,))
+        # template arguments after the tile: the number of bf16 planes, then
+        # whether the epilogue scatters into the next contraction's panels
+        tail = [x.strip() for x in args[args.index(t.group(0)) + len(t.group(0)):].split(",") if x.strip()]
+        kind = {"1": "bf16", "2": "bf16x3", "3": "bf16x6"}.get(tail[0], tail[0]) if tail else "?"
+        scatter = ",scatter" if len(tail) > 1 and tail[1] == "true" else ""
+        return "gemm_bf16_kernel<%sx%sx%s,%s%s>" % (t.groups() + (kind, scatter))
     src = "f64" if "double" in args else "f32"
     dst = {"0": "f32", "1": "f64", "2": "bf16", "3": "bf16x2", "4": "acc", "5": "bf16x3"}.get(last, last)
     return "copy_kernel<%s,%s>" % (src, dst)

@@ -2245,7 +2245,7 @@ void run_step(BatchStep& B, hipStream_t s, bool tune = false) {
     if (tune) autotune_gemm(B.tc, B.host_groups, B.prec, launch, s);
     if (B.tc.cfg < 0) fail(SYMTEN_E_INVAL, "internal: batched GEMM launched before tuning");
     const int cfg = B.tc.cfg;
-    profile_launch(gemm_kernel_name(B.prec, cfg) + ",batched", B.info.useful_flops, B.info.gemm_flops, B.gemm_bytes,
+    profile_launch(gemm_kernel_name(B.prec, cfg, B.scatter != nullptr) + ",batched", B.info.useful_flops, B.info.gemm_flops, B.gemm_bytes,
                    s, [&] { launch(cfg); });
 }
 

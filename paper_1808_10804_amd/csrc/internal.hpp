@@ -484,7 +484,7 @@ void profile_launch(const std::string& name, int64_t uf, int64_t gf, int64_t byt
                     const std::function<void()>& launch);
 void profile_begin();
 std::vector<symten_kernel_stat> profile_end();
-std::string gemm_kernel_name(Prec p, int cfg);
+std::string gemm_kernel_name(Prec p, int cfg, bool scatter = false);
 std::string copy_kernel_name(bool src64, Prec p);
 int panel_dst_kind(Prec p);
 int64_t copy_bytes(const std::vector<CopyTask>& tasks, size_t se, size_t de);

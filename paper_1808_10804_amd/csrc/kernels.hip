@@ -565,8 +565,11 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
     constexpr int LDH = BK + 8;
     static_assert(PL >= 1 && PL <= 3, "one to three bf16 planes");
     static_assert(TI >= 1 && TJ >= 1 && BK % 16 == 0, "tile shape");
-    __shared__ __attribute__((aligned(16))) unsigned short As[PL][BM * LDH];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[PL][BN * LDH];
+    // one LDS region: the A and B tiles of the K loop; the scatter
+    // epilogue's tables and staged products afterwards
+    __shared__ __attribute__((aligned(16))) unsigned short smem[PL * (BM + BN) * LDH];
+    unsigned short (*As)[BM * LDH] = reinterpret_cast<unsigned short (*)[BM * LDH]>(smem);
+    unsigned short (*Bs)[BN * LDH] = reinterpret_cast<unsigned short (*)[BN * LDH]>(smem + PL * BM * LDH);
 
   // Entry t of the list belongs to XCD t mod 8, and workgroup b runs on XCD
   // b mod 8.  Each workgroup starts with its own entry; with a queue (a
@@ -769,11 +772,22 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const TileWork* __restri
                             *(uint2*)(P + d[0] + p * g.c_lo) = v;
                         }
                     } else {
+                        // pairs of consecutive, aligned positions as one 4-byte store
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            if (d[q] >= 0)
+                        for (int q = 0; q < 4; q += 2) {
+                            if (d[q] >= 0 && (d[q] & 1) == 0 && d[q + 1] == d[q] + 1) {
 #pragma unroll
-                                for (int p = 0; p < PL; ++p) P[d[q] + p * g.c_lo] = h[q][p];
+                                for (int p = 0; p < PL; ++p)
+                                    *(uint32_t*)(P + d[q] + p * g.c_lo) =
+                                        (uint32_t)h[q][p] | ((uint32_t)h[q + 1][p] << 16);
+                            } else {
+#pragma unroll
+                                for (int k = q; k < q + 2; ++k)
+                                    if (d[k] >= 0)
+#pragma unroll
+                                        for (int p = 0; p < PL; ++p) P[d[k] + p * g.c_lo] = h[k][p];
+                            }
+                        }
                     }
                 }
             }

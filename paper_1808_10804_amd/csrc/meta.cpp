@@ -786,15 +786,16 @@ std::vector<symten_kernel_stat> profile_end() {
     return out;
 }
 
-std::string gemm_kernel_name(Prec p, int cfg) {
+std::string gemm_kernel_name(Prec p, int cfg, bool scatter) {
     const std::string t = std::to_string(gemm_tile_bm(p, cfg)) + "x" + std::to_string(gemm_tile_bn(p, cfg)) + "x" +
                           std::to_string(gemm_tile_bk(p, cfg));
+    const std::string sc = scatter ? ",scatter" : "";
     switch (p) {
         case Prec::F64: return "gemm_f64_kernel<" + t + ">";
         case Prec::F32: return "gemm_f32_kernel<" + t + ",f32>";
-        case Prec::BF16: return "gemm_bf16_kernel<" + t + ",bf16>";
-        case Prec::BF16X3: return "gemm_bf16_kernel<" + t + ",bf16x3>";
-        default: return "gemm_bf16_kernel<" + t + ",bf16x6>";
+        case Prec::BF16: return "gemm_bf16_kernel<" + t + ",bf16" + sc + ">";
+        case Prec::BF16X3: return "gemm_bf16_kernel<" + t + ",bf16x3" + sc + ">";
+        default: return "gemm_bf16_kernel<" + t + ",bf16x6" + sc + ">";
     }
 }
 

@@ -29,15 +29,19 @@ def _counter_csv(path, rows):
 def test_profile_names():
     assert bench.profile_name(GEMM) == "gemm_f32_kernel<64x64x32,f32>"
     assert bench.profile_name(COPY) == "copy_kernel<f32,bf16x2>"
-    # the bf16 kernel's last template argument is its number of planes
+    # the bf16 kernel's template arguments after the tile: its number of
+    # planes, then whether it has the scatter epilogue
     assert bench.profile_name(
-        "void symten::gemm_bf16_kernel<symten::DevPtrs, symten::TileShape<256, 128, 32>, 2>(a)") == \
+        "void symten::gemm_bf16_kernel<symten::DevPtrs, symten::TileShape<256, 128, 32>, 2, false>(a)") == \
         "gemm_bf16_kernel<256x128x32,bf16x3>"
     assert bench.profile_name(
-        "void symten::gemm_bf16_kernel<symten::DevPtrs, symten::TileShape<64, 64, 32>, 3>(a)") == \
+        "void symten::gemm_bf16_kernel<symten::DevPtrs, symten::TileShape<64, 128, 32>, 2, true>(a)") == \
+        "gemm_bf16_kernel<64x128x32,bf16x3,scatter>"
+    assert bench.profile_name(
+        "void symten::gemm_bf16_kernel<symten::DevPtrs, symten::TileShape<64, 64, 32>, 3, false>(a)") == \
         "gemm_bf16_kernel<64x64x32,bf16x6>"
     assert bench.profile_name(
-        "void symten::gemm_bf16_kernel<symten::ArgPtrs, symten::TileShape<64, 64, 32>, 1>(a)") == \
+        "void symten::gemm_bf16_kernel<symten::ArgPtrs, symten::TileShape<64, 64, 32>, 1, false>(a)") == \
         "gemm_bf16_kernel<64x64x32,bf16>"
     assert bench.profile_name(COPY.replace("float, 3>", "float, 5>")) == "copy_kernel<f32,bf16x3>"
     assert bench.profile_name(
