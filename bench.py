@@ -680,16 +680,20 @@ def main():
             mv = bench_move(args, 2, "f32", min(args.steps, 10), min(args.warmup, 2), with_cpu=False)
             out["move_D6_chi64_f32"] = {k: mv[k] for k in ("value", "unit", "ms_per_step", "steps", "config",
                                                           "roofline", "useful_flops_per_move", "gemm_phase_gflops",
-                                                          "phase_ms", "kept", "trunc_err")}
+                                                          "phase_ms", "kept", "trunc_err", "consecutive_moves")}
         print(json.dumps(out))
         return
     print(json.dumps(bench_move(args, args.config, args.prec, args.steps, args.warmup,
                                 with_cpu=not args.no_cpu_baseline)))
 
 
+EVOLVING_MOVES = 6
+
+
 def bench_move(args, config_no, prec, steps, warmup, with_cpu):
     """One full left move of workload `config_no` per step (the environment
-    reset to the same C1, C4, T4 before every move)."""
+    reset to the same C1, C4, T4 before every move, so that every step does
+    the same work), then EVOLVING_MOVES consecutive moves without resets."""
     import torch
     import paper_1808_10804_amd as st
     from synth import config, draw, TENSOR_INDEX
@@ -730,6 +734,21 @@ def bench_move(args, config_no, prec, steps, warmup, with_cpu):
     kstats = st.profile_end()
 
     stats = step(stats=True)
+
+    # A run of consecutive left moves from the same start, without resets:
+    # each move works on the environment the previous one left, and a new
+    # chi-leg structure is planned on the host (and its GEMM tiles chosen)
+    # the first time it appears, as in a real CTM run.
+    run_env = st.CtmEnv([T[k] for k in ("C1", "C2", "C3", "C4")], [T[k] for k in ("T1", "T2", "T3", "T4")])
+    run_ms, run_kept = [], []
+    for _ in range(EVOLVING_MOVES):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = run_env.move(T["a"], chi, prec=prec, stats=True, stream=stream)
+        torch.cuda.synchronize()
+        run_ms.append((time.perf_counter() - t0) * 1e3)
+        run_kept.append(s["kept"])
+
     flops = stats["flops_corners"] + stats["flops_halves"] + stats["flops_renorm"]
     value = flops / (ms_per_step * 1e-3) / 1e9
     gemm_ms = stats["ms_corners"] + stats["ms_halves"] + stats["ms_renorm"]
@@ -747,6 +766,8 @@ def bench_move(args, config_no, prec, steps, warmup, with_cpu):
         "phase_ms": {k: stats[k] for k in ("ms_corners", "ms_halves", "ms_proj", "ms_renorm", "ms_total")},
         "kept": stats["kept"], "trunc_err": stats["trunc_err"],
         "kernels": sorted(kstats, key=lambda k: -k["ms"])[:6],
+        "consecutive_moves": {"what": "left moves from the same start without resets (new chi legs "
+                                      "planned when first seen)", "ms": run_ms, "kept": run_kept},
     }
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline(cfgd, flops)

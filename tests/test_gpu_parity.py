@@ -225,6 +225,26 @@ def test_ctm_move_cfg2(cfg2, prec):
         assert e_L <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["bf16", "bf16x6", "f32"])
+def test_batched_corners_other_precisions(prec):
+    """The batched chain in the other bf16 precisions (step 2's GEMM writes
+    step 3's one- and three-plane panels) and in FP32 (no scatter): equal to
+    the single-corner path up to FP32 reordering, and to the oracle within
+    the precision's tolerance."""
+    draws = batched_draws(batch=4, chi_range=(32, 48))
+    cfgs = [dict(phys={-1: 1, 1: 1}, virt=d["virt"], chi=d["chi"], flux=1) for d in draws]
+    devs = [device_side(cf, 1813, "f32", batch=b) for b, cf in enumerate(cfgs)]
+    args = [[d["C1"] for d in devs], [d["T1"] for d in devs], [d["T4"] for d in devs], [d["a"] for d in devs]]
+    outs, _ = st.enlarged_corners_batched(*args, prec=prec, use_graph=True)
+    for b, (cf, dv, o) in enumerate(zip(cfgs, devs, outs)):
+        single, _ = st.enlarged_corner(1, dv["C1"], dv["T1"], dv["T4"], dv["a"], prec=prec)
+        # BF16: FP32 reordering can flip the bf16 rounding of an intermediate
+        assert rel(o.download(), single.download()) <= (TOL["bf16"] if prec == "bf16" else 1e-6)
+        w, T, a, _ = oracle_side(cf, 1813, batch=b)
+        ref = u1.enlarged_corners(w, T, a)[0].transpose(2, 0, 3, 1)
+        assert rel(to_dense(o, u1.corner_tables(w, 1)[2]["out"].legs), ref) <= TOL[prec]
+
+
 def test_batched_corners_match_single_and_oracle():
     draws = batched_draws(batch=6, chi_range=(32, 48))
     cfgs = [dict(phys={-1: 1, 1: 1}, virt=d["virt"], chi=d["chi"], flux=1) for d in draws]
