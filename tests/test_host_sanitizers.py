@@ -1,7 +1,8 @@
 """The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer.
 
 The host-side library tests (block enumeration, contraction planning, SU(2)
-bookkeeping and recoupling scalars, error codes, planner properties) run in a
+bookkeeping and recoupling scalars, error codes, planner properties, the
+scatter epilogue's tables) run in a
 child process against a second build of libsymten whose host code carries
 both sanitizers (device code as usual, never launched here).  Any report
 fails the test: UBSan is built not to recover, ASan halts on its first error.
@@ -13,7 +14,8 @@ import sys
 from paper_1808_10804_amd import build
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HOST_TESTS = ["tests/test_lib_host.py", "tests/test_lib_su2_host.py", "tests/test_planner_property_host.py"]
+HOST_TESTS = ["tests/test_lib_host.py", "tests/test_lib_su2_host.py", "tests/test_planner_property_host.py",
+              "tests/test_scatter_tables_host.py"]
 
 
 def test_host_tests_pass_under_asan_and_ubsan():
