@@ -526,6 +526,32 @@ int ctm_move_projectors(ctm_env_t env, symten_t* P, symten_t* Pt);
  * environment keeps its own reference to t's storage.                      */
 int ctm_env_set(ctm_env_t env, int k, symten_t t);
 
+/* ---- FP64 symmetric eigensolver of the projector stage ----------------- */
+
+/* Sec. 3 (the projector scheme it cites): every sector of a cut needs the
+ * singular triplets of one matrix; ctm_move takes them from a symmetric
+ * eigenproblem (the Gram matrix Y Y^T, or the Jordan-Wielandt matrix
+ * [[0, Y], [Y^T, 0]] in FP64 moves), solved by these kernels: Householder
+ * tridiagonalisation with the rows of each matrix held in the LDS of its own
+ * workgroups (one exchange between them per column), every eigenvalue by
+ * multisection of Sturm counts, eigenvectors by inverse iteration (close
+ * eigenvalues reorthogonalised), back-transformation through the reflectors.
+ * count problems; A[i]: device, n[i] x n[i], column-major with leading
+ * dimension lda[i] >= n[i], symmetric with both triangles stored, read only
+ * (row i is read as column i); w[i]: device,
+ * n[i] doubles, receives every eigenvalue in ascending order; Z[i]: device,
+ * n[i] x k[i] column-major (ld n[i]), receives the eigenvectors of the k[i]
+ * largest eigenvalues, column j for the (j+1)-th largest, unit norm, sign
+ * unspecified (k[i] = 0: values only, Z[i] may be NULL).  Buffers stay the
+ * caller's.  Orders above symten_eigh_max_order fail with
+ * SYMTEN_E_CAPACITY, a bad argument with SYMTEN_E_INVAL.  Synchronises
+ * `stream` once, between the values and the vectors.                       */
+int symten_eigh(int count, const int* n, const double* const* A, const int* lda, double* const* w,
+                const int* k, double* const* Z, void* stream);
+/* Largest order symten_eigh (and the projector stage's own solver) takes on
+ * the current device; larger blocks of a cut go to the vendor eigensolver. */
+int symten_eigh_max_order(int* nmax);
+
 /* ---- kernel timing ------------------------------------------------------ */
 
 /* While enabled, every gather and grouped-GEMM launch is bracketed by HIP

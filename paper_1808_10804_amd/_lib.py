@@ -136,6 +136,8 @@ SIGNATURES = {
     "ctm_move_singular_values": (C.c_int, [H, C.POINTER(C.c_double), C.c_int64, I64P]),
     "ctm_move_projectors": (C.c_int, [H, C.POINTER(H), C.POINTER(H)]),
     "ctm_env_set": (C.c_int, [H, C.c_int, H]),
+    "symten_eigh": (C.c_int, [C.c_int, IP, C.POINTER(P), IP, C.POINTER(P), IP, C.POINTER(P), P]),
+    "symten_eigh_max_order": (C.c_int, [IP]),
     "symten_profile_begin": (C.c_int, []),
     "symten_profile_end": (C.c_int, [C.POINTER(KernelStat), C.c_int, IP]),
     "symten_last_error": (C.c_char_p, []),

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsymten.so")
-SOURCES = ["kernels.hip", "meta.cpp", "su2.cpp", "abi.cpp", "noalloc.hip", "match.hip"]
+SOURCES = ["kernels.hip", "meta.cpp", "su2.cpp", "abi.cpp", "noalloc.hip", "match.hip", "eig.hip"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 SAN_DIR = os.path.join(HERE, "_build_san")
 SAN_LIB = os.path.join(SAN_DIR, "libsymten.so")

@@ -466,6 +466,40 @@ __global__ void eig_to_svd_kernel(const double* __restrict__ Z, int NE, const do
         for (int r = threadIdx.x; r < rd; r += blockDim.x)
             V[r + (int64_t)j * rd] = f * Z[voff + r + (int64_t)idx * NE];
 }
+// Singular values of a sector from the eigenvalues w (ascending, NE of
+// them) of its Jordan-Wielandt (s = lambda) or Gram (s = sqrt(lambda))
+// matrix: the mn largest, descending, negatives (rounding) clamped to 0.
+__global__ void eigval_to_s_kernel(const double* __restrict__ w, int NE, int mn, int jw, double* __restrict__ S) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < mn; j += gridDim.x * blockDim.x) {
+        const double lam = fmax(w[NE - 1 - j], 0.0);
+        S[j] = jw ? lam : sqrt(lam);
+    }
+}
+// Left (and, Jordan-Wielandt, right) singular vectors of the k largest values
+// from eigenvectors Zk (NE x k, column j for the j-th largest):
+// Jordan-Wielandt u = sqrt2 z[0:ru], v = sqrt2 z[ru:ru+rd]; Gram u = z.
+__global__ void vec_to_uv_kernel(const double* __restrict__ Zk, int NE, int k, int ru, int rd, int jw,
+                                 double* __restrict__ U, double* __restrict__ V) {
+    const int j = blockIdx.x;
+    if (j >= k) return;
+    const double f = jw ? sqrt(2.0) : 1.0;
+    for (int r = threadIdx.x; r < ru; r += blockDim.x) U[r + (int64_t)j * ru] = f * Zk[r + (int64_t)j * NE];
+    if (jw)
+        for (int r = threadIdx.x; r < rd; r += blockDim.x) V[r + (int64_t)j * rd] = f * Zk[ru + r + (int64_t)j * NE];
+}
+// Compact Jordan-Wielandt matrix [[0, Y], [Y^T, 0]] of order ru + rd from
+// Y (ru x rd, column-major, ld ru).
+__global__ void jw_build_compact_kernel(const double* __restrict__ Y, int ru, int rd, double* __restrict__ J) {
+    const int N = ru + rd;
+    const int64_t tot = (int64_t)N * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(i % N), c = (int)(i / N);
+        double v = 0.0;
+        if (r < ru && c >= ru) v = Y[r + (int64_t)(c - ru) * ru];
+        else if (r >= ru && c < ru) v = Y[c + (int64_t)(r - ru) * ru];
+        J[i] = v;
+    }
+}
 // Non-finite entries of X (NaN, Inf) are replaced by 0 and reported in
 // *flag, so that the eigensolver only ever sees finite matrices; the move
 // then fails after the read-back (SYMTEN_E_LINALG).
@@ -527,6 +561,23 @@ void launch_eig_to_svd(const double* Z, int NE, const double* w, int voff, int m
     if (mn <= 0) return;
     hipLaunchKernelGGL(eig_to_svd_kernel, dim3(mn), dim3(256), 0, st, Z, NE, w, voff, mn, ru, rd, jw ? 1 : 0, S, U,
                        V);
+    HIPCHK(hipGetLastError());
+}
+void launch_eigval_to_s(const double* w, int NE, int mn, bool jw, double* S, hipStream_t st) {
+    if (mn <= 0) return;
+    hipLaunchKernelGGL(eigval_to_s_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, w, NE, mn,
+                       jw ? 1 : 0, S);
+    HIPCHK(hipGetLastError());
+}
+void launch_vec_to_uv(const double* Zk, int NE, int k, int ru, int rd, bool jw, double* U, double* V, hipStream_t st) {
+    if (k <= 0) return;
+    hipLaunchKernelGGL(vec_to_uv_kernel, dim3((unsigned)k), dim3(256), 0, st, Zk, NE, k, ru, rd, jw ? 1 : 0, U, V);
+    HIPCHK(hipGetLastError());
+}
+void launch_jw_build_compact(const double* Y, int ru, int rd, double* J, hipStream_t st) {
+    const int64_t N = (int64_t)ru + rd;
+    if (N <= 0) return;
+    hipLaunchKernelGGL(jw_build_compact_kernel, dim3((unsigned)g1d(N * N)), dim3(256), 0, st, Y, ru, rd, J);
     HIPCHK(hipGetLastError());
 }
 void launch_pad_blocks(const PadArgs& a, double* dst, hipStream_t st) {
@@ -637,16 +688,21 @@ struct ProjOut {
 
 // Work buffers of one cut's eigensolves, enqueued but not yet read back.
 struct ProjWork {
-    int ru = 0, rd = 0, ld = 0;
+    int ru = 0, rd = 0, ld = 0;  // ld: of H_u^T, H_d^T
+    int ldy = 0;                 // of Y
     double *HuT = nullptr, *HdT = nullptr, *Y = nullptr;
-    int* info = nullptr;
+    int* info = nullptr;         // rocSOLVER's status (vendor route only)
     int* nonfinite = nullptr;    // set when Y held NaN or Inf (zeroed before the solve)
+    int prob = -1;               // own route: the sector's problem in the cut set's EighWork
+    int ne = 0;                  // own route: order of its eigenproblem
+    double* w = nullptr;         // own route: its eigenvalues, ascending
     BufferPtr U, V, S;
 };
 struct ProjPending {
     std::vector<ProjWork> w;
     std::vector<BufferPtr> keep_alive;
     bool aux_used[ctm_env::kAux] = {};
+    std::shared_ptr<EighWork> eig;   // own route: shared by the cuts solved together
 };
 
 // One size class of a cut: its blocks zero-padded to N, Y = H_u^T H_d, the
@@ -707,6 +763,7 @@ void solve_class(const std::vector<CutSector>& secs, std::vector<ProjWork>& w, c
         x.HdT = (double*)Hb->ptr + (2 * i + 1) * N2;    // H_d^T
         x.Y = (double*)Mb->ptr + i * N2;
         x.ld = N;
+        x.ldy = N;
         x.info = (int*)ib->ptr + i;
         x.nonfinite = (int*)fb->ptr;
         x.S = device_alloc(8 * std::max(1, b.mn));
@@ -716,6 +773,96 @@ void solve_class(const std::vector<CutSector>& secs, std::vector<ProjWork>& w, c
                           b.mn, x.ru, x.rd, f64, (double*)x.S->ptr, (double*)x.U->ptr, (double*)x.V->ptr, cs);
     }
     for (auto& x : {Hb, Mb, Zb, wb, Eb, ib, fb}) keep.push_back(x);
+}
+
+// The library's own eigensolver (every eigenproblem of the given cuts fits
+// its LDS): per sector, H_u^T and H_d^T as FP64 col-major blocks, Y = H_u^T
+// H_d (ru x rd, compact), its Gram or compact Jordan-Wielandt matrix; then
+// one set of launches tridiagonalises every matrix of every cut and finds
+// all eigenvalues, and each sector's singular values are taken from them.
+// Everything is enqueued on s; no host thread, no side stream.
+std::vector<ProjPending> issue_solves_own(ctm_env* env, const std::vector<std::vector<CutSector>*>& cuts, bool f64,
+                                          hipStream_t s) {
+    rb_check(rocblas_set_stream(env->rb, s), "rocblas_set_stream");
+    const double one = 1.0, zero = 0.0;
+    std::vector<ProjPending> pend(cuts.size());
+    std::vector<EighProblem> probs;
+    BufferPtr fb = device_alloc(4 * cuts.size());
+    launch_fill_zero(fb->ptr, 4 * (int64_t)cuts.size(), s);
+    for (size_t c = 0; c < cuts.size(); ++c) {
+        std::vector<CutSector>& secs = *cuts[c];
+        if (secs.empty()) fail(SYMTEN_E_LINALG, "ctm_move: the halves have no common sector");
+        pend[c].w.resize(secs.size());
+        pend[c].keep_alive.push_back(fb);
+        for (size_t i = 0; i < secs.size(); ++i) {
+            CutSector& b = secs[i];
+            ProjWork& x = pend[c].w[i];
+            x.ru = b.mu;
+            x.rd = b.md;
+            b.mn = std::min(b.n, std::min(b.mu, b.md));
+            const int N = std::max(b.n, std::max(b.mu, b.md));
+            const size_t N2 = (size_t)N * N;
+            BufferPtr Hb = device_alloc(8 * N2 * 2);
+            PadArgs pa{};
+            pa.count = 2;
+            pa.N = N;
+            pa.src_f64 = f64;
+            pa.src[0] = b.hu;
+            pa.rows[0] = b.mu;
+            pa.cols[0] = b.n;
+            pa.src[1] = b.hd;
+            pa.rows[1] = b.md;
+            pa.cols[1] = b.n;
+            launch_pad_blocks(pa, (double*)Hb->ptr, s);
+            x.HuT = (double*)Hb->ptr;
+            x.HdT = (double*)Hb->ptr + N2;
+            x.ld = N;
+            BufferPtr Yb = device_alloc(8 * std::max<size_t>(1, (size_t)b.mu * b.md));
+            x.Y = (double*)Yb->ptr;
+            x.ldy = std::max(1, b.mu);
+            rb_check(rocblas_dgemm(env->rb, rocblas_operation_none, rocblas_operation_transpose, b.mu, b.md, b.n,
+                                   &one, x.HuT, N, x.HdT, N, &zero, x.Y, x.ldy),
+                     "rocblas_dgemm(Y)");
+            x.nonfinite = (int*)fb->ptr + c;
+            launch_nonfinite_guard(x.Y, (int64_t)b.mu * b.md, x.nonfinite, s);
+            x.ne = f64 ? b.mu + b.md : b.mu;
+            BufferPtr Ab = device_alloc(8 * (size_t)x.ne * x.ne);
+            if (f64)
+                launch_jw_build_compact(x.Y, b.mu, b.md, (double*)Ab->ptr, s);
+            else
+                rb_check(rocblas_dgemm(env->rb, rocblas_operation_none, rocblas_operation_transpose, b.mu, b.mu, b.md,
+                                       &one, x.Y, x.ldy, x.Y, x.ldy, &zero, (double*)Ab->ptr, x.ne),
+                         "rocblas_dgemm(YY^T)");
+            BufferPtr wb = device_alloc(8 * (size_t)x.ne);
+            x.w = (double*)wb->ptr;
+            x.prob = (int)probs.size();
+            EighProblem ep;
+            ep.n = x.ne;
+            ep.lda = x.ne;
+            ep.A = (const double*)Ab->ptr;
+            ep.w = x.w;
+            probs.push_back(ep);
+            x.S = device_alloc(8 * std::max(1, b.mn));
+            for (auto& k : {Hb, Yb, Ab, wb}) pend[c].keep_alive.push_back(k);
+        }
+    }
+    auto wk = eigh_values(probs, s);
+    for (size_t c = 0; c < cuts.size(); ++c) {
+        pend[c].eig = wk;
+        std::vector<CutSector>& secs = *cuts[c];
+        for (size_t i = 0; i < secs.size(); ++i) {
+            ProjWork& x = pend[c].w[i];
+            launch_eigval_to_s(x.w, x.ne, secs[i].mn, f64, (double*)x.S->ptr, s);
+        }
+    }
+    return pend;
+}
+
+bool own_solver_fits(const std::vector<std::vector<CutSector>*>& cuts, bool f64) {
+    for (auto* secs : cuts)
+        for (auto& b : *secs)
+            if (!eigh_fits(f64 ? b.mu + b.md : b.mu)) return false;
+    return true;
 }
 
 // Enqueues the eigensolves of every sector of the given cuts (no host
@@ -729,6 +876,7 @@ void solve_class(const std::vector<CutSector>& secs, std::vector<ProjWork>& w, c
 // their own, each with the stream's own rocBLAS handle.
 std::vector<ProjPending> issue_solves(ctm_env* env, const std::vector<std::vector<CutSector>*>& cuts, bool f64,
                                       hipStream_t s, hipEvent_t start) {
+    if (own_solver_fits(cuts, f64)) return issue_solves_own(env, cuts, f64, s);
     rb_check(rocblas_set_stream(env->rb, s), "rocblas_set_stream");
     constexpr int kSlots = ctm_env::kAux + 1;
     struct SolveClass {
@@ -829,6 +977,7 @@ ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPendin
     std::vector<ProjWork>& w = pend.w;
     ProjOut out;
     std::vector<int> sv_off;
+    std::vector<std::vector<double>> w_host(secs.size());
     {
         for (int a = 0; a < ctm_env::kAux; ++a)
             if (pend.aux_used[a]) {
@@ -843,14 +992,23 @@ ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPendin
         for (size_t i = 0; i < secs.size(); ++i) {
             if (secs[i].mn)
                 HIPCHK(hipMemcpyAsync(out.sv.data() + sv_off[i], pend.w[i].S->ptr, 8 * secs[i].mn, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(&infos[i], pend.w[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
+            if (pend.w[i].info)
+                HIPCHK(hipMemcpyAsync(&infos[i], pend.w[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipMemcpyAsync(&bad[i], pend.w[i].nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+        }
+        if (pend.eig) {
+            // eigenvalues of the cut's problems (for the eigenvector phase)
+            for (size_t i = 0; i < secs.size(); ++i) {
+                w_host[i].resize(pend.w[i].ne);
+                HIPCHK(hipMemcpyAsync(w_host[i].data(), pend.w[i].w, 8 * (size_t)pend.w[i].ne, hipMemcpyDeviceToHost, s));
+            }
+            eigh_status(*pend.eig, s);   // synchronises s
         }
         HIPCHK(hipStreamSynchronize(s));
         for (size_t i = 0; i < secs.size(); ++i)
             if (bad[i]) fail(SYMTEN_E_LINALG, "ctm_move: NaN or Inf in the halves of the cut");
         for (size_t i = 0; i < secs.size(); ++i)
-            if (infos[i] != 0) fail(SYMTEN_E_LINALG, "rocsolver_dsyevd did not converge");
+            if (pend.w[i].info && infos[i] != 0) fail(SYMTEN_E_LINALG, "rocsolver_dsyevd did not converge");
         for (double v : out.sv)
             if (!std::isfinite(v)) fail(SYMTEN_E_LINALG, "non-finite singular value");
     }
@@ -898,6 +1056,32 @@ ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPendin
     out.gap = nkeep < (int)all.size() ? (all[nkeep - 1].s - all[nkeep].s) / out.smax : INFINITY;
     for (int i = 0; i < nkeep; ++i) secs[all[i].sec].k += 1;
     // the kept set of a sector is a prefix of its descending list
+    if (pend.eig) {
+        // own route: eigenvectors of the kept values only, then u (and v)
+        std::vector<int> kv(eigh_problems(*pend.eig), 0);
+        std::vector<double*> zs(kv.size(), nullptr);
+        std::vector<const double*> wh(kv.size(), nullptr);
+        std::vector<BufferPtr> zb(secs.size());
+        for (size_t i = 0; i < secs.size(); ++i) {
+            ProjWork& x = w[i];
+            const int k = secs[i].k;
+            if (k == 0) continue;
+            zb[i] = device_alloc(8 * (size_t)x.ne * k);
+            kv[x.prob] = k;
+            zs[x.prob] = (double*)zb[i]->ptr;
+            wh[x.prob] = w_host[i].data();
+        }
+        eigh_vectors(*pend.eig, kv, zs, wh, s);
+        for (size_t i = 0; i < secs.size(); ++i) {
+            ProjWork& x = w[i];
+            const int k = secs[i].k;
+            if (k == 0) continue;
+            x.U = device_alloc(8 * (size_t)x.ru * k);
+            x.V = device_alloc(8 * (size_t)x.rd * k);
+            launch_vec_to_uv((const double*)zb[i]->ptr, x.ne, k, x.ru, x.rd, f64, (double*)x.U->ptr,
+                             (double*)x.V->ptr, s);
+        }
+    }
     // ---- P = H_d V_k S^-1/2 (n x k), P~ = S^-1/2 U_k^T H_u^T (k x n) -------
     for (auto& c : secs) {
         c.pbase = out.ptot;
@@ -917,7 +1101,7 @@ ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPendin
         if (!f64) {
             // Gram path: V_k = Y^T U_k S_k^-1  (rd x k, ld rd)
             rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, x.rd, k, x.ru, &one,
-                                   (const double*)x.Y, x.ld, (const double*)x.U->ptr, x.ru, &zero, (double*)x.V->ptr,
+                                   (const double*)x.Y, x.ldy, (const double*)x.U->ptr, x.ru, &zero, (double*)x.V->ptr,
                                    x.rd),
                      "rocblas_dgemm(V)");
             launch_scale_cols((double*)x.V->ptr, x.rd, x.rd, k, (const double*)x.S->ptr, -1.0, s);
@@ -2006,6 +2190,47 @@ int symten_contract_noalloc(symten_t out, symten_t A, symten_t B, int ncon, cons
         if (!out) fail(SYMTEN_E_INVAL, "contract_noalloc: null output tensor");
         auto p = cached_plan(T(A), T(B), ncon, legsA, legsB, out_perm, prec);
         contract_noalloc(T(out), T(A), T(B), p, S(stream));
+    });
+}
+
+int symten_eigh(int count, const int* n, const double* const* A, const int* lda, double* const* w, const int* k,
+                double* const* Z, void* stream) {
+    return guard_on(stream, [&] {
+        if (count < 0) fail(SYMTEN_E_INVAL, "eigh: negative count");
+        if (count == 0) return;
+        if (!n || !A || !lda || !w || !k || !Z) fail(SYMTEN_E_INVAL, "eigh: null array");
+        std::vector<EighProblem> probs(count);
+        for (int i = 0; i < count; ++i) {
+            if (n[i] < 1 || lda[i] < n[i] || !A[i] || !w[i]) fail(SYMTEN_E_INVAL, "eigh: bad problem");
+            if (k[i] < 0 || k[i] > n[i] || (k[i] > 0 && !Z[i])) fail(SYMTEN_E_INVAL, "eigh: bad vector count");
+            if (!eigh_fits(n[i])) fail(SYMTEN_E_CAPACITY, "eigh: order above symten_eigh_max_order");
+            probs[i].n = n[i];
+            probs[i].lda = lda[i];
+            probs[i].A = A[i];
+            probs[i].w = w[i];
+        }
+        hipStream_t s = S(stream);
+        auto wk = eigh_values(probs, s);
+        eigh_status(*wk, s);   // synchronises s
+        std::vector<std::vector<double>> wh(count);
+        std::vector<const double*> whp(count);
+        std::vector<int> kv(count);
+        std::vector<double*> zs(count);
+        for (int i = 0; i < count; ++i) {
+            wh[i].resize(n[i]);
+            HIPCHK(hipMemcpy(wh[i].data(), w[i], 8 * (size_t)n[i], hipMemcpyDeviceToHost));
+            whp[i] = wh[i].data();
+            kv[i] = k[i];
+            zs[i] = Z[i];
+        }
+        eigh_vectors(*wk, kv, zs, whp, s);
+    });
+}
+
+int symten_eigh_max_order(int* nmax) {
+    return guard([&] {
+        if (!nmax) fail(SYMTEN_E_INVAL, "null output");
+        *nmax = eigh_max_order();
     });
 }
 

@@ -280,6 +280,26 @@ struct DoubleLayerArgs {
 void launch_double_layer(const DoubleLayerArgs& a, hipStream_t s);
 // scatter of a contiguous-block tensor into a dense array
 void launch_sign_fix_rows(double* Pt, int ldPt, int rows, int n, double* P, int ldP, hipStream_t s);
+// FP64 symmetric eigensolver of the projector stage (eig.hip).  Phase one
+// enqueues the tridiagonalisations and all eigenvalues (w, ascending);
+// phase two, once the caller has the eigenvalues on the host, the
+// eigenvectors of the kv[i] largest into Z[i] (n x kv, column-major, column
+// j for the (j+1)-th largest).  The work object keeps the buffers the
+// phases share.
+struct EighProblem {
+    int n = 0, lda = 0;
+    const double* A = nullptr;   // n x n, column-major, both triangles
+    double* w = nullptr;         // n eigenvalues, ascending
+};
+struct EighWork;
+bool eigh_fits(int n);
+int eigh_problems(const EighWork& wk);
+int eigh_max_order();
+std::shared_ptr<EighWork> eigh_values(const std::vector<EighProblem>& probs, hipStream_t s);
+// synchronises s; fails if a tridiagonalisation's workgroups did not meet
+void eigh_status(const EighWork& wk, hipStream_t s);
+void eigh_vectors(EighWork& wk, const std::vector<int>& kv, const std::vector<double*>& Z,
+                  const std::vector<const double*>& w_host, hipStream_t s);
 
 // -------------------------------------------------------------- contraction --
 struct GroupPlan {

@@ -281,6 +281,34 @@ def match_blocks(A, B, legsA, legsB, pair_cap=None, out_cap=None, stream=None):
     return rows.astype(np.int64), outl.cpu().numpy()[:min(int(cnt[3]), out_cap), :ro], cnt
 
 
+def eigh(mats, k, stream=None):
+    """FP64 symmetric eigensolver of the projector stage (symten_eigh) on
+    torch float64 device matrices (square, symmetric, contiguous; read
+    column by column).  k: eigenvectors wanted per matrix (an int or one per
+    matrix).  Returns [(w ascending, Z with the eigenvector of the j-th
+    largest eigenvalue in column j)], torch device tensors."""
+    import torch
+    count = len(mats)
+    ks = [int(k)] * count if isinstance(k, int) else [int(x) for x in k]
+    ws = [torch.empty(m.shape[0], dtype=torch.float64, device=m.device) for m in mats]
+    zs = [torch.zeros((max(x, 1), m.shape[0]), dtype=torch.float64, device=m.device) for m, x in zip(mats, ks)]
+    P = C.c_void_p
+    n = (C.c_int * count)(*[m.shape[0] for m in mats])
+    A = (P * count)(*[m.data_ptr() for m in mats])
+    W = (P * count)(*[x.data_ptr() for x in ws])
+    Z = (P * count)(*[z.data_ptr() for z in zs])
+    check(lib().symten_eigh(count, n, A, n, W, (C.c_int * count)(*ks), Z, _stream(stream)))
+    check(lib().symten_sync(_stream(stream)))
+    # zs rows are columns of the column-major n x k result
+    return [(w, z[:x].T) for w, z, x in zip(ws, zs, ks)]
+
+
+def eigh_max_order():
+    n = C.c_int()
+    check(lib().symten_eigh_max_order(C.byref(n)))
+    return int(n.value)
+
+
 def plan_info(A, B, legsA, legsB, out_perm=None):
     """Host-only planning; returns (stats dict, metadata-only output Tensor)."""
     st = _lib.PlanStats()
