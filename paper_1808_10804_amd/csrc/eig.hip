@@ -18,7 +18,7 @@
 //      lanes evaluating Sturm counts of T at 64 points of the current
 //      interval, about 9 passes to 2 ulp.
 //   3. Eigenvectors of T for the kept eigenvalues by inverse iteration
-//      (tridiagonal LU with partial pivoting, three solves from a fixed
+//      (tridiagonal LU with partial pivoting, two solves from a fixed
 //      pseudo-random start); eigenvalues closer than 1e-3 ||T|| form a
 //      cluster whose vectors are computed by one thread in order and
 //      reorthogonalised against the earlier ones in every solve.
@@ -174,12 +174,28 @@ struct Xchg {
 constexpr int kSlots = 2;   // n <= kSlots * kTriThreads: entries j = tid + kTriThreads s per thread
 
 // Step 1.  bmap[b] = (job, rank) of workgroup b; job < 0: idle workgroup.
-// Dynamic LDS: R rows of n, three vectors of n, reduction scratch.
-// Per column k: the Householder vector of column k (every workgroup, from
-// the column with the pending update applied), then one pass over the own
-// rows i > k that applies the pending update and forms p_i; the owner of row
-// k+1 publishes it; barrier; then p and row k+1 are loaded together, w
-// becomes the pending update and row k+1 becomes column k+1.
+// Dynamic LDS: R rows of n, v and w of the last two columns (2 x 2 n), the
+// reduction scratch.  Thread t owns the entries j = t + kTriThreads q of the
+// column vectors (the column, v, p, w), kept in registers.  Per column k:
+// (a) the Householder vector from the column (every workgroup; its norm and
+// the two leading entries come out of one block reduction); (b) one pass
+// over the own rows i > k that applies the pending update of column k-1 and
+// forms p_i = tau (row_i . v); the owner of row k+1 publishes it; (c) the
+// barrier; (d) p and row k+1 are loaded together, w = p - (tau/2)(p.v) v
+// (second block reduction) becomes the pending update and row k+1 with it
+// the next column.  Block reductions alternate between two scratch halves,
+// so each costs one workgroup barrier.
+__device__ inline double block_sum_x(double x, double* red, int& par) {
+    x = wave_sum(x);
+    double* r = red + par * kTriWaves;
+    if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kTriWaves; ++i) s += r[i];
+    par ^= 1;
+    return s;
+}
 __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(const TridJob* __restrict__ jobs,
                                                                const int2* __restrict__ bmap) {
     const int2 bm = bmap[blockIdx.x];
@@ -188,14 +204,14 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(const TridJob* __r
     const int g = bm.y, G = J.G, n = J.n;
     extern __shared__ double sm[];
     double* rows = sm;
-    double* vp = rows + (size_t)J.R * n;   // v of the pending update (column k-1)
-    double* wp = vp + n;                   // w of the pending update
-    double* vn = wp + n;                   // the column, then v of column k
-    double* red = vn + n;
+    double* vb = rows + (size_t)J.R * n;   // v of columns k (vb + (k & 1) n)
+    double* wb = vb + 2 * (size_t)n;       // w of columns k (wb + (k & 1) n)
+    double* red = wb + 2 * (size_t)n;      // 2 x kTriWaves
+    double* slot = red + 2 * kTriWaves;    // the column's diagonal entry and alpha
     __shared__ int failed;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) failed = 0;
-    int epoch = 0;
+    int epoch = 0, par = 0;
     const int nloc = g < n ? (n - g + G - 1) / G : 0;   // rows i = g + r G
     // exchange area: G maxima, G XCC ids, then per column k the published
     // row k+1 (npad) and the p slices (npad)
@@ -234,31 +250,43 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(const TridJob* __r
     if (g == 0 && tid == 0) *J.scale = sc;
     for (int r = 0; r < nloc; ++r)
         for (int j = tid; j < n; j += kTriThreads) rows[(size_t)r * n + j] *= sc;
-    double part = 0.0;
+    // the pending update of column -1 is zero
     for (int j = tid; j < n; j += kTriThreads) {
-        vp[j] = 0.0;
-        wp[j] = 0.0;
-        const double c = J.A[j] * sc;   // column 0
-        vn[j] = c;
-        if (j >= 2) part += c * c;
+        vb[n + j] = 0.0;
+        wb[n + j] = 0.0;
     }
-    double xn2 = block_sum<kTriWaves>(part, red);
-    if (n == 1 && g == 0 && tid == 0) J.d[0] = vn[0];
+    double col[kSlots], vr[kSlots];
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) {
+        const int j = tid + q * kTriThreads;
+        col[q] = j < n ? J.A[j] * sc : 0.0;   // column 0
+        if (j == 0) slot[0] = col[q];
+        if (j == 1) slot[1] = col[q];
+        if (j >= 2 && j < n) part += col[q] * col[q];
+    }
+    double xn2 = block_sum_x(part, red, par);
+    if (n == 1 && g == 0 && tid == 0) J.d[0] = slot[0];
 
     for (int k = 0; k + 1 < n; ++k) {
-        // Householder vector of column k (in vn)
-        const double dk = vn[k], alpha = vn[k + 1];
+        // (a) Householder vector of column k
+        const double dk = slot[0], alpha = slot[1];
         double tau = 0.0, beta = alpha, scal = 0.0;
         if (xn2 > 0.0) {
             beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
             tau = (beta - alpha) / beta;
             scal = 1.0 / (alpha - beta);
         }
-        __syncthreads();   // vn[k], vn[k+1] read before they change
-        for (int j = k + 1 + tid; j < n; j += kTriThreads) {
-            const double v = j == k + 1 ? 1.0 : vn[j] * scal;
-            vn[j] = v;
-            if (g == 0) J.V[(size_t)k * n + j] = v;
+        double* v = vb + (size_t)(k & 1) * n;
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+            const int j = tid + q * kTriThreads;
+            vr[q] = 0.0;
+            if (j > k && j < n) {
+                vr[q] = j == k + 1 ? 1.0 : col[q] * scal;
+                v[j] = vr[q];
+                if (g == 0) J.V[(size_t)k * n + j] = vr[q];
+            }
         }
         if (g == 0 && tid == 0) {
             J.d[k] = dk;
@@ -266,8 +294,9 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(const TridJob* __r
             J.tau[k] = tau;
         }
         __syncthreads();
-        // own rows i > k, one per wave at a time: pending update,
-        // p_i = tau (row_i . v); row k+1 is published
+        // (b) own rows i > k, one per wave at a time
+        const double* vp = vb + (size_t)((k + 1) & 1) * n;   // v, w of column k-1
+        const double* wp = wb + (size_t)((k + 1) & 1) * n;
         const int64_t pofs = oP + k * npad, rofs = oR + k * npad;
         const int r0 = k + 1 <= g ? 0 : (k + 1 - g + G - 1) / G;
         for (int r = r0 + wave; r < nloc; r += kTriWaves) {
@@ -280,15 +309,17 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(const TridJob* __r
             for (int j = k + 1 + lane; j < n; j += 64) {
                 const double a = row[j] - vpi * wp[j] - wpi * vp[j];
                 row[j] = a;
-                acc += a * vn[j];
+                acc += a * v[j];
                 if (pub) X.st(rofs + j, a);
             }
             acc = wave_sum(acc);
             if (lane == 0) X.st(pofs + i, tau * acc);
         }
+        // (c)
         job_barrier(J.counter, epoch, G, &failed);
-        // p and row k+1, loaded together
+        // (d) p and row k+1, loaded together
         double pr[kSlots], rr[kSlots];
+        const double p1 = X.ld(pofs + k + 1);
         part = 0.0;
 #pragma unroll
         for (int q = 0; q < kSlots; ++q) {
@@ -298,37 +329,29 @@ __global__ __launch_bounds__(kTriThreads) void tridiag_kernel(const TridJob* __r
                 pr[q] = X.ld(pofs + j);
                 rr[q] = X.ld(rofs + j);
             }
+            part += pr[q] * vr[q];
         }
-#pragma unroll
-        for (int q = 0; q < kSlots; ++q) {
-            const int j = tid + q * kTriThreads;
-            if (j > k && j < n) part += pr[q] * vn[j];
-        }
-        const double c2 = 0.5 * tau * block_sum<kTriWaves>(part, red);
-#pragma unroll
-        for (int q = 0; q < kSlots; ++q) {
-            const int j = tid + q * kTriThreads;
-            if (j > k && j < n) wp[j] = pr[q] - c2 * vn[j];
-        }
-        double* t = vp;
-        vp = vn;
-        vn = t;
-        __syncthreads();
-        // column k+1: row k+1 with the new pending update
-        const double vpk = vp[k + 1], wpk = wp[k + 1];
+        const double c2 = 0.5 * tau * block_sum_x(part, red, par);
+        const double w1 = p1 - c2;   // w of entry k+1 (v's entry there is 1)
+        double* w = wb + (size_t)(k & 1) * n;
         part = 0.0;
 #pragma unroll
         for (int q = 0; q < kSlots; ++q) {
             const int j = tid + q * kTriThreads;
             if (j > k && j < n) {
-                const double c = rr[q] - vp[j] * wpk - wp[j] * vpk;
-                vn[j] = c;
+                const double wj = pr[q] - c2 * vr[q];
+                w[j] = wj;
+                const double c = rr[q] - vr[q] * w1 - wj;   // row k+1 with the update of column k
+                col[q] = c;
+                if (j == k + 1) slot[0] = c;
+                if (j == k + 2) slot[1] = c;
                 if (j >= k + 3) part += c * c;
             }
         }
-        xn2 = block_sum<kTriWaves>(part, red);
-        if (k + 2 == n && g == 0 && tid == 0) J.d[n - 1] = vn[n - 1];
+        xn2 = block_sum_x(part, red, par);
+        if (k + 2 == n && g == 0 && tid == 0) J.d[n - 1] = slot[0];
     }
+    __syncthreads();
     if (tid == 0 && failed) *J.status = 1;
 }
 
@@ -382,7 +405,12 @@ __global__ __launch_bounds__(kEigThreads) void bisect_kernel(const BisJob* __res
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
         for (int i = 1; i < n; ++i) {
-            q = (d[i] - x) - e2[i - 1] / q;
+            // e2 / q with the hardware reciprocal and one Newton step
+            // (full precision in two fused operations instead of a
+            // division's sequence)
+            const double r0 = __builtin_amdgcn_rcp(q);
+            const double r1 = fma(r0, fma(-q, r0, 1.0), r0);
+            q = (d[i] - x) - e2[i - 1] * r1;
             if (fabs(q) < pivmin) q = -pivmin;
             cnt += q < 0.0;
         }
@@ -398,6 +426,12 @@ __global__ __launch_bounds__(kEigThreads) void bisect_kernel(const BisJob* __res
     }
     if (lane == 0) J.w[j] = 0.5 * (a + b) / *J.scale;
 }
+
+// Inverse iteration solves per eigenvector: from a random start, the first
+// solve leaves an error of about |lambda error| / gap, the second one at
+// rounding level (eigenvalues from the multisection are accurate to
+// 2 eps ||T||).
+constexpr int kInvIters = 2;
 
 struct VecJob {
     const double *d, *e, *scale, *w;   // w: eigenvalues ascending, unscaled
@@ -468,7 +502,8 @@ __global__ __launch_bounds__(64) void tdvec_kernel(const VecJob* __restrict__ jo
                 enx = i + 3 < n ? e[i + 2] : 0.0;
                 if (fabs(cd) >= fabs(s0)) {
                     if (fabs(cd) < small) cd = cd < 0.0 ? -small : small;
-                    const double r = 1.0 / cd;
+                    const double r0 = __builtin_amdgcn_rcp(cd);
+                    const double r = fma(r0, fma(-cd, r0, 1.0), r0);
                     const double f = s0 * r;
                     dl[i] = f;
                     du[i] = cu;
@@ -477,9 +512,11 @@ __global__ __launch_bounds__(64) void tdvec_kernel(const VecJob* __restrict__ jo
                     piv[i] = 0.0;
                     nd -= f * cu;
                 } else {
-                    const double f = cd / s0;
+                    const double r0 = __builtin_amdgcn_rcp(s0);
+                    const double r = fma(r0, fma(-s0, r0, 1.0), r0);
+                    const double f = cd * r;
                     dl[i] = f;
-                    rdd[i] = 1.0 / s0;
+                    rdd[i] = r;
                     du[i] = nd;
                     du2[i] = nu;
                     piv[i] = 1.0;
@@ -494,7 +531,7 @@ __global__ __launch_bounds__(64) void tdvec_kernel(const VecJob* __restrict__ jo
         }
         for (int i = lane; i < n; i += 64) z[i] = start_entry(i, jr);
         __syncthreads();
-        for (int it = 0; it < 3; ++it) {
+        for (int it = 0; it < kInvIters; ++it) {
             if (lane == 0) {
                 // L U y = P z in place: forward with the interchanges ...
                 double zi = z[0];
@@ -689,7 +726,7 @@ DevInfo dev_info() {
 // does not fit the chip's LDS).
 void tridiag_shape(int n, const DevInfo& di, int& R, int& G) {
     R = G = 0;
-    const int64_t doubles = di.lds / 8 - 3LL * n - kTriWaves;
+    const int64_t doubles = di.lds / 8 - 4LL * n - 2 * kTriWaves - 2;
     if (n <= 0 || doubles < n) return;
     R = (int)std::min<int64_t>(doubles / n, n);
     G = (n + R - 1) / R;
