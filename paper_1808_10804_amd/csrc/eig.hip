@@ -976,8 +976,12 @@ std::shared_ptr<EighWork> eigh_values(const std::vector<EighProblem>& probs, hip
         const TridJob* djobs = (const TridJob*)db->ptr;
         const int2* dmap = (const int2*)((const char*)db->ptr + jb);
         void* args[] = {(void*)&djobs, (void*)&dmap};
-        HIPCHK(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3((unsigned)bmap.size()),
-                                          dim3(kTriThreads), args, (unsigned)lds_bytes, s));
+        int64_t flops = 0;   // Householder tridiagonalisation: 4/3 n^3 (FP64)
+        for (int p : L) flops += 4 * (int64_t)probs[p].n * probs[p].n * probs[p].n / 3;
+        profile_launch("eigh_tridiag", flops, flops, 0, s, [&] {
+            HIPCHK(hipLaunchCooperativeKernel((const void*)tridiag_kernel, dim3((unsigned)bmap.size()),
+                                              dim3(kTriThreads), args, (unsigned)lds_bytes, s));
+        });
     }
     // ---- step 2: one wave per eigenvalue, four per workgroup
     {
@@ -996,9 +1000,11 @@ std::shared_ptr<EighWork> eigh_values(const std::vector<EighProblem>& probs, hip
         descs.push_back(db);
         const size_t lb = 16 * (size_t)nmax;
         if (lb > lds_bytes) fail(SYMTEN_E_CAPACITY, "eigh: tridiagonal matrix exceeds LDS");
-        hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)bmap.size()), dim3(kEigThreads), lb, s,
-                           (const BisJob*)db->ptr, (const int2*)((const char*)db->ptr + jb));
-        HIPCHK(hipGetLastError());
+        profile_launch("eigh_bisect", 0, 0, 0, s, [&] {
+            hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)bmap.size()), dim3(kEigThreads), lb, s,
+                               (const BisJob*)db->ptr, (const int2*)((const char*)db->ptr + jb));
+            HIPCHK(hipGetLastError());
+        });
     }
     for (auto& b : descs) wk->keep.push_back(b);
     return wk;
@@ -1078,12 +1084,18 @@ void eigh_vectors(EighWork& wk, const std::vector<int>& kv, const std::vector<do
     const size_t lb = 8 * ((size_t)(ch + 2) * nmax + 4);
     if (lb > (size_t)di.lds || lv > (size_t)di.lds || nmax > kSlots * kTriThreads)
         fail(SYMTEN_E_CAPACITY, "eigh: vectors exceed LDS");
-    hipLaunchKernelGGL(tdvec_kernel, dim3((unsigned)cl.size()), dim3(64), lv, s, (const VecJob*)base,
-                       (const VecCluster*)(base + b1));
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(backtr_kernel, dim3((unsigned)bmap.size()), dim3(kBackThreads), lb, s,
-                       (const BackJob*)(base + b1 + b2), (const int2*)(base + b1 + b2 + b3), ch);
-    HIPCHK(hipGetLastError());
+    profile_launch("eigh_tdvec", 0, 0, 0, s, [&] {
+        hipLaunchKernelGGL(tdvec_kernel, dim3((unsigned)cl.size()), dim3(64), lv, s, (const VecJob*)base,
+                           (const VecCluster*)(base + b1));
+        HIPCHK(hipGetLastError());
+    });
+    int64_t bflops = 0;   // back-transformation: 2 n^2 per vector
+    for (int p = 0; p < np; ++p) bflops += 2 * (int64_t)wk.probs[p].n * wk.probs[p].n * kv[p];
+    profile_launch("eigh_backtr", bflops, bflops, 0, s, [&] {
+        hipLaunchKernelGGL(backtr_kernel, dim3((unsigned)bmap.size()), dim3(kBackThreads), lb, s,
+                           (const BackJob*)(base + b1 + b2), (const int2*)(base + b1 + b2 + b3), ch);
+        HIPCHK(hipGetLastError());
+    });
     wk.keep.push_back(zt);
     wk.keep.push_back(work);
     wk.keep.push_back(db);

@@ -197,11 +197,14 @@ def test_ctm_move_cfg1_f64(cfg1):
     assert stats["flops_renorm"] == fl["renorm"]
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16x6", "bf16x3"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x6", "bf16x3"])
 def test_ctm_move_cfg2(cfg2, prec):
+    """The D = 6, chi = 64 left move against the oracle.  FP64 takes the
+    Jordan-Wielandt route, whose largest block (order 1392) the library's
+    eigensolver spreads over four XCDs' workgroups."""
     c, (w, T, a, _) = cfg2
     chi = c["chi_target"]
-    dev = device_side(c, c["seed"], "f32")
+    dev = device_side(c, c["seed"], "f64" if prec == "f64" else "f32")
     env, stats, mv, pr = _move_compare(w, T, a, chi, dev, prec)
     gap = pr["gap"]
     assert gap > 100 * TOL[prec]            # unambiguous cut for this tolerance
