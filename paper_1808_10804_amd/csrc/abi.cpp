@@ -409,6 +409,19 @@ struct ctm_env {
     // set at the cut, about ten times the per-value error of the move's
     // precision (set by every move)
     double degen_tol = 1e-8;
+    // pinned host staging of the projector stage's one read-back
+    char* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    char* pinned_buffer(size_t bytes) {
+        if (bytes > pinned_bytes) {
+            if (pinned) HIPCHK(hipHostFree(pinned));
+            pinned = nullptr;
+            pinned_bytes = 0;
+            HIPCHK(hipHostMalloc((void**)&pinned, bytes, hipHostMallocDefault));
+            pinned_bytes = bytes;
+        }
+        return pinned;
+    }
     static double degenerate_tol(int prec) {
         switch (prec) {
             case SYMTEN_PREC_F64: return 1e-8;
@@ -425,6 +438,7 @@ struct ctm_env {
             if (aux[i]) (void)hipStreamDestroy(aux[i]);
         }
         if (ev_start) (void)hipEventDestroy(ev_start);
+        if (pinned) (void)hipHostFree(pinned);
     }
 };
 
@@ -696,13 +710,21 @@ struct ProjWork {
     int prob = -1;               // own route: the sector's problem in the cut set's EighWork
     int ne = 0;                  // own route: order of its eigenproblem
     double* w = nullptr;         // own route: its eigenvalues, ascending
+    double* sdev = nullptr;      // own route: its singular values (in the cut's read-back area)
     BufferPtr U, V, S;
+    const double* s_ptr() const { return sdev ? sdev : (const double*)S->ptr; }
 };
 struct ProjPending {
     std::vector<ProjWork> w;
     std::vector<BufferPtr> keep_alive;
     bool aux_used[ctm_env::kAux] = {};
     std::shared_ptr<EighWork> eig;   // own route: shared by the cuts solved together
+    // own route: the cut's read-back area, one copy to the host: ints
+    // [nonfinite flag, solver status per sector], then doubles from
+    // rb_head: per sector its eigenvalues (w_off) and singular values (s_off)
+    BufferPtr rb;
+    size_t rb_doubles = 0, rb_head = 0;
+    std::vector<size_t> w_off, s_off;
 };
 
 // One size class of a cut: its blocks zero-padded to N, Y = H_u^T H_d, the
@@ -787,19 +809,31 @@ std::vector<ProjPending> issue_solves_own(ctm_env* env, const std::vector<std::v
     const double one = 1.0, zero = 0.0;
     std::vector<ProjPending> pend(cuts.size());
     std::vector<EighProblem> probs;
-    BufferPtr fb = device_alloc(4 * cuts.size());
-    launch_fill_zero(fb->ptr, 4 * (int64_t)cuts.size(), s);
     for (size_t c = 0; c < cuts.size(); ++c) {
         std::vector<CutSector>& secs = *cuts[c];
         if (secs.empty()) fail(SYMTEN_E_LINALG, "ctm_move: the halves have no common sector");
-        pend[c].w.resize(secs.size());
-        pend[c].keep_alive.push_back(fb);
+        ProjPending& pc = pend[c];
+        pc.w.resize(secs.size());
+        pc.rb_head = (1 + secs.size() + 1) / 2;   // ints, in doubles
+        size_t tot = pc.rb_head;
+        for (auto& b : secs) {
+            b.mn = std::min(b.n, std::min(b.mu, b.md));
+            pc.w_off.push_back(tot);
+            tot += f64 ? b.mu + b.md : b.mu;
+            pc.s_off.push_back(tot);
+            tot += std::max(1, b.mn);
+        }
+        pc.rb_doubles = tot;
+        pc.rb = device_alloc(8 * tot);
+        launch_fill_zero(pc.rb->ptr, 8 * (int64_t)pc.rb_head, s);
+        pc.keep_alive.push_back(pc.rb);
+        int* head = (int*)pc.rb->ptr;
+        double* area = (double*)pc.rb->ptr;
         for (size_t i = 0; i < secs.size(); ++i) {
             CutSector& b = secs[i];
-            ProjWork& x = pend[c].w[i];
+            ProjWork& x = pc.w[i];
             x.ru = b.mu;
             x.rd = b.md;
-            b.mn = std::min(b.n, std::min(b.mu, b.md));
             const int N = std::max(b.n, std::max(b.mu, b.md));
             const size_t N2 = (size_t)N * N;
             BufferPtr Hb = device_alloc(8 * N2 * 2);
@@ -823,7 +857,7 @@ std::vector<ProjPending> issue_solves_own(ctm_env* env, const std::vector<std::v
             rb_check(rocblas_dgemm(env->rb, rocblas_operation_none, rocblas_operation_transpose, b.mu, b.md, b.n,
                                    &one, x.HuT, N, x.HdT, N, &zero, x.Y, x.ldy),
                      "rocblas_dgemm(Y)");
-            x.nonfinite = (int*)fb->ptr + c;
+            x.nonfinite = head;
             launch_nonfinite_guard(x.Y, (int64_t)b.mu * b.md, x.nonfinite, s);
             x.ne = f64 ? b.mu + b.md : b.mu;
             BufferPtr Ab = device_alloc(8 * (size_t)x.ne * x.ne);
@@ -833,17 +867,17 @@ std::vector<ProjPending> issue_solves_own(ctm_env* env, const std::vector<std::v
                 rb_check(rocblas_dgemm(env->rb, rocblas_operation_none, rocblas_operation_transpose, b.mu, b.mu, b.md,
                                        &one, x.Y, x.ldy, x.Y, x.ldy, &zero, (double*)Ab->ptr, x.ne),
                          "rocblas_dgemm(YY^T)");
-            BufferPtr wb = device_alloc(8 * (size_t)x.ne);
-            x.w = (double*)wb->ptr;
+            x.w = area + pc.w_off[i];
+            x.sdev = area + pc.s_off[i];
             x.prob = (int)probs.size();
             EighProblem ep;
             ep.n = x.ne;
             ep.lda = x.ne;
             ep.A = (const double*)Ab->ptr;
             ep.w = x.w;
+            ep.status = head + 1 + i;
             probs.push_back(ep);
-            x.S = device_alloc(8 * std::max(1, b.mn));
-            for (auto& k : {Hb, Yb, Ab, wb}) pend[c].keep_alive.push_back(k);
+            for (auto& k : {Hb, Yb, Ab}) pc.keep_alive.push_back(k);
         }
     }
     auto wk = eigh_values(probs, s);
@@ -852,7 +886,7 @@ std::vector<ProjPending> issue_solves_own(ctm_env* env, const std::vector<std::v
         std::vector<CutSector>& secs = *cuts[c];
         for (size_t i = 0; i < secs.size(); ++i) {
             ProjWork& x = pend[c].w[i];
-            launch_eigval_to_s(x.w, x.ne, secs[i].mn, f64, (double*)x.S->ptr, s);
+            launch_eigval_to_s(x.w, x.ne, secs[i].mn, f64, x.sdev, s);
         }
     }
     return pend;
@@ -989,22 +1023,32 @@ ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPendin
         for (auto& c : secs) { sv_off.push_back(tot); tot += c.mn; }
         out.sv.resize(tot);
         std::vector<int> infos(secs.size()), bad(secs.size());
-        for (size_t i = 0; i < secs.size(); ++i) {
-            if (secs[i].mn)
-                HIPCHK(hipMemcpyAsync(out.sv.data() + sv_off[i], pend.w[i].S->ptr, 8 * secs[i].mn, hipMemcpyDeviceToHost, s));
-            if (pend.w[i].info)
-                HIPCHK(hipMemcpyAsync(&infos[i], pend.w[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(&bad[i], pend.w[i].nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
-        }
         if (pend.eig) {
-            // eigenvalues of the cut's problems (for the eigenvector phase)
+            // own route: the cut's whole read-back area in one copy
+            const size_t bytes = 8 * pend.rb_doubles;
+            char* h = env->pinned_buffer(bytes);
+            HIPCHK(hipMemcpyAsync(h, pend.rb->ptr, bytes, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            const int* head = (const int*)h;
+            const double* area = (const double*)h;
             for (size_t i = 0; i < secs.size(); ++i) {
-                w_host[i].resize(pend.w[i].ne);
-                HIPCHK(hipMemcpyAsync(w_host[i].data(), pend.w[i].w, 8 * (size_t)pend.w[i].ne, hipMemcpyDeviceToHost, s));
+                bad[i] = head[0];
+                if (head[1 + i])
+                    fail(SYMTEN_E_HIP, "ctm_move: the workgroups of an eigensolve did not meet at a barrier");
+                w_host[i].assign(area + pend.w_off[i], area + pend.w_off[i] + pend.w[i].ne);
+                std::copy(area + pend.s_off[i], area + pend.s_off[i] + secs[i].mn, out.sv.begin() + sv_off[i]);
             }
-            eigh_status(*pend.eig, s);   // synchronises s
+        } else {
+            for (size_t i = 0; i < secs.size(); ++i) {
+                if (secs[i].mn)
+                    HIPCHK(hipMemcpyAsync(out.sv.data() + sv_off[i], pend.w[i].S->ptr, 8 * secs[i].mn,
+                                          hipMemcpyDeviceToHost, s));
+                if (pend.w[i].info)
+                    HIPCHK(hipMemcpyAsync(&infos[i], pend.w[i].info, sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(&bad[i], pend.w[i].nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+            }
+            HIPCHK(hipStreamSynchronize(s));
         }
-        HIPCHK(hipStreamSynchronize(s));
         for (size_t i = 0; i < secs.size(); ++i)
             if (bad[i]) fail(SYMTEN_E_LINALG, "ctm_move: NaN or Inf in the halves of the cut");
         for (size_t i = 0; i < secs.size(); ++i)
@@ -1104,18 +1148,18 @@ ProjOut finish_projectors(ctm_env* env, std::vector<CutSector>& secs, ProjPendin
                                    (const double*)x.Y, x.ldy, (const double*)x.U->ptr, x.ru, &zero, (double*)x.V->ptr,
                                    x.rd),
                      "rocblas_dgemm(V)");
-            launch_scale_cols((double*)x.V->ptr, x.rd, x.rd, k, (const double*)x.S->ptr, -1.0, s);
+            launch_scale_cols((double*)x.V->ptr, x.rd, x.rd, k, x.s_ptr(), -1.0, s);
         }
         // P = H_d V_k S^-1/2  (n x k, ld n; H_d = (H_d^T)^T)
         rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, n, k, x.rd, &one,
                                (const double*)x.HdT, x.ld, (const double*)x.V->ptr, x.rd, &zero, Pq, n),
                  "rocblas_dgemm(P)");
-        launch_scale_cols(Pq, n, n, k, (const double*)x.S->ptr, -0.5, s);
+        launch_scale_cols(Pq, n, n, k, x.s_ptr(), -0.5, s);
         // P~ = S^-1/2 U_k^T H_u^T  (k x n, ld k)
         rb_check(rocblas_dgemm(env->rb, rocblas_operation_transpose, rocblas_operation_none, k, n, x.ru, &one,
                                (const double*)x.U->ptr, x.ru, (const double*)x.HuT, x.ld, &zero, Ptq, k),
                  "rocblas_dgemm(Pt)");
-        launch_scale_rows(Ptq, k, k, n, (const double*)x.S->ptr, -0.5, s);
+        launch_scale_rows(Ptq, k, k, n, x.s_ptr(), -0.5, s);
         launch_sign_fix_rows(Ptq, k, k, n, Pq, n, s);
     }
     // the work buffers go back to the pool here; later launches that reuse

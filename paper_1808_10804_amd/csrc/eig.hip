@@ -17,11 +17,15 @@
 //   2. All eigenvalues by multisection: one wavefront per eigenvalue, its 64
 //      lanes evaluating Sturm counts of T at 64 points of the current
 //      interval, about 9 passes to 2 ulp.
-//   3. Eigenvectors of T for the kept eigenvalues by inverse iteration
-//      (tridiagonal LU with partial pivoting, two solves from a fixed
-//      pseudo-random start); eigenvalues closer than 1e-3 ||T|| form a
-//      cluster whose vectors are computed by one thread in order and
-//      reorthogonalised against the earlier ones in every solve.
+//   3. Eigenvectors of T for the kept eigenvalues from the twisted
+//      factorisation of T - lam I (two recurrences, no iteration; for an
+//      eigenvalue apart from the others both run at once).  Eigenvalues
+//      closer than 1e-3 ||T|| form a cluster, done in order by one
+//      wavefront: each vector has the earlier ones projected out, and if
+//      less than half of it is left (a degenerate value) it comes from
+//      inverse iteration instead (tridiagonal LU with partial pivoting, two
+//      solves from a fixed pseudo-random start, reorthogonalised in every
+//      solve).
 //   4. Back-transformation z <- Q z through the stored reflectors, one
 //      vector per workgroup held in LDS, one block-wide reduction per
 //      reflector, the reflectors streamed through LDS in chunks.
@@ -487,6 +491,88 @@ __global__ __launch_bounds__(64) void tdvec_kernel(const VecJob* __restrict__ jo
             __syncthreads();
             continue;
         }
+        {
+            // first the twisted factorisation (as in twist_kernel, both
+            // recurrences on lane 0, dl and du holding D+ and D-), then the
+            // cluster's earlier vectors projected out; unless little is left
+            // (the value degenerate with an earlier one), that is the vector
+            const double pv = DBL_MIN * fmax(1.0, tnorm * tnorm) / DBL_EPSILON;
+            auto guard = [&](double q) { return fabs(q) < pv ? (q < 0.0 ? -pv : pv) : q; };
+            auto rcp = [&](double q) {
+                const double r0 = __builtin_amdgcn_rcp(q);
+                return fma(r0, fma(-q, r0, 1.0), r0);
+            };
+            if (lane == 0) {
+                double q = guard(d[0] - lam);
+                dl[0] = q;
+                for (int i = 1; i < n; ++i) {
+                    q = guard((d[i] - lam) - e[i - 1] * e[i - 1] * rcp(q));
+                    dl[i] = q;
+                }
+                q = guard(d[n - 1] - lam);
+                du[n - 1] = q;
+                for (int i = n - 2; i >= 0; --i) {
+                    q = guard((d[i] - lam) - e[i] * e[i] * rcp(q));
+                    du[i] = q;
+                }
+            }
+            __syncthreads();
+            double bv = INFINITY;
+            int bi = n;
+            for (int i = lane; i < n; i += 64) {
+                const double gv = fabs(dl[i] + du[i] - (d[i] - lam));
+                if (gv < bv) {
+                    bv = gv;
+                    bi = i;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                if (ov < bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
+                }
+            }
+            const int r = bi;
+            for (int i = lane; i < n; i += 64) z[i] = i < r ? -e[i] / dl[i] : (i > r ? -e[i - 1] / du[i] : 1.0);
+            __syncthreads();
+            if (lane == 0) {
+                double c = 1.0;
+                for (int i = r - 1; i >= 0; --i) {
+                    c *= z[i];
+                    z[i] = c;
+                }
+                c = 1.0;
+                for (int i = r + 1; i < n; ++i) {
+                    c *= z[i];
+                    z[i] = c;
+                }
+            }
+            __syncthreads();
+            double part = 0.0;
+            for (int i = lane; i < n; i += 64) part += z[i] * z[i];
+            double inv = 1.0 / sqrt(wave_sum(part));
+            for (int i = lane; i < n; i += 64) z[i] *= inv;
+            for (int q = 0; q < m; ++q) {
+                const double* y = J.Zt + (size_t)(C.first + q) * n;
+                double pq = 0.0;
+                for (int i = lane; i < n; i += 64) pq += y[i] * z[i];
+                const double dot = wave_sum(pq);
+                for (int i = lane; i < n; i += 64) z[i] -= dot * y[i];
+            }
+            part = 0.0;
+            for (int i = lane; i < n; i += 64) part += z[i] * z[i];
+            const double left = wave_sum(part);
+            if (left >= 0.25) {
+                inv = 1.0 / sqrt(left);
+                for (int i = lane; i < n; i += 64) zo[i] = z[i] * inv;
+                __syncthreads();   // later members of the cluster read this vector
+                continue;
+            }
+            __syncthreads();
+        }
         if (lane == 0) {
             // LU with partial pivoting of T - lam I (LAPACK's tridiagonal
             // scheme; row interchanges recorded in piv, tiny pivots raised
@@ -596,6 +682,137 @@ __global__ __launch_bounds__(64) void tdvec_kernel(const VecJob* __restrict__ jo
         for (int i = lane; i < n; i += 64) zo[i] = z[i];
         __syncthreads();   // later members of the cluster read this vector
     }
+}
+
+// Step 3 for an eigenvalue apart from the others (a cluster of one): the
+// eigenvector straight from the twisted factorisation of T - lam I.  Wave 0
+// runs the top-down recurrence D+_i = (d_i - lam) - e_{i-1}^2 / D+_{i-1},
+// wave 1 the bottom-up one D-_i = (d_i - lam) - e_i^2 / D-_{i+1} at the same
+// time; the twist r minimises |gamma_i| = |D+_i + D-_i - (d_i - lam)| (ties:
+// the lower index); then z_r = 1, z_i = -e_i z_{i+1} / D+_i above r and
+// z_i = -e_{i-1} z_{i-1} / D-_i below it, normalised.  Its residual is
+// |gamma_r| / ||z||, which an eigenvalue accurate to 2 eps ||T|| keeps at
+// rounding level (no iteration).  Dynamic LDS: d, e, D+, D-, z (5 n).
+__global__ __launch_bounds__(128) void twist_kernel(const VecJob* __restrict__ jobs,
+                                                     const VecCluster* __restrict__ clusters) {
+    const VecCluster C = clusters[blockIdx.x];
+    const VecJob J = jobs[C.job];
+    const int n = J.n, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    extern __shared__ double sm[];
+    double *d = sm, *e = sm + n, *dp = sm + 2 * n, *dm = sm + 3 * n, *z = sm + 4 * n;
+    __shared__ double red_v[2];
+    __shared__ int red_i[2];
+    for (int i = tid; i < n; i += 128) {
+        d[i] = J.d[i];
+        e[i] = i + 1 < n ? J.e[i] : 0.0;
+    }
+    __syncthreads();
+    double tl = 0.0, em = 0.0;
+    for (int i = tid; i < n; i += 128) {
+        tl = fmax(tl, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + fabs(e[i]));
+        em = fmax(em, e[i] * e[i]);
+    }
+    tl = wave_max(tl);
+    em = wave_max(em);
+    if (lane == 0) red_v[wave] = tl;
+    __syncthreads();
+    const double tnorm = fmax(red_v[0], red_v[1]);
+    __syncthreads();
+    const int jr = C.first;
+    double* zo = J.Zt + (size_t)jr * n;
+    if (n == 1 || tnorm == 0.0) {   // T = 0: the unit vectors
+        for (int i = tid; i < n; i += 128) zo[i] = i == jr ? 1.0 : 0.0;
+        return;
+    }
+    const double lam = J.w[n - 1 - jr] * *J.scale;
+    // pivots below this are raised to it (keeping the sign): never zero
+    const double piv = DBL_MIN * fmax(1.0, em) / DBL_EPSILON;
+    auto guard = [&](double q) { return fabs(q) < piv ? (q < 0.0 ? -piv : piv) : q; };
+    auto rcp = [&](double q) {
+        const double r0 = __builtin_amdgcn_rcp(q);
+        return fma(r0, fma(-q, r0, 1.0), r0);
+    };
+    if (lane == 0 && wave == 0) {
+        double q = guard(d[0] - lam);
+        dp[0] = q;
+        double dn = d[1], ep = e[0];
+        for (int i = 1; i < n; ++i) {
+            const double a = dn - lam, e2 = ep * ep;
+            if (i + 1 < n) {
+                dn = d[i + 1];
+                ep = e[i];
+            }
+            q = guard(a - e2 * rcp(q));
+            dp[i] = q;
+        }
+    } else if (lane == 0 && wave == 1) {
+        double q = guard(d[n - 1] - lam);
+        dm[n - 1] = q;
+        double dn = d[n - 2], ep = e[n - 2];
+        for (int i = n - 2; i >= 0; --i) {
+            const double a = dn - lam, e2 = ep * ep;
+            if (i > 0) {
+                dn = d[i - 1];
+                ep = e[i - 1];
+            }
+            q = guard(a - e2 * rcp(q));
+            dm[i] = q;
+        }
+    }
+    __syncthreads();
+    // twist: argmin |gamma| (lowest index on ties)
+    double bv = INFINITY;
+    int bi = n;
+    for (int i = tid; i < n; i += 128) {
+        const double g = fabs(dp[i] + dm[i] - (d[i] - lam));
+        if (g < bv) {
+            bv = g;
+            bi = i;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov < bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+        }
+    }
+    if (lane == 0) {
+        red_v[wave] = bv;
+        red_i[wave] = bi;
+    }
+    __syncthreads();
+    const int r = (red_v[1] < red_v[0] || (red_v[1] == red_v[0] && red_i[1] < red_i[0])) ? red_i[1] : red_i[0];
+    // ratios in parallel, then the two product chains at once
+    for (int i = tid; i < n; i += 128) {
+        if (i < r) z[i] = -e[i] / dp[i];
+        else if (i > r) z[i] = -e[i - 1] / dm[i];
+        else z[i] = 1.0;
+    }
+    __syncthreads();
+    if (lane == 0 && wave == 0) {
+        double c = 1.0;
+        for (int i = r - 1; i >= 0; --i) {
+            c *= z[i];
+            z[i] = c;
+        }
+    } else if (lane == 0 && wave == 1) {
+        double c = 1.0;
+        for (int i = r + 1; i < n; ++i) {
+            c *= z[i];
+            z[i] = c;
+        }
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int i = tid; i < n; i += 128) part += z[i] * z[i];
+    part = wave_sum(part);
+    if (lane == 0) red_v[wave] = part;
+    __syncthreads();
+    const double inv = 1.0 / sqrt(red_v[0] + red_v[1]);
+    for (int i = tid; i < n; i += 128) zo[i] = z[i] * inv;
 }
 
 struct BackJob {
@@ -812,10 +1029,10 @@ void set_lds_limits(const DevInfo& di) {
     HIPCHK(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(mu);
     if (done.count(dev)) return;
-    const char* names[] = {"tridiag", "bisect", "backtr", "tdvec"};
+    const char* names[] = {"tridiag", "bisect", "backtr", "tdvec", "twist"};
     const void* fns[] = {(const void*)tridiag_kernel, (const void*)bisect_kernel, (const void*)backtr_kernel,
-                         (const void*)tdvec_kernel};
-    for (int i = 0; i < 4; ++i) {
+                         (const void*)tdvec_kernel, (const void*)twist_kernel};
+    for (int i = 0; i < 5; ++i) {
         const hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, di.lds);
         if (e != hipSuccess)
             fail(SYMTEN_E_HIP, std::string("eigh: dynamic LDS limit of the ") + names[i] + " kernel: " +
@@ -906,7 +1123,7 @@ std::shared_ptr<EighWork> eigh_values(const std::vector<EighProblem>& probs, hip
         J.V = q; q += (size_t)n * n;
         J.scale = q; q += 1;
         J.counter = counters + p;
-        J.status = wk->status + p;
+        J.status = probs[p].status ? probs[p].status : wk->status + p;
         wk->d.push_back(J.d);
         wk->e.push_back(J.e);
         wk->tau.push_back(J.tau);
@@ -1045,6 +1262,9 @@ void eigh_vectors(EighWork& wk, const std::vector<int>& kv, const std::vector<do
         ztot += (size_t)n * k;
     }
     if (cl.empty()) return;
+    std::stable_partition(cl.begin(), cl.end(), [](const VecCluster& c) { return c.count == 1; });
+    int n_single = 0;
+    for (auto& c : cl) n_single += c.count == 1;
     size_t worktot = 0;
     for (auto& c : cl) {
         c.woff = (int64_t)worktot;
@@ -1084,11 +1304,21 @@ void eigh_vectors(EighWork& wk, const std::vector<int>& kv, const std::vector<do
     const size_t lb = 8 * ((size_t)(ch + 2) * nmax + 4);
     if (lb > (size_t)di.lds || lv > (size_t)di.lds || nmax > kSlots * kTriThreads)
         fail(SYMTEN_E_CAPACITY, "eigh: vectors exceed LDS");
-    profile_launch("eigh_tdvec", 0, 0, 0, s, [&] {
-        hipLaunchKernelGGL(tdvec_kernel, dim3((unsigned)cl.size()), dim3(64), lv, s, (const VecJob*)base,
-                           (const VecCluster*)(base + b1));
-        HIPCHK(hipGetLastError());
-    });
+    // clusters of one first in the list (the twisted factorisation), then
+    // the rest (inverse iteration with reorthogonalisation)
+    const int nsingle = n_single;
+    if (nsingle > 0)
+        profile_launch("eigh_twist", 0, 0, 0, s, [&] {
+            hipLaunchKernelGGL(twist_kernel, dim3((unsigned)nsingle), dim3(128), 8 * 5 * (size_t)nmax, s,
+                               (const VecJob*)base, (const VecCluster*)(base + b1));
+            HIPCHK(hipGetLastError());
+        });
+    if ((int)cl.size() > nsingle)
+        profile_launch("eigh_tdvec", 0, 0, 0, s, [&] {
+            hipLaunchKernelGGL(tdvec_kernel, dim3((unsigned)(cl.size() - nsingle)), dim3(64), lv, s,
+                               (const VecJob*)base, (const VecCluster*)(base + b1) + nsingle);
+            HIPCHK(hipGetLastError());
+        });
     int64_t bflops = 0;   // back-transformation: 2 n^2 per vector
     for (int p = 0; p < np; ++p) bflops += 2 * (int64_t)wk.probs[p].n * wk.probs[p].n * kv[p];
     profile_launch("eigh_backtr", bflops, bflops, 0, s, [&] {

@@ -290,6 +290,8 @@ struct EighProblem {
     int n = 0, lda = 0;
     const double* A = nullptr;   // n x n, column-major, both triangles
     double* w = nullptr;         // n eigenvalues, ascending
+    int* status = nullptr;       // optional, zeroed by the caller: set to 1 if
+                                 // the tridiagonalisation's barrier gave up
 };
 struct EighWork;
 bool eigh_fits(int n);
