@@ -1,6 +1,7 @@
 // Host bookkeeping of libsymten: allowed-block enumeration, contraction
 // planning (charge-sector grouping of matched block pairs), plan execution,
 // the double layer, and a caching device allocator.
+#include <charconv>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -286,23 +287,42 @@ std::string tensor_signature(const Tensor& t) {
         std::lock_guard<std::mutex> lk(t.memo.mu);
         if (t.memo.valid) return t.memo.sig;
     }
-    std::ostringstream os;
-    os << "g" << t.group << "f" << t.flux << "t" << t.dtype << "|";
+    // the same fields as before, appended with std::to_chars (a stream was
+    // the host cost of planning a move's new tensors)
+    std::string sig;
+    sig.reserve(32 + 16 * t.legs.size() + 48 * t.blocks.size());
+    char buf[24];
+    auto put = [&](int64_t v, char sep) {
+        const auto r = std::to_chars(buf, buf + sizeof(buf), v);
+        sig.append(buf, r.ptr);
+        if (sep) sig.push_back(sep);
+    };
+    sig.push_back('g');
+    put(t.group, 'f');
+    put(t.flux, 't');
+    put(t.dtype, '|');
     for (auto& l : t.legs) {
-        os << l.dir << ":";
-        for (size_t i = 0; i < l.q.size(); ++i) os << l.q[i] << "x" << l.d[i] << ",";
-        os << ";";
+        put(l.dir, ':');
+        for (size_t i = 0; i < l.q.size(); ++i) {
+            put(l.q[i], 'x');
+            put(l.d[i], ',');
+        }
+        sig.push_back(';');
     }
-    os << "|";
+    sig.push_back('|');
     for (auto& b : t.blocks) {
-        for (int x : b.q) os << x << ",";
-        for (int x : b.tree) os << "t" << x;
-        os << "@" << b.offset << "/";
-        for (auto s : b.stride) os << s << ",";
-        os << ";";
+        for (int x : b.q) put(x, ',');
+        for (int x : b.tree) {
+            sig.push_back('t');
+            put(x, 0);
+        }
+        sig.push_back('@');
+        put(b.offset, '/');
+        for (auto st : b.stride) put(st, ',');
+        sig.push_back(';');
     }
     std::lock_guard<std::mutex> lk(t.memo.mu);
-    t.memo.sig = os.str();
+    t.memo.sig = std::move(sig);
     t.memo.valid = true;
     return t.memo.sig;
 }
