@@ -394,6 +394,46 @@ def test_su2_run_vs_oracle():
     assert abs(r["err_steps"] - ro["err_steps"]) <= 1e-9 * abs(ro["kappa"])
 
 
+def test_u1_expansion_keeps_multiplets_over_ten_moves():
+    """Ten truncating moves (directions 0..3 in turn) of an SU(2) environment
+    and, side by side, of the library's S^z expansion of it on the U(1)
+    path, FP64, each U(1) move truncated to the states the SU(2) move kept.
+    The U(1) path treats each S^z sector on its own; its truncation keeps a
+    degenerate set whole (Sec. 3's scheme, multiplets split by rounding only),
+    so after every move its kept table is the SU(2) table counted by S^z
+    components (sector 2m holds every kept multiplet with 2J >= |2m| of the
+    same parity), bit for bit, its kept spectrum is the reduced spectrum with
+    each value 2J+1 times, and the two environments close to the same kappa."""
+    c = dict(chi={0: 2, 1: 2, 2: 1}, dd={0: 2, 1: 2, 2: 1}, chi_target=7)
+    legs = _env_legs(c["chi"], c["dd"])
+    vals = su2_values(legs, 1817)
+    env, dev = _su2_env(legs, vals, "f64")
+    U = {n: t.to_u1() for n, t in dev.items()}
+    envu = st.CtmEnv([U[k] for k in ("C1", "C2", "C3", "C4")], [U[k] for k in ("T1", "T2", "T3", "T4")])
+    for i in range(10):
+        d = i % 4
+        print(f"move {i} direction {d}", flush=True)
+        s2 = env.move(dev["a"], c["chi_target"], prec="f64", direction=d)
+        k2 = {tj: n for tj, n in s2["kept"].items() if n > 0}
+        states = sum((tj + 1) * n for tj, n in k2.items())
+        assert 0 < states <= c["chi_target"]
+        s1 = envu.move(U["a"], states, prec="f64", direction=d)
+        k1 = {q: n for q, n in s1["kept"].items() if n > 0}
+        want = {}
+        for tj, n in k2.items():
+            for q in range(-tj, tj + 1, 2):
+                want[q] = want.get(q, 0) + n
+        got = _spectrum_states(env.singular_values(), s2)[:states]
+        ref = np.sort(envu.singular_values())[::-1][:states]
+        err = np.max(np.abs(got - ref)) / ref[0]
+        kg, _ = env.site_partition(dev["a"])
+        ku, _ = envu.site_partition(U["a"])
+        print(f"  kept su2 {k2} u1 {k1}; spectrum {err:.2e}; kappa {kg:.14e} / {ku:.14e}", flush=True)
+        assert k1 == want, (i, k1, want)
+        assert err <= 1e-10, (i, err)
+        assert abs(kg - ku) <= 1e-10 * abs(ku), (i, kg, ku)
+
+
 def test_su2_heisenberg_energy_vs_oracle():
     """Bond energies of an SU(2) state (spin 1/2, virtual multiplets j = 0, 1/2)
     in an SU(2) environment: the library measures the S^z components (the
