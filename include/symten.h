@@ -408,12 +408,14 @@ int ctm_env_get(ctm_env_t env, int k, symten_t* t);
  * each side of the cut are fused by a unitary isometry into one multiplet
  * leg, sectors are its total spins J, each kept value is a multiplet of
  * 2J+1 states and multiplets are kept whole (descending, stopping at the
- * first that does not fit).  Synchronises `stream` once (truncation needs
- * the singular values on the host) and again at the end when `st` is not
- * NULL.  The eigensolves of the projector stage run on three side streams of
- * the environment beside `stream`, each enqueued by a short-lived host thread
- * of the library; all of them are joined to `stream` before the call
- * returns.  Calls on one environment must not overlap.                      */
+ * first that does not fit).  Synchronises `stream` once during the move
+ * (truncation needs the singular values on the host) and returns with
+ * `stream` synchronised: the updated tensors are complete on return.  The
+ * eigensolves of the projector stage run on `stream` (the library's solver,
+ * orders up to symten_eigh_max_order); larger ones (rocSOLVER) run on three
+ * side streams of the environment, each enqueued by a short-lived host
+ * thread, all joined to `stream` before the call returns.  Calls on one
+ * environment must not overlap.                                             */
 int ctm_move(ctm_env_t env, symten_t a, int dir, int chi, int prec,
              ctm_move_stats* st, void* stream);
 
@@ -452,7 +454,8 @@ int ctm_cell_get(ctm_env_t env, int x, int y, int k, symten_t* t);
  * the next column is processed.  Other directions turn the cell (site
  * (x, y) -> (y, Lx-1-x), every site as in ctm_move) and back.
  * ctm_move_singular_values returns the kept values of every cut of the
- * move, cut after cut, each cut's descending.                              */
+ * move, cut after cut, each cut's descending.  Returns with `stream`
+ * synchronised, as ctm_move does.                                          */
 int ctm_cell_move(ctm_env_t env, const symten_t* a, int dir, int chi, int prec, void* stream);
 /* ctm_site_partition on the environment of site (x, y).                   */
 int ctm_cell_site_partition(ctm_env_t env, int x, int y, symten_t a, int block, double* kappa, double* z,

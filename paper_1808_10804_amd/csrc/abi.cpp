@@ -2746,7 +2746,7 @@ int ctm_move_projectors(ctm_env_t env, symten_t* P, symten_t* Pt) {
 }
 
 int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_stats* st, void* stream) {
-    return guard_on(stream, [&] {
+    const int rc = guard_on(stream, [&] {
         if (!env) fail(SYMTEN_E_INVAL, "null environment");
         if (dir < CTM_LEFT || dir > CTM_BOTTOM) fail(SYMTEN_E_INVAL, "ctm_move: direction must be 0..3");
         if (chi < 1) fail(SYMTEN_E_INVAL, "chi must be positive");
@@ -2823,6 +2823,15 @@ int ctm_move(ctm_env_t env, symten_t a_h, int dir, int chi, int prec, ctm_move_s
         for (int r = dir; r < 4; ++r) rotate_ccw(C, Tt, ar);
         for (int i = 0; i < 4; ++i) { env->C[i] = C[i]; env->T[i] = Tt[i]; }
     });
+    // The move ends with its stream synchronised.  Its read-back of the
+    // spectrum already waits for the stream once; returning while the last
+    // kernels (vectors, projectors, renormalisation) still ran let the
+    // caller enqueue the next move behind them, and back-to-back D = 6,
+    // chi = 64 moves then took 8.5-8.6 ms against 6.9 ms with this wait
+    // (measured with host timers; the difference does not appear under a
+    // kernel trace, which gives every dispatch its own completion signal).
+    if (rc != SYMTEN_OK) return rc;
+    return guard_on(stream, [&] { HIPCHK(hipStreamSynchronize(S(stream))); });
 }
 
 int ctm_cell_create(ctm_env_t* env, int Lx, int Ly, const symten_t* C, const symten_t* Tt) {
@@ -2858,7 +2867,7 @@ int ctm_cell_get(ctm_env_t env, int x, int y, int k, symten_t* t) {
 }
 
 int ctm_cell_move(ctm_env_t env, const symten_t* a_h, int dir, int chi, int prec, void* stream) {
-    return guard_on(stream, [&] {
+    const int rc = guard_on(stream, [&] {
         if (!env || !a_h || env->Lx < 1) fail(SYMTEN_E_INVAL, "not a unit-cell environment");
         if (dir < CTM_LEFT || dir > CTM_BOTTOM) fail(SYMTEN_E_INVAL, "ctm_cell_move: direction must be 0..3");
         if (chi < 1) fail(SYMTEN_E_INVAL, "chi must be positive");
@@ -2913,6 +2922,9 @@ int ctm_cell_move(ctm_env_t env, const symten_t* a_h, int dir, int chi, int prec
         }
         turn((4 - dir) % 4);
     });
+    // ends with its stream synchronised, as ctm_move does (same reason)
+    if (rc != SYMTEN_OK) return rc;
+    return guard_on(stream, [&] { HIPCHK(hipStreamSynchronize(S(stream))); });
 }
 
 int ctm_cell_site_partition(ctm_env_t env, int x, int y, symten_t a, int block, double* kappa, double* z,
