@@ -384,6 +384,8 @@ class CtmEnv:
     """CTM environment C1..C4, T1..T4 (clockwise bonds) with one-move updates."""
 
     def __init__(self, Cs, Ts):
+        # the caller's tensors by slot (0..3: C1..C4, 4..7: T1..T4), held
+        # while the environment may use them
         self._keep = list(Cs) + list(Ts)
         h = C.c_void_p()
         check(lib().ctm_env_create(C.byref(h), (C.c_void_p * 4)(*[c._h for c in Cs]),
@@ -408,7 +410,7 @@ class CtmEnv:
     def set(self, k, t):
         """Replace tensor k (0..3: C1..C4, 4..7: T1..T4)."""
         check(lib().ctm_env_set(self._h, int(k), t._h))
-        self._keep.append(t)
+        self._keep[int(k)] = t
 
     def move(self, a, chi, prec="f32", direction=0, stats=True, stream=None):
         st = _lib.MoveStats() if stats else None
