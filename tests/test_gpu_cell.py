@@ -110,6 +110,22 @@ def test_ising_2x2_cell(beta):
             assert abs(np.log(k) - exact) < 1e-10
 
 
+def test_cell_move_returns_with_its_stream_synchronised():
+    """ctm_cell_move returns with the caller's stream idle (a torch stream of
+    default priority, queried without waiting), toward every side."""
+    import torch
+    c = config(1)
+    dev, _, _ = _site(c, 0)
+    cell = st.CtmCell([[([dev[k] for k in ENV[:4]], [dev[k] for k in ENV[4:]])]])
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for d in range(4):
+            cell.move([[dev["a"]]], 16, prec="f64", direction=d, stream=s.cuda_stream)
+            assert s.query(), f"stream busy after the cell move toward {d}"
+    s.synchronize()
+
+
 def test_1x1_entry_points_refuse_a_cell():
     """A unit-cell environment goes through the cell entry points only: the
     1x1 partition function and run refuse it (SYMTEN_E_INVAL) instead of

@@ -260,6 +260,23 @@ def test_heisenberg_ferromagnet_product_state():
     assert abs(eh - 0.25) <= 1e-14 and abs(ev - 0.25) <= 1e-14
 
 
+def test_move_returns_with_its_stream_synchronised():
+    """ctm_move returns with the caller's stream idle: the updated tensors
+    are complete on return (a torch stream of default priority, queried
+    without waiting), toward every side."""
+    import torch
+    c = config(1)
+    dev = device_side(c, c["seed"], "f32")
+    env = _env(dev)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for d in range(4):
+            env.move(dev["a"], c["chi_target"], prec="f32", direction=d, stream=s.cuda_stream)
+            assert s.query(), f"stream busy after the move toward {d}"
+    s.synchronize()
+
+
 def test_move_on_a_torch_stream_equals_the_null_stream():
     """The same FP32 move (cfg 2 shape at D = 4, chi = 16) issued on a torch
     stream of default priority and on the null stream: the side streams of
