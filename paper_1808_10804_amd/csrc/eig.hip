@@ -829,11 +829,14 @@ struct BackJob {
 // in V, read as 16-byte pairs): the loads of the next chunk are issued into
 // registers before the current chunk is applied, so their latency overlaps
 // its work.  Entries a reflector does not store (rows i <= j) are never
-// read.  Dynamic LDS: the vector, tau, one chunk.
-constexpr int kBackThreads = 256;
+// read.  Dynamic LDS: the vector, tau, one chunk.  A cut keeps few vectors
+// (one workgroup each, on a fraction of the compute units), so the
+// per-reflector latency sets the time: eight waves (0.43 ms for the 65
+// vectors of the D = 6, chi = 64 cut) beat four (0.50) and sixteen (0.50).
+constexpr int kBackThreads = 512;
 constexpr int kBackWaves = kBackThreads / 64;
 constexpr int kChunk = 16;        // reflectors per chunk at most
-constexpr int kChunkLoads = 16;   // 16-byte loads per thread per chunk at most (the chunk size follows)
+constexpr int kChunkLoads = 8;    // 16-byte loads per thread per chunk at most (the chunk size follows)
 __global__ __launch_bounds__(kBackThreads) void backtr_kernel(const BackJob* __restrict__ jobs,
                                                                const int2* __restrict__ bmap, int ch) {
     const int2 bm = bmap[blockIdx.x];
